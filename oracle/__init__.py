@@ -1,0 +1,29 @@
+"""FP64 CPU oracle of the Newton-step linear solve (TEST INFRASTRUCTURE ONLY).
+
+Plain, slow, obviously-correct NumPy/SciPy implementation of what the GPU
+library computes: block-CSR products, the additive Vanka smoother (eq. vanka,
+Sec. 4.3), Q2 grid transfers, the geometric multigrid V-cycle (Sec. 4.3 (II)),
+flexible GMRES (Sec. 4.3 (I)), the condensed deformation update (Sec. 3.1,
+eq. problem:2) and the ALE extension solve (eq. problem:3).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library; both receive
+their inputs from the separate input generator ``fsigen``.
+
+Every function here is pinned by a ``-m "not gpu"`` test against something
+other than itself (closed forms, library routines, invariants); see
+``tests/test_oracle_pins.py``.
+"""
+from .linalg import to_csr, matvec, masked_residual
+from .patches import element_patches, patch_dofs
+from .vanka import local_matrices, local_inverses, vanka_sweep, VankaData
+from .transfer import prolongation_1d, prolongation
+from .mg import Hierarchy, vcycle
+from .fgmres import fgmres
+from .deform import deform_update
+from .step import newton_step_solve
+
+__all__ = ["to_csr", "matvec", "masked_residual", "element_patches", "patch_dofs",
+           "local_matrices", "local_inverses", "vanka_sweep", "VankaData", "prolongation_1d",
+           "prolongation", "Hierarchy", "vcycle", "fgmres", "deform_update",
+           "newton_step_solve"]

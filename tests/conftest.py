@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@pytest.fixture(scope="session")
+def prob_t2():
+    from fsigen import config_problem
+    return config_problem("t2", seed=0)
+
+
+@pytest.fixture(scope="session")
+def prob_t3():
+    from fsigen import config_problem
+    return config_problem("t3", seed=0)
