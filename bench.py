@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark: one Newton-step linear solve of the condensed ALE FSI system.
+
+A step is the whole hot path on one batch of synthetic input resident in HBM:
+  momentum solve (FGMRES + V-cycle + additive Vanka, eq. problem:1)
+  -> condensed deformation update du = k theta dv on interface/solid nodes
+  -> deformation system M du = M (k theta dv) solved by the same machinery
+  -> ALE extension solve E_f du_f = b5 - E_i du_i (eq. problem:3).
+Workload (default): 3D box [0,1]^3, solid block [0.3,0.7]x[0.4,0.6]^2, 32^3 Q2
+hexes (65^3 nodes), 4 levels, rel. residual 1e-8 (FP64-checked).
+
+Prints ONE JSON line (rank 0).  value = (momentum + ALE unknowns) solved per
+second of step wall time, FP64 path; the FP32-mixed path is reported in the
+same line under "mixed".
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def vanka_bytes(npatch, np_, nl, s):
+    """Algorithmic bytes of one Vanka patch-kernel launch: every patch streams
+    its n_p x n_p inverse once, gathers n_p residual entries, writes n_p
+    corrections and reads its node list."""
+    return npatch * (np_ * np_ * s + 2 * np_ * s + nl * 4)
+
+
+def spmv_bytes(nnzb, nrows, b, s):
+    """Algorithmic bytes of one residual SpMV d = r - A x: block values and
+    column indices once, row pointers, x, r and d once, the mask bytes."""
+    return nnzb * (b * b * s + 4) + 4 * (nrows + 1) + 3 * nrows * b * s + nrows * b
+
+
+def run_gpu(P, precision, steps, warmup, with_mass=True):
+    import torch
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import level_dicts
+
+    dev = torch.device("cuda:0")
+    ctx = fsimg.fsimg_ctx_create(0)
+    hs = {}
+    t0 = time.perf_counter()
+    systems = ["mom", "ale"] + (["mass"] if with_mass else [])
+    for name in systems:
+        o = fsimg.fsimg_default_opts(precision=precision, profile=0)
+        hs[name] = fsimg.fsimg_hier_create(ctx, level_dicts(P, name), o)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for name in systems:
+        fsimg.fsimg_factor(hs[name])
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    lev = P.levels[0]
+    nn = lev.nnodes
+    d = P.dim
+    k, th = P.params["k"], P.params["theta"]
+    b_mom = torch.tensor(P.rhs["mom"], device=dev)
+    b_ale = torch.tensor(P.rhs["ale"], device=dev)
+    node_mask = torch.tensor(lev.node_solid, device=dev)
+    x_mom = torch.zeros_like(b_mom)
+    x_ale = torch.zeros(nn * d, device=dev, dtype=torch.float64)
+    b_mass = torch.zeros_like(x_ale)
+    x_mass = torch.zeros_like(x_ale)
+    stream = torch.cuda.current_stream()
+
+    def step(profile=False):
+        x_mom.zero_()
+        if profile:
+            opts_prof(hs["mom"], 1)
+        st_m = fsimg.fsimg_solve(hs["mom"], b_mom, x_mom, stream)
+        if profile:
+            opts_prof(hs["mom"], 0)
+        fsimg.fsimg_deform_update(nn, d, node_mask, k, th, x_mom, d + 1, 1, None, None, x_ale, stream)
+        st_s = None
+        if with_mass:
+            fsimg.fsimg_level_apply(hs["mass"], 0, fsimg.FSIMG_FP64, x_ale, b_mass, stream)
+            x_mass.zero_()
+            st_s = fsimg.fsimg_solve(hs["mass"], b_mass, x_mass, stream)
+        st_a = fsimg.fsimg_solve(hs["ale"], b_ale, x_ale, stream)
+        return st_m, st_s, st_a
+
+    def opts_prof(h, on):
+        fsimg.fsimg_hier_set_profile(h, on)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    # per-kernel timing with HIP events on the launch stream, over one more
+    # set of timed steps (the same work)
+    prof = [step(profile=True)[0] for _ in range(max(1, min(steps, 3)))]
+    torch.cuda.synchronize()
+    info_m = fsimg.fsimg_hier_info(hs["mom"], 0)
+    res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, stats=stats[-1], prof=prof,
+               info_m=info_m, x_mom=x_mom.cpu().numpy(), x_ale=x_ale.cpu().numpy())
+    for h in hs.values():
+        fsimg.fsimg_hier_destroy(h)
+    fsimg.fsimg_ctx_destroy(ctx)
+    return res
+
+
+def cpu_baseline(P, iters_gpu, budget_s=20.0):
+    """The FP64 oracle on the host: FGMRES iterations on the momentum system of
+    the same workload for about budget_s seconds (setup untimed); the
+    per-iteration time scaled by the GPU's iteration count gives the oracle's
+    momentum DoF/s."""
+    import numpy as np
+    from oracle.fgmres import fgmres
+    from oracle.mg import Hierarchy, vcycle
+
+    t0 = time.perf_counter()
+    cells = [lv.cells for lv in P.levels]
+    H = Hierarchy(P.system("mom"), cells, omega=0.8, weighting="mult")
+    t_setup = time.perf_counter() - t0
+    lev = H.levels[0]
+    b = P.rhs["mom"]
+    # one iteration first to size the sample
+    w0, c0 = time.perf_counter(), time.process_time()
+    fgmres(lev.A, b, np.zeros_like(b), lambda v: vcycle(H, v), lev.mask, rtol=1e-30, maxiter=1)
+    t1 = time.perf_counter() - w0
+    n_it = max(1, min(20, int(budget_s / max(t1, 1e-3))))
+    w0, c0 = time.perf_counter(), time.process_time()
+    fgmres(lev.A, b, np.zeros_like(b), lambda v: vcycle(H, v), lev.mask, rtol=1e-30, maxiter=n_it,
+           restart=20)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    t_it = wall / n_it
+    n = b.shape[0]
+    return dict(value=n / (t_it * iters_gpu), unit="DoF/s", cores=round(cpu / wall, 1),
+                kind="oracle",
+                sample=(f"{n_it} FGMRES(20)+V-cycle iterations of the momentum system ({n} unknowns), "
+                        f"{wall:.1f} s wall; DoF/s = unknowns / (s per iteration x {iters_gpu} "
+                        f"iterations the GPU solve took); host {os.cpu_count()} cpus; oracle setup "
+                        f"{t_setup:.0f} s untimed"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mass", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="run one precision only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"sharding of this path is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    from fsigen import config_problem
+    from oracle import to_csr
+
+    t0 = time.perf_counter()
+    P = config_problem(args.config, seed=0)
+    log(f"problem {args.config} generated in {time.perf_counter() - t0:.1f} s")
+    from paper_1904_02401_amd import fsimg
+    lev = P.levels[0]
+    n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
+    n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
+    runs = {}
+    precs = [("fp64", fsimg.FSIMG_FP64), ("mixed", fsimg.FSIMG_MIXED)]
+    if args.only:
+        precs = [p for p in precs if p[0] == args.only]
+    elif args.no_mixed:
+        precs = precs[:1]
+    for tag, prec in precs:
+        r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass)
+        A = to_csr(lev.systems["mom"])
+        mask = lev.systems["mom"].dirichlet.astype(bool)
+        rr = P.rhs["mom"] - A @ r["x_mom"]
+        rr[mask] = 0.0
+        r["rel_res_host"] = float(np.linalg.norm(rr) / np.linalg.norm(P.rhs["mom"]))
+        Aa = to_csr(lev.systems["ale"])
+        amask = lev.systems["ale"].dirichlet.astype(bool)
+        ra = P.rhs["ale"] - Aa @ r["x_ale"]
+        ra[amask] = 0.0
+        r["rel_res_ale_host"] = float(np.linalg.norm(ra))  # relative to ||r0|| below
+        runs[tag] = r
+        st_m, st_s, st_a = r["stats"]
+        log(f"{tag}: {r['t_step'] * 1e3:.2f} ms/step, momentum {st_m['iters']} it "
+            f"(rel res {r['rel_res_host']:.2e} host), ALE {st_a['iters']} it, "
+            f"mass {st_s['iters'] if st_s else '-'} it; setup {r['t_setup']:.2f} s, "
+            f"factor {r['t_factor']:.2f} s")
+    main_tag = precs[0][0]
+    R = runs[main_tag]
+    s = 8 if main_tag == "fp64" else 4
+    info = R["info_m"]
+    prof = R["prof"]
+    v_ms = sum(p["vanka_ms"] for p in prof)
+    v_n = sum(p["vanka_launches"] for p in prof)
+    s_ms = sum(p["spmv_ms"] for p in prof)
+    s_n = sum(p["spmv_launches"] for p in prof)
+    nl = 27 if P.dim == 3 else 9
+    vb = vanka_bytes(info["npatch"], info["np"], nl, s)
+    sb = spmv_bytes(info["nnzb"], info["nrows"], lev.systems["mom"].b, s)
+    v_avg = v_ms / max(v_n, 1) * 1e-3
+    s_avg = s_ms / max(s_n, 1) * 1e-3
+    v_gbs = vb / v_avg / 1e9 if v_n else 0.0
+    s_gbs = sb / s_avg / 1e9 if s_n else 0.0
+    dominant = ("vanka_patch", v_gbs, vb, v_avg, v_n) if v_ms >= s_ms else ("bsr_spmv_residual", s_gbs, sb, s_avg, s_n)
+    value = (n_mom + n_ale) / R["t_step"]
+    out = {
+        "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
+        "value": value,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["t_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_tag == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 32^3 Q2 hexes, 4 MG levels, "
+                                "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")
+                   if args.config == "c2" else args.config,
+                   "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
+                   "precision": main_tag},
+        "roofline": {"bound": "hbm", "kernel": dominant[0], "achieved": dominant[1],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dominant[1] / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": dominant[2],
+                     "avg_launch_ms": dominant[3] * 1e3, "launches": dominant[4]},
+        "kernels": {"vanka_patch": {"GB/s": v_gbs, "avg_ms": v_avg * 1e3, "launches": v_n,
+                                    "bytes_per_launch": vb},
+                    "bsr_spmv_residual": {"GB/s": s_gbs, "avg_ms": s_avg * 1e3, "launches": s_n,
+                                          "bytes_per_launch": sb}},
+        "solve": {"momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
+                  "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
+                  "rel_res_momentum_fp64_host": R["rel_res_host"],
+                  "setup_s": R["t_setup"], "factor_s": R["t_factor"]},
+    }
+    if "mixed" in runs and main_tag != "mixed":
+        M = runs["mixed"]
+        out["mixed"] = {"value": (n_mom + n_ale) / M["t_step"], "ms_per_step": M["t_step"] * 1e3,
+                        "momentum_iters": M["stats"][0]["iters"], "ale_iters": M["stats"][2]["iters"],
+                        "rel_res_momentum_fp64_host": M["rel_res_host"],
+                        "rel_err_vs_fp64": float(np.linalg.norm(M["x_mom"] - R["x_mom"]) /
+                                                 np.linalg.norm(R["x_mom"])),
+                        "speedup_vs_fp64": R["t_step"] / M["t_step"]}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(P, R["stats"][0]["iters"])
+    log(f"peak host RSS {resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6:.1f} GB")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

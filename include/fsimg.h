@@ -1,0 +1,225 @@
+/*
+ * fsimg — MI355X (gfx950) library for the linear solves inside one
+ * approximate Newton step of a monolithic ALE fluid-structure solver
+ * (Failer & Richter, "A parallel Newton multigrid framework for monolithic
+ * fluid-structure interactions", arXiv:1904.02401).
+ *
+ * The reduced Jacobian of Sec. 4.2 (eq. REDUCEDMATRIX) splits into
+ *   (1) the momentum system in (p, v), eq. problem:1,
+ *   (2) the deformation update on interface/solid dofs, eq. problem:2,
+ *   (3) the ALE extension, eq. problem:3.
+ * (1) and (3) (and, optionally, (2) as a mass-matrix system) are solved by
+ * flexible GMRES (Sec. 4.3 (I)) preconditioned with a geometric multigrid
+ * V-cycle (Sec. 4.3 (II)) whose smoother is the additive Vanka iteration on
+ * element patches (eq. vanka, Sec. 4.3 (III)); (2) is one vector addition
+ * (Sec. 3.1, condensation of the deformation).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are block-CSR (BSR) with square b x b blocks stored row-major,
+ *   the block layout of the paper's linear-algebra module (Sec. 4.3: block
+ *   vectors and block matrices with n_c x n_c blocks).  Structure arrays are
+ *   int32; value offsets are computed in 64 bit.
+ * - Vectors are node-major block vectors: entry (node, component) at
+ *   node * b + component.  Momentum components are (p, v_1, .., v_d).
+ * - Node numbering is lexicographic on a tensor-product Q2 mesh with
+ *   2*cells[a]+1 nodes per axis, x fastest; element patches are the 3^d
+ *   nodes of one cell (Sec. 4.3: "P_i includes all degrees of freedom in one
+ *   element").  Level l+1 is the uniform coarsening of level l.
+ * - Identity ("dirichlet") rows: at those dofs the solution keeps the value
+ *   that x carries in; b is ignored there.  Inhomogeneous data (such as the
+ *   interface deformation of eq. problem:3) are passed in through x.
+ * - Device pointers: every vector argument named *_dev is device memory of
+ *   the context's GPU, owned by the caller; the library never frees caller
+ *   memory.  Host arrays in descriptors are copied during the call and may
+ *   be freed on return.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Work is ordered on it.  Entry points that return results to
+ *   the host (fsimg_solve, fsimg_factor) synchronise the stream.
+ * - Errors: every entry point returns an fsimg_status; nothing is thrown or
+ *   aborted across the ABI.  fsimg_last_error() gives a thread-local message.
+ * - Threading: a context and its hierarchies may be used from one host
+ *   thread at a time.  Calls on different hierarchies that share a stream
+ *   serialise on that stream.
+ */
+#ifndef FSIMG_H
+#define FSIMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSIMG_OK = 0,
+  FSIMG_ERR_ARG = 1,       /* invalid argument (sizes, pointers, options) */
+  FSIMG_ERR_OOM = 2,       /* device allocation failed */
+  FSIMG_ERR_HIP = 3,       /* a HIP runtime call failed */
+  FSIMG_ERR_SINGULAR = 4,  /* zero / tiny pivot in a patch or coarse matrix */
+  FSIMG_ERR_NOCONV = 5,    /* iteration limit reached; x holds the last iterate */
+  FSIMG_ERR_NONFINITE = 6, /* NaN / Inf in the right-hand side or the iteration */
+  FSIMG_ERR_BUDGET = 7,    /* the allocation would exceed the context's HBM budget */
+  FSIMG_ERR_STATE = 8      /* call out of order (e.g. solve before factor) */
+} fsimg_status;
+
+typedef enum { FSIMG_FP64 = 0, FSIMG_MIXED = 1 } fsimg_precision;
+
+/* How the overlapping patch corrections of one Vanka step are summed.
+   GATHER: every patch writes its local correction, then one pass adds, per
+   dof, the contributions of its patches in patch order (no colours needed).
+   PARITY / GREEDY: patches are coloured so that patches of one colour share
+   no node (Sec. 5.5.3); colours are applied one after another and write the
+   solution directly.  PARITY uses the 2^d cell-parity colours, GREEDY the
+   paper's greedy colouring with fluid and solid patches kept apart. */
+typedef enum { FSIMG_VANKA_GATHER = 0, FSIMG_VANKA_PARITY = 1, FSIMG_VANKA_GREEDY = 2 } fsimg_vanka_schedule;
+
+/* Summation weight of overlapping patch corrections (reading of eq. vanka):
+   PLAIN adds them as printed; MULT divides the sum at each dof by the number
+   of element patches that contain it. */
+typedef enum { FSIMG_WEIGHT_PLAIN = 0, FSIMG_WEIGHT_MULT = 1 } fsimg_weighting;
+
+/* One multigrid level; level 0 = finest.  Host arrays, copied. */
+typedef struct {
+  int dim;                  /* 2 or 3 */
+  int block;                /* b: d+1 (momentum) or d (ALE / deformation); 1..4 */
+  int cells[3];             /* cells per axis (unused axes: 1) */
+  int64_t nrows;            /* block rows = prod(2*cells[a]+1) */
+  int64_t nnzb;             /* nonzero blocks */
+  const int32_t *rowptr;    /* [nrows+1] */
+  const int32_t *colind;    /* [nnzb], sorted within each row, diagonal present */
+  const double *vals;       /* [nnzb*b*b] row-major blocks */
+  const uint8_t *dirichlet; /* [nrows*b], 1 = identity row (row must be e_i) */
+  const uint8_t *cell_class; /* [prod(cells)] or NULL: patch class per cell (e.g. 0 fluid,
+                                1 solid); GREEDY colouring never mixes classes in a colour */
+} fsimg_level_desc;
+
+typedef struct {
+  double omega;        /* Vanka damping (Sec. 4.3: omega_V ~ 0.8) */
+  double rtol;         /* stop when ||r||_2 <= rtol * ||r_0||_2 (FP64 residual) */
+  int nu_pre, nu_post; /* Vanka steps before / after the coarse correction */
+  int restart;         /* FGMRES restart length m, 1..32 */
+  int max_iter;        /* total FGMRES iterations */
+  int precision;       /* fsimg_precision */
+  int vanka_schedule;  /* fsimg_vanka_schedule */
+  int vanka_weighting; /* fsimg_weighting */
+  int profile;         /* 1: time the finest-level smoother kernels with events */
+} fsimg_opts;
+
+typedef struct {
+  int status;          /* fsimg_status of the solve */
+  int iters;           /* FGMRES iterations (= V-cycles) */
+  int restarts;        /* completed restart cycles */
+  double rel_res;      /* ||b - A x||_2 / ||r_0||_2 recomputed in FP64 */
+  double solve_ms;     /* host wall time of the solve */
+  /* profile == 1: summed event times (ms) and launch counts of the finest
+     level's Vanka patch kernel and residual SpMV kernel */
+  double vanka_ms; int vanka_launches;
+  double spmv_ms; int spmv_launches;
+} fsimg_stats;
+
+typedef struct {
+  int64_t nrows, n;     /* block rows, scalar unknowns */
+  int64_t nnzb;
+  int64_t npatch;       /* active patches (at least one non-identity dof) */
+  int np;               /* dofs per patch = 3^d * b */
+  int ncolours;         /* colours of the selected schedule (1 for GATHER) */
+  size_t bytes;         /* device bytes held by this level */
+} fsimg_level_info;
+
+typedef struct fsimg_ctx fsimg_ctx;
+typedef struct fsimg_hier fsimg_hier;
+
+/* Default options: omega 0.8, rtol 1e-8, nu 2/2, restart 20, max_iter 200,
+   FP64, GATHER, MULT, no profiling. */
+void fsimg_default_opts(fsimg_opts *opts);
+
+/* Create a context on HIP device `device`; all allocations of hierarchies
+   created in it are charged against hbm_budget_bytes (0 = no limit). */
+fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **out);
+void fsimg_ctx_destroy(fsimg_ctx *ctx);
+size_t fsimg_ctx_bytes_in_use(const fsimg_ctx *ctx);
+
+/* Device bytes a hierarchy with these levels and options will hold. */
+fsimg_status fsimg_hier_footprint(const fsimg_level_desc *levels, int nlev, const fsimg_opts *opts,
+                                  size_t *bytes);
+
+/* Upload the level matrices (H1: structure, FP64 values, FP32 copies in
+   mixed mode, masks), build patch lists, multiplicities, the chosen colouring
+   and the transfer data.  ERR_BUDGET if the footprint exceeds the budget. */
+fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, int nlev,
+                               const fsimg_opts *opts, void *stream, fsimg_hier **out);
+void fsimg_hier_destroy(fsimg_hier *h);
+fsimg_status fsimg_hier_info(const fsimg_hier *h, int level, fsimg_level_info *out);
+
+/* Switch the per-launch HIP-event timing of the finest level's Vanka patch
+   kernel and residual SpMV on (1) or off (0) for the following solves (the
+   `profile` option of fsimg_opts, changeable after creation).  Timing only. */
+fsimg_status fsimg_hier_set_profile(fsimg_hier *h, int on);
+
+/* Replace the values of one level (same structure); on_device != 0 means
+   vals is a device pointer.  Invalidates the factorisation. */
+fsimg_status fsimg_hier_update_values(fsimg_hier *h, int level, const double *vals, int on_device,
+                                      void *stream);
+
+/* Factor: every patch matrix A_i = R_i A R_i^T is inverted exactly (LU with
+   partial pivoting in FP64, Sec. 4.3: local matrices inverted exactly) and
+   stored (FP64, or FP32 in mixed mode); the coarsest matrix is inverted in
+   FP64 (dense Gauss-Jordan with partial pivoting).  ERR_SINGULAR names the
+   level and patch in fsimg_last_error(). */
+fsimg_status fsimg_factor(fsimg_hier *h, void *stream);
+
+/* Solve A x = b on level 0 by FGMRES(m) + V-cycle.  b_dev, x_dev: FP64
+   device vectors of nrows*b; x_dev is the initial guess (and carries the
+   identity-row data) on entry and the solution on return.  stats may be
+   NULL.  Returns OK, NOCONV (x = last iterate) or NONFINITE. */
+fsimg_status fsimg_solve(fsimg_hier *h, const double *b_dev, double *x_dev, fsimg_stats *stats,
+                         void *stream);
+
+/* Condensed deformation update (Sec. 3.1 and eq. problem:2):
+     u_new = u_old + k theta v_new + k (1 - theta) v_old   at nodes with mask != 0,
+     u_new = 0                                            elsewhere.
+   v_new[node*v_stride + v_offset + c], u_old / v_old / u_new [nnodes*dim]
+   (u_old, v_old may be NULL = 0).  All device pointers. */
+fsimg_status fsimg_deform_update(int64_t nnodes, int dim, const uint8_t *mask_dev, double k,
+                                 double theta, const double *v_new_dev, int v_stride, int v_offset,
+                                 const double *u_old_dev, const double *v_old_dev,
+                                 double *u_new_dev, void *stream);
+
+/* ---- single steps of the path (the same kernels the solve uses) ----
+   `precision` selects the buffers: FSIMG_FP64 -> double vectors and FP64
+   matrices / inverses; FSIMG_MIXED -> float vectors and the FP32 copies. */
+
+/* y = A_l x (no masking). */
+fsimg_status fsimg_level_apply(fsimg_hier *h, int level, int precision, const void *x_dev,
+                               void *y_dev, void *stream);
+/* d = b - A_l x, zero at identity rows. */
+fsimg_status fsimg_level_residual(fsimg_hier *h, int level, int precision, const void *b_dev,
+                                  const void *x_dev, void *d_dev, void *stream);
+/* One Vanka step on level l (requires fsimg_factor):
+   d = b - A x; x += omega * W * sum_i R_i^T A_i^{-1} R_i d, identity dofs kept. */
+fsimg_status fsimg_vanka_step(fsimg_hier *h, int level, int precision, const void *b_dev,
+                              void *x_dev, void *stream);
+/* r_c = R r_f from level l to l+1 (R = P^T), zero at coarse identity rows. */
+fsimg_status fsimg_restrict(fsimg_hier *h, int level, int precision, const void *rf_dev,
+                            void *rc_dev, void *stream);
+/* x_f += P x_c from level l+1 to l, then zero at fine identity rows. */
+fsimg_status fsimg_prolong_add(fsimg_hier *h, int level, int precision, const void *xc_dev,
+                               void *xf_dev, void *stream);
+/* x = A_{L-1}^{-1} r on the coarsest level (FP64), zero at identity rows. */
+fsimg_status fsimg_coarse_solve(fsimg_hier *h, const double *r_dev, double *x_dev, void *stream);
+/* z = V-cycle(r) on level 0 (the preconditioner), zero at identity rows. */
+fsimg_status fsimg_vcycle(fsimg_hier *h, int precision, const void *r_dev, void *z_dev,
+                          void *stream);
+/* Copy the stored inverse of one active patch of level l to host memory as a
+   dense row-major n_p x n_p FP64 matrix; *elem receives the patch's cell. */
+fsimg_status fsimg_patch_inverse(fsimg_hier *h, int level, int64_t patch, double *out_host,
+                                 int64_t *elem, void *stream);
+
+const char *fsimg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSIMG_H */

@@ -1,0 +1,97 @@
+// Internal declarations shared by the HIP kernel files and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fsimg.h"
+
+namespace fsimg {
+
+constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
+constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
+
+// One multigrid level on the device.  Vectors of the V-cycle exist in the
+// precision of the hierarchy (T = double for FP64, float for mixed).
+struct DevLevel {
+  int dim = 0, b = 0, nl = 0, np = 0;   // nl = 3^d nodes per patch, np = nl*b
+  int npc64 = 0, npc32 = 0;             // padded column counts of stored inverses
+  int cells[3] = {1, 1, 1}, nnode[3] = {1, 1, 1};
+  int64_t nrows = 0, n = 0, nnzb = 0;
+  int32_t *rowptr = nullptr, *colind = nullptr;
+  double *vals64 = nullptr;
+  float *vals32 = nullptr;
+  uint8_t *mask = nullptr;
+  // Vanka patches (active ones only), ordered by the smoothing schedule
+  int64_t npatch = 0;
+  int32_t *pnodes = nullptr;            // [npatch*nl]
+  std::vector<int64_t> pelem;           // host: cell of each active patch
+  std::vector<int64_t> colour_start;    // host: patch ranges per colour
+  double *inv64 = nullptr;              // [npatch*np*npc64]
+  float *inv32 = nullptr;               // [npatch*np*npc32]
+  int32_t *gptr = nullptr, *gidx = nullptr;  // node -> (patch*nl + local node), patch order
+  double *scale64 = nullptr;            // per node weight of the summed correction
+  float *scale32 = nullptr;
+  // V-cycle work vectors (one precision is allocated)
+  double *r64 = nullptr, *x64 = nullptr, *d64 = nullptr, *Y64 = nullptr;
+  float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *Y32 = nullptr;
+  // coarsest level: dense FP64 inverse
+  double *cinv = nullptr;
+  double *ct0 = nullptr, *ct1 = nullptr;  // FP64 coarse work vectors (mixed mode casts)
+};
+
+// ---------------------------------------------------------------- kernels
+template <typename T>
+void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T *y, bool resid,
+                     hipStream_t s);
+template <typename T>
+void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
+                        int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s);
+template <typename T>
+void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
+                         hipStream_t s);
+template <typename T>
+void launch_restrict(const DevLevel &F, const DevLevel &C, const T *rf, T *rc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const DevLevel &F, const DevLevel &C, const T *xc, T *xf, hipStream_t s);
+template <typename T>
+void launch_fill(T *x, int64_t n, T v, hipStream_t s);
+void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
+void launch_cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+void launch_mask_zero(double *x, const uint8_t *mask, int64_t n, hipStream_t s);
+
+// Krylov (FP64).  Two-stage deterministic reductions: per-block partials,
+// then one block per output in fixed order.
+void launch_multidot(const double *V, int nvec, int64_t n, const double *w, double *partial,
+                     hipStream_t s);
+void launch_axpy_dot(const double *V, int nvec, int64_t n, const double *h, double *w,
+                     double *partial, hipStream_t s);   // w -= V h; partial of V^T w
+void launch_axpy_norm(const double *V, int nvec, int64_t n, const double *h, double *w,
+                      double *partial, hipStream_t s);  // w -= V h; partial of w.w
+void launch_reduce_partials(const double *partial, int nvec, double *out, hipStream_t s);
+void launch_add_small(const double *a, const double *b, double *out, int n, hipStream_t s);
+void launch_scale_by_rsqrt(const double *w, const double *ss, double *v, int64_t n, hipStream_t s);
+void launch_combine(const double *Z, int k, int64_t n, const double *y, double *x, hipStream_t s);
+void launch_nonfinite_count(const double *x, int64_t n, int *flag, hipStream_t s);
+
+// factorisation
+size_t patch_factor_lds_bytes(int np);
+template <typename Tout>
+void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s);
+void launch_densify(const DevLevel &L, double *dense, hipStream_t s);
+void launch_gj_pivot(int64_t n, int64_t k, double *a, int *piv, double *rowk, double *colk,
+                     double thr, int *status, hipStream_t s);
+void launch_gj_update(int64_t n, int64_t k, double *a, const double *rowk, const double *colk,
+                      hipStream_t s);
+void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, double *out,
+                      hipStream_t s);
+void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s);
+void launch_dense_gemv(int64_t n, const double *A, const double *x, const uint8_t *mask, double *y,
+                       hipStream_t s);
+void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
+                   const double *v_new, int v_stride, int v_offset, const double *u_old,
+                   const double *v_old, double *u_new, hipStream_t s);
+
+}  // namespace fsimg

@@ -1,0 +1,523 @@
+// Krylov vector kernels (FP64), patch / coarse factorisation and the
+// deformation update.
+#include <cfloat>
+
+#include "fsimg_internal.h"
+
+namespace fsimg {
+
+namespace {
+
+constexpr int kWave = 64;
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Block sum of one value per thread (256 threads), result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// ----------------------------------------------------------- Krylov kernels
+// V is row-major (nvec x n).  Every thread keeps NV accumulators in registers
+// (compile-time bound, runtime count nvec <= NV), one pass over V and w.
+template <int NV>
+__global__ __launch_bounds__(256) void k_multidot(const double *__restrict__ V, int nvec, int64_t n,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ partial) {
+  __shared__ double red[4];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) acc[k] += V[(int64_t)k * n + i] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if (k < nvec) {
+      const double t = block_sum(acc[k], red);
+      if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nvec + k] = t;
+    }
+}
+
+// w -= V h, then per-block partials of V^T w (MODE 0) or of w.w (MODE 1)
+template <int NV, int MODE>
+__global__ __launch_bounds__(256) void k_axpy_red(const double *__restrict__ V, int nvec, int64_t n,
+                                                  const double *__restrict__ h,
+                                                  double *__restrict__ w,
+                                                  double *__restrict__ partial) {
+  __shared__ double red[4];
+  __shared__ double hs[NV];
+  if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nvec ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[MODE == 0 ? NV : 1];
+#pragma unroll
+  for (int k = 0; k < (MODE == 0 ? NV : 1); ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v[NV];
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) {
+        v[k] = V[(int64_t)k * n + i];
+        wi -= hs[k] * v[k];
+      }
+    w[i] = wi;
+    if (MODE == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (k < nvec) acc[k] += v[k] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) {
+        const double t = block_sum(acc[k], red);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nvec + k] = t;
+      }
+  } else {
+    const double t = block_sum(acc[0], red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  }
+}
+
+// one block per output: sum of kRedBlocks partials in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partial, int nvec,
+                                                         double *__restrict__ out) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  double t = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t += partial[(int64_t)i * nvec + k];
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) out[k] = t;
+}
+
+__global__ void k_add_small(const double *a, const double *b, double *out, int n) {
+  const int i = threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+__global__ __launch_bounds__(256) void k_scale_by_rsqrt(const double *__restrict__ w,
+                                                        const double *__restrict__ ss,
+                                                        double *__restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = w[i] / sqrt(ss[0]);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_combine(const double *__restrict__ Z, int k, int64_t n,
+                                                 const double *__restrict__ y,
+                                                 double *__restrict__ x) {
+  __shared__ double ys[NV];
+  if (threadIdx.x < NV) ys[threadIdx.x] = threadIdx.x < k ? y[threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    if (j < k) s += ys[j] * Z[(int64_t)j * n + i];
+  x[i] += s;
+}
+
+__global__ void k_nonfinite(const double *__restrict__ x, int64_t n, int *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
+}
+
+// -------------------------------------------------- patch factorisation
+// One workgroup per patch: extract A_i = R_i A R_i^T from the block-CSR
+// matrix into LDS (row stride np+1), invert it in place by Gauss-Jordan
+// elimination with partial (row) pivoting in FP64, undo the row interchanges
+// as column interchanges, and store the inverse in the column-group-major
+// layout read by the Vanka apply kernel.
+__device__ __forceinline__ int64_t find_block(const int32_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ colind, int64_t row,
+                                              int32_t col) {
+  int64_t lo = rowptr[row], hi = rowptr[row + 1] - 1;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t c = colind[mid];
+    if (c == col) return mid;
+    if (c < col) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_patch_factor(int64_t npatch, int b, int nl, int np, int npc,
+                                                      const int32_t *__restrict__ pnodes,
+                                                      const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ colind,
+                                                      const double *__restrict__ vals,
+                                                      Tout *__restrict__ inv,
+                                                      int *__restrict__ status) {
+  extern __shared__ double sm[];
+  const int ld = np + 1;
+  double *a = sm;
+  double *rowk = a + (size_t)np * ld;
+  double *colk = rowk + np;
+  int *perm = reinterpret_cast<int *>(colk + np);
+  int *colmap = perm + np;
+  __shared__ double red[4];
+  __shared__ int s_piv;
+  const int tid = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int32_t *pn = pnodes + p * nl;
+  const int bb = b * b;
+  for (int pr = tid; pr < nl * nl; pr += blockDim.x) {
+    const int l1 = pr / nl, l2 = pr - l1 * nl;
+    const int64_t pos = find_block(rowptr, colind, pn[l1], pn[l2]);
+    for (int c1 = 0; c1 < b; ++c1)
+      for (int c2 = 0; c2 < b; ++c2)
+        a[(l1 * b + c1) * ld + l2 * b + c2] = pos >= 0 ? vals[pos * bb + c1 * b + c2] : 0.0;
+  }
+  __syncthreads();
+  // scale for the singularity test: max |a_ij|
+  double m = 0.0;
+  for (int idx = tid; idx < np * np; idx += blockDim.x) {
+    const int i = idx / np, j = idx - i * np;
+    m = fmax(m, fabs(a[i * ld + j]));
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = m;
+  __syncthreads();
+  const double amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double thr = 1e-15 * amax;
+  const int rg = blockDim.x / np;              // row groups
+  const int my_j = tid % np, my_i0 = tid / np;  // column owned in the elimination
+  bool singular = false;
+  for (int k = 0; k < np; ++k) {
+    if (tid < kWave) {  // pivot search in column k, ties to the lowest row
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < np; i += kWave) {
+        const double v = fabs(a[i * ld + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) { s_piv = bi; perm[k] = bi; }
+    }
+    __syncthreads();
+    const int pk = s_piv;
+    if (pk != k)
+      for (int j = tid; j < np; j += blockDim.x) {
+        const double t = a[k * ld + j];
+        a[k * ld + j] = a[pk * ld + j];
+        a[pk * ld + j] = t;
+      }
+    __syncthreads();
+    const double pv = a[k * ld + k];
+    if (!(fabs(pv) > thr)) singular = true;
+    for (int j = tid; j < np; j += blockDim.x) rowk[j] = (j == k ? 1.0 : a[k * ld + j]) / pv;
+    for (int i = tid; i < np; i += blockDim.x) colk[i] = a[i * ld + k];
+    __syncthreads();
+    if (my_i0 < rg) {
+      const double rj = rowk[my_j];
+      for (int i = my_i0; i < np; i += rg) {
+        if (i == k) a[i * ld + my_j] = rj;
+        else a[i * ld + my_j] = (my_j == k ? 0.0 : a[i * ld + my_j]) - colk[i] * rj;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int j = 0; j < np; ++j) colmap[j] = j;
+    for (int k = np - 1; k >= 0; --k) {
+      const int t = colmap[k];
+      colmap[k] = colmap[perm[k]];
+      colmap[perm[k]] = t;
+    }
+    if (singular) {
+      atomicOr(&status[0], 1);
+      atomicMin(&status[1], (int)p);
+    }
+  }
+  __syncthreads();
+  constexpr int G = 16 / sizeof(Tout);
+  Tout *out = inv + p * (int64_t)np * npc;
+  for (int idx = tid; idx < np * npc; idx += blockDim.x) {
+    const int g = idx / (np * G);
+    const int rem = idx - g * np * G;
+    const int r = rem / G, q = rem - r * G;
+    const int c = g * G + q;
+    out[idx] = c < np ? (Tout)a[r * ld + colmap[c]] : Tout(0);
+  }
+}
+
+// ------------------------------------------------------- coarse level
+__global__ __launch_bounds__(256) void k_densify(int64_t nrows, int b,
+                                                 const int32_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ colind,
+                                                 const double *__restrict__ vals,
+                                                 double *__restrict__ dense) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (row >= nrows) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t n = nrows * b;
+  const int bb = b * b;
+  for (int64_t j = rowptr[row]; j < rowptr[row + 1]; ++j) {
+    const int64_t col = colind[j];
+    if (lane < bb) {
+      const int r = lane / b, c = lane - r * b;
+      dense[(row * b + r) * n + col * b + c] = vals[j * bb + lane];
+    }
+  }
+}
+
+// pivot search + row swap + pivot row / column copies for column k (one block)
+__global__ __launch_bounds__(1024) void k_gj_pivot(int64_t n, int64_t k, double *__restrict__ a,
+                                                   int *__restrict__ piv, double *__restrict__ rowk,
+                                                   double *__restrict__ colk, double thr,
+                                                   int *__restrict__ status) {
+  __shared__ double sb[16];
+  __shared__ int si[16];
+  __shared__ int s_p;
+  double best = -1.0;
+  int64_t bi = k;
+  for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
+    const double v = fabs(a[i * n + k]);
+    if (v > best) { best = v; bi = i; }
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o);
+    const int64_t oi = __shfl_xor(bi, o);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { sb[w] = best; si[w] = (int)bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sb[0];
+    int bix = si[0];
+    for (int i = 1; i < (int)(blockDim.x / kWave); ++i)
+      if (sb[i] > bv || (sb[i] == bv && si[i] < bix)) { bv = sb[i]; bix = si[i]; }
+    s_p = bix;
+    piv[k] = bix;
+  }
+  __syncthreads();
+  const int64_t p = s_p;
+  if (p != k)
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+      const double t = a[k * n + j];
+      a[k * n + j] = a[p * n + j];
+      a[p * n + j] = t;
+    }
+  __syncthreads();
+  const double pv = a[k * n + k];
+  if (threadIdx.x == 0 && !(fabs(pv) > thr)) {
+    atomicOr(&status[0], 1);
+    atomicMin(&status[1], (int)k);
+  }
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) rowk[j] = (j == k ? 1.0 : a[k * n + j]) / pv;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) colk[i] = a[i * n + k];
+}
+
+__global__ __launch_bounds__(256) void k_gj_update(int64_t n, int64_t k, double *__restrict__ a,
+                                                   const double *__restrict__ rowk,
+                                                   const double *__restrict__ colk) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= n) return;
+  const int64_t o = i * n + j;
+  if (i == k) a[o] = rowk[j];
+  else a[o] = (j == k ? 0.0 : a[o]) - colk[i] * rowk[j];
+}
+
+__global__ void k_gj_colmap(int64_t n, const int *__restrict__ piv, int *__restrict__ colmap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int64_t j = 0; j < n; ++j) colmap[j] = (int)j;
+  for (int64_t k = n - 1; k >= 0; --k) {
+    const int t = colmap[k];
+    colmap[k] = colmap[piv[k]];
+    colmap[piv[k]] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gj_out(int64_t n, const double *__restrict__ a,
+                                                const int *__restrict__ colmap,
+                                                double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < n) out[i * n + j] = a[i * n + colmap[j]];
+}
+
+__global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ a, int64_t n,
+                                                double *__restrict__ partial) {
+  __shared__ double red[4];
+  double m = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m = fmax(m, fabs(a[i]));
+  for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// y = A x for a dense row-major FP64 matrix, one wavefront per row
+__global__ __launch_bounds__(256) void k_dense_gemv(int64_t n, const double *__restrict__ A,
+                                                    const double *__restrict__ x,
+                                                    const uint8_t *__restrict__ mask,
+                                                    double *__restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (row >= n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const double *ar = A + row * n;
+  double s = 0.0;
+  for (int64_t j = lane; j < n; j += kWave) s += ar[j] * x[j];
+  s = wave_sum(s);
+  if (lane == 0) y[row] = mask[row] ? 0.0 : s;
+}
+
+__global__ __launch_bounds__(256) void k_deform(int64_t nnodes, int dim,
+                                                const uint8_t *__restrict__ mask, double kth,
+                                                double k1, const double *__restrict__ v_new,
+                                                int v_stride, int v_offset,
+                                                const double *__restrict__ u_old,
+                                                const double *__restrict__ v_old,
+                                                double *__restrict__ u_new) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes * dim) return;
+  const int64_t node = i / dim;
+  const int c = (int)(i - node * dim);
+  double u = 0.0;
+  if (mask[node]) {
+    u = kth * v_new[node * v_stride + v_offset + c];
+    if (u_old) u += u_old[i];
+    if (v_old) u += k1 * v_old[i];
+  }
+  u_new[i] = u;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+#define FSIMG_NV_DISPATCH(nvec, KER, ...)                         \
+  do {                                                            \
+    if ((nvec) <= 8) KER(8, __VA_ARGS__);                         \
+    else if ((nvec) <= 16) KER(16, __VA_ARGS__);                  \
+    else KER(32, __VA_ARGS__);                                    \
+  } while (0)
+
+void launch_multidot(const double *V, int nvec, int64_t n, const double *w, double *partial,
+                     hipStream_t s) {
+#define K(NV, dummy)                                                                            \
+  hipLaunchKernelGGL((k_multidot<NV>), dim3(kRedBlocks), dim3(256), 0, s, V, nvec, n, w, partial)
+  FSIMG_NV_DISPATCH(nvec, K, 0);
+#undef K
+}
+void launch_axpy_dot(const double *V, int nvec, int64_t n, const double *h, double *w,
+                     double *partial, hipStream_t s) {
+#define K(NV, dummy)                                                                            \
+  hipLaunchKernelGGL((k_axpy_red<NV, 0>), dim3(kRedBlocks), dim3(256), 0, s, V, nvec, n, h, w,  \
+                     partial)
+  FSIMG_NV_DISPATCH(nvec, K, 0);
+#undef K
+}
+void launch_axpy_norm(const double *V, int nvec, int64_t n, const double *h, double *w,
+                      double *partial, hipStream_t s) {
+#define K(NV, dummy)                                                                            \
+  hipLaunchKernelGGL((k_axpy_red<NV, 1>), dim3(kRedBlocks), dim3(256), 0, s, V, nvec, n, h, w,  \
+                     partial)
+  FSIMG_NV_DISPATCH(nvec, K, 0);
+#undef K
+}
+void launch_reduce_partials(const double *partial, int nvec, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(256), 0, s, partial, nvec, out);
+}
+void launch_add_small(const double *a, const double *b, double *out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_small, dim3(1), dim3(64), 0, s, a, b, out, n);
+}
+void launch_scale_by_rsqrt(const double *w, const double *ss, double *v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by_rsqrt, dim3(grid_for(n, 256)), dim3(256), 0, s, w, ss, v, n);
+}
+void launch_combine(const double *Z, int k, int64_t n, const double *y, double *x, hipStream_t s) {
+#define K(NV, dummy)                                                                            \
+  hipLaunchKernelGGL((k_combine<NV>), dim3(grid_for(n, 256)), dim3(256), 0, s, Z, k, n, y, x)
+  FSIMG_NV_DISPATCH(k, K, 0);
+#undef K
+}
+void launch_nonfinite_count(const double *x, int64_t n, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, flag);
+}
+
+size_t patch_factor_lds_bytes(int np) {
+  return sizeof(double) * ((size_t)np * (np + 1) + 2 * (size_t)np) + 2 * sizeof(int) * (size_t)np;
+}
+
+template <typename Tout>
+void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s) {
+  if (L.npatch == 0) return;
+  const size_t lds = patch_factor_lds_bytes(L.np);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_patch_factor<Tout>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_patch_factor<Tout>), dim3((unsigned)L.npatch), dim3(256), lds, s, L.npatch,
+                     L.b, L.nl, L.np, npc, L.pnodes, L.rowptr, L.colind, L.vals64, inv, status);
+}
+template void launch_patch_factor<double>(const DevLevel &, double *, int, int *, hipStream_t);
+template void launch_patch_factor<float>(const DevLevel &, float *, int, int *, hipStream_t);
+
+void launch_densify(const DevLevel &L, double *dense, hipStream_t s) {
+  hipLaunchKernelGGL(k_densify, dim3(grid_for(L.nrows, 4)), dim3(256), 0, s, L.nrows, L.b,
+                     L.rowptr, L.colind, L.vals64, dense);
+}
+void launch_gj_pivot(int64_t n, int64_t k, double *a, int *piv, double *rowk, double *colk,
+                     double thr, int *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, n, k, a, piv, rowk, colk, thr, status);
+}
+void launch_gj_update(int64_t n, int64_t k, double *a, const double *rowk, const double *colk,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_update, dim3(grid_for(n, 256), (unsigned)n), dim3(256), 0, s, n, k, a,
+                     rowk, colk);
+}
+void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, double *out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_colmap, dim3(1), dim3(64), 0, s, n, piv, colmap);
+  hipLaunchKernelGGL(k_gj_out, dim3(grid_for(n, 256), (unsigned)n), dim3(256), 0, s, n, a, colmap,
+                     out);
+}
+void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(kRedBlocks), dim3(256), 0, s, a, n, partial);
+}
+void launch_dense_gemv(int64_t n, const double *A, const double *x, const uint8_t *mask, double *y,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(n, 4)), dim3(256), 0, s, n, A, x, mask, y);
+}
+void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
+                   const double *v_new, int v_stride, int v_offset, const double *u_old,
+                   const double *v_old, double *u_new, hipStream_t s) {
+  const int64_t n = nnodes * dim;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_deform, dim3(grid_for(n, 256)), dim3(256), 0, s, nnodes, dim, mask,
+                     k * theta, k * (1.0 - theta), v_new, v_stride, v_offset, u_old, v_old, u_new);
+}
+
+}  // namespace fsimg

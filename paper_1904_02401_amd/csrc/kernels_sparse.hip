@@ -1,0 +1,374 @@
+// Bandwidth-bound kernels of the Newton-step solve on gfx950 (wave64):
+// block-CSR residual SpMV, additive Vanka apply, Q2 grid transfers, casts.
+#include "fsimg_internal.h"
+
+namespace fsimg {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int G = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int G = 4; };
+
+__device__ __forceinline__ double vget(const double2 &v, int q) { return q == 0 ? v.x : v.y; }
+__device__ __forceinline__ float vget(const float4 &v, int q) {
+  return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// ------------------------------------------------------------ BSR SpMV
+// One wavefront per block row.  The 64 lanes cover KB = 64 / (B*B) blocks
+// of the row at a time, one matrix entry per lane, so every wave-wide load
+// of block values is a contiguous, fully coalesced 64-entry segment.  The
+// per-lane products are summed over the KB blocks and the B columns of each
+// block row with cross-lane shuffles; lanes 0..B-1 write the B results.
+template <int B, typename T>
+__device__ __forceinline__ T row_reduce(T acc, int lane) {
+  constexpr int BB = B * B;
+  if constexpr ((B & (B - 1)) == 0) {
+    for (int m = 1; m < B; m <<= 1) acc += __shfl_xor(acc, m);
+    for (int m = BB; m < kWave; m <<= 1) acc += __shfl_xor(acc, m);
+    return __shfl(acc, (lane % B) * B);
+  } else {
+    constexpr int KB = kWave / BB;
+    T s = 0;
+#pragma unroll
+    for (int k0 = 0; k0 < KB; ++k0)
+#pragma unroll
+      for (int c = 0; c < B; ++c) s += __shfl(acc, k0 * BB + (lane % B) * B + c);
+    return s;
+  }
+}
+
+template <int B, typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind,
+                                                  const T *__restrict__ vals,
+                                                  const T *__restrict__ x,
+                                                  const T *__restrict__ b,
+                                                  const uint8_t *__restrict__ mask,
+                                                  T *__restrict__ y) {
+  constexpr int BB = B * B;
+  constexpr int KB = kWave / BB;
+  constexpr int ACT = KB * BB;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (row >= nrows) return;  // uniform per wave
+  const int64_t rs = rowptr[row], re = rowptr[row + 1];
+  T acc = 0;
+  if (lane < ACT) {
+    const int k0 = lane / BB, e = lane - k0 * BB, c = e % B;
+#pragma unroll 4
+    for (int64_t j = rs + k0; j < re; j += KB) {
+      const int64_t col = colind[j];
+      acc += vals[j * BB + e] * x[col * B + c];
+    }
+  }
+  const T tot = row_reduce<B, T>(acc, lane);
+  if (lane < B) {
+    const int64_t dof = row * B + lane;
+    if (RESID)
+      y[dof] = mask[dof] ? T(0) : b[dof] - tot;
+    else
+      y[dof] = tot;
+  }
+}
+
+// ------------------------------------------------------------ Vanka apply
+// Each active patch i computes y_i = A_i^{-1} d_i, d_i = R_i d (eq. vanka).
+// A workgroup of 256 threads holds floor(256/np) patches; thread r of a
+// patch owns row r.  The inverse is stored "column-group-major": entry
+// (r, c) at ((c / G) * np + r) * G + c % G with G = 16 bytes / sizeof(T),
+// so at each step the np threads of a patch read one contiguous np*16-byte
+// segment with 16-byte loads.  d_i is gathered once into LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vanka_patch(
+    int64_t p0, int64_t p1, int np, int npc, int b, int nl, int ppw,
+    const int32_t *__restrict__ pnodes, const T *__restrict__ inv, const T *__restrict__ d,
+    T *__restrict__ Y, int scatter, T *__restrict__ x, const T *__restrict__ scale,
+    const uint8_t *__restrict__ mask, T omega) {
+  using V = typename Vec16<T>::type;
+  constexpr int G = Vec16<T>::G;
+  extern __shared__ unsigned char smem_raw[];
+  T *dl = reinterpret_cast<T *>(smem_raw);
+  const int t = threadIdx.x;
+  const int s = t / np;
+  const int r = t - s * np;
+  const int64_t p = p0 + (int64_t)blockIdx.x * ppw + s;
+  const bool act = (s < ppw) && (p < p1);
+  int node = 0, c = 0;
+  if (act) {
+    const int ln = r / b;
+    c = r - ln * b;
+    node = pnodes[p * nl + ln];
+    dl[s * npc + r] = d[(int64_t)node * b + c];
+  }
+  if (s < ppw && r < npc - np) dl[s * npc + np + r] = T(0);
+  __syncthreads();
+  if (!act) return;
+  const V *A = reinterpret_cast<const V *>(inv + p * (int64_t)np * npc) + r;
+  const T *dv = dl + s * npc;
+  T acc = 0;
+  const int ng = npc / G;
+#pragma unroll 6
+  for (int g = 0; g < ng; ++g) {
+    const V v = A[(int64_t)g * np];
+#pragma unroll
+    for (int q = 0; q < G; ++q) acc += vget(v, q) * dv[g * G + q];
+  }
+  if (!scatter) {
+    Y[p * np + r] = acc;
+  } else {
+    const int64_t dof = (int64_t)node * b + c;
+    if (!mask[dof]) x[dof] += omega * scale[node] * acc;
+  }
+}
+
+// Sum, per dof, the corrections of all patches containing its node, in
+// patch order: x += omega * w(node) * sum_i (R_i^T y_i); identity dofs keep x.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vanka_gather(int64_t n, int b,
+                                                      const int32_t *__restrict__ gptr,
+                                                      const int32_t *__restrict__ gidx,
+                                                      const T *__restrict__ Y,
+                                                      const T *__restrict__ scale,
+                                                      const uint8_t *__restrict__ mask, T omega,
+                                                      int assign, T *__restrict__ x) {
+  const int64_t dof = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dof >= n) return;
+  const int64_t node = dof / b;
+  const int c = (int)(dof - node * b);
+  T s = 0;
+  const int e1 = gptr[node + 1];
+  for (int e = gptr[node]; e < e1; ++e) s += Y[(int64_t)gidx[e] * b + c];
+  const T xv = assign ? T(0) : x[dof];
+  x[dof] = mask[dof] ? xv : xv + omega * scale[node] * s;
+}
+
+// ------------------------------------------------------------ Q2 transfers
+// 1D canonical Q2 interpolation between a coarse axis with nc cells and its
+// bisection: fine node i takes coarse node i/2 (i even), else the quadratic
+// Lagrange values at the quarter points of coarse cell i/4.
+template <typename T>
+__device__ __forceinline__ int prolong_1d(int i, int *idx, T *w) {
+  if ((i & 1) == 0) { idx[0] = i >> 1; w[0] = T(1); return 1; }
+  const int e = i >> 2;
+  idx[0] = 2 * e; idx[1] = 2 * e + 1; idx[2] = 2 * e + 2;
+  if ((i & 3) == 1) { w[0] = T(0.375); w[1] = T(0.75); w[2] = T(-0.125); }
+  else { w[0] = T(-0.125); w[1] = T(0.75); w[2] = T(0.375); }
+  return 3;
+}
+// transpose: the fine nodes that coarse node I interpolates into
+template <typename T>
+__device__ __forceinline__ int restrict_1d(int I, int nc, int *idx, T *w) {
+  int k = 0;
+  idx[k] = 2 * I; w[k++] = T(1);
+  if ((I & 1) == 0) {
+    const int e = I >> 1;
+    if (e < nc) { idx[k] = 4 * e + 1; w[k++] = T(0.375); idx[k] = 4 * e + 3; w[k++] = T(-0.125); }
+    if (e >= 1) { idx[k] = 4 * e - 3; w[k++] = T(-0.125); idx[k] = 4 * e - 1; w[k++] = T(0.375); }
+  } else {
+    const int e = (I - 1) >> 1;
+    idx[k] = 4 * e + 1; w[k++] = T(0.75); idx[k] = 4 * e + 3; w[k++] = T(0.75);
+  }
+  return k;
+}
+
+template <int B, int DIM, typename T>
+__global__ __launch_bounds__(256) void k_restrict(int cx, int cy, int cz, const T *__restrict__ rf,
+                                                  T *__restrict__ rc,
+                                                  const uint8_t *__restrict__ maskc) {
+  const int NX = 2 * cx + 1, NY = 2 * cy + 1, NZ = DIM == 3 ? 2 * cz + 1 : 1;
+  const int FX = 4 * cx + 1, FY = 4 * cy + 1;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= (int64_t)NX * NY * NZ) return;
+  const int I = (int)(node % NX), J = (int)((node / NX) % NY), K = (int)(node / ((int64_t)NX * NY));
+  int ix[5], iy[5], iz[5];
+  T wx[5], wy[5], wz[5];
+  const int nx = restrict_1d<T>(I, cx, ix, wx), ny = restrict_1d<T>(J, cy, iy, wy);
+  int nz = 1;
+  iz[0] = 0; wz[0] = T(1);
+  if (DIM == 3) nz = restrict_1d<T>(K, cz, iz, wz);
+  T acc[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc[c] = 0;
+  for (int a = 0; a < nz; ++a)
+    for (int bb = 0; bb < ny; ++bb) {
+      const T wyz = wy[bb] * wz[a];
+      const int64_t base = ((int64_t)iz[a] * FY + iy[bb]) * FX;
+      for (int q = 0; q < nx; ++q) {
+        const T w = wyz * wx[q];
+        const T *src = rf + (base + ix[q]) * B;
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc[c] += w * src[c];
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const int64_t dof = node * B + c;
+    rc[dof] = maskc[dof] ? T(0) : acc[c];
+  }
+}
+
+template <int B, int DIM, typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(int cx, int cy, int cz,
+                                                     const T *__restrict__ xc, T *__restrict__ xf,
+                                                     const uint8_t *__restrict__ maskf) {
+  const int NX = 2 * cx + 1, NY = 2 * cy + 1;
+  const int FX = 4 * cx + 1, FY = 4 * cy + 1, FZ = DIM == 3 ? 4 * cz + 1 : 1;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= (int64_t)FX * FY * FZ) return;
+  const int i = (int)(node % FX), j = (int)((node / FX) % FY), k = (int)(node / ((int64_t)FX * FY));
+  int ix[3], iy[3], iz[3];
+  T wx[3], wy[3], wz[3];
+  const int nx = prolong_1d<T>(i, ix, wx), ny = prolong_1d<T>(j, iy, wy);
+  int nz = 1;
+  iz[0] = 0; wz[0] = T(1);
+  if (DIM == 3) nz = prolong_1d<T>(k, iz, wz);
+  T acc[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc[c] = 0;
+  for (int a = 0; a < nz; ++a)
+    for (int bb = 0; bb < ny; ++bb) {
+      const T wyz = wy[bb] * wz[a];
+      const int64_t base = ((int64_t)iz[a] * NY + iy[bb]) * NX;
+      for (int q = 0; q < nx; ++q) {
+        const T w = wyz * wx[q];
+        const T *src = xc + (base + ix[q]) * B;
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc[c] += w * src[c];
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const int64_t dof = node * B + c;
+    xf[dof] = maskf[dof] ? T(0) : xf[dof] + acc[c];
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T *x, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void k_cast_d2f(const double *x, float *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ void k_cast_f2d(const float *x, double *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+__global__ void k_mask_zero(double *x, const uint8_t *mask, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && mask[i]) x[i] = 0.0;
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T *y, bool resid,
+                     hipStream_t s) {
+  const unsigned grid = grid_for(L.nrows, 4);
+#define FSIMG_SPMV_CASE(BV)                                                                      \
+  case BV:                                                                                       \
+    if (resid)                                                                                   \
+      hipLaunchKernelGGL((k_bsr_spmv<BV, T, true>), dim3(grid), dim3(256), 0, s, L.nrows,        \
+                         L.rowptr, L.colind, vals, x, b, L.mask, y);                             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_bsr_spmv<BV, T, false>), dim3(grid), dim3(256), 0, s, L.nrows,       \
+                         L.rowptr, L.colind, vals, x, b, L.mask, y);                             \
+    break;
+  switch (L.b) {
+    FSIMG_SPMV_CASE(1)
+    FSIMG_SPMV_CASE(2)
+    FSIMG_SPMV_CASE(3)
+    FSIMG_SPMV_CASE(4)
+    default: break;
+  }
+#undef FSIMG_SPMV_CASE
+}
+
+template <typename T>
+void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
+                        int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s) {
+  if (p1 <= p0) return;
+  const int ppw = 256 / L.np;
+  const unsigned grid = grid_for(p1 - p0, ppw);
+  const size_t lds = sizeof(T) * (size_t)ppw * npc;
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(256), lds, s, p0, p1, L.np, npc, L.b,
+                     L.nl, ppw, L.pnodes, inv, d, Y, scatter ? 1 : 0, x, scale, L.mask, omega);
+}
+
+template <typename T>
+void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
+                         hipStream_t s) {
+  hipLaunchKernelGGL((k_vanka_gather<T>), dim3(grid_for(L.n, 256)), dim3(256), 0, s, L.n, L.b,
+                     L.gptr, L.gidx, Y, scale, L.mask, omega, assign ? 1 : 0, x);
+}
+
+template <typename T>
+void launch_restrict(const DevLevel &F, const DevLevel &C, const T *rf, T *rc, hipStream_t s) {
+  const unsigned grid = grid_for(C.nrows, 256);
+#define FSIMG_R(BV, DV)                                                                          \
+  if (C.b == BV && C.dim == DV) {                                                                \
+    hipLaunchKernelGGL((k_restrict<BV, DV, T>), dim3(grid), dim3(256), 0, s, C.cells[0],         \
+                       C.cells[1], C.cells[2], rf, rc, C.mask);                                  \
+    return;                                                                                      \
+  }
+  FSIMG_R(1, 2) FSIMG_R(2, 2) FSIMG_R(3, 2) FSIMG_R(4, 2)
+  FSIMG_R(1, 3) FSIMG_R(2, 3) FSIMG_R(3, 3) FSIMG_R(4, 3)
+#undef FSIMG_R
+  (void)F;
+}
+
+template <typename T>
+void launch_prolong_add(const DevLevel &F, const DevLevel &C, const T *xc, T *xf, hipStream_t s) {
+  const unsigned grid = grid_for(F.nrows, 256);
+#define FSIMG_P(BV, DV)                                                                          \
+  if (F.b == BV && F.dim == DV) {                                                                \
+    hipLaunchKernelGGL((k_prolong_add<BV, DV, T>), dim3(grid), dim3(256), 0, s, C.cells[0],      \
+                       C.cells[1], C.cells[2], xc, xf, F.mask);                                  \
+    return;                                                                                      \
+  }
+  FSIMG_P(1, 2) FSIMG_P(2, 2) FSIMG_P(3, 2) FSIMG_P(4, 2)
+  FSIMG_P(1, 3) FSIMG_P(2, 3) FSIMG_P(3, 3) FSIMG_P(4, 3)
+#undef FSIMG_P
+}
+
+template <typename T>
+void launch_fill(T *x, int64_t n, T v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, v);
+}
+void launch_cast_d2f(const double *x, float *y, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_cast_d2f, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+}
+void launch_cast_f2d(const float *x, double *y, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_cast_f2d, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+}
+void launch_mask_zero(double *x, const uint8_t *mask, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mask_zero, dim3(grid_for(n, 256)), dim3(256), 0, s, x, mask, n);
+}
+
+#define FSIMG_INST(T)                                                                            \
+  template void launch_bsr_spmv<T>(const DevLevel &, const T *, const T *, const T *, T *, bool, \
+                                   hipStream_t);                                                 \
+  template void launch_vanka_patch<T>(const DevLevel &, const T *, int, const T *, T *, int64_t, \
+                                      int64_t, bool, T *, const T *, T, hipStream_t);            \
+  template void launch_vanka_gather<T>(const DevLevel &, const T *, const T *, T, bool, T *,     \
+                                       hipStream_t);                                             \
+  template void launch_restrict<T>(const DevLevel &, const DevLevel &, const T *, T *,           \
+                                   hipStream_t);                                                 \
+  template void launch_prolong_add<T>(const DevLevel &, const DevLevel &, const T *, T *,        \
+                                      hipStream_t);                                              \
+  template void launch_fill<T>(T *, int64_t, T, hipStream_t);
+FSIMG_INST(double)
+FSIMG_INST(float)
+#undef FSIMG_INST
+
+}  // namespace fsimg

@@ -1,0 +1,288 @@
+"""ctypes binding of the fsimg C ABI (include/fsimg.h).
+
+Argument marshalling only: every function forwards to the entry point of the
+same name in libfsimg.so, which runs all numerical work in HIP kernels on the
+GPU.  Device vectors are passed as torch tensors (or raw integer device
+addresses); streams as torch.cuda.Stream, raw hipStream_t integers, or None
+(the current torch stream).  There is no CPU fallback: if the library is
+missing, importing this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsimg.so")
+
+FSIMG_OK, FSIMG_ERR_ARG, FSIMG_ERR_OOM, FSIMG_ERR_HIP, FSIMG_ERR_SINGULAR = 0, 1, 2, 3, 4
+FSIMG_ERR_NOCONV, FSIMG_ERR_NONFINITE, FSIMG_ERR_BUDGET, FSIMG_ERR_STATE = 5, 6, 7, 8
+FSIMG_FP64, FSIMG_MIXED = 0, 1
+FSIMG_VANKA_GATHER, FSIMG_VANKA_PARITY, FSIMG_VANKA_GREEDY = 0, 1, 2
+FSIMG_WEIGHT_PLAIN, FSIMG_WEIGHT_MULT = 0, 1
+
+_STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_SINGULAR",
+                 5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_BUDGET", 8: "ERR_STATE"}
+
+
+class FsimgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"fsimg {_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class fsimg_level_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("block", ctypes.c_int), ("cells", ctypes.c_int * 3),
+                ("nrows", ctypes.c_int64), ("nnzb", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p), ("dirichlet", ctypes.c_void_p),
+                ("cell_class", ctypes.c_void_p)]
+
+
+class fsimg_opts(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("rtol", ctypes.c_double), ("nu_pre", ctypes.c_int),
+                ("nu_post", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("vanka_schedule", ctypes.c_int),
+                ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int)]
+
+
+class fsimg_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("vanka_ms", ctypes.c_double), ("vanka_launches", ctypes.c_int),
+                ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fsimg_level_info(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("n", ctypes.c_int64), ("nnzb", ctypes.c_int64),
+                ("npatch", ctypes.c_int64), ("np", ctypes.c_int), ("ncolours", ctypes.c_int),
+                ("bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# entry point -> argument types
+_P, _I, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "fsimg_default_opts": (None, [ctypes.POINTER(fsimg_opts)]),
+    "fsimg_ctx_create": (_I, [_I, _SZ, ctypes.POINTER(_P)]),
+    "fsimg_ctx_destroy": (None, [_P]),
+    "fsimg_ctx_bytes_in_use": (_SZ, [_P]),
+    "fsimg_hier_footprint": (_I, [ctypes.POINTER(fsimg_level_desc), _I, ctypes.POINTER(fsimg_opts),
+                                  ctypes.POINTER(_SZ)]),
+    "fsimg_hier_create": (_I, [_P, ctypes.POINTER(fsimg_level_desc), _I, ctypes.POINTER(fsimg_opts),
+                               _P, ctypes.POINTER(_P)]),
+    "fsimg_hier_destroy": (None, [_P]),
+    "fsimg_hier_info": (_I, [_P, _I, ctypes.POINTER(fsimg_level_info)]),
+    "fsimg_hier_update_values": (_I, [_P, _I, _P, _I, _P]),
+    "fsimg_hier_set_profile": (_I, [_P, _I]),
+    "fsimg_factor": (_I, [_P, _P]),
+    "fsimg_solve": (_I, [_P, _P, _P, ctypes.POINTER(fsimg_stats), _P]),
+    "fsimg_deform_update": (_I, [_I64, _I, _P, _D, _D, _P, _I, _I, _P, _P, _P, _P]),
+    "fsimg_level_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_level_residual": (_I, [_P, _I, _I, _P, _P, _P, _P]),
+    "fsimg_vanka_step": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_prolong_add": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_coarse_solve": (_I, [_P, _P, _P, _P]),
+    "fsimg_vcycle": (_I, [_P, _I, _P, _P, _P]),
+    "fsimg_patch_inverse": (_I, [_P, _I, _I64, _P, ctypes.POINTER(_I64), _P]),
+    "fsimg_last_error": (ctypes.c_char_p, []),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfsimg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise FsimgError(FSIMG_ERR_STATE, f"{path} not built: run __graft_entry__.build()")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != FSIMG_OK:
+        raise FsimgError(status, load().fsimg_last_error().decode())
+
+
+def _dev(t):
+    """device address of a tensor (or an int address / None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+# ---------------------------------------------------------------- helpers
+def fsimg_default_opts(**overrides) -> fsimg_opts:
+    o = fsimg_opts()
+    load().fsimg_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+class LevelDescs:
+    """Host-side descriptor array for a list of levels; keeps the numpy
+    buffers alive for the duration of a call."""
+
+    def __init__(self, levels):
+        self._keep = []
+        n = len(levels)
+        self.arr = (fsimg_level_desc * n)()
+        for i, lv in enumerate(levels):
+            d = self.arr[i]
+            d.dim, d.block = int(lv["dim"]), int(lv["block"])
+            cells = list(lv["cells"]) + [1] * (3 - len(lv["cells"]))
+            for a in range(3):
+                d.cells[a] = int(cells[a])
+            rp = np.ascontiguousarray(lv["rowptr"], dtype=np.int32)
+            ci = np.ascontiguousarray(lv["colind"], dtype=np.int32)
+            va = np.ascontiguousarray(lv["vals"], dtype=np.float64)
+            di = np.ascontiguousarray(lv["dirichlet"], dtype=np.uint8)
+            cc = lv.get("cell_class")
+            cc = None if cc is None else np.ascontiguousarray(cc, dtype=np.uint8)
+            self._keep += [rp, ci, va, di, cc]
+            d.nrows = rp.shape[0] - 1
+            d.nnzb = ci.shape[0]
+            d.rowptr, d.colind = rp.ctypes.data, ci.ctypes.data
+            d.vals, d.dirichlet = va.ctypes.data, di.ctypes.data
+            d.cell_class = None if cc is None else cc.ctypes.data
+        self.n = n
+
+
+# ------------------------------------------------------------- entry points
+def fsimg_ctx_create(device: int = 0, hbm_budget_bytes: int = 0):
+    out = ctypes.c_void_p()
+    _check(load().fsimg_ctx_create(device, hbm_budget_bytes, ctypes.byref(out)))
+    return out.value
+
+
+def fsimg_ctx_destroy(ctx):
+    load().fsimg_ctx_destroy(ctx)
+
+
+def fsimg_ctx_bytes_in_use(ctx) -> int:
+    return load().fsimg_ctx_bytes_in_use(ctx)
+
+
+def fsimg_hier_footprint(levels, opts) -> int:
+    d = LevelDescs(levels)
+    out = ctypes.c_size_t()
+    _check(load().fsimg_hier_footprint(d.arr, d.n, ctypes.byref(opts), ctypes.byref(out)))
+    return out.value
+
+
+def fsimg_hier_create(ctx, levels, opts, stream=None):
+    d = LevelDescs(levels)
+    out = ctypes.c_void_p()
+    _check(load().fsimg_hier_create(ctx, d.arr, d.n, ctypes.byref(opts), _stream(stream),
+                                    ctypes.byref(out)))
+    return out.value
+
+
+def fsimg_hier_destroy(h):
+    load().fsimg_hier_destroy(h)
+
+
+def fsimg_hier_info(h, level: int) -> dict:
+    info = fsimg_level_info()
+    _check(load().fsimg_hier_info(h, level, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def fsimg_hier_update_values(h, level: int, vals, stream=None):
+    if isinstance(vals, np.ndarray):
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        _check(load().fsimg_hier_update_values(h, level, v.ctypes.data, 0, _stream(stream)))
+    else:
+        _check(load().fsimg_hier_update_values(h, level, _dev(vals), 1, _stream(stream)))
+
+
+def fsimg_hier_set_profile(h, on: int):
+    _check(load().fsimg_hier_set_profile(h, int(on)))
+
+
+def fsimg_factor(h, stream=None):
+    _check(load().fsimg_factor(h, _stream(stream)))
+
+
+def fsimg_solve(h, b, x, stream=None, raise_on_noconv: bool = True) -> dict:
+    st = fsimg_stats()
+    rc = load().fsimg_solve(h, _dev(b), _dev(x), ctypes.byref(st), _stream(stream))
+    if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
+        _check(rc)
+    return st.as_dict()
+
+
+def fsimg_deform_update(nnodes: int, dim: int, mask, k: float, theta: float, v_new, v_stride: int,
+                        v_offset: int, u_old, v_old, u_new, stream=None):
+    _check(load().fsimg_deform_update(nnodes, dim, _dev(mask), k, theta, _dev(v_new), v_stride,
+                                      v_offset, _dev(u_old), _dev(v_old), _dev(u_new),
+                                      _stream(stream)))
+
+
+def fsimg_level_apply(h, level, precision, x, y, stream=None):
+    _check(load().fsimg_level_apply(h, level, precision, _dev(x), _dev(y), _stream(stream)))
+
+
+def fsimg_level_residual(h, level, precision, b, x, d, stream=None):
+    _check(load().fsimg_level_residual(h, level, precision, _dev(b), _dev(x), _dev(d),
+                                       _stream(stream)))
+
+
+def fsimg_vanka_step(h, level, precision, b, x, stream=None):
+    _check(load().fsimg_vanka_step(h, level, precision, _dev(b), _dev(x), _stream(stream)))
+
+
+def fsimg_restrict(h, level, precision, rf, rc, stream=None):
+    _check(load().fsimg_restrict(h, level, precision, _dev(rf), _dev(rc), _stream(stream)))
+
+
+def fsimg_prolong_add(h, level, precision, xc, xf, stream=None):
+    _check(load().fsimg_prolong_add(h, level, precision, _dev(xc), _dev(xf), _stream(stream)))
+
+
+def fsimg_coarse_solve(h, r, x, stream=None):
+    _check(load().fsimg_coarse_solve(h, _dev(r), _dev(x), _stream(stream)))
+
+
+def fsimg_vcycle(h, precision, r, z, stream=None):
+    _check(load().fsimg_vcycle(h, precision, _dev(r), _dev(z), _stream(stream)))
+
+
+def fsimg_patch_inverse(h, level: int, patch: int, stream=None):
+    info = fsimg_hier_info(h, level)
+    npp = info["np"]
+    out = np.empty((npp, npp), dtype=np.float64)
+    elem = ctypes.c_int64()
+    _check(load().fsimg_patch_inverse(h, level, patch, out.ctypes.data, ctypes.byref(elem),
+                                      _stream(stream)))
+    return out, elem.value

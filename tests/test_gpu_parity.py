@@ -1,0 +1,360 @@
+"""GPU path vs the FP64 oracle, step by step and end to end, through the C ABI.
+
+Tolerances: FP64 kernels agree with the oracle up to summation order
+(<= 1e-12 relative); FP32 kernels up to FP32 rounding of the same
+arithmetic (<= 1e-5 relative); solves are judged by their FP64 residual
+recomputed on the host (<= rtol = 1e-8) and reported against the oracle's
+solution."""
+import numpy as np
+import pytest
+
+from fsigen import config_problem
+from oracle import (Hierarchy, VankaData, local_matrices, prolongation, to_csr, vanka_sweep,
+                    vcycle, deform_update)
+from oracle.step import solve_system
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1904_02401_amd import fsimg  # noqa: E402
+from paper_1904_02401_amd.problems import level_dicts  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fsimg.fsimg_ctx_create(0)
+    yield c
+    fsimg.fsimg_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def probs():
+    return {name: config_problem(name, seed=0) for name in ("t2", "t3", "c1")}
+
+
+class Hier:
+    def __init__(self, ctx, prob, system, **opts):
+        self.opts = fsimg.fsimg_default_opts(**opts)
+        self.h = fsimg.fsimg_hier_create(ctx, level_dicts(prob, system), self.opts)
+        self.prob, self.system = prob, system
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        fsimg.fsimg_hier_destroy(self.h)
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+# -------------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("t3", "ale"),
+                                         ("c1", "mom"), ("c1", "mass")])
+def test_spmv_and_residual_fp64(ctx, probs, name, system):
+    P = probs[name]
+    rng = np.random.default_rng(0)
+    with Hier(ctx, P, system) as H:
+        for l, lev in enumerate(P.levels):
+            m = lev.systems[system]
+            A = to_csr(m)
+            x = rng.standard_normal(A.shape[0])
+            b = rng.standard_normal(A.shape[0])
+            y = torch.empty(A.shape[0], device=DEV, dtype=torch.float64)
+            fsimg.fsimg_level_apply(H.h, l, fsimg.FSIMG_FP64, _t(x), y)
+            ref = A @ x
+            assert _rel(_np(y), ref) < 1e-14
+            fsimg.fsimg_level_residual(H.h, l, fsimg.FSIMG_FP64, _t(b), _t(x), y)
+            rr = b - ref
+            rr[m.dirichlet.astype(bool)] = 0.0
+            assert _rel(_np(y), rr) < 1e-14
+
+
+def test_spmv_fp32(ctx, probs):
+    P = probs["t3"]
+    rng = np.random.default_rng(1)
+    with Hier(ctx, P, "mom", precision=fsimg.FSIMG_MIXED) as H:
+        A = to_csr(P.levels[0].systems["mom"])
+        x = rng.standard_normal(A.shape[0]).astype(np.float32)
+        y = torch.empty(A.shape[0], device=DEV, dtype=torch.float32)
+        fsimg.fsimg_level_apply(H.h, 0, fsimg.FSIMG_MIXED, _t(x, torch.float32), y)
+        A32 = A.astype(np.float32).astype(np.float64)
+        ref = A32 @ x.astype(np.float64)
+        # FP32 accumulation over ~62 blocks * 4 terms per row
+        assert np.abs(_np(y) - ref).max() < 1e-5 * np.abs(A32).dot(np.abs(x)).max()
+
+
+# ---------------------------------------------------------------- transfers
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("c1", "ale")])
+def test_transfers_fp64(ctx, probs, name, system):
+    P = probs[name]
+    rng = np.random.default_rng(2)
+    with Hier(ctx, P, system) as H:
+        for l in range(len(P.levels) - 1):
+            mf = P.levels[l].systems[system]
+            mc = P.levels[l + 1].systems[system]
+            Pm = prolongation(P.levels[l + 1].cells, mf.b)
+            rf = rng.standard_normal(Pm.shape[0])
+            rc = torch.empty(Pm.shape[1], device=DEV, dtype=torch.float64)
+            fsimg.fsimg_restrict(H.h, l, fsimg.FSIMG_FP64, _t(rf), rc)
+            ref = Pm.T @ rf
+            ref[mc.dirichlet.astype(bool)] = 0.0
+            assert _rel(_np(rc), ref) < 1e-14
+            xc = rng.standard_normal(Pm.shape[1])
+            xf0 = rng.standard_normal(Pm.shape[0])
+            xf = _t(xf0)
+            fsimg.fsimg_prolong_add(H.h, l, fsimg.FSIMG_FP64, _t(xc), xf)
+            ref = xf0 + Pm @ xc
+            ref[mf.dirichlet.astype(bool)] = 0.0
+            assert _rel(_np(xf), ref) < 1e-14
+
+
+# ------------------------------------------------------------ factorisation
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("t3", "ale"), ("t3", "mass")])
+def test_patch_inverses_fp64(ctx, probs, name, system):
+    P = probs[name]
+    lev = P.levels[0]
+    m = lev.systems[system]
+    with Hier(ctx, P, system) as H:
+        fsimg.fsimg_factor(H.h)
+        info = fsimg.fsimg_hier_info(H.h, 0)
+        assert info["npatch"] > 0
+        idx = np.unique(np.linspace(0, info["npatch"] - 1, 12).astype(int))
+        for p in idx:
+            X, elem = fsimg.fsimg_patch_inverse(H.h, 0, int(p))
+            Ai = local_matrices(m, lev.cells, np.array([elem]))[0]
+            Xref = np.linalg.inv(Ai)
+            cond = np.linalg.cond(Ai)
+            assert _rel(X, Xref) < 1e-15 * cond * 100
+            assert np.abs(Ai @ X - np.eye(Ai.shape[0])).max() < 1e-15 * cond * 100
+
+
+def test_patch_inverses_fp32_storage(ctx, probs):
+    P = probs["t3"]
+    lev = P.levels[0]
+    m = lev.systems["mom"]
+    with Hier(ctx, P, "mom", precision=fsimg.FSIMG_MIXED) as H:
+        fsimg.fsimg_factor(H.h)
+        for p in (0, 17, 100):
+            X, elem = fsimg.fsimg_patch_inverse(H.h, 0, p)
+            Xref = np.linalg.inv(local_matrices(m, lev.cells, np.array([elem]))[0])
+            # computed in FP64, rounded once to FP32
+            assert np.abs(X - Xref).max() <= 1e-7 * np.abs(Xref).max()
+
+
+# --------------------------------------------------------------- smoothing
+@pytest.mark.parametrize("schedule", [fsimg.FSIMG_VANKA_GATHER, fsimg.FSIMG_VANKA_PARITY,
+                                      fsimg.FSIMG_VANKA_GREEDY])
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("t3", "ale")])
+def test_vanka_step_fp64(ctx, probs, name, system, schedule):
+    P = probs[name]
+    lev = P.levels[0]
+    m = lev.systems[system]
+    A = to_csr(m)
+    mask = m.dirichlet.astype(bool)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.shape[0])
+    b[mask] = 0.0
+    x0 = rng.standard_normal(A.shape[0]) * 0.1
+    x0[mask] = 0.0
+    V = VankaData.build(m, lev.cells, omega=0.8, weighting="mult")
+    ref = vanka_sweep(A, b, x0, V, mask)
+    with Hier(ctx, P, system, vanka_schedule=schedule) as H:
+        fsimg.fsimg_factor(H.h)
+        x = _t(x0)
+        fsimg.fsimg_vanka_step(H.h, 0, fsimg.FSIMG_FP64, _t(b), x)
+        assert _rel(_np(x) - x0, ref - x0) < 1e-11
+        info = fsimg.fsimg_hier_info(H.h, 0)
+        if schedule == fsimg.FSIMG_VANKA_PARITY:
+            assert info["ncolours"] == 2 ** P.dim
+        elif schedule == fsimg.FSIMG_VANKA_GREEDY:
+            assert info["ncolours"] >= 2 ** P.dim
+
+
+def test_vanka_plain_weighting(ctx, probs):
+    P = probs["t2"]
+    lev = P.levels[0]
+    m = lev.systems["mom"]
+    A = to_csr(m)
+    mask = m.dirichlet.astype(bool)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(A.shape[0])
+    b[mask] = 0.0
+    V = VankaData.build(m, lev.cells, omega=0.8, weighting="plain")
+    ref = vanka_sweep(A, b, np.zeros_like(b), V, mask)
+    with Hier(ctx, P, "mom", vanka_weighting=fsimg.FSIMG_WEIGHT_PLAIN) as H:
+        fsimg.fsimg_factor(H.h)
+        x = torch.zeros(A.shape[0], device=DEV, dtype=torch.float64)
+        fsimg.fsimg_vanka_step(H.h, 0, fsimg.FSIMG_FP64, _t(b), x)
+        assert _rel(_np(x), ref) < 1e-11
+
+
+# ------------------------------------------------------------ coarse / V-cycle
+@pytest.mark.parametrize("name", ["t2", "t3", "c1"])
+def test_coarse_solve_and_vcycle_fp64(ctx, probs, name):
+    P = probs[name]
+    mats = P.system("mom")
+    cells = [lv.cells for lv in P.levels]
+    Ho = Hierarchy(mats, cells, omega=0.8, weighting="mult")
+    rng = np.random.default_rng(5)
+    with Hier(ctx, P, "mom") as H:
+        fsimg.fsimg_factor(H.h)
+        mc = mats[-1]
+        rc = rng.standard_normal(mc.nrows * mc.b)
+        rc[mc.dirichlet.astype(bool)] = 0.0
+        xc = torch.empty_like(_t(rc))
+        fsimg.fsimg_coarse_solve(H.h, _t(rc), xc)
+        assert _rel(_np(xc), Ho.coarse_solve(rc)) < 1e-10
+        r = rng.standard_normal(mats[0].nrows * mats[0].b)
+        r[mats[0].dirichlet.astype(bool)] = 0.0
+        z = torch.empty_like(_t(r))
+        fsimg.fsimg_vcycle(H.h, fsimg.FSIMG_FP64, _t(r), z)
+        assert _rel(_np(z), vcycle(Ho, r)) < 1e-10
+
+
+def test_vcycle_mixed_close_to_fp64(ctx, probs):
+    P = probs["t3"]
+    mats = P.system("mom")
+    cells = [lv.cells for lv in P.levels]
+    Ho = Hierarchy(mats, cells, omega=0.8, weighting="mult")
+    r = np.random.default_rng(6).standard_normal(mats[0].nrows * mats[0].b)
+    r[mats[0].dirichlet.astype(bool)] = 0.0
+    with Hier(ctx, P, "mom", precision=fsimg.FSIMG_MIXED) as H:
+        fsimg.fsimg_factor(H.h)
+        z = torch.empty(r.shape[0], device=DEV, dtype=torch.float32)
+        fsimg.fsimg_vcycle(H.h, fsimg.FSIMG_MIXED, _t(r, torch.float32), z)
+        assert _rel(_np(z), vcycle(Ho, r)) < 1e-3
+
+
+# ------------------------------------------------------------------ solves
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("c1", "mom"), ("c1", "ale"),
+                                         ("t3", "ale")])
+def test_solve_residual_checked_on_host(ctx, probs, name, system, precision):
+    P = probs[name]
+    m = P.levels[0].systems[system]
+    A = to_csr(m)
+    mask = m.dirichlet.astype(bool)
+    b = P.rhs[system]
+    x0 = np.zeros_like(b)
+    if system == "ale":  # interface / solid data in x0
+        x0[mask] = np.random.default_rng(7).standard_normal(int(mask.sum())) * 1e-3
+    with Hier(ctx, P, system, precision=precision) as H:
+        fsimg.fsimg_factor(H.h)
+        x = _t(x0)
+        st = fsimg.fsimg_solve(H.h, _t(b), x)
+        xh = _np(x)
+    r0 = b - A @ x0
+    r0[mask] = 0.0
+    r = b - A @ xh
+    r[mask] = 0.0
+    rel = np.linalg.norm(r) / np.linalg.norm(r0)
+    assert rel <= 1e-8 * 1.01, (rel, st)
+    assert abs(rel - st["rel_res"]) <= 1e-3 * rel + 1e-14
+    np.testing.assert_array_equal(xh[mask], x0[mask])
+    cells = [lv.cells for lv in P.levels]
+    xo, info, _ = solve_system(P.system(system), cells, b, x0=x0, rtol=1e-10, weighting="mult")
+    assert _rel(xh, xo) < 1e-5
+    if precision == fsimg.FSIMG_FP64:
+        assert abs(st["iters"] - info["iters"]) <= 3  # same method, same iteration count
+
+
+def test_deform_update_and_ale_chain(ctx, probs):
+    """Momentum solve -> condensed deformation update (kernel) -> ALE solve with
+    the interface / solid increments as data; compared with the oracle chain."""
+    from oracle.step import newton_step_solve
+    P = probs["t3"]
+    lev = P.levels[0]
+    k, th = P.params["k"], P.params["theta"]
+    nn = lev.nnodes
+    mask_nodes = _t(lev.node_solid, torch.uint8)
+    # plain condensation identity on the state
+    un = torch.empty(nn * 3, device=DEV, dtype=torch.float64)
+    fsimg.fsimg_deform_update(nn, 3, mask_nodes, k, th, _t(P.v_cur.ravel()), 3, 0,
+                              _t(P.u_old.ravel()), _t(P.v_old.ravel()), un)
+    ref = deform_update(lev.node_solid.astype(bool), k, th, P.v_cur, u_old=P.u_old, v_old=P.v_old)
+    np.testing.assert_allclose(_np(un).reshape(nn, 3), ref, rtol=1e-15, atol=1e-18)
+    # full chain
+    out = newton_step_solve(P, rtol=1e-10, weighting="mult")
+    with Hier(ctx, P, "mom") as Hm, Hier(ctx, P, "ale") as Ha:
+        fsimg.fsimg_factor(Hm.h)
+        fsimg.fsimg_factor(Ha.h)
+        xm = torch.zeros(nn * 4, device=DEV, dtype=torch.float64)
+        fsimg.fsimg_solve(Hm.h, _t(P.rhs["mom"]), xm)
+        du = torch.empty(nn * 3, device=DEV, dtype=torch.float64)
+        fsimg.fsimg_deform_update(nn, 3, mask_nodes, k, th, xm, 4, 1, None, None, du)
+        lift = _np(du)
+        fsimg.fsimg_solve(Ha.h, _t(P.rhs["ale"]), du)
+        xa = _np(du)
+    assert _rel(lift, out["lift"]) < 1e-5
+    assert _rel(xa, out["du"]) < 1e-5
+    m = lev.systems["ale"]
+    mask = m.dirichlet.astype(bool)
+    np.testing.assert_array_equal(xa[mask], lift[mask])
+
+
+# ------------------------------------------------------------- error paths
+def test_error_paths(ctx, probs):
+    P = probs["t2"]
+    # singular patch: zero a non-identity row block of the finest level
+    levels = level_dicts(P, "mom")
+    vals = levels[0]["vals"].copy()
+    m = P.levels[0].systems["mom"]
+    row = 2 * (2 * P.levels[0].cells[0] + 1) + 2  # an interior node
+    vals[m.rowptr[row]:m.rowptr[row + 1]] = 0.0
+    levels[0] = dict(levels[0], vals=vals)
+    opts = fsimg.fsimg_default_opts()
+    h = fsimg.fsimg_hier_create(ctx, levels, opts)
+    try:
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_factor(h)
+        assert ei.value.status == fsimg.FSIMG_ERR_SINGULAR
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+    with Hier(ctx, P, "mom", max_iter=1) as H:
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_solve(H.h, _t(P.rhs["mom"]), torch.zeros(m.nrows * 3, device=DEV, dtype=torch.float64))
+        assert ei.value.status == fsimg.FSIMG_ERR_STATE  # not factored
+        fsimg.fsimg_factor(H.h)
+        x = torch.zeros(m.nrows * 3, device=DEV, dtype=torch.float64)
+        st = fsimg.fsimg_solve(H.h, _t(P.rhs["mom"]), x, raise_on_noconv=False)
+        assert st["status"] == fsimg.FSIMG_ERR_NOCONV and st["iters"] == 1
+        bn = P.rhs["mom"].copy()
+        bn[int(np.nonzero(m.dirichlet == 0)[0][7])] = np.nan  # a non-identity row
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_solve(H.h, _t(bn), torch.zeros_like(x))
+        assert ei.value.status == fsimg.FSIMG_ERR_NONFINITE
+    small = fsimg.fsimg_ctx_create(0, 1 << 20)
+    try:
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_hier_create(small, level_dicts(P, "mom"), fsimg.fsimg_default_opts())
+        assert ei.value.status == fsimg.FSIMG_ERR_BUDGET
+        assert fsimg.fsimg_ctx_bytes_in_use(small) == 0
+    finally:
+        fsimg.fsimg_ctx_destroy(small)
+
+
+def test_deterministic_repeat(ctx, probs):
+    P = probs["t3"]
+    with Hier(ctx, P, "mom") as H:
+        fsimg.fsimg_factor(H.h)
+        xs = []
+        for _ in range(2):
+            x = torch.zeros(P.rhs["mom"].shape[0], device=DEV, dtype=torch.float64)
+            fsimg.fsimg_solve(H.h, _t(P.rhs["mom"]), x)
+            xs.append(_np(x))
+    np.testing.assert_array_equal(xs[0], xs[1])
