@@ -43,6 +43,67 @@ def spmv_bytes(nnzb, nrows, b, s):
     return nnzb * (b * b * s + 4) + 4 * (nrows + 1) + 3 * nrows * b * s + nrows * b
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch recorded from rocprofv3 counters, or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_1904_02401_amd", "csrc", "kernels_sparse.hip")
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and not line.startswith("#") and f[0] == kernel and f[1] == workload:
+            return float(f[2]) if f[3] == cur else None
+    return None
+
+
+def _split_err(x, ref, b):
+    """relative 2-norm error of the velocity and of the pressure components
+    (their scales differ by orders of magnitude)."""
+    import numpy as np
+    x, ref = x.reshape(-1, b), ref.reshape(-1, b)
+    out = {}
+    for name, sl in (("velocity", slice(1, b)), ("pressure", slice(0, 1))):
+        out[name] = float(np.linalg.norm(x[:, sl] - ref[:, sl]) / max(np.linalg.norm(ref[:, sl]), 1e-300))
+    return out
+
+
+def kernels_only(P, precision, reps):
+    """Launch only the finest-level smoother step (residual SpMV + Vanka patch
+    kernel + gather) of the momentum system `reps` times: the workload of the
+    hardware-counter runs."""
+    import torch
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import level_dicts
+    ctx = fsimg.fsimg_ctx_create(0)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), fsimg.fsimg_default_opts(precision=precision))
+    fsimg.fsimg_factor(h)
+    dt = torch.float64 if precision == fsimg.FSIMG_FP64 else torch.float32
+    b = torch.tensor(P.rhs["mom"], device="cuda:0", dtype=dt)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        fsimg.fsimg_vanka_step(h, 0, precision, b, x)
+    torch.cuda.synchronize()
+    fsimg.fsimg_hier_destroy(h)
+    fsimg.fsimg_ctx_destroy(ctx)
+    log(f"kernels-only: {reps} finest-level smoothing steps done")
+
+
+def calib_copy(nbytes, reps):
+    """Plain device-to-device copy of a known size (counter calibration)."""
+    import torch
+    a = torch.empty(nbytes // 8, device="cuda:0", dtype=torch.float64).fill_(1.0)
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    log(f"calib-copy: {reps} copies of {nbytes} bytes")
+
+
 def run_gpu(P, precision, steps, warmup, with_mass=True):
     import torch
     from paper_1904_02401_amd import fsimg
@@ -161,7 +222,14 @@ def main():
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
+    ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
+                    help="only launch REPS finest-level smoothing steps (counter runs)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy(args.calib_copy << 20, 5)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"sharding of this path is described in DESIGN.md and not built", file=sys.stderr)
@@ -174,6 +242,10 @@ def main():
     P = config_problem(args.config, seed=0)
     log(f"problem {args.config} generated in {time.perf_counter() - t0:.1f} s")
     from paper_1904_02401_amd import fsimg
+    if args.kernels_only:
+        kernels_only(P, fsimg.FSIMG_MIXED if args.only == "mixed" else fsimg.FSIMG_FP64,
+                     args.kernels_only)
+        return
     lev = P.levels[0]
     n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
     n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
@@ -217,7 +289,11 @@ def main():
     s_avg = s_ms / max(s_n, 1) * 1e-3
     v_gbs = vb / v_avg / 1e9 if v_n else 0.0
     s_gbs = sb / s_avg / 1e9 if s_n else 0.0
-    dominant = ("vanka_patch", v_gbs, vb, v_avg, v_n) if v_ms >= s_ms else ("bsr_spmv_residual", s_gbs, sb, s_avg, s_n)
+    tname = "double" if main_tag == "fp64" else "float"
+    bm = lev.systems["mom"].b
+    dominant = ((f"k_vanka_patch<{tname}>", v_gbs, vb, v_avg, v_n) if v_ms >= s_ms
+                else (f"k_bsr_spmv<{bm},{tname},true>", s_gbs, sb, s_avg, s_n))
+    traffic = measured_traffic(dominant[0], f"{args.config}-momentum-level0")
     value = (n_mom + n_ale) / R["t_step"]
     out = {
         "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
@@ -239,7 +315,7 @@ def main():
                    "precision": main_tag},
         "roofline": {"bound": "hbm", "kernel": dominant[0], "achieved": dominant[1],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dominant[1] / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": dominant[2],
+                     "traffic": traffic, "bytes_per_launch": dominant[2],
                      "avg_launch_ms": dominant[3] * 1e3, "launches": dominant[4]},
         "kernels": {"vanka_patch": {"GB/s": v_gbs, "avg_ms": v_avg * 1e3, "launches": v_n,
                                     "bytes_per_launch": vb},
@@ -255,8 +331,7 @@ def main():
         out["mixed"] = {"value": (n_mom + n_ale) / M["t_step"], "ms_per_step": M["t_step"] * 1e3,
                         "momentum_iters": M["stats"][0]["iters"], "ale_iters": M["stats"][2]["iters"],
                         "rel_res_momentum_fp64_host": M["rel_res_host"],
-                        "rel_err_vs_fp64": float(np.linalg.norm(M["x_mom"] - R["x_mom"]) /
-                                                 np.linalg.norm(R["x_mom"])),
+                        "rel_err_vs_fp64": _split_err(M["x_mom"], R["x_mom"], P.dim + 1),
                         "speedup_vs_fp64": R["t_step"] / M["t_step"]}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")

@@ -281,3 +281,27 @@ def test_condensation_identity_and_mass_solve(prob_t3):
     r[amask] = 0.0
     assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(
         np.where(amask, 0.0, P.rhs["ale"] - Aa @ out["lift"]))
+
+
+def test_vanka_sum_reading_plain_diverges_averaged_contracts(prob_t2):
+    """Reading of the overlapping sum in eq. (vanka): as a stationary
+    multigrid iteration x += Vcycle(b - A x), the printed plain sum with
+    omega = 0.8 diverges on element patches, the multiplicity-averaged sum
+    contracts."""
+    mats = prob_t2.system("mom")
+    cells = [lv.cells for lv in prob_t2.levels]
+    b = prob_t2.rhs["mom"]
+    rates = {}
+    for wt in ("plain", "mult"):
+        H = Hierarchy(mats, cells, omega=0.8, weighting=wt)
+        A, mask = H.levels[0].A, H.levels[0].mask
+        x = np.zeros_like(b)
+        for _ in range(8):
+            r = b - A @ x
+            r[mask] = 0.0
+            x = x + vcycle(H, r)
+        r = b - A @ x
+        r[mask] = 0.0
+        rates[wt] = (np.linalg.norm(r) / np.linalg.norm(b)) ** (1 / 8)
+    assert rates["plain"] > 1.0
+    assert rates["mult"] < 0.6
