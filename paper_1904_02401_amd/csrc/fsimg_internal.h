@@ -49,6 +49,7 @@ void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T
 template <typename T>
 void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
                         int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s);
+void vanka_shape(int np, int *ppw, int *threads);
 template <typename T>
 void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
                          hipStream_t s);

@@ -18,11 +18,17 @@ __device__ __forceinline__ float vget(const float4 &v, int q) {
 }
 
 // ------------------------------------------------------------ BSR SpMV
-// One wavefront per block row.  The 64 lanes cover KB = 64 / (B*B) blocks
-// of the row at a time, one matrix entry per lane, so every wave-wide load
-// of block values is a contiguous, fully coalesced 64-entry segment.  The
-// per-lane products are summed over the KB blocks and the B columns of each
-// block row with cross-lane shuffles; lanes 0..B-1 write the B results.
+// One wavefront per block row.  The row's column indices (at most 128
+// blocks, the Q2 maximum is 125) are loaded once with one coalesced load and
+// broadcast by cross-lane shuffles, so no global load depends on another
+// inside the row: every value / x load of the row is issued in one fully
+// unrolled, predicated sweep.  Rows longer than 128 blocks take a plain loop.
+//
+// b = 4: each lane loads 16 bytes of a block (2 doubles / 4 floats) and the
+// matching 16 bytes of x, so a wave covers 8 (FP64) or 16 (FP32) blocks per
+// step with 1 KB coalesced value loads.  Other b: one entry per lane,
+// 64 / b^2 blocks per step.  Partial products are summed across lanes with
+// xor-shuffles; lanes 0..b-1 write the b results of the row.
 template <int B, typename T>
 __device__ __forceinline__ T row_reduce(T acc, int lane) {
   constexpr int BB = B * B;
@@ -41,6 +47,73 @@ __device__ __forceinline__ T row_reduce(T acc, int lane) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T dot16(const typename Vec16<T>::type &a, const typename Vec16<T>::type &b);
+template <>
+__device__ __forceinline__ double dot16<double>(const double2 &a, const double2 &b) {
+  return a.x * b.x + a.y * b.y;
+}
+template <>
+__device__ __forceinline__ float dot16<float>(const float4 &a, const float4 &b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+}
+
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_bsr4_spmv(int64_t nrows, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ colind,
+                                                   const T *__restrict__ vals,
+                                                   const T *__restrict__ x,
+                                                   const T *__restrict__ b,
+                                                   const uint8_t *__restrict__ mask,
+                                                   T *__restrict__ y) {
+  using V = typename Vec16<T>::type;
+  constexpr int G = Vec16<T>::G;   // entries per 16-byte load
+  constexpr int LPB = 16 / G;      // lanes per 4x4 block
+  constexpr int KB = kWave / LPB;  // blocks per wave step
+  constexpr int MAXT = 128 / KB;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (row >= nrows) return;  // uniform per wave
+  const int64_t rs = rowptr[row];
+  const int nb = (int)(rowptr[row + 1] - rs);
+  const int k0 = lane / LPB, q = lane - k0 * LPB;
+  const int cofs = (q * G) & 3;
+  const T *vrow = vals + rs * 16 + q * G;
+  T acc = 0;
+  if (nb <= 128) {
+    const int c0 = lane < nb ? colind[rs + lane] : 0;
+    const int c1 = lane + kWave < nb ? colind[rs + kWave + lane] : 0;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      const int jj = t * KB + k0;
+      const int col = __shfl(t * KB < kWave ? c0 : c1, jj & (kWave - 1));
+      if (jj < nb) {
+        const V a = *reinterpret_cast<const V *>(vrow + (int64_t)jj * 16);
+        const V xv = *reinterpret_cast<const V *>(x + (int64_t)col * 4 + cofs);
+        acc += dot16<T>(a, xv);
+      }
+    }
+  } else {
+    for (int jj = k0; jj < nb; jj += KB) {
+      const int col = colind[rs + jj];
+      const V a = *reinterpret_cast<const V *>(vrow + (int64_t)jj * 16);
+      const V xv = *reinterpret_cast<const V *>(x + (int64_t)col * 4 + cofs);
+      acc += dot16<T>(a, xv);
+    }
+  }
+  // lanes holding block row r: q * G / 4 == r; sum over them and over k0
+  for (int m = 1; m < 4 / G; m <<= 1) acc += __shfl_xor(acc, m);
+  for (int m = LPB; m < kWave; m <<= 1) acc += __shfl_xor(acc, m);
+  const T tot = __shfl(acc, (lane & 3) * (4 / G));
+  if (lane < 4) {
+    const int64_t dof = row * 4 + lane;
+    if (RESID)
+      y[dof] = mask[dof] ? T(0) : b[dof] - tot;
+    else
+      y[dof] = tot;
+  }
+}
+
 template <int B, typename T, bool RESID>
 __global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ colind,
@@ -52,18 +125,28 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *
   constexpr int BB = B * B;
   constexpr int KB = kWave / BB;
   constexpr int ACT = KB * BB;
+  constexpr int MAXT = (128 + KB - 1) / KB;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (row >= nrows) return;  // uniform per wave
-  const int64_t rs = rowptr[row], re = rowptr[row + 1];
+  const int64_t rs = rowptr[row];
+  const int nb = (int)(rowptr[row + 1] - rs);
+  const int k0 = lane / BB, e = lane - k0 * BB, c = e % B;
+  const bool on = lane < ACT;
   T acc = 0;
-  if (lane < ACT) {
-    const int k0 = lane / BB, e = lane - k0 * BB, c = e % B;
-#pragma unroll 4
-    for (int64_t j = rs + k0; j < re; j += KB) {
-      const int64_t col = colind[j];
-      acc += vals[j * BB + e] * x[col * B + c];
+  if (nb <= 128) {
+    const int c0 = lane < nb ? colind[rs + lane] : 0;
+    const int c1 = lane + kWave < nb ? colind[rs + kWave + lane] : 0;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      const int jj = t * KB + k0;
+      const int ca = __shfl(c0, jj & (kWave - 1));
+      const int cb = __shfl(c1, jj & (kWave - 1));
+      const int col = jj < kWave ? ca : cb;
+      if (on && jj < nb) acc += vals[(rs + jj) * BB + e] * x[(int64_t)col * B + c];
     }
+  } else if (on) {
+    for (int jj = k0; jj < nb; jj += KB) acc += vals[(rs + jj) * BB + e] * x[(int64_t)colind[rs + jj] * B + c];
   }
   const T tot = row_reduce<B, T>(acc, lane);
   if (lane < B) {
@@ -77,13 +160,13 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *
 
 // ------------------------------------------------------------ Vanka apply
 // Each active patch i computes y_i = A_i^{-1} d_i, d_i = R_i d (eq. vanka).
-// A workgroup of 256 threads holds floor(256/np) patches; thread r of a
-// patch owns row r.  The inverse is stored "column-group-major": entry
+// A workgroup holds ppw patches (vanka_shape: e.g. 7 patches of 108 rows in
+// 768 threads, 98% of the lanes busy); thread r of a patch owns row r.  The inverse is stored "column-group-major": entry
 // (r, c) at ((c / G) * np + r) * G + c % G with G = 16 bytes / sizeof(T),
 // so at each step the np threads of a patch read one contiguous np*16-byte
 // segment with 16-byte loads.  d_i is gathered once into LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_vanka_patch(
+__global__ __launch_bounds__(1024) void k_vanka_patch(
     int64_t p0, int64_t p1, int np, int npc, int b, int nl, int ppw,
     const int32_t *__restrict__ pnodes, const T *__restrict__ inv, const T *__restrict__ d,
     T *__restrict__ Y, int scatter, T *__restrict__ x, const T *__restrict__ scale,
@@ -271,6 +354,18 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 }  // namespace
 
+// Patches per workgroup for the Vanka apply: the workgroup holds ppw patches
+// of np row-threads rounded up to whole wavefronts; choose the ppw that
+// leaves the fewest idle lanes (ties: the smaller workgroup).
+void vanka_shape(int np, int *ppw, int *threads) {
+  double best = -1.0;
+  for (int p = 1; p * np <= 1024; ++p) {
+    const int t = (p * np + 63) / 64 * 64;
+    const double u = (double)(p * np) / t;
+    if (u > best + 1e-12) { best = u; *ppw = p; *threads = t; }
+  }
+}
+
 template <typename T>
 void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T *y, bool resid,
                      hipStream_t s) {
@@ -288,7 +383,14 @@ void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T
     FSIMG_SPMV_CASE(1)
     FSIMG_SPMV_CASE(2)
     FSIMG_SPMV_CASE(3)
-    FSIMG_SPMV_CASE(4)
+    case 4:
+      if (resid)
+        hipLaunchKernelGGL((k_bsr4_spmv<T, true>), dim3(grid), dim3(256), 0, s, L.nrows, L.rowptr,
+                           L.colind, vals, x, b, L.mask, y);
+      else
+        hipLaunchKernelGGL((k_bsr4_spmv<T, false>), dim3(grid), dim3(256), 0, s, L.nrows, L.rowptr,
+                           L.colind, vals, x, b, L.mask, y);
+      break;
     default: break;
   }
 #undef FSIMG_SPMV_CASE
@@ -298,10 +400,11 @@ template <typename T>
 void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
                         int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s) {
   if (p1 <= p0) return;
-  const int ppw = 256 / L.np;
+  int ppw = 1, threads = 64;
+  vanka_shape(L.np, &ppw, &threads);
   const unsigned grid = grid_for(p1 - p0, ppw);
   const size_t lds = sizeof(T) * (size_t)ppw * npc;
-  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(256), lds, s, p0, p1, L.np, npc, L.b,
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(threads), lds, s, p0, p1, L.np, npc, L.b,
                      L.nl, ppw, L.pnodes, inv, d, Y, scatter ? 1 : 0, x, scale, L.mask, omega);
 }
 
