@@ -315,6 +315,12 @@ double node_mult(const fsimg_level_desc &L, int64_t node) {
   return m;
 }
 
+int64_t count_free(const fsimg_level_desc &L) {
+  int64_t f = 0;
+  for (int64_t i = 0; i < L.nrows * L.block; ++i) f += L.dirichlet[i] == 0;
+  return f;
+}
+
 size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, bool coarse,
                    const fsimg_opts &o) {
   const bool mixed = o.precision == FSIMG_MIXED;
@@ -329,7 +335,8 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
     s += (size_t)L.nrows * ts;                       // scale
     s += (size_t)3 * n * ts + (size_t)npatch * np * ts;  // r, x, d, Y
   } else {
-    s += (size_t)n * n * 8 + (size_t)2 * n * 8 + (size_t)2 * n * ts;
+    const int64_t nf = count_free(L);
+    s += (size_t)nf * nf * 8 + (size_t)(nf + n) * 4 + (size_t)2 * n * 8 + (size_t)2 * n * ts;
   }
   return s;
 }
@@ -397,8 +404,7 @@ void vanka_apply(fsimg_hier *h, int l, const T *d, T *x, bool assign, hipStream_
 }
 
 void coarse_solve64(fsimg_hier *h, const double *r, double *x, hipStream_t s) {
-  DevLevel &C = h->lev.back();
-  launch_dense_gemv(C.n, C.cinv, r, C.mask, x, s);
+  launch_coarse_gemv(h->lev.back(), r, x, s);
 }
 
 template <typename T>
@@ -647,7 +653,17 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
         FSIMG_HIPC(hipStreamSynchronize(s));
       }
     } else {
-      FSIMG_CHK(dalloc(h, &L.cinv, L.n * L.n));
+      std::vector<int32_t> cf, ci(L.n, -1);
+      for (int64_t i = 0; i < L.n; ++i)
+        if (!D.dirichlet[i]) { ci[i] = (int32_t)cf.size(); cf.push_back((int32_t)i); }
+      L.nfree = (int64_t)cf.size();
+      FSIMG_CHK(dalloc(h, &L.cidx, L.n));
+      FSIMG_HIPC(hipMemcpyAsync(L.cidx, ci.data(), L.n * 4, hipMemcpyHostToDevice, s));
+      if (L.nfree > 0) {
+        FSIMG_CHK(dalloc(h, &L.cfree, L.nfree));
+        FSIMG_HIPC(hipMemcpyAsync(L.cfree, cf.data(), L.nfree * 4, hipMemcpyHostToDevice, s));
+      }
+      FSIMG_CHK(dalloc(h, &L.cinv, L.nfree * L.nfree));
       FSIMG_CHK(dalloc(h, &L.ct0, L.n));
       FSIMG_CHK(dalloc(h, &L.ct1, L.n));
       if (mixed) {
@@ -688,7 +704,7 @@ fsimg_status fsimg_hier_info(const fsimg_hier *h, int level, fsimg_level_info *o
   size_t bytes = 0;
   const void *ptrs[] = {L.rowptr, L.colind, L.vals64, L.vals32, L.mask, L.pnodes, L.inv64, L.inv32,
                         L.gptr, L.gidx, L.scale64, L.scale32, L.r64, L.x64, L.d64, L.Y64,
-                        L.r32, L.x32, L.d32, L.Y32, L.cinv, L.ct0, L.ct1};
+                        L.r32, L.x32, L.d32, L.Y32, L.cinv, L.ct0, L.ct1, L.cfree, L.cidx};
   for (const void *p : ptrs)
     for (const auto &a : h->allocs)
       if (p && a.first == p) bytes += a.second;
@@ -742,7 +758,11 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   }
   // coarsest level: dense Gauss-Jordan inverse in FP64
   DevLevel &C = h->lev.back();
-  const int64_t n = C.n;
+  const int64_t n = C.nfree;
+  if (n == 0) {
+    h->factored = true;
+    return FSIMG_OK;
+  }
   double *a = nullptr, *rowk = nullptr, *colk = nullptr, *part = nullptr;
   int *piv = nullptr, *colmap = nullptr;
   fsimg_status st = FSIMG_OK;

@@ -37,8 +37,11 @@ struct DevLevel {
   // V-cycle work vectors (one precision is allocated)
   double *r64 = nullptr, *x64 = nullptr, *d64 = nullptr, *Y64 = nullptr;
   float *r32 = nullptr, *x32 = nullptr, *d32 = nullptr, *Y32 = nullptr;
-  // coarsest level: dense FP64 inverse
-  double *cinv = nullptr;
+  // coarsest level: dense FP64 inverse restricted to the non-identity dofs
+  int64_t nfree = 0;
+  int32_t *cfree = nullptr;             // [nfree] free dof -> dof
+  int32_t *cidx = nullptr;              // [n] dof -> free index or -1
+  double *cinv = nullptr;               // [nfree*nfree]
   double *ct0 = nullptr, *ct1 = nullptr;  // FP64 coarse work vectors (mixed mode casts)
 };
 
@@ -81,7 +84,7 @@ void launch_nonfinite_count(const double *x, int64_t n, int *flag, hipStream_t s
 size_t patch_factor_lds_bytes(int np);
 template <typename Tout>
 void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s);
-void launch_densify(const DevLevel &L, double *dense, hipStream_t s);
+void launch_densify(const DevLevel &L, double *dense, hipStream_t s);  // free x free block
 void launch_gj_pivot(int64_t n, int64_t k, double *a, int *piv, double *rowk, double *colk,
                      double thr, int *status, hipStream_t s);
 void launch_gj_update(int64_t n, int64_t k, double *a, const double *rowk, const double *colk,
@@ -89,8 +92,7 @@ void launch_gj_update(int64_t n, int64_t k, double *a, const double *rowk, const
 void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, double *out,
                       hipStream_t s);
 void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s);
-void launch_dense_gemv(int64_t n, const double *A, const double *x, const uint8_t *mask, double *y,
-                       hipStream_t s);
+void launch_coarse_gemv(const DevLevel &C, const double *x, double *y, hipStream_t s);
 void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
                    const double *v_new, int v_stride, int v_offset, const double *u_old,
                    const double *v_old, double *u_new, hipStream_t s);

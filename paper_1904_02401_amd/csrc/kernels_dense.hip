@@ -272,22 +272,269 @@ __global__ __launch_bounds__(256) void k_patch_factor(int64_t npatch, int b, int
   }
 }
 
+// ------------------------------------------- patch factorisation (MFMA)
+// Blocked Gauss-Jordan inversion with partial pivoting, FP64, the patch
+// matrix (padded with an identity block to N = 16*NT rows) held in registers
+// in the accumulator layout of v_mfma_f64_16x16x4f64: wave w owns tile-row w
+// (rows 16w..16w+15) and, per tile-column tj, lane l holds the four entries
+// (16w + 4v + l/16, 16tj + l%16), v = 0..3.
+// For each panel of 4 columns P:
+//   - the panel columns go to LDS; wave 0 runs the 4 Gauss-Jordan steps on
+//     them in registers (pivot search, row swap, elimination by shuffles) and
+//     writes back the processed columns G_P and the pivot rows;
+//   - every wave applies the panel's row swaps to its rows (through LDS);
+//   - the non-panel columns take the delayed rank-4 update
+//       A[:, Q] += (G_P - I_P) A[P, Q]
+//     as one MFMA per 16x16 tile (K = 4), the panel columns take G_P.
+// The row interchanges are finally undone as column interchanges when the
+// inverse is written in the column-group-major layout of the Vanka apply.
+typedef double fsimg_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double d4get(const fsimg_d4 &a, int v) {
+  return v == 0 ? a[0] : (v == 1 ? a[1] : (v == 2 ? a[2] : a[3]));
+}
+__device__ __forceinline__ void d4set(fsimg_d4 &a, int v, double x) {
+  if (v == 0) a[0] = x;
+  else if (v == 1) a[1] = x;
+  else if (v == 2) a[2] = x;
+  else a[3] = x;
+}
+
+template <int NT, typename Tout>
+__global__ __launch_bounds__(NT * 64, 4) void k_patch_factor_mfma(
+    int64_t npatch, int b, int nl, int np, int npc, const int32_t *__restrict__ pnodes,
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+    const double *__restrict__ vals, Tout *__restrict__ inv, int *__restrict__ status) {
+  constexpr int N = NT * 16;
+  constexpr int NTH = NT * 64;
+  __shared__ int bpos[27 * 27];
+  __shared__ double pin[N][4];     // panel columns before the panel's elimination
+  __shared__ double gpan[N][4];    // panel columns after it (G_P)
+  __shared__ double rowbuf[8][N];  // pre-swap rows k0..k0+3 and the 4 pivot rows
+  __shared__ int piv[N];
+  __shared__ int cmap[N];
+  __shared__ double red[NT];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l >> 4, lc = l & 15;
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int32_t *pn = pnodes + p * nl;
+  for (int pr = tid; pr < nl * nl; pr += NTH) {
+    const int l1 = pr / nl, l2 = pr - l1 * nl;
+    bpos[pr] = (int)find_block(rowptr, colind, pn[l1], pn[l2]);
+  }
+  __syncthreads();
+  fsimg_d4 acc[NT];
+  double amax = 0.0;
+  const int bb = b * b;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + 4 * v + lr, c = 16 * tj + lc;
+      double val;
+      if (r < np && c < np) {
+        const int pos = bpos[(r / b) * nl + c / b];
+        val = pos >= 0 ? vals[(int64_t)pos * bb + (r % b) * b + c % b] : 0.0;
+        amax = fmax(amax, fabs(val));
+      } else {
+        val = r == c ? 1.0 : 0.0;
+      }
+      acc[tj][v] = val;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+  if (l == 0) red[w] = amax;
+  // the padding block is the identity and stays untouched: panels past np are skipped
+  const int kend = (np + 3) & ~3;
+  for (int k = kend + tid; k < N; k += NTH) piv[k] = k;
+  __syncthreads();
+  double thr = 0.0;
+  for (int i = 0; i < NT; ++i) thr = fmax(thr, red[i]);
+  thr *= 1e-15;
+  bool singular = false;
+  const int r0 = l, r1 = l + 64;
+  const bool ok0 = r0 < N, ok1 = r1 < N;
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const int tp = k0 >> 4, cp = k0 & 15;
+    // phase 1: publish the panel columns
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+      if (tj == tp && lc >= cp && lc < cp + 4)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pin[16 * w + 4 * v + lr][lc - cp] = acc[tj][v];
+    __syncthreads();
+    // phase 2: every wave eliminates the panel redundantly in registers
+    // (lane l holds panel rows l and l+64), then publishes the rows the
+    // panel's interchanges and the rank-4 update read
+    double a0[4], a1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      a0[c] = ok0 ? pin[r0][c] : 0.0;
+      a1[c] = ok1 ? pin[r1][c] : 0.0;
+    }
+    int pv4[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = k0 + jj;
+      double best = -1.0;
+      int bi = j;
+      if (ok0 && r0 >= j && fabs(a0[jj]) > best) { best = fabs(a0[jj]); bi = r0; }
+      if (ok1 && r1 >= j && fabs(a1[jj]) > best) { best = fabs(a1[jj]); bi = r1; }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int pr = bi;
+      pv4[jj] = pr;
+      double vj[4], vp[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        vj[c] = __shfl((j >> 6) ? a1[c] : a0[c], j & 63);
+        vp[c] = __shfl((pr >> 6) ? a1[c] : a0[c], pr & 63);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (r0 == j) a0[c] = vp[c]; else if (r0 == pr) a0[c] = vj[c];
+        if (r1 == j) a1[c] = vp[c]; else if (r1 == pr) a1[c] = vj[c];
+      }
+      const double pv = vp[jj];
+      if (!(fabs(pv) > thr)) singular = true;
+      double rj[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rj[c] = (c == jj ? 1.0 : vp[c]) / pv;
+      const double f0 = a0[jj], f1 = a1[jj];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a0[c] = r0 == j ? rj[c] : (c == jj ? 0.0 : a0[c]) - f0 * rj[c];
+        a1[c] = r1 == j ? rj[c] : (c == jj ? 0.0 : a1[c]) - f1 * rj[c];
+      }
+    }
+    // slot rows: k0..k0+3 and the pivot rows, pre-swap values
+    int slotrow[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { slotrow[q] = k0 + q; slotrow[4 + q] = pv4[q]; }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int x = slotrow[s];
+      if ((x >> 4) == w && ((x & 15) & 3) == lr) {
+        const int v = (x & 15) >> 2;
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) rowbuf[s][16 * tj + lc] = d4get(acc[tj], v);
+      }
+    }
+    if (w == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (ok0) gpan[r0][c] = a0[c];
+        if (ok1) gpan[r1][c] = a1[c];
+      }
+      if (l < 4) piv[k0 + l] = l == 0 ? pv4[0] : (l == 1 ? pv4[1] : (l == 2 ? pv4[2] : pv4[3]));
+    }
+    __syncthreads();
+    // phase 3: row interchanges, rank-4 update by MFMA, panel columns
+    // source row of position r after the 4 interchanges: walk them backwards
+    auto src_of = [&](int r) {
+      int x = r;
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const int a = k0 + q, bq = pv4[q];
+        x = x == a ? bq : (x == bq ? a : x);
+      }
+      return x;
+    };
+    auto slot_of = [&](int x) {
+      int s = 7;
+#pragma unroll
+      for (int t = 7; t >= 0; --t)
+        if (slotrow[t] == x) s = t;
+      return s;
+    };
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + 4 * v + lr;
+      const int x = src_of(r);
+      if (x != r) {
+        const int s = slot_of(x);
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[tj][v] = rowbuf[s][16 * tj + lc];
+      }
+    }
+    const int ra = 16 * w + lc;
+    const double aw = gpan[ra][lr] - (ra == k0 + lr ? 1.0 : 0.0);
+    const int sb = slot_of(src_of(k0 + lr));
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      const int c = 16 * tj + lc;
+      const double bv = (c >= k0 && c < k0 + 4) ? 0.0 : rowbuf[sb][c];
+      acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv, acc[tj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+      if (tj == tp && lc >= cp && lc < cp + 4)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[tj][v] = gpan[16 * w + 4 * v + lr][lc - cp];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // undo the row interchanges as column interchanges, in reverse order
+    for (int j = 0; j < N; ++j) cmap[j] = j;
+    for (int k = N - 1; k >= 0; --k) {
+      const int t = cmap[k];
+      cmap[k] = cmap[piv[k]];
+      cmap[piv[k]] = t;
+    }
+    if (singular) {
+      atomicOr(&status[0], 1);
+      atomicMin(&status[1], (int)p);
+    }
+  }
+  __syncthreads();
+  // column j of the work array is column c of the inverse, cmap[c] = j
+  int cinv[NT];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) cinv[tj] = -1;
+  for (int c = 0; c < N; ++c) {
+    const int j = cmap[c];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+      if (j == 16 * tj + lc) cinv[tj] = c;
+  }
+  constexpr int G = 16 / sizeof(Tout);
+  Tout *out = inv + p * (int64_t)np * npc;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + 4 * v + lr;
+      const int c = cinv[tj];
+      if (r < np && c < np) out[((int64_t)(c / G) * np + r) * G + c % G] = (Tout)acc[tj][v];
+    }
+  for (int idx = tid; idx < np * (npc - np); idx += NTH) {
+    const int r = idx / (npc - np), c = np + idx % (npc - np);
+    out[((int64_t)(c / G) * np + r) * G + c % G] = Tout(0);
+  }
+}
+
 // ------------------------------------------------------- coarse level
-__global__ __launch_bounds__(256) void k_densify(int64_t nrows, int b,
+// dense block of the free (non-identity) dofs: dense[cidx[i]][cidx[j]] = A[i][j]
+__global__ __launch_bounds__(256) void k_densify(int64_t nrows, int b, int64_t nf,
                                                  const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ colind,
                                                  const double *__restrict__ vals,
+                                                 const int32_t *__restrict__ cidx,
                                                  double *__restrict__ dense) {
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
   if (row >= nrows) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t n = nrows * b;
   const int bb = b * b;
   for (int64_t j = rowptr[row]; j < rowptr[row + 1]; ++j) {
     const int64_t col = colind[j];
     if (lane < bb) {
       const int r = lane / b, c = lane - r * b;
-      dense[(row * b + r) * n + col * b + c] = vals[j * bb + lane];
+      const int fi = cidx[row * b + r], fj = cidx[col * b + c];
+      if (fi >= 0 && fj >= 0) dense[(int64_t)fi * nf + fj] = vals[j * bb + lane];
     }
   }
 }
@@ -382,19 +629,25 @@ __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ a, in
   if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-// y = A x for a dense row-major FP64 matrix, one wavefront per row
-__global__ __launch_bounds__(256) void k_dense_gemv(int64_t n, const double *__restrict__ A,
-                                                    const double *__restrict__ x,
-                                                    const uint8_t *__restrict__ mask,
-                                                    double *__restrict__ y) {
+// y[free[i]] = sum_j A[i][j] x[free[j]] for the dense FP64 coarse inverse,
+// one wavefront per row; the identity dofs of y are zeroed separately
+__global__ __launch_bounds__(256) void k_coarse_gemv(int64_t nf, const double *__restrict__ A,
+                                                     const int32_t *__restrict__ cfree,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y) {
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
-  if (row >= n) return;
+  if (row >= nf) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const double *ar = A + row * n;
+  const double *ar = A + row * nf;
   double s = 0.0;
-  for (int64_t j = lane; j < n; j += kWave) s += ar[j] * x[j];
+  for (int64_t j = lane; j < nf; j += kWave) s += ar[j] * x[cfree[j]];
   s = wave_sum(s);
-  if (lane == 0) y[row] = mask[row] ? 0.0 : s;
+  if (lane == 0) y[cfree[row]] = s;
+}
+
+__global__ void k_zero_masked(double *__restrict__ y, const uint8_t *__restrict__ mask, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && mask[i]) y[i] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_deform(int64_t nnodes, int dim,
@@ -476,6 +729,21 @@ size_t patch_factor_lds_bytes(int np) {
 template <typename Tout>
 void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s) {
   if (L.npatch == 0) return;
+  if (L.np <= 128 && L.nl <= 27) {
+    const int nt = (L.np + 15) / 16;
+#define FSIMG_MF(NTV)                                                                            \
+  case NTV:                                                                                      \
+    hipLaunchKernelGGL((k_patch_factor_mfma<NTV, Tout>), dim3((unsigned)L.npatch), dim3(NTV * 64), \
+                       0, s, L.npatch, L.b, L.nl, L.np, npc, L.pnodes, L.rowptr, L.colind,       \
+                       L.vals64, inv, status);                                                   \
+    return;
+    switch (nt) {
+      FSIMG_MF(1) FSIMG_MF(2) FSIMG_MF(3) FSIMG_MF(4)
+      FSIMG_MF(5) FSIMG_MF(6) FSIMG_MF(7) FSIMG_MF(8)
+      default: break;
+    }
+#undef FSIMG_MF
+  }
   const size_t lds = patch_factor_lds_bytes(L.np);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_patch_factor<Tout>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -486,8 +754,8 @@ template void launch_patch_factor<double>(const DevLevel &, double *, int, int *
 template void launch_patch_factor<float>(const DevLevel &, float *, int, int *, hipStream_t);
 
 void launch_densify(const DevLevel &L, double *dense, hipStream_t s) {
-  hipLaunchKernelGGL(k_densify, dim3(grid_for(L.nrows, 4)), dim3(256), 0, s, L.nrows, L.b,
-                     L.rowptr, L.colind, L.vals64, dense);
+  hipLaunchKernelGGL(k_densify, dim3(grid_for(L.nrows, 4)), dim3(256), 0, s, L.nrows, L.b, L.nfree,
+                     L.rowptr, L.colind, L.vals64, L.cidx, dense);
 }
 void launch_gj_pivot(int64_t n, int64_t k, double *a, int *piv, double *rowk, double *colk,
                      double thr, int *status, hipStream_t s) {
@@ -507,9 +775,11 @@ void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, d
 void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s) {
   hipLaunchKernelGGL(k_absmax, dim3(kRedBlocks), dim3(256), 0, s, a, n, partial);
 }
-void launch_dense_gemv(int64_t n, const double *A, const double *x, const uint8_t *mask, double *y,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(n, 4)), dim3(256), 0, s, n, A, x, mask, y);
+void launch_coarse_gemv(const DevLevel &C, const double *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_masked, dim3(grid_for(C.n, 256)), dim3(256), 0, s, y, C.mask, C.n);
+  if (C.nfree > 0)
+    hipLaunchKernelGGL(k_coarse_gemv, dim3(grid_for(C.nfree, 4)), dim3(256), 0, s, C.nfree, C.cinv,
+                       C.cfree, x, y);
 }
 void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
                    const double *v_new, int v_stride, int v_offset, const double *u_old,
