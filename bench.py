@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--mu", type=float, default=None, help="solid shear modulus override")
+    ap.add_argument("--lam", type=float, default=None, help="solid Lame lambda override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-mass", action="store_true")
@@ -239,7 +241,12 @@ def main():
     from oracle import to_csr
 
     t0 = time.perf_counter()
-    P = config_problem(args.config, seed=0)
+    over = {}
+    if args.mu is not None:
+        over["mu_s"] = args.mu
+    if args.lam is not None:
+        over["lambda_s"] = args.lam
+    P = config_problem(args.config, seed=0, params=over or None)
     log(f"problem {args.config} generated in {time.perf_counter() - t0:.1f} s")
     from paper_1904_02401_amd import fsimg
     if args.kernels_only:
@@ -310,7 +317,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 32^3 Q2 hexes, 4 MG levels, "
                                 "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")
-                   if args.config == "c2" else args.config,
+                   if args.config == "c2" else
+                   ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 64^3 Q2 hexes, 5 MG levels, "
+                    "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")
+                   if args.config == "c3" else args.config,
+                   "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
                    "precision": main_tag},
         "roofline": {"bound": "hbm", "kernel": dominant[0], "achieved": dominant[1],
