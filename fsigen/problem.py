@@ -431,6 +431,28 @@ SOLID_2D = ((0.3, 0.45), (0.7, 0.55))
 SOLID_3D = ((0.3, 0.4, 0.4), (0.7, 0.6, 0.6))
 
 
+def batch_instance(index: int, base_seed: int = 1000, sizes=(16, 20, 24, 32, 40),
+                   systems=("mom",)) -> Problem:
+    """Instance `index` of the batched workload: 3D, N ~ U(sizes) cells per
+    axis (3 levels for N = 4c or 5c with c = 4, 4 levels otherwise, so the
+    coarsest level keeps 3..5 cells), solid block centred at (1/2, 1/2, 1/2)
+    with half-widths x ~ U[0.1, 0.25], y, z ~ U[0.05, 0.15],
+    mu_s ~ logU[1e4, 1e6], lambda_s = 4 mu_s; seeded by base_seed + index."""
+    rng = np.random.Generator(np.random.PCG64(base_seed + index))
+    n = int(rng.choice(np.asarray(sizes)))
+    hw = (rng.uniform(0.1, 0.25), rng.uniform(0.05, 0.15), rng.uniform(0.05, 0.15))
+    mu = float(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+    coarse = n
+    nlev = 1
+    while coarse % 2 == 0 and coarse // 2 >= 3:
+        coarse //= 2
+        nlev += 1
+    nlev = min(nlev, 4)
+    box = (tuple(0.5 - h for h in hw), tuple(0.5 + h for h in hw))
+    return make_problem(3, n, nlev, box, seed=base_seed + index,
+                        params={"mu_s": mu, "lambda_s": 4.0 * mu}, systems=systems)
+
+
 def config_problem(name: str, seed: int = 0, **kw) -> Problem:
     """Named workloads: 'c1' (2D 32^2, 3 levels), 'c2' (3D 32^3, 4 levels),
     'c3' (3D 64^3, 5 levels) and small test cases 't2' (2D 8^2, 2 levels),

@@ -177,6 +177,19 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream);
 fsimg_status fsimg_solve(fsimg_hier *h, const double *b_dev, double *x_dev, fsimg_stats *stats,
                          void *stream);
 
+/* Solve n independent systems A_i x_i = b_i at once (the same method as
+   fsimg_solve, in lockstep): every multigrid operation runs as one launch per
+   level for all instances, the Krylov iterations advance together and each
+   instance stops at its own tolerance.  Each instance's arithmetic depends
+   only on that instance, so its result is bitwise the one it gets alone.
+   All hierarchies must belong to one context and share precision, block
+   size, dimension and solver options; sizes and level counts may differ.
+   stats: array of n (may be NULL).  Returns OK if every instance converged,
+   else the first failing status (per-instance status in stats).
+   fsimg_solve with the GATHER schedule is this call with n = 1. */
+fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *const *b_dev,
+                               double *const *x_dev, fsimg_stats *stats, void *stream);
+
 /* Condensed deformation update (Sec. 3.1 and eq. problem:2):
      u_new = u_old + k theta v_new + k (1 - theta) v_old   at nodes with mask != 0,
      u_new = 0                                            elsewhere.

@@ -2,6 +2,7 @@
 // setup (patches, colouring, transfer data), factorisation driver, V-cycle,
 // flexible GMRES, and the extern "C" entry points declared in fsimg.h.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -10,7 +11,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "fsimg_internal.h"
+#include "hier.h"
 
 using namespace fsimg;
 
@@ -21,7 +22,10 @@ fsimg_status fail(fsimg_status s, const std::string &msg) {
   g_err = msg;
   return s;
 }
+std::atomic<uint64_t> g_uid{1};
 }  // namespace
+
+fsimg_status fsimg::set_error(fsimg_status s, const std::string &msg) { return fail(s, msg); }
 
 #define FSIMG_HIP(expr)                                                                         \
   do {                                                                                          \
@@ -34,57 +38,6 @@ fsimg_status fail(fsimg_status s, const std::string &msg) {
     fsimg_status st_ = (expr);              \
     if (st_ != FSIMG_OK) return st_;        \
   } while (0)
-
-struct fsimg_ctx {
-  int device = 0;
-  size_t budget = 0;
-  size_t in_use = 0;
-};
-
-struct EventTimer {
-  std::vector<hipEvent_t> ev;
-  size_t used = 0;
-  void begin_solve() { used = 0; }
-  hipEvent_t next() {
-    if (used == ev.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      ev.push_back(e);
-    }
-    return ev[used++];
-  }
-  double total_ms(int *count) const {
-    double t = 0.0;
-    int c = 0;
-    for (size_t i = 0; i + 1 < used; i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) { t += ms; ++c; }
-    }
-    *count = c;
-    return t;
-  }
-  ~EventTimer() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-  }
-};
-
-struct fsimg_hier {
-  fsimg_ctx *ctx = nullptr;
-  fsimg_opts opts{};
-  std::vector<DevLevel> lev;
-  std::vector<std::pair<void *, size_t>> allocs;
-  std::vector<std::vector<uint8_t>> host_mask;
-  std::vector<std::vector<uint8_t>> host_class;
-  bool factored = false;
-  int m = 20;
-  // FGMRES workspace (FP64)
-  double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *small = nullptr;
-  double *hpin = nullptr;
-  int *dstatus = nullptr;
-  int *hstatus = nullptr;
-  EventTimer tv, ts;
-  bool profiling = false;
-};
 
 namespace {
 
@@ -500,7 +453,11 @@ fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **o
   return FSIMG_OK;
 }
 
-void fsimg_ctx_destroy(fsimg_ctx *ctx) { delete ctx; }
+void fsimg_ctx_destroy(fsimg_ctx *ctx) {
+  if (!ctx) return;
+  destroy_plan(ctx->plan);
+  delete ctx;
+}
 
 size_t fsimg_ctx_bytes_in_use(const fsimg_ctx *ctx) { return ctx ? ctx->in_use : 0; }
 
@@ -542,6 +499,12 @@ fsimg_status fsimg_hier_footprint(const fsimg_level_desc *levels, int nlev, cons
 void fsimg_hier_destroy(fsimg_hier *h) {
   if (!h) return;
   (void)hipSetDevice(h->ctx->device);
+  if (h->ctx->plan) {  // a cached batch plan that covers this hierarchy is stale
+    if (plan_covers(h->ctx->plan, h->uid)) {
+      destroy_plan(h->ctx->plan);
+      h->ctx->plan = nullptr;
+    }
+  }
   for (auto &a : h->allocs) {
     (void)hipFree(a.first);
     h->ctx->in_use -= a.second;
@@ -566,6 +529,7 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
     return fail(FSIMG_ERR_BUDGET, "hierarchy needs " + std::to_string(need) + " bytes, " +
                                       std::to_string(ctx->budget - ctx->in_use) + " left in the budget");
   auto *h = new fsimg_hier;
+  h->uid = g_uid.fetch_add(1);
   h->ctx = ctx;
   h->opts = *opts;
   h->m = opts->restart;
@@ -804,10 +768,19 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   return FSIMG_OK;
 }
 
+fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *const *b_dev,
+                               double *const *x_dev, fsimg_stats *stats, void *stream) {
+  if (n < 1 || !hiers || !hiers[0]) return fail(FSIMG_ERR_ARG, "empty batch");
+  FSIMG_HIP(hipSetDevice(hiers[0]->ctx->device));
+  return solve_batch(hiers[0]->ctx, n, hiers, b_dev, x_dev, stats, static_cast<hipStream_t>(stream));
+}
+
 fsimg_status fsimg_solve(fsimg_hier *h, const double *b, double *x, fsimg_stats *stats, void *stream) {
   if (!h || !b || !x) return fail(FSIMG_ERR_ARG, "null argument");
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run before fsimg_solve");
   FSIMG_HIP(hipSetDevice(h->ctx->device));
+  if (h->opts.vanka_schedule == FSIMG_VANKA_GATHER)  // the batched driver with one instance
+    return solve_batch(h->ctx, 1, &h, &b, &x, stats, static_cast<hipStream_t>(stream));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   DevLevel &F = h->lev[0];

@@ -1,0 +1,509 @@
+// Batched solve driver: FGMRES(m) + V-cycle over many independent
+// hierarchies at once, one launch per operation and level for all of them.
+//
+// Levels are aligned from the top (level 0 = finest of every instance).  At
+// level l an instance either smooths (l < L_i - 1), solves its coarse problem
+// (l = L_i - 1) or has nothing to do, so each instance runs exactly the
+// V-cycle it would run alone.  The Krylov iterations advance in lockstep: one
+// device-to-host copy per iteration returns every instance's new Hessenberg
+// column, the Givens rotations and stop tests run per instance on the host,
+// and instances that stop are masked out of the following launches.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "hier.h"
+
+using namespace fsimg;
+
+struct BatchPlan {
+  std::vector<uint64_t> key;
+  int n = 0, Lmax = 0, b = 0, dim = 0, np = 0, nl = 0, npc = 0;
+  bool mixed = false;
+  void *dbuf = nullptr;
+  size_t dbytes = 0;
+  size_t kry_off = 0;
+  DLev *dlev = nullptr;  // [Lmax][n]
+  DKry *dkry = nullptr;  // [n]
+  int *active = nullptr, *kcnt = nullptr, *flags = nullptr;
+  double *hs = nullptr;  // [n * kHS]
+  std::vector<WorkSet> ws_spmv, ws_patch, ws_gather, ws_restrict, ws_prolong, ws_cn, ws_cf;
+  WorkSet ws_row0{}, ws_vec0{}, ws_kry{}, ws_inst{};
+  std::vector<DKry> hkry;
+  double *hs_host = nullptr;
+  int *int_host = nullptr;  // active | kcnt | flags staging, 3n ints
+  EventTimer tv, ts;
+};
+
+namespace fsimg {
+
+void destroy_plan(BatchPlan *p) {
+  if (!p) return;
+  if (p->dbuf) (void)hipFree(p->dbuf);
+  if (p->hs_host) (void)hipHostFree(p->hs_host);
+  if (p->int_host) (void)hipHostFree(p->int_host);
+  delete p;
+}
+
+bool plan_covers(const BatchPlan *p, uint64_t uid) {
+  if (!p) return false;
+  for (uint64_t k : p->key)
+    if (k == uid) return true;
+  return false;
+}
+
+namespace {
+
+struct Blob {
+  std::vector<unsigned char> data;
+  size_t add(const void *src, size_t bytes) {
+    const size_t off = (data.size() + 255) & ~size_t(255);
+    data.resize(off + bytes);
+    if (src && bytes) std::memcpy(data.data() + off, src, bytes);
+    return off;
+  }
+};
+
+struct WsHost {
+  std::vector<int32_t> inst;
+  std::vector<int64_t> pre{0};
+  void push(int i, int64_t blocks) {
+    if (blocks <= 0) return;
+    inst.push_back(i);
+    pre.push_back(pre.back() + blocks);
+  }
+};
+
+struct WsRef {
+  size_t inst_off, pre_off;
+  int nset;
+  int64_t nblocks;
+};
+
+WsRef stage(Blob &blob, const WsHost &w) {
+  WsRef r;
+  r.nset = (int)w.inst.size();
+  r.nblocks = w.pre.back();
+  r.inst_off = blob.add(w.inst.data(), w.inst.size() * sizeof(int32_t));
+  r.pre_off = blob.add(w.pre.data(), w.pre.size() * sizeof(int64_t));
+  return r;
+}
+
+WorkSet resolve(void *base, const WsRef &r) {
+  WorkSet w;
+  w.inst = reinterpret_cast<const int32_t *>(static_cast<unsigned char *>(base) + r.inst_off);
+  w.pre = reinterpret_cast<const int64_t *>(static_cast<unsigned char *>(base) + r.pre_off);
+  w.nset = r.nset;
+  w.nblocks = r.nblocks;
+  return w;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+DLev to_dlev(const DevLevel &L) {
+  DLev d{};
+  d.rowptr = L.rowptr; d.colind = L.colind; d.v64 = L.vals64; d.v32 = L.vals32; d.mask = L.mask;
+  d.nrows = L.nrows; d.n = L.n;
+  for (int a = 0; a < 3; ++a) d.cells[a] = L.cells[a];
+  d.npatch = L.npatch; d.pnodes = L.pnodes; d.inv64 = L.inv64; d.inv32 = L.inv32;
+  d.gptr = L.gptr; d.gidx = L.gidx; d.sc64 = L.scale64; d.sc32 = L.scale32;
+  d.r64 = L.r64; d.x64 = L.x64; d.d64 = L.d64; d.Y64 = L.Y64;
+  d.r32 = L.r32; d.x32 = L.x32; d.d32 = L.d32; d.Y32 = L.Y32;
+  d.nfree = L.nfree; d.cfree = L.cfree; d.cinv = L.cinv; d.ct0 = L.ct0; d.ct1 = L.ct1;
+  return d;
+}
+
+fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan **out) {
+  auto *P = new BatchPlan;
+  P->n = n;
+  P->b = hs[0]->lev[0].b;
+  P->dim = hs[0]->lev[0].dim;
+  P->nl = hs[0]->lev[0].nl;
+  P->np = hs[0]->lev[0].np;
+  P->mixed = hs[0]->opts.precision == FSIMG_MIXED;
+  P->npc = P->mixed ? hs[0]->lev[0].npc32 : hs[0]->lev[0].npc64;
+  for (int i = 0; i < n; ++i) {
+    P->key.push_back(hs[i]->uid);
+    P->Lmax = std::max(P->Lmax, (int)hs[i]->lev.size());
+  }
+  const int Lmax = P->Lmax;
+  int ppw = 1, threads = 64;
+  vanka_shape(P->np, &ppw, &threads);
+  Blob blob;
+  std::vector<DLev> dl((size_t)Lmax * n);
+  for (int l = 0; l < Lmax; ++l)
+    for (int i = 0; i < n; ++i)
+      if (l < (int)hs[i]->lev.size()) dl[(size_t)l * n + i] = to_dlev(hs[i]->lev[l]);
+  const size_t lev_off = blob.add(dl.data(), dl.size() * sizeof(DLev));
+  P->hkry.resize(n);
+  P->kry_off = blob.add(nullptr, n * sizeof(DKry));
+  const size_t act_off = blob.add(nullptr, n * sizeof(int));
+  const size_t k_off = blob.add(nullptr, n * sizeof(int));
+  const size_t fl_off = blob.add(nullptr, n * sizeof(int));
+  const size_t hs_off = blob.add(nullptr, (size_t)n * kHS * sizeof(double));
+  std::vector<WsRef> r_spmv, r_patch, r_gather, r_restrict, r_prolong, r_cn, r_cf;
+  for (int l = 0; l < Lmax; ++l) {
+    WsHost sp, pa, ga, re, pr, cn, cf;
+    for (int i = 0; i < n; ++i) {
+      const int Li = (int)hs[i]->lev.size();
+      if (l < Li - 1) {
+        const DevLevel &L = hs[i]->lev[l];
+        sp.push(i, cdiv(L.nrows, 4));
+        pa.push(i, cdiv(L.npatch, ppw));
+        ga.push(i, cdiv(L.n, 256));
+        re.push(i, cdiv(hs[i]->lev[l + 1].nrows, 256));
+        pr.push(i, cdiv(L.nrows, 256));
+      } else if (l == Li - 1) {
+        const DevLevel &L = hs[i]->lev[l];
+        cn.push(i, cdiv(L.n, 256));
+        cf.push(i, cdiv(L.nfree, 4));
+      }
+    }
+    r_spmv.push_back(stage(blob, sp));
+    r_patch.push_back(stage(blob, pa));
+    r_gather.push_back(stage(blob, ga));
+    r_restrict.push_back(stage(blob, re));
+    r_prolong.push_back(stage(blob, pr));
+    r_cn.push_back(stage(blob, cn));
+    r_cf.push_back(stage(blob, cf));
+  }
+  WsHost row0, vec0, kr, ins;
+  for (int i = 0; i < n; ++i) {
+    const DevLevel &L = hs[i]->lev[0];
+    row0.push(i, cdiv(L.nrows, 4));
+    vec0.push(i, cdiv(L.n, 256));
+    kr.push(i, krylov_blocks(L.n));
+    ins.push(i, 1);
+  }
+  const WsRef r_row0 = stage(blob, row0), r_vec0 = stage(blob, vec0), r_kry = stage(blob, kr),
+              r_ins = stage(blob, ins);
+  P->dbytes = blob.data.size();
+  if (ctx->budget && ctx->in_use + P->dbytes > ctx->budget) {
+    delete P;
+    return set_error(FSIMG_ERR_BUDGET, "batch descriptor tables exceed the HBM budget");
+  }
+  if (hipMalloc(&P->dbuf, P->dbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return set_error(FSIMG_ERR_OOM, "batch descriptor allocation failed");
+  }
+  if (hipMemcpy(P->dbuf, blob.data.data(), P->dbytes, hipMemcpyHostToDevice) != hipSuccess) {
+    destroy_plan(P);
+    return set_error(FSIMG_ERR_HIP, "batch descriptor upload failed");
+  }
+  unsigned char *base = static_cast<unsigned char *>(P->dbuf);
+  P->dlev = reinterpret_cast<DLev *>(base + lev_off);
+  P->dkry = reinterpret_cast<DKry *>(base + P->kry_off);
+  P->active = reinterpret_cast<int *>(base + act_off);
+  P->kcnt = reinterpret_cast<int *>(base + k_off);
+  P->flags = reinterpret_cast<int *>(base + fl_off);
+  P->hs = reinterpret_cast<double *>(base + hs_off);
+  for (int l = 0; l < Lmax; ++l) {
+    P->ws_spmv.push_back(resolve(base, r_spmv[l]));
+    P->ws_patch.push_back(resolve(base, r_patch[l]));
+    P->ws_gather.push_back(resolve(base, r_gather[l]));
+    P->ws_restrict.push_back(resolve(base, r_restrict[l]));
+    P->ws_prolong.push_back(resolve(base, r_prolong[l]));
+    P->ws_cn.push_back(resolve(base, r_cn[l]));
+    P->ws_cf.push_back(resolve(base, r_cf[l]));
+  }
+  P->ws_row0 = resolve(base, r_row0);
+  P->ws_vec0 = resolve(base, r_vec0);
+  P->ws_kry = resolve(base, r_kry);
+  P->ws_inst = resolve(base, r_ins);
+  if (hipHostMalloc((void **)&P->hs_host, (size_t)n * kHS * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&P->int_host, (size_t)3 * n * sizeof(int), hipHostMallocDefault) !=
+          hipSuccess) {
+    destroy_plan(P);
+    return set_error(FSIMG_ERR_HIP, "pinned host staging allocation failed");
+  }
+  *out = P;
+  return FSIMG_OK;
+}
+
+template <typename T>
+void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
+  const int n = P.n;
+  const T omega = (T)o.omega;
+  const int *act = P.active;
+  for (int l = 0; l < P.Lmax; ++l) {
+    const DLev *L = P.dlev + (size_t)l * n;
+    if (P.ws_patch[l].nset > 0 || P.ws_spmv[l].nset > 0) {
+      const bool p0 = prof && l == 0;
+      if (o.nu_pre == 0) launch_b_fill_x<T>(L, act, P.ws_gather[l], s);
+      for (int k = 0; k < o.nu_pre; ++k) {
+        if (k > 0) {
+          hipEvent_t a = p0 ? P.ts.next() : nullptr;
+          hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
+          if (a) (void)hipEventRecord(a, s);
+          launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+          if (b2) (void)hipEventRecord(b2, s);
+        }
+        hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
+        hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
+        launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, omega, k == 0, k == 0, L, act, P.ws_patch[l],
+                          P.ws_gather[l], s, v0, v1);
+      }
+      hipEvent_t a = p0 ? P.ts.next() : nullptr;
+      hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
+      if (a) (void)hipEventRecord(a, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+      if (b2) (void)hipEventRecord(b2, s);
+      launch_b_restrict<T>(P.b, P.dim, L, L + n, act, P.ws_restrict[l], s);
+    }
+    if (P.ws_cn[l].nset > 0) launch_b_coarse<T>(L, act, P.ws_cn[l], P.ws_cf[l], s);
+  }
+  for (int l = P.Lmax - 2; l >= 0; --l) {
+    if (P.ws_prolong[l].nset == 0) continue;
+    const DLev *L = P.dlev + (size_t)l * n;
+    const bool p0 = prof && l == 0;
+    launch_b_prolong<T>(P.b, P.dim, L, L + n, act, P.ws_prolong[l], s);
+    for (int k = 0; k < o.nu_post; ++k) {
+      hipEvent_t a = p0 ? P.ts.next() : nullptr;
+      hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
+      if (a) (void)hipEventRecord(a, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+      if (b2) (void)hipEventRecord(b2, s);
+      hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
+      hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
+      launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, omega, false, false, L, act, P.ws_patch[l],
+                        P.ws_gather[l], s, v0, v1);
+    }
+  }
+}
+
+struct InstState {
+  double beta0 = 0, tol = 0, rnorm = 0;
+  int it = 0, restarts = 0, k = 0, status = FSIMG_OK;
+  bool done = false, in_cycle = false;
+  std::vector<double> H, cs, sn, g, y;
+};
+
+}  // namespace
+
+fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
+                         double *const *x, fsimg_stats *stats, hipStream_t s) {
+  if (n < 1 || !hs || !b || !x) return set_error(FSIMG_ERR_ARG, "empty batch or null arrays");
+  const fsimg_opts &o = hs[0]->opts;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !b[i] || !x[i]) return set_error(FSIMG_ERR_ARG, "null hierarchy or vector in batch");
+    if (hs[i]->ctx != ctx) return set_error(FSIMG_ERR_ARG, "batch hierarchies must share one context");
+    if (!hs[i]->factored) return set_error(FSIMG_ERR_STATE, "fsimg_factor must run before the solve");
+    const fsimg_opts &q = hs[i]->opts;
+    if (q.precision != o.precision || hs[i]->lev[0].b != hs[0]->lev[0].b ||
+        hs[i]->lev[0].dim != hs[0]->lev[0].dim || q.omega != o.omega || q.nu_pre != o.nu_pre ||
+        q.nu_post != o.nu_post || q.restart != o.restart || q.rtol != o.rtol ||
+        q.max_iter != o.max_iter)
+      return set_error(FSIMG_ERR_ARG, "batch hierarchies must share precision, block size, "
+                                      "dimension and solver options");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return set_error(FSIMG_ERR_ARG, "a hierarchy appears twice in a batch");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  BatchPlan *P = ctx->plan;
+  bool same = P && (int)P->key.size() == n;
+  for (int i = 0; same && i < n; ++i) same = P->key[i] == hs[i]->uid;
+  if (!same) {
+    destroy_plan(ctx->plan);
+    ctx->plan = nullptr;
+    fsimg_status st = build_plan(ctx, n, hs, &P);
+    if (st != FSIMG_OK) return st;
+    ctx->plan = P;
+  }
+  const bool prof = o.profile != 0;
+  P->tv.begin_solve();
+  P->ts.begin_solve();
+  const int m = o.restart;
+  for (int i = 0; i < n; ++i) {
+    fsimg_hier *h = hs[i];
+    DKry &K = P->hkry[i];
+    K.V = h->V; K.Z = h->Z; K.w = h->w; K.partial = h->partial;
+    K.b = b[i]; K.x = x[i]; K.n = h->lev[0].n; K.nblk = krylov_blocks(K.n); K.pad = 0;
+  }
+  int *act_h = P->int_host, *k_h = P->int_host + n, *fl_h = P->int_host + 2 * n;
+  double *hh = P->hs_host;
+  auto upload_act = [&]() {
+    return hipMemcpyAsync(P->active, act_h, n * sizeof(int), hipMemcpyHostToDevice, s);
+  };
+  auto fetch = [&](bool flags) {
+    hipError_t e = hipMemcpyAsync(hh, P->hs, (size_t)n * kHS * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && flags)
+      e = hipMemcpyAsync(fl_h, P->flags, n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
+#define FSIMG_BHIP(expr)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return set_error(FSIMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+  FSIMG_BHIP(hipMemcpyAsync(P->dkry, P->hkry.data(), n * sizeof(DKry), hipMemcpyHostToDevice, s));
+  std::vector<InstState> S(n);
+  for (int i = 0; i < n; ++i) {
+    act_h[i] = 1;
+    fl_h[i] = 0;
+    S[i].H.assign((size_t)(m + 1) * m, 0.0);
+    S[i].cs.assign(m, 0.0);
+    S[i].sn.assign(m, 0.0);
+    S[i].g.assign(m + 1, 0.0);
+    S[i].y.assign(m, 0.0);
+  }
+  FSIMG_BHIP(upload_act());
+  FSIMG_BHIP(hipMemcpyAsync(P->flags, fl_h, n * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_b_spmv<double>(P->b, BS_RESID, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
+  launch_b_nonfinite(P->dkry, P->active, P->ws_vec0, P->flags, s);
+  launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
+  launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
+  FSIMG_BHIP(fetch(true));
+  for (int i = 0; i < n; ++i) {
+    InstState &q = S[i];
+    q.beta0 = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
+    q.rnorm = q.beta0;
+    q.tol = o.rtol * q.beta0;
+    if (fl_h[i] || !std::isfinite(q.beta0)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
+    else if (q.beta0 == 0.0) q.done = true;
+    act_h[i] = q.done ? 0 : 1;
+  }
+  while (true) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      S[i].in_cycle = !S[i].done;
+      act_h[i] = S[i].in_cycle ? 1 : 0;
+      any |= S[i].in_cycle;
+      if (S[i].in_cycle) {
+        std::fill(S[i].H.begin(), S[i].H.end(), 0.0);
+        std::fill(S[i].g.begin(), S[i].g.end(), 0.0);
+        S[i].g[0] = S[i].rnorm;
+        S[i].k = 0;
+      }
+    }
+    if (!any) break;
+    FSIMG_BHIP(upload_act());
+    launch_b_scale(P->dkry, P->active, P->ws_vec0, P->hs, 0, s);  // v_0 = r / ||r||
+    for (int j = 0; j < m; ++j) {
+      bool live = false;
+      for (int i = 0; i < n; ++i) live |= act_h[i] != 0;
+      if (!live) break;
+      if (P->mixed) {
+        launch_b_copy_in<float>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+        vcycle_batch<float>(*P, o, s, prof);
+        launch_b_copy_out<float>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+      } else {
+        launch_b_copy_in<double>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+        vcycle_batch<double>(*P, o, s, prof);
+        launch_b_copy_out<double>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+      }
+      launch_b_spmv<double>(P->b, BS_AZ, P->dlev, P->dkry, P->active, P->ws_row0, j, s);
+      // classical Gram-Schmidt, two passes
+      launch_b_multidot(P->dkry, P->active, P->ws_kry, j + 1, false, s);
+      launch_b_reduce(P->dkry, P->active, P->ws_inst, j + 1, P->hs, kOffH1, s);
+      launch_b_axpy_red(P->dkry, P->active, P->ws_kry, j + 1, false, P->hs, kOffH1, s);
+      launch_b_reduce(P->dkry, P->active, P->ws_inst, j + 1, P->hs, kOffH2, s);
+      launch_b_axpy_red(P->dkry, P->active, P->ws_kry, j + 1, true, P->hs, kOffH2, s);
+      launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
+      launch_b_add_h(P->active, P->ws_inst, j + 1, P->hs, s);
+      launch_b_scale(P->dkry, P->active, P->ws_vec0, P->hs, j + 1, s);
+      FSIMG_BHIP(fetch(false));
+      bool changed = false;
+      for (int i = 0; i < n; ++i) {
+        if (!act_h[i]) continue;
+        InstState &q = S[i];
+        const double *hc = hh + (size_t)i * kHS;
+        for (int r = 0; r <= j; ++r) q.H[(size_t)r * m + j] = hc[kOffH + r];
+        const double hn = std::sqrt(hc[kOffSS]);
+        q.H[(size_t)(j + 1) * m + j] = hn;
+        for (int r = 0; r < j; ++r) {
+          const double a0 = q.H[(size_t)r * m + j], a1 = q.H[(size_t)(r + 1) * m + j];
+          q.H[(size_t)r * m + j] = q.cs[r] * a0 + q.sn[r] * a1;
+          q.H[(size_t)(r + 1) * m + j] = -q.sn[r] * a0 + q.cs[r] * a1;
+        }
+        const double hjj = q.H[(size_t)j * m + j];
+        const double den = std::hypot(hjj, hn);
+        q.cs[j] = hjj / den;
+        q.sn[j] = hn / den;
+        q.H[(size_t)j * m + j] = den;
+        q.H[(size_t)(j + 1) * m + j] = 0.0;
+        q.g[j + 1] = -q.sn[j] * q.g[j];
+        q.g[j] = q.cs[j] * q.g[j];
+        ++q.it;
+        q.k = j + 1;
+        if (!std::isfinite(q.g[j + 1]) || std::fabs(q.g[j + 1]) <= q.tol || q.it >= o.max_iter ||
+            hn == 0.0) {
+          act_h[i] = 0;
+          changed = true;
+        }
+      }
+      if (changed) FSIMG_BHIP(upload_act());
+    }
+    // x += Z y for every instance of this cycle, then the true residual
+    int kmax = 1;
+    for (int i = 0; i < n; ++i) {
+      InstState &q = S[i];
+      k_h[i] = 0;
+      act_h[i] = q.in_cycle ? 1 : 0;
+      if (!q.in_cycle) continue;
+      const int k = q.k;
+      for (int r = k - 1; r >= 0; --r) {
+        double t = q.g[r];
+        for (int c = r + 1; c < k; ++c) t -= q.H[(size_t)r * m + c] * q.y[c];
+        q.y[r] = t / q.H[(size_t)r * m + r];
+      }
+      for (int r = 0; r < k; ++r) hh[(size_t)i * kHS + kOffY + r] = q.y[r];
+      k_h[i] = k;
+      kmax = std::max(kmax, k);
+    }
+    FSIMG_BHIP(hipMemcpyAsync(P->hs, hh, (size_t)n * kHS * sizeof(double), hipMemcpyHostToDevice, s));
+    FSIMG_BHIP(hipMemcpyAsync(P->kcnt, k_h, n * sizeof(int), hipMemcpyHostToDevice, s));
+    FSIMG_BHIP(upload_act());
+    launch_b_combine(P->dkry, P->active, P->ws_vec0, P->hs, P->kcnt, kmax, s);
+    launch_b_spmv<double>(P->b, BS_RESID, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
+    launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
+    launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
+    FSIMG_BHIP(fetch(false));
+    for (int i = 0; i < n; ++i) {
+      InstState &q = S[i];
+      if (!q.in_cycle) continue;
+      ++q.restarts;
+      q.rnorm = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
+      if (!std::isfinite(q.rnorm)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
+      else if (q.rnorm <= q.tol) q.done = true;
+      else if (q.it >= o.max_iter) { q.status = FSIMG_ERR_NOCONV; q.done = true; }
+    }
+  }
+  FSIMG_BHIP(hipGetLastError());
+  double vms = 0.0, sms = 0.0;
+  int vn = 0, sn = 0;
+  if (prof) {
+    FSIMG_BHIP(hipStreamSynchronize(s));
+    vms = P->tv.total_ms(&vn);
+    sms = P->ts.total_ms(&sn);
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  fsimg_status ret = FSIMG_OK;
+  for (int i = 0; i < n; ++i) {
+    const InstState &q = S[i];
+    if (stats) {
+      fsimg_stats &st = stats[i];
+      st = fsimg_stats{};
+      st.status = q.status;
+      st.iters = q.it;
+      st.restarts = q.restarts;
+      st.rel_res = q.beta0 > 0.0 ? q.rnorm / q.beta0 : 0.0;
+      st.solve_ms = ms;
+      st.vanka_ms = vms; st.vanka_launches = vn;
+      st.spmv_ms = sms; st.spmv_launches = sn;
+    }
+    if (ret == FSIMG_OK && q.status != FSIMG_OK) ret = (fsimg_status)q.status;
+  }
+#undef FSIMG_BHIP
+  if (ret == FSIMG_ERR_NOCONV) return set_error(ret, "an instance reached max_iter without converging");
+  if (ret == FSIMG_ERR_NONFINITE) return set_error(ret, "non-finite residual in an instance");
+  return ret;
+}
+
+}  // namespace fsimg

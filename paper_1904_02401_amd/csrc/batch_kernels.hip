@@ -1,0 +1,553 @@
+// Batched kernels: one launch covers one operation on one multigrid level of
+// many independent instances (hierarchies of uneven size).  A workgroup finds
+// its instance by binary search in the launch's prefix of work blocks; every
+// per-instance computation (rows, patches, nodes, reduction blocking) depends
+// on that instance alone, so an instance's result does not depend on which
+// other instances share the launch.
+#include "device_ops.h"
+
+namespace fsimg {
+
+namespace {
+
+using dev::kWave;
+
+__device__ __forceinline__ int seg_of(const WorkSet &ws, int64_t blk) {
+  int lo = 0, hi = ws.nset - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ws.pre[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T> struct LV;
+template <> struct LV<double> {
+  static __device__ __forceinline__ const double *vals(const DLev &L) { return L.v64; }
+  static __device__ __forceinline__ double *r(const DLev &L) { return L.r64; }
+  static __device__ __forceinline__ double *x(const DLev &L) { return L.x64; }
+  static __device__ __forceinline__ double *d(const DLev &L) { return L.d64; }
+  static __device__ __forceinline__ double *Y(const DLev &L) { return L.Y64; }
+  static __device__ __forceinline__ const double *inv(const DLev &L) { return L.inv64; }
+  static __device__ __forceinline__ const double *sc(const DLev &L) { return L.sc64; }
+};
+template <> struct LV<float> {
+  static __device__ __forceinline__ const float *vals(const DLev &L) { return L.v32; }
+  static __device__ __forceinline__ float *r(const DLev &L) { return L.r32; }
+  static __device__ __forceinline__ float *x(const DLev &L) { return L.x32; }
+  static __device__ __forceinline__ float *d(const DLev &L) { return L.d32; }
+  static __device__ __forceinline__ float *Y(const DLev &L) { return L.Y32; }
+  static __device__ __forceinline__ const float *inv(const DLev &L) { return L.inv32; }
+  static __device__ __forceinline__ const float *sc(const DLev &L) { return L.sc32; }
+};
+
+// ------------------------------------------------------------ SpMV
+// SRC BS_VCYCLE: d = r - A x on the level's work vectors (T);
+//     BS_AZ:     w = A z_j, 0 at identity rows (FP64, level 0);
+//     BS_RESID:  w = b - A x with the caller's b, x (FP64, level 0).
+template <int B, typename T, int SRC>
+__global__ __launch_bounds__(256) void kb_spmv(const DLev *__restrict__ lev,
+                                               const DKry *__restrict__ kry,
+                                               const int *__restrict__ active, WorkSet ws, int j) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t row = (blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave;
+  if (row >= L.nrows) return;
+  if constexpr (SRC == BS_VCYCLE) {
+    dev::spmv_row<B, T, 1>(row, lane, L.rowptr, L.colind, LV<T>::vals(L), LV<T>::x(L), LV<T>::r(L),
+                           L.mask, LV<T>::d(L));
+  } else if constexpr (SRC == BS_AZ) {
+    const DKry &K = kry[i];
+    dev::spmv_row<B, double, 2>(row, lane, L.rowptr, L.colind, L.v64, K.Z + (int64_t)j * K.n,
+                                nullptr, L.mask, K.w);
+  } else {
+    const DKry &K = kry[i];
+    dev::spmv_row<B, double, 1>(row, lane, L.rowptr, L.colind, L.v64, K.x, K.b, L.mask, K.w);
+  }
+}
+
+// ------------------------------------------------------------ Vanka
+template <typename T>
+__global__ __launch_bounds__(1024) void kb_vanka_patch(const DLev *__restrict__ lev,
+                                                       const int *__restrict__ active, WorkSet ws,
+                                                       int np, int npc, int b, int nl, int ppw,
+                                                       int first) {
+  extern __shared__ unsigned char smem_raw[];
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;  // uniform per workgroup
+  const DLev &L = lev[i];
+  const int64_t pfirst = (blockIdx.x - ws.pre[s]) * ppw;
+  dev::vanka_patch_wg<T>(pfirst, L.npatch, np, npc, b, nl, ppw, L.pnodes, LV<T>::inv(L),
+                         first ? LV<T>::r(L) : LV<T>::d(L), LV<T>::Y(L), 0, nullptr, nullptr,
+                         L.mask, T(0), reinterpret_cast<T *>(smem_raw));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_vanka_gather(const DLev *__restrict__ lev,
+                                                       const int *__restrict__ active, WorkSet ws,
+                                                       int b, T omega, int assign) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int64_t dof = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (dof >= L.n) return;
+  dev::vanka_gather_dof<T>(dof, b, L.gptr, L.gidx, LV<T>::Y(L), LV<T>::sc(L), L.mask, omega, assign,
+                           LV<T>::x(L));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_fill_x(const DLev *__restrict__ lev,
+                                                 const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < L.n) LV<T>::x(L)[k] = T(0);
+}
+
+// ------------------------------------------------------------ transfers
+template <int B, int DIM, typename T>
+__global__ __launch_bounds__(256) void kb_restrict(const DLev *__restrict__ levF,
+                                                   const DLev *__restrict__ levC,
+                                                   const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &C = levC[i];
+  const int64_t node = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (node >= C.nrows) return;
+  dev::restrict_node<B, DIM, T>(node, C.cells[0], C.cells[1], C.cells[2], LV<T>::d(levF[i]),
+                                LV<T>::r(C), C.mask);
+}
+
+template <int B, int DIM, typename T>
+__global__ __launch_bounds__(256) void kb_prolong(const DLev *__restrict__ levF,
+                                                  const DLev *__restrict__ levC,
+                                                  const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &F = levF[i];
+  const DLev &C = levC[i];
+  const int64_t node = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (node >= F.nrows) return;
+  dev::prolong_node<B, DIM, T>(node, C.cells[0], C.cells[1], C.cells[2], LV<T>::x(C), LV<T>::x(F),
+                               F.mask);
+}
+
+// ------------------------------------------------------------ coarse solve
+// FP64 dense inverse on the free dofs: x = C^-1 r.  Mixed precision casts the
+// FP32 residual into ct0 first and the FP64 result ct1 back afterwards.
+template <typename T>
+__global__ __launch_bounds__(256) void kb_coarse_pre(const DLev *__restrict__ lev,
+                                                     const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k >= L.n) return;
+  double *out = std::is_same<T, double>::value ? L.x64 : L.ct1;
+  if (L.mask[k]) out[k] = 0.0;
+  if (!std::is_same<T, double>::value) L.ct0[k] = (double)L.r32[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_coarse_gemv(const DLev *__restrict__ lev,
+                                                      const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int64_t row = (blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave;
+  if (row >= L.nfree) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const double *in = std::is_same<T, double>::value ? L.r64 : L.ct0;
+  double *out = std::is_same<T, double>::value ? L.x64 : L.ct1;
+  const double *ar = L.cinv + row * L.nfree;
+  double acc = 0.0;
+  for (int64_t c = lane; c < L.nfree; c += kWave) acc += ar[c] * in[L.cfree[c]];
+  acc = dev::wave_sum(acc);
+  if (lane == 0) out[L.cfree[row]] = acc;
+}
+
+__global__ __launch_bounds__(256) void kb_coarse_post(const DLev *__restrict__ lev,
+                                                      const int *__restrict__ active, WorkSet ws) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DLev &L = lev[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < L.n) L.x32[k] = (float)L.ct1[k];
+}
+
+// ------------------------------------------------------------ Krylov
+template <typename T>
+__global__ __launch_bounds__(256) void kb_copy_in(const DLev *__restrict__ lev0,
+                                                  const DKry *__restrict__ kry,
+                                                  const int *__restrict__ active, WorkSet ws, int j) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < K.n) LV<T>::r(lev0[i])[k] = (T)K.V[(int64_t)j * K.n + k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_copy_out(const DLev *__restrict__ lev0,
+                                                   const DKry *__restrict__ kry,
+                                                   const int *__restrict__ active, WorkSet ws, int j) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < K.n) K.Z[(int64_t)j * K.n + k] = (double)LV<T>::x(lev0[i])[k];
+}
+
+// per-block partials of V[0..nvec)^T w (or of w.w): each instance owns nblk
+// blocks and strides over its own vector only
+template <int NV, int NORM>
+__global__ __launch_bounds__(256) void kb_multidot(const DKry *__restrict__ kry,
+                                                   const int *__restrict__ active, WorkSet ws,
+                                                   int nvec) {
+  __shared__ double red[4];
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int64_t lb = blockIdx.x - ws.pre[s];
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const double *V = NORM ? K.w : K.V;
+  const int64_t stride = (int64_t)K.nblk * 256;
+  for (int64_t t = lb * 256 + threadIdx.x; t < K.n; t += stride) {
+    const double wi = K.w[t];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) acc[k] += V[(int64_t)k * K.n + t] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if (k < nvec) {
+      const double tt = dev::block_sum(acc[k], red);
+      if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
+    }
+}
+
+// w -= V h, then partials of V^T w (NORM 0) or of w.w (NORM 1)
+template <int NV, int NORM>
+__global__ __launch_bounds__(256) void kb_axpy_red(const DKry *__restrict__ kry,
+                                                   const int *__restrict__ active, WorkSet ws,
+                                                   int nvec, const double *__restrict__ hs, int hoff) {
+  __shared__ double red[4];
+  __shared__ double hv[NV];
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  if (threadIdx.x < NV) hv[threadIdx.x] = threadIdx.x < nvec ? hs[(int64_t)i * kHS + hoff + threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t lb = blockIdx.x - ws.pre[s];
+  double acc[NORM ? 1 : NV];
+#pragma unroll
+  for (int k = 0; k < (NORM ? 1 : NV); ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)K.nblk * 256;
+  for (int64_t t = lb * 256 + threadIdx.x; t < K.n; t += stride) {
+    double v[NV];
+    double wi = K.w[t];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) {
+        v[k] = K.V[(int64_t)k * K.n + t];
+        wi -= hv[k] * v[k];
+      }
+    K.w[t] = wi;
+    if (NORM) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (k < nvec) acc[k] += v[k] * wi;
+    }
+  }
+  if (NORM) {
+    const double tt = dev::block_sum(acc[0], red);
+    if (threadIdx.x == 0) K.partial[lb] = tt;
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nvec) {
+        const double tt = dev::block_sum(acc[k], red);
+        if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
+      }
+  }
+}
+
+// one workgroup per (instance, component): fixed-order sum of the partials
+__global__ __launch_bounds__(256) void kb_reduce(const DKry *__restrict__ kry,
+                                                 const int *__restrict__ active, WorkSet ws,
+                                                 int nvec, double *__restrict__ hs, int off) {
+  __shared__ double red[4];
+  const int s = blockIdx.x / nvec, k = blockIdx.x - s * nvec;
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < K.nblk; b += blockDim.x) t += K.partial[(int64_t)b * nvec + k];
+  t = dev::block_sum(t, red);
+  if (threadIdx.x == 0) hs[(int64_t)i * kHS + off + k] = t;
+}
+
+__global__ void kb_add_h(const int *__restrict__ active, WorkSet ws, int nvec,
+                         double *__restrict__ hs) {
+  const int i = ws.inst[blockIdx.x];
+  if (!active[i] || threadIdx.x >= nvec) return;
+  double *h = hs + (int64_t)i * kHS;
+  h[kOffH + threadIdx.x] = h[kOffH1 + threadIdx.x] + h[kOffH2 + threadIdx.x];
+}
+
+// V[target] = w / sqrt(ss)
+__global__ __launch_bounds__(256) void kb_scale(const DKry *__restrict__ kry,
+                                                const int *__restrict__ active, WorkSet ws,
+                                                const double *__restrict__ hs, int target) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < K.n) K.V[(int64_t)target * K.n + k] = K.w[k] / sqrt(hs[(int64_t)i * kHS + kOffSS]);
+}
+
+// x += Z y with this instance's k directions
+template <int NV>
+__global__ __launch_bounds__(256) void kb_combine(const DKry *__restrict__ kry,
+                                                  const int *__restrict__ active, WorkSet ws,
+                                                  const double *__restrict__ hs,
+                                                  const int *__restrict__ kcnt) {
+  __shared__ double ys[NV];
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int kk = kcnt[i];
+  if (threadIdx.x < NV) ys[threadIdx.x] = threadIdx.x < kk ? hs[(int64_t)i * kHS + kOffY + threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t t = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (t >= K.n) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < NV; ++jj)
+    if (jj < kk) acc += ys[jj] * K.Z[(int64_t)jj * K.n + t];
+  K.x[t] += acc;
+}
+
+__global__ __launch_bounds__(256) void kb_nonfinite(const DKry *__restrict__ kry,
+                                                    const int *__restrict__ active, WorkSet ws,
+                                                    int *__restrict__ flags) {
+  const int s = seg_of(ws, blockIdx.x);
+  const int i = ws.inst[s];
+  if (!active[i]) return;
+  const DKry &K = kry[i];
+  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  if (k < K.n && !isfinite(K.w[k])) atomicOr(&flags[i], 1);
+}
+
+inline dim3 grid_of(const WorkSet &ws) { return dim3((unsigned)ws.nblocks); }
+
+}  // namespace
+
+int krylov_blocks(int64_t n) {
+  const int64_t nb = (n + 1023) / 1024;
+  return (int)(nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb));
+}
+
+template <typename T>
+void launch_b_spmv(int b, int src, const DLev *lev, const DKry *kry, const int *active,
+                   const WorkSet &ws, int j, hipStream_t s) {
+  if (ws.nblocks == 0) return;
+#define FSIMG_BS(BV, SV, TT)                                                                     \
+  if (b == BV && src == SV) {                                                                    \
+    hipLaunchKernelGGL((kb_spmv<BV, TT, SV>), grid_of(ws), dim3(256), 0, s, lev, kry, active, ws, \
+                       j);                                                                       \
+    return;                                                                                      \
+  }
+  FSIMG_BS(1, BS_VCYCLE, T) FSIMG_BS(2, BS_VCYCLE, T) FSIMG_BS(3, BS_VCYCLE, T)
+  FSIMG_BS(4, BS_VCYCLE, T)
+  FSIMG_BS(1, BS_AZ, double) FSIMG_BS(2, BS_AZ, double) FSIMG_BS(3, BS_AZ, double)
+  FSIMG_BS(4, BS_AZ, double)
+  FSIMG_BS(1, BS_RESID, double) FSIMG_BS(2, BS_RESID, double) FSIMG_BS(3, BS_RESID, double)
+  FSIMG_BS(4, BS_RESID, double)
+#undef FSIMG_BS
+}
+
+template <typename T>
+void launch_b_vanka(int np, int b, int nl, int npc, T omega, bool first, bool assign,
+                    const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  int ppw = 1, threads = 64;
+  vanka_shape(np, &ppw, &threads);
+  if (e0) (void)hipEventRecord(e0, s);
+  if (wp.nblocks > 0)
+    hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(threads), sizeof(T) * (size_t)ppw * npc,
+                       s, lev, active, wp, np, npc, b, nl, ppw, first ? 1 : 0);
+  if (e1) (void)hipEventRecord(e1, s);
+  if (wg.nblocks > 0)
+    hipLaunchKernelGGL((kb_vanka_gather<T>), grid_of(wg), dim3(256), 0, s, lev, active, wg, b, omega,
+                       assign ? 1 : 0);
+}
+
+template <typename T>
+void launch_b_fill_x(const DLev *lev, const int *active, const WorkSet &ws, hipStream_t s) {
+  if (ws.nblocks > 0)
+    hipLaunchKernelGGL((kb_fill_x<T>), grid_of(ws), dim3(256), 0, s, lev, active, ws);
+}
+
+template <typename T>
+void launch_b_restrict(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
+                       const WorkSet &ws, hipStream_t s) {
+  if (ws.nblocks == 0) return;
+#define FSIMG_BR(BV, DV)                                                                         \
+  if (b == BV && dim == DV) {                                                                    \
+    hipLaunchKernelGGL((kb_restrict<BV, DV, T>), grid_of(ws), dim3(256), 0, s, levF, levC, active, \
+                       ws);                                                                      \
+    return;                                                                                      \
+  }
+  FSIMG_BR(1, 2) FSIMG_BR(2, 2) FSIMG_BR(3, 2) FSIMG_BR(4, 2)
+  FSIMG_BR(1, 3) FSIMG_BR(2, 3) FSIMG_BR(3, 3) FSIMG_BR(4, 3)
+#undef FSIMG_BR
+}
+
+template <typename T>
+void launch_b_prolong(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
+                      const WorkSet &ws, hipStream_t s) {
+  if (ws.nblocks == 0) return;
+#define FSIMG_BP(BV, DV)                                                                         \
+  if (b == BV && dim == DV) {                                                                    \
+    hipLaunchKernelGGL((kb_prolong<BV, DV, T>), grid_of(ws), dim3(256), 0, s, levF, levC, active, \
+                       ws);                                                                      \
+    return;                                                                                      \
+  }
+  FSIMG_BP(1, 2) FSIMG_BP(2, 2) FSIMG_BP(3, 2) FSIMG_BP(4, 2)
+  FSIMG_BP(1, 3) FSIMG_BP(2, 3) FSIMG_BP(3, 3) FSIMG_BP(4, 3)
+#undef FSIMG_BP
+}
+
+template <typename T>
+void launch_b_coarse(const DLev *lev, const int *active, const WorkSet &wn, const WorkSet &wf,
+                     hipStream_t s) {
+  if (wn.nblocks > 0) hipLaunchKernelGGL((kb_coarse_pre<T>), grid_of(wn), dim3(256), 0, s, lev, active, wn);
+  if (wf.nblocks > 0) hipLaunchKernelGGL((kb_coarse_gemv<T>), grid_of(wf), dim3(256), 0, s, lev, active, wf);
+  if (!std::is_same<T, double>::value && wn.nblocks > 0)
+    hipLaunchKernelGGL(kb_coarse_post, grid_of(wn), dim3(256), 0, s, lev, active, wn);
+}
+
+template <typename T>
+void launch_b_copy_in(const DLev *lev0, const DKry *kry, const int *active, const WorkSet &ws,
+                      int j, hipStream_t s) {
+  if (ws.nblocks > 0)
+    hipLaunchKernelGGL((kb_copy_in<T>), grid_of(ws), dim3(256), 0, s, lev0, kry, active, ws, j);
+}
+
+template <typename T>
+void launch_b_copy_out(const DLev *lev0, const DKry *kry, const int *active, const WorkSet &ws,
+                       int j, hipStream_t s) {
+  if (ws.nblocks > 0)
+    hipLaunchKernelGGL((kb_copy_out<T>), grid_of(ws), dim3(256), 0, s, lev0, kry, active, ws, j);
+}
+
+#define FSIMG_NVB(nvec, KER)            \
+  do {                                  \
+    if ((nvec) <= 8) KER(8);            \
+    else if ((nvec) <= 16) KER(16);     \
+    else KER(32);                       \
+  } while (0)
+
+void launch_b_multidot(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm_w,
+                       hipStream_t s) {
+  if (wk.nblocks == 0) return;
+  if (norm_w) {
+    hipLaunchKernelGGL((kb_multidot<8, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, 1);
+    return;
+  }
+#define K(NV) hipLaunchKernelGGL((kb_multidot<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec)
+  FSIMG_NVB(nvec, K);
+#undef K
+}
+
+void launch_b_axpy_red(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm,
+                       const double *hs, int hoff, hipStream_t s) {
+  if (wk.nblocks == 0) return;
+  if (norm) {
+#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff)
+    FSIMG_NVB(nvec, K);
+#undef K
+  } else {
+#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff)
+    FSIMG_NVB(nvec, K);
+#undef K
+  }
+}
+
+void launch_b_reduce(const DKry *kry, const int *active, const WorkSet &wk, int nvec, double *hs,
+                     int off, hipStream_t s) {
+  if (wk.nset == 0) return;
+  hipLaunchKernelGGL(kb_reduce, dim3((unsigned)(wk.nset * nvec)), dim3(256), 0, s, kry, active, wk,
+                     nvec, hs, off);
+}
+
+void launch_b_add_h(const int *active, const WorkSet &wk, int nvec, double *hs, hipStream_t s) {
+  if (wk.nset == 0) return;
+  hipLaunchKernelGGL(kb_add_h, dim3((unsigned)wk.nset), dim3(64), 0, s, active, wk, nvec, hs);
+}
+
+void launch_b_scale(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
+                    int target, hipStream_t s) {
+  if (wv.nblocks > 0)
+    hipLaunchKernelGGL(kb_scale, grid_of(wv), dim3(256), 0, s, kry, active, wv, hs, target);
+}
+
+void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
+                      const int *kcnt, int kmax, hipStream_t s) {
+  if (wv.nblocks == 0) return;
+#define K(NV) hipLaunchKernelGGL((kb_combine<NV>), grid_of(wv), dim3(256), 0, s, kry, active, wv, hs, kcnt)
+  FSIMG_NVB(kmax, K);
+#undef K
+}
+
+void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, int *flags,
+                        hipStream_t s) {
+  if (wv.nblocks > 0)
+    hipLaunchKernelGGL(kb_nonfinite, grid_of(wv), dim3(256), 0, s, kry, active, wv, flags);
+}
+
+#define FSIMG_BINST(T)                                                                           \
+  template void launch_b_spmv<T>(int, int, const DLev *, const DKry *, const int *,              \
+                                 const WorkSet &, int, hipStream_t);                             \
+  template void launch_b_vanka<T>(int, int, int, int, T, bool, bool, const DLev *, const int *,  \
+                                  const WorkSet &, const WorkSet &, hipStream_t, hipEvent_t,     \
+                                  hipEvent_t);                                                   \
+  template void launch_b_fill_x<T>(const DLev *, const int *, const WorkSet &, hipStream_t);     \
+  template void launch_b_restrict<T>(int, int, const DLev *, const DLev *, const int *,          \
+                                     const WorkSet &, hipStream_t);                              \
+  template void launch_b_prolong<T>(int, int, const DLev *, const DLev *, const int *,           \
+                                    const WorkSet &, hipStream_t);                               \
+  template void launch_b_coarse<T>(const DLev *, const int *, const WorkSet &, const WorkSet &,  \
+                                   hipStream_t);                                                 \
+  template void launch_b_copy_in<T>(const DLev *, const DKry *, const int *, const WorkSet &, int, \
+                                    hipStream_t);                                                \
+  template void launch_b_copy_out<T>(const DLev *, const DKry *, const int *, const WorkSet &,   \
+                                     int, hipStream_t);
+FSIMG_BINST(double)
+FSIMG_BINST(float)
+#undef FSIMG_BINST
+
+}  // namespace fsimg

@@ -45,6 +45,96 @@ struct DevLevel {
   double *ct0 = nullptr, *ct1 = nullptr;  // FP64 coarse work vectors (mixed mode casts)
 };
 
+// ------------------------------------------------- batched execution
+// Device view of one level of one instance (hierarchy) for the batched
+// kernels: every batched launch covers one level of many instances.
+struct DLev {
+  const int32_t *rowptr, *colind;
+  const double *v64;
+  const float *v32;
+  const uint8_t *mask;
+  int64_t nrows, n;
+  int cells[4];
+  int64_t npatch;
+  const int32_t *pnodes;
+  const double *inv64;
+  const float *inv32;
+  const int32_t *gptr, *gidx;
+  const double *sc64;
+  const float *sc32;
+  double *r64, *x64, *d64, *Y64;
+  float *r32, *x32, *d32, *Y32;
+  int64_t nfree;
+  const int32_t *cfree;
+  const double *cinv;
+  double *ct0, *ct1;
+};
+
+// Krylov state of one instance (FP64): basis V, preconditioned directions
+// Z, work vector w, reduction partials, and the caller's b / x.
+struct DKry {
+  double *V, *Z, *w, *partial;
+  const double *b;
+  double *x;
+  int64_t n;
+  int nblk;  // reduction blocks of this instance (depends on n only)
+  int pad;
+};
+
+// One batched launch: the instances it covers and the prefix sums of their
+// work blocks (pre[s] = first block of instance inst[s]).
+struct WorkSet {
+  const int32_t *inst;
+  const int64_t *pre;
+  int nset;
+  int64_t nblocks;
+};
+
+constexpr int kHS = 160;  // per-instance small vector: h1[32] h2[32] h[32] ss y[32]
+constexpr int kOffH1 = 0, kOffH2 = 32, kOffH = 64, kOffSS = 96, kOffY = 128;
+
+int krylov_blocks(int64_t n);  // reduction blocks of a vector of length n
+
+enum BatchSpmvSrc { BS_VCYCLE = 0, BS_AZ = 1, BS_RESID = 2 };
+
+template <typename T>
+void launch_b_spmv(int b, int src, const DLev *lev, const DKry *kry, const int *active,
+                   const WorkSet &ws, int j, hipStream_t s);
+template <typename T>
+void launch_b_vanka(int np, int b, int nl, int npc, T omega, bool first, bool assign,
+                    const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+void launch_b_fill_x(const DLev *lev, const int *active, const WorkSet &ws, hipStream_t s);
+template <typename T>
+void launch_b_restrict(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
+                       const WorkSet &ws, hipStream_t s);
+template <typename T>
+void launch_b_prolong(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
+                      const WorkSet &ws, hipStream_t s);
+template <typename T>
+void launch_b_coarse(const DLev *lev, const int *active, const WorkSet &wn, const WorkSet &wf,
+                     hipStream_t s);
+template <typename T>
+void launch_b_copy_in(const DLev *lev0, const DKry *kry, const int *active, const WorkSet &ws,
+                      int j, hipStream_t s);
+template <typename T>
+void launch_b_copy_out(const DLev *lev0, const DKry *kry, const int *active, const WorkSet &ws,
+                       int j, hipStream_t s);
+void launch_b_multidot(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm_w,
+                       hipStream_t s);
+void launch_b_axpy_red(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm,
+                       const double *hs, int hoff, hipStream_t s);
+void launch_b_reduce(const DKry *kry, const int *active, const WorkSet &wk, int nvec, double *hs,
+                     int off, hipStream_t s);
+void launch_b_add_h(const int *active, const WorkSet &wk, int nvec, double *hs, hipStream_t s);
+void launch_b_scale(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
+                    int target, hipStream_t s);
+void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
+                      const int *kcnt, int kmax, hipStream_t s);
+void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, int *flags,
+                        hipStream_t s);
+
 // ---------------------------------------------------------------- kernels
 template <typename T>
 void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T *y, bool resid,

@@ -1,0 +1,74 @@
+// Host-side structures of contexts and hierarchies, shared by the C-ABI
+// implementation and the batched solve driver.
+#pragma once
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "fsimg_internal.h"
+
+struct BatchPlan;
+using fsimg::DevLevel;
+
+struct fsimg_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  BatchPlan *plan = nullptr;  // descriptor tables of the last batch composition
+};
+
+struct EventTimer {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  void begin_solve() { used = 0; }
+  hipEvent_t next() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  double total_ms(int *count) const {
+    double t = 0.0;
+    int c = 0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) { t += ms; ++c; }
+    }
+    *count = c;
+    return t;
+  }
+  ~EventTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+struct fsimg_hier {
+  uint64_t uid = 0;  // unique per created hierarchy (batch plan cache key)
+  fsimg_ctx *ctx = nullptr;
+  fsimg_opts opts{};
+  std::vector<DevLevel> lev;
+  std::vector<std::pair<void *, size_t>> allocs;
+  std::vector<std::vector<uint8_t>> host_mask;
+  std::vector<std::vector<uint8_t>> host_class;
+  bool factored = false;
+  int m = 20;
+  // FGMRES workspace (FP64)
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *small = nullptr;
+  double *hpin = nullptr;
+  int *dstatus = nullptr;
+  int *hstatus = nullptr;
+  EventTimer tv, ts;
+  bool profiling = false;
+};
+
+
+namespace fsimg {
+fsimg_status set_error(fsimg_status s, const std::string &msg);
+void destroy_plan(BatchPlan *p);
+bool plan_covers(const BatchPlan *p, uint64_t uid);
+// batched FGMRES over n hierarchies (shared options / precision / block size)
+fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
+                         double *const *x, fsimg_stats *stats, hipStream_t s);
+}  // namespace fsimg

@@ -84,6 +84,8 @@ _SIGS = {
     "fsimg_hier_set_profile": (_I, [_P, _I]),
     "fsimg_factor": (_I, [_P, _P]),
     "fsimg_solve": (_I, [_P, _P, _P, ctypes.POINTER(fsimg_stats), _P]),
+    "fsimg_solve_batch": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                               ctypes.POINTER(fsimg_stats), _P]),
     "fsimg_deform_update": (_I, [_I64, _I, _P, _D, _D, _P, _I, _I, _P, _P, _P, _P]),
     "fsimg_level_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "fsimg_level_residual": (_I, [_P, _I, _I, _P, _P, _P, _P]),
@@ -240,6 +242,20 @@ def fsimg_solve(h, b, x, stream=None, raise_on_noconv: bool = True) -> dict:
     if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
         _check(rc)
     return st.as_dict()
+
+
+def fsimg_solve_batch(hiers, bs, xs, stream=None, raise_on_noconv: bool = True) -> list:
+    """Solve len(hiers) independent systems in one batched solve; returns the
+    per-instance stats."""
+    n = len(hiers)
+    H = (ctypes.c_void_p * n)(*hiers)
+    B = (ctypes.c_void_p * n)(*[_dev(t) for t in bs])
+    X = (ctypes.c_void_p * n)(*[_dev(t) for t in xs])
+    st = (fsimg_stats * n)()
+    rc = load().fsimg_solve_batch(n, H, B, X, st, _stream(stream))
+    if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
+        _check(rc)
+    return [s.as_dict() for s in st]
 
 
 def fsimg_deform_update(nnodes: int, dim: int, mask, k: float, theta: float, v_new, v_stride: int,
