@@ -211,6 +211,194 @@ def cpu_baseline(P, iters_gpu, budget_s=20.0):
                         f"{t_setup:.0f} s untimed"))
 
 
+def run_batched(args):
+    """Batched workload: independent 3D instances (N ~ U{16,20,24,32,40},
+    random solid box and mu), mixed precision, momentum systems solved to
+    1e-8 in lockstep batches that fill an HBM budget (admission waves)."""
+    import numpy as np
+    import torch
+    from fsigen import batch_instance
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import level_dicts
+
+    prec = fsimg.FSIMG_FP64 if args.only == "fp64" else fsimg.FSIMG_MIXED
+    budget = int(args.budget_gb * (1 << 30))
+    ctx = fsimg.fsimg_ctx_create(0, budget)
+    opts = fsimg.fsimg_default_opts(precision=prec)
+    dev = torch.device("cuda:0")
+    waves, unknowns, solve_s, sizes, iters = [], 0, 0.0, [], []
+    pending = list(range(args.instances))
+    check = None
+    while pending:
+        wave, used, probs = [], 0, []
+        while pending:
+            P = batch_instance(pending[0])
+            fp = fsimg.fsimg_hier_footprint(level_dicts(P, "mom"), opts)
+            if wave and used + fp > budget * 0.95:
+                break
+            pending.pop(0)
+            wave.append(P)
+            used += fp
+        log(f"wave {len(waves)}: {len(wave)} instances, footprint {used / 2**30:.1f} GiB")
+        hs = [fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), opts) for P in wave]
+        for h in hs:
+            fsimg.fsimg_factor(h)
+        bs = [torch.tensor(P.rhs["mom"], device=dev) for P in wave]
+        for rep in range(2):  # warm-up, then timed
+            xs = [torch.zeros_like(b) for b in bs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = fsimg.fsimg_solve_batch(hs, bs, xs)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        if check is None:  # one instance solved alone must equal its in-batch result
+            xa = torch.zeros_like(bs[0])
+            fsimg.fsimg_solve(hs[0], bs[0], xa)
+            torch.cuda.synchronize()
+            check = bool(torch.equal(xa, xs[0]))
+        n_w = sum(int(b.numel()) for b in bs)
+        unknowns += n_w
+        solve_s += t
+        waves.append({"instances": len(wave), "unknowns": n_w, "solve_s": t,
+                      "footprint_GiB": used / 2**30})
+        sizes += [P.levels[0].cells[0] for P in wave]
+        iters += [s["iters"] for s in sts]
+        for h in hs:
+            fsimg.fsimg_hier_destroy(h)
+        del hs, bs, xs
+    fsimg.fsimg_ctx_destroy(ctx)
+    out = {
+        "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
+        "value": unknowns / solve_s, "unit": "DoF/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": solve_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if prec == fsimg.FSIMG_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.instances} independent 3D momentum systems, N ~ U{{16,20,24,32,40}}, "
+                               "solid box and mu ~ logU[1e4,1e6] per seed, lambda = 4 mu, batched "
+                               "FGMRES + V-cycle to 1e-8, admission waves under an HBM budget",
+                   "budget_GiB": args.budget_gb, "waves": waves,
+                   "iters_min_mean_max": [min(iters), float(np.mean(iters)), max(iters)],
+                   "cells_per_axis": sizes, "alone_equals_batched": check},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args):
+    """Serving workload: Poisson arrivals of FSI simulations (10 time steps of
+    3..5 Newton steps; 70 % 2D 64^2..256^2, 30 % 3D 16^3..48^3), hierarchies
+    resident in HBM, first-fit admission by footprint, continuous batching,
+    mixed precision.  Latency = arrival -> last solve of the simulation."""
+    import numpy as np
+    import torch
+    from fsigen import serve_instance
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import request_data
+
+    rng = np.random.Generator(np.random.PCG64(args.seed))
+    sizes2, sizes3 = (64, 80, 96, 128, 160, 192, 256), (16, 20, 24, 32, 40, 48)
+    t0 = time.perf_counter()
+    pool = {}
+    for d, sz in [(2, n) for n in sizes2] + [(3, n) for n in sizes3 if n <= args.max3d]:
+        P = serve_instance(d, n=sz, seed=sz)
+        log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels")
+        pool[(d, sz)] = (request_data(P), P.levels[0].systems["mom"].nrows * (d + 1),
+                         P.levels[0].systems["ale"].nrows * d)
+    log(f"serving pool of {len(pool)} simulations generated in {time.perf_counter() - t0:.1f} s")
+    # arrival process
+    arrivals, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.window:
+            break
+        d = 2 if rng.uniform() < 0.7 else 3
+        sz = int(rng.choice(sizes2 if d == 2 else [n for n in sizes3 if n <= args.max3d]))
+        ns = rng.integers(3, 6, size=10)
+        arrivals.append((t, d, sz, ns))
+    budget = int(args.budget_gb * (1 << 30))
+    ctx = fsimg.fsimg_ctx_create(0, budget)
+    opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
+    srv = fsimg.fsimg_server_create(ctx, opts, args.max_active)
+    stream = torch.cuda.current_stream()
+    meta, lat, qdelay, done_ids, work = {}, [], [], [], 0.0
+    nxt, steps = 0, 0
+    start = fsimg.fsimg_server_clock(srv)
+    last_log = 0.0
+    while True:
+        now = fsimg.fsimg_server_clock(srv) - start
+        while nxt < len(arrivals) and arrivals[nxt][0] <= now:
+            ta, d, sz, ns = arrivals[nxt]
+            data, nm, na = pool[(d, sz)]
+            rid = fsimg.fsimg_server_submit(srv, data, ns, start + ta)
+            meta[rid] = (start + ta, d, sz, nm, na, int(ns.sum()))
+            nxt += 1
+        active, queued = fsimg.fsimg_server_step(srv, stream)
+        steps += 1
+        ids, adm, fin = fsimg.fsimg_server_poll(srv)
+        for rid, a, f in zip(ids, adm, fin):
+            arr, d, sz, nm, na, nsteps = meta[abs(int(rid))]
+            if rid > 0:
+                lat.append(f - arr)
+                qdelay.append(a - arr)
+                done_ids.append(int(rid))
+                work += nsteps * (nm + na)
+        now = fsimg.fsimg_server_clock(srv) - start
+        if now - last_log > 10.0:
+            last_log = now
+            log(f"  t={now:.1f} s: {nxt} arrived, {active} running, {queued} queued, "
+                f"{len(lat)} completed")
+        if nxt >= len(arrivals) and active == 0 and queued == 0:
+            break
+        if now > args.max_wall:
+            break
+        if active == 0 and nxt < len(arrivals):
+            time.sleep(max(0.0, min(arrivals[nxt][0] - now, 0.05)))
+    wall = fsimg.fsimg_server_clock(srv) - start
+    # one completed request rerun alone must give the same result
+    same = None
+    if done_ids:
+        rid = done_ids[len(done_ids) // 2]
+        arr, d, sz, nm, na, nsteps = meta[rid]
+        xm_mix, xa_mix = fsimg.fsimg_server_result(srv, rid, nm, na)
+        srv2 = fsimg.fsimg_server_create(ctx, opts)
+        data = pool[(d, sz)][0]
+        ns_alone = next(a[3] for a in arrivals if abs(a[0] + start - arr) < 1e-12)
+        rid2 = fsimg.fsimg_server_submit(srv2, data, ns_alone, fsimg.fsimg_server_clock(srv2))
+        while True:
+            act, q = fsimg.fsimg_server_step(srv2, stream)
+            if act == 0 and q == 0:
+                break
+        fsimg.fsimg_server_poll(srv2)
+        xm_al, xa_al = fsimg.fsimg_server_result(srv2, rid2, nm, na)
+        same = bool(np.array_equal(xm_mix, xm_al) and np.array_equal(xa_mix, xa_al))
+        fsimg.fsimg_server_destroy(srv2)
+    fsimg.fsimg_server_destroy(srv)
+    fsimg.fsimg_ctx_destroy(ctx)
+    lat_a = np.array(lat) if lat else np.array([np.nan])
+    q_a = np.array(qdelay) if qdelay else np.array([np.nan])
+    out = {
+        "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
+        "value": work / wall, "unit": "DoF/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": wall / max(steps, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": ("serving: Poisson arrivals of FSI simulations, 10 time steps x 3..5 "
+                                "Newton steps (momentum + deformation + ALE solves to 1e-8), 70% 2D "
+                                f"64^2..256^2, 30% 3D 16^3..{max(n for n in sizes3 if n <= args.max3d)}^3, "
+                                "mixed precision, resident hierarchies, first-fit admission by HBM "
+                                "footprint, continuous batching"),
+                   "max_active": args.max_active,
+                   "rate_req_s": args.rate, "window_s": args.window, "budget_GiB": args.budget_gb,
+                   "arrived": len(arrivals), "completed": len(lat),
+                   "offered_req_s": len(arrivals) / args.window,
+                   "achieved_req_s": len(lat) / wall, "wall_s": wall,
+                   "latency_p50_s": float(np.percentile(lat_a, 50)),
+                   "latency_p99_s": float(np.percentile(lat_a, 99)),
+                   "queue_delay_p50_s": float(np.percentile(q_a, 50)),
+                   "queue_delay_p99_s": float(np.percentile(q_a, 99)),
+                   "alone_equals_mix": same},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,14 +416,29 @@ def main():
                     help="only launch REPS finest-level smoothing steps (counter runs)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--instances", type=int, default=64, help="batched workload size")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the batched workload")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--window", type=float, default=3.0, help="serving: arrival window (s)")
+    ap.add_argument("--max-wall", type=float, default=90.0, help="serving: stop after this many s")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-active", type=int, default=0,
+                    help="serving: admitted requests at most (0 = as many as fit)")
+    ap.add_argument("--max3d", type=int, default=48, help="serving: largest 3D mesh (cells per axis)")
     args = ap.parse_args()
-    if args.calib_copy:
-        calib_copy(args.calib_copy << 20, 5)
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"sharding of this path is described in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c4":
+        run_batched(args)
+        return
+    if args.config == "c5":
+        run_serving(args)
+        return
+    if args.calib_copy:
+        calib_copy(args.calib_copy << 20, 5)
+        return
     import numpy as np
     from fsigen import config_problem
     from oracle import to_csr

@@ -453,6 +453,19 @@ def batch_instance(index: int, base_seed: int = 1000, sizes=(16, 20, 24, 32, 40)
                         params={"mu_s": mu, "lambda_s": 4.0 * mu}, systems=systems)
 
 
+def serve_instance(dim: int, n: int, seed: int = 0) -> Problem:
+    """One simulation of the serving workload: the 2D or 3D box configuration
+    with n cells per axis, coarsened while the coarsest level keeps at least
+    3 cells per axis (4 in 2D), momentum and ALE systems."""
+    coarse, nlev = n, 1
+    lim = 4 if dim == 2 else 3
+    while coarse % 2 == 0 and coarse // 2 >= lim:
+        coarse //= 2
+        nlev += 1
+    return make_problem(dim, n, nlev, SOLID_2D if dim == 2 else SOLID_3D, seed=seed,
+                        systems=("mom", "ale"))
+
+
 def config_problem(name: str, seed: int = 0, **kw) -> Problem:
     """Named workloads: 'c1' (2D 32^2, 3 levels), 'c2' (3D 32^3, 4 levels),
     'c3' (3D 64^3, 5 levels) and small test cases 't2' (2D 8^2, 2 levels),

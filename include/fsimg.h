@@ -230,6 +230,56 @@ fsimg_status fsimg_vcycle(fsimg_hier *h, int precision, const void *r_dev, void 
 fsimg_status fsimg_patch_inverse(fsimg_hier *h, int level, int64_t patch, double *out_host,
                                  int64_t *elem, void *stream);
 
+/* ---- serving: many simulations sharing one GPU ----
+   A request is one FSI simulation: time_steps time steps, newton_steps[t]
+   Newton steps in step t; every Newton step is the linear solve of the
+   reduced Jacobian (Sec. 4.2): momentum solve, condensed deformation update,
+   ALE solve.  The Jacobian is refactored at the start of every time step
+   (the paper reassembles about once per time step, Sec. 5.5.2); the ALE
+   matrix is factored once per request.  Requests wait in a queue until their
+   hierarchies fit in the context's HBM budget (first fit in arrival order);
+   admitted requests keep their hierarchies resident, and every server step
+   solves the current Newton step of all admitted requests together (one
+   batched solve per system and dimension), so requests join and leave
+   between steps.  Each result equals the result of the request alone. */
+typedef struct {
+  int nlev;                         /* levels of both systems */
+  const fsimg_level_desc *mom;      /* momentum levels, finest first */
+  const fsimg_level_desc *ale;      /* ALE levels, finest first */
+  const double *b_mom, *b_ale;      /* finest-level right-hand sides */
+  const uint8_t *node_solid;        /* finest nodes on interface / in the solid */
+  int time_steps;
+  const int *newton_steps;          /* [time_steps] */
+  double k, theta;                  /* time step and theta of the deformation update */
+  double arrival;                   /* arrival time on the server clock (s) */
+} fsimg_request;
+
+typedef struct fsimg_server fsimg_server;
+
+/* opts: solver options of every hierarchy the server creates; max_active:
+   admitted requests at most (0 = no limit).  Host arrays of submitted
+   requests are read at admission: the caller keeps them valid until the
+   request is admitted (fsimg_server_step reports admissions). */
+fsimg_status fsimg_server_create(fsimg_ctx *ctx, const fsimg_opts *opts, int max_active,
+                                 fsimg_server **out);
+void fsimg_server_destroy(fsimg_server *srv);
+double fsimg_server_clock(const fsimg_server *srv);  /* seconds since creation */
+fsimg_status fsimg_server_submit(fsimg_server *srv, const fsimg_request *req, int64_t *id);
+/* Admit what fits, then run one Newton step of every admitted request.
+   Reports the number of admitted (running) and queued requests after the
+   step.  ERR_BUDGET if the queue head can never fit an empty budget. */
+fsimg_status fsimg_server_step(fsimg_server *srv, int *n_active, int *n_queued, void *stream);
+/* Completed requests since the last call: ids, admission and finish times
+   (server clock), at most max entries. */
+fsimg_status fsimg_server_poll(fsimg_server *srv, int64_t *ids, double *admitted, double *finished,
+                               int max, int *count);
+/* Copy the last momentum and ALE solutions of a request (running or
+   completed and not yet released) to host memory (either pointer may be NULL). */
+fsimg_status fsimg_server_result(fsimg_server *srv, int64_t id, double *x_mom_host,
+                                 double *x_ale_host);
+/* Forget a completed request's stored solution. */
+fsimg_status fsimg_server_release(fsimg_server *srv, int64_t id);
+
 const char *fsimg_last_error(void);
 
 #ifdef __cplusplus

@@ -455,7 +455,7 @@ fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **o
 
 void fsimg_ctx_destroy(fsimg_ctx *ctx) {
   if (!ctx) return;
-  destroy_plan(ctx->plan);
+  for (BatchPlan *p : ctx->plans) destroy_plan(p);
   delete ctx;
 }
 
@@ -499,10 +499,15 @@ fsimg_status fsimg_hier_footprint(const fsimg_level_desc *levels, int nlev, cons
 void fsimg_hier_destroy(fsimg_hier *h) {
   if (!h) return;
   (void)hipSetDevice(h->ctx->device);
-  if (h->ctx->plan) {  // a cached batch plan that covers this hierarchy is stale
-    if (plan_covers(h->ctx->plan, h->uid)) {
-      destroy_plan(h->ctx->plan);
-      h->ctx->plan = nullptr;
+  {  // cached batch plans that cover this hierarchy are stale
+    auto &ps = h->ctx->plans;
+    for (size_t i = 0; i < ps.size();) {
+      if (plan_covers(ps[i], h->uid)) {
+        destroy_plan(ps[i]);
+        ps.erase(ps.begin() + (long)i);
+      } else {
+        ++i;
+      }
     }
   }
   for (auto &a : h->allocs) {

@@ -20,6 +20,7 @@
 using namespace fsimg;
 
 struct BatchPlan {
+  fsimg_ctx *ctx = nullptr;  // the budget the descriptor tables are charged to
   std::vector<uint64_t> key;
   int n = 0, Lmax = 0, b = 0, dim = 0, np = 0, nl = 0, npc = 0;
   bool mixed = false;
@@ -42,10 +43,25 @@ namespace fsimg {
 
 void destroy_plan(BatchPlan *p) {
   if (!p) return;
-  if (p->dbuf) (void)hipFree(p->dbuf);
+  if (p->dbuf) {
+    (void)hipFree(p->dbuf);
+    if (p->ctx) {
+      p->ctx->in_use -= p->dbytes;
+      p->ctx->plan_bytes -= p->dbytes;
+    }
+  }
   if (p->hs_host) (void)hipHostFree(p->hs_host);
   if (p->int_host) (void)hipHostFree(p->int_host);
   delete p;
+}
+
+size_t plan_bytes_bound(int nlev) {
+  // per instance: level descriptors, Krylov descriptor, three flags, the
+  // Hessenberg slot and one (instance, prefix) entry in each work set; per
+  // plan: one prefix entry and 256-byte alignment of every table
+  const size_t nset = 7 * (size_t)nlev + 4, ntab = 6 + 2 * nset;
+  return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 3 * sizeof(int) + kHS * sizeof(double) +
+         nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 256;
 }
 
 bool plan_covers(const BatchPlan *p, uint64_t uid) {
@@ -190,6 +206,9 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
     delete P;
     return set_error(FSIMG_ERR_OOM, "batch descriptor allocation failed");
   }
+  P->ctx = ctx;
+  ctx->in_use += P->dbytes;
+  ctx->plan_bytes += P->dbytes;
   if (hipMemcpy(P->dbuf, blob.data.data(), P->dbytes, hipMemcpyHostToDevice) != hipSuccess) {
     destroy_plan(P);
     return set_error(FSIMG_ERR_HIP, "batch descriptor upload failed");
@@ -304,16 +323,25 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
       if (hs[j] == hs[i]) return set_error(FSIMG_ERR_ARG, "a hierarchy appears twice in a batch");
   }
   const auto t0 = std::chrono::steady_clock::now();
-  BatchPlan *P = ctx->plan;
-  bool same = P && (int)P->key.size() == n;
-  for (int i = 0; same && i < n; ++i) same = P->key[i] == hs[i]->uid;
-  if (!same) {
-    destroy_plan(ctx->plan);
-    ctx->plan = nullptr;
+  BatchPlan *P = nullptr;
+  for (size_t c = 0; c < ctx->plans.size() && !P; ++c) {
+    BatchPlan *q = ctx->plans[c];
+    bool same = (int)q->key.size() == n;
+    for (int i = 0; same && i < n; ++i) same = q->key[i] == hs[i]->uid;
+    if (same) {
+      P = q;
+      ctx->plans.erase(ctx->plans.begin() + (long)c);
+    }
+  }
+  if (!P) {
+    while (ctx->plans.size() >= kPlanCache) {  // least recently used first
+      destroy_plan(ctx->plans.back());
+      ctx->plans.pop_back();
+    }
     fsimg_status st = build_plan(ctx, n, hs, &P);
     if (st != FSIMG_OK) return st;
-    ctx->plan = P;
   }
+  ctx->plans.insert(ctx->plans.begin(), P);  // most recent first
   const bool prof = o.profile != 0;
   P->tv.begin_solve();
   P->ts.begin_solve();

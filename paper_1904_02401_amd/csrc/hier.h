@@ -14,7 +14,8 @@ struct fsimg_ctx {
   int device = 0;
   size_t budget = 0;
   size_t in_use = 0;
-  BatchPlan *plan = nullptr;  // descriptor tables of the last batch composition
+  size_t plan_bytes = 0;  // part of in_use held by cached batch plans
+  std::vector<BatchPlan *> plans;  // descriptor tables of recent batch compositions (LRU)
 };
 
 struct EventTimer {
@@ -67,6 +68,10 @@ struct fsimg_hier {
 namespace fsimg {
 fsimg_status set_error(fsimg_status s, const std::string &msg);
 void destroy_plan(BatchPlan *p);
+constexpr size_t kPlanCache = 8;  // batch compositions whose descriptor tables stay cached
+// device bytes one instance adds to a batch plan whose deepest hierarchy has
+// nlev levels, plus the plan's fixed part (an upper bound)
+size_t plan_bytes_bound(int nlev);
 bool plan_covers(const BatchPlan *p, uint64_t uid);
 // batched FGMRES over n hierarchies (shared options / precision / block size)
 fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,

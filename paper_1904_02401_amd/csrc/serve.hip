@@ -1,0 +1,349 @@
+// Serving loop: many FSI simulations share one GPU.  Requests queue until
+// their hierarchies fit in the HBM budget, stay resident while they run, and
+// every server step advances all running requests by one Newton step with
+// batched solves (continuous batching: requests join and leave between
+// steps).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "hier.h"
+
+using namespace fsimg;
+
+namespace {
+
+struct Req {
+  int64_t id = 0;
+  fsimg_request r{};
+  std::vector<int> newton;
+  int state = 0;  // 0 queued, 1 running, 2 finished
+  int status = FSIMG_OK;
+  fsimg_hier *hm = nullptr, *ha = nullptr;
+  double *b_mom = nullptr, *x_mom = nullptr, *b_ale = nullptr, *x_ale = nullptr;
+  uint8_t *mask = nullptr;
+  size_t vec_bytes = 0;
+  size_t reserve = 0;  // batch plan allowance held while running
+  int t = 0, nstep = 0, dim = 0, bm = 0, ba = 0;
+  int64_t nnodes = 0, nm = 0, na = 0;
+  double admitted = -1.0, finished = -1.0;
+  std::vector<double> xm_host, xa_host;
+};
+
+}  // namespace
+
+struct fsimg_server {
+  fsimg_ctx *ctx = nullptr;
+  fsimg_opts opts{};
+  int max_active = 0;
+  std::chrono::steady_clock::time_point t0;
+  int64_t next_id = 1;
+  size_t reserved = 0;  // plan allowance of the running requests
+  std::deque<Req *> queue;
+  std::vector<Req *> running;
+  std::vector<Req *> finished_unpolled;
+  std::map<int64_t, Req *> all;
+};
+
+namespace {
+
+double now_s(const fsimg_server *s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+void release_device(fsimg_server *S, Req *q) {
+  if (q->hm) fsimg_hier_destroy(q->hm);
+  if (q->ha) fsimg_hier_destroy(q->ha);
+  q->hm = q->ha = nullptr;
+  for (void *p : {(void *)q->b_mom, (void *)q->x_mom, (void *)q->b_ale, (void *)q->x_ale,
+                  (void *)q->mask})
+    if (p) (void)hipFree(p);
+  q->b_mom = q->x_mom = q->b_ale = q->x_ale = nullptr;
+  q->mask = nullptr;
+  S->ctx->in_use -= q->vec_bytes;
+  q->vec_bytes = 0;
+  S->reserved -= q->reserve;
+  q->reserve = 0;
+}
+
+// batch descriptor tables: every cached plan may hold an instance of each
+// running request, at the depth of the deepest hierarchy the library accepts.
+// Admission keeps (hierarchies + vectors + these allowances) within the
+// budget, so plan tables, which are charged to the budget when built, fit.
+size_t plan_reserve() { return kPlanCache * plan_bytes_bound(16); }
+
+// bytes held against the budget apart from the plan tables
+size_t held(const fsimg_server *S) { return S->ctx->in_use - S->ctx->plan_bytes + S->reserved; }
+
+size_t request_bytes(const fsimg_server *S, const Req *q, fsimg_status *st) {
+  size_t fm = 0, fa = 0;
+  *st = fsimg_hier_footprint(q->r.mom, q->r.nlev, &S->opts, &fm);
+  if (*st == FSIMG_OK) *st = fsimg_hier_footprint(q->r.ale, q->r.nlev, &S->opts, &fa);
+  return fm + fa + (size_t)(2 * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes + plan_reserve();
+}
+
+// create hierarchies, factor, upload vectors; false if it does not fit now
+fsimg_status admit(fsimg_server *S, Req *q, hipStream_t s) {
+  fsimg_status st = fsimg_hier_create(S->ctx, q->r.mom, q->r.nlev, &S->opts, s, &q->hm);
+  if (st == FSIMG_OK) st = fsimg_hier_create(S->ctx, q->r.ale, q->r.nlev, &S->opts, s, &q->ha);
+  if (st == FSIMG_OK) st = fsimg_factor(q->hm, s);
+  if (st == FSIMG_OK) st = fsimg_factor(q->ha, s);
+  if (st != FSIMG_OK) {
+    release_device(S, q);
+    return st;
+  }
+  const size_t bytes = (size_t)(2 * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes;
+  if (S->ctx->budget && S->ctx->in_use + bytes > S->ctx->budget) {
+    release_device(S, q);
+    return set_error(FSIMG_ERR_BUDGET, "request vectors exceed the budget");
+  }
+  bool ok = hipMalloc(&q->b_mom, q->nm * 8) == hipSuccess &&
+            hipMalloc(&q->x_mom, q->nm * 8) == hipSuccess &&
+            hipMalloc(&q->b_ale, q->na * 8) == hipSuccess &&
+            hipMalloc(&q->x_ale, q->na * 8) == hipSuccess &&
+            hipMalloc(&q->mask, q->nnodes) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    release_device(S, q);
+    return set_error(FSIMG_ERR_OOM, "request vector allocation failed");
+  }
+  q->vec_bytes = bytes;
+  S->ctx->in_use += bytes;
+  q->reserve = plan_reserve();
+  S->reserved += q->reserve;
+  ok = hipMemcpyAsync(q->b_mom, q->r.b_mom, q->nm * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipMemcpyAsync(q->b_ale, q->r.b_ale, q->na * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipMemcpyAsync(q->mask, q->r.node_solid, q->nnodes, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    release_device(S, q);
+    return set_error(FSIMG_ERR_HIP, "request upload failed");
+  }
+  q->state = 1;
+  q->admitted = now_s(S);
+  return FSIMG_OK;
+}
+
+void finish(fsimg_server *S, Req *q, hipStream_t s) {
+  q->xm_host.resize(q->nm);
+  q->xa_host.resize(q->na);
+  (void)hipMemcpyAsync(q->xm_host.data(), q->x_mom, q->nm * 8, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(q->xa_host.data(), q->x_ale, q->na * 8, hipMemcpyDeviceToHost, s);
+  (void)hipStreamSynchronize(s);
+  q->finished = now_s(S);
+  q->state = 2;
+  release_device(S, q);
+  S->finished_unpolled.push_back(q);
+}
+
+}  // namespace
+
+extern "C" {
+
+fsimg_status fsimg_server_create(fsimg_ctx *ctx, const fsimg_opts *opts, int max_active,
+                                 fsimg_server **out) {
+  if (!ctx || !opts || !out || max_active < 0) return set_error(FSIMG_ERR_ARG, "bad server arguments");
+  auto *S = new fsimg_server;
+  S->ctx = ctx;
+  S->opts = *opts;
+  S->max_active = max_active;
+  S->t0 = std::chrono::steady_clock::now();
+  *out = S;
+  return FSIMG_OK;
+}
+
+void fsimg_server_destroy(fsimg_server *S) {
+  if (!S) return;
+  for (auto &kv : S->all) {
+    release_device(S, kv.second);
+    delete kv.second;
+  }
+  delete S;
+}
+
+double fsimg_server_clock(const fsimg_server *S) { return S ? now_s(S) : 0.0; }
+
+fsimg_status fsimg_server_submit(fsimg_server *S, const fsimg_request *r, int64_t *id) {
+  if (!S || !r || !r->mom || !r->ale || !r->b_mom || !r->b_ale || !r->node_solid ||
+      !r->newton_steps || r->time_steps < 1 || r->nlev < 1)
+    return set_error(FSIMG_ERR_ARG, "incomplete request");
+  const fsimg_level_desc &m0 = r->mom[0], &a0 = r->ale[0];
+  if (m0.dim != a0.dim || m0.block != m0.dim + 1 || a0.block != a0.dim || m0.nrows != a0.nrows)
+    return set_error(FSIMG_ERR_ARG, "request systems must be momentum (b = d+1) and ALE (b = d) "
+                                    "on the same mesh");
+  auto *q = new Req;
+  q->id = S->next_id++;
+  q->r = *r;
+  q->newton.assign(r->newton_steps, r->newton_steps + r->time_steps);
+  for (int v : q->newton)
+    if (v < 1) {
+      delete q;
+      return set_error(FSIMG_ERR_ARG, "every time step needs at least one Newton step");
+    }
+  q->r.newton_steps = q->newton.data();
+  q->dim = m0.dim;
+  q->bm = m0.block;
+  q->ba = a0.block;
+  q->nnodes = m0.nrows;
+  q->nm = m0.nrows * m0.block;
+  q->na = a0.nrows * a0.block;
+  S->queue.push_back(q);
+  S->all[q->id] = q;
+  if (id) *id = q->id;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, void *stream) {
+  if (!S) return set_error(FSIMG_ERR_ARG, "null server");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  fsimg_status ret = FSIMG_OK;
+  // admission: first fit in arrival order
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
+    Req *q = *it;
+    if (S->max_active && (int)S->running.size() >= S->max_active) break;
+    fsimg_status st;
+    const size_t need = request_bytes(S, q, &st);
+    if (st != FSIMG_OK) {  // invalid descriptors: the request fails
+      q->status = st;
+      q->state = 2;
+      S->finished_unpolled.push_back(q);
+      it = S->queue.erase(it);
+      continue;
+    }
+    if (S->ctx->budget && need > S->ctx->budget) {  // can never fit
+      q->status = FSIMG_ERR_BUDGET;
+      q->state = 2;
+      S->finished_unpolled.push_back(q);
+      it = S->queue.erase(it);
+      ret = set_error(FSIMG_ERR_BUDGET, "a request needs more than the whole HBM budget");
+      continue;
+    }
+    if (S->ctx->budget && held(S) + need > S->ctx->budget) {
+      ++it;
+      continue;
+    }
+    st = admit(S, q, s);
+    if (st == FSIMG_OK) {
+      S->running.push_back(q);
+      it = S->queue.erase(it);
+    } else if (st == FSIMG_ERR_BUDGET || st == FSIMG_ERR_OOM) {
+      ++it;
+    } else {
+      q->status = st;
+      q->state = 2;
+      S->finished_unpolled.push_back(q);
+      it = S->queue.erase(it);
+    }
+  }
+  if (!S->running.empty()) {
+    // one Newton step of every running request: batched per system and dimension
+    for (int dim = 2; dim <= 3; ++dim) {
+      std::vector<fsimg_hier *> hs;
+      std::vector<const double *> bs;
+      std::vector<double *> xs;
+      std::vector<Req *> group;
+      for (Req *q : S->running)
+        if (q->dim == dim) group.push_back(q);
+      if (group.empty()) continue;
+      for (Req *q : group) {
+        launch_fill<double>(q->x_mom, q->nm, 0.0, s);
+        hs.push_back(q->hm);
+        bs.push_back(q->b_mom);
+        xs.push_back(q->x_mom);
+      }
+      std::vector<fsimg_stats> st(group.size());
+      fsimg_status r1 = solve_batch(S->ctx, (int)group.size(), hs.data(), bs.data(), xs.data(),
+                                    st.data(), s);
+      if (r1 != FSIMG_OK && r1 != FSIMG_ERR_NOCONV && r1 != FSIMG_ERR_NONFINITE) return r1;
+      for (size_t g = 0; g < group.size(); ++g) {
+        Req *q = group[g];
+        if (st[g].status != FSIMG_OK && q->status == FSIMG_OK) q->status = st[g].status;
+        launch_deform(q->nnodes, dim, q->mask, q->r.k, q->r.theta, q->x_mom, dim + 1, 1, nullptr,
+                      nullptr, q->x_ale, s);
+        hs[g] = q->ha;
+        bs[g] = q->b_ale;
+        xs[g] = q->x_ale;
+      }
+      fsimg_status r2 = solve_batch(S->ctx, (int)group.size(), hs.data(), bs.data(), xs.data(),
+                                    st.data(), s);
+      if (r2 != FSIMG_OK && r2 != FSIMG_ERR_NOCONV && r2 != FSIMG_ERR_NONFINITE) return r2;
+      for (size_t g = 0; g < group.size(); ++g)
+        if (st[g].status != FSIMG_OK && group[g]->status == FSIMG_OK) group[g]->status = st[g].status;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(FSIMG_ERR_HIP, "server step sync failed");
+    std::vector<Req *> still;
+    for (Req *q : S->running) {
+      if (++q->nstep == q->newton[q->t]) {
+        q->nstep = 0;
+        if (++q->t == q->r.time_steps) {
+          finish(S, q, s);
+          continue;
+        }
+        fsimg_status st = fsimg_factor(q->hm, s);  // a new time step: new Jacobian
+        if (st != FSIMG_OK) {
+          q->status = st;
+          finish(S, q, s);
+          continue;
+        }
+      }
+      still.push_back(q);
+    }
+    S->running.swap(still);
+  }
+  if (n_active) *n_active = (int)S->running.size();
+  if (n_queued) *n_queued = (int)S->queue.size();
+  return ret;
+}
+
+fsimg_status fsimg_server_poll(fsimg_server *S, int64_t *ids, double *admitted, double *finished,
+                               int max, int *count) {
+  if (!S || !count || max < 0) return set_error(FSIMG_ERR_ARG, "bad poll arguments");
+  int c = 0;
+  while (c < max && !S->finished_unpolled.empty()) {
+    Req *q = S->finished_unpolled.front();
+    S->finished_unpolled.erase(S->finished_unpolled.begin());
+    if (ids) ids[c] = q->status == FSIMG_OK ? q->id : -q->id;
+    if (admitted) admitted[c] = q->admitted;
+    if (finished) finished[c] = q->finished;
+    ++c;
+  }
+  *count = c;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_server_result(fsimg_server *S, int64_t id, double *xm, double *xa) {
+  if (!S) return set_error(FSIMG_ERR_ARG, "null server");
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return set_error(FSIMG_ERR_ARG, "unknown request id");
+  Req *q = it->second;
+  if (q->state == 2) {
+    if (xm && !q->xm_host.empty()) std::copy(q->xm_host.begin(), q->xm_host.end(), xm);
+    if (xa && !q->xa_host.empty()) std::copy(q->xa_host.begin(), q->xa_host.end(), xa);
+    return FSIMG_OK;
+  }
+  if (q->state == 1) {
+    if (xm && hipMemcpy(xm, q->x_mom, q->nm * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return set_error(FSIMG_ERR_HIP, "result copy failed");
+    if (xa && hipMemcpy(xa, q->x_ale, q->na * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return set_error(FSIMG_ERR_HIP, "result copy failed");
+    return FSIMG_OK;
+  }
+  return set_error(FSIMG_ERR_STATE, "request not started");
+}
+
+fsimg_status fsimg_server_release(fsimg_server *S, int64_t id) {
+  if (!S) return set_error(FSIMG_ERR_ARG, "null server");
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return set_error(FSIMG_ERR_ARG, "unknown request id");
+  if (it->second->state != 2) return set_error(FSIMG_ERR_STATE, "request still queued or running");
+  for (auto &f : S->finished_unpolled)
+    if (f == it->second) return set_error(FSIMG_ERR_STATE, "poll the request before releasing it");
+  delete it->second;
+  S->all.erase(it);
+  return FSIMG_OK;
+}
+
+}  // extern "C"

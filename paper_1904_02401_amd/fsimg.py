@@ -58,6 +58,14 @@ class fsimg_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fsimg_request(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int), ("mom", ctypes.POINTER(fsimg_level_desc)),
+                ("ale", ctypes.POINTER(fsimg_level_desc)), ("b_mom", ctypes.c_void_p),
+                ("b_ale", ctypes.c_void_p), ("node_solid", ctypes.c_void_p),
+                ("time_steps", ctypes.c_int), ("newton_steps", ctypes.c_void_p),
+                ("k", ctypes.c_double), ("theta", ctypes.c_double), ("arrival", ctypes.c_double)]
+
+
 class fsimg_level_info(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("n", ctypes.c_int64), ("nnzb", ctypes.c_int64),
                 ("npatch", ctypes.c_int64), ("np", ctypes.c_int), ("ncolours", ctypes.c_int),
@@ -95,6 +103,14 @@ _SIGS = {
     "fsimg_coarse_solve": (_I, [_P, _P, _P, _P]),
     "fsimg_vcycle": (_I, [_P, _I, _P, _P, _P]),
     "fsimg_patch_inverse": (_I, [_P, _I, _I64, _P, ctypes.POINTER(_I64), _P]),
+    "fsimg_server_create": (_I, [_P, ctypes.POINTER(fsimg_opts), _I, ctypes.POINTER(_P)]),
+    "fsimg_server_destroy": (None, [_P]),
+    "fsimg_server_clock": (_D, [_P]),
+    "fsimg_server_submit": (_I, [_P, ctypes.POINTER(fsimg_request), ctypes.POINTER(_I64)]),
+    "fsimg_server_step": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
+    "fsimg_server_poll": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(_I)]),
+    "fsimg_server_result": (_I, [_P, _I64, _P, _P]),
+    "fsimg_server_release": (_I, [_P, _I64]),
     "fsimg_last_error": (ctypes.c_char_p, []),
 }
 EXPORTED = tuple(_SIGS)
@@ -157,6 +173,7 @@ class LevelDescs:
 
     def __init__(self, levels):
         self._keep = []
+        self.levels = levels
         n = len(levels)
         self.arr = (fsimg_level_desc * n)()
         for i, lv in enumerate(levels):
@@ -302,3 +319,72 @@ def fsimg_patch_inverse(h, level: int, patch: int, stream=None):
     _check(load().fsimg_patch_inverse(h, level, patch, out.ctypes.data, ctypes.byref(elem),
                                       _stream(stream)))
     return out, elem.value
+
+
+# ------------------------------------------------------------------ serving
+class RequestData:
+    """Host data of one simulation request: momentum / ALE level descriptors,
+    right-hand sides, interface/solid node mask.  The arrays must stay alive
+    until the request is admitted; one RequestData may back many requests."""
+
+    def __init__(self, mom_levels, ale_levels, b_mom, b_ale, node_solid, k, theta):
+        self.mom = LevelDescs(mom_levels)
+        self.ale = LevelDescs(ale_levels)
+        self.b_mom = np.ascontiguousarray(b_mom, dtype=np.float64)
+        self.b_ale = np.ascontiguousarray(b_ale, dtype=np.float64)
+        self.node_solid = np.ascontiguousarray(node_solid, dtype=np.uint8)
+        self.k, self.theta = float(k), float(theta)
+        self.nlev = self.mom.n
+
+
+def fsimg_server_create(ctx, opts, max_active: int = 0):
+    out = ctypes.c_void_p()
+    _check(load().fsimg_server_create(ctx, ctypes.byref(opts), max_active, ctypes.byref(out)))
+    return out.value
+
+
+def fsimg_server_destroy(srv):
+    load().fsimg_server_destroy(srv)
+
+
+def fsimg_server_clock(srv) -> float:
+    return load().fsimg_server_clock(srv)
+
+
+def fsimg_server_submit(srv, data: RequestData, newton_steps, arrival: float) -> int:
+    ns = np.ascontiguousarray(newton_steps, dtype=np.int32)
+    req = fsimg_request(nlev=data.nlev, mom=data.mom.arr, ale=data.ale.arr,
+                        b_mom=data.b_mom.ctypes.data, b_ale=data.b_ale.ctypes.data,
+                        node_solid=data.node_solid.ctypes.data, time_steps=len(ns),
+                        newton_steps=ns.ctypes.data, k=data.k, theta=data.theta, arrival=arrival)
+    rid = ctypes.c_int64()
+    _check(load().fsimg_server_submit(srv, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def fsimg_server_step(srv, stream=None):
+    a, q = ctypes.c_int(), ctypes.c_int()
+    _check(load().fsimg_server_step(srv, ctypes.byref(a), ctypes.byref(q), _stream(stream)))
+    return a.value, q.value
+
+
+def fsimg_server_poll(srv, max_n: int = 1024):
+    ids = np.zeros(max_n, dtype=np.int64)
+    adm = np.zeros(max_n)
+    fin = np.zeros(max_n)
+    c = ctypes.c_int()
+    _check(load().fsimg_server_poll(srv, ids.ctypes.data, adm.ctypes.data, fin.ctypes.data, max_n,
+                                    ctypes.byref(c)))
+    n = c.value
+    return ids[:n], adm[:n], fin[:n]
+
+
+def fsimg_server_result(srv, rid: int, n_mom: int, n_ale: int):
+    xm = np.zeros(n_mom)
+    xa = np.zeros(n_ale)
+    _check(load().fsimg_server_result(srv, rid, xm.ctypes.data, xa.ctypes.data))
+    return xm, xa
+
+
+def fsimg_server_release(srv, rid: int):
+    _check(load().fsimg_server_release(srv, rid))

@@ -12,3 +12,12 @@ def level_dicts(problem, system: str, with_class: bool = True):
                         colind=m.colind, vals=m.vals, dirichlet=m.dirichlet,
                         cell_class=lev.cell_solid if with_class else None))
     return out
+
+
+def request_data(problem):
+    """fsimg.RequestData (momentum + ALE) of an fsigen.Problem."""
+    from .fsimg import RequestData
+    fine = problem.levels[0]
+    return RequestData(level_dicts(problem, "mom"), level_dicts(problem, "ale"), problem.rhs["mom"],
+                       problem.rhs["ale"], fine.node_solid, problem.params["k"],
+                       problem.params["theta"])
