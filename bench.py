@@ -43,19 +43,29 @@ def spmv_bytes(nnzb, nrows, b, s):
     return nnzb * (b * b * s + 4) + 4 * (nrows + 1) + 3 * nrows * b * s + nrows * b
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch recorded from rocprofv3 counters, or None when the
-    kernel source changed since the counters were taken."""
+KERNEL_SOURCES = ("batch_kernels.hip", "device_ops.h")
+
+
+def kernel_source_hash():
+    """sha256[:16] over the sources that define the batched solve kernels."""
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1904_02401_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(role, workload, prec):
+    """HBM bytes per launch recorded from rocprofv3 counters, or None when the
+    kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_1904_02401_amd", "csrc", "kernels_sparse.hip")
-    if not os.path.exists(path) or not os.path.exists(src):
+    if not os.path.exists(path):
         return None
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    cur = kernel_source_hash()
     for line in open(path):
         f = line.split()
-        if len(f) == 4 and not line.startswith("#") and f[0] == kernel and f[1] == workload:
-            return float(f[2]) if f[3] == cur else None
+        if len(f) == 5 and not line.startswith("#") and f[:3] == [role, workload, prec]:
+            return float(f[3]) if f[4] == cur else None
     return None
 
 
@@ -189,6 +199,7 @@ def cpu_baseline(P, iters_gpu, budget_s=20.0):
     cells = [lv.cells for lv in P.levels]
     H = Hierarchy(P.system("mom"), cells, omega=0.8, weighting="mult")
     t_setup = time.perf_counter() - t0
+    log(f"oracle hierarchy built in {t_setup:.0f} s")
     lev = H.levels[0]
     b = P.rhs["mom"]
     # one iteration first to size the sample
@@ -408,7 +419,7 @@ def main():
     ap.add_argument("--mu", type=float, default=None, help="solid shear modulus override")
     ap.add_argument("--lam", type=float, default=None, help="solid Lame lambda override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
@@ -460,10 +471,10 @@ def main():
     n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
     n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
     runs = {}
-    precs = [("fp64", fsimg.FSIMG_FP64), ("mixed", fsimg.FSIMG_MIXED)]
+    precs = [("mixed", fsimg.FSIMG_MIXED), ("fp64", fsimg.FSIMG_FP64)]
     if args.only:
         precs = [p for p in precs if p[0] == args.only]
-    elif args.no_mixed:
+    elif args.no_fp64:
         precs = precs[:1]
     for tag, prec in precs:
         r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass)
@@ -483,27 +494,34 @@ def main():
             f"(rel res {r['rel_res_host']:.2e} host), ALE {st_a['iters']} it, "
             f"mass {st_s['iters'] if st_s else '-'} it; setup {r['t_setup']:.2f} s, "
             f"factor {r['t_factor']:.2f} s")
+    def kernel_rates(R, tag):
+        s = 8 if tag == "fp64" else 4
+        info = R["info_m"]
+        prof = R["prof"]
+        v_ms = sum(p["vanka_ms"] for p in prof)
+        v_n = sum(p["vanka_launches"] for p in prof)
+        s_ms = sum(p["spmv_ms"] for p in prof)
+        s_n = sum(p["spmv_launches"] for p in prof)
+        nl = 27 if P.dim == 3 else 9
+        vb = vanka_bytes(info["npatch"], info["np"], nl, s)
+        sb = spmv_bytes(info["nnzb"], info["nrows"], lev.systems["mom"].b, s)
+        v_avg = v_ms / max(v_n, 1) * 1e-3
+        s_avg = s_ms / max(s_n, 1) * 1e-3
+        tname = "double" if tag == "fp64" else "float"
+        bm = lev.systems["mom"].b
+        return {"vanka_patch": {"kernel": f"kb_vanka_patch<{tname}>",
+                                "GB/s": vb / v_avg / 1e9 if v_n else 0.0, "avg_ms": v_avg * 1e3,
+                                "launches": v_n, "bytes_per_launch": vb, "total_ms": v_ms},
+                "spmv_residual": {"kernel": f"kb_spmv<{bm}, {tname}, 0>",
+                                  "GB/s": sb / s_avg / 1e9 if s_n else 0.0, "avg_ms": s_avg * 1e3,
+                                  "launches": s_n, "bytes_per_launch": sb, "total_ms": s_ms}}
+
     main_tag = precs[0][0]
     R = runs[main_tag]
-    s = 8 if main_tag == "fp64" else 4
-    info = R["info_m"]
-    prof = R["prof"]
-    v_ms = sum(p["vanka_ms"] for p in prof)
-    v_n = sum(p["vanka_launches"] for p in prof)
-    s_ms = sum(p["spmv_ms"] for p in prof)
-    s_n = sum(p["spmv_launches"] for p in prof)
-    nl = 27 if P.dim == 3 else 9
-    vb = vanka_bytes(info["npatch"], info["np"], nl, s)
-    sb = spmv_bytes(info["nnzb"], info["nrows"], lev.systems["mom"].b, s)
-    v_avg = v_ms / max(v_n, 1) * 1e-3
-    s_avg = s_ms / max(s_n, 1) * 1e-3
-    v_gbs = vb / v_avg / 1e9 if v_n else 0.0
-    s_gbs = sb / s_avg / 1e9 if s_n else 0.0
-    tname = "double" if main_tag == "fp64" else "float"
-    bm = lev.systems["mom"].b
-    dominant = ((f"k_vanka_patch<{tname}>", v_gbs, vb, v_avg, v_n) if v_ms >= s_ms
-                else (f"k_bsr_spmv<{bm},{tname},true>", s_gbs, sb, s_avg, s_n))
-    traffic = measured_traffic(dominant[0], f"{args.config}-momentum-level0")
+    kr = kernel_rates(R, main_tag)
+    role = max(kr, key=lambda k: kr[k]["total_ms"])
+    dom = kr[role]
+    traffic = measured_traffic(role, f"{args.config}-momentum-level0", main_tag)
     value = (n_mom + n_ale) / R["t_step"]
     out = {
         "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
@@ -527,26 +545,24 @@ def main():
                    "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
                    "precision": main_tag},
-        "roofline": {"bound": "hbm", "kernel": dominant[0], "achieved": dominant[1],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dominant[1] / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": dominant[2],
-                     "avg_launch_ms": dominant[3] * 1e3, "launches": dominant[4]},
-        "kernels": {"vanka_patch": {"GB/s": v_gbs, "avg_ms": v_avg * 1e3, "launches": v_n,
-                                    "bytes_per_launch": vb},
-                    "bsr_spmv_residual": {"GB/s": s_gbs, "avg_ms": s_avg * 1e3, "launches": s_n,
-                                          "bytes_per_launch": sb}},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GB/s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
+                     "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"]},
+        "kernels": kr,
         "solve": {"momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
                   "rel_res_momentum_fp64_host": R["rel_res_host"],
                   "setup_s": R["t_setup"], "factor_s": R["t_factor"]},
     }
-    if "mixed" in runs and main_tag != "mixed":
-        M = runs["mixed"]
-        out["mixed"] = {"value": (n_mom + n_ale) / M["t_step"], "ms_per_step": M["t_step"] * 1e3,
-                        "momentum_iters": M["stats"][0]["iters"], "ale_iters": M["stats"][2]["iters"],
-                        "rel_res_momentum_fp64_host": M["rel_res_host"],
-                        "rel_err_vs_fp64": _split_err(M["x_mom"], R["x_mom"], P.dim + 1),
-                        "speedup_vs_fp64": R["t_step"] / M["t_step"]}
+    if "fp64" in runs and main_tag != "fp64":
+        F = runs["fp64"]
+        out["fp64"] = {"value": (n_mom + n_ale) / F["t_step"], "ms_per_step": F["t_step"] * 1e3,
+                       "momentum_iters": F["stats"][0]["iters"], "ale_iters": F["stats"][2]["iters"],
+                       "rel_res_momentum_fp64_host": F["rel_res_host"],
+                       "kernels": kernel_rates(F, "fp64")}
+        out["mixed_speedup_vs_fp64"] = F["t_step"] / R["t_step"]
+        out["mixed_rel_err_vs_fp64"] = _split_err(R["x_mom"], F["x_mom"], P.dim + 1)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(P, R["stats"][0]["iters"])
