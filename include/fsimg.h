@@ -105,6 +105,9 @@ typedef struct {
   int vanka_schedule;  /* fsimg_vanka_schedule */
   int vanka_weighting; /* fsimg_weighting */
   int profile;         /* 1: time the finest-level smoother kernels with events */
+  int graphs;          /* 1: replay each FGMRES iteration (V-cycle, A z, Gram-Schmidt) as a
+                          HIP graph captured once per batch composition; 0: launch eagerly.
+                          Results are identical either way; profiling runs launch eagerly */
 } fsimg_opts;
 
 typedef struct {
@@ -229,6 +232,33 @@ fsimg_status fsimg_vcycle(fsimg_hier *h, int precision, const void *r_dev, void 
    dense row-major n_p x n_p FP64 matrix; *elem receives the patch's cell. */
 fsimg_status fsimg_patch_inverse(fsimg_hier *h, int level, int64_t patch, double *out_host,
                                  int64_t *elem, void *stream);
+
+/* ---- launch-shape tuning (no effect on any result bit) ----
+   Two launch shapes of the bandwidth-bound kernels are free parameters
+   that leave every result unchanged: the block rows each wavefront of the
+   SpMV handles (1, 2 or 4) and the Vanka patches per workgroup (ppw, with
+   ppw * n_p <= 1024).  A context keeps a table keyed by (kind, block size b
+   for the SpMV or patch size n_p for Vanka, word bytes 4 / 8, size bucket
+   floor(log2(rows or patches))); keys without an entry use built-in
+   defaults.  Batch compositions cached before a change are dropped. */
+typedef enum { FSIMG_TUNE_SPMV_ROWS = 0, FSIMG_TUNE_VANKA_PPW = 1 } fsimg_tune_kind;
+
+/* Measure every candidate shape on the levels of h (its precision, plus the
+   FP64 level-0 SpMV of the outer iteration) for keys the table lacks
+   (force = 1: for all of them), and keep the fastest.  Uses h's work
+   vectors: do not overlap with a solve of h.  Synchronises the stream. */
+fsimg_status fsimg_hier_tune(fsimg_hier *h, int force, void *stream);
+/* set / read one entry (read gives the value in use: the entry or the
+   default).  ERR_ARG for an unknown kind or a value outside its range. */
+fsimg_status fsimg_tune_set(fsimg_ctx *ctx, int kind, int key, int word, int64_t size, int value);
+fsimg_status fsimg_tune_get(const fsimg_ctx *ctx, int kind, int key, int word, int64_t size,
+                            int *value);
+/* JSON file of the table: {"arch": "gfx950", "entries": [{"kind": k,
+   "key": b_or_np, "word": w, "bucket": e, "value": v}, ...]}.  Loading a
+   file written for another GPU architecture fails with ERR_ARG and leaves
+   the table unchanged; loaded entries replace entries with the same key. */
+fsimg_status fsimg_tune_save(const fsimg_ctx *ctx, const char *path);
+fsimg_status fsimg_tune_load(fsimg_ctx *ctx, const char *path);
 
 /* ---- serving: many simulations sharing one GPU ----
    A request is one FSI simulation: time_steps time steps, newton_steps[t]

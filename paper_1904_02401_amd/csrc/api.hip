@@ -437,6 +437,7 @@ void fsimg_default_opts(fsimg_opts *o) {
   o->vanka_schedule = FSIMG_VANKA_GATHER;
   o->vanka_weighting = FSIMG_WEIGHT_MULT;
   o->profile = 0;
+  o->graphs = 1;
 }
 
 fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **out) {
@@ -455,7 +456,7 @@ fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **o
 
 void fsimg_ctx_destroy(fsimg_ctx *ctx) {
   if (!ctx) return;
-  for (BatchPlan *p : ctx->plans) destroy_plan(p);
+  drop_plans(ctx);
   delete ctx;
 }
 
@@ -471,6 +472,7 @@ static fsimg_status validate_opts(const fsimg_opts *o) {
   if (o->precision != FSIMG_FP64 && o->precision != FSIMG_MIXED) return fail(FSIMG_ERR_ARG, "bad precision");
   if (o->vanka_schedule < 0 || o->vanka_schedule > 2) return fail(FSIMG_ERR_ARG, "bad schedule");
   if (o->vanka_weighting < 0 || o->vanka_weighting > 1) return fail(FSIMG_ERR_ARG, "bad weighting");
+  if (o->graphs < 0 || o->graphs > 1) return fail(FSIMG_ERR_ARG, "graphs must be 0 or 1");
   return FSIMG_OK;
 }
 
@@ -560,6 +562,7 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
   for (int l = 0; l < nlev; ++l) {
     const fsimg_level_desc &D = levels[l];
     DevLevel &L = h->lev[l];
+    L.tune = &ctx->tune;
     L.dim = D.dim;
     L.b = D.block;
     L.nl = D.dim == 2 ? 9 : 27;

@@ -24,6 +24,8 @@ struct BatchPlan {
   std::vector<uint64_t> key;
   int n = 0, Lmax = 0, b = 0, dim = 0, np = 0, nl = 0, npc = 0;
   bool mixed = false;
+  std::vector<int> rpw, ppw;  // per level: SpMV rows per wave, Vanka patches per workgroup
+  int rpw0 = 1;               // FP64 level-0 SpMV (A z, true residual)
   void *dbuf = nullptr;
   size_t dbytes = 0;
   size_t kry_off = 0;
@@ -37,12 +39,20 @@ struct BatchPlan {
   double *hs_host = nullptr;
   int *int_host = nullptr;  // active | kcnt | flags staging, 3n ints
   EventTimer tv, ts;
+  // FGMRES iteration j (copy-in, V-cycle, copy-out, A z_j, CGS2, norm, scale,
+  // Hessenberg column to the host) captured once per j and replayed
+  hipStream_t cap = nullptr;
+  std::vector<hipGraphExec_t> iter_graph;
+  fsimg_opts graph_opts{};
 };
 
 namespace fsimg {
 
 void destroy_plan(BatchPlan *p) {
   if (!p) return;
+  for (hipGraphExec_t g : p->iter_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
   if (p->dbuf) {
     (void)hipFree(p->dbuf);
     if (p->ctx) {
@@ -62,6 +72,11 @@ size_t plan_bytes_bound(int nlev) {
   const size_t nset = 7 * (size_t)nlev + 4, ntab = 6 + 2 * nset;
   return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 3 * sizeof(int) + kHS * sizeof(double) +
          nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 256;
+}
+
+void drop_plans(fsimg_ctx *ctx) {
+  for (BatchPlan *p : ctx->plans) destroy_plan(p);
+  ctx->plans.clear();
 }
 
 bool plan_covers(const BatchPlan *p, uint64_t uid) {
@@ -146,8 +161,26 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
     P->Lmax = std::max(P->Lmax, (int)hs[i]->lev.size());
   }
   const int Lmax = P->Lmax;
-  int ppw = 1, threads = 64;
-  vanka_shape(P->np, &ppw, &threads);
+  // launch shapes per level, from the largest instance at that level
+  const int word = P->mixed ? 4 : 8;
+  P->rpw.assign(Lmax, 1);
+  P->ppw.assign(Lmax, 1);
+  for (int l = 0; l < Lmax; ++l) {
+    int64_t rows = 0, patches = 0;
+    for (int i = 0; i < n; ++i)
+      if (l < (int)hs[i]->lev.size()) {
+        rows = std::max(rows, hs[i]->lev[l].nrows);
+        patches = std::max(patches, hs[i]->lev[l].npatch);
+      }
+    const TuneTable *tt = hs[0]->lev[0].tune;
+    P->rpw[l] = spmv_rows_per_wave(tt, P->b, word, rows);
+    P->ppw[l] = vanka_patches_per_wg(tt, P->np, word, patches);
+  }
+  {
+    int64_t rows = 0;
+    for (int i = 0; i < n; ++i) rows = std::max(rows, hs[i]->lev[0].nrows);
+    P->rpw0 = spmv_rows_per_wave(hs[0]->lev[0].tune, P->b, 8, rows);
+  }
   Blob blob;
   std::vector<DLev> dl((size_t)Lmax * n);
   for (int l = 0; l < Lmax; ++l)
@@ -167,8 +200,8 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
       const int Li = (int)hs[i]->lev.size();
       if (l < Li - 1) {
         const DevLevel &L = hs[i]->lev[l];
-        sp.push(i, cdiv(L.nrows, 4));
-        pa.push(i, cdiv(L.npatch, ppw));
+        sp.push(i, cdiv(L.nrows, 4 * P->rpw[l]));
+        pa.push(i, cdiv(L.npatch, P->ppw[l]));
         ga.push(i, cdiv(L.n, 256));
         re.push(i, cdiv(hs[i]->lev[l + 1].nrows, 256));
         pr.push(i, cdiv(L.nrows, 256));
@@ -189,7 +222,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   WsHost row0, vec0, kr, ins;
   for (int i = 0; i < n; ++i) {
     const DevLevel &L = hs[i]->lev[0];
-    row0.push(i, cdiv(L.nrows, 4));
+    row0.push(i, cdiv(L.nrows, 4 * P->rpw0));
     vec0.push(i, cdiv(L.n, 256));
     kr.push(i, krylov_blocks(L.n));
     ins.push(i, 1);
@@ -259,18 +292,18 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
           hipEvent_t a = p0 ? P.ts.next() : nullptr;
           hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
           if (a) (void)hipEventRecord(a, s);
-          launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+          launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
           if (b2) (void)hipEventRecord(b2, s);
         }
         hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
         hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
-        launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, omega, k == 0, k == 0, L, act, P.ws_patch[l],
+        launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, k == 0, k == 0, L, act, P.ws_patch[l],
                           P.ws_gather[l], s, v0, v1);
       }
       hipEvent_t a = p0 ? P.ts.next() : nullptr;
       hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
       if (a) (void)hipEventRecord(a, s);
-      launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
       if (b2) (void)hipEventRecord(b2, s);
       launch_b_restrict<T>(P.b, P.dim, L, L + n, act, P.ws_restrict[l], s);
     }
@@ -285,14 +318,78 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
       hipEvent_t a = p0 ? P.ts.next() : nullptr;
       hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
       if (a) (void)hipEventRecord(a, s);
-      launch_b_spmv<T>(P.b, BS_VCYCLE, L, P.dkry, act, P.ws_spmv[l], 0, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
       if (b2) (void)hipEventRecord(b2, s);
       hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
       hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
-      launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, omega, false, false, L, act, P.ws_patch[l],
+      launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, false, false, L, act, P.ws_patch[l],
                         P.ws_gather[l], s, v0, v1);
     }
   }
+}
+
+// the launches of FGMRES iteration j for every active instance: z_j = M^-1 v_j
+// (V-cycle in the plan's precision), w = A z_j, two Gram-Schmidt passes, the
+// norm of w and v_{j+1} = w / ||w|| (Hessenberg column left in P.hs)
+void issue_iteration(BatchPlan &P, const fsimg_opts &o, int j, hipStream_t s, bool prof) {
+  if (P.mixed) {
+    launch_b_copy_in<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+    vcycle_batch<float>(P, o, s, prof);
+    launch_b_copy_out<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+  } else {
+    launch_b_copy_in<double>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+    vcycle_batch<double>(P, o, s, prof);
+    launch_b_copy_out<double>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+  }
+  launch_b_spmv<double>(P.b, BS_AZ, P.rpw0, P.dlev, P.dkry, P.active, P.ws_row0, j, s);
+  // classical Gram-Schmidt, two passes
+  launch_b_multidot(P.dkry, P.active, P.ws_kry, j + 1, false, s);
+  launch_b_reduce(P.dkry, P.active, P.ws_inst, j + 1, P.hs, kOffH1, s);
+  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, false, P.hs, kOffH1, s);
+  launch_b_reduce(P.dkry, P.active, P.ws_inst, j + 1, P.hs, kOffH2, s);
+  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, true, P.hs, kOffH2, s);
+  launch_b_reduce(P.dkry, P.active, P.ws_inst, 1, P.hs, kOffSS, s);
+  launch_b_add_h(P.active, P.ws_inst, j + 1, P.hs, s);
+  launch_b_scale(P.dkry, P.active, P.ws_vec0, P.hs, j + 1, s);
+}
+
+bool same_solver_opts(const fsimg_opts &a, const fsimg_opts &b) {
+  return a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post &&
+         a.precision == b.precision && a.restart == b.restart;
+}
+
+// the executable graph of iteration j, captured on the plan's own stream the
+// first time it is needed (kernel and copy nodes only; the instances' active
+// flags are read from device memory, so one graph serves every iteration j of
+// every later solve of this batch composition)
+hipError_t iteration_graph(BatchPlan &P, const fsimg_opts &o, int j,
+                           hipError_t (*fetch_async)(BatchPlan &, hipStream_t)) {
+  if (!P.iter_graph.empty() && !same_solver_opts(P.graph_opts, o)) {
+    for (hipGraphExec_t g : P.iter_graph)
+      if (g) (void)hipGraphExecDestroy(g);
+    P.iter_graph.clear();
+  }
+  if ((int)P.iter_graph.size() < o.restart) P.iter_graph.resize(o.restart, nullptr);
+  P.graph_opts = o;
+  if (P.iter_graph[j]) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (!P.cap) e = hipStreamCreateWithFlags(&P.cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  issue_iteration(P, o, j, P.cap, false);
+  hipError_t e2 = fetch_async(P, P.cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(P.cap, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&P.iter_graph[j], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  return e;
+}
+
+hipError_t fetch_async(BatchPlan &P, hipStream_t s) {
+  return hipMemcpyAsync(P.hs_host, P.hs, (size_t)P.n * kHS * sizeof(double), hipMemcpyDeviceToHost,
+                        s);
 }
 
 struct InstState {
@@ -343,6 +440,7 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
   }
   ctx->plans.insert(ctx->plans.begin(), P);  // most recent first
   const bool prof = o.profile != 0;
+  const bool use_graph = o.graphs != 0 && !prof;
   P->tv.begin_solve();
   P->ts.begin_solve();
   const int m = o.restart;
@@ -383,7 +481,7 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
   }
   FSIMG_BHIP(upload_act());
   FSIMG_BHIP(hipMemcpyAsync(P->flags, fl_h, n * sizeof(int), hipMemcpyHostToDevice, s));
-  launch_b_spmv<double>(P->b, BS_RESID, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
+  launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
   launch_b_nonfinite(P->dkry, P->active, P->ws_vec0, P->flags, s);
   launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
   launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
@@ -417,26 +515,14 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
       bool live = false;
       for (int i = 0; i < n; ++i) live |= act_h[i] != 0;
       if (!live) break;
-      if (P->mixed) {
-        launch_b_copy_in<float>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
-        vcycle_batch<float>(*P, o, s, prof);
-        launch_b_copy_out<float>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+      if (use_graph) {
+        FSIMG_BHIP(iteration_graph(*P, o, j, &fetch_async));
+        FSIMG_BHIP(hipGraphLaunch(P->iter_graph[j], s));
+        FSIMG_BHIP(hipStreamSynchronize(s));
       } else {
-        launch_b_copy_in<double>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
-        vcycle_batch<double>(*P, o, s, prof);
-        launch_b_copy_out<double>(P->dlev, P->dkry, P->active, P->ws_vec0, j, s);
+        issue_iteration(*P, o, j, s, prof);
+        FSIMG_BHIP(fetch(false));
       }
-      launch_b_spmv<double>(P->b, BS_AZ, P->dlev, P->dkry, P->active, P->ws_row0, j, s);
-      // classical Gram-Schmidt, two passes
-      launch_b_multidot(P->dkry, P->active, P->ws_kry, j + 1, false, s);
-      launch_b_reduce(P->dkry, P->active, P->ws_inst, j + 1, P->hs, kOffH1, s);
-      launch_b_axpy_red(P->dkry, P->active, P->ws_kry, j + 1, false, P->hs, kOffH1, s);
-      launch_b_reduce(P->dkry, P->active, P->ws_inst, j + 1, P->hs, kOffH2, s);
-      launch_b_axpy_red(P->dkry, P->active, P->ws_kry, j + 1, true, P->hs, kOffH2, s);
-      launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
-      launch_b_add_h(P->active, P->ws_inst, j + 1, P->hs, s);
-      launch_b_scale(P->dkry, P->active, P->ws_vec0, P->hs, j + 1, s);
-      FSIMG_BHIP(fetch(false));
       bool changed = false;
       for (int i = 0; i < n; ++i) {
         if (!act_h[i]) continue;
@@ -489,7 +575,7 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
     FSIMG_BHIP(hipMemcpyAsync(P->kcnt, k_h, n * sizeof(int), hipMemcpyHostToDevice, s));
     FSIMG_BHIP(upload_act());
     launch_b_combine(P->dkry, P->active, P->ws_vec0, P->hs, P->kcnt, kmax, s);
-    launch_b_spmv<double>(P->b, BS_RESID, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
+    launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
     launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
     launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
     FSIMG_BHIP(fetch(false));

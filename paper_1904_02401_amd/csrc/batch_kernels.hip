@@ -4,6 +4,8 @@
 // per-instance computation (rows, patches, nodes, reduction blocking) depends
 // on that instance alone, so an instance's result does not depend on which
 // other instances share the launch.
+#include <type_traits>
+
 #include "device_ops.h"
 
 namespace fsimg {
@@ -45,8 +47,8 @@ template <> struct LV<float> {
 // SRC BS_VCYCLE: d = r - A x on the level's work vectors (T);
 //     BS_AZ:     w = A z_j, 0 at identity rows (FP64, level 0);
 //     BS_RESID:  w = b - A x with the caller's b, x (FP64, level 0).
-template <int B, typename T, int SRC>
-__global__ __launch_bounds__(256) void kb_spmv(const DLev *__restrict__ lev,
+template <int B, typename T, int SRC, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void kb_spmv(const DLev *__restrict__ lev,
                                                const DKry *__restrict__ kry,
                                                const int *__restrict__ active, WorkSet ws, int j) {
   const int s = seg_of(ws, blockIdx.x);
@@ -54,18 +56,19 @@ __global__ __launch_bounds__(256) void kb_spmv(const DLev *__restrict__ lev,
   if (!active[i]) return;
   const DLev &L = lev[i];
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row = (blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave;
-  if (row >= L.nrows) return;
+  const int64_t row0 = ((blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave) * R;
+  if (row0 >= L.nrows) return;
   if constexpr (SRC == BS_VCYCLE) {
-    dev::spmv_row<B, T, 1>(row, lane, L.rowptr, L.colind, LV<T>::vals(L), LV<T>::x(L), LV<T>::r(L),
-                           L.mask, LV<T>::d(L));
+    dev::spmv_rows<B, T, 1, R>(row0, L.nrows, lane, L.rowptr, L.colind, LV<T>::vals(L),
+                               LV<T>::x(L), LV<T>::r(L), L.mask, LV<T>::d(L));
   } else if constexpr (SRC == BS_AZ) {
     const DKry &K = kry[i];
-    dev::spmv_row<B, double, 2>(row, lane, L.rowptr, L.colind, L.v64, K.Z + (int64_t)j * K.n,
-                                nullptr, L.mask, K.w);
+    dev::spmv_rows<B, double, 2, R>(row0, L.nrows, lane, L.rowptr, L.colind, L.v64,
+                                    K.Z + (int64_t)j * K.n, nullptr, L.mask, K.w);
   } else {
     const DKry &K = kry[i];
-    dev::spmv_row<B, double, 1>(row, lane, L.rowptr, L.colind, L.v64, K.x, K.b, L.mask, K.w);
+    dev::spmv_rows<B, double, 1, R>(row0, L.nrows, lane, L.rowptr, L.colind, L.v64, K.x, K.b,
+                                    L.mask, K.w);
   }
 }
 
@@ -371,34 +374,37 @@ int krylov_blocks(int64_t n) {
 }
 
 template <typename T>
-void launch_b_spmv(int b, int src, const DLev *lev, const DKry *kry, const int *active,
+void launch_b_spmv(int b, int src, int rpw, const DLev *lev, const DKry *kry, const int *active,
                    const WorkSet &ws, int j, hipStream_t s) {
   if (ws.nblocks == 0) return;
-#define FSIMG_BS(BV, SV, TT)                                                                     \
-  if (b == BV && src == SV) {                                                                    \
-    hipLaunchKernelGGL((kb_spmv<BV, TT, SV>), grid_of(ws), dim3(256), 0, s, lev, kry, active, ws, \
-                       j);                                                                       \
+#define FSIMG_BS(BV, SV, TT, RV)                                                                 \
+  if (b == BV && src == SV && rpw == RV) {                                                       \
+    hipLaunchKernelGGL((kb_spmv<BV, TT, SV, RV>), grid_of(ws), dim3(256), 0, s, lev, kry, active, \
+                       ws, j);                                                                   \
     return;                                                                                      \
   }
-  FSIMG_BS(1, BS_VCYCLE, T) FSIMG_BS(2, BS_VCYCLE, T) FSIMG_BS(3, BS_VCYCLE, T)
-  FSIMG_BS(4, BS_VCYCLE, T)
-  FSIMG_BS(1, BS_AZ, double) FSIMG_BS(2, BS_AZ, double) FSIMG_BS(3, BS_AZ, double)
-  FSIMG_BS(4, BS_AZ, double)
-  FSIMG_BS(1, BS_RESID, double) FSIMG_BS(2, BS_RESID, double) FSIMG_BS(3, BS_RESID, double)
-  FSIMG_BS(4, BS_RESID, double)
+#define FSIMG_BS_R(BV, SV, TT) FSIMG_BS(BV, SV, TT, 1) FSIMG_BS(BV, SV, TT, 2) FSIMG_BS(BV, SV, TT, 4)
+  FSIMG_BS_R(1, BS_VCYCLE, T) FSIMG_BS_R(2, BS_VCYCLE, T) FSIMG_BS_R(3, BS_VCYCLE, T)
+  FSIMG_BS_R(4, BS_VCYCLE, T)
+  if constexpr (std::is_same<T, double>::value) {
+    FSIMG_BS_R(1, BS_AZ, double) FSIMG_BS_R(2, BS_AZ, double) FSIMG_BS_R(3, BS_AZ, double)
+    FSIMG_BS_R(4, BS_AZ, double)
+    FSIMG_BS_R(1, BS_RESID, double) FSIMG_BS_R(2, BS_RESID, double)
+    FSIMG_BS_R(3, BS_RESID, double) FSIMG_BS_R(4, BS_RESID, double)
+  }
+#undef FSIMG_BS_R
 #undef FSIMG_BS
 }
 
 template <typename T>
-void launch_b_vanka(int np, int b, int nl, int npc, T omega, bool first, bool assign,
+void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first, bool assign,
                     const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  int ppw = 1, threads = 64;
-  vanka_shape(np, &ppw, &threads);
   if (e0) (void)hipEventRecord(e0, s);
   if (wp.nblocks > 0)
-    hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(threads), sizeof(T) * (size_t)ppw * npc,
-                       s, lev, active, wp, np, npc, b, nl, ppw, first ? 1 : 0);
+    hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(vanka_threads(np, ppw)),
+                       sizeof(T) * (size_t)ppw * npc, s, lev, active, wp, np, npc, b, nl, ppw,
+                       first ? 1 : 0);
   if (e1) (void)hipEventRecord(e1, s);
   if (wg.nblocks > 0)
     hipLaunchKernelGGL((kb_vanka_gather<T>), grid_of(wg), dim3(256), 0, s, lev, active, wg, b, omega,
@@ -530,9 +536,10 @@ void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, i
 }
 
 #define FSIMG_BINST(T)                                                                           \
-  template void launch_b_spmv<T>(int, int, const DLev *, const DKry *, const int *,              \
+  template void launch_b_spmv<T>(int, int, int, const DLev *, const DKry *, const int *,         \
                                  const WorkSet &, int, hipStream_t);                             \
-  template void launch_b_vanka<T>(int, int, int, int, T, bool, bool, const DLev *, const int *,  \
+  template void launch_b_vanka<T>(int, int, int, int, int, T, bool, bool, const DLev *,          \
+                                  const int *,                                                   \
                                   const WorkSet &, const WorkSet &, hipStream_t, hipEvent_t,     \
                                   hipEvent_t);                                                   \
   template void launch_b_fill_x<T>(const DLev *, const int *, const WorkSet &, hipStream_t);     \

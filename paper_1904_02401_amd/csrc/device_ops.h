@@ -10,136 +10,231 @@ namespace dev {
 
 constexpr int kWave = 64;
 
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using type = double2; static constexpr int G = 2; };
-template <> struct Vec16<float> { using type = float4; static constexpr int G = 4; };
+// Pointers reach the batched kernels inside descriptor structs, where the
+// compiler cannot see that they address global memory and would emit flat
+// loads (which also count against the LDS counter, so every cross-lane
+// shuffle would wait for them).  The bodies below therefore access memory
+// through global-address-space views of their pointer arguments.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p) {
+  return (gptr<T>)p;
+}
 
-__device__ __forceinline__ double vget(const double2 &v, int q) { return q == 0 ? v.x : v.y; }
-__device__ __forceinline__ float vget(const float4 &v, int q) {
+// 16-byte vectors as clang native vector types (loadable through
+// global-address-space pointers)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = dvec2; static constexpr int G = 2; };
+template <> struct Vec16<float> { using type = fvec4; static constexpr int G = 4; };
+
+__device__ __forceinline__ double vget(const dvec2 &v, int q) { return q == 0 ? v.x : v.y; }
+__device__ __forceinline__ float vget(const fvec4 &v, int q) {
   return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
 }
 
 template <typename T>
 __device__ __forceinline__ T dot16(const typename Vec16<T>::type &a, const typename Vec16<T>::type &b);
 template <>
-__device__ __forceinline__ double dot16<double>(const double2 &a, const double2 &b) {
+__device__ __forceinline__ double dot16<double>(const dvec2 &a, const dvec2 &b) {
   return a.x * b.x + a.y * b.y;
 }
 template <>
-__device__ __forceinline__ float dot16<float>(const float4 &a, const float4 &b) {
+__device__ __forceinline__ float dot16<float>(const fvec4 &a, const fvec4 &b) {
   return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
 }
 
 // ------------------------------------------------------------ BSR SpMV
-// One wavefront per block row.  The row's column indices (at most 128
-// blocks, the Q2 maximum is 125) are loaded once with one coalesced load and
-// broadcast by cross-lane shuffles, so no global load depends on another
-// inside the row: every value / x load of the row is issued in one fully
-// unrolled, predicated sweep.  Rows longer than 128 blocks take a plain loop.
+// One wavefront per R consecutive block rows.  The R + 1 row pointers come
+// in with one load; each row's column indices (at most 128 blocks, the Q2
+// maximum is 125) with one or two coalesced loads, broadcast by cross-lane
+// shuffles.  Then every value / x load of all R rows is issued in one fully
+// unrolled, predicated sweep, so a wave keeps R rows' bytes in flight after
+// two dependent round trips.  Rows longer than 128 blocks take a plain loop
+// with the same lane mapping and summation order.
 //
 // b = 4: each lane loads 16 bytes of a block (2 doubles / 4 floats) and the
 // matching 16 bytes of x, so a wave covers 8 (FP64) or 16 (FP32) blocks per
-// step with 1 KB coalesced value loads.  Other b: one entry per lane,
-// 64 / b^2 blocks per step.  Partial products are summed across lanes with
-// xor-shuffles; lanes 0..b-1 write the b results of the row.
+// step with 1 KB coalesced value loads.  b = 1, 2, 3: each lane owns one
+// block row (b values and the b entries of x), 64 / b blocks per step.
+// Lane partials are summed across lanes in a fixed tree; lanes 0..b-1 write
+// the b results of the row.  The result of a row does not depend on R.
 //
 // MODE 0: y = A x;  1: y = b - A x, 0 at identity rows;  2: y = A x, 0 at
 // identity rows.
 template <int B, typename T>
-__device__ __forceinline__ T row_reduce(T acc, int lane) {
-  constexpr int BB = B * B;
-  if constexpr ((B & (B - 1)) == 0) {
-    for (int m = 1; m < B; m <<= 1) acc += __shfl_xor(acc, m);
-    for (int m = BB; m < kWave; m <<= 1) acc += __shfl_xor(acc, m);
-    return __shfl(acc, (lane % B) * B);
+struct RowMap {
+  static constexpr bool kVec = (B == 4);
+  static constexpr int LPB = kVec ? 16 / Vec16<T>::G : B;  // lanes per block
+  static constexpr int KB = kWave / LPB;                     // blocks per wave step
+  static constexpr int ACT = KB * LPB;                       // lanes in use
+  static constexpr int MAXT = (128 + KB - 1) / KB;           // steps covering 128 blocks
+};
+
+// lane partial of one block (index jj of the row, column col)
+template <int B, typename T>
+__device__ __forceinline__ T block_partial(gptr<const T> vals, gptr<const T> x, int64_t blk, int col,
+                                           int q) {
+  if constexpr (B == 4) {
+    using V = typename Vec16<T>::type;
+    constexpr int G = Vec16<T>::G;
+    const V a = *reinterpret_cast<gptr<const V>>(vals + blk * 16 + q * G);
+    const V xv = *reinterpret_cast<gptr<const V>>(x + (int64_t)col * 4 + ((q * G) & 3));
+    return dot16<T>(a, xv);
   } else {
-    constexpr int KB = kWave / BB;
-    T s = 0;
+    gptr<const T> v = vals + blk * (B * B) + q * B;
+    gptr<const T> xv = x + (int64_t)col * B;
+    T s = v[0] * xv[0];
 #pragma unroll
-    for (int k0 = 0; k0 < KB; ++k0)
-#pragma unroll
-      for (int c = 0; c < B; ++c) s += __shfl(acc, k0 * BB + (lane % B) * B + c);
+    for (int c = 1; c < B; ++c) s += v[c] * xv[c];
     return s;
   }
 }
 
-template <int B, typename T, int MODE>
-__device__ __forceinline__ void spmv_row(int64_t row, int lane, const int32_t *__restrict__ rowptr,
-                                         const int32_t *__restrict__ colind,
-                                         const T *__restrict__ vals, const T *__restrict__ x,
-                                         const T *__restrict__ b, const uint8_t *__restrict__ mask,
-                                         T *__restrict__ y) {
-  const int64_t rs = rowptr[row];
-  const int nb = (int)(rowptr[row + 1] - rs);
-  T tot;
+// sum the lane partials of a row; lanes 0..B-1 receive the B results
+template <int B, typename T>
+__device__ __forceinline__ T row_total(T acc, int lane) {
   if constexpr (B == 4) {
-    using V = typename Vec16<T>::type;
-    constexpr int G = Vec16<T>::G;   // entries per 16-byte load
-    constexpr int LPB = 16 / G;      // lanes per 4x4 block
-    constexpr int KB = kWave / LPB;  // blocks per wave step
-    constexpr int MAXT = 128 / KB;
-    const int k0 = lane / LPB, q = lane - k0 * LPB;
-    const int cofs = (q * G) & 3;
-    const T *vrow = vals + rs * 16 + q * G;
-    T acc = 0;
-    if (nb <= 128) {
-      const int c0 = lane < nb ? colind[rs + lane] : 0;
-      const int c1 = lane + kWave < nb ? colind[rs + kWave + lane] : 0;
-#pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        const int jj = t * KB + k0;
-        const int col = __shfl(t * KB < kWave ? c0 : c1, jj & (kWave - 1));
-        if (jj < nb) {
-          const V a = *reinterpret_cast<const V *>(vrow + (int64_t)jj * 16);
-          const V xv = *reinterpret_cast<const V *>(x + (int64_t)col * 4 + cofs);
-          acc += dot16<T>(a, xv);
-        }
-      }
-    } else {
-      for (int jj = k0; jj < nb; jj += KB) {
-        const int col = colind[rs + jj];
-        const V a = *reinterpret_cast<const V *>(vrow + (int64_t)jj * 16);
-        const V xv = *reinterpret_cast<const V *>(x + (int64_t)col * 4 + cofs);
-        acc += dot16<T>(a, xv);
-      }
-    }
-    // lanes holding block row r: q * G / 4 == r; sum over them and over k0
+    constexpr int G = Vec16<T>::G;
+    constexpr int LPB = 16 / G;
+    // lanes holding block row r: q * G / 4 == r; sum over them and over blocks
     for (int m = 1; m < 4 / G; m <<= 1) acc += __shfl_xor(acc, m);
     for (int m = LPB; m < kWave; m <<= 1) acc += __shfl_xor(acc, m);
-    tot = __shfl(acc, (lane & 3) * (4 / G));
+    return __shfl(acc, (lane & 3) * (4 / G));
+  } else if constexpr ((B & (B - 1)) == 0) {
+    for (int m = B; m < kWave; m <<= 1) acc += __shfl_xor(acc, m);
+    return acc;
   } else {
-    constexpr int BB = B * B;
-    constexpr int KB = kWave / BB;
-    constexpr int ACT = KB * BB;
-    constexpr int MAXT = (128 + KB - 1) / KB;
-    const int k0 = lane / BB, e = lane - k0 * BB, c = e % B;
-    const bool on = lane < ACT;
-    T acc = 0;
-    if (nb <= 128) {
-      const int c0 = lane < nb ? colind[rs + lane] : 0;
-      const int c1 = lane + kWave < nb ? colind[rs + kWave + lane] : 0;
+    // B = 3: 21 block groups of 3 lanes; tree over groups (absent ones are 0)
+    constexpr int ACT = RowMap<B, T>::ACT;
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        const int jj = t * KB + k0;
-        const int ca = __shfl(c0, jj & (kWave - 1));
-        const int cb = __shfl(c1, jj & (kWave - 1));
-        const int col = jj < kWave ? ca : cb;
-        if (on && jj < nb) acc += vals[(rs + jj) * BB + e] * x[(int64_t)col * B + c];
-      }
-    } else if (on) {
-      for (int jj = k0; jj < nb; jj += KB)
-        acc += vals[(rs + jj) * BB + e] * x[(int64_t)colind[rs + jj] * B + c];
+    for (int sft = 16; sft >= 1; sft >>= 1) {
+      const int src = lane + B * sft;
+      const T o = __shfl(acc, src & (kWave - 1));
+      if (src < ACT) acc += o;
     }
-    tot = row_reduce<B, T>(acc, lane);
+    return acc;
   }
-  if (lane < B) {
-    const int64_t dof = row * B + lane;
-    if (MODE == 1)
-      y[dof] = mask[dof] ? T(0) : b[dof] - tot;
-    else if (MODE == 2)
-      y[dof] = mask[dof] ? T(0) : tot;
+}
+
+// NS wave steps over R rows with no branch inside: indices past the end of
+// a row are clamped to its last block (a cached re-read) and their products
+// masked out, so the compiler can issue every value / x load of the R rows
+// before the first use.  acc starts at +0 and masked steps add +0, so the
+// sums equal those of a loop over the row's blocks only.
+template <int B, typename T, int NS, int R>
+__device__ __forceinline__ void sweep_rows(const int (&rs)[R], const int (&nb)[R],
+                                           const int (&c0)[R], const int (&c1)[R], int k0, int q,
+                                           bool on, gptr<const T> vals, gptr<const T> x,
+                                           T (&acc)[R]) {
+  using M = RowMap<B, T>;
+  int col[R][NS];
+  int64_t blk[R][NS];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int jj = t * M::KB + k0;
+      const int jc = nb[r] > 0 ? min(jj, nb[r] - 1) : 0;
+      const int ca = __shfl(c0[r], jc & (kWave - 1));
+      int cv = ca;
+      if (t * M::KB + M::KB > kWave) {
+        const int cb = __shfl(c1[r], jc & (kWave - 1));
+        cv = jc < kWave ? ca : cb;
+      }
+      col[r][t] = cv;
+      blk[r][t] = nb[r] > 0 ? (int64_t)rs[r] + jc : 0;
+    }
+  T p[R][NS];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) p[r][t] = block_partial<B, T>(vals, x, blk[r][t], col[r][t], q);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) acc[r] += (on && t * M::KB + k0 < nb[r]) ? p[r][t] : T(0);
+}
+
+template <int B, typename T, int MODE, int R>
+__device__ __forceinline__ void spmv_rows(int64_t row0, int64_t nrows, int lane,
+                                          const int32_t *rowptr_, const int32_t *colind_,
+                                          const T *vals_, const T *x_, const T *b_,
+                                          const uint8_t *mask_, T *y_) {
+  using M = RowMap<B, T>;
+  const gptr<const int32_t> rowptr = glb(rowptr_), colind = glb(colind_);
+  const gptr<const T> vals = glb(vals_), x = glb(x_), b = glb(b_);
+  const gptr<const uint8_t> mask = glb(mask_);
+  const gptr<T> y = glb(y_);
+  const int k0 = lane / M::LPB, q = lane - k0 * M::LPB;
+  const bool on = lane < M::ACT;
+  int rp = 0;
+  if (lane <= R) rp = rowptr[row0 + lane <= nrows ? row0 + lane : nrows];
+  int rs[R], nb[R];
+  int nbmax = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    rs[r] = __shfl(rp, r);
+    nb[r] = __shfl(rp, r + 1) - rs[r];
+    nbmax = max(nbmax, nb[r]);
+  }
+  // the row's identity flags and right-hand side, fetched now so that
+  // their latency overlaps the sweep instead of following the reduction
+  uint8_t mrow[R];
+  T brow[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    mrow[r] = 0;
+    brow[r] = T(0);
+    if (lane < B && row0 + r < nrows) {
+      const int64_t dof = (row0 + r) * B + lane;
+      if (MODE != 0) mrow[r] = mask[dof];
+      if (MODE == 1) brow[r] = b[dof];
+    }
+  }
+  T acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = T(0);
+  if (nbmax <= 128) {
+    int c0[R], c1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      c0[r] = lane < nb[r] ? colind[rs[r] + lane] : 0;
+      c1[r] = lane + kWave < nb[r] ? colind[rs[r] + kWave + lane] : 0;
+    }
+    // steps in use, rounded up to a quarter of the 128-block maximum
+    constexpr int S1 = (M::MAXT + 3) / 4, S2 = (M::MAXT + 1) / 2, S3 = (3 * M::MAXT + 3) / 4;
+    const int steps = (nbmax + M::KB - 1) / M::KB;
+    if (steps <= S1)
+      sweep_rows<B, T, S1, R>(rs, nb, c0, c1, k0, q, on, vals, x, acc);
+    else if (steps <= S2)
+      sweep_rows<B, T, S2, R>(rs, nb, c0, c1, k0, q, on, vals, x, acc);
+    else if (steps <= S3)
+      sweep_rows<B, T, S3, R>(rs, nb, c0, c1, k0, q, on, vals, x, acc);
     else
-      y[dof] = tot;
+      sweep_rows<B, T, M::MAXT, R>(rs, nb, c0, c1, k0, q, on, vals, x, acc);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (on)
+        for (int jj = k0; jj < nb[r]; jj += M::KB)
+          acc[r] += block_partial<B, T>(vals, x, (int64_t)rs[r] + jj, colind[rs[r] + jj], q);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const T tot = row_total<B, T>(acc[r], lane);
+    const int64_t row = row0 + r;
+    if (lane < B && row < nrows) {
+      const int64_t dof = row * B + lane;
+      if (MODE == 1)
+        y[dof] = mrow[r] ? T(0) : brow[r] - tot;
+      else if (MODE == 2)
+        y[dof] = mrow[r] ? T(0) : tot;
+      else
+        y[dof] = tot;
+    }
   }
 }
 
@@ -154,12 +249,15 @@ __device__ __forceinline__ void spmv_row(int64_t row, int lane, const int32_t *_
 // the workgroup.
 template <typename T>
 __device__ __forceinline__ void vanka_patch_wg(int64_t pfirst, int64_t pend, int np, int npc, int b,
-                                               int nl, int ppw, const int32_t *__restrict__ pnodes,
-                                               const T *__restrict__ inv, const T *__restrict__ d,
-                                               T *__restrict__ Y, int scatter, T *__restrict__ x,
-                                               const T *__restrict__ scale,
-                                               const uint8_t *__restrict__ mask, T omega, T *dl) {
+                                               int nl, int ppw, const int32_t *pnodes_,
+                                               const T *inv_, const T *d_, T *Y_, int scatter,
+                                               T *x_, const T *scale_, const uint8_t *mask_,
+                                               T omega, T *dl) {
   using V = typename Vec16<T>::type;
+  const gptr<const int32_t> pnodes = glb(pnodes_);
+  const gptr<const T> inv = glb(inv_), d = glb(d_), scale = glb(scale_);
+  const gptr<const uint8_t> mask = glb(mask_);
+  const gptr<T> Y = glb(Y_), x = glb(x_);
   constexpr int G = Vec16<T>::G;
   const int t = threadIdx.x;
   const int s = t / np;
@@ -176,7 +274,7 @@ __device__ __forceinline__ void vanka_patch_wg(int64_t pfirst, int64_t pend, int
   if (s < ppw && r < npc - np) dl[s * npc + np + r] = T(0);
   __syncthreads();
   if (!act) return;
-  const V *A = reinterpret_cast<const V *>(inv + p * (int64_t)np * npc) + r;
+  gptr<const V> A = reinterpret_cast<gptr<const V>>(inv + p * (int64_t)np * npc) + r;
   const T *dv = dl + s * npc;
   T acc = 0;
   const int ng = npc / G;
@@ -198,16 +296,18 @@ __device__ __forceinline__ void vanka_patch_wg(int64_t pfirst, int64_t pend, int
 // patch order: x += omega * w(node) * sum_i (R_i^T y_i); identity dofs keep x
 // (assign: x starts from 0).
 template <typename T>
-__device__ __forceinline__ void vanka_gather_dof(int64_t dof, int b, const int32_t *__restrict__ gptr,
-                                                 const int32_t *__restrict__ gidx,
-                                                 const T *__restrict__ Y, const T *__restrict__ scale,
-                                                 const uint8_t *__restrict__ mask, T omega, int assign,
-                                                 T *__restrict__ x) {
+__device__ __forceinline__ void vanka_gather_dof(int64_t dof, int b, const int32_t *gptr_,
+                                                 const int32_t *gidx_, const T *Y_, const T *scale_,
+                                                 const uint8_t *mask_, T omega, int assign, T *x_) {
+  const gptr<const int32_t> gp = glb(gptr_), gidx = glb(gidx_);
+  const gptr<const T> Y = glb(Y_), scale = glb(scale_);
+  const gptr<const uint8_t> mask = glb(mask_);
+  const gptr<T> x = glb(x_);
   const int64_t node = dof / b;
   const int c = (int)(dof - node * b);
   T s = 0;
-  const int e1 = gptr[node + 1];
-  for (int e = gptr[node]; e < e1; ++e) s += Y[(int64_t)gidx[e] * b + c];
+  const int e1 = gp[node + 1];
+  for (int e = gp[node]; e < e1; ++e) s += Y[(int64_t)gidx[e] * b + c];
   const T xv = assign ? T(0) : x[dof];
   x[dof] = mask[dof] ? xv : xv + omega * scale[node] * s;
 }
@@ -244,8 +344,10 @@ __device__ __forceinline__ int restrict_1d(int I, int nc, int *idx, T *w) {
 // r_c(node) = sum over the fine nodes it interpolates into; 0 at identity rows
 template <int B, int DIM, typename T>
 __device__ __forceinline__ void restrict_node(int64_t node, int cx, int cy, int cz,
-                                              const T *__restrict__ rf, T *__restrict__ rc,
-                                              const uint8_t *__restrict__ maskc) {
+                                              const T *rf_, T *rc_, const uint8_t *maskc_) {
+  const gptr<const T> rf = glb(rf_);
+  const gptr<T> rc = glb(rc_);
+  const gptr<const uint8_t> maskc = glb(maskc_);
   const int NX = 2 * cx + 1, NY = 2 * cy + 1;
   const int FX = 4 * cx + 1, FY = 4 * cy + 1;
   const int I = (int)(node % NX), J = (int)((node / NX) % NY), K = (int)(node / ((int64_t)NX * NY));
@@ -264,7 +366,7 @@ __device__ __forceinline__ void restrict_node(int64_t node, int cx, int cy, int 
       const int64_t base = ((int64_t)iz[a] * FY + iy[bb]) * FX;
       for (int q = 0; q < nx; ++q) {
         const T w = wyz * wx[q];
-        const T *src = rf + (base + ix[q]) * B;
+        gptr<const T> src = rf + (base + ix[q]) * B;
 #pragma unroll
         for (int c = 0; c < B; ++c) acc[c] += w * src[c];
       }
@@ -279,8 +381,10 @@ __device__ __forceinline__ void restrict_node(int64_t node, int cx, int cy, int 
 // x_f(node) += interpolated coarse correction; 0 at identity rows
 template <int B, int DIM, typename T>
 __device__ __forceinline__ void prolong_node(int64_t node, int cx, int cy, int cz,
-                                             const T *__restrict__ xc, T *__restrict__ xf,
-                                             const uint8_t *__restrict__ maskf) {
+                                             const T *xc_, T *xf_, const uint8_t *maskf_) {
+  const gptr<const T> xc = glb(xc_);
+  const gptr<T> xf = glb(xf_);
+  const gptr<const uint8_t> maskf = glb(maskf_);
   const int NX = 2 * cx + 1, NY = 2 * cy + 1;
   const int FX = 4 * cx + 1, FY = 4 * cy + 1;
   const int i = (int)(node % FX), j = (int)((node / FX) % FY), k = (int)(node / ((int64_t)FX * FY));
@@ -299,7 +403,7 @@ __device__ __forceinline__ void prolong_node(int64_t node, int cx, int cy, int c
       const int64_t base = ((int64_t)iz[a] * NY + iy[bb]) * NX;
       for (int q = 0; q < nx; ++q) {
         const T w = wyz * wx[q];
-        const T *src = xc + (base + ix[q]) * B;
+        gptr<const T> src = xc + (base + ix[q]) * B;
 #pragma unroll
         for (int c = 0; c < B; ++c) acc[c] += w * src[c];
       }

@@ -10,12 +10,22 @@
 
 namespace fsimg {
 
+// Launch shapes that do not change any result bit (rows per wavefront of the
+// SpMV, patches per workgroup of the Vanka apply), chosen per (operation,
+// block size or patch size, word size, size bucket = floor(log2 size)) by
+// measurement (fsimg_hier_tune) or by the built-in defaults.  Owned by a
+// context; read by every launch of its hierarchies.
+struct TuneTable;
+int spmv_rows_per_wave(const TuneTable *t, int b, int word, int64_t nrows);  // 1, 2 or 4
+int vanka_patches_per_wg(const TuneTable *t, int np, int word, int64_t npatch);
+
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
 
 // One multigrid level on the device.  Vectors of the V-cycle exist in the
 // precision of the hierarchy (T = double for FP64, float for mixed).
 struct DevLevel {
+  const TuneTable *tune = nullptr;      // launch shapes (the owning context's table)
   int dim = 0, b = 0, nl = 0, np = 0;   // nl = 3^d nodes per patch, np = nl*b
   int npc64 = 0, npc32 = 0;             // padded column counts of stored inverses
   int cells[3] = {1, 1, 1}, nnode[3] = {1, 1, 1};
@@ -97,11 +107,13 @@ int krylov_blocks(int64_t n);  // reduction blocks of a vector of length n
 
 enum BatchSpmvSrc { BS_VCYCLE = 0, BS_AZ = 1, BS_RESID = 2 };
 
+// rpw: block rows per wavefront (the work set counts workgroups of 4 * rpw rows)
 template <typename T>
-void launch_b_spmv(int b, int src, const DLev *lev, const DKry *kry, const int *active,
+void launch_b_spmv(int b, int src, int rpw, const DLev *lev, const DKry *kry, const int *active,
                    const WorkSet &ws, int j, hipStream_t s);
+// ppw: patches per workgroup (the work set counts workgroups of ppw patches)
 template <typename T>
-void launch_b_vanka(int np, int b, int nl, int npc, T omega, bool first, bool assign,
+void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first, bool assign,
                     const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
@@ -142,7 +154,17 @@ void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T
 template <typename T>
 void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
                         int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s);
-void vanka_shape(int np, int *ppw, int *threads);
+// threads of a Vanka workgroup holding ppw patches of np rows (whole waves)
+inline int vanka_threads(int np, int ppw) { return (ppw * np + 63) / 64 * 64; }
+// default patches per workgroup: the fewest idle lanes (ties: smaller group)
+int vanka_default_ppw(int np);
+// SpMV with an explicit shape (for the tuner's measurements)
+template <typename T>
+void launch_bsr_spmv_rpw(const DevLevel &L, const T *vals, const T *x, const T *b, T *y,
+                         bool resid, int rpw, hipStream_t s);
+template <typename T>
+void launch_vanka_patch_ppw(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
+                            int64_t p1, int ppw, hipStream_t s);
 template <typename T>
 void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
                          hipStream_t s);

@@ -1,6 +1,8 @@
 // Host-side structures of contexts and hierarchies, shared by the C-ABI
 // implementation and the batched solve driver.
 #pragma once
+#include <array>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -10,12 +12,20 @@
 struct BatchPlan;
 using fsimg::DevLevel;
 
+namespace fsimg {
+struct TuneTable {
+  // (fsimg_tune_kind, block size or patch size, word bytes, floor(log2 size)) -> value
+  std::map<std::array<int, 4>, int> entries;
+};
+}  // namespace fsimg
+
 struct fsimg_ctx {
   int device = 0;
   size_t budget = 0;
   size_t in_use = 0;
   size_t plan_bytes = 0;  // part of in_use held by cached batch plans
   std::vector<BatchPlan *> plans;  // descriptor tables of recent batch compositions (LRU)
+  fsimg::TuneTable tune;           // launch shapes of this context's kernels
 };
 
 struct EventTimer {
@@ -73,6 +83,7 @@ constexpr size_t kPlanCache = 8;  // batch compositions whose descriptor tables 
 // nlev levels, plus the plan's fixed part (an upper bound)
 size_t plan_bytes_bound(int nlev);
 bool plan_covers(const BatchPlan *p, uint64_t uid);
+void drop_plans(fsimg_ctx *ctx);  // destroy every cached batch plan (e.g. after a shape change)
 // batched FGMRES over n hierarchies (shared options / precision / block size)
 fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
                          double *const *x, fsimg_stats *stats, hipStream_t s);

@@ -10,8 +10,8 @@ namespace {
 
 using dev::kWave;
 
-template <int B, typename T, int MODE>
-__global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *__restrict__ rowptr,
+template <int B, typename T, int MODE, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_bsr_spmv(int64_t nrows, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ colind,
                                                   const T *__restrict__ vals,
                                                   const T *__restrict__ x,
@@ -19,9 +19,9 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(int64_t nrows, const int32_t *
                                                   const uint8_t *__restrict__ mask,
                                                   T *__restrict__ y) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (row >= nrows) return;  // uniform per wave
-  dev::spmv_row<B, T, MODE>(row, lane, rowptr, colind, vals, x, b, mask, y);
+  const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * R;
+  if (row0 >= nrows) return;  // uniform per wave
+  dev::spmv_rows<B, T, MODE, R>(row0, nrows, lane, rowptr, colind, vals, x, b, mask, y);
 }
 
 template <typename T>
@@ -93,50 +93,66 @@ inline unsigned grid_for(int64_t n, int per_block) {
 }  // namespace
 
 // Patches per workgroup for the Vanka apply: the workgroup holds ppw patches
-// of np row-threads rounded up to whole wavefronts; choose the ppw that
-// leaves the fewest idle lanes (ties: the smaller workgroup).
-void vanka_shape(int np, int *ppw, int *threads) {
+// of np row-threads rounded up to whole wavefronts; the default ppw leaves
+// the fewest idle lanes (ties: the smaller workgroup).
+int vanka_default_ppw(int np) {
   double best = -1.0;
+  int ppw = 1;
   for (int p = 1; p * np <= 1024; ++p) {
-    const int t = (p * np + 63) / 64 * 64;
-    const double u = (double)(p * np) / t;
-    if (u > best + 1e-12) { best = u; *ppw = p; *threads = t; }
+    const double u = (double)(p * np) / vanka_threads(np, p);
+    if (u > best + 1e-12) { best = u; ppw = p; }
   }
+  return ppw;
+}
+
+template <typename T>
+void launch_bsr_spmv_rpw(const DevLevel &L, const T *vals, const T *x, const T *b, T *y,
+                         bool resid, int rpw, hipStream_t s) {
+  const unsigned grid = grid_for(L.nrows, 4 * rpw);
+#define FSIMG_SPMV_CASE(BV, RV)                                                                  \
+  if (L.b == BV && rpw == RV) {                                                                  \
+    if (resid)                                                                                   \
+      hipLaunchKernelGGL((k_bsr_spmv<BV, T, 1, RV>), dim3(grid), dim3(256), 0, s, L.nrows,       \
+                         L.rowptr, L.colind, vals, x, b, L.mask, y);                             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_bsr_spmv<BV, T, 0, RV>), dim3(grid), dim3(256), 0, s, L.nrows,       \
+                         L.rowptr, L.colind, vals, x, b, L.mask, y);                             \
+    return;                                                                                      \
+  }
+  FSIMG_SPMV_CASE(1, 1) FSIMG_SPMV_CASE(2, 1) FSIMG_SPMV_CASE(3, 1) FSIMG_SPMV_CASE(4, 1)
+  FSIMG_SPMV_CASE(1, 2) FSIMG_SPMV_CASE(2, 2) FSIMG_SPMV_CASE(3, 2) FSIMG_SPMV_CASE(4, 2)
+  FSIMG_SPMV_CASE(1, 4) FSIMG_SPMV_CASE(2, 4) FSIMG_SPMV_CASE(3, 4) FSIMG_SPMV_CASE(4, 4)
+#undef FSIMG_SPMV_CASE
 }
 
 template <typename T>
 void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T *y, bool resid,
                      hipStream_t s) {
-  const unsigned grid = grid_for(L.nrows, 4);
-#define FSIMG_SPMV_CASE(BV)                                                                      \
-  case BV:                                                                                       \
-    if (resid)                                                                                   \
-      hipLaunchKernelGGL((k_bsr_spmv<BV, T, 1>), dim3(grid), dim3(256), 0, s, L.nrows, L.rowptr, \
-                         L.colind, vals, x, b, L.mask, y);                                       \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_bsr_spmv<BV, T, 0>), dim3(grid), dim3(256), 0, s, L.nrows, L.rowptr, \
-                         L.colind, vals, x, b, L.mask, y);                                       \
-    break;
-  switch (L.b) {
-    FSIMG_SPMV_CASE(1)
-    FSIMG_SPMV_CASE(2)
-    FSIMG_SPMV_CASE(3)
-    FSIMG_SPMV_CASE(4)
-    default: break;
-  }
-#undef FSIMG_SPMV_CASE
+  launch_bsr_spmv_rpw<T>(L, vals, x, b, y, resid,
+                         spmv_rows_per_wave(L.tune, L.b, (int)sizeof(T), L.nrows), s);
+}
+
+template <typename T>
+void launch_vanka_patch_ppw(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
+                            int64_t p1, int ppw, hipStream_t s) {
+  if (p1 <= p0) return;
+  const unsigned grid = grid_for(p1 - p0, ppw);
+  const size_t lds = sizeof(T) * (size_t)ppw * npc;
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(L.np, ppw)), lds, s, p0, p1,
+                     L.np, npc, L.b, L.nl, ppw, L.pnodes, inv, d, Y, 0, (T *)nullptr,
+                     (const T *)nullptr, L.mask, T(0));
 }
 
 template <typename T>
 void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
                         int64_t p1, bool scatter, T *x, const T *scale, T omega, hipStream_t s) {
   if (p1 <= p0) return;
-  int ppw = 1, threads = 64;
-  vanka_shape(L.np, &ppw, &threads);
+  const int ppw = vanka_patches_per_wg(L.tune, L.np, (int)sizeof(T), L.npatch);
   const unsigned grid = grid_for(p1 - p0, ppw);
   const size_t lds = sizeof(T) * (size_t)ppw * npc;
-  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(threads), lds, s, p0, p1, L.np, npc, L.b,
-                     L.nl, ppw, L.pnodes, inv, d, Y, scatter ? 1 : 0, x, scale, L.mask, omega);
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(L.np, ppw)), lds, s, p0, p1,
+                     L.np, npc, L.b, L.nl, ppw, L.pnodes, inv, d, Y, scatter ? 1 : 0, x, scale,
+                     L.mask, omega);
 }
 
 template <typename T>
@@ -194,6 +210,10 @@ void launch_mask_zero(double *x, const uint8_t *mask, int64_t n, hipStream_t s) 
                                    hipStream_t);                                                 \
   template void launch_vanka_patch<T>(const DevLevel &, const T *, int, const T *, T *, int64_t, \
                                       int64_t, bool, T *, const T *, T, hipStream_t);            \
+  template void launch_bsr_spmv_rpw<T>(const DevLevel &, const T *, const T *, const T *, T *,   \
+                                       bool, int, hipStream_t);                                  \
+  template void launch_vanka_patch_ppw<T>(const DevLevel &, const T *, int, const T *, T *,      \
+                                          int64_t, int64_t, int, hipStream_t);                   \
   template void launch_vanka_gather<T>(const DevLevel &, const T *, const T *, T, bool, T *,     \
                                        hipStream_t);                                             \
   template void launch_restrict<T>(const DevLevel &, const DevLevel &, const T *, T *,           \

@@ -22,6 +22,7 @@ FSIMG_ERR_NOCONV, FSIMG_ERR_NONFINITE, FSIMG_ERR_BUDGET, FSIMG_ERR_STATE = 5, 6,
 FSIMG_FP64, FSIMG_MIXED = 0, 1
 FSIMG_VANKA_GATHER, FSIMG_VANKA_PARITY, FSIMG_VANKA_GREEDY = 0, 1, 2
 FSIMG_WEIGHT_PLAIN, FSIMG_WEIGHT_MULT = 0, 1
+FSIMG_TUNE_SPMV_ROWS, FSIMG_TUNE_VANKA_PPW = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_SINGULAR",
                  5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_BUDGET", 8: "ERR_STATE"}
@@ -45,7 +46,8 @@ class fsimg_opts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("rtol", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("vanka_schedule", ctypes.c_int),
-                ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class fsimg_stats(ctypes.Structure):
@@ -111,6 +113,11 @@ _SIGS = {
     "fsimg_server_poll": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(_I)]),
     "fsimg_server_result": (_I, [_P, _I64, _P, _P]),
     "fsimg_server_release": (_I, [_P, _I64]),
+    "fsimg_hier_tune": (_I, [_P, _I, _P]),
+    "fsimg_tune_set": (_I, [_P, _I, _I, _I, _I64, _I]),
+    "fsimg_tune_get": (_I, [_P, _I, _I, _I, _I64, ctypes.POINTER(_I)]),
+    "fsimg_tune_save": (_I, [_P, ctypes.c_char_p]),
+    "fsimg_tune_load": (_I, [_P, ctypes.c_char_p]),
     "fsimg_last_error": (ctypes.c_char_p, []),
 }
 EXPORTED = tuple(_SIGS)
@@ -388,3 +395,25 @@ def fsimg_server_result(srv, rid: int, n_mom: int, n_ale: int):
 
 def fsimg_server_release(srv, rid: int):
     _check(load().fsimg_server_release(srv, rid))
+
+
+def fsimg_hier_tune(h, force: bool = False, stream=None):
+    _check(load().fsimg_hier_tune(h, 1 if force else 0, _stream(stream)))
+
+
+def fsimg_tune_set(ctx, kind: int, key: int, word: int, size: int, value: int):
+    _check(load().fsimg_tune_set(ctx, kind, key, word, size, value))
+
+
+def fsimg_tune_get(ctx, kind: int, key: int, word: int, size: int) -> int:
+    v = ctypes.c_int()
+    _check(load().fsimg_tune_get(ctx, kind, key, word, size, ctypes.byref(v)))
+    return v.value
+
+
+def fsimg_tune_save(ctx, path: str):
+    _check(load().fsimg_tune_save(ctx, os.fsencode(path)))
+
+
+def fsimg_tune_load(ctx, path: str):
+    _check(load().fsimg_tune_load(ctx, os.fsencode(path)))
