@@ -114,7 +114,7 @@ def calib_copy(nbytes, reps):
     log(f"calib-copy: {reps} copies of {nbytes} bytes")
 
 
-def run_gpu(P, precision, steps, warmup, with_mass=True):
+def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True):
     import torch
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import level_dicts
@@ -134,6 +134,24 @@ def run_gpu(P, precision, steps, warmup, with_mass=True):
         fsimg.fsimg_factor(hs[name])
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    shapes = {}
+    if tune:
+        # launch shapes measured on these hierarchies (no result bit depends on them)
+        for name in systems:
+            fsimg.fsimg_hier_tune(hs[name])
+        torch.cuda.synchronize()
+        word = 8 if precision == fsimg.FSIMG_FP64 else 4
+        for name in systems:
+            for l in range(len(P.levels) - 1):
+                info = fsimg.fsimg_hier_info(hs[name], l)
+                m = P.levels[l].systems[name]
+                shapes[f"{name}/L{l}"] = {
+                    "spmv_rows_per_wave": fsimg.fsimg_tune_get(ctx, fsimg.FSIMG_TUNE_SPMV_ROWS, m.b, word,
+                                                               m.nrows),
+                    "vanka_patches_per_wg": fsimg.fsimg_tune_get(ctx, fsimg.FSIMG_TUNE_VANKA_PPW,
+                                                                 info["np"], word, max(info["npatch"], 1))}
+    t_tune = time.perf_counter() - t0
     lev = P.levels[0]
     nn = lev.nnodes
     d = P.dim
@@ -178,7 +196,8 @@ def run_gpu(P, precision, steps, warmup, with_mass=True):
     prof = [step(profile=True)[0] for _ in range(max(1, min(steps, 3)))]
     torch.cuda.synchronize()
     info_m = fsimg.fsimg_hier_info(hs["mom"], 0)
-    res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, stats=stats[-1], prof=prof,
+    res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, t_tune=t_tune, shapes=shapes,
+               stats=stats[-1], prof=prof,
                info_m=info_m, x_mom=x_mom.cpu().numpy(), x_ale=x_ale.cpu().numpy())
     for h in hs.values():
         fsimg.fsimg_hier_destroy(h)
@@ -420,6 +439,7 @@ def main():
     ap.add_argument("--lam", type=float, default=None, help="solid Lame lambda override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes, no tuning")
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
@@ -477,7 +497,7 @@ def main():
     elif args.no_fp64:
         precs = precs[:1]
     for tag, prec in precs:
-        r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass)
+        r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass, tune=not args.no_tune)
         A = to_csr(lev.systems["mom"])
         mask = lev.systems["mom"].dirichlet.astype(bool)
         rr = P.rhs["mom"] - A @ r["x_mom"]
@@ -553,7 +573,8 @@ def main():
         "solve": {"momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
                   "rel_res_momentum_fp64_host": R["rel_res_host"],
-                  "setup_s": R["t_setup"], "factor_s": R["t_factor"]},
+                  "setup_s": R["t_setup"], "factor_s": R["t_factor"], "tune_s": R["t_tune"],
+                  "launch_shapes": R["shapes"]},
     }
     if "fp64" in runs and main_tag != "fp64":
         F = runs["fp64"]

@@ -200,7 +200,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
       const int Li = (int)hs[i]->lev.size();
       if (l < Li - 1) {
         const DevLevel &L = hs[i]->lev[l];
-        sp.push(i, cdiv(L.nrows, 4 * P->rpw[l]));
+        sp.push(i, cdiv(L.nrows, 4 * P->rpw[l] * spmv_group_rows(P->b, word)));
         pa.push(i, cdiv(L.npatch, P->ppw[l]));
         ga.push(i, cdiv(L.n, 256));
         re.push(i, cdiv(hs[i]->lev[l + 1].nrows, 256));
@@ -222,7 +222,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   WsHost row0, vec0, kr, ins;
   for (int i = 0; i < n; ++i) {
     const DevLevel &L = hs[i]->lev[0];
-    row0.push(i, cdiv(L.nrows, 4 * P->rpw0));
+    row0.push(i, cdiv(L.nrows, 4 * P->rpw0 * spmv_group_rows(P->b, 8)));
     vec0.push(i, cdiv(L.n, 256));
     kr.push(i, krylov_blocks(L.n));
     ins.push(i, 1);

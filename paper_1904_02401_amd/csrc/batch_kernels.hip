@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   if (!active[i]) return;
   const DLev &L = lev[i];
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row0 = ((blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave) * R;
+  constexpr int GR = spmv_group_rows(B, SRC == BS_VCYCLE ? (int)sizeof(T) : 8);
+  const int64_t row0 = ((blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave) * R * GR;
   if (row0 >= L.nrows) return;
   if constexpr (SRC == BS_VCYCLE) {
     dev::spmv_rows<B, T, 1, R>(row0, L.nrows, lane, L.rowptr, L.colind, LV<T>::vals(L),

@@ -159,7 +159,7 @@ __device__ __forceinline__ void sweep_rows(const int (&rs)[R], const int (&nb)[R
 }
 
 template <int B, typename T, int MODE, int R>
-__device__ __forceinline__ void spmv_rows(int64_t row0, int64_t nrows, int lane,
+__device__ __forceinline__ void spmv_rows_wave(int64_t row0, int64_t nrows, int lane,
                                           const int32_t *rowptr_, const int32_t *colind_,
                                           const T *vals_, const T *x_, const T *b_,
                                           const uint8_t *mask_, T *y_) {
@@ -235,6 +235,110 @@ __device__ __forceinline__ void spmv_rows(int64_t row0, int64_t nrows, int lane,
       else
         y[dof] = tot;
     }
+  }
+}
+
+// FP32 (and b <= 2): 64 / LR rows per wavefront, LR lanes per row, one lane
+// per block (its b x b values and the b entries of x); a lane takes blocks
+// li, li + LR, ... of its row.  For the short FP32 rows this keeps more rows
+// in flight per wave than the whole-wave mapping above.  Lane partials are
+// summed by an xor tree inside the row's lane group.
+template <int B, typename T, int MODE, int LR>
+__device__ __forceinline__ void spmv_group(int64_t row0, int64_t nrows, int lane,
+                                           gptr<const int32_t> rowptr, gptr<const int32_t> colind,
+                                           gptr<const T> vals, gptr<const T> x, gptr<const T> b,
+                                           gptr<const uint8_t> mask, gptr<T> y) {
+  constexpr int RPW = kWave / LR;  // rows of this group
+  constexpr int NI = 128 / LR;     // blocks per lane at most
+  const int li = lane % LR, rsub = lane / LR;
+  const int rp = lane <= RPW ? rowptr[min(row0 + lane, nrows)] : 0;
+  const int64_t row = row0 + rsub;
+  const bool live = row < nrows;
+  const int rs = __shfl(rp, rsub);
+  const int nb = live ? __shfl(rp, rsub + 1) - rs : 0;
+  int nbmax = nb;
+  for (int m = LR; m < kWave; m <<= 1) nbmax = max(nbmax, __shfl_xor(nbmax, m));
+  uint8_t mv = 0;
+  T bv = T(0);
+  if (li < B && live) {
+    if (MODE != 0) mv = mask[row * B + li];
+    if (MODE == 1) bv = b[row * B + li];
+  }
+  T acc[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) acc[r] = T(0);
+  if (nbmax <= 128) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      if (it * LR < nbmax) {
+        const int jj = it * LR + li;
+        const bool ok = jj < nb;
+        const int64_t blk = nb > 0 ? (int64_t)rs + (ok ? jj : nb - 1) : 0;
+        const int col = colind[blk];
+        gptr<const T> v = vals + blk * (B * B);
+        gptr<const T> xv = x + (int64_t)col * B;
+        T xr[B], vv[B * B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) xr[c] = xv[c];
+#pragma unroll
+        for (int e = 0; e < B * B; ++e) vv[e] = v[e];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          T p = vv[r * B] * xr[0];
+#pragma unroll
+          for (int c = 1; c < B; ++c) p += vv[r * B + c] * xr[c];
+          acc[r] += ok ? p : T(0);
+        }
+      }
+    }
+  } else {
+    for (int jj = li; jj < nb; jj += LR) {
+      const int64_t blk = (int64_t)rs + jj;
+      gptr<const T> v = vals + blk * (B * B);
+      gptr<const T> xv = x + (int64_t)colind[blk] * B;
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        T p = v[r * B] * xv[0];
+#pragma unroll
+        for (int c = 1; c < B; ++c) p += v[r * B + c] * xv[c];
+        acc[r] += p;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+    for (int m = LR / 2; m > 0; m >>= 1) acc[r] += __shfl_xor(acc[r], m);
+  T tot = acc[0];
+#pragma unroll
+  for (int r = 1; r < B; ++r) tot = li == r ? acc[r] : tot;
+  if (li < B && live) {
+    const int64_t dof = row * B + li;
+    if (MODE == 1)
+      y[dof] = mv ? T(0) : bv - tot;
+    else if (MODE == 2)
+      y[dof] = mv ? T(0) : tot;
+    else
+      y[dof] = tot;
+  }
+}
+
+// R row groups per wavefront (a group = 64 / lanes-per-row rows), starting
+// at row0; the result of a row does not depend on R.
+template <int B, typename T, int MODE, int R>
+__device__ __forceinline__ void spmv_rows(int64_t row0, int64_t nrows, int lane,
+                                          const int32_t *rowptr_, const int32_t *colind_,
+                                          const T *vals_, const T *x_, const T *b_,
+                                          const uint8_t *mask_, T *y_) {
+  constexpr int LR = kWave / spmv_group_rows(B, (int)sizeof(T));
+  if constexpr (LR == kWave) {
+    spmv_rows_wave<B, T, MODE, R>(row0, nrows, lane, rowptr_, colind_, vals_, x_, b_, mask_, y_);
+  } else {
+    constexpr int RPW = kWave / LR;
+#pragma unroll
+    for (int g = 0; g < R; ++g)
+      if (row0 + g * RPW < nrows)
+        spmv_group<B, T, MODE, LR>(row0 + g * RPW, nrows, lane, glb(rowptr_), glb(colind_),
+                                   glb(vals_), glb(x_), glb(b_), glb(mask_), glb(y_));
   }
 }
 

@@ -19,6 +19,15 @@ struct TuneTable;
 int spmv_rows_per_wave(const TuneTable *t, int b, int word, int64_t nrows);  // 1, 2 or 4
 int vanka_patches_per_wg(const TuneTable *t, int np, int word, int64_t npatch);
 
+// Rows one wavefront of the SpMV covers per row group: 1 for the whole-wave
+// mapping (FP64, b >= 3), else 64 / lanes-per-row of the row-group mapping
+// (FP32 b = 4: 32 lanes per row; b <= 3 in FP32, b <= 2 in FP64: 16).  A
+// launch with R row groups per wave covers 4 * R * this many rows per
+// 256-thread workgroup.
+constexpr int spmv_group_rows(int b, int word) {
+  return (word == 8 && b >= 3) ? 1 : (b == 4 ? 2 : 4);
+}
+
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
 

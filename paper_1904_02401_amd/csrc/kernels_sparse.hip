@@ -19,7 +19,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                                   const uint8_t *__restrict__ mask,
                                                   T *__restrict__ y) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * R;
+  const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * R *
+                       spmv_group_rows(B, (int)sizeof(T));
   if (row0 >= nrows) return;  // uniform per wave
   dev::spmv_rows<B, T, MODE, R>(row0, nrows, lane, rowptr, colind, vals, x, b, mask, y);
 }
@@ -108,7 +109,7 @@ int vanka_default_ppw(int np) {
 template <typename T>
 void launch_bsr_spmv_rpw(const DevLevel &L, const T *vals, const T *x, const T *b, T *y,
                          bool resid, int rpw, hipStream_t s) {
-  const unsigned grid = grid_for(L.nrows, 4 * rpw);
+  const unsigned grid = grid_for(L.nrows, 4 * rpw * spmv_group_rows(L.b, (int)sizeof(T)));
 #define FSIMG_SPMV_CASE(BV, RV)                                                                  \
   if (L.b == BV && rpw == RV) {                                                                  \
     if (resid)                                                                                   \
