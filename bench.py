@@ -529,10 +529,11 @@ def main():
         s_avg = s_ms / max(s_n, 1) * 1e-3
         tname = "double" if tag == "fp64" else "float"
         bm = lev.systems["mom"].b
+        rpw = R["shapes"].get("mom/L0", {}).get("spmv_rows_per_wave", 1)
         return {"vanka_patch": {"kernel": f"kb_vanka_patch<{tname}>",
                                 "GB/s": vb / v_avg / 1e9 if v_n else 0.0, "avg_ms": v_avg * 1e3,
                                 "launches": v_n, "bytes_per_launch": vb, "total_ms": v_ms},
-                "spmv_residual": {"kernel": f"kb_spmv<{bm}, {tname}, 0>",
+                "spmv_residual": {"kernel": f"kb_spmv<{bm}, {tname}, 0, {rpw}>",
                                   "GB/s": sb / s_avg / 1e9 if s_n else 0.0, "avg_ms": s_avg * 1e3,
                                   "launches": s_n, "bytes_per_launch": sb, "total_ms": s_ms}}
 

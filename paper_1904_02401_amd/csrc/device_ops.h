@@ -376,14 +376,26 @@ __device__ __forceinline__ void vanka_patch_wg(int64_t pfirst, int64_t pend, int
     dl[s * npc + r] = d[(int64_t)node * b + c];
   }
   if (s < ppw && r < npc - np) dl[s * npc + np + r] = T(0);
+  // the first column groups of the inverse do not depend on d: fetch them
+  // before the barrier so that their latency overlaps the gather
+  constexpr int PF = 6;
+  const int ng = npc / G;
+  gptr<const V> A = reinterpret_cast<gptr<const V>>(inv + (act ? p : 0) * (int64_t)np * npc) + r;
+  V pre[PF];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) pre[k] = (act && k < ng) ? A[(int64_t)k * np] : V{};
   __syncthreads();
   if (!act) return;
-  gptr<const V> A = reinterpret_cast<gptr<const V>>(inv + p * (int64_t)np * npc) + r;
   const T *dv = dl + s * npc;
   T acc = 0;
-  const int ng = npc / G;
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+    if (k < ng) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) acc += vget(pre[k], q) * dv[k * G + q];
+    }
 #pragma unroll 6
-  for (int g = 0; g < ng; ++g) {
+  for (int g = PF; g < ng; ++g) {
     const V v = A[(int64_t)g * np];
 #pragma unroll
     for (int q = 0; q < G; ++q) acc += vget(v, q) * dv[g * G + q];
