@@ -126,6 +126,7 @@ struct Tuner {
       const double ms = time_launches(
           [&] { launch_bsr_spmv_rpw<T>(L, vals, x, b, y, true, R, s); }, s, e0, e1, 5);
       if (ms >= 0.0 && ms < best_ms) { best_ms = ms; best = R; }
+      if (ms > 1.5 * best_ms) break;  // more rows per wave only gets slower from here
     }
     t.entries[{FSIMG_TUNE_SPMV_ROWS, L.b, word, bucket_of(L.nrows)}] = best;
     changed = true;
