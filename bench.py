@@ -313,44 +313,29 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serving(args):
-    """Serving workload: Poisson arrivals of FSI simulations (10 time steps of
-    3..5 Newton steps; 70 % 2D 64^2..256^2, 30 % 3D 16^3..48^3), hierarchies
-    resident in HBM, first-fit admission by footprint, continuous batching,
-    mixed precision.  Latency = arrival -> last solve of the simulation."""
+def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
+    """One serving run at one arrival rate on a fresh server; returns the
+    figures of that run."""
     import numpy as np
     import torch
-    from fsigen import serve_instance
     from paper_1904_02401_amd import fsimg
-    from paper_1904_02401_amd.problems import request_data
 
     rng = np.random.Generator(np.random.PCG64(args.seed))
-    sizes2, sizes3 = (64, 80, 96, 128, 160, 192, 256), (16, 20, 24, 32, 40, 48)
-    t0 = time.perf_counter()
-    pool = {}
-    for d, sz in [(2, n) for n in sizes2] + [(3, n) for n in sizes3 if n <= args.max3d]:
-        P = serve_instance(d, n=sz, seed=sz)
-        log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels")
-        pool[(d, sz)] = (request_data(P), P.levels[0].systems["mom"].nrows * (d + 1),
-                         P.levels[0].systems["ale"].nrows * d)
-    log(f"serving pool of {len(pool)} simulations generated in {time.perf_counter() - t0:.1f} s")
-    # arrival process
     arrivals, t = [], 0.0
     while True:
-        t += rng.exponential(1.0 / args.rate)
+        t += rng.exponential(1.0 / rate)
         if t > args.window:
             break
         d = 2 if rng.uniform() < 0.7 else 3
-        sz = int(rng.choice(sizes2 if d == 2 else [n for n in sizes3 if n <= args.max3d]))
+        sz = int(rng.choice(sizes2 if d == 2 else sizes3))
         ns = rng.integers(3, 6, size=10)
         arrivals.append((t, d, sz, ns))
-    budget = int(args.budget_gb * (1 << 30))
-    ctx = fsimg.fsimg_ctx_create(0, budget)
+    ctx = fsimg.fsimg_ctx_create(0, int(args.budget_gb * (1 << 30)))
     opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
     srv = fsimg.fsimg_server_create(ctx, opts, args.max_active)
     stream = torch.cuda.current_stream()
-    meta, lat, qdelay, done_ids, work = {}, [], [], [], 0.0
-    nxt, steps = 0, 0
+    meta, lat, qdelay, done_ids, work, failed = {}, [], [], [], 0.0, []
+    nxt, steps, max_active_seen = 0, 0, 0
     start = fsimg.fsimg_server_clock(srv)
     last_log = 0.0
     while True:
@@ -359,40 +344,43 @@ def run_serving(args):
             ta, d, sz, ns = arrivals[nxt]
             data, nm, na = pool[(d, sz)]
             rid = fsimg.fsimg_server_submit(srv, data, ns, start + ta)
-            meta[rid] = (start + ta, d, sz, nm, na, int(ns.sum()))
+            meta[rid] = (start + ta, d, sz, nm, na, int(ns.sum()), ns)
             nxt += 1
         active, queued = fsimg.fsimg_server_step(srv, stream)
         steps += 1
-        ids, adm, fin = fsimg.fsimg_server_poll(srv)
-        for rid, a, f in zip(ids, adm, fin):
-            arr, d, sz, nm, na, nsteps = meta[abs(int(rid))]
+        max_active_seen = max(max_active_seen, active)
+        for rid, a, f in zip(*fsimg.fsimg_server_poll(srv)):
+            arr, d, sz, nm, na, nsteps, _ = meta[abs(int(rid))]
             if rid > 0:
                 lat.append(f - arr)
                 qdelay.append(a - arr)
                 done_ids.append(int(rid))
                 work += nsteps * (nm + na)
+            else:
+                st = fsimg.fsimg_server_request_status(srv, abs(int(rid)))
+                failed.append({"dim": d, "cells": sz, "status": st})
+                log(f"  request {abs(int(rid))} ({d}D {sz}^{d}) failed with status {st}")
         now = fsimg.fsimg_server_clock(srv) - start
         if now - last_log > 10.0:
             last_log = now
-            log(f"  t={now:.1f} s: {nxt} arrived, {active} running, {queued} queued, "
+            log(f"  rate {rate}/s t={now:.1f} s: {nxt} arrived, {active} running, {queued} queued, "
                 f"{len(lat)} completed")
         if nxt >= len(arrivals) and active == 0 and queued == 0:
             break
         if now > args.max_wall:
+            log(f"  rate {rate}/s: stopped at {now:.1f} s with {active} running, {queued} queued")
             break
         if active == 0 and nxt < len(arrivals):
             time.sleep(max(0.0, min(arrivals[nxt][0] - now, 0.05)))
     wall = fsimg.fsimg_server_clock(srv) - start
-    # one completed request rerun alone must give the same result
     same = None
-    if done_ids:
+    if check_alone and done_ids:
+        # a completed request served again alone must give the same result
         rid = done_ids[len(done_ids) // 2]
-        arr, d, sz, nm, na, nsteps = meta[rid]
+        arr, d, sz, nm, na, nsteps, ns = meta[rid]
         xm_mix, xa_mix = fsimg.fsimg_server_result(srv, rid, nm, na)
         srv2 = fsimg.fsimg_server_create(ctx, opts)
-        data = pool[(d, sz)][0]
-        ns_alone = next(a[3] for a in arrivals if abs(a[0] + start - arr) < 1e-12)
-        rid2 = fsimg.fsimg_server_submit(srv2, data, ns_alone, fsimg.fsimg_server_clock(srv2))
+        rid2 = fsimg.fsimg_server_submit(srv2, pool[(d, sz)][0], ns, fsimg.fsimg_server_clock(srv2))
         while True:
             act, q = fsimg.fsimg_server_step(srv2, stream)
             if act == 0 and q == 0:
@@ -405,27 +393,57 @@ def run_serving(args):
     fsimg.fsimg_ctx_destroy(ctx)
     lat_a = np.array(lat) if lat else np.array([np.nan])
     q_a = np.array(qdelay) if qdelay else np.array([np.nan])
+    return {"rate_req_s": rate, "arrived": len(arrivals), "completed": len(lat),
+            "offered_req_s": len(arrivals) / args.window, "achieved_req_s": len(lat) / wall,
+            "wall_s": wall, "server_steps": steps, "max_running": max_active_seen,
+            "dof_per_s": work / wall,
+            "latency_p50_s": float(np.percentile(lat_a, 50)),
+            "latency_p99_s": float(np.percentile(lat_a, 99)),
+            "queue_delay_p50_s": float(np.percentile(q_a, 50)),
+            "queue_delay_p99_s": float(np.percentile(q_a, 99)),
+            "alone_equals_mix": same, "failed": failed}
+
+
+def run_serving(args):
+    """Serving workload: Poisson arrivals of FSI simulations (10 time steps of
+    3..5 Newton steps; 70 % 2D 64^2..256^2, 30 % 3D 16^3..48^3), hierarchies
+    resident in HBM, first-fit admission by footprint, continuous batching,
+    mixed precision.  Latency = arrival -> last solve of the simulation.
+    --rates runs a sweep of arrival rates on the same request pool."""
+    from fsigen import serve_instance
+    from paper_1904_02401_amd.problems import request_data
+
+    sizes2 = (64, 80, 96, 128, 160, 192, 256)
+    sizes3 = tuple(n for n in (16, 20, 24, 32, 40, 48) if n <= args.max3d)
+    t0 = time.perf_counter()
+    pool = {}
+    for d, sz in [(2, n) for n in sizes2] + [(3, n) for n in sizes3]:
+        P = serve_instance(d, n=sz, seed=sz)
+        log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels")
+        pool[(d, sz)] = (request_data(P), P.levels[0].systems["mom"].nrows * (d + 1),
+                         P.levels[0].systems["ale"].nrows * d)
+    log(f"serving pool of {len(pool)} simulations generated in {time.perf_counter() - t0:.1f} s")
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    runs = []
+    for k, rate in enumerate(rates):
+        runs.append(serve_once(args, pool, rate, sizes2, sizes3, check_alone=(k == len(rates) - 1)))
+        log(f"rate {rate}/s: {json.dumps(runs[-1])}")
+    main = runs[-1]
     out = {
         "metric": "MG-FGMRES DoF/s + smoother HBM GB/s, FP32-mixed vs FP64 @1e-8; p99 solve latency",
-        "value": work / wall, "unit": "DoF/s", "n_gpus": 1, "steps": steps, "warmup": 0,
-        "ms_per_step": wall / max(steps, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "value": main["dof_per_s"], "unit": "DoF/s", "n_gpus": 1, "steps": main["server_steps"],
+        "warmup": 0, "ms_per_step": main["wall_s"] / max(main["server_steps"], 1) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
         "config": {"workload": ("serving: Poisson arrivals of FSI simulations, 10 time steps x 3..5 "
                                 "Newton steps (momentum + deformation + ALE solves to 1e-8), 70% 2D "
-                                f"64^2..256^2, 30% 3D 16^3..{max(n for n in sizes3 if n <= args.max3d)}^3, "
-                                "mixed precision, resident hierarchies, first-fit admission by HBM "
-                                "footprint, continuous batching"),
-                   "max_active": args.max_active,
-                   "rate_req_s": args.rate, "window_s": args.window, "budget_GiB": args.budget_gb,
-                   "arrived": len(arrivals), "completed": len(lat),
-                   "offered_req_s": len(arrivals) / args.window,
-                   "achieved_req_s": len(lat) / wall, "wall_s": wall,
-                   "latency_p50_s": float(np.percentile(lat_a, 50)),
-                   "latency_p99_s": float(np.percentile(lat_a, 99)),
-                   "queue_delay_p50_s": float(np.percentile(q_a, 50)),
-                   "queue_delay_p99_s": float(np.percentile(q_a, 99)),
-                   "alone_equals_mix": same},
+                                f"64^2..256^2, 30% 3D 16^3..{max(sizes3)}^3, mixed precision, resident "
+                                "hierarchies, first-fit admission by HBM footprint, continuous batching"),
+                   "window_s": args.window, "budget_GiB": args.budget_gb,
+                   "max_active": args.max_active, **main},
     }
+    if len(runs) > 1:
+        out["sweep"] = runs
     print(json.dumps(out), flush=True)
 
 
@@ -450,6 +468,7 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="batched workload size")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the batched workload")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--rates", default="", help="serving: comma-separated arrival-rate sweep")
     ap.add_argument("--window", type=float, default=3.0, help="serving: arrival window (s)")
     ap.add_argument("--max-wall", type=float, default=90.0, help="serving: stop after this many s")
     ap.add_argument("--seed", type=int, default=0)

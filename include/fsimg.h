@@ -307,6 +307,10 @@ fsimg_status fsimg_server_poll(fsimg_server *srv, int64_t *ids, double *admitted
    completed and not yet released) to host memory (either pointer may be NULL). */
 fsimg_status fsimg_server_result(fsimg_server *srv, int64_t id, double *x_mom_host,
                                  double *x_ale_host);
+/* Status of a request: FSIMG_OK while queued / running or after success,
+   else the error that ended it (e.g. ERR_NOCONV of one of its solves,
+   ERR_BUDGET if it can never fit).  ERR_ARG for an unknown id. */
+fsimg_status fsimg_server_request_status(fsimg_server *srv, int64_t id, int *status);
 /* Forget a completed request's stored solution. */
 fsimg_status fsimg_server_release(fsimg_server *srv, int64_t id);
 

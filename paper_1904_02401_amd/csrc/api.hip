@@ -63,17 +63,6 @@ fsimg_status dalloc(fsimg_hier *h, T **p, size_t count) {
   return FSIMG_OK;
 }
 
-void dfree(fsimg_hier *h, void *p) {
-  if (!p) return;
-  for (size_t i = 0; i < h->allocs.size(); ++i)
-    if (h->allocs[i].first == p) {
-      (void)hipFree(p);
-      h->ctx->in_use -= h->allocs[i].second;
-      h->allocs.erase(h->allocs.begin() + (long)i);
-      return;
-    }
-}
-
 inline int npc_for(int np, int elem_bytes) {
   const int g = 16 / elem_bytes;
   return (np + g - 1) / g * g;
@@ -290,6 +279,8 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
   } else {
     const int64_t nf = count_free(L);
     s += (size_t)nf * nf * 8 + (size_t)(nf + n) * 4 + (size_t)2 * n * 8 + (size_t)2 * n * ts;
+    if (nf > 0)  // Gauss-Jordan workspace
+      s += (size_t)nf * nf * 8 + (size_t)2 * nf * 8 + (size_t)2 * nf * 4 + (size_t)kRedBlocks * 8;
   }
   return s;
 }
@@ -636,6 +627,14 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
         FSIMG_HIPC(hipMemcpyAsync(L.cfree, cf.data(), L.nfree * 4, hipMemcpyHostToDevice, s));
       }
       FSIMG_CHK(dalloc(h, &L.cinv, L.nfree * L.nfree));
+      if (L.nfree > 0) {
+        FSIMG_CHK(dalloc(h, &L.gj_a, L.nfree * L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_rowk, L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_colk, L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_piv, L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_colmap, L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_part, kRedBlocks));
+      }
       FSIMG_CHK(dalloc(h, &L.ct0, L.n));
       FSIMG_CHK(dalloc(h, &L.ct1, L.n));
       if (mixed) {
@@ -676,7 +675,8 @@ fsimg_status fsimg_hier_info(const fsimg_hier *h, int level, fsimg_level_info *o
   size_t bytes = 0;
   const void *ptrs[] = {L.rowptr, L.colind, L.vals64, L.vals32, L.mask, L.pnodes, L.inv64, L.inv32,
                         L.gptr, L.gidx, L.scale64, L.scale32, L.r64, L.x64, L.d64, L.Y64,
-                        L.r32, L.x32, L.d32, L.Y32, L.cinv, L.ct0, L.ct1, L.cfree, L.cidx};
+                        L.r32, L.x32, L.d32, L.Y32, L.cinv, L.ct0, L.ct1, L.cfree, L.cidx,
+                        L.gj_a, L.gj_rowk, L.gj_colk, L.gj_piv, L.gj_colmap, L.gj_part};
   for (const void *p : ptrs)
     for (const auto &a : h->allocs)
       if (p && a.first == p) bytes += a.second;
@@ -735,16 +735,10 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
     h->factored = true;
     return FSIMG_OK;
   }
-  double *a = nullptr, *rowk = nullptr, *colk = nullptr, *part = nullptr;
-  int *piv = nullptr, *colmap = nullptr;
+  double *a = C.gj_a, *rowk = C.gj_rowk, *colk = C.gj_colk, *part = C.gj_part;
+  int *piv = C.gj_piv, *colmap = C.gj_colmap;
   fsimg_status st = FSIMG_OK;
   do {
-    if ((st = dalloc(h, &a, (size_t)n * n)) != FSIMG_OK) break;
-    if ((st = dalloc(h, &rowk, n)) != FSIMG_OK) break;
-    if ((st = dalloc(h, &colk, n)) != FSIMG_OK) break;
-    if ((st = dalloc(h, &piv, n)) != FSIMG_OK) break;
-    if ((st = dalloc(h, &colmap, n)) != FSIMG_OK) break;
-    if ((st = dalloc(h, &part, kRedBlocks)) != FSIMG_OK) break;
     launch_fill<double>(a, n * n, 0.0, s);
     launch_densify(C, a, s);
     launch_absmax(a, n * n, part, s);
@@ -770,7 +764,6 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
       st = fail(FSIMG_ERR_SINGULAR, "singular coarse matrix (level " + std::to_string(nlev - 1) +
                                         ", pivot column " + std::to_string(h->hstatus[1]) + ")");
   } while (0);
-  dfree(h, a); dfree(h, rowk); dfree(h, colk); dfree(h, piv); dfree(h, colmap); dfree(h, part);
   if (st != FSIMG_OK) return st;
   h->factored = true;
   return FSIMG_OK;

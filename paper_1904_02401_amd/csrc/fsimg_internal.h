@@ -62,6 +62,10 @@ struct DevLevel {
   int32_t *cidx = nullptr;              // [n] dof -> free index or -1
   double *cinv = nullptr;               // [nfree*nfree]
   double *ct0 = nullptr, *ct1 = nullptr;  // FP64 coarse work vectors (mixed mode casts)
+  // Gauss-Jordan workspace of the coarse factorisation, allocated with the
+  // hierarchy so that refactoring never allocates
+  double *gj_a = nullptr, *gj_rowk = nullptr, *gj_colk = nullptr, *gj_part = nullptr;
+  int *gj_piv = nullptr, *gj_colmap = nullptr;
 };
 
 // ------------------------------------------------- batched execution

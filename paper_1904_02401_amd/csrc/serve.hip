@@ -334,6 +334,14 @@ fsimg_status fsimg_server_result(fsimg_server *S, int64_t id, double *xm, double
   return set_error(FSIMG_ERR_STATE, "request not started");
 }
 
+fsimg_status fsimg_server_request_status(fsimg_server *S, int64_t id, int *status) {
+  if (!S || !status) return set_error(FSIMG_ERR_ARG, "null server or status");
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return set_error(FSIMG_ERR_ARG, "unknown request id");
+  *status = it->second->status;
+  return FSIMG_OK;
+}
+
 fsimg_status fsimg_server_release(fsimg_server *S, int64_t id) {
   if (!S) return set_error(FSIMG_ERR_ARG, "null server");
   auto it = S->all.find(id);

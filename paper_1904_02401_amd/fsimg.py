@@ -112,6 +112,7 @@ _SIGS = {
     "fsimg_server_step": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "fsimg_server_poll": (_I, [_P, _P, _P, _P, _I, ctypes.POINTER(_I)]),
     "fsimg_server_result": (_I, [_P, _I64, _P, _P]),
+    "fsimg_server_request_status": (_I, [_P, _I64, ctypes.POINTER(_I)]),
     "fsimg_server_release": (_I, [_P, _I64]),
     "fsimg_hier_tune": (_I, [_P, _I, _P]),
     "fsimg_tune_set": (_I, [_P, _I, _I, _I, _I64, _I]),
@@ -391,6 +392,12 @@ def fsimg_server_result(srv, rid: int, n_mom: int, n_ale: int):
     xa = np.zeros(n_ale)
     _check(load().fsimg_server_result(srv, rid, xm.ctypes.data, xa.ctypes.data))
     return xm, xa
+
+
+def fsimg_server_request_status(srv, rid: int) -> int:
+    st = ctypes.c_int()
+    _check(load().fsimg_server_request_status(srv, rid, ctypes.byref(st)))
+    return st.value
 
 
 def fsimg_server_release(srv, rid: int):

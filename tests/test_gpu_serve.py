@@ -121,3 +121,29 @@ def test_serve_admission_by_budget(probs):
             fsimg.fsimg_ctx_destroy(small)
     finally:
         fsimg.fsimg_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_footprint_bounds_hierarchy_and_refactor_allocates_nothing(probs, precision):
+    """Admission relies on the footprint: it must cover what a hierarchy
+    holds, and factoring (again, at every new time step) must not allocate."""
+    ctx = fsimg.fsimg_ctx_create(0)
+    try:
+        opts = fsimg.fsimg_default_opts(precision=precision)
+        for key in ((2, 16), (3, 6)):
+            data = probs[key][1]
+            for levels in (data.mom.levels, data.ale.levels):
+                need = fsimg.fsimg_hier_footprint(levels, opts)
+                h = fsimg.fsimg_hier_create(ctx, levels, opts)
+                try:
+                    held = fsimg.fsimg_ctx_bytes_in_use(ctx)
+                    assert held <= need
+                    fsimg.fsimg_factor(h)
+                    assert fsimg.fsimg_ctx_bytes_in_use(ctx) == held
+                    fsimg.fsimg_factor(h)
+                    assert fsimg.fsimg_ctx_bytes_in_use(ctx) == held
+                finally:
+                    fsimg.fsimg_hier_destroy(h)
+                assert fsimg.fsimg_ctx_bytes_in_use(ctx) == 0
+    finally:
+        fsimg.fsimg_ctx_destroy(ctx)
