@@ -410,17 +410,33 @@ def run_serving(args):
     resident in HBM, first-fit admission by footprint, continuous batching,
     mixed precision.  Latency = arrival -> last solve of the simulation.
     --rates runs a sweep of arrival rates on the same request pool."""
-    from fsigen import serve_instance
+    from fsigen import serve_request
     from paper_1904_02401_amd.problems import request_data
 
     sizes2 = (64, 80, 96, 128, 160, 192, 256)
     sizes3 = tuple(n for n in (16, 20, 24, 32, 40, 48) if n <= args.max3d)
     t0 = time.perf_counter()
+    import torch
+    pinned = []
+
+    def pin(a):
+        # momentum values are uploaded again at every change of state: keep
+        # them in page-locked host memory so that the copies run at DMA speed
+        t = torch.empty(a.shape, dtype=torch.float64, pin_memory=True)
+        t.numpy()[...] = a
+        pinned.append(t)
+        return t.numpy()
+
     pool = {}
     for d, sz in [(2, n) for n in sizes2] + [(3, n) for n in sizes3]:
-        P = serve_instance(d, n=sz, seed=sz)
-        log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels")
-        pool[(d, sz)] = (request_data(P), P.levels[0].systems["mom"].nrows * (d + 1),
+        P, states, rhs = serve_request(d, sz, seed=sz, n_states=args.n_states, n_rhs=args.n_rhs)
+        if args.n_states > 1:
+            for prob in [P] + states:
+                for lv in prob.levels:
+                    lv.systems["mom"].vals = pin(lv.systems["mom"].vals)
+        log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels, {1 + len(states)} states, "
+            f"{1 + len(rhs)} right-hand sides")
+        pool[(d, sz)] = (request_data(P, states, rhs), P.levels[0].systems["mom"].nrows * (d + 1),
                          P.levels[0].systems["ale"].nrows * d)
     log(f"serving pool of {len(pool)} simulations generated in {time.perf_counter() - t0:.1f} s")
     rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
@@ -436,11 +452,14 @@ def run_serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": ("serving: Poisson arrivals of FSI simulations, 10 time steps x 3..5 "
-                                "Newton steps (momentum + deformation + ALE solves to 1e-8), 70% 2D "
+                                "Newton steps (momentum + deformation + ALE solves to 1e-8; a new "
+                                "Jacobian state uploaded and refactored every time step, a new "
+                                "right-hand side every Newton step), 70% 2D "
                                 f"64^2..256^2, 30% 3D 16^3..{max(sizes3)}^3, mixed precision, resident "
                                 "hierarchies, first-fit admission by HBM footprint, continuous batching"),
                    "window_s": args.window, "budget_GiB": args.budget_gb,
-                   "max_active": args.max_active, **main},
+                   "max_active": args.max_active, "states_cycled": args.n_states,
+                   "rhs_cycled": args.n_rhs, **main},
     }
     if len(runs) > 1:
         out["sweep"] = runs
@@ -474,6 +493,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-active", type=int, default=0,
                     help="serving: admitted requests at most (0 = as many as fit)")
+    ap.add_argument("--n-states", type=int, default=2,
+                    help="serving: Jacobian states cycled over a request's time steps")
+    ap.add_argument("--n-rhs", type=int, default=3,
+                    help="serving: momentum right-hand sides cycled over a request's Newton steps")
     ap.add_argument("--max3d", type=int, default=48, help="serving: largest 3D mesh (cells per axis)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -6,7 +6,9 @@ right-hand sides; it contains none of the solver's arithmetic (no smoother,
 transfer, Krylov or coarse-solve code).
 """
 from .problem import (BSR, Level, Problem, PARAMS_DEFAULT, build_native, graded_axis,
-                      make_problem, make_level, config_problem, batch_instance, serve_instance)
+                      make_problem, make_level, config_problem, batch_instance, serve_instance,
+                      serve_request)
 
 __all__ = ["BSR", "Level", "Problem", "PARAMS_DEFAULT", "build_native", "graded_axis",
-           "make_problem", "make_level", "config_problem", "batch_instance", "serve_instance"]
+           "make_problem", "make_level", "config_problem", "batch_instance", "serve_instance",
+           "serve_request"]

@@ -366,9 +366,11 @@ def _bsr_apply_scalar(m: BSR, x: np.ndarray) -> np.ndarray:
 
 
 def make_problem(dim: int, n_fine: int, nlev: int, solid_box, seed: int = 0, params=None,
-                 systems=("mom", "ale", "mass")) -> Problem:
+                 systems=("mom", "ale", "mass"), extra_rhs: int = 0) -> Problem:
     """Seeded synthetic Newton-step problem on [0,1]^dim with n_fine cells per
-    axis on the finest of nlev levels (level 0 = finest)."""
+    axis on the finest of nlev levels (level 0 = finest).  extra_rhs further
+    momentum right-hand sides (same recipe, drawn after the others) go to
+    rhs["mom_more"]."""
     p = dict(PARAMS_DEFAULT)
     if params:
         p.update(params)
@@ -408,6 +410,13 @@ def make_problem(dim: int, n_fine: int, nlev: int, solid_box, seed: int = 0, par
         b = _bsr_apply_scalar(sm, xi).ravel()
         b[fine.systems["ale"].dirichlet.astype(bool)] = 0.0
         rhs["ale"] = b / np.linalg.norm(b)
+    if extra_rhs and "mom" in systems:
+        rhs["mom_more"] = []
+        for _ in range(extra_rhs):
+            xi = rng.standard_normal((nn, dim + 1))
+            b = _bsr_apply_scalar(sm, xi).ravel()
+            b[fine.systems["mom"].dirichlet.astype(bool)] = 0.0
+            rhs["mom_more"].append(b / np.linalg.norm(b))
     return Problem(dim=dim, params=p, seed=seed, levels=levels, rhs=rhs, solid_box=solid_box,
                    **fine_state)
 
@@ -457,13 +466,31 @@ def serve_instance(dim: int, n: int, seed: int = 0) -> Problem:
     """One simulation of the serving workload: the 2D or 3D box configuration
     with n cells per axis, coarsened while the coarsest level keeps at least
     3 cells per axis (4 in 2D), momentum and ALE systems."""
+    return make_problem(dim, n, _serve_levels(dim, n), SOLID_2D if dim == 2 else SOLID_3D,
+                        seed=seed, systems=("mom", "ale"))
+
+
+def _serve_levels(dim: int, n: int) -> int:
     coarse, nlev = n, 1
     lim = 4 if dim == 2 else 3
     while coarse % 2 == 0 and coarse // 2 >= lim:
         coarse //= 2
         nlev += 1
-    return make_problem(dim, n, nlev, SOLID_2D if dim == 2 else SOLID_3D, seed=seed,
-                        systems=("mom", "ale"))
+    return nlev
+
+
+def serve_request(dim: int, n: int, seed: int = 0, n_states: int = 2, n_rhs: int = 3):
+    """A serving request's data: the simulation of serve_instance (state 0,
+    momentum + ALE, first momentum right-hand side), n_states - 1 further
+    seeded states on the same mesh (momentum only: the Jacobian of later time
+    steps) and n_rhs - 1 further momentum right-hand sides (later Newton
+    steps).  Returns (problem, [state problems], [right-hand sides])."""
+    nlev = _serve_levels(dim, n)
+    box = SOLID_2D if dim == 2 else SOLID_3D
+    P = make_problem(dim, n, nlev, box, seed=seed, systems=("mom", "ale"), extra_rhs=n_rhs - 1)
+    states = [make_problem(dim, n, nlev, box, seed=seed + 7919 * s, systems=("mom",))
+              for s in range(1, n_states)]
+    return P, states, list(P.rhs.get("mom_more", []))
 
 
 def config_problem(name: str, seed: int = 0, **kw) -> Problem:

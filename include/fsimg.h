@@ -264,9 +264,14 @@ fsimg_status fsimg_tune_load(fsimg_ctx *ctx, const char *path);
    A request is one FSI simulation: time_steps time steps, newton_steps[t]
    Newton steps in step t; every Newton step is the linear solve of the
    reduced Jacobian (Sec. 4.2): momentum solve, condensed deformation update,
-   ALE solve.  The Jacobian is refactored at the start of every time step
-   (the paper reassembles about once per time step, Sec. 5.5.2); the ALE
-   matrix is factored once per request.  Requests wait in a queue until their
+   ALE solve.  Time step t uses momentum state t % n_states (state 0: the
+   values of `mom`; state s >= 1: state_vals[(s - 1) * nlev + l] for level
+   l, same pattern); a time step with another state than the previous one
+   uploads its values and refactors (the paper reassembles about once per
+   time step, Sec. 5.5.2).  Newton step i of the request (counted over all
+   time steps) solves the momentum system with right-hand side i % n_rhs
+   (0: b_mom; j >= 1: rhs_mom[j - 1]).  The ALE matrix is fixed per request
+   and factored once.  Requests wait in a queue until their
    hierarchies fit in the context's HBM budget (first fit in arrival order);
    admitted requests keep their hierarchies resident, and every server step
    solves the current Newton step of all admitted requests together (one
@@ -282,14 +287,20 @@ typedef struct {
   const int *newton_steps;          /* [time_steps] */
   double k, theta;                  /* time step and theta of the deformation update */
   double arrival;                   /* arrival time on the server clock (s) */
+  int n_states;                     /* momentum states cycled over time steps (>= 1) */
+  const double *const *state_vals;  /* [(n_states - 1) * nlev] or NULL */
+  int n_rhs;                        /* momentum right-hand sides cycled over Newton steps (>= 1) */
+  const double *const *rhs_mom;     /* [n_rhs - 1] or NULL */
 } fsimg_request;
 
 typedef struct fsimg_server fsimg_server;
 
 /* opts: solver options of every hierarchy the server creates; max_active:
-   admitted requests at most (0 = no limit).  Host arrays of submitted
-   requests are read at admission: the caller keeps them valid until the
-   request is admitted (fsimg_server_step reports admissions). */
+   admitted requests at most (0 = no limit).  Host arrays of a submitted
+   request are read at admission (the descriptors, right-hand sides, node
+   mask) and, with n_states > 1, the momentum values of every state again at
+   each change of state: the caller keeps them valid until the request
+   completes (fsimg_server_poll reports completions). */
 fsimg_status fsimg_server_create(fsimg_ctx *ctx, const fsimg_opts *opts, int max_active,
                                  fsimg_server **out);
 void fsimg_server_destroy(fsimg_server *srv);

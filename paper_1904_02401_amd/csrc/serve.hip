@@ -27,6 +27,10 @@ struct Req {
   uint8_t *mask = nullptr;
   size_t vec_bytes = 0;
   size_t reserve = 0;  // batch plan allowance held while running
+  std::vector<const double *> states;  // [(n_states - 1) * nlev] host value arrays
+  std::vector<const double *> rhs;     // [n_rhs] host right-hand sides (b_mom first)
+  int mstate = 0;                      // momentum state held by hm
+  int64_t newton_done = 0;             // Newton steps completed over all time steps
   int t = 0, nstep = 0, dim = 0, bm = 0, ba = 0;
   int64_t nnodes = 0, nm = 0, na = 0;
   double admitted = -1.0, finished = -1.0;
@@ -82,7 +86,8 @@ size_t request_bytes(const fsimg_server *S, const Req *q, fsimg_status *st) {
   size_t fm = 0, fa = 0;
   *st = fsimg_hier_footprint(q->r.mom, q->r.nlev, &S->opts, &fm);
   if (*st == FSIMG_OK) *st = fsimg_hier_footprint(q->r.ale, q->r.nlev, &S->opts, &fa);
-  return fm + fa + (size_t)(2 * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes + plan_reserve();
+  return fm + fa + (size_t)((q->rhs.size() + 1) * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes +
+         plan_reserve();
 }
 
 // create hierarchies, factor, upload vectors; false if it does not fit now
@@ -95,12 +100,13 @@ fsimg_status admit(fsimg_server *S, Req *q, hipStream_t s) {
     release_device(S, q);
     return st;
   }
-  const size_t bytes = (size_t)(2 * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes;
+  const size_t nr = q->rhs.size();
+  const size_t bytes = (size_t)((nr + 1) * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes;
   if (S->ctx->budget && S->ctx->in_use + bytes > S->ctx->budget) {
     release_device(S, q);
     return set_error(FSIMG_ERR_BUDGET, "request vectors exceed the budget");
   }
-  bool ok = hipMalloc(&q->b_mom, q->nm * 8) == hipSuccess &&
+  bool ok = hipMalloc(&q->b_mom, nr * q->nm * 8) == hipSuccess &&
             hipMalloc(&q->x_mom, q->nm * 8) == hipSuccess &&
             hipMalloc(&q->b_ale, q->na * 8) == hipSuccess &&
             hipMalloc(&q->x_ale, q->na * 8) == hipSuccess &&
@@ -114,7 +120,10 @@ fsimg_status admit(fsimg_server *S, Req *q, hipStream_t s) {
   S->ctx->in_use += bytes;
   q->reserve = plan_reserve();
   S->reserved += q->reserve;
-  ok = hipMemcpyAsync(q->b_mom, q->r.b_mom, q->nm * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+  for (size_t j = 0; j < nr && ok; ++j)
+    ok = hipMemcpyAsync(q->b_mom + j * q->nm, q->rhs[j], q->nm * 8, hipMemcpyHostToDevice, s) ==
+         hipSuccess;
+  ok = ok &&
        hipMemcpyAsync(q->b_ale, q->r.b_ale, q->na * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
        hipMemcpyAsync(q->mask, q->r.node_solid, q->nnodes, hipMemcpyHostToDevice, s) == hipSuccess &&
        hipStreamSynchronize(s) == hipSuccess;
@@ -184,6 +193,25 @@ fsimg_status fsimg_server_submit(fsimg_server *S, const fsimg_request *r, int64_
       return set_error(FSIMG_ERR_ARG, "every time step needs at least one Newton step");
     }
   q->r.newton_steps = q->newton.data();
+  if (r->n_states < 1 || r->n_rhs < 1 || (r->n_states > 1 && !r->state_vals) ||
+      (r->n_rhs > 1 && !r->rhs_mom)) {
+    delete q;
+    return set_error(FSIMG_ERR_ARG, "n_states and n_rhs must be >= 1, with their arrays");
+  }
+  if (r->n_states > 1)
+    q->states.assign(r->state_vals, r->state_vals + (size_t)(r->n_states - 1) * r->nlev);
+  q->rhs.push_back(r->b_mom);
+  for (int j = 1; j < r->n_rhs; ++j) q->rhs.push_back(r->rhs_mom[j - 1]);
+  for (const double *p : q->states)
+    if (!p) {
+      delete q;
+      return set_error(FSIMG_ERR_ARG, "null state values");
+    }
+  for (const double *p : q->rhs)
+    if (!p) {
+      delete q;
+      return set_error(FSIMG_ERR_ARG, "null right-hand side");
+    }
   q->dim = m0.dim;
   q->bm = m0.block;
   q->ba = a0.block;
@@ -251,7 +279,7 @@ fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, vo
       for (Req *q : group) {
         launch_fill<double>(q->x_mom, q->nm, 0.0, s);
         hs.push_back(q->hm);
-        bs.push_back(q->b_mom);
+        bs.push_back(q->b_mom + (size_t)(q->newton_done % (int64_t)q->rhs.size()) * q->nm);
         xs.push_back(q->x_mom);
       }
       std::vector<fsimg_stats> st(group.size());
@@ -276,13 +304,25 @@ fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, vo
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(FSIMG_ERR_HIP, "server step sync failed");
     std::vector<Req *> still;
     for (Req *q : S->running) {
+      ++q->newton_done;
       if (++q->nstep == q->newton[q->t]) {
         q->nstep = 0;
         if (++q->t == q->r.time_steps) {
           finish(S, q, s);
           continue;
         }
-        fsimg_status st = fsimg_factor(q->hm, s);  // a new time step: new Jacobian
+        // a new time step: its Jacobian (another state: upload its values), refactored
+        fsimg_status st = FSIMG_OK;
+        const int want = q->t % q->r.n_states;
+        if (want != q->mstate) {
+          for (int l = 0; l < q->r.nlev && st == FSIMG_OK; ++l) {
+            const double *v = want == 0 ? q->r.mom[l].vals
+                                        : q->states[(size_t)(want - 1) * q->r.nlev + l];
+            st = fsimg_hier_update_values(q->hm, l, v, 0, s);
+          }
+          q->mstate = want;
+        }
+        if (st == FSIMG_OK) st = fsimg_factor(q->hm, s);
         if (st != FSIMG_OK) {
           q->status = st;
           finish(S, q, s);

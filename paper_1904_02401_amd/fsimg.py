@@ -65,7 +65,9 @@ class fsimg_request(ctypes.Structure):
                 ("ale", ctypes.POINTER(fsimg_level_desc)), ("b_mom", ctypes.c_void_p),
                 ("b_ale", ctypes.c_void_p), ("node_solid", ctypes.c_void_p),
                 ("time_steps", ctypes.c_int), ("newton_steps", ctypes.c_void_p),
-                ("k", ctypes.c_double), ("theta", ctypes.c_double), ("arrival", ctypes.c_double)]
+                ("k", ctypes.c_double), ("theta", ctypes.c_double), ("arrival", ctypes.c_double),
+                ("n_states", ctypes.c_int), ("state_vals", ctypes.POINTER(ctypes.c_void_p)),
+                ("n_rhs", ctypes.c_int), ("rhs_mom", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class fsimg_level_info(ctypes.Structure):
@@ -332,10 +334,14 @@ def fsimg_patch_inverse(h, level: int, patch: int, stream=None):
 # ------------------------------------------------------------------ serving
 class RequestData:
     """Host data of one simulation request: momentum / ALE level descriptors,
-    right-hand sides, interface/solid node mask.  The arrays must stay alive
-    until the request is admitted; one RequestData may back many requests."""
+    further momentum states (per state, one value array per level, same
+    pattern), momentum right-hand sides (the first is b_mom), the ALE
+    right-hand side and the interface/solid node mask.  The arrays must stay
+    alive until the request completes; one RequestData may back many
+    requests."""
 
-    def __init__(self, mom_levels, ale_levels, b_mom, b_ale, node_solid, k, theta):
+    def __init__(self, mom_levels, ale_levels, b_mom, b_ale, node_solid, k, theta,
+                 states=(), rhs=()):
         self.mom = LevelDescs(mom_levels)
         self.ale = LevelDescs(ale_levels)
         self.b_mom = np.ascontiguousarray(b_mom, dtype=np.float64)
@@ -343,6 +349,14 @@ class RequestData:
         self.node_solid = np.ascontiguousarray(node_solid, dtype=np.uint8)
         self.k, self.theta = float(k), float(theta)
         self.nlev = self.mom.n
+        self.states = [[np.ascontiguousarray(v, dtype=np.float64) for v in st] for st in states]
+        for st in self.states:
+            if len(st) != self.nlev:
+                raise ValueError("every state needs one value array per level")
+        self.rhs = [np.ascontiguousarray(b, dtype=np.float64) for b in rhs]
+        flat = [v.ctypes.data for st in self.states for v in st]
+        self.state_ptrs = (ctypes.c_void_p * max(len(flat), 1))(*flat)
+        self.rhs_ptrs = (ctypes.c_void_p * max(len(self.rhs), 1))(*[b.ctypes.data for b in self.rhs])
 
 
 def fsimg_server_create(ctx, opts, max_active: int = 0):
@@ -364,7 +378,9 @@ def fsimg_server_submit(srv, data: RequestData, newton_steps, arrival: float) ->
     req = fsimg_request(nlev=data.nlev, mom=data.mom.arr, ale=data.ale.arr,
                         b_mom=data.b_mom.ctypes.data, b_ale=data.b_ale.ctypes.data,
                         node_solid=data.node_solid.ctypes.data, time_steps=len(ns),
-                        newton_steps=ns.ctypes.data, k=data.k, theta=data.theta, arrival=arrival)
+                        newton_steps=ns.ctypes.data, k=data.k, theta=data.theta, arrival=arrival,
+                        n_states=1 + len(data.states), state_vals=data.state_ptrs,
+                        n_rhs=1 + len(data.rhs), rhs_mom=data.rhs_ptrs)
     rid = ctypes.c_int64()
     _check(load().fsimg_server_submit(srv, ctypes.byref(req), ctypes.byref(rid)))
     return rid.value

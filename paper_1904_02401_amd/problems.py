@@ -14,10 +14,14 @@ def level_dicts(problem, system: str, with_class: bool = True):
     return out
 
 
-def request_data(problem):
-    """fsimg.RequestData (momentum + ALE) of an fsigen.Problem."""
+def request_data(problem, states=(), rhs=()):
+    """fsimg.RequestData (momentum + ALE) of an fsigen.Problem; `states` are
+    further problems on the same mesh whose momentum values are cycled over
+    the time steps, `rhs` further momentum right-hand sides cycled over the
+    Newton steps."""
     from .fsimg import RequestData
     fine = problem.levels[0]
+    vals = [[lv.systems["mom"].vals for lv in st.levels] for st in states]
     return RequestData(level_dicts(problem, "mom"), level_dicts(problem, "ale"), problem.rhs["mom"],
                        problem.rhs["ale"], fine.node_solid, problem.params["k"],
-                       problem.params["theta"])
+                       problem.params["theta"], states=vals, rhs=list(rhs))

@@ -1,11 +1,13 @@
 """Serving loop: requests of mixed dimension and depth join and leave a
-continuous batch; each result must equal the same request served alone
-(bitwise), and admission must respect the HBM budget."""
+continuous batch, cycling Jacobian states over time steps and right-hand
+sides over Newton steps; each result must equal the same request served
+alone (bitwise) and solve the system of its last Newton step, and admission
+must respect the HBM budget."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from fsigen import serve_instance
+from fsigen import serve_request
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -24,8 +26,8 @@ def probs():
     cache = {}
     for d, n, _ in MIX:
         if (d, n) not in cache:
-            P = serve_instance(d, n, seed=n)
-            cache[(d, n)] = (P, request_data(P))
+            P, states, rhs = serve_request(d, n, seed=n, n_states=2, n_rhs=3)
+            cache[(d, n)] = (P, request_data(P, states, rhs), states, rhs)
     return cache
 
 
@@ -34,13 +36,22 @@ def _sizes(P):
     return m.nrows * m.b, a.nrows * a.b
 
 
-def _mom_res(P, x):
-    m = P.levels[0].systems["mom"]
+def _mom_res(P, x, state=None, b=None):
+    m = (state or P).levels[0].systems["mom"]
+    b = P.rhs["mom"] if b is None else b
     n = m.nrows * m.b
     A = sp.bsr_matrix((m.vals, m.colind, m.rowptr), shape=(n, n))
-    r = P.rhs["mom"] - A @ x
+    r = b - A @ x
     r[m.dirichlet.astype(bool)] = 0.0
-    return np.linalg.norm(r) / np.linalg.norm(P.rhs["mom"])
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def _last_system(entry, ns):
+    """(state problem or None, right-hand side) of a request's last Newton step."""
+    P, _, states, rhs = entry
+    st = (len(ns) - 1) % (1 + len(states))
+    j = (int(np.sum(ns)) - 1) % (1 + len(rhs))
+    return (None if st == 0 else states[st - 1]), (P.rhs["mom"] if j == 0 else rhs[j - 1])
 
 
 def _serve(ctx, probs, items, max_active=0, max_steps=200):
@@ -77,7 +88,8 @@ def test_serve_mix_equals_alone(probs):
         assert len(trace) == max(sum(ns) for _, _, ns in MIX)
         for rid, (d, n, ns) in zip(ids, MIX):
             P = probs[(d, n)][0]
-            assert _mom_res(P, mix[rid][0]) <= 1e-8 * 1.01
+            st, b = _last_system(probs[(d, n)], ns)
+            assert _mom_res(P, mix[rid][0], st, b) <= 1e-8 * 1.01
             assert np.all(np.isfinite(mix[rid][1]))
             ids1, alone, _ = _serve(ctx, probs, [(d, n, ns)])
             np.testing.assert_array_equal(mix[rid][0], alone[ids1[0]][0])
@@ -100,8 +112,9 @@ def test_serve_admission_by_budget(probs):
         assert trace[0] == (1, 2), "only one request fits at first"
         assert max(a for a, _ in trace) == 1
         P = probs[(2, 16)][0]
-        for rid in ids:
-            assert _mom_res(P, out[rid][0]) <= 1e-8 * 1.01
+        for rid, (_, _, ns) in zip(ids, items):
+            st, b = _last_system(probs[(2, 16)], ns)
+            assert _mom_res(P, out[rid][0], st, b) <= 1e-8 * 1.01
         assert fsimg.fsimg_ctx_bytes_in_use(ctx) == 0
         # a request larger than the whole budget fails, the server keeps going
         small = fsimg.fsimg_ctx_create(0, 1 << 20)
