@@ -79,6 +79,14 @@ typedef enum { FSIMG_VANKA_GATHER = 0, FSIMG_VANKA_PARITY = 1, FSIMG_VANKA_GREED
    PLAIN adds them as printed; MULT divides the sum at each dof by the number
    of element patches that contain it. */
 typedef enum { FSIMG_WEIGHT_PLAIN = 0, FSIMG_WEIGHT_MULT = 1 } fsimg_weighting;
+/* Vanka patch shapes (Sec. 5.5.1, the patch-size study).  ELEMENT: one patch
+   per element (3^d nodes).  BLOCK: the 5^d nodes of a 2 x 2 (x 2) block of
+   elements at even element coordinates form one patch -- in 2D every such
+   block, in 3D only blocks whose eight elements all have a nonzero
+   cell_class (solid); elements outside blocks keep one-element patches.
+   With MULT weighting a dof's correction is divided by the number of
+   patches containing it.  BLOCK needs the GATHER schedule. */
+typedef enum { FSIMG_PATCH_ELEMENT = 0, FSIMG_PATCH_BLOCK = 1 } fsimg_patches;
 
 /* One multigrid level; level 0 = finest.  Host arrays, copied. */
 typedef struct {
@@ -108,6 +116,7 @@ typedef struct {
   int graphs;          /* 1: replay each FGMRES iteration (V-cycle, A z, Gram-Schmidt) as a
                           HIP graph captured once per batch composition; 0: launch eagerly.
                           Results are identical either way; profiling runs launch eagerly */
+  int vanka_patches;   /* fsimg_patches */
 } fsimg_opts;
 
 typedef struct {

@@ -33,16 +33,20 @@ class MGLevel:
 
 
 class Hierarchy:
-    def __init__(self, mats, cells_per_level, omega=0.8, nu_pre=2, nu_post=2, weighting="plain"):
+    def __init__(self, mats, cells_per_level, omega=0.8, nu_pre=2, nu_post=2, weighting="plain",
+                 patches="element", cell_solid=None):
         """mats: per-level block-CSR systems (finest first), cells_per_level:
-        cells per axis on each level."""
+        cells per axis on each level; patches "element" or "block" (2 x 2 (x 2)
+        element blocks, in 3D solid only: cell_solid per level)."""
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.levels = []
         L = len(mats)
         for l, (m, cells) in enumerate(zip(mats, cells_per_level)):
             lev = MGLevel(A=to_csr(m), mask=m.dirichlet.astype(bool), cells=tuple(cells))
             if l < L - 1:
-                lev.vanka = VankaData.build(m, cells, omega=omega, weighting=weighting)
+                lev.vanka = VankaData.build(m, cells, omega=omega, weighting=weighting,
+                                            patches=patches,
+                                            cell_solid=None if cell_solid is None else cell_solid[l])
                 lev.P = prolongation(tuple(cells_per_level[l + 1]), m.b)
             else:
                 lev.lu = sla.lu_factor(lev.A.toarray())

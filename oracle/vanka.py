@@ -20,14 +20,19 @@ from .patches import patch_dofs
 
 
 def local_matrices(m, cells, patches=None) -> np.ndarray:
-    """A_i = R_i A R_i^T for element patches: [npatch, n_p, n_p] (dense, FP64).
-
-    Looks every (row node, column node) block up in the block-CSR structure;
-    a block absent from the structure is zero."""
+    """A_i = R_i A R_i^T for element patches: [npatch, n_p, n_p] (dense, FP64)."""
     from .patches import element_patches
     nodes = element_patches(cells)
     if patches is not None:
         nodes = nodes[patches]
+    return local_matrices_nodes(m, nodes)
+
+
+def local_matrices_nodes(m, nodes) -> np.ndarray:
+    """A_i = R_i A R_i^T for patches given by their node lists [npatch, nl].
+
+    Looks every (row node, column node) block up in the block-CSR structure;
+    a block absent from the structure is zero."""
     b = m.b
     n = m.rowptr.shape[0] - 1
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(m.rowptr))
@@ -66,29 +71,55 @@ class VankaData:
     omega: float
 
     @staticmethod
-    def build(m, cells, omega: float = 0.8, weighting: str = "plain") -> "VankaData":
-        dofs = patch_dofs(cells, m.b)
+    def build(m, cells, omega: float = 0.8, weighting: str = "plain", patches: str = "element",
+              cell_solid=None):
+        """patches="element": one VankaData of the one-element patches.
+        patches="block": a list of VankaData, one per patch size (2 x 2 (x 2)
+        element blocks, see patches.block_patch_groups), sharing one scale:
+        the multiplicity counts the patches of every group."""
         n = (m.rowptr.shape[0] - 1) * m.b
+        if patches == "element":
+            groups = [(patch_dofs(cells, m.b), None)]
+        elif patches == "block":
+            from .patches import block_patch_groups
+            groups = []
+            for nodes, _ in block_patch_groups(cells, cell_solid):
+                if nodes.shape[0]:
+                    dofs = (nodes[:, :, None] * m.b + np.arange(m.b)).reshape(nodes.shape[0], -1)
+                    groups.append((dofs, nodes))
+        else:
+            raise ValueError(patches)
         if weighting == "plain":
             scale = np.ones(n)
         elif weighting == "mult":
-            mult = np.bincount(dofs.ravel(), minlength=n).astype(np.float64)
+            mult = np.zeros(n)
+            for dofs, _ in groups:
+                mult += np.bincount(dofs.ravel(), minlength=n)
             scale = 1.0 / np.maximum(mult, 1.0)
         else:
             raise ValueError(weighting)
-        return VankaData(dofs=dofs, inv=local_inverses(m, cells), scale=scale, omega=omega)
+        if patches == "element":
+            return VankaData(dofs=groups[0][0], inv=local_inverses(m, cells), scale=scale, omega=omega)
+        return [VankaData(dofs=dofs, inv=np.linalg.inv(local_matrices_nodes(m, nodes)), scale=scale,
+                          omega=omega) for dofs, nodes in groups]
 
 
-def vanka_sweep(A, b: np.ndarray, x: np.ndarray, V: VankaData, mask: np.ndarray,
+def vanka_sweep(A, b: np.ndarray, x: np.ndarray, V, mask: np.ndarray,
                 d: np.ndarray = None) -> np.ndarray:
-    """One additive Vanka step; returns the new x.  ``d`` may pass a residual
-    b - A x that is already known.  Identity rows keep their value."""
+    """One additive Vanka step; returns the new x.  ``V`` is a VankaData or a
+    list of them (patch groups of different sizes, one shared scale).  ``d``
+    may pass a residual b - A x that is already known.  Identity rows keep
+    their value."""
     if d is None:
         d = b - A @ x
     d = d.copy()
     d[mask] = 0.0
-    loc = np.matmul(V.inv, d[V.dofs][:, :, None])[:, :, 0]  # A_i^{-1} R_i d
-    corr = np.bincount(V.dofs.ravel(), weights=loc.ravel(), minlength=x.shape[0])
-    xn = x + V.omega * V.scale * corr
+    groups = V if isinstance(V, list) else [V]
+    corr = np.zeros(x.shape[0])
+    for g in groups:
+        loc = np.matmul(g.inv, d[g.dofs][:, :, None])[:, :, 0]  # A_i^{-1} R_i d
+        corr += np.bincount(g.dofs.ravel(), weights=loc.ravel(), minlength=x.shape[0])
+    V0 = groups[0]
+    xn = x + V0.omega * V0.scale * corr
     xn[mask] = x[mask]
     return xn

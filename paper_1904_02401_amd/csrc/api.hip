@@ -121,6 +121,10 @@ struct PatchPlan {
   std::vector<int64_t> colour_start;   // ranges of equal colour (schedule != GATHER)
   std::vector<int32_t> nodes;          // [npatch*nl]
   std::vector<int32_t> gptr, gidx;
+  // block patches (second group): first element of each active block, nodes
+  int blk_nl = 0;
+  std::vector<int64_t> blk_first;
+  std::vector<int32_t> blk_nodes;      // [nblk*blk_nl]
 };
 
 void element_nodes(const fsimg_level_desc &L, int64_t e, int32_t *out) {
@@ -137,27 +141,85 @@ void element_nodes(const fsimg_level_desc &L, int64_t e, int32_t *out) {
   }
 }
 
+// nodes of the 2 x 2 (x 2) element block whose first element has coordinates
+// lo: the 5^d nodes of its node box, lexicographic (x fastest)
+void block_nodes(const fsimg_level_desc &L, const int lo[3], int32_t *out) {
+  const int nn[3] = {2 * L.cells[0] + 1, 2 * L.cells[1] + 1, 2 * L.cells[2] + 1};
+  const int nl = L.dim == 2 ? 25 : 125;
+  for (int i = 0; i < nl; ++i) {
+    const int la[3] = {i % 5, (i / 5) % 5, i / 25};
+    int64_t g = 0, stride = 1;
+    for (int a = 0; a < L.dim; ++a) { g += stride * (2 * lo[a] + la[a]); stride *= nn[a]; }
+    out[i] = (int32_t)g;
+  }
+}
+
+// node -> Y slots of the patches containing it, in patch order: element
+// patches (slot p*nl + local node), then block patches (slot npatch*nl +
+// q*nlb + local node)
 void build_gather(const fsimg_level_desc &L, int nl, const std::vector<int32_t> &nodes, int64_t npatch,
-                  std::vector<int32_t> &gptr, std::vector<int32_t> &gidx) {
+                  std::vector<int32_t> &gptr, std::vector<int32_t> &gidx, int nlb = 0,
+                  const std::vector<int32_t> *bnodes = nullptr) {
+  const int64_t nblk = (bnodes && nlb) ? (int64_t)bnodes->size() / nlb : 0;
   gptr.assign(L.nrows + 1, 0);
   for (int64_t p = 0; p < npatch; ++p)
     for (int l = 0; l < nl; ++l) gptr[nodes[p * nl + l] + 1]++;
+  for (int64_t q = 0; q < nblk; ++q)
+    for (int l = 0; l < nlb; ++l) gptr[(*bnodes)[q * nlb + l] + 1]++;
   for (int64_t i = 0; i < L.nrows; ++i) gptr[i + 1] += gptr[i];
   gidx.assign(gptr[L.nrows], 0);
   std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
   for (int64_t p = 0; p < npatch; ++p)
     for (int l = 0; l < nl; ++l) gidx[fill[nodes[p * nl + l]]++] = (int32_t)(p * nl + l);
+  for (int64_t q = 0; q < nblk; ++q)
+    for (int l = 0; l < nlb; ++l)
+      gidx[fill[(*bnodes)[q * nlb + l]]++] = (int32_t)(npatch * nl + q * nlb + l);
 }
 
 fsimg_status plan_patches(const fsimg_level_desc &L, int schedule, const uint8_t *cell_class,
-                          PatchPlan &P) {
+                          PatchPlan &P, int patches = FSIMG_PATCH_ELEMENT) {
   const int nl = L.dim == 2 ? 9 : 27;
   const int b = L.block;
   int64_t ncell = 1;
   for (int a = 0; a < L.dim; ++a) ncell *= L.cells[a];
+  std::vector<char> covered(ncell, 0);
+  if (patches == FSIMG_PATCH_BLOCK) {
+    // 2 x 2 (x 2) blocks at even element coordinates; in 3D only all-solid ones
+    const int nlb = L.dim == 2 ? 25 : 125;
+    P.blk_nl = nlb;
+    const int nb[3] = {L.cells[0] / 2, L.dim > 1 ? L.cells[1] / 2 : 1,
+                       L.dim > 2 ? L.cells[2] / 2 : 1};
+    std::vector<int32_t> bn(nlb);
+    for (int k = 0; k < (L.dim > 2 ? nb[2] : 1); ++k)
+      for (int j = 0; j < nb[1]; ++j)
+        for (int i = 0; i < nb[0]; ++i) {
+          const int lo[3] = {2 * i, 2 * j, 2 * k};
+          int64_t mem[8];
+          int nm = 0;
+          for (int dz = 0; dz < (L.dim > 2 ? 2 : 1); ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+              for (int dx = 0; dx < 2; ++dx)
+                mem[nm++] = (lo[0] + dx) + (int64_t)L.cells[0] * ((lo[1] + dy) +
+                                                                 (int64_t)L.cells[1] * (lo[2] + dz));
+          bool take = true;
+          if (L.dim == 3)
+            for (int m = 0; m < nm; ++m) take = take && cell_class && cell_class[mem[m]] != 0;
+          if (!take) continue;
+          for (int m = 0; m < nm; ++m) covered[mem[m]] = 1;
+          block_nodes(L, lo, bn.data());
+          bool any = false;
+          for (int l = 0; l < nlb && !any; ++l)
+            for (int c = 0; c < b; ++c)
+              if (!L.dirichlet[(int64_t)bn[l] * b + c]) { any = true; break; }
+          if (!any) continue;
+          P.blk_first.push_back(mem[0]);
+          P.blk_nodes.insert(P.blk_nodes.end(), bn.begin(), bn.end());
+        }
+  }
   std::vector<int64_t> act;
   std::vector<int32_t> tmp(nl);
   for (int64_t e = 0; e < ncell; ++e) {
+    if (covered[e]) continue;
     element_nodes(L, e, tmp.data());
     bool any = false;
     for (int l = 0; l < nl && !any; ++l)
@@ -227,7 +289,7 @@ fsimg_status plan_patches(const fsimg_level_desc &L, int schedule, const uint8_t
   }
   P.colour_start.push_back(np_);
   if (schedule == FSIMG_VANKA_GATHER) P.colour_start = {0, np_};
-  build_gather(L, nl, P.nodes, np_, P.gptr, P.gidx);
+  build_gather(L, nl, P.nodes, np_, P.gptr, P.gidx, P.blk_nl, &P.blk_nodes);
   // validator: patches of one colour never share a node
   if (schedule != FSIMG_VANKA_GATHER) {
     std::vector<int> pc(np_);
@@ -264,7 +326,7 @@ int64_t count_free(const fsimg_level_desc &L) {
 }
 
 size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, bool coarse,
-                   const fsimg_opts &o) {
+                   const fsimg_opts &o, int64_t nblk = 0) {
   const bool mixed = o.precision == FSIMG_MIXED;
   const int b = L.block, nl = L.dim == 2 ? 9 : 27, np = nl * b;
   const int64_t n = L.nrows * b;
@@ -276,6 +338,13 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
     s += (size_t)npatch * np * npc_for(np, (int)ts) * ts;
     s += (size_t)L.nrows * ts;                       // scale
     s += (size_t)3 * n * ts + (size_t)npatch * np * ts;  // r, x, d, Y
+    if (nblk > 0) {  // block patches: nodes, inverses, corrections, factorisation scratch
+      const int nlb = L.dim == 2 ? 25 : 125, npb = nlb * b;
+      s += (size_t)nblk * nlb * 4 + (size_t)nblk * npb * npc_for(npb, (int)ts) * ts +
+           (size_t)nblk * npb * ts;
+      if (npb > 128 || nlb > 27)
+        s += (size_t)nblk * npb * npb * 8 + (size_t)nblk * npb * (8 + 8 + 4) + (size_t)nblk * 8;
+    }
   } else {
     const int64_t nf = count_free(L);
     s += (size_t)nf * nf * 8 + (size_t)(nf + n) * 4 + (size_t)2 * n * 8 + (size_t)2 * n * ts;
@@ -300,6 +369,8 @@ template <> struct Sel<double> {
   static const double *inv(const DevLevel &L) { return L.inv64; }
   static int npc(const DevLevel &L) { return L.npc64; }
   static const double *scale(const DevLevel &L) { return L.scale64; }
+  static const double *binv(const DevLevel &L) { return L.blk.inv64; }
+  static int bnpc(const DevLevel &L) { return L.blk.npc64; }
 };
 template <> struct Sel<float> {
   static float *r(DevLevel &L) { return L.r32; }
@@ -310,6 +381,8 @@ template <> struct Sel<float> {
   static const float *inv(const DevLevel &L) { return L.inv32; }
   static int npc(const DevLevel &L) { return L.npc32; }
   static const float *scale(const DevLevel &L) { return L.scale32; }
+  static const float *binv(const DevLevel &L) { return L.blk.inv32; }
+  static int bnpc(const DevLevel &L) { return L.blk.npc32; }
 };
 
 template <typename T>
@@ -334,6 +407,8 @@ void vanka_apply(fsimg_hier *h, int l, const T *d, T *x, bool assign, hipStream_
     launch_vanka_patch<T>(L, Sel<T>::inv(L), Sel<T>::npc(L), d, Sel<T>::Y(L), 0, L.npatch, false,
                           nullptr, nullptr, omega, s);
     if (prof && e1) (void)hipEventRecord(e1, s);
+    if (L.blk.npatch > 0)
+      launch_vanka_blocks<T>(L, Sel<T>::binv(L), Sel<T>::bnpc(L), d, Sel<T>::Y(L) + L.blk.yofs, s);
     launch_vanka_gather<T>(L, Sel<T>::Y(L), Sel<T>::scale(L), omega, assign, x, s);
   } else {
     if (assign) launch_fill<T>(x, L.n, T(0), s);
@@ -429,6 +504,7 @@ void fsimg_default_opts(fsimg_opts *o) {
   o->vanka_weighting = FSIMG_WEIGHT_MULT;
   o->profile = 0;
   o->graphs = 1;
+  o->vanka_patches = FSIMG_PATCH_ELEMENT;
 }
 
 fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **out) {
@@ -464,6 +540,9 @@ static fsimg_status validate_opts(const fsimg_opts *o) {
   if (o->vanka_schedule < 0 || o->vanka_schedule > 2) return fail(FSIMG_ERR_ARG, "bad schedule");
   if (o->vanka_weighting < 0 || o->vanka_weighting > 1) return fail(FSIMG_ERR_ARG, "bad weighting");
   if (o->graphs < 0 || o->graphs > 1) return fail(FSIMG_ERR_ARG, "graphs must be 0 or 1");
+  if (o->vanka_patches < 0 || o->vanka_patches > 1) return fail(FSIMG_ERR_ARG, "bad patch shape");
+  if (o->vanka_patches == FSIMG_PATCH_BLOCK && o->vanka_schedule != FSIMG_VANKA_GATHER)
+    return fail(FSIMG_ERR_ARG, "block patches need the GATHER schedule");
   return FSIMG_OK;
 }
 
@@ -475,14 +554,16 @@ fsimg_status fsimg_hier_footprint(const fsimg_level_desc *levels, int nlev, cons
   size_t s = 0;
   for (int l = 0; l < nlev; ++l) {
     const bool coarse = l == nlev - 1;
-    int64_t npatch = 0, ng = 0;
+    int64_t npatch = 0, ng = 0, nblk = 0;
     if (!coarse) {
       PatchPlan P;
-      FSIMG_TRY(plan_patches(levels[l], FSIMG_VANKA_GATHER, nullptr, P));
+      FSIMG_TRY(plan_patches(levels[l], FSIMG_VANKA_GATHER, levels[l].cell_class, P,
+                             opts->vanka_patches));
       npatch = (int64_t)P.elem.size();
       ng = (int64_t)P.gidx.size();
+      nblk = P.blk_nl ? (int64_t)P.blk_nodes.size() / P.blk_nl : 0;
     }
-    s += level_bytes(levels[l], npatch, ng, coarse, *opts);
+    s += level_bytes(levels[l], npatch, ng, coarse, *opts, nblk);
   }
   s += krylov_bytes(levels[0].nrows * levels[0].block, opts->restart);
   *bytes = s;
@@ -581,8 +662,28 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
     const bool coarse = l == nlev - 1;
     if (!coarse) {
       PatchPlan P;
-      FSIMG_CHK(plan_patches(D, opts->vanka_schedule, D.cell_class, P));
+      FSIMG_CHK(plan_patches(D, opts->vanka_schedule, D.cell_class, P, opts->vanka_patches));
       L.npatch = (int64_t)P.elem.size();
+      PatchBlocks &B = L.blk;
+      B.npatch = P.blk_nl ? (int64_t)P.blk_nodes.size() / P.blk_nl : 0;
+      if (B.npatch > 0) {
+        B.nl = P.blk_nl;
+        B.np = B.nl * L.b;
+        B.npc64 = npc_for(B.np, 8);
+        B.npc32 = npc_for(B.np, 4);
+        B.yofs = L.npatch * L.np;
+        FSIMG_CHK(dalloc(h, &B.pnodes, P.blk_nodes.size()));
+        FSIMG_HIPC(hipMemcpyAsync(B.pnodes, P.blk_nodes.data(), P.blk_nodes.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+        if (B.np > 128 || B.nl > 27) {
+          FSIMG_CHK(dalloc(h, &B.work, B.npatch * B.np * B.np));
+          FSIMG_CHK(dalloc(h, &B.rowk, B.npatch * B.np));
+          FSIMG_CHK(dalloc(h, &B.colk, B.npatch * B.np));
+          FSIMG_CHK(dalloc(h, &B.piv, B.npatch * B.np));
+          FSIMG_CHK(dalloc(h, &B.amax, B.npatch));
+        }
+      }
+      const int64_t ylen = L.npatch * L.np + B.npatch * B.np;
       L.pelem = P.elem;
       L.colour_start = P.colour_start;
       FSIMG_CHK(dalloc(h, &L.pnodes, P.nodes.size()));
@@ -593,26 +694,35 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
       if (!P.gidx.empty())
         FSIMG_HIPC(hipMemcpyAsync(L.gidx, P.gidx.data(), P.gidx.size() * 4, hipMemcpyHostToDevice, s));
       std::vector<double> sc(L.nrows);
-      for (int64_t i = 0; i < L.nrows; ++i)
-        sc[i] = opts->vanka_weighting == FSIMG_WEIGHT_MULT ? 1.0 / node_mult(D, i) : 1.0;
+      for (int64_t i = 0; i < L.nrows; ++i) {
+        // the number of patches containing the node: geometric for element
+        // patches; counted over the plan with blocks (a node inside a block
+        // belongs to that one patch)
+        double mult = node_mult(D, i);
+        if (opts->vanka_patches == FSIMG_PATCH_BLOCK)
+          mult = std::max(1, P.gptr[i + 1] - P.gptr[i]);
+        sc[i] = opts->vanka_weighting == FSIMG_WEIGHT_MULT ? 1.0 / mult : 1.0;
+      }
       if (mixed) {
         std::vector<float> sf(sc.begin(), sc.end());
         FSIMG_CHK(dalloc(h, &L.scale32, L.nrows));
         FSIMG_HIPC(hipMemcpyAsync(L.scale32, sf.data(), L.nrows * 4, hipMemcpyHostToDevice, s));
         FSIMG_CHK(dalloc(h, &L.inv32, L.npatch * L.np * L.npc32));
+        if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv32, B.npatch * B.np * B.npc32));
         FSIMG_CHK(dalloc(h, &L.r32, L.n));
         FSIMG_CHK(dalloc(h, &L.x32, L.n));
         FSIMG_CHK(dalloc(h, &L.d32, L.n));
-        FSIMG_CHK(dalloc(h, &L.Y32, L.npatch * L.np));
+        FSIMG_CHK(dalloc(h, &L.Y32, ylen));
         FSIMG_HIPC(hipStreamSynchronize(s));
       } else {
         FSIMG_CHK(dalloc(h, &L.scale64, L.nrows));
         FSIMG_HIPC(hipMemcpyAsync(L.scale64, sc.data(), L.nrows * 8, hipMemcpyHostToDevice, s));
         FSIMG_CHK(dalloc(h, &L.inv64, L.npatch * L.np * L.npc64));
+        if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv64, B.npatch * B.np * B.npc64));
         FSIMG_CHK(dalloc(h, &L.r64, L.n));
         FSIMG_CHK(dalloc(h, &L.x64, L.n));
         FSIMG_CHK(dalloc(h, &L.d64, L.n));
-        FSIMG_CHK(dalloc(h, &L.Y64, L.npatch * L.np));
+        FSIMG_CHK(dalloc(h, &L.Y64, ylen));
         FSIMG_HIPC(hipStreamSynchronize(s));
       }
     } else {
@@ -713,19 +823,30 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   const int nlev = (int)h->lev.size();
   for (int l = 0; l + 1 < nlev; ++l) {
     DevLevel &L = h->lev[l];
-    if (L.npatch == 0) continue;
-    const int init[2] = {0, INT_MAX};
-    FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
-    if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
-    else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
-    FSIMG_HIP(hipGetLastError());
-    FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    FSIMG_HIP(hipStreamSynchronize(s));
-    if (h->hstatus[0]) {
-      const int64_t p = h->hstatus[1];
-      return fail(FSIMG_ERR_SINGULAR, "singular patch matrix on level " + std::to_string(l) +
-                                          ": patch " + std::to_string(p) + " (cell " +
-                                          std::to_string(p >= 0 && p < L.npatch ? L.pelem[p] : -1) + ")");
+    for (int g = 0; g < 2; ++g) {  // element patches, then block patches
+      const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
+      if (np_ == 0) continue;
+      const int init[2] = {0, INT_MAX};
+      FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
+      if (g == 0) {
+        if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
+        else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
+      } else {
+        if (mixed) launch_patch_factor_blocks<float>(L, L.blk.inv32, L.blk.npc32, h->dstatus, s);
+        else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, s);
+      }
+      FSIMG_HIP(hipGetLastError());
+      FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      FSIMG_HIP(hipStreamSynchronize(s));
+      if (h->hstatus[0]) {
+        const int64_t p = h->hstatus[1];
+        return fail(FSIMG_ERR_SINGULAR,
+                    std::string("singular ") + (g == 0 ? "patch" : "block patch") +
+                        " matrix on level " + std::to_string(l) + ": patch " + std::to_string(p) +
+                        (g == 0 ? " (cell " + std::to_string(p >= 0 && p < L.npatch ? L.pelem[p] : -1) +
+                                      ")"
+                                : std::string()));
+      }
     }
   }
   // coarsest level: dense Gauss-Jordan inverse in FP64

@@ -25,6 +25,8 @@ struct BatchPlan {
   int n = 0, Lmax = 0, b = 0, dim = 0, np = 0, nl = 0, npc = 0;
   bool mixed = false;
   std::vector<int> rpw, ppw;  // per level: SpMV rows per wave, Vanka patches per workgroup
+  std::vector<int> ppw2;      // per level: block patches per workgroup
+  int np2 = 0, nl2 = 0, npc2 = 0;  // block patches (0: none in any instance)
   int rpw0 = 1;               // FP64 level-0 SpMV (A z, true residual)
   void *dbuf = nullptr;
   size_t dbytes = 0;
@@ -33,7 +35,7 @@ struct BatchPlan {
   DKry *dkry = nullptr;  // [n]
   int *active = nullptr, *kcnt = nullptr, *flags = nullptr;
   double *hs = nullptr;  // [n * kHS]
-  std::vector<WorkSet> ws_spmv, ws_patch, ws_gather, ws_restrict, ws_prolong, ws_cn, ws_cf;
+  std::vector<WorkSet> ws_spmv, ws_patch, ws_patch2, ws_gather, ws_restrict, ws_prolong, ws_cn, ws_cf;
   WorkSet ws_row0{}, ws_vec0{}, ws_kry{}, ws_inst{};
   std::vector<DKry> hkry;
   double *hs_host = nullptr;
@@ -69,7 +71,7 @@ size_t plan_bytes_bound(int nlev) {
   // per instance: level descriptors, Krylov descriptor, three flags, the
   // Hessenberg slot and one (instance, prefix) entry in each work set; per
   // plan: one prefix entry and 256-byte alignment of every table
-  const size_t nset = 7 * (size_t)nlev + 4, ntab = 6 + 2 * nset;
+  const size_t nset = 8 * (size_t)nlev + 4, ntab = 6 + 2 * nset;
   return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 3 * sizeof(int) + kHS * sizeof(double) +
          nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 256;
 }
@@ -140,6 +142,8 @@ DLev to_dlev(const DevLevel &L) {
   d.nrows = L.nrows; d.n = L.n;
   for (int a = 0; a < 3; ++a) d.cells[a] = L.cells[a];
   d.npatch = L.npatch; d.pnodes = L.pnodes; d.inv64 = L.inv64; d.inv32 = L.inv32;
+  d.npatch2 = L.blk.npatch; d.yofs2 = L.blk.yofs; d.pnodes2 = L.blk.pnodes;
+  d.inv64_2 = L.blk.inv64; d.inv32_2 = L.blk.inv32;
   d.gptr = L.gptr; d.gidx = L.gidx; d.sc64 = L.scale64; d.sc32 = L.scale32;
   d.r64 = L.r64; d.x64 = L.x64; d.d64 = L.d64; d.Y64 = L.Y64;
   d.r32 = L.r32; d.x32 = L.x32; d.d32 = L.d32; d.Y32 = L.Y32;
@@ -165,16 +169,26 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   const int word = P->mixed ? 4 : 8;
   P->rpw.assign(Lmax, 1);
   P->ppw.assign(Lmax, 1);
+  P->ppw2.assign(Lmax, 1);
+  for (int i = 0; i < n; ++i)
+    for (const DevLevel &L : hs[i]->lev)
+      if (L.blk.npatch > 0) {
+        P->np2 = L.blk.np;
+        P->nl2 = L.blk.nl;
+        P->npc2 = P->mixed ? L.blk.npc32 : L.blk.npc64;
+      }
   for (int l = 0; l < Lmax; ++l) {
-    int64_t rows = 0, patches = 0;
+    int64_t rows = 0, patches = 0, blocks = 0;
     for (int i = 0; i < n; ++i)
       if (l < (int)hs[i]->lev.size()) {
         rows = std::max(rows, hs[i]->lev[l].nrows);
         patches = std::max(patches, hs[i]->lev[l].npatch);
+        blocks = std::max(blocks, hs[i]->lev[l].blk.npatch);
       }
     const TuneTable *tt = hs[0]->lev[0].tune;
     P->rpw[l] = spmv_rows_per_wave(tt, P->b, word, rows);
     P->ppw[l] = vanka_patches_per_wg(tt, P->np, word, patches);
+    if (blocks > 0) P->ppw2[l] = vanka_patches_per_wg(tt, P->np2, word, blocks);
   }
   {
     int64_t rows = 0;
@@ -193,15 +207,16 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   const size_t k_off = blob.add(nullptr, n * sizeof(int));
   const size_t fl_off = blob.add(nullptr, n * sizeof(int));
   const size_t hs_off = blob.add(nullptr, (size_t)n * kHS * sizeof(double));
-  std::vector<WsRef> r_spmv, r_patch, r_gather, r_restrict, r_prolong, r_cn, r_cf;
+  std::vector<WsRef> r_spmv, r_patch, r_patch2, r_gather, r_restrict, r_prolong, r_cn, r_cf;
   for (int l = 0; l < Lmax; ++l) {
-    WsHost sp, pa, ga, re, pr, cn, cf;
+    WsHost sp, pa, pa2, ga, re, pr, cn, cf;
     for (int i = 0; i < n; ++i) {
       const int Li = (int)hs[i]->lev.size();
       if (l < Li - 1) {
         const DevLevel &L = hs[i]->lev[l];
         sp.push(i, cdiv(L.nrows, 4 * P->rpw[l] * spmv_group_rows(P->b, word)));
         pa.push(i, cdiv(L.npatch, P->ppw[l]));
+        pa2.push(i, cdiv(L.blk.npatch, P->ppw2[l]));
         ga.push(i, cdiv(L.n, 256));
         re.push(i, cdiv(hs[i]->lev[l + 1].nrows, 256));
         pr.push(i, cdiv(L.nrows, 256));
@@ -213,6 +228,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
     }
     r_spmv.push_back(stage(blob, sp));
     r_patch.push_back(stage(blob, pa));
+    r_patch2.push_back(stage(blob, pa2));
     r_gather.push_back(stage(blob, ga));
     r_restrict.push_back(stage(blob, re));
     r_prolong.push_back(stage(blob, pr));
@@ -256,6 +272,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   for (int l = 0; l < Lmax; ++l) {
     P->ws_spmv.push_back(resolve(base, r_spmv[l]));
     P->ws_patch.push_back(resolve(base, r_patch[l]));
+    P->ws_patch2.push_back(resolve(base, r_patch2[l]));
     P->ws_gather.push_back(resolve(base, r_gather[l]));
     P->ws_restrict.push_back(resolve(base, r_restrict[l]));
     P->ws_prolong.push_back(resolve(base, r_prolong[l]));
@@ -284,7 +301,7 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
   const int *act = P.active;
   for (int l = 0; l < P.Lmax; ++l) {
     const DLev *L = P.dlev + (size_t)l * n;
-    if (P.ws_patch[l].nset > 0 || P.ws_spmv[l].nset > 0) {
+    if (P.ws_patch[l].nset > 0 || P.ws_patch2[l].nset > 0 || P.ws_spmv[l].nset > 0) {
       const bool p0 = prof && l == 0;
       if (o.nu_pre == 0) launch_b_fill_x<T>(L, act, P.ws_gather[l], s);
       for (int k = 0; k < o.nu_pre; ++k) {
@@ -297,6 +314,8 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
         }
         hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
         hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
+        launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], k == 0, L, act,
+                                 P.ws_patch2[l], s);
         launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, k == 0, k == 0, L, act, P.ws_patch[l],
                           P.ws_gather[l], s, v0, v1);
       }
@@ -322,6 +341,8 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
       if (b2) (void)hipEventRecord(b2, s);
       hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
       hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
+      launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], false, L, act,
+                               P.ws_patch2[l], s);
       launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, false, false, L, act, P.ws_patch[l],
                         P.ws_gather[l], s, v0, v1);
     }

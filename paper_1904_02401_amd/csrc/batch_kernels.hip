@@ -31,6 +31,7 @@ template <> struct LV<double> {
   static __device__ __forceinline__ double *d(const DLev &L) { return L.d64; }
   static __device__ __forceinline__ double *Y(const DLev &L) { return L.Y64; }
   static __device__ __forceinline__ const double *inv(const DLev &L) { return L.inv64; }
+  static __device__ __forceinline__ const double *inv2(const DLev &L) { return L.inv64_2; }
   static __device__ __forceinline__ const double *sc(const DLev &L) { return L.sc64; }
 };
 template <> struct LV<float> {
@@ -40,6 +41,7 @@ template <> struct LV<float> {
   static __device__ __forceinline__ float *d(const DLev &L) { return L.d32; }
   static __device__ __forceinline__ float *Y(const DLev &L) { return L.Y32; }
   static __device__ __forceinline__ const float *inv(const DLev &L) { return L.inv32; }
+  static __device__ __forceinline__ const float *inv2(const DLev &L) { return L.inv32_2; }
   static __device__ __forceinline__ const float *sc(const DLev &L) { return L.sc32; }
 };
 
@@ -74,20 +76,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 }
 
 // ------------------------------------------------------------ Vanka
+// grp 0: element patches; grp 1: block patches (corrections at Y + yofs2)
 template <typename T>
 __global__ __launch_bounds__(1024) void kb_vanka_patch(const DLev *__restrict__ lev,
                                                        const int *__restrict__ active, WorkSet ws,
                                                        int np, int npc, int b, int nl, int ppw,
-                                                       int first) {
+                                                       int first, int grp) {
   extern __shared__ unsigned char smem_raw[];
   const int s = seg_of(ws, blockIdx.x);
   const int i = ws.inst[s];
   if (!active[i]) return;  // uniform per workgroup
   const DLev &L = lev[i];
   const int64_t pfirst = (blockIdx.x - ws.pre[s]) * ppw;
-  dev::vanka_patch_wg<T>(pfirst, L.npatch, np, npc, b, nl, ppw, L.pnodes, LV<T>::inv(L),
-                         first ? LV<T>::r(L) : LV<T>::d(L), LV<T>::Y(L), 0, nullptr, nullptr,
-                         L.mask, T(0), reinterpret_cast<T *>(smem_raw));
+  const bool g2 = grp != 0;
+  dev::vanka_patch_wg<T>(pfirst, g2 ? L.npatch2 : L.npatch, np, npc, b, nl, ppw,
+                         g2 ? L.pnodes2 : L.pnodes, g2 ? LV<T>::inv2(L) : LV<T>::inv(L),
+                         first ? LV<T>::r(L) : LV<T>::d(L), LV<T>::Y(L) + (g2 ? L.yofs2 : 0), 0,
+                         nullptr, nullptr, L.mask, T(0), reinterpret_cast<T *>(smem_raw));
 }
 
 template <typename T>
@@ -405,11 +410,20 @@ void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first
   if (wp.nblocks > 0)
     hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(vanka_threads(np, ppw)),
                        sizeof(T) * (size_t)ppw * npc, s, lev, active, wp, np, npc, b, nl, ppw,
-                       first ? 1 : 0);
+                       first ? 1 : 0, 0);
   if (e1) (void)hipEventRecord(e1, s);
   if (wg.nblocks > 0)
     hipLaunchKernelGGL((kb_vanka_gather<T>), grid_of(wg), dim3(256), 0, s, lev, active, wg, b, omega,
                        assign ? 1 : 0);
+}
+
+template <typename T>
+void launch_b_vanka_blocks(int np, int b, int nl, int npc, int ppw, bool first, const DLev *lev,
+                           const int *active, const WorkSet &wp, hipStream_t s) {
+  if (wp.nblocks > 0)
+    hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(vanka_threads(np, ppw)),
+                       sizeof(T) * (size_t)ppw * npc, s, lev, active, wp, np, npc, b, nl, ppw,
+                       first ? 1 : 0, 1);
 }
 
 template <typename T>
@@ -543,6 +557,8 @@ void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, i
                                   const int *,                                                   \
                                   const WorkSet &, const WorkSet &, hipStream_t, hipEvent_t,     \
                                   hipEvent_t);                                                   \
+  template void launch_b_vanka_blocks<T>(int, int, int, int, int, bool, const DLev *, const int *, \
+                                         const WorkSet &, hipStream_t);                          \
   template void launch_b_fill_x<T>(const DLev *, const int *, const WorkSet &, hipStream_t);     \
   template void launch_b_restrict<T>(int, int, const DLev *, const DLev *, const int *,          \
                                      const WorkSet &, hipStream_t);                              \

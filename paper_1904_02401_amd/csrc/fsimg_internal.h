@@ -31,6 +31,22 @@ constexpr int spmv_group_rows(int b, int word) {
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
 
+// Block patches (2 x 2 (x 2) elements, 5^d nodes) of a level: the second
+// patch group, empty unless requested.  Their corrections follow those of
+// the element patches in the level's Y buffer.
+struct PatchBlocks {
+  int nl = 0, np = 0, npc64 = 0, npc32 = 0;
+  int64_t npatch = 0;
+  int32_t *pnodes = nullptr;            // [npatch*nl]
+  double *inv64 = nullptr;              // [npatch*np*npc64]
+  float *inv32 = nullptr;               // [npatch*np*npc32]
+  int64_t yofs = 0;                     // offset in Y (entries): npatch * np of the element group
+  // batched Gauss-Jordan scratch of the factorisation when np > 128
+  double *work = nullptr;               // [npatch*np*np]
+  double *rowk = nullptr, *colk = nullptr, *amax = nullptr;  // [npatch*np], [npatch*np], [npatch]
+  int *piv = nullptr;                   // [npatch*np]
+};
+
 // One multigrid level on the device.  Vectors of the V-cycle exist in the
 // precision of the hierarchy (T = double for FP64, float for mixed).
 struct DevLevel {
@@ -50,7 +66,9 @@ struct DevLevel {
   std::vector<int64_t> colour_start;    // host: patch ranges per colour
   double *inv64 = nullptr;              // [npatch*np*npc64]
   float *inv32 = nullptr;               // [npatch*np*npc32]
-  int32_t *gptr = nullptr, *gidx = nullptr;  // node -> (patch*nl + local node), patch order
+  int32_t *gptr = nullptr, *gidx = nullptr;  // node -> Y slot (patch*nl + local node; block
+                                             // patches after the element ones), patch order
+  PatchBlocks blk;
   double *scale64 = nullptr;            // per node weight of the summed correction
   float *scale32 = nullptr;
   // V-cycle work vectors (one precision is allocated)
@@ -82,6 +100,10 @@ struct DLev {
   const int32_t *pnodes;
   const double *inv64;
   const float *inv32;
+  int64_t npatch2, yofs2;   // block patches (second group)
+  const int32_t *pnodes2;
+  const double *inv64_2;
+  const float *inv32_2;
   const int32_t *gptr, *gidx;
   const double *sc64;
   const float *sc32;
@@ -129,6 +151,10 @@ template <typename T>
 void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first, bool assign,
                     const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// the block-patch group's local corrections (before launch_b_vanka's gather)
+template <typename T>
+void launch_b_vanka_blocks(int np, int b, int nl, int npc, int ppw, bool first, const DLev *lev,
+                           const int *active, const WorkSet &wp, hipStream_t s);
 template <typename T>
 void launch_b_fill_x(const DLev *lev, const int *active, const WorkSet &ws, hipStream_t s);
 template <typename T>
@@ -175,9 +201,14 @@ int vanka_default_ppw(int np);
 template <typename T>
 void launch_bsr_spmv_rpw(const DevLevel &L, const T *vals, const T *x, const T *b, T *y,
                          bool resid, int rpw, hipStream_t s);
+// all patches of group grp (0 element, 1 block) with ppw patches per workgroup
 template <typename T>
-void launch_vanka_patch_ppw(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
-                            int64_t p1, int ppw, hipStream_t s);
+void launch_vanka_patch_ppw(const DevLevel &L, int grp, const T *inv, int npc, const T *d, T *Y,
+                            int ppw, hipStream_t s);
+// the block patches' local corrections into Y (= the level's Y + L.blk.yofs)
+template <typename T>
+void launch_vanka_blocks(const DevLevel &L, const T *inv, int npc, const T *d, T *Y,
+                         hipStream_t s);
 template <typename T>
 void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
                          hipStream_t s);
@@ -209,6 +240,11 @@ void launch_nonfinite_count(const double *x, int64_t n, int *flag, hipStream_t s
 size_t patch_factor_lds_bytes(int np);
 template <typename Tout>
 void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s);
+// the block patches of L (MFMA kernel up to 128 dofs, batched Gauss-Jordan
+// in L.blk.work beyond)
+template <typename Tout>
+void launch_patch_factor_blocks(const DevLevel &L, Tout *inv, int npc, int *status,
+                                hipStream_t s);
 void launch_densify(const DevLevel &L, double *dense, hipStream_t s);  // free x free block
 void launch_gj_pivot(int64_t n, int64_t k, double *a, int *piv, double *rowk, double *colk,
                      double thr, int *status, hipStream_t s);

@@ -1,5 +1,6 @@
 // Krylov vector kernels (FP64), patch / coarse factorisation and the
 // deformation update.
+#include <algorithm>
 #include <cfloat>
 
 #include "fsimg_internal.h"
@@ -517,6 +518,138 @@ __global__ __launch_bounds__(NT * 64, 4) void k_patch_factor_mfma(
   }
 }
 
+// -------------------------------------------------- large patches
+// Patches with more than 128 dofs (the 500-dof solid blocks of 3D) are
+// inverted by batched Gauss-Jordan with partial pivoting in FP64: A_i is
+// assembled into a per-patch n_p x n_p work matrix, then one pivot launch
+// and one update launch per column eliminate that column in every patch at
+// once, and the row interchanges are undone as column interchanges when
+// the inverse is written in the apply kernel's column-group-major layout.
+__global__ __launch_bounds__(256) void k_big_load(int64_t npatch, int b, int nl, int np,
+                                                  const int32_t *__restrict__ pnodes,
+                                                  const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind,
+                                                  const double *__restrict__ vals,
+                                                  double *__restrict__ work,
+                                                  double *__restrict__ amax) {
+  __shared__ double red[4];
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int32_t *pn = pnodes + p * nl;
+  double *a = work + p * (int64_t)np * np;
+  const int bb = b * b;
+  double m = 0.0;
+  for (int pr = threadIdx.x; pr < nl * nl; pr += blockDim.x) {
+    const int l1 = pr / nl, l2 = pr - l1 * nl;
+    const int64_t pos = find_block(rowptr, colind, pn[l1], pn[l2]);
+    for (int bi = 0; bi < b; ++bi)
+      for (int bj = 0; bj < b; ++bj) {
+        const double v = pos >= 0 ? vals[pos * bb + bi * b + bj] : 0.0;
+        a[(int64_t)(l1 * b + bi) * np + l2 * b + bj] = v;
+        m = fmax(m, fabs(v));
+      }
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) amax[p] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_big_pivot(int64_t npatch, int np, int k,
+                                                   double *__restrict__ work, int *__restrict__ piv,
+                                                   double *__restrict__ rowk,
+                                                   double *__restrict__ colk,
+                                                   const double *__restrict__ amax,
+                                                   int *__restrict__ status) {
+  __shared__ double sb[4];
+  __shared__ int si[4];
+  __shared__ int s_p;
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  double *a = work + p * (int64_t)np * np;
+  double best = -1.0;
+  int bi = k;
+  for (int i = k + threadIdx.x; i < np; i += blockDim.x) {
+    const double v = fabs(a[(int64_t)i * np + k]);
+    if (v > best) { best = v; bi = i; }
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o);
+    const int oi = __shfl_xor(bi, o);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { sb[w] = best; si[w] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = sb[0];
+    int bix = si[0];
+    for (int i = 1; i < (int)(blockDim.x / kWave); ++i)
+      if (sb[i] > bv || (sb[i] == bv && si[i] < bix)) { bv = sb[i]; bix = si[i]; }
+    s_p = bix;
+    piv[p * np + k] = bix;
+  }
+  __syncthreads();
+  const int pr = s_p;
+  if (pr != k)
+    for (int j = threadIdx.x; j < np; j += blockDim.x) {
+      const double t = a[(int64_t)k * np + j];
+      a[(int64_t)k * np + j] = a[(int64_t)pr * np + j];
+      a[(int64_t)pr * np + j] = t;
+    }
+  __syncthreads();
+  const double pv = a[(int64_t)k * np + k];
+  if (threadIdx.x == 0 && !(fabs(pv) > 1e-15 * amax[p])) {
+    atomicOr(&status[0], 1);
+    atomicMin(&status[1], (int)p);
+  }
+  for (int j = threadIdx.x; j < np; j += blockDim.x)
+    rowk[p * np + j] = (j == k ? 1.0 : a[(int64_t)k * np + j]) / pv;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) colk[p * np + i] = a[(int64_t)i * np + k];
+}
+
+__global__ __launch_bounds__(256) void k_big_update(int64_t npatch, int np, int k,
+                                                    double *__restrict__ work,
+                                                    const double *__restrict__ rowk,
+                                                    const double *__restrict__ colk) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= np) return;
+  for (int64_t p = blockIdx.z; p < npatch; p += gridDim.z) {
+    double *a = work + p * (int64_t)np * np;
+    const double *rk = rowk + p * np;
+    const int64_t o = (int64_t)i * np + j;
+    if (i == k) a[o] = rk[j];
+    else a[o] = (j == k ? 0.0 : a[o]) - colk[p * np + i] * rk[j];
+  }
+}
+
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_big_out(int np, int npc, const double *__restrict__ work,
+                                                 const int *__restrict__ piv,
+                                                 Tout *__restrict__ inv) {
+  __shared__ int colmap[1024];
+  const int64_t p = blockIdx.x;
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < npc; ++j) colmap[j] = j;
+    for (int k = np - 1; k >= 0; --k) {
+      const int t = colmap[k], q = piv[p * np + k];
+      colmap[k] = colmap[q];
+      colmap[q] = t;
+    }
+  }
+  __syncthreads();
+  constexpr int G = 16 / sizeof(Tout);
+  const double *a = work + p * (int64_t)np * np;
+  Tout *out = inv + p * (int64_t)np * npc;
+  for (int e = threadIdx.x; e < np * npc; e += blockDim.x) {
+    const int r = e / npc, c = e - r * npc;
+    const double v = c < np ? a[(int64_t)r * np + colmap[c]] : 0.0;
+    out[((int64_t)(c / G) * np + r) * G + (c % G)] = (Tout)v;
+  }
+}
+
+
 // ------------------------------------------------------- coarse level
 // dense block of the free (non-identity) dofs: dense[cidx[i]][cidx[j]] = A[i][j]
 __global__ __launch_bounds__(256) void k_densify(int64_t nrows, int b, int64_t nf,
@@ -726,16 +859,18 @@ size_t patch_factor_lds_bytes(int np) {
   return sizeof(double) * ((size_t)np * (np + 1) + 2 * (size_t)np) + 2 * sizeof(int) * (size_t)np;
 }
 
+// one patch group (npatch patches of nl nodes, np dofs) of level L's matrix
 template <typename Tout>
-void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s) {
-  if (L.npatch == 0) return;
-  if (L.np <= 128 && L.nl <= 27) {
-    const int nt = (L.np + 15) / 16;
+void factor_group(const DevLevel &L, int64_t npatch, int nl, int np, const int32_t *pnodes,
+                  Tout *inv, int npc, int *status, const PatchBlocks *big, hipStream_t s) {
+  if (npatch == 0) return;
+  if (np <= 128 && nl <= 27) {
+    const int nt = (np + 15) / 16;
 #define FSIMG_MF(NTV)                                                                            \
   case NTV:                                                                                      \
-    hipLaunchKernelGGL((k_patch_factor_mfma<NTV, Tout>), dim3((unsigned)L.npatch), dim3(NTV * 64), \
-                       0, s, L.npatch, L.b, L.nl, L.np, npc, L.pnodes, L.rowptr, L.colind,       \
-                       L.vals64, inv, status);                                                   \
+    hipLaunchKernelGGL((k_patch_factor_mfma<NTV, Tout>), dim3((unsigned)npatch), dim3(NTV * 64),   \
+                       0, s, npatch, L.b, nl, np, npc, pnodes, L.rowptr, L.colind, L.vals64, inv,  \
+                       status);                                                                  \
     return;
     switch (nt) {
       FSIMG_MF(1) FSIMG_MF(2) FSIMG_MF(3) FSIMG_MF(4)
@@ -744,12 +879,41 @@ void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hip
     }
 #undef FSIMG_MF
   }
-  const size_t lds = patch_factor_lds_bytes(L.np);
+  if (big && big->work && np <= 1024) {
+    hipLaunchKernelGGL(k_big_load, dim3((unsigned)npatch), dim3(256), 0, s, npatch, L.b, nl, np,
+                       pnodes, L.rowptr, L.colind, L.vals64, big->work, big->amax);
+    for (int k = 0; k < np; ++k) {
+      hipLaunchKernelGGL(k_big_pivot, dim3((unsigned)npatch), dim3(256), 0, s, npatch, np, k,
+                         big->work, big->piv, big->rowk, big->colk, big->amax, status);
+      hipLaunchKernelGGL(k_big_update, dim3((unsigned)((np + 255) / 256), (unsigned)np,
+                                            (unsigned)std::min<int64_t>(npatch, 65535)),
+                         dim3(256), 0, s, npatch, np, k, big->work, big->rowk, big->colk);
+    }
+    hipLaunchKernelGGL((k_big_out<Tout>), dim3((unsigned)npatch), dim3(256), 0, s, np, npc,
+                       big->work, big->piv, inv);
+    return;
+  }
+  const size_t lds = patch_factor_lds_bytes(np);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_patch_factor<Tout>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_patch_factor<Tout>), dim3((unsigned)L.npatch), dim3(256), lds, s, L.npatch,
-                     L.b, L.nl, L.np, npc, L.pnodes, L.rowptr, L.colind, L.vals64, inv, status);
+  hipLaunchKernelGGL((k_patch_factor<Tout>), dim3((unsigned)npatch), dim3(256), lds, s, npatch,
+                     L.b, nl, np, npc, pnodes, L.rowptr, L.colind, L.vals64, inv, status);
 }
+
+template <typename Tout>
+void launch_patch_factor(const DevLevel &L, Tout *inv, int npc, int *status, hipStream_t s) {
+  factor_group<Tout>(L, L.npatch, L.nl, L.np, L.pnodes, inv, npc, status, nullptr, s);
+}
+
+template <typename Tout>
+void launch_patch_factor_blocks(const DevLevel &L, Tout *inv, int npc, int *status,
+                                hipStream_t s) {
+  factor_group<Tout>(L, L.blk.npatch, L.blk.nl, L.blk.np, L.blk.pnodes, inv, npc, status, &L.blk,
+                     s);
+}
+template void launch_patch_factor_blocks<double>(const DevLevel &, double *, int, int *,
+                                                 hipStream_t);
+template void launch_patch_factor_blocks<float>(const DevLevel &, float *, int, int *, hipStream_t);
 template void launch_patch_factor<double>(const DevLevel &, double *, int, int *, hipStream_t);
 template void launch_patch_factor<float>(const DevLevel &, float *, int, int *, hipStream_t);
 

@@ -134,14 +134,16 @@ void launch_bsr_spmv(const DevLevel &L, const T *vals, const T *x, const T *b, T
 }
 
 template <typename T>
-void launch_vanka_patch_ppw(const DevLevel &L, const T *inv, int npc, const T *d, T *Y, int64_t p0,
-                            int64_t p1, int ppw, hipStream_t s) {
-  if (p1 <= p0) return;
-  const unsigned grid = grid_for(p1 - p0, ppw);
+void launch_vanka_patch_ppw(const DevLevel &L, int grp, const T *inv, int npc, const T *d, T *Y,
+                            int ppw, hipStream_t s) {
+  const int64_t npatch = grp ? L.blk.npatch : L.npatch;
+  const int np = grp ? L.blk.np : L.np, nl = grp ? L.blk.nl : L.nl;
+  if (npatch == 0) return;
+  const unsigned grid = grid_for(npatch, ppw);
   const size_t lds = sizeof(T) * (size_t)ppw * npc;
-  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(L.np, ppw)), lds, s, p0, p1,
-                     L.np, npc, L.b, L.nl, ppw, L.pnodes, inv, d, Y, 0, (T *)nullptr,
-                     (const T *)nullptr, L.mask, T(0));
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(np, ppw)), lds, s,
+                     (int64_t)0, npatch, np, npc, L.b, nl, ppw, grp ? L.blk.pnodes : L.pnodes, inv,
+                     d, Y, 0, (T *)nullptr, (const T *)nullptr, L.mask, T(0));
 }
 
 template <typename T>
@@ -154,6 +156,19 @@ void launch_vanka_patch(const DevLevel &L, const T *inv, int npc, const T *d, T 
   hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(L.np, ppw)), lds, s, p0, p1,
                      L.np, npc, L.b, L.nl, ppw, L.pnodes, inv, d, Y, scatter ? 1 : 0, x, scale,
                      L.mask, omega);
+}
+
+template <typename T>
+void launch_vanka_blocks(const DevLevel &L, const T *inv, int npc, const T *d, T *Y,
+                         hipStream_t s) {
+  const PatchBlocks &B = L.blk;
+  if (B.npatch == 0) return;
+  const int ppw = vanka_patches_per_wg(L.tune, B.np, (int)sizeof(T), B.npatch);
+  const unsigned grid = grid_for(B.npatch, ppw);
+  const size_t lds = sizeof(T) * (size_t)ppw * npc;
+  hipLaunchKernelGGL((k_vanka_patch<T>), dim3(grid), dim3(vanka_threads(B.np, ppw)), lds, s,
+                     (int64_t)0, B.npatch, B.np, npc, L.b, B.nl, ppw, B.pnodes, inv, d, Y, 0,
+                     (T *)nullptr, (const T *)nullptr, L.mask, T(0));
 }
 
 template <typename T>
@@ -213,8 +228,10 @@ void launch_mask_zero(double *x, const uint8_t *mask, int64_t n, hipStream_t s) 
                                       int64_t, bool, T *, const T *, T, hipStream_t);            \
   template void launch_bsr_spmv_rpw<T>(const DevLevel &, const T *, const T *, const T *, T *,   \
                                        bool, int, hipStream_t);                                  \
-  template void launch_vanka_patch_ppw<T>(const DevLevel &, const T *, int, const T *, T *,      \
-                                          int64_t, int64_t, int, hipStream_t);                   \
+  template void launch_vanka_patch_ppw<T>(const DevLevel &, int, const T *, int, const T *, T *,  \
+                                          int, hipStream_t);                                     \
+  template void launch_vanka_blocks<T>(const DevLevel &, const T *, int, const T *, T *,         \
+                                       hipStream_t);                                             \
   template void launch_vanka_gather<T>(const DevLevel &, const T *, const T *, T, bool, T *,     \
                                        hipStream_t);                                             \
   template void launch_restrict<T>(const DevLevel &, const DevLevel &, const T *, T *,           \

@@ -87,8 +87,8 @@ struct LevelVec;
 template <>
 struct LevelVec<double> {
   static const double *vals(const DevLevel &L) { return L.vals64; }
-  static const double *inv(const DevLevel &L) { return L.inv64; }
-  static int npc(const DevLevel &L) { return L.npc64; }
+  static const double *inv(const DevLevel &L, int g) { return g ? L.blk.inv64 : L.inv64; }
+  static int npc(const DevLevel &L, int g) { return g ? L.blk.npc64 : L.npc64; }
   static double *x(const DevLevel &L) { return L.x64; }
   static double *r(const DevLevel &L) { return L.r64; }
   static double *d(const DevLevel &L) { return L.d64; }
@@ -97,8 +97,8 @@ struct LevelVec<double> {
 template <>
 struct LevelVec<float> {
   static const float *vals(const DevLevel &L) { return L.vals32; }
-  static const float *inv(const DevLevel &L) { return L.inv32; }
-  static int npc(const DevLevel &L) { return L.npc32; }
+  static const float *inv(const DevLevel &L, int g) { return g ? L.blk.inv32 : L.inv32; }
+  static int npc(const DevLevel &L, int g) { return g ? L.blk.npc32 : L.npc32; }
   static float *x(const DevLevel &L) { return L.x32; }
   static float *r(const DevLevel &L) { return L.r32; }
   static float *d(const DevLevel &L) { return L.d32; }
@@ -133,21 +133,24 @@ struct Tuner {
   }
 
   template <typename T>
-  void vanka(const DevLevel &L) {
+  void vanka(const DevLevel &L, int g) {
     const int word = (int)sizeof(T);
-    if (L.npatch == 0 || !need(FSIMG_TUNE_VANKA_PPW, L.np, word, L.npatch)) return;
-    int best = vanka_default_ppw(L.np);
+    const int64_t npatch = g ? L.blk.npatch : L.npatch;
+    const int np = g ? L.blk.np : L.np;
+    if (npatch == 0 || !need(FSIMG_TUNE_VANKA_PPW, np, word, npatch)) return;
+    int best = vanka_default_ppw(np);
     double best_ms = 1e300;
-    for (int p : ppw_candidates(L.np)) {
+    T *Y = LevelVec<T>::Y(L) + (g ? L.blk.yofs : 0);
+    for (int p : ppw_candidates(np)) {
       const double ms = time_launches(
           [&] {
-            launch_vanka_patch_ppw<T>(L, LevelVec<T>::inv(L), LevelVec<T>::npc(L), LevelVec<T>::r(L),
-                                      LevelVec<T>::Y(L), 0, L.npatch, p, s);
+            launch_vanka_patch_ppw<T>(L, g, LevelVec<T>::inv(L, g), LevelVec<T>::npc(L, g),
+                                      LevelVec<T>::r(L), Y, p, s);
           },
           s, e0, e1, 5);
       if (ms >= 0.0 && ms < best_ms) { best_ms = ms; best = p; }
     }
-    t.entries[{FSIMG_TUNE_VANKA_PPW, L.np, word, bucket_of(L.npatch)}] = best;
+    t.entries[{FSIMG_TUNE_VANKA_PPW, np, word, bucket_of(npatch)}] = best;
     changed = true;
   }
 
@@ -157,7 +160,8 @@ struct Tuner {
     for (int l = 0; l + 1 < nl; ++l) {  // levels that smooth
       const DevLevel &L = h->lev[l];
       spmv<T>(L, LevelVec<T>::vals(L), LevelVec<T>::x(L), LevelVec<T>::r(L), LevelVec<T>::d(L));
-      vanka<T>(L);
+      vanka<T>(L, 0);
+      vanka<T>(L, 1);
     }
   }
 };

@@ -23,6 +23,7 @@ FSIMG_FP64, FSIMG_MIXED = 0, 1
 FSIMG_VANKA_GATHER, FSIMG_VANKA_PARITY, FSIMG_VANKA_GREEDY = 0, 1, 2
 FSIMG_WEIGHT_PLAIN, FSIMG_WEIGHT_MULT = 0, 1
 FSIMG_TUNE_SPMV_ROWS, FSIMG_TUNE_VANKA_PPW = 0, 1
+FSIMG_PATCH_ELEMENT, FSIMG_PATCH_BLOCK = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_SINGULAR",
                  5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_BUDGET", 8: "ERR_STATE"}
@@ -47,7 +48,7 @@ class fsimg_opts(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("vanka_schedule", ctypes.c_int),
                 ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("vanka_patches", ctypes.c_int)]
 
 
 class fsimg_stats(ctypes.Structure):

@@ -305,3 +305,102 @@ def test_vanka_sum_reading_plain_diverges_averaged_contracts(prob_t2):
         rates[wt] = (np.linalg.norm(r) / np.linalg.norm(b)) ** (1 / 8)
     assert rates["plain"] > 1.0
     assert rates["mult"] < 0.6
+
+
+# ------------------------------------------------------------ block patches
+def test_block_patch_groups_partition_and_shapes():
+    """2 x 2 (x 2) element blocks (Sec. 5.5.1): in 2D every aligned block, in
+    3D only all-solid blocks; the patches of both groups cover every element
+    exactly once and a block holds the 5^d nodes of its node box."""
+    from oracle.patches import block_patch_groups
+    cells2 = (4, 6)
+    g = block_patch_groups(cells2)
+    assert g[0][0].shape[0] == 0 and g[1][0].shape == (6, 25)
+    nn = [2 * c + 1 for c in cells2]
+    allnodes = np.unique(g[1][0])
+    assert allnodes.size == nn[0] * nn[1]
+    # odd cell counts leave a strip of one-element patches
+    g = block_patch_groups((5, 4))
+    assert g[1][0].shape[0] == 4 and g[0][0].shape[0] == 4
+    # 3D: solid cells (x 2..5, y 4..5, z 4..5 of 8^3) give two blocks
+    cells3 = (8, 8, 8)
+    sol = np.zeros(512, dtype=np.uint8)
+    for k in range(4, 6):
+        for j in range(4, 6):
+            for i in range(2, 6):
+                sol[i + 8 * (j + 8 * k)] = 1
+    g = block_patch_groups(cells3, sol)
+    assert g[1][0].shape == (2, 125)
+    assert g[0][0].shape[0] == 512 - 16
+    covered = np.zeros(512, int)
+    covered[g[0][1]] += 1
+    for f in g[1][1]:
+        i, j, k = f % 8, (f // 8) % 8, f // 64
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    covered[(i + dx) + 8 * ((j + dy) + 8 * (k + dz))] += 1
+    assert np.all(covered == 1)
+
+
+def test_block_patch_on_a_two_by_two_mesh_is_direct_solve():
+    """A 2 x 2 element mesh is one block patch: one step with omega = 1 is
+    numpy.linalg.solve(A, b)."""
+    from fsigen.problem import make_level, PARAMS_DEFAULT
+    rng = np.random.default_rng(5)
+    coords = [np.linspace(0.0, 1.0, 5)] * 2
+    st = {k: rng.standard_normal((25, 2)) * 0.01 for k in ("v_old", "u_old", "v_cur")}
+    st["u_cur"] = st["u_old"] + 0.005 * (st["v_cur"] + st["v_old"])
+    lev = make_level(2, (2, 2), coords, ((0.3, 0.3), (0.7, 0.7)), st, PARAMS_DEFAULT)
+    for name in ("mom", "ale"):
+        m = lev.systems[name]
+        A = to_csr(m)
+        mask = m.dirichlet.astype(bool)
+        b = rng.standard_normal(A.shape[0])
+        b[mask] = 0.0
+        V = VankaData.build(m, lev.cells, omega=1.0, weighting="mult", patches="block")
+        assert len(V) == 1 and V[0].dofs.shape == (1, 25 * m.b)
+        x = vanka_sweep(A, b, np.zeros_like(b), V, mask)
+        ref = np.linalg.solve(A.toarray(), b)
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-12 * max(np.abs(ref).max(), 1e-300))
+
+
+def test_block_multiplicity_counts_patches(prob_t2):
+    """With blocks a node inside a 2 x 2 block belongs to that one patch; the
+    averaged weighting divides by the number of patches, not elements."""
+    m = prob_t2.levels[0].systems["mom"]
+    cells = prob_t2.levels[0].cells
+    V = VankaData.build(m, cells, omega=0.8, weighting="mult", patches="block")
+    n = m.nrows * m.b
+    mult = np.zeros(n)
+    for g in V:
+        mult += np.bincount(g.dofs.ravel(), minlength=n)
+    np.testing.assert_array_equal(V[0].scale, 1.0 / np.maximum(mult, 1.0))
+    nx = 2 * cells[0] + 1
+    centre = (2 + 2 * nx) * m.b   # node (2, 2): centre of the first block
+    corner = (4 + 4 * nx) * m.b   # node (4, 4): shared by four blocks
+    assert mult[centre] == 1 and mult[corner] == 4
+
+
+def test_block_patches_converge_where_element_patches_stall():
+    """Nearly incompressible solid (lambda / mu = 40): the V-cycle with
+    one-element patches does not reduce the residual, the one with 2 x 2
+    blocks converges (the paper chooses the larger solid patches, Sec. 5.5.1)."""
+    from fsigen.problem import make_problem, SOLID_2D
+    from oracle.fgmres import fgmres
+    from oracle.mg import vcycle
+    P = make_problem(2, 16, 3, SOLID_2D, seed=0, params=dict(mu_s=5e4, lambda_s=2e6),
+                     systems=("mom",))
+    mats = [lv.systems["mom"] for lv in P.levels]
+    cells = [lv.cells for lv in P.levels]
+    solid = [lv.cell_solid for lv in P.levels]
+    b = P.rhs["mom"]
+    its = {}
+    for patches in ("element", "block"):
+        H = Hierarchy(mats, cells, omega=0.8, weighting="mult", patches=patches, cell_solid=solid)
+        lev = H.levels[0]
+        x, info = fgmres(lev.A, b, np.zeros_like(b), lambda v: vcycle(H, v), lev.mask, rtol=1e-8,
+                         maxiter=120, restart=20)
+        its[patches] = (info["iters"], info["converged"])
+    assert its["block"][1] and its["block"][0] <= 40
+    assert not its["element"][1]
