@@ -53,13 +53,14 @@ template <int B, typename T, int SRC, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void kb_spmv(const DLev *__restrict__ lev,
                                                const DKry *__restrict__ kry,
                                                const int *__restrict__ active, WorkSet ws, int j) {
-  const int s = seg_of(ws, blockIdx.x);
+  const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
+  const int s = seg_of(ws, lb);
   const int i = ws.inst[s];
   if (!active[i]) return;
   const DLev &L = lev[i];
   const int lane = threadIdx.x & (kWave - 1);
   constexpr int GR = spmv_group_rows(B, SRC == BS_VCYCLE ? (int)sizeof(T) : 8);
-  const int64_t row0 = ((blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave) * R * GR;
+  const int64_t row0 = ((lb - ws.pre[s]) * 4 + threadIdx.x / kWave) * R * GR;
   if (row0 >= L.nrows) return;
   if constexpr (SRC == BS_VCYCLE) {
     dev::spmv_rows<B, T, 1, R>(row0, L.nrows, lane, L.rowptr, L.colind, LV<T>::vals(L),
@@ -83,11 +84,12 @@ __global__ __launch_bounds__(1024) void kb_vanka_patch(const DLev *__restrict__ 
                                                        int np, int npc, int b, int nl, int ppw,
                                                        int first, int grp) {
   extern __shared__ unsigned char smem_raw[];
-  const int s = seg_of(ws, blockIdx.x);
+  const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
+  const int s = seg_of(ws, lb);
   const int i = ws.inst[s];
   if (!active[i]) return;  // uniform per workgroup
   const DLev &L = lev[i];
-  const int64_t pfirst = (blockIdx.x - ws.pre[s]) * ppw;
+  const int64_t pfirst = (lb - ws.pre[s]) * ppw;
   const bool g2 = grp != 0;
   dev::vanka_patch_wg<T>(pfirst, g2 ? L.npatch2 : L.npatch, np, npc, b, nl, ppw,
                          g2 ? L.pnodes2 : L.pnodes, g2 ? LV<T>::inv2(L) : LV<T>::inv(L),
@@ -99,11 +101,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_vanka_gather(const DLev *__restrict__ lev,
                                                        const int *__restrict__ active, WorkSet ws,
                                                        int b, T omega, int assign) {
-  const int s = seg_of(ws, blockIdx.x);
+  const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
+  const int s = seg_of(ws, lb);
   const int i = ws.inst[s];
   if (!active[i]) return;
   const DLev &L = lev[i];
-  const int64_t dof = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
+  const int64_t dof = (lb - ws.pre[s]) * 256 + threadIdx.x;
   if (dof >= L.n) return;
   dev::vanka_gather_dof<T>(dof, b, L.gptr, L.gidx, LV<T>::Y(L), LV<T>::sc(L), L.mask, omega, assign,
                            LV<T>::x(L));

@@ -46,6 +46,15 @@ __device__ __forceinline__ float dot16<float>(const fvec4 &a, const fvec4 &b) {
   return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumbering them so that XCD k takes the k-th contiguous eighth of
+// the logical block range keeps neighbouring rows (and the x entries they
+// share) in one L2.  A bijection of [0, nblocks).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t q = nblocks >> 3, r = nblocks & 7, xc = b & 7, j = b >> 3;
+  return xc * q + (xc < r ? xc : r) + j;
+}
+
 // ------------------------------------------------------------ BSR SpMV
 // One wavefront per R consecutive block rows.  The R + 1 row pointers come
 // in with one load; each row's column indices (at most 128 blocks, the Q2

@@ -19,7 +19,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                                   const uint8_t *__restrict__ mask,
                                                   T *__restrict__ y) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * R *
+  const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
+  const int64_t row0 = (lb * (blockDim.x / kWave) + (threadIdx.x / kWave)) * R *
                        spmv_group_rows(B, (int)sizeof(T));
   if (row0 >= nrows) return;  // uniform per wave
   dev::spmv_rows<B, T, MODE, R>(row0, nrows, lane, rowptr, colind, vals, x, b, mask, y);
@@ -32,7 +33,8 @@ __global__ __launch_bounds__(1024) void k_vanka_patch(
     T *__restrict__ Y, int scatter, T *__restrict__ x, const T *__restrict__ scale,
     const uint8_t *__restrict__ mask, T omega) {
   extern __shared__ unsigned char smem_raw[];
-  dev::vanka_patch_wg<T>(p0 + (int64_t)blockIdx.x * ppw, p1, np, npc, b, nl, ppw, pnodes, inv, d, Y,
+  dev::vanka_patch_wg<T>(p0 + dev::xcd_block(blockIdx.x, gridDim.x) * ppw, p1, np, npc, b, nl, ppw,
+                         pnodes, inv, d, Y,
                          scatter, x, scale, mask, omega, reinterpret_cast<T *>(smem_raw));
 }
 
