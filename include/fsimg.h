@@ -23,9 +23,10 @@
  * - Vectors are node-major block vectors: entry (node, component) at
  *   node * b + component.  Momentum components are (p, v_1, .., v_d).
  * - Node numbering is lexicographic on a tensor-product Q2 mesh with
- *   2*cells[a]+1 nodes per axis, x fastest; element patches are the 3^d
- *   nodes of one cell (Sec. 4.3: "P_i includes all degrees of freedom in one
- *   element").  Level l+1 is the uniform coarsening of level l.
+ *   2*cells[a]+1 nodes per axis, x fastest; a Vanka patch holds all dofs of
+ *   the 3^d nodes of one cell (Sec. 4.3), or, with FSIMG_PATCH_BLOCK, of the
+ *   5^d nodes of a 2 x 2 (x 2) block of cells (Sec. 5.5.1).  Level l+1 is the
+ *   uniform coarsening of level l.
  * - Identity ("dirichlet") rows: at those dofs the solution keeps the value
  *   that x carries in; b is ignored there.  Inhomogeneous data (such as the
  *   interface deformation of eq. problem:3) are passed in through x.
