@@ -114,7 +114,7 @@ def calib_copy(nbytes, reps):
     log(f"calib-copy: {reps} copies of {nbytes} bytes")
 
 
-def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0):
+def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0):
     import torch
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import level_dicts
@@ -125,7 +125,8 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0):
     t0 = time.perf_counter()
     systems = ["mom", "ale"] + (["mass"] if with_mass else [])
     for name in systems:
-        o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches)
+        o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches,
+                                     vanka_schedule=schedule)
         hs[name] = fsimg.fsimg_hier_create(ctx, level_dicts(P, name), o)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -477,6 +478,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes, no tuning")
+    ap.add_argument("--schedule", choices=["gather", "parity", "greedy"], default="gather",
+                    help="Vanka schedule: per-dof gather (batched path) or coloured scatter")
     ap.add_argument("--patches", choices=["element", "block"], default="element",
                     help="Vanka patches: one element, or 2x2(x2) element blocks (3D: solid only)")
     ap.add_argument("--no-mass", action="store_true")
@@ -542,7 +545,9 @@ def main():
         precs = precs[:1]
     for tag, prec in precs:
         r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass, tune=not args.no_tune,
-                    patches=fsimg.FSIMG_PATCH_BLOCK if args.patches == "block" else fsimg.FSIMG_PATCH_ELEMENT)
+                    patches=fsimg.FSIMG_PATCH_BLOCK if args.patches == "block" else fsimg.FSIMG_PATCH_ELEMENT,
+                    schedule={"gather": fsimg.FSIMG_VANKA_GATHER, "parity": fsimg.FSIMG_VANKA_PARITY,
+                              "greedy": fsimg.FSIMG_VANKA_GREEDY}[args.schedule])
         A = to_csr(lev.systems["mom"])
         mask = lev.systems["mom"].dirichlet.astype(bool)
         rr = P.rhs["mom"] - A @ r["x_mom"]
@@ -605,15 +610,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_tag == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 32^3 Q2 hexes, 4 MG levels, "
-                                "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")
-                   if args.config == "c2" else
-                   ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 64^3 Q2 hexes, 5 MG levels, "
-                    "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")
-                   if args.config == "c3" else args.config,
+        "config": {"workload": {
+            "c1": ("2D [0,1]^2, solid [0.3,0.7]x[0.45,0.55], 32^2 Q2 quads, 3 MG levels, "
+                   "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8"),
+            "c2": ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 32^3 Q2 hexes, 4 MG levels, "
+                   "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8"),
+            "c3": ("3D [0,1]^3, solid [0.3,0.7]x[0.4,0.6]^2, 64^3 Q2 hexes, 5 MG levels, "
+                   "momentum (p,v) + deformation + ALE solves to rel. residual 1e-8")}.get(
+                       args.config, args.config),
                    "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
-                   "precision": main_tag, "vanka_patches": args.patches},
+                   "precision": main_tag, "vanka_patches": args.patches,
+                   "vanka_schedule": args.schedule},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
