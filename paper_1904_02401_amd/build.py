@@ -43,5 +43,24 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+CABI_DRIVER = os.path.join(ROOT, "tests", "_cabi_driver")
+
+
+def build_cabi_driver() -> str:
+    """The plain-C test client of the ABI (tests/cabi_driver.c), linked
+    against libfsimg.so and the HIP runtime with gcc."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "cabi_driver.c"), "-o", CABI_DRIVER,
+           "-L", HERE, "-lfsimg", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath," + HERE, "-Wl,-rpath,$ORIGIN/../paper_1904_02401_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gcc failed for the C client:\n{r.stdout}\n{r.stderr}")
+    return CABI_DRIVER
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -140,6 +140,49 @@ def test_c2_sampled_vanka_update(ctx, c2):
         assert abs(xg[dof] - ref) <= 1e-10 * max(abs(ref - x0[dof]), 1e-30) + 1e-15
 
 
+def test_c2_sampled_block_vanka_update(ctx, c2):
+    """Block patches at full size (128 solid blocks of 500 dofs, batched
+    Gauss-Jordan): at a node strictly inside a solid block the only patch is
+    the block, so the update is omega times the block's local solve."""
+    from oracle.patches import block_patch_groups
+    from oracle.vanka import local_matrices_nodes
+    P = c2
+    lev = P.levels[0]
+    m = lev.systems["mom"]
+    b = m.b
+    rng = np.random.default_rng(13)
+    x0 = rng.standard_normal(m.nrows * b) * 1e-3
+    x0[m.dirichlet.astype(bool)] = 0.0
+    rhs = P.rhs["mom"]
+    opts = fsimg.fsimg_default_opts(vanka_patches=fsimg.FSIMG_PATCH_BLOCK)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), opts)
+    try:
+        fsimg.fsimg_factor(h)
+        xt = torch.tensor(x0, device=DEV)
+        fsimg.fsimg_vanka_step(h, 0, fsimg.FSIMG_FP64, torch.tensor(rhs, device=DEV), xt)
+        torch.cuda.synchronize()
+        xg = xt.cpu().numpy()
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+    d = _masked_res(m, rhs, x0)
+    groups = block_patch_groups(lev.cells, lev.cell_solid)
+    bnodes = groups[1][0]
+    assert bnodes.shape == (128, 125)
+    for q in rng.choice(bnodes.shape[0], 6, replace=False):
+        nodes = bnodes[q]
+        dofs = (nodes[:, None] * b + np.arange(b)).ravel()
+        y = np.linalg.solve(local_matrices_nodes(m, nodes[None, :])[0], d[dofs])
+        # the 27 nodes strictly inside the 5 x 5 x 5 node box belong to this block only
+        inner = [i + 5 * (j + 5 * k) for k in range(1, 4) for j in range(1, 4) for i in range(1, 4)]
+        for ln in rng.choice(inner, 3, replace=False):
+            for c in range(b):
+                dof = int(nodes[ln]) * b + c
+                if m.dirichlet[dof]:
+                    continue
+                ref = x0[dof] + 0.8 * y[ln * b + c]
+                assert abs(xg[dof] - ref) <= 1e-10 * max(abs(ref - x0[dof]), 1e-30) + 1e-15
+
+
 def test_c3_mixed_solve(ctx):
     """64^3 mixed precision (FP32 V-cycle, FP64 outer): FP64 residual <= 1e-8."""
     P = config_problem("c3", seed=0, systems=("mom",))
