@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix rate
 
 
 def log(msg):
@@ -196,9 +197,17 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     # set of timed steps (the same work)
     prof = [step(profile=True)[0] for _ in range(max(1, min(steps, 3)))]
     torch.cuda.synchronize()
+    # the finest momentum level's patch factorisation (MFMA), event-timed on
+    # the launch stream; refactoring the same values reproduces the inverses
+    opts_prof(hs["mom"], 1)
+    factor_ms = []
+    for _ in range(3):
+        fsimg.fsimg_factor(hs["mom"], stream)
+        factor_ms.append(fsimg.fsimg_hier_info(hs["mom"], 0)["factor_ms"])
+    opts_prof(hs["mom"], 0)
     info_m = fsimg.fsimg_hier_info(hs["mom"], 0)
     res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, t_tune=t_tune, shapes=shapes,
-               stats=stats[-1], prof=prof,
+               stats=stats[-1], prof=prof, factor_ms=factor_ms,
                info_m=info_m, x_mom=x_mom.cpu().numpy(), x_ale=x_ale.cpu().numpy())
     for h in hs.values():
         fsimg.fsimg_hier_destroy(h)
@@ -590,6 +599,20 @@ def main():
                                   "GB/s": sb / s_avg / 1e9 if s_n else 0.0, "avg_ms": s_avg * 1e3,
                                   "launches": s_n, "bytes_per_launch": sb, "total_ms": s_ms}}
 
+    def factor_rate(R, tag):
+        # algorithmic flops of inverting one n_p x n_p matrix: 2 n_p^3
+        info = R["info_m"]
+        if args.patches != "element" or not R["factor_ms"]:
+            return None
+        ms = sum(R["factor_ms"]) / len(R["factor_ms"])
+        flops = info["npatch"] * 2.0 * info["np"] ** 3
+        nt = (info["np"] + 15) // 16
+        tf = flops / (ms * 1e-3) / 1e12
+        return {"kernel": f"k_patch_factor_mfma<{nt}, {'double' if tag == 'fp64' else 'float'}>",
+                "bound": "mfma", "achieved": tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP64_MFMA_PEAK_TFLOPS, "flops_per_launch": flops, "avg_launch_ms": ms,
+                "launches": len(R["factor_ms"]), "patches": info["npatch"], "n_p": info["np"]}
+
     main_tag = precs[0][0]
     R = runs[main_tag]
     kr = kernel_rates(R, main_tag)
@@ -627,6 +650,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
                      "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"]},
         "kernels": kr,
+        "patch_factor": factor_rate(R, main_tag),
         "solve": {"momentum_converged": R["stats"][0]["status"] == fsimg.FSIMG_OK,
                   "momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,

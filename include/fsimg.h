@@ -113,7 +113,8 @@ typedef struct {
   int precision;       /* fsimg_precision */
   int vanka_schedule;  /* fsimg_vanka_schedule */
   int vanka_weighting; /* fsimg_weighting */
-  int profile;         /* 1: time the finest-level smoother kernels with events */
+  int profile;         /* 1: time the finest-level smoother kernels and every level's patch
+                          factorisation with events */
   int graphs;          /* 1: replay each FGMRES iteration (V-cycle, A z, Gram-Schmidt) as a
                           HIP graph captured once per batch composition; 0: launch eagerly.
                           Results are identical either way; profiling runs launch eagerly */
@@ -139,6 +140,8 @@ typedef struct {
   int np;               /* dofs per patch = 3^d * b */
   int ncolours;         /* colours of the selected schedule (1 for GATHER) */
   size_t bytes;         /* device bytes held by this level */
+  double factor_ms;     /* profiling on: HIP-event time (ms) of this level's last patch
+                           factorisation (every patch group), else 0 */
 } fsimg_level_info;
 
 typedef struct fsimg_ctx fsimg_ctx;

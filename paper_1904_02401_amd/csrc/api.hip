@@ -791,6 +791,7 @@ fsimg_status fsimg_hier_info(const fsimg_hier *h, int level, fsimg_level_info *o
     for (const auto &a : h->allocs)
       if (p && a.first == p) bytes += a.second;
   out->bytes = bytes;
+  out->factor_ms = L.factor_ms;
   return FSIMG_OK;
 }
 
@@ -821,13 +822,28 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool mixed = hier_mixed(h);
   const int nlev = (int)h->lev.size();
+  const bool prof = h->opts.profile != 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (prof) {
+    FSIMG_HIP(hipEventCreate(&ev[0]));
+    FSIMG_HIP(hipEventCreate(&ev[1]));
+  }
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
   for (int l = 0; l + 1 < nlev; ++l) {
     DevLevel &L = h->lev[l];
+    L.factor_ms = 0.0;
     for (int g = 0; g < 2; ++g) {  // element patches, then block patches
       const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
       if (np_ == 0) continue;
       const int init[2] = {0, INT_MAX};
       FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
+      if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
       if (g == 0) {
         if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
         else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
@@ -836,8 +852,14 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
         else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, s);
       }
       FSIMG_HIP(hipGetLastError());
+      if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
       FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       FSIMG_HIP(hipStreamSynchronize(s));
+      if (prof) {
+        float ms = 0.0f;
+        FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        L.factor_ms += ms;
+      }
       if (h->hstatus[0]) {
         const int64_t p = h->hstatus[1];
         return fail(FSIMG_ERR_SINGULAR,

@@ -53,6 +53,7 @@ struct DevLevel {
   const TuneTable *tune = nullptr;      // launch shapes (the owning context's table)
   int dim = 0, b = 0, nl = 0, np = 0;   // nl = 3^d nodes per patch, np = nl*b
   int npc64 = 0, npc32 = 0;             // padded column counts of stored inverses
+  double factor_ms = 0.0;               // event time of the last patch factorisation (profiling)
   int cells[3] = {1, 1, 1}, nnode[3] = {1, 1, 1};
   int64_t nrows = 0, n = 0, nnzb = 0;
   int32_t *rowptr = nullptr, *colind = nullptr;

@@ -274,244 +274,329 @@ __global__ __launch_bounds__(256) void k_patch_factor(int64_t npatch, int b, int
 }
 
 // ------------------------------------------- patch factorisation (MFMA)
-// Blocked Gauss-Jordan inversion with partial pivoting, FP64, the patch
-// matrix (padded with an identity block to N = 16*NT rows) held in registers
-// in the accumulator layout of v_mfma_f64_16x16x4f64: wave w owns tile-row w
-// (rows 16w..16w+15) and, per tile-column tj, lane l holds the four entries
-// (16w + 4v + l/16, 16tj + l%16), v = 0..3.
-// For each panel of 4 columns P:
-//   - the panel columns go to LDS; wave 0 runs the 4 Gauss-Jordan steps on
-//     them in registers (pivot search, row swap, elimination by shuffles) and
-//     writes back the processed columns G_P and the pivot rows;
-//   - every wave applies the panel's row swaps to its rows (through LDS);
-//   - the non-panel columns take the delayed rank-4 update
-//       A[:, Q] += (G_P - I_P) A[P, Q]
-//     as one MFMA per 16x16 tile (K = 4), the panel columns take G_P.
-// The row interchanges are finally undone as column interchanges when the
-// inverse is written in the column-group-major layout of the Vanka apply.
+// Blocked Gauss-Jordan inversion with partial pivoting in FP64, in exchange
+// form: rows are never interchanged.  The pivot of column k is the largest
+// |a_ik| over the rows not yet used as pivots (ties to the lowest row), and
+// the in-place result M holds the inverse with rows and columns permuted:
+// A^{-1}[k][r_j] = M[r_k][j], r_k the pivot row of column k.
+// The matrix, padded with an identity block to N = 16*NT rows, lives in the
+// registers of NT update waves in the accumulator layout of
+// v_mfma_f64_16x16x4f64 (wave w owns rows 16w..16w+15; per tile-column tj
+// lane l holds (16w + 4v + l/16, 16tj + l%16), v = 0..3).  One more wave,
+// the panel wave, eliminates each panel of 8 columns in its registers (lane
+// l holds rows l and l+64; the pivot search is a DPP / lane-read maximum of
+// a key packing |a_ik| and the row) and publishes the processed columns G
+// and the pivot rows.  Per panel P:
+//   1. the panel wave eliminates P (its columns were published before);
+//   2. the owners of P's pivot rows (set R) publish those rows;
+//   3. the update waves apply A[:,Q] += (G - E_R) A[R,Q] (two MFMAs with
+//      K = 4 per 16x16 tile; P's own columns become G) to the tile column of
+//      panel P+1 first and publish P+1's columns, so that the panel wave
+//      eliminates P+1 while they update the other tile columns.
 typedef double fsimg_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double d4get(const fsimg_d4 &a, int v) {
   return v == 0 ? a[0] : (v == 1 ? a[1] : (v == 2 ? a[2] : a[3]));
 }
-__device__ __forceinline__ void d4set(fsimg_d4 &a, int v, double x) {
-  if (v == 0) a[0] = x;
-  else if (v == 1) a[1] = x;
-  else if (v == 2) a[2] = x;
-  else a[3] = x;
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// maximum over the 64 lanes: within each row of 16 lanes by DPP (two quad
+// permutations, the half-row and row mirrors), then across the four rows
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
+  x = max(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false));
+  x = max(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false));
+  x = max(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false));
+  x = max(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)x, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)x, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)x, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)x, 48);
+  return max(max(a, b), max(c, d));
+}
+// pivot key of row i (< 128): the high word of |a| (exponent and 20 mantissa
+// bits) with its 8 low bits replaced by 255 - i, so that the maximum takes
+// the largest |a| to a relative 2^-12 and then the lowest row; 0 for rows
+// that may not pivot.  NaN entries have the largest keys, so a NaN pivot is
+// found and reported.
+__device__ __forceinline__ unsigned pivot_key(double a, int i, bool allowed) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(a) >> 32) & 0x7FFFFFFFu;
+  return allowed ? ((hi & ~0xFFu) | (unsigned)(255 - i)) : 0u;
+}
+// 1/x for normal x with 1/x normal: hardware reciprocal estimate and two
+// Newton steps y <- y + y (1 - x y)
+__device__ __forceinline__ double recip_newton(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
 }
 
 template <int NT, typename Tout>
-__global__ __launch_bounds__(NT * 64, 4) void k_patch_factor_mfma(
+__global__ __launch_bounds__((NT + 1) * 64) __attribute__((amdgpu_waves_per_eu(NT >= 7 ? 5 : 6))) void
+k_patch_factor_mfma(
     int64_t npatch, int b, int nl, int np, int npc, const int32_t *__restrict__ pnodes,
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
     const double *__restrict__ vals, Tout *__restrict__ inv, int *__restrict__ status) {
   constexpr int N = NT * 16;
-  constexpr int NTH = NT * 64;
+  constexpr int NW = NT + 1;
+  constexpr int NTH = NW * 64;
+  constexpr int PW = 8;               // panel width
+  constexpr int NSM = 3 * N * PW;     // doubles of pan[2][N][PW] and rowbuf[PW][N]
+  constexpr int CAP = 2 * NSM;        // int32 slots for the patch's column lists
+  __shared__ double smem[NSM];
   __shared__ int bpos[27 * 27];
-  __shared__ double pin[N][4];     // panel columns before the panel's elimination
-  __shared__ double gpan[N][4];    // panel columns after it (G_P)
-  __shared__ double rowbuf[8][N];  // pre-swap rows k0..k0+3 and the 4 pivot rows
-  __shared__ int piv[N];
-  __shared__ int cmap[N];
-  __shared__ double red[NT];
+  __shared__ int sp[27], sbeg[27], soff[28];
+  __shared__ int piv[N];              // pivot row of every column
+  __shared__ int rinv[N];             // column whose pivot a row is
+  __shared__ double red[NW];
+  // pan: panel columns, then G (alternating buffers); rowbuf: the panel's
+  // pivot rows before its update; both alias the column lists of the
+  // extraction, which are dead by then
+  double(*pan)[N][PW] = reinterpret_cast<double(*)[N][PW]>(smem);
+  double(*rowbuf)[N] = reinterpret_cast<double(*)[N]>(smem + 2 * N * PW);
+  int32_t *cols = reinterpret_cast<int32_t *>(smem);
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int lr = l >> 4, lc = l & 15;
   const int64_t p = blockIdx.x;
   if (p >= npatch) return;
+  // extraction: the block rows of the patch nodes go to LDS, then every
+  // (node, node) block is found by binary search there
   const int32_t *pn = pnodes + p * nl;
-  for (int pr = tid; pr < nl * nl; pr += NTH) {
-    const int l1 = pr / nl, l2 = pr - l1 * nl;
-    bpos[pr] = (int)find_block(rowptr, colind, pn[l1], pn[l2]);
-  }
-  __syncthreads();
-  fsimg_d4 acc[NT];
-  double amax = 0.0;
-  const int bb = b * b;
-#pragma unroll
-  for (int tj = 0; tj < NT; ++tj) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + 4 * v + lr, c = 16 * tj + lc;
-      double val;
-      if (r < np && c < np) {
-        const int pos = bpos[(r / b) * nl + c / b];
-        val = pos >= 0 ? vals[(int64_t)pos * bb + (r % b) * b + c % b] : 0.0;
-        amax = fmax(amax, fabs(val));
-      } else {
-        val = r == c ? 1.0 : 0.0;
-      }
-      acc[tj][v] = val;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
-  if (l == 0) red[w] = amax;
-  // the padding block is the identity and stays untouched: panels past np are skipped
-  const int kend = (np + 3) & ~3;
-  for (int k = kend + tid; k < N; k += NTH) piv[k] = k;
-  __syncthreads();
-  double thr = 0.0;
-  for (int i = 0; i < NT; ++i) thr = fmax(thr, red[i]);
-  thr *= 1e-15;
-  bool singular = false;
-  const int r0 = l, r1 = l + 64;
-  const bool ok0 = r0 < N, ok1 = r1 < N;
-  for (int k0 = 0; k0 < kend; k0 += 4) {
-    const int tp = k0 >> 4, cp = k0 & 15;
-    // phase 1: publish the panel columns
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
-      if (tj == tp && lc >= cp && lc < cp + 4)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pin[16 * w + 4 * v + lr][lc - cp] = acc[tj][v];
-    __syncthreads();
-    // phase 2: every wave eliminates the panel redundantly in registers
-    // (lane l holds panel rows l and l+64), then publishes the rows the
-    // panel's interchanges and the rank-4 update read
-    double a0[4], a1[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      a0[c] = ok0 ? pin[r0][c] : 0.0;
-      a1[c] = ok1 ? pin[r1][c] : 0.0;
-    }
-    int pv4[4];
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int j = k0 + jj;
-      double best = -1.0;
-      int bi = j;
-      if (ok0 && r0 >= j && fabs(a0[jj]) > best) { best = fabs(a0[jj]); bi = r0; }
-      if (ok1 && r1 >= j && fabs(a1[jj]) > best) { best = fabs(a1[jj]); bi = r1; }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int pr = bi;
-      pv4[jj] = pr;
-      double vj[4], vp[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        vj[c] = __shfl((j >> 6) ? a1[c] : a0[c], j & 63);
-        vp[c] = __shfl((pr >> 6) ? a1[c] : a0[c], pr & 63);
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (r0 == j) a0[c] = vp[c]; else if (r0 == pr) a0[c] = vj[c];
-        if (r1 == j) a1[c] = vp[c]; else if (r1 == pr) a1[c] = vj[c];
-      }
-      const double pv = vp[jj];
-      if (!(fabs(pv) > thr)) singular = true;
-      double rj[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) rj[c] = (c == jj ? 1.0 : vp[c]) / pv;
-      const double f0 = a0[jj], f1 = a1[jj];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        a0[c] = r0 == j ? rj[c] : (c == jj ? 0.0 : a0[c]) - f0 * rj[c];
-        a1[c] = r1 == j ? rj[c] : (c == jj ? 0.0 : a1[c]) - f1 * rj[c];
-      }
-    }
-    // slot rows: k0..k0+3 and the pivot rows, pre-swap values
-    int slotrow[8];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) { slotrow[q] = k0 + q; slotrow[4 + q] = pv4[q]; }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int x = slotrow[s];
-      if ((x >> 4) == w && ((x & 15) & 3) == lr) {
-        const int v = (x & 15) >> 2;
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj) rowbuf[s][16 * tj + lc] = d4get(acc[tj], v);
-      }
-    }
-    if (w == 0) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (ok0) gpan[r0][c] = a0[c];
-        if (ok1) gpan[r1][c] = a1[c];
-      }
-      if (l < 4) piv[k0 + l] = l == 0 ? pv4[0] : (l == 1 ? pv4[1] : (l == 2 ? pv4[2] : pv4[3]));
-    }
-    __syncthreads();
-    // phase 3: row interchanges, rank-4 update by MFMA, panel columns
-    // source row of position r after the 4 interchanges: walk them backwards
-    auto src_of = [&](int r) {
-      int x = r;
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const int a = k0 + q, bq = pv4[q];
-        x = x == a ? bq : (x == bq ? a : x);
-      }
-      return x;
-    };
-    auto slot_of = [&](int x) {
-      int s = 7;
-#pragma unroll
-      for (int t = 7; t >= 0; --t)
-        if (slotrow[t] == x) s = t;
-      return s;
-    };
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + 4 * v + lr;
-      const int x = src_of(r);
-      if (x != r) {
-        const int s = slot_of(x);
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj) acc[tj][v] = rowbuf[s][16 * tj + lc];
-      }
-    }
-    const int ra = 16 * w + lc;
-    const double aw = gpan[ra][lr] - (ra == k0 + lr ? 1.0 : 0.0);
-    const int sb = slot_of(src_of(k0 + lr));
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj) {
-      const int c = 16 * tj + lc;
-      const double bv = (c >= k0 && c < k0 + 4) ? 0.0 : rowbuf[sb][c];
-      acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, bv, acc[tj], 0, 0, 0);
-    }
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
-      if (tj == tp && lc >= cp && lc < cp + 4)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[tj][v] = gpan[16 * w + 4 * v + lr][lc - cp];
+  if (tid < nl) {
+    const int32_t node = pn[tid];
+    const int32_t beg = rowptr[node];
+    sp[tid] = node;
+    sbeg[tid] = beg;
+    soff[tid + 1] = rowptr[node + 1] - beg;
   }
   __syncthreads();
   if (tid == 0) {
-    // undo the row interchanges as column interchanges, in reverse order
-    for (int j = 0; j < N; ++j) cmap[j] = j;
-    for (int k = N - 1; k >= 0; --k) {
-      const int t = cmap[k];
-      cmap[k] = cmap[piv[k]];
-      cmap[piv[k]] = t;
+    soff[0] = 0;
+    for (int t = 0; t < nl; ++t) soff[t + 1] += soff[t];
+  }
+  __syncthreads();
+  const bool staged = soff[nl] <= CAP;
+  if (staged)
+    for (int l1 = w; l1 < nl; l1 += NW) {
+      const int beg = sbeg[l1], o = soff[l1], len = soff[l1 + 1] - o;
+      for (int j = l; j < len; j += 64) cols[o + j] = colind[beg + j];
     }
-    if (singular) {
+  __syncthreads();
+  const unsigned mnl = (65536u + nl - 1) / nl;  // q = (x * mnl) >> 16 is x / nl for x < 729
+  for (int pr = tid; pr < nl * nl; pr += NTH) {
+    const int l1 = (int)(((unsigned)pr * mnl) >> 16), l2 = pr - l1 * nl;
+    int pos = -1;
+    if (staged) {
+      const int32_t col = sp[l2];
+      int lo = soff[l1], hi = soff[l1 + 1] - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t c = cols[mid];
+        if (c == col) {
+          pos = sbeg[l1] + (mid - soff[l1]);
+          break;
+        }
+        if (c < col) lo = mid + 1;
+        else hi = mid - 1;
+      }
+    } else {
+      pos = (int)find_block(rowptr, colind, sp[l1], sp[l2]);
+    }
+    bpos[pr] = pos;
+  }
+  // the padding block is the identity and stays untouched: panels past np
+  // are skipped and their columns pivot on their own rows
+  const int kend = (np + PW - 1) & ~(PW - 1);
+  for (int k = tid; k < N; k += NTH) {
+    rinv[k] = N;
+    if (k >= kend) piv[k] = k;
+  }
+  __syncthreads();
+  constexpr int G = 16 / sizeof(Tout);
+  Tout *out = inv + p * (int64_t)np * npc;
+  // Wave-specialised from here on: the panel wave and the update waves run
+  // loops of their own with the same sequence of barriers (three per panel,
+  // two after the last), on a branch that is uniform per wave.
+  if (__builtin_amdgcn_readfirstlane(w) == NT) {
+    __syncthreads();  // the update waves have loaded A and published panel 0
+    double thr = 0.0;
+    for (int i = 0; i < NT; ++i) thr = fmax(thr, red[i]);
+    thr *= 1e-15;
+    // rows i0 = l and i1 = l + 64 (where < N), whether they pivoted yet
+    const int i0 = l, i1 = l + 64;
+    const bool ok0 = i0 < N, ok1 = i1 < N;
+    bool used0 = !ok0, used1 = !ok1, singular = false;
+    for (int k0 = 0, buf = 0; k0 < kend; k0 += PW, buf ^= 1) {
+      double a0[PW], a1[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        a0[c] = ok0 ? pan[buf][i0][c] : 0.0;
+        a1[c] = ok1 ? pan[buf][i1][c] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < PW; ++jj) {
+        const unsigned key =
+            wave_max_u32(max(pivot_key(a0[jj], i0, !used0), pivot_key(a1[jj], i1, !used1)));
+        const int r = 255 - (int)(key & 0xFFu);  // uniform
+        const int rl = r & 63;
+        double vp[PW];
+        if (r >= 64) {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) vp[c] = readlane_d(a1[c], rl);
+        } else {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) vp[c] = readlane_d(a0[c], rl);
+        }
+        used0 = used0 || i0 == r;
+        used1 = used1 || i1 == r;
+        const double pv = vp[jj];
+        if (!(fabs(pv) > thr)) singular = true;
+        const double rp = recip_newton(pv);
+        const double f0 = a0[jj], f1 = a1[jj];
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+          if (c == jj) {
+            a0[c] = -f0 * rp;
+            a1[c] = -f1 * rp;
+          } else {
+            const double rj = vp[c] * rp;
+            a0[c] = fma(-f0, rj, a0[c]);
+            a1[c] = fma(-f1, rj, a1[c]);
+          }
+        }
+        // the pivot row itself becomes row r / pivot, with 1 / pivot in column jj
+        if (r >= 64) {
+          if (l == rl)
+#pragma unroll
+            for (int c = 0; c < PW; ++c) a1[c] = c == jj ? rp : vp[c] * rp;
+        } else {
+          if (l == rl)
+#pragma unroll
+            for (int c = 0; c < PW; ++c) a0[c] = c == jj ? rp : vp[c] * rp;
+        }
+        if (l == 0) piv[k0 + jj] = r;
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        if (ok0) pan[buf][i0][c] = a0[c];
+        if (ok1) pan[buf][i1][c] = a1[c];
+      }
+      __syncthreads();  // G and the pivots are out
+      __syncthreads();  // the pivot rows are out
+      __syncthreads();  // the next panel's columns are out
+    }
+    __syncthreads();
+    for (int k = tid; k < N; k += NTH) rinv[piv[k]] = k;
+    if (l == 0 && singular) {
       atomicOr(&status[0], 1);
       atomicMin(&status[1], (int)p);
     }
-  }
-  __syncthreads();
-  // column j of the work array is column c of the inverse, cmap[c] = j
-  int cinv[NT];
-#pragma unroll
-  for (int tj = 0; tj < NT; ++tj) cinv[tj] = -1;
-  for (int c = 0; c < N; ++c) {
-    const int j = cmap[c];
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
-      if (j == 16 * tj + lc) cinv[tj] = c;
-  }
-  constexpr int G = 16 / sizeof(Tout);
-  Tout *out = inv + p * (int64_t)np * npc;
-#pragma unroll
-  for (int tj = 0; tj < NT; ++tj)
+    __syncthreads();
+  } else {
+    fsimg_d4 acc[NT];
+    double amax = 0.0;
+    const int bb = b * b;
+    const unsigned mb = (65536u + b - 1) / b;  // x / b for x < 128
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * w + 4 * v + lr;
-      const int c = cinv[tj];
-      if (r < np && c < np) out[((int64_t)(c / G) * np + r) * G + c % G] = (Tout)acc[tj][v];
+      const int rq = (int)(((unsigned)r * mb) >> 16), rr = r - rq * b;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int c = 16 * tj + lc;
+        const int cq = (int)(((unsigned)c * mb) >> 16), cr = c - cq * b;
+        double val;
+        if (r < np && c < np) {
+          const int pos = bpos[rq * nl + cq];
+          val = pos >= 0 ? vals[(int64_t)pos * bb + rr * b + cr] : 0.0;
+          amax = fmax(amax, fabs(val));
+        } else {
+          val = r == c ? 1.0 : 0.0;
+        }
+        acc[tj][v] = val;
+      }
     }
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    if (l == 0) red[w] = amax;
+    if (lc < PW)  // panel 0's columns
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pan[0][16 * w + 4 * v + lr][lc] = acc[0][v];
+    __syncthreads();
+    for (int k0 = 0, buf = 0; k0 < kend; k0 += PW, buf ^= 1) {
+      const int tp = k0 >> 4, cp = k0 & 15;
+      const int k1 = k0 + PW, tn = k1 >> 4, cn = k1 & 15;
+      const bool more = k1 < kend;
+      __syncthreads();  // G and the pivots of this panel
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int x = piv[k0 + q];
+        if ((x >> 4) == w && (x & 3) == lr) {
+          const int v = (x & 15) >> 2;
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj) rowbuf[q][16 * tj + lc] = d4get(acc[tj], v);
+        }
+      }
+      __syncthreads();  // the pivot rows
+      double aw[PW / 4];
+      const int ra = 16 * w + lc;
+#pragma unroll
+      for (int h = 0; h < PW / 4; ++h) {
+        const int q = 4 * h + lr;
+        aw[h] = pan[buf][ra][q] - (ra == piv[k0 + q] ? 1.0 : 0.0);
+      }
+      // the next panel's tile column first
+      if (more)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+          if (tj == tn) {
+#pragma unroll
+            for (int h = 0; h < PW / 4; ++h)
+              acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[h], rowbuf[4 * h + lr][16 * tj + lc],
+                                                             acc[tj], 0, 0, 0);
+            if (tj == tp && lc >= cp && lc < cp + PW)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[tj][v] = pan[buf][16 * w + 4 * v + lr][lc - cp];
+            if (lc >= cn && lc < cn + PW)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) pan[buf ^ 1][16 * w + 4 * v + lr][lc - cn] = acc[tj][v];
+          }
+      __syncthreads();  // the next panel's columns
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+        if (!(more && tj == tn)) {
+#pragma unroll
+          for (int h = 0; h < PW / 4; ++h)
+            acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[h], rowbuf[4 * h + lr][16 * tj + lc],
+                                                           acc[tj], 0, 0, 0);
+          if (tj == tp && lc >= cp && lc < cp + PW)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[tj][v] = pan[buf][16 * w + 4 * v + lr][lc - cp];
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < N; k += NTH) rinv[piv[k]] = k;
+    __syncthreads();
+    // M[i][j] = A^{-1}[rinv[i]][piv[j]], written in the column-group-major
+    // layout of the Vanka apply (groups of G columns, n_p rows each)
+    int cj[NT];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) cj[tj] = piv[16 * tj + lc];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ro = rinv[16 * w + 4 * v + lr];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int c = cj[tj];
+        if (ro < np && c < np) out[((int64_t)(c / G) * np + ro) * G + c % G] = (Tout)acc[tj][v];
+      }
+    }
+  }
   for (int idx = tid; idx < np * (npc - np); idx += NTH) {
     const int r = idx / (npc - np), c = np + idx % (npc - np);
     out[((int64_t)(c / G) * np + r) * G + c % G] = Tout(0);
@@ -868,7 +953,7 @@ void factor_group(const DevLevel &L, int64_t npatch, int nl, int np, const int32
     const int nt = (np + 15) / 16;
 #define FSIMG_MF(NTV)                                                                            \
   case NTV:                                                                                      \
-    hipLaunchKernelGGL((k_patch_factor_mfma<NTV, Tout>), dim3((unsigned)npatch), dim3(NTV * 64),   \
+    hipLaunchKernelGGL((k_patch_factor_mfma<NTV, Tout>), dim3((unsigned)npatch), dim3((NTV + 1) * 64),   \
                        0, s, npatch, L.b, nl, np, npc, pnodes, L.rowptr, L.colind, L.vals64, inv,  \
                        status);                                                                  \
     return;

@@ -74,7 +74,7 @@ class fsimg_request(ctypes.Structure):
 class fsimg_level_info(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("n", ctypes.c_int64), ("nnzb", ctypes.c_int64),
                 ("npatch", ctypes.c_int64), ("np", ctypes.c_int), ("ncolours", ctypes.c_int),
-                ("bytes", ctypes.c_size_t)]
+                ("bytes", ctypes.c_size_t), ("factor_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
