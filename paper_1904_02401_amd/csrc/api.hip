@@ -349,7 +349,8 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
     const int64_t nf = count_free(L);
     s += (size_t)nf * nf * 8 + (size_t)(nf + n) * 4 + (size_t)2 * n * 8 + (size_t)2 * n * ts;
     if (nf > 0)  // Gauss-Jordan workspace
-      s += (size_t)nf * nf * 8 + (size_t)2 * nf * 8 + (size_t)2 * nf * 4 + (size_t)kRedBlocks * 8;
+      s += (size_t)nf * nf * 8 + (size_t)2 * kCoarseStage * nf * 8 + (size_t)2 * nf * 4 +
+           (size_t)kRedBlocks * 8;
   }
   return s;
 }
@@ -739,8 +740,8 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
       FSIMG_CHK(dalloc(h, &L.cinv, L.nfree * L.nfree));
       if (L.nfree > 0) {
         FSIMG_CHK(dalloc(h, &L.gj_a, L.nfree * L.nfree));
-        FSIMG_CHK(dalloc(h, &L.gj_rowk, L.nfree));
-        FSIMG_CHK(dalloc(h, &L.gj_colk, L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_rowk, (int64_t)kCoarseStage * L.nfree));
+        FSIMG_CHK(dalloc(h, &L.gj_colk, (int64_t)kCoarseStage * L.nfree));
         FSIMG_CHK(dalloc(h, &L.gj_piv, L.nfree));
         FSIMG_CHK(dalloc(h, &L.gj_colmap, L.nfree));
         FSIMG_CHK(dalloc(h, &L.gj_part, kRedBlocks));
@@ -895,11 +896,15 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
       st = fail(FSIMG_ERR_HIP, "status init");
       break;
     }
-    for (int64_t k = 0; k < n; ++k) {
-      launch_gj_pivot(n, k, a, piv, rowk, colk, 1e-15 * amax, h->dstatus, s);
-      launch_gj_update(n, k, a, rowk, colk, s);
+    if (!launch_coarse_gj_blocked(n, a, piv, colmap, colk, rowk, 1e-15 * amax, h->dstatus, C.cinv,
+                                  s)) {
+      // beyond the blocked kernel's size: one pivot and one update launch per column
+      for (int64_t k = 0; k < n; ++k) {
+        launch_gj_pivot(n, k, a, piv, rowk, colk, 1e-15 * amax, h->dstatus, s);
+        launch_gj_update(n, k, a, rowk, colk, s);
+      }
+      launch_gj_finish(n, a, piv, colmap, C.cinv, s);
     }
-    launch_gj_finish(n, a, piv, colmap, C.cinv, s);
     if (hipGetLastError() != hipSuccess) { st = fail(FSIMG_ERR_HIP, "coarse factor launch"); break; }
     if (hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = fail(FSIMG_ERR_HIP, "coarse status copy"); break; }

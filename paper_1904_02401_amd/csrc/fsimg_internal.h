@@ -30,6 +30,7 @@ constexpr int spmv_group_rows(int b, int word) {
 
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
+constexpr int kCoarseStage = 32;  // panel width of the coarse Gauss-Jordan (staged pivot rows)
 
 // Block patches (2 x 2 (x 2) elements, 5^d nodes) of a level: the second
 // patch group, empty unless requested.  Their corrections follow those of
@@ -253,6 +254,11 @@ void launch_gj_update(int64_t n, int64_t k, double *a, const double *rowk, const
                       hipStream_t s);
 void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, double *out,
                       hipStream_t s);
+// Blocked Gauss-Jordan inverse of the dense n x n matrix a (destroyed) into
+// out, for n <= 4096 (returns false otherwise, launching nothing).  piv, iwork:
+// int[n]; ub, rb: double[kCoarseStage * n].
+bool launch_coarse_gj_blocked(int64_t n, double *a, int *piv, int *iwork, double *ub, double *rb,
+                              double thr, int *status, double *out, hipStream_t s);
 void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s);
 void launch_coarse_gemv(const DevLevel &C, const double *x, double *y, hipStream_t s);
 void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,

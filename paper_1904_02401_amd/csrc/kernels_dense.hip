@@ -834,6 +834,297 @@ __global__ __launch_bounds__(256) void k_gj_out(int64_t n, const double *__restr
   if (j < n) out[i * n + j] = a[i * n + colmap[j]];
 }
 
+// ------------------------------- coarse inverse: blocked Gauss-Jordan (n <= 4096)
+// Exchange form, as for the patches: the pivot of column k is the largest
+// |a_ik| over the rows not yet used (ties to the lowest row), no rows move,
+// and A^{-1}[k][r_j] = M[r_k][j] at the end.  Panels of kCoarsePB columns,
+// each made of sub-panels t of PW columns with pivot rows R_t:
+//   k_cgj_panel (one workgroup of 1024 threads, thread t owning rows
+//     t + 1024 s, s < RPT), per sub-panel: bring its columns up to date with
+//     the panel's earlier sub-panels (left-looking), eliminate them in
+//     registers, keep U_t = G_t - E_{R_t} (G_t: the processed columns), and
+//     apply U_t to the earlier sub-panels' columns;
+//   k_cgj_stage stages the pivot rows as they stood at their own sub-panel,
+//     rb_t = A[R_t] + sum_{t' < t} U_t'[R_t] rb_t';
+//   k_cgj_update applies A[:,Q] += sum_t U_t rb_t[:,Q] to every column
+//     outside the panel.
+constexpr int kCoarsePB = kCoarseStage;
+
+// pivot key of row i (< 65536): |a| with its 16 low mantissa bits replaced by
+// 65535 - i (largest |a| to a relative 2^-36, then the lowest row); 0 for
+// rows that may not pivot
+__device__ __forceinline__ unsigned long long coarse_key(double a, int i, bool allowed) {
+  const unsigned long long m = (unsigned long long)__double_as_longlong(fabs(a));
+  return allowed ? ((m & ~0xFFFFull) | (unsigned long long)(65535 - i)) : 0ull;
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+  auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+  x = mx(x, dpp_u64<0xB1>(x));
+  x = mx(x, dpp_u64<0x4E>(x));
+  x = mx(x, dpp_u64<0x141>(x));
+  x = mx(x, dpp_u64<0x140>(x));
+  return mx(mx(readlane_u64(x, 0), readlane_u64(x, 16)), mx(readlane_u64(x, 32), readlane_u64(x, 48)));
+}
+
+template <int RPT, int PW>
+__global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, double *__restrict__ a,
+                                                    int *__restrict__ piv, int *__restrict__ used_g,
+                                                    double *__restrict__ ub, double thr,
+                                                    int *__restrict__ status) {
+  constexpr int PB = kCoarsePB, NSUB = PB / PW;
+  __shared__ unsigned long long red[16];
+  __shared__ double prow[PW];
+  __shared__ double rbs[PW][PW];
+  __shared__ double bfix[PW][PB];
+  __shared__ int ptv[PB];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int64_t kend = min(k0 + (int64_t)PB, n);
+  const int npb = (int)(kend - k0);
+  int row[RPT];
+  bool ok[RPT], used[RPT];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    row[s] = t + 1024 * s;
+    ok[s] = row[s] < n;
+    used[s] = ok[s] ? used_g[row[s]] != 0 : true;
+  }
+  bool singular = false;
+  int sing_k = (int)n;
+  for (int sub = 0; sub < NSUB; ++sub) {
+    const int64_t c0 = k0 + (int64_t)sub * PW;
+    if (c0 >= kend) break;
+    const int nc = (int)min<int64_t>(PW, kend - c0);
+    double x[RPT][PW];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+#pragma unroll
+      for (int c = 0; c < PW; ++c)
+        x[s][c] = (ok[s] && c < nc) ? a[(int64_t)row[s] * n + c0 + c] : 0.0;
+    // left-looking: the panel's earlier sub-panels, in order, each with its
+    // pivot rows as they stand at that point
+    for (int tt = 0; tt < sub; ++tt) {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int r = ptv[tt * PW + q];
+#pragma unroll
+        for (int s = 0; s < RPT; ++s)
+          if (ok[s] && row[s] == r)
+#pragma unroll
+            for (int c = 0; c < PW; ++c) rbs[q][c] = x[s][c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RPT; ++s)
+        if (ok[s])
+#pragma unroll
+          for (int q = 0; q < PW; ++q) {
+            const double u = ub[(int64_t)row[s] * PB + tt * PW + q];
+#pragma unroll
+            for (int c = 0; c < PW; ++c) x[s][c] = fma(u, rbs[q][c], x[s][c]);
+          }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int jj = 0; jj < PW; ++jj) {
+      if (jj >= nc) break;
+      unsigned long long key = 0;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const unsigned long long ks = coarse_key(x[s][jj], row[s], !used[s]);
+        key = ks > key ? ks : key;
+      }
+      key = wave_max_u64(key);
+      if (l == 0) red[w] = key;
+      __syncthreads();
+      key = red[0];
+      for (int i = 1; i < 16; ++i) key = red[i] > key ? red[i] : key;
+      const int r = 65535 - (int)(key & 0xFFFFull);
+#pragma unroll
+      for (int s = 0; s < RPT; ++s)
+        if (ok[s] && row[s] == r)
+#pragma unroll
+          for (int c = 0; c < PW; ++c) prow[c] = x[s][c];
+      __syncthreads();
+      const double pv = prow[jj];
+      if (!(fabs(pv) > thr) && !singular) {
+        singular = true;
+        sing_k = (int)(c0 + jj);
+      }
+      const double rp = 1.0 / pv;
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const double f = x[s][jj];
+#pragma unroll
+        for (int c = 0; c < PW; ++c) x[s][c] = c == jj ? -f * rp : fma(-f, prow[c] * rp, x[s][c]);
+        if (ok[s] && row[s] == r) {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) x[s][c] = c == jj ? rp : prow[c] * rp;
+          used[s] = true;
+        }
+      }
+      if (t == 0) {
+        ptv[sub * PW + jj] = r;
+        piv[c0 + jj] = r;
+      }
+    }
+    // G_t to the matrix, U_t = G_t - E_{R_t} kept in ub
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+      if (ok[s])
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+          if (c < nc) a[(int64_t)row[s] * n + c0 + c] = x[s][c];
+    __syncthreads();  // the sub-panel's pivots are complete
+#pragma unroll
+    for (int s = 0; s < RPT; ++s)
+      if (ok[s])
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+          if (c < nc) {
+            if (row[s] == ptv[sub * PW + c]) x[s][c] -= 1.0;
+            ub[(int64_t)row[s] * PB + sub * PW + c] = x[s][c];
+          }
+    // the earlier sub-panels' columns take U_t: rows R_t of them first
+    const int w0 = (int)(c0 - k0);
+    for (int idx = t; idx < nc * w0; idx += 1024) {
+      const int q = idx / w0, cc = idx - q * w0;
+      bfix[q][cc] = a[(int64_t)ptv[sub * PW + q] * n + k0 + cc];
+    }
+    __syncthreads();
+    if (w0 > 0)  // w0 is a multiple of 4
+#pragma unroll
+      for (int s = 0; s < RPT; ++s)
+        if (ok[s])
+          for (int c4 = 0; c4 < w0; c4 += 4) {
+            double *ar = a + (int64_t)row[s] * n + k0 + c4;
+            double v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = ar[c];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int q = 0; q < PW; ++q)
+                if (q < nc) v[c] = fma(x[s][q], bfix[q][c4 + c], v[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ar[c] = v[c];
+          }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < RPT; ++s)
+    if (ok[s]) used_g[row[s]] = used[s] ? 1 : 0;
+  if (t == 0 && singular) {
+    atomicOr(&status[0], 1);
+    atomicMin(&status[1], sing_k);
+  }
+}
+
+// The panel's pivot rows as they stood at their own sub-panel (columns
+// outside the panel): rb_p = A[r_p] + sum over the earlier sub-panels' rows q
+// of U[r_p][q] rb_q.  A block takes 8 columns; thread (p, column) holds row p,
+// and the sub-panels' rows are final, and published, one sub-panel at a time.
+template <int PW>
+__global__ __launch_bounds__(256) void k_cgj_stage(int64_t n, int64_t k0, int npb,
+                                                   const double *__restrict__ a,
+                                                   const int *__restrict__ piv,
+                                                   const double *__restrict__ ub,
+                                                   double *__restrict__ rb) {
+  constexpr int PB = kCoarsePB, JW = 256 / PB, NSUB = PB / PW;
+  __shared__ double ured[PB][PB + 1];
+  __shared__ double rbl[PB][JW];
+  for (int idx = threadIdx.x; idx < PB * PB; idx += 256) {
+    const int p = idx / PB, q = idx - p * PB;
+    ured[p][q] = (p < npb && q < npb) ? ub[(int64_t)piv[k0 + p] * PB + q] : 0.0;
+  }
+  const int p = threadIdx.x / JW, jl = threadIdx.x - p * JW;
+  const int64_t j = (int64_t)blockIdx.x * JW + jl;
+  const bool act = p < npb && j < n && !(j >= k0 && j < k0 + npb);
+  double v = act ? a[(int64_t)piv[k0 + p] * n + j] : 0.0;
+  const int tp = p / PW;
+  __syncthreads();
+  for (int t = 0; t < NSUB; ++t) {
+    if (tp == t) rbl[p][jl] = v;
+    __syncthreads();
+    if (tp > t)
+#pragma unroll
+      for (int q = 0; q < PW; ++q) v = fma(ured[p][t * PW + q], rbl[t * PW + q][jl], v);
+  }
+  if (act) rb[(int64_t)p * n + j] = v;
+}
+
+// A[i][j] += sum_q U[i][q] rb[q][j] for every column j outside the panel;
+// a block takes 64 rows and 256 columns, four rows at a time
+__global__ __launch_bounds__(256) void k_cgj_update(int64_t n, int64_t k0, int npb,
+                                                    double *__restrict__ a,
+                                                    const double *__restrict__ ub,
+                                                    const double *__restrict__ rb) {
+  constexpr int TR = 64;
+  __shared__ double us[TR][kCoarsePB];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * TR;
+  for (int idx = threadIdx.x; idx < TR * kCoarsePB; idx += 256) {
+    const int r = idx / kCoarsePB, q = idx - r * kCoarsePB;
+    const int64_t i = i0 + r;
+    us[r][q] = (i < n && q < npb) ? ub[i * kCoarsePB + q] : 0.0;
+  }
+  __syncthreads();
+  if (j >= n || (j >= k0 && j < k0 + npb)) return;
+  double rbj[kCoarsePB];
+#pragma unroll
+  for (int q = 0; q < kCoarsePB; ++q) rbj[q] = q < npb ? rb[q * n + j] : 0.0;
+  const int rows = (int)min<int64_t>(TR, n - i0);
+  int r = 0;
+  for (; r + 4 <= rows; r += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[(i0 + r + u) * n + j];
+#pragma unroll
+    for (int q = 0; q < kCoarsePB; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = fma(us[r + u][q], rbj[q], v[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[(i0 + r + u) * n + j] = v[u];
+  }
+  for (; r < rows; ++r) {
+    double v = a[(i0 + r) * n + j];
+#pragma unroll
+    for (int q = 0; q < kCoarsePB; ++q) v = fma(us[r][q], rbj[q], v);
+    a[(i0 + r) * n + j] = v;
+  }
+}
+
+__global__ void k_cgj_zero(int64_t n, int *__restrict__ v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) v[k] = 0;
+}
+
+__global__ void k_cgj_rinv(int64_t n, const int *__restrict__ piv, int *__restrict__ rinv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) rinv[piv[k]] = (int)k;
+}
+
+// out[i][j] = A^{-1}[i][j] = M[piv[i]][rinv[j]]
+__global__ __launch_bounds__(256) void k_cgj_out(int64_t n, const double *__restrict__ a,
+                                                 const int *__restrict__ piv,
+                                                 const int *__restrict__ rinv,
+                                                 double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j < n) out[i * n + j] = a[(int64_t)piv[i] * n + rinv[j]];
+}
+
 __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ a, int64_t n,
                                                 double *__restrict__ partial) {
   __shared__ double red[4];
@@ -1020,6 +1311,35 @@ void launch_gj_finish(int64_t n, const double *a, const int *piv, int *colmap, d
   hipLaunchKernelGGL(k_gj_colmap, dim3(1), dim3(64), 0, s, n, piv, colmap);
   hipLaunchKernelGGL(k_gj_out, dim3(grid_for(n, 256), (unsigned)n), dim3(256), 0, s, n, a, colmap,
                      out);
+}
+bool launch_coarse_gj_blocked(int64_t n, double *a, int *piv, int *iwork, double *ub, double *rb,
+                              double thr, int *status, double *out, hipStream_t s) {
+  const int rpt = (int)((n + 1023) / 1024);
+  if (n < 1 || rpt > 4) return false;
+  hipLaunchKernelGGL(k_cgj_zero, dim3(grid_for(n, 256)), dim3(256), 0, s, n, iwork);
+  for (int64_t k0 = 0; k0 < n; k0 += kCoarsePB) {
+    const int npb = (int)std::min<int64_t>(kCoarsePB, n - k0);
+    // rows per thread 1, 2: sub-panels of 8 columns; 3, 4: of 4 (registers)
+    if (rpt <= 2) {
+      if (rpt == 1)
+        hipLaunchKernelGGL((k_cgj_panel<1, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      else
+        hipLaunchKernelGGL((k_cgj_panel<2, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      hipLaunchKernelGGL((k_cgj_stage<8>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
+    } else {
+      if (rpt == 3)
+        hipLaunchKernelGGL((k_cgj_panel<3, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      else
+        hipLaunchKernelGGL((k_cgj_panel<4, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      hipLaunchKernelGGL((k_cgj_stage<4>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
+    }
+    hipLaunchKernelGGL(k_cgj_update, dim3(grid_for(n, 256), (unsigned)((n + 63) / 64)), dim3(256), 0,
+                       s, n, k0, npb, a, ub, rb);
+  }
+  hipLaunchKernelGGL(k_cgj_rinv, dim3(grid_for(n, 256)), dim3(256), 0, s, n, piv, iwork);
+  hipLaunchKernelGGL(k_cgj_out, dim3(grid_for(n, 256), (unsigned)n), dim3(256), 0, s, n, a, piv,
+                     iwork, out);
+  return true;
 }
 void launch_absmax(const double *a, int64_t n, double *partial, hipStream_t s) {
   hipLaunchKernelGGL(k_absmax, dim3(kRedBlocks), dim3(256), 0, s, a, n, partial);

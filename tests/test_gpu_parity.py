@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from fsigen import config_problem
+from fsigen.problem import SOLID_2D, SOLID_3D, make_problem
 from oracle import (Hierarchy, VankaData, local_matrices, prolongation, to_csr, vanka_sweep,
                     vcycle, deform_update)
 from oracle.step import solve_system
@@ -224,6 +225,28 @@ def test_coarse_solve_and_vcycle_fp64(ctx, probs, name):
         z = torch.empty_like(_t(r))
         fsimg.fsimg_vcycle(H.h, fsimg.FSIMG_FP64, _t(r), z)
         assert _rel(_np(z), vcycle(Ho, r)) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(2, 28), (3, 10), (3, 12)])
+def test_coarse_inverse_sizes(ctx, dim, n):
+    """Coarse inverses across the row layouts of the blocked Gauss-Jordan
+    (2D 28^2, two levels: 2 320 free coarse dofs, three rows per thread; 3D
+    10^3: 3 758, four rows per thread) and beyond its limit (3D 12^3: 6 550,
+    one pivot and one update launch per column), against the oracle's dense LU
+    of the coarse matrix."""
+    P = make_problem(dim, n, 2, SOLID_2D if dim == 2 else SOLID_3D, seed=0, systems=("mom",))
+    mats = P.system("mom")
+    mc = mats[-1]
+    Ho = Hierarchy([mc], [P.levels[-1].cells])
+    rng = np.random.default_rng(8)
+    with Hier(ctx, P, "mom") as H:
+        fsimg.fsimg_factor(H.h)
+        for _ in range(2):
+            rc = rng.standard_normal(mc.nrows * mc.b)
+            rc[mc.dirichlet.astype(bool)] = 0.0
+            xc = torch.empty_like(_t(rc))
+            fsimg.fsimg_coarse_solve(H.h, _t(rc), xc)
+            assert _rel(_np(xc), Ho.coarse_solve(rc)) < 1e-10
 
 
 def test_vcycle_mixed_close_to_fp64(ctx, probs):
