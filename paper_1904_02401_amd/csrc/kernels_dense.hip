@@ -293,6 +293,9 @@ __global__ __launch_bounds__(256) void k_patch_factor(int64_t npatch, int b, int
 //      K = 4 per 16x16 tile; P's own columns become G) to the tile column of
 //      panel P+1 first and publish P+1's columns, so that the panel wave
 //      eliminates P+1 while they update the other tile columns.
+// Occupancy: six waves per SIMD (at most 80 VGPRs; at n_p = 108 three are
+// spilled, in the write-out) lets three 8-wave workgroups share a CU, which
+// hides one patch's panel chain behind the others' MFMA work.
 typedef double fsimg_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double d4get(const fsimg_d4 &a, int v) {
@@ -338,7 +341,7 @@ __device__ __forceinline__ double recip_newton(double x) {
 }
 
 template <int NT, typename Tout>
-__global__ __launch_bounds__((NT + 1) * 64) __attribute__((amdgpu_waves_per_eu(NT >= 7 ? 5 : 6))) void
+__global__ __launch_bounds__((NT + 1) * 64) __attribute__((amdgpu_waves_per_eu(NT >= 8 ? 5 : 6))) void
 k_patch_factor_mfma(
     int64_t npatch, int b, int nl, int np, int npc, const int32_t *__restrict__ pnodes,
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
@@ -835,19 +838,25 @@ __global__ __launch_bounds__(256) void k_gj_out(int64_t n, const double *__restr
 }
 
 // ------------------------------- coarse inverse: blocked Gauss-Jordan (n <= 4096)
-// Exchange form, as for the patches: the pivot of column k is the largest
-// |a_ik| over the rows not yet used (ties to the lowest row), no rows move,
-// and A^{-1}[k][r_j] = M[r_k][j] at the end.  Panels of kCoarsePB columns,
-// each made of sub-panels t of PW columns with pivot rows R_t:
+// The kernels factor B = A^T, whose column-major storage is the row-major
+// array of A, so that a thread's accesses to its rows of a panel column are
+// contiguous across threads: B(i, j) = a[j n + i].  Exchange form, as for
+// the patches: the pivot of column k is the largest |b_ik| over the rows not
+// yet used (ties to the lowest row), no rows move, and B^{-1}[k][r_j] =
+// M[r_k][j] at the end, i.e. A^{-1}[x][y] = M[r_y][rinv(x)].  Panels of
+// kCoarsePB columns, each made of sub-panels t of PW columns with pivot rows
+// R_t (ub, U column-major: U(i, q) = ub[q n + i]):
 //   k_cgj_panel (one workgroup of 1024 threads, thread t owning rows
 //     t + 1024 s, s < RPT), per sub-panel: bring its columns up to date with
 //     the panel's earlier sub-panels (left-looking), eliminate them in
-//     registers, keep U_t = G_t - E_{R_t} (G_t: the processed columns), and
-//     apply U_t to the earlier sub-panels' columns;
+//     registers and keep U_t = G_t - E_{R_t} (G_t: the processed columns,
+//     left in the matrix);
 //   k_cgj_stage stages the pivot rows as they stood at their own sub-panel,
-//     rb_t = A[R_t] + sum_{t' < t} U_t'[R_t] rb_t';
-//   k_cgj_update applies A[:,Q] += sum_t U_t rb_t[:,Q] to every column
-//     outside the panel.
+//     rb_t = A[R_t] + sum_{t' < t} U_t'[R_t] rb_t' for the columns outside
+//     the panel; for a column of sub-panel s it starts from G_s and takes
+//     only the later sub-panels (rb_t = 0 for t <= s);
+//   k_cgj_update applies A += sum_t U_t rb_t to every column, which also
+//     brings each sub-panel's columns G_s up to the panel's end.
 constexpr int kCoarsePB = kCoarseStage;
 
 // pivot key of row i (< 65536): |a| with its 16 low mantissa bits replaced by
@@ -884,10 +893,9 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
                                                     double *__restrict__ ub, double thr,
                                                     int *__restrict__ status) {
   constexpr int PB = kCoarsePB, NSUB = PB / PW;
-  __shared__ unsigned long long red[16];
-  __shared__ double prow[PW];
+  __shared__ unsigned long long skey[2][16];
+  __shared__ double srow[2][16][PW];
   __shared__ double rbs[PW][PW];
-  __shared__ double bfix[PW][PB];
   __shared__ int ptv[PB];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int64_t kend = min(k0 + (int64_t)PB, n);
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
     for (int s = 0; s < RPT; ++s)
 #pragma unroll
       for (int c = 0; c < PW; ++c)
-        x[s][c] = (ok[s] && c < nc) ? a[(int64_t)row[s] * n + c0 + c] : 0.0;
+        x[s][c] = (ok[s] && c < nc) ? a[(c0 + c) * n + row[s]] : 0.0;
     // left-looking: the panel's earlier sub-panels, in order, each with its
     // pivot rows as they stand at that point
     for (int tt = 0; tt < sub; ++tt) {
@@ -930,7 +938,7 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
         if (ok[s])
 #pragma unroll
           for (int q = 0; q < PW; ++q) {
-            const double u = ub[(int64_t)row[s] * PB + tt * PW + q];
+            const double u = ub[(int64_t)(tt * PW + q) * n + row[s]];
 #pragma unroll
             for (int c = 0; c < PW; ++c) x[s][c] = fma(u, rbs[q][c], x[s][c]);
           }
@@ -939,24 +947,39 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
 #pragma unroll
     for (int jj = 0; jj < PW; ++jj) {
       if (jj >= nc) break;
+      // one barrier per step: every wave publishes its best candidate's key
+      // and row (double-buffered by step), every thread then picks the best
+      const int bsel = jj & 1;
       unsigned long long key = 0;
+      int bs = 0;
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
         const unsigned long long ks = coarse_key(x[s][jj], row[s], !used[s]);
-        key = ks > key ? ks : key;
+        if (ks > key) {
+          key = ks;
+          bs = s;
+        }
       }
-      key = wave_max_u64(key);
-      if (l == 0) red[w] = key;
+      const unsigned long long wkey = wave_max_u64(key);
+      if (wkey != 0 && key == wkey)
+#pragma unroll
+        for (int s = 0; s < RPT; ++s)
+          if (s == bs)
+#pragma unroll
+            for (int c = 0; c < PW; ++c) srow[bsel][w][c] = x[s][c];
+      if (l == 0) skey[bsel][w] = wkey;
       __syncthreads();
-      key = red[0];
-      for (int i = 1; i < 16; ++i) key = red[i] > key ? red[i] : key;
+      int wb = 0;
+      key = skey[bsel][0];
+      for (int i = 1; i < 16; ++i)
+        if (skey[bsel][i] > key) {
+          key = skey[bsel][i];
+          wb = i;
+        }
       const int r = 65535 - (int)(key & 0xFFFFull);
+      double prow[PW];
 #pragma unroll
-      for (int s = 0; s < RPT; ++s)
-        if (ok[s] && row[s] == r)
-#pragma unroll
-          for (int c = 0; c < PW; ++c) prow[c] = x[s][c];
-      __syncthreads();
+      for (int c = 0; c < PW; ++c) prow[c] = srow[bsel][wb][c];
       const double pv = prow[jj];
       if (!(fabs(pv) > thr) && !singular) {
         singular = true;
@@ -974,10 +997,8 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
           used[s] = true;
         }
       }
-      if (t == 0) {
-        ptv[sub * PW + jj] = r;
-        piv[c0 + jj] = r;
-      }
+      if (t == 0) ptv[sub * PW + jj] = r;  // LDS only: a global store here would
+                                           // hold up every following barrier
     }
     // G_t to the matrix, U_t = G_t - E_{R_t} kept in ub
 #pragma unroll
@@ -985,7 +1006,7 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
       if (ok[s])
 #pragma unroll
         for (int c = 0; c < PW; ++c)
-          if (c < nc) a[(int64_t)row[s] * n + c0 + c] = x[s][c];
+          if (c < nc) a[(c0 + c) * n + row[s]] = x[s][c];
     __syncthreads();  // the sub-panel's pivots are complete
 #pragma unroll
     for (int s = 0; s < RPT; ++s)
@@ -994,34 +1015,10 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
         for (int c = 0; c < PW; ++c)
           if (c < nc) {
             if (row[s] == ptv[sub * PW + c]) x[s][c] -= 1.0;
-            ub[(int64_t)row[s] * PB + sub * PW + c] = x[s][c];
+            ub[(int64_t)(sub * PW + c) * n + row[s]] = x[s][c];
           }
-    // the earlier sub-panels' columns take U_t: rows R_t of them first
-    const int w0 = (int)(c0 - k0);
-    for (int idx = t; idx < nc * w0; idx += 1024) {
-      const int q = idx / w0, cc = idx - q * w0;
-      bfix[q][cc] = a[(int64_t)ptv[sub * PW + q] * n + k0 + cc];
-    }
-    __syncthreads();
-    if (w0 > 0)  // w0 is a multiple of 4
-#pragma unroll
-      for (int s = 0; s < RPT; ++s)
-        if (ok[s])
-          for (int c4 = 0; c4 < w0; c4 += 4) {
-            double *ar = a + (int64_t)row[s] * n + k0 + c4;
-            double v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = ar[c];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-              for (int q = 0; q < PW; ++q)
-                if (q < nc) v[c] = fma(x[s][q], bfix[q][c4 + c], v[c]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) ar[c] = v[c];
-          }
-    __syncthreads();
   }
+  if (t < npb) piv[k0 + t] = ptv[t];
 #pragma unroll
   for (int s = 0; s < RPT; ++s)
     if (ok[s]) used_g[row[s]] = used[s] ? 1 : 0;
@@ -1031,10 +1028,11 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
   }
 }
 
-// The panel's pivot rows as they stood at their own sub-panel (columns
-// outside the panel): rb_p = A[r_p] + sum over the earlier sub-panels' rows q
-// of U[r_p][q] rb_q.  A block takes 8 columns; thread (p, column) holds row p,
-// and the sub-panels' rows are final, and published, one sub-panel at a time.
+// The panel's pivot rows as they stood at their own sub-panel: rb_p = A[r_p]
+// + sum over the earlier sub-panels' rows q of U[r_p][q] rb_q (for a column
+// of the panel's sub-panel s: from G_s, later sub-panels only).  A block
+// takes 8 columns; thread (p, column) holds row p, and the sub-panels' rows
+// are final, and published, one sub-panel at a time.
 template <int PW>
 __global__ __launch_bounds__(256) void k_cgj_stage(int64_t n, int64_t k0, int npb,
                                                    const double *__restrict__ a,
@@ -1046,13 +1044,16 @@ __global__ __launch_bounds__(256) void k_cgj_stage(int64_t n, int64_t k0, int np
   __shared__ double rbl[PB][JW];
   for (int idx = threadIdx.x; idx < PB * PB; idx += 256) {
     const int p = idx / PB, q = idx - p * PB;
-    ured[p][q] = (p < npb && q < npb) ? ub[(int64_t)piv[k0 + p] * PB + q] : 0.0;
+    ured[p][q] = (p < npb && q < npb) ? ub[(int64_t)q * n + piv[k0 + p]] : 0.0;
   }
   const int p = threadIdx.x / JW, jl = threadIdx.x - p * JW;
   const int64_t j = (int64_t)blockIdx.x * JW + jl;
-  const bool act = p < npb && j < n && !(j >= k0 && j < k0 + npb);
-  double v = act ? a[(int64_t)piv[k0 + p] * n + j] : 0.0;
   const int tp = p / PW;
+  // sub-panel of column j (-1 outside the panel): rows of it and of earlier
+  // sub-panels contribute nothing there
+  const int tj = (j >= k0 && j < k0 + npb) ? (int)(j - k0) / PW : -1;
+  const bool act = p < npb && j < n;
+  double v = (act && tp > tj) ? a[j * n + piv[k0 + p]] : 0.0;
   __syncthreads();
   for (int t = 0; t < NSUB; ++t) {
     if (tp == t) rbl[p][jl] = v;
@@ -1064,44 +1065,43 @@ __global__ __launch_bounds__(256) void k_cgj_stage(int64_t n, int64_t k0, int np
   if (act) rb[(int64_t)p * n + j] = v;
 }
 
-// A[i][j] += sum_q U[i][q] rb[q][j] for every column j outside the panel;
-// a block takes 64 rows and 256 columns, four rows at a time
-__global__ __launch_bounds__(256) void k_cgj_update(int64_t n, int64_t k0, int npb,
-                                                    double *__restrict__ a,
+// B(i, j) += sum_q U(i, q) rb[q][j] for every column j; a block takes 256
+// rows (one per thread, U(i, :) in registers) and kCgjCols columns
+constexpr int kCgjCols = 16;
+__global__ __launch_bounds__(256) void k_cgj_update(int64_t n, int npb, double *__restrict__ a,
                                                     const double *__restrict__ ub,
                                                     const double *__restrict__ rb) {
-  constexpr int TR = 64;
-  __shared__ double us[TR][kCoarsePB];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.y * TR;
-  for (int idx = threadIdx.x; idx < TR * kCoarsePB; idx += 256) {
-    const int r = idx / kCoarsePB, q = idx - r * kCoarsePB;
-    const int64_t i = i0 + r;
-    us[r][q] = (i < n && q < npb) ? ub[i * kCoarsePB + q] : 0.0;
+  constexpr int PB = kCoarsePB, TC = kCgjCols;
+  __shared__ double rbs[TC][PB];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.y * TC;
+  for (int idx = threadIdx.x; idx < TC * PB; idx += 256) {
+    const int c = idx / PB, q = idx - c * PB;
+    rbs[c][q] = (j0 + c < n && q < npb) ? rb[(int64_t)q * n + j0 + c] : 0.0;
   }
   __syncthreads();
-  if (j >= n || (j >= k0 && j < k0 + npb)) return;
-  double rbj[kCoarsePB];
+  if (i >= n) return;
+  double u[PB];
 #pragma unroll
-  for (int q = 0; q < kCoarsePB; ++q) rbj[q] = q < npb ? rb[q * n + j] : 0.0;
-  const int rows = (int)min<int64_t>(TR, n - i0);
-  int r = 0;
-  for (; r + 4 <= rows; r += 4) {
+  for (int q = 0; q < PB; ++q) u[q] = q < npb ? ub[(int64_t)q * n + i] : 0.0;
+  const int cols = (int)min<int64_t>(TC, n - j0);
+  int c = 0;
+  for (; c + 4 <= cols; c += 4) {
     double v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = a[(i0 + r + u) * n + j];
+    for (int e = 0; e < 4; ++e) v[e] = a[(j0 + c + e) * n + i];
 #pragma unroll
-    for (int q = 0; q < kCoarsePB; ++q)
+    for (int q = 0; q < PB; ++q)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = fma(us[r + u][q], rbj[q], v[u]);
+      for (int e = 0; e < 4; ++e) v[e] = fma(u[q], rbs[c + e][q], v[e]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[(i0 + r + u) * n + j] = v[u];
+    for (int e = 0; e < 4; ++e) a[(j0 + c + e) * n + i] = v[e];
   }
-  for (; r < rows; ++r) {
-    double v = a[(i0 + r) * n + j];
+  for (; c < cols; ++c) {
+    double v = a[(j0 + c) * n + i];
 #pragma unroll
-    for (int q = 0; q < kCoarsePB; ++q) v = fma(us[r][q], rbj[q], v);
-    a[(i0 + r) * n + j] = v;
+    for (int q = 0; q < PB; ++q) v = fma(u[q], rbs[c][q], v);
+    a[(j0 + c) * n + i] = v;
   }
 }
 
@@ -1115,14 +1115,14 @@ __global__ void k_cgj_rinv(int64_t n, const int *__restrict__ piv, int *__restri
   if (k < n) rinv[piv[k]] = (int)k;
 }
 
-// out[i][j] = A^{-1}[i][j] = M[piv[i]][rinv[j]]
+// out[x][y] = A^{-1}[x][y] = M(r_y, rinv(x)) = a[rinv(x) n + r_y]
 __global__ __launch_bounds__(256) void k_cgj_out(int64_t n, const double *__restrict__ a,
                                                  const int *__restrict__ piv,
                                                  const int *__restrict__ rinv,
                                                  double *__restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = blockIdx.y;
-  if (j < n) out[i * n + j] = a[(int64_t)piv[i] * n + rinv[j]];
+  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t x = blockIdx.y;
+  if (y < n) out[x * n + y] = a[(int64_t)rinv[x] * n + piv[y]];
 }
 
 __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ a, int64_t n,
@@ -1319,22 +1319,21 @@ bool launch_coarse_gj_blocked(int64_t n, double *a, int *piv, int *iwork, double
   hipLaunchKernelGGL(k_cgj_zero, dim3(grid_for(n, 256)), dim3(256), 0, s, n, iwork);
   for (int64_t k0 = 0; k0 < n; k0 += kCoarsePB) {
     const int npb = (int)std::min<int64_t>(kCoarsePB, n - k0);
-    // rows per thread 1, 2: sub-panels of 8 columns; 3, 4: of 4 (registers)
-    if (rpt <= 2) {
+    // rows per thread 1 to 3: sub-panels of 8 columns; 4: of 4 (registers)
+    if (rpt <= 3) {
       if (rpt == 1)
         hipLaunchKernelGGL((k_cgj_panel<1, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
-      else
+      else if (rpt == 2)
         hipLaunchKernelGGL((k_cgj_panel<2, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      else
+        hipLaunchKernelGGL((k_cgj_panel<3, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
       hipLaunchKernelGGL((k_cgj_stage<8>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
     } else {
-      if (rpt == 3)
-        hipLaunchKernelGGL((k_cgj_panel<3, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
-      else
-        hipLaunchKernelGGL((k_cgj_panel<4, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      hipLaunchKernelGGL((k_cgj_panel<4, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
       hipLaunchKernelGGL((k_cgj_stage<4>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
     }
-    hipLaunchKernelGGL(k_cgj_update, dim3(grid_for(n, 256), (unsigned)((n + 63) / 64)), dim3(256), 0,
-                       s, n, k0, npb, a, ub, rb);
+    hipLaunchKernelGGL(k_cgj_update, dim3(grid_for(n, 256), (unsigned)grid_for(n, kCgjCols)),
+                       dim3(256), 0, s, n, npb, a, ub, rb);
   }
   hipLaunchKernelGGL(k_cgj_rinv, dim3(grid_for(n, 256)), dim3(256), 0, s, n, piv, iwork);
   hipLaunchKernelGGL(k_cgj_out, dim3(grid_for(n, 256), (unsigned)n), dim3(256), 0, s, n, a, piv,
