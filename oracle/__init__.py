@@ -2,7 +2,7 @@
 
 Plain, slow, obviously-correct NumPy/SciPy implementation of what the GPU
 library computes: block-CSR products, the additive Vanka smoother (eq. vanka,
-Sec. 4.3), Q2 grid transfers, the geometric multigrid V-cycle (Sec. 4.3 (II)),
+Sec. 4.3), the block ILU(0) smoother (Sec. 5.5's comparison smoother), Q2 grid transfers, the geometric multigrid V-cycle (Sec. 4.3 (II)),
 flexible GMRES (Sec. 4.3 (I)), the condensed deformation update (Sec. 3.1,
 eq. problem:2) and the ALE extension solve (eq. problem:3).
 
@@ -19,11 +19,12 @@ from .patches import element_patches, patch_dofs
 from .vanka import local_matrices, local_inverses, vanka_sweep, VankaData
 from .transfer import prolongation_1d, prolongation
 from .mg import Hierarchy, vcycle
+from .ilu import BlockILU, ilu_sweep
 from .fgmres import fgmres
 from .deform import deform_update
 from .step import newton_step_solve
 
 __all__ = ["to_csr", "matvec", "masked_residual", "element_patches", "patch_dofs",
            "local_matrices", "local_inverses", "vanka_sweep", "VankaData", "prolongation_1d",
-           "prolongation", "Hierarchy", "vcycle", "fgmres", "deform_update",
+           "prolongation", "Hierarchy", "vcycle", "BlockILU", "ilu_sweep", "fgmres", "deform_update",
            "newton_step_solve"]

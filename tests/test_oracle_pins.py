@@ -404,3 +404,94 @@ def test_block_patches_converge_where_element_patches_stall():
         its[patches] = (info["iters"], info["converged"])
     assert its["block"][1] and its["block"][0] <= 40
     assert not its["element"][1]
+
+
+# ------------------------------------------------------------ block ILU(0) smoother
+class _BSR:
+    def __init__(self, rowptr, colind, vals, b):
+        self.rowptr, self.colind, self.vals, self.b = rowptr, colind, vals, b
+        self.nrows = rowptr.shape[0] - 1
+
+
+def _bsr_from_blocks(blocks, n, b):
+    """blocks: dict (i, j) -> b x b array."""
+    rows = [sorted(j for (i, j) in blocks if i == r) for r in range(n)]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum([len(r) for r in rows])
+    colind = np.array([j for r in rows for j in r], dtype=np.int64)
+    vals = np.stack([blocks[(r, j)] for r in range(n) for j in rows[r]]).reshape(-1)
+    return _BSR(rowptr, colind, vals, b)
+
+
+def test_ilu_is_exact_lu_without_fill_in():
+    """A block-tridiagonal pattern produces no fill-in, so ILU(0) is the
+    exact block LU and one undamped ILU step from zero solves the system."""
+    from oracle import BlockILU, ilu_sweep
+    rng = np.random.default_rng(21)
+    n, b = 30, 3
+    blocks = {}
+    for i in range(n):
+        blocks[(i, i)] = rng.standard_normal((b, b)) + 6.0 * np.eye(b)
+        if i > 0:
+            blocks[(i, i - 1)] = rng.standard_normal((b, b))
+            blocks[(i - 1, i)] = rng.standard_normal((b, b))
+    m = _bsr_from_blocks(blocks, n, b)
+    A = to_csr(m)
+    rhs = rng.standard_normal(n * b)
+    ref = np.linalg.solve(A.toarray(), rhs)
+    ilu = BlockILU(m)
+    assert np.linalg.norm(ilu.solve(rhs) - ref) <= 1e-12 * np.linalg.norm(ref)
+    x = ilu_sweep(A, rhs, np.zeros(n * b), ilu, np.zeros(n * b, dtype=bool))
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_ilu_block_diagonal_is_block_jacobi():
+    from oracle import BlockILU
+    rng = np.random.default_rng(22)
+    n, b = 12, 4
+    blocks = {(i, i): rng.standard_normal((b, b)) + 5.0 * np.eye(b) for i in range(n)}
+    m = _bsr_from_blocks(blocks, n, b)
+    d = rng.standard_normal(n * b)
+    ref = np.concatenate([np.linalg.solve(blocks[(i, i)], d[i * b:(i + 1) * b]) for i in range(n)])
+    assert np.abs(BlockILU(m).solve(d) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_ilu_product_reproduces_the_matrix_on_its_pattern():
+    """The defining property of ILU(0): (L U)_ij = A_ij on every block of the
+    pattern (the discarded fill-in lies outside it), on a 2D Q2 momentum
+    matrix with Dirichlet rows; L unit block-lower, U block-upper."""
+    from oracle import BlockILU
+    P = make_problem(2, 8, 2, SOLID_2D, seed=0, systems=("mom",))
+    m = P.levels[0].systems["mom"]
+    A = to_csr(m).toarray()
+    L, U = BlockILU(m).lower_upper_dense()
+    b = m.b
+    assert np.allclose(np.tril(L, -1) + np.eye(L.shape[0]), L)  # unit lower
+    LU = L @ U
+    on = np.zeros_like(A, dtype=bool)
+    for i in range(m.nrows):
+        for p in range(m.rowptr[i], m.rowptr[i + 1]):
+            j = m.colind[p]
+            on[i * b:(i + 1) * b, j * b:(j + 1) * b] = True
+    assert np.abs(LU - A)[on].max() <= 1e-11 * np.abs(A).max()
+    assert np.abs(LU - A)[~on].max() > 1e-8 * np.abs(A).max()  # fill-in was dropped
+
+
+def test_ilu_smoothed_mg_converges_mesh_independently():
+    """FGMRES with an ILU-smoothed V-cycle reaches 1e-8 (true residual checked
+    with SciPy) in few, mesh-independent iterations, no more than with Vanka."""
+    its = []
+    for n, nl in ((16, 2), (32, 3)):
+        P = make_problem(2, n, nl, SOLID_2D, seed=0, systems=("mom",))
+        cells = [l.cells for l in P.levels]
+        mats = P.system("mom")
+        H = Hierarchy(mats, cells, smoother="ilu")
+        x, info, _ = solve_system(mats, cells, P.rhs["mom"], rtol=1e-8, H=H)
+        A = to_csr(mats[0])
+        r = P.rhs["mom"] - A @ x
+        r[mats[0].dirichlet.astype(bool)] = 0.0
+        assert info["converged"] and np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(P.rhs["mom"])
+        _, info_v, _ = solve_system(mats, cells, P.rhs["mom"], rtol=1e-8, weighting="mult")
+        assert info["iters"] <= info_v["iters"]
+        its.append(info["iters"])
+    assert its[1] - its[0] <= 2 and its[1] <= 12
