@@ -88,6 +88,16 @@ typedef enum { FSIMG_WEIGHT_PLAIN = 0, FSIMG_WEIGHT_MULT = 1 } fsimg_weighting;
    With MULT weighting a dof's correction is divided by the number of
    patches containing it.  BLOCK needs the GATHER schedule. */
 typedef enum { FSIMG_PATCH_ELEMENT = 0, FSIMG_PATCH_BLOCK = 1 } fsimg_patches;
+/* Multigrid smoother.  VANKA: the additive Vanka iteration above (Sec. 4.3).
+   ILU: the comparison smoother of Sec. 5.5, read as a block incomplete LU
+   without fill-in on the matrix's block pattern (one b x b block per coupled
+   node pair, the matrix's node order), x += omega_ilu (L U)^{-1} (b - A x)
+   with identity rows kept.  The factors are computed in FP64 by fsimg_factor
+   (level-scheduled: rows whose lower-triangle couplings are all factored go
+   together) and applied by level-scheduled triangular solves.  ILU
+   hierarchies are solved by fsimg_solve only: fsimg_solve_batch and the
+   server reject them (ERR_ARG); the Vanka options are then ignored. */
+typedef enum { FSIMG_SMOOTHER_VANKA = 0, FSIMG_SMOOTHER_ILU = 1 } fsimg_smoother;
 
 /* One multigrid level; level 0 = finest.  Host arrays, copied. */
 typedef struct {
@@ -119,6 +129,8 @@ typedef struct {
                           HIP graph captured once per batch composition; 0: launch eagerly.
                           Results are identical either way; profiling runs launch eagerly */
   int vanka_patches;   /* fsimg_patches */
+  int smoother;        /* fsimg_smoother */
+  double omega_ilu;    /* ILU damping (default 1: the undamped incomplete-LU step) */
 } fsimg_opts;
 
 typedef struct {
@@ -202,7 +214,8 @@ fsimg_status fsimg_solve(fsimg_hier *h, const double *b_dev, double *x_dev, fsim
    size, dimension and solver options; sizes and level counts may differ.
    stats: array of n (may be NULL).  Returns OK if every instance converged,
    else the first failing status (per-instance status in stats).
-   fsimg_solve with the GATHER schedule is this call with n = 1. */
+   fsimg_solve with the GATHER schedule is this call with n = 1.  ERR_ARG for
+   hierarchies with the ILU smoother. */
 fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *const *b_dev,
                                double *const *x_dev, fsimg_stats *stats, void *stream);
 
@@ -226,10 +239,20 @@ fsimg_status fsimg_level_apply(fsimg_hier *h, int level, int precision, const vo
 /* d = b - A_l x, zero at identity rows. */
 fsimg_status fsimg_level_residual(fsimg_hier *h, int level, int precision, const void *b_dev,
                                   const void *x_dev, void *d_dev, void *stream);
-/* One Vanka step on level l (requires fsimg_factor):
-   d = b - A x; x += omega * W * sum_i R_i^T A_i^{-1} R_i d, identity dofs kept. */
+/* One Vanka step on level l (requires fsimg_factor; ERR_STATE on an ILU
+   hierarchy): d = b - A x; x += omega * W * sum_i R_i^T A_i^{-1} R_i d,
+   identity dofs kept. */
 fsimg_status fsimg_vanka_step(fsimg_hier *h, int level, int precision, const void *b_dev,
                               void *x_dev, void *stream);
+/* One ILU step on level l of an ILU hierarchy (requires fsimg_factor; else
+   ERR_STATE): d = b - A x; x += omega_ilu (L U)^{-1} d, identity dofs kept. */
+fsimg_status fsimg_ilu_step(fsimg_hier *h, int level, int precision, const void *b_dev,
+                            void *x_dev, void *stream);
+/* The FP64 ILU factors of level l, copied to the host array out
+   [nnzb * b * b], in the matrix's block-CSR layout: the blocks left of the
+   diagonal hold L (unit diagonal implied), the others U.  ERR_STATE if the
+   hierarchy is not an ILU one or not factored. */
+fsimg_status fsimg_ilu_factors(fsimg_hier *h, int level, double *out);
 /* r_c = R r_f from level l to l+1 (R = P^T), zero at coarse identity rows. */
 fsimg_status fsimg_restrict(fsimg_hier *h, int level, int precision, const void *rf_dev,
                             void *rc_dev, void *stream);
@@ -308,8 +331,9 @@ typedef struct {
 
 typedef struct fsimg_server fsimg_server;
 
-/* opts: solver options of every hierarchy the server creates; max_active:
-   admitted requests at most (0 = no limit).  Host arrays of a submitted
+/* opts: solver options of every hierarchy the server creates (the Vanka
+   smoother: ERR_ARG for ILU); max_active: admitted requests at most (0 = no
+   limit).  Host arrays of a submitted
    request are read at admission (the descriptors, right-hand sides, node
    mask) and, with n_states > 1, the momentum values of every state again at
    each change of state: the caller keeps them valid until the request

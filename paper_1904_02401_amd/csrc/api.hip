@@ -333,7 +333,13 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
   const size_t ts = mixed ? 4 : 8;
   size_t s = (size_t)(L.nrows + 1) * 4 + (size_t)L.nnzb * 4 + (size_t)L.nnzb * b * b * 8 + (size_t)n;
   if (mixed) s += (size_t)L.nnzb * b * b * 4;
-  if (!coarse) {
+  if (!coarse && o.smoother == FSIMG_SMOOTHER_ILU) {
+    s += (size_t)npatch * nl * 4 + (size_t)(L.nrows + 1) * 4 + (size_t)ngidx * 4;
+    s += (size_t)L.nrows * ts + (size_t)3 * n * ts;  // scale; r, x, d
+    s += (size_t)L.nnzb * b * b * 8 + (size_t)L.nrows * b * b * 8;  // FP64 factors, U_ii^-1
+    if (mixed) s += (size_t)L.nnzb * b * b * 4 + (size_t)L.nrows * b * b * 4;
+    s += (size_t)3 * L.nrows * 4 + (size_t)n * ts;  // diagonal positions, schedules, work
+  } else if (!coarse) {
     s += (size_t)npatch * nl * 4 + (size_t)(L.nrows + 1) * 4 + (size_t)ngidx * 4;
     s += (size_t)npatch * np * npc_for(np, (int)ts) * ts;
     s += (size_t)L.nrows * ts;                       // scale
@@ -423,6 +429,30 @@ void vanka_apply(fsimg_hier *h, int l, const T *d, T *x, bool assign, hipStream_
   }
 }
 
+template <typename T> struct IluSel;
+template <> struct IluSel<double> {
+  static const double *F(const DevLevel &L) { return L.ilu64; }
+  static const double *dinv(const DevLevel &L) { return L.dinv64; }
+  static double *work(DevLevel &L) { return L.iw64; }
+};
+template <> struct IluSel<float> {
+  static const float *F(const DevLevel &L) { return L.ilu32; }
+  static const float *dinv(const DevLevel &L) { return L.dinv32; }
+  static float *work(DevLevel &L) { return L.iw32; }
+};
+
+// one smoothing step with the residual d already computed (Vanka or ILU)
+template <typename T>
+void smooth_apply(fsimg_hier *h, int l, const T *d, T *x, bool assign, hipStream_t s) {
+  if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
+    DevLevel &L = h->lev[l];
+    launch_ilu_apply<T>(L, IluSel<T>::F(L), IluSel<T>::dinv(L), IluSel<T>::work(L), d,
+                        (T)h->opts.omega_ilu, assign, x, s);
+    return;
+  }
+  vanka_apply<T>(h, l, d, x, assign, s);
+}
+
 void coarse_solve64(fsimg_hier *h, const double *r, double *x, hipStream_t s) {
   launch_coarse_gemv(h->lev.back(), r, x, s);
 }
@@ -446,10 +476,10 @@ void vcycle(fsimg_hier *h, int l, const T *r, T *x, hipStream_t s) {
   if (nu1 == 0) launch_fill<T>(x, F.n, T(0), s);
   for (int k = 0; k < nu1; ++k) {
     if (k == 0) {
-      vanka_apply<T>(h, l, r, x, true, s);  // x = 0: the residual is r
+      smooth_apply<T>(h, l, r, x, true, s);  // x = 0: the residual is r
     } else {
       residual<T>(h, l, r, x, d, s);
-      vanka_apply<T>(h, l, d, x, false, s);
+      smooth_apply<T>(h, l, d, x, false, s);
     }
   }
   residual<T>(h, l, r, x, d, s);
@@ -459,7 +489,7 @@ void vcycle(fsimg_hier *h, int l, const T *r, T *x, hipStream_t s) {
   launch_prolong_add<T>(F, C, Sel<T>::x(C), x, s);
   for (int k = 0; k < nu2; ++k) {
     residual<T>(h, l, r, x, d, s);
-    vanka_apply<T>(h, l, d, x, false, s);
+    smooth_apply<T>(h, l, d, x, false, s);
   }
 }
 
@@ -506,6 +536,8 @@ void fsimg_default_opts(fsimg_opts *o) {
   o->profile = 0;
   o->graphs = 1;
   o->vanka_patches = FSIMG_PATCH_ELEMENT;
+  o->smoother = FSIMG_SMOOTHER_VANKA;
+  o->omega_ilu = 1.0;
 }
 
 fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **out) {
@@ -544,6 +576,10 @@ static fsimg_status validate_opts(const fsimg_opts *o) {
   if (o->vanka_patches < 0 || o->vanka_patches > 1) return fail(FSIMG_ERR_ARG, "bad patch shape");
   if (o->vanka_patches == FSIMG_PATCH_BLOCK && o->vanka_schedule != FSIMG_VANKA_GATHER)
     return fail(FSIMG_ERR_ARG, "block patches need the GATHER schedule");
+  if (o->smoother != FSIMG_SMOOTHER_VANKA && o->smoother != FSIMG_SMOOTHER_ILU)
+    return fail(FSIMG_ERR_ARG, "bad smoother");
+  if (o->smoother == FSIMG_SMOOTHER_ILU && !(o->omega_ilu > 0.0))
+    return fail(FSIMG_ERR_ARG, "omega_ilu must be > 0");
   return FSIMG_OK;
 }
 
@@ -593,6 +629,67 @@ void fsimg_hier_destroy(fsimg_hier *h) {
   if (h->hpin) (void)hipHostFree(h->hpin);
   if (h->hstatus) (void)hipHostFree(h->hstatus);
   delete h;
+}
+
+// Block ILU(0) data of one level: factor / inverse storage, the diagonal
+// positions and the level schedules of the lower and upper triangles (level of
+// row i = 1 + the largest level among the rows it depends on).
+fsimg_status ilu_setup(fsimg_hier *h, const fsimg_level_desc &D, DevLevel &L, bool mixed,
+                       hipStream_t s) {
+  const int64_t n = D.nrows, bb = (int64_t)D.block * D.block;
+  std::vector<int32_t> diag(n), lev(n);
+  int maxrow = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t b0 = D.rowptr[i], b1 = D.rowptr[i + 1];
+    maxrow = std::max(maxrow, (int)(b1 - b0));
+    diag[i] = -1;
+    for (int32_t p = b0; p < b1; ++p)
+      if (D.colind[p] == i) diag[i] = p;
+    if (diag[i] < 0) return fail(FSIMG_ERR_ARG, "ILU: block row without a diagonal block");
+  }
+  if (maxrow > kIluMaxRow)
+    return fail(FSIMG_ERR_ARG, "ILU: block rows longer than " + std::to_string(kIluMaxRow));
+  L.ilu_maxrow = maxrow;
+  auto schedule = [&](bool lower, std::vector<int32_t> &order, std::vector<int64_t> &ptr) {
+    int nl = 0;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = lower ? t : n - 1 - t;
+      int v = 0;
+      for (int32_t p = D.rowptr[i]; p < D.rowptr[i + 1]; ++p) {
+        const int32_t k = D.colind[p];
+        if (lower ? k < i : k > i) v = std::max(v, lev[k] + 1);
+      }
+      lev[i] = v;
+      nl = std::max(nl, v + 1);
+    }
+    ptr.assign(nl + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++ptr[lev[i] + 1];
+    for (int v = 0; v < nl; ++v) ptr[v + 1] += ptr[v];
+    std::vector<int64_t> at(ptr.begin(), ptr.end() - 1);
+    order.resize(n);
+    for (int64_t i = 0; i < n; ++i) order[at[lev[i]]++] = (int32_t)i;  // ascending within a level
+  };
+  std::vector<int32_t> lo, uo;
+  schedule(true, lo, L.lptr);
+  schedule(false, uo, L.uptr);
+  FSIMG_TRY(dalloc(h, &L.ilu64, D.nnzb * bb));
+  FSIMG_TRY(dalloc(h, &L.dinv64, n * bb));
+  FSIMG_TRY(dalloc(h, &L.idiag, n));
+  FSIMG_TRY(dalloc(h, &L.lorder, n));
+  FSIMG_TRY(dalloc(h, &L.uorder, n));
+  if (mixed) {
+    FSIMG_TRY(dalloc(h, &L.ilu32, D.nnzb * bb));
+    FSIMG_TRY(dalloc(h, &L.dinv32, n * bb));
+    FSIMG_TRY(dalloc(h, &L.iw32, n * D.block));
+  } else {
+    FSIMG_TRY(dalloc(h, &L.iw64, n * D.block));
+  }
+  if (hipMemcpyAsync(L.idiag, diag.data(), n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(L.lorder, lo.data(), n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(L.uorder, uo.data(), n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FSIMG_ERR_HIP, "ILU schedule upload");
+  return FSIMG_OK;
 }
 
 fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, int nlev,
@@ -704,28 +801,34 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
           mult = std::max(1, P.gptr[i + 1] - P.gptr[i]);
         sc[i] = opts->vanka_weighting == FSIMG_WEIGHT_MULT ? 1.0 / mult : 1.0;
       }
+      const bool vanka = opts->smoother == FSIMG_SMOOTHER_VANKA;
       if (mixed) {
         std::vector<float> sf(sc.begin(), sc.end());
         FSIMG_CHK(dalloc(h, &L.scale32, L.nrows));
         FSIMG_HIPC(hipMemcpyAsync(L.scale32, sf.data(), L.nrows * 4, hipMemcpyHostToDevice, s));
-        FSIMG_CHK(dalloc(h, &L.inv32, L.npatch * L.np * L.npc32));
-        if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv32, B.npatch * B.np * B.npc32));
+        if (vanka) {
+          FSIMG_CHK(dalloc(h, &L.inv32, L.npatch * L.np * L.npc32));
+          if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv32, B.npatch * B.np * B.npc32));
+          FSIMG_CHK(dalloc(h, &L.Y32, ylen));
+        }
         FSIMG_CHK(dalloc(h, &L.r32, L.n));
         FSIMG_CHK(dalloc(h, &L.x32, L.n));
         FSIMG_CHK(dalloc(h, &L.d32, L.n));
-        FSIMG_CHK(dalloc(h, &L.Y32, ylen));
         FSIMG_HIPC(hipStreamSynchronize(s));
       } else {
         FSIMG_CHK(dalloc(h, &L.scale64, L.nrows));
         FSIMG_HIPC(hipMemcpyAsync(L.scale64, sc.data(), L.nrows * 8, hipMemcpyHostToDevice, s));
-        FSIMG_CHK(dalloc(h, &L.inv64, L.npatch * L.np * L.npc64));
-        if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv64, B.npatch * B.np * B.npc64));
+        if (vanka) {
+          FSIMG_CHK(dalloc(h, &L.inv64, L.npatch * L.np * L.npc64));
+          if (B.npatch > 0) FSIMG_CHK(dalloc(h, &B.inv64, B.npatch * B.np * B.npc64));
+          FSIMG_CHK(dalloc(h, &L.Y64, ylen));
+        }
         FSIMG_CHK(dalloc(h, &L.r64, L.n));
         FSIMG_CHK(dalloc(h, &L.x64, L.n));
         FSIMG_CHK(dalloc(h, &L.d64, L.n));
-        FSIMG_CHK(dalloc(h, &L.Y64, ylen));
         FSIMG_HIPC(hipStreamSynchronize(s));
       }
+      if (!vanka) FSIMG_CHK(ilu_setup(h, D, L, mixed, s));
     } else {
       std::vector<int32_t> cf, ci(L.n, -1);
       for (int64_t i = 0; i < L.n; ++i)
@@ -839,6 +942,32 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   for (int l = 0; l + 1 < nlev; ++l) {
     DevLevel &L = h->lev[l];
     L.factor_ms = 0.0;
+    if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
+      const int64_t nv = L.nnzb * L.b * L.b;
+      const int init[2] = {0, INT_MAX};
+      FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
+      FSIMG_HIP(hipMemcpyAsync(L.ilu64, L.vals64, nv * 8, hipMemcpyDeviceToDevice, s));
+      if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
+      launch_ilu_factor(L, h->dstatus, s);
+      FSIMG_HIP(hipGetLastError());
+      if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
+      if (mixed) {
+        launch_cast_d2f(L.ilu64, L.ilu32, nv, s);
+        launch_cast_d2f(L.dinv64, L.dinv32, L.nrows * L.b * L.b, s);
+      }
+      FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      FSIMG_HIP(hipStreamSynchronize(s));
+      if (prof) {
+        float ms = 0.0f;
+        FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        L.factor_ms = ms;
+      }
+      if (h->hstatus[0])
+        return fail(FSIMG_ERR_SINGULAR, "singular diagonal block in the ILU factors of level " +
+                                            std::to_string(l) + ": block row " +
+                                            std::to_string(h->hstatus[1]));
+      continue;
+    }
     for (int g = 0; g < 2; ++g) {  // element patches, then block patches
       const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
       if (np_ == 0) continue;
@@ -920,6 +1049,9 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
 fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *const *b_dev,
                                double *const *x_dev, fsimg_stats *stats, void *stream) {
   if (n < 1 || !hiers || !hiers[0]) return fail(FSIMG_ERR_ARG, "empty batch");
+  for (int k = 0; k < n; ++k)
+    if (hiers[k] && hiers[k]->opts.smoother != FSIMG_SMOOTHER_VANKA)
+      return fail(FSIMG_ERR_ARG, "batched solves take Vanka hierarchies only (ILU: fsimg_solve)");
   FSIMG_HIP(hipSetDevice(hiers[0]->ctx->device));
   return solve_batch(hiers[0]->ctx, n, hiers, b_dev, x_dev, stats, static_cast<hipStream_t>(stream));
 }
@@ -928,7 +1060,8 @@ fsimg_status fsimg_solve(fsimg_hier *h, const double *b, double *x, fsimg_stats 
   if (!h || !b || !x) return fail(FSIMG_ERR_ARG, "null argument");
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run before fsimg_solve");
   FSIMG_HIP(hipSetDevice(h->ctx->device));
-  if (h->opts.vanka_schedule == FSIMG_VANKA_GATHER)  // the batched driver with one instance
+  if (h->opts.vanka_schedule == FSIMG_VANKA_GATHER &&
+      h->opts.smoother == FSIMG_SMOOTHER_VANKA)  // the batched driver with one instance
     return solve_batch(h->ctx, 1, &h, &b, &x, stats, static_cast<hipStream_t>(stream));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
@@ -1102,6 +1235,8 @@ fsimg_status fsimg_vanka_step(fsimg_hier *h, int level, int precision, const voi
   FSIMG_TRY(check_level(h, level, false));
   FSIMG_TRY(check_prec(h, precision));
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
+  if (h->opts.smoother != FSIMG_SMOOTHER_VANKA)
+    return fail(FSIMG_ERR_STATE, "the hierarchy uses the ILU smoother");
   if (!b || !x) return fail(FSIMG_ERR_ARG, "null vector");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (precision == FSIMG_FP64) {
@@ -1112,6 +1247,38 @@ fsimg_status fsimg_vanka_step(fsimg_hier *h, int level, int precision, const voi
     vanka_apply<float>(h, level, h->lev[level].d32, (float *)x, false, s);
   }
   FSIMG_HIP(hipGetLastError());
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_ilu_step(fsimg_hier *h, int level, int precision, const void *b, void *x,
+                            void *stream) {
+  FSIMG_TRY(check_level(h, level, false));
+  FSIMG_TRY(check_prec(h, precision));
+  if (h->opts.smoother != FSIMG_SMOOTHER_ILU)
+    return fail(FSIMG_ERR_STATE, "the hierarchy uses the Vanka smoother");
+  if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
+  if (!b || !x) return fail(FSIMG_ERR_ARG, "null vector");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == FSIMG_FP64) {
+    residual<double>(h, level, (const double *)b, (const double *)x, h->lev[level].d64, s);
+    smooth_apply<double>(h, level, h->lev[level].d64, (double *)x, false, s);
+  } else {
+    residual<float>(h, level, (const float *)b, (const float *)x, h->lev[level].d32, s);
+    smooth_apply<float>(h, level, h->lev[level].d32, (float *)x, false, s);
+  }
+  FSIMG_HIP(hipGetLastError());
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_ilu_factors(fsimg_hier *h, int level, double *out) {
+  FSIMG_TRY(check_level(h, level, false));
+  if (h->opts.smoother != FSIMG_SMOOTHER_ILU)
+    return fail(FSIMG_ERR_STATE, "the hierarchy uses the Vanka smoother");
+  if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
+  if (!out) return fail(FSIMG_ERR_ARG, "null out");
+  FSIMG_HIP(hipSetDevice(h->ctx->device));
+  const DevLevel &L = h->lev[level];
+  FSIMG_HIP(hipMemcpy(out, L.ilu64, (size_t)L.nnzb * L.b * L.b * 8, hipMemcpyDeviceToHost));
   return FSIMG_OK;
 }
 
@@ -1164,6 +1331,8 @@ fsimg_status fsimg_patch_inverse(fsimg_hier *h, int level, int64_t patch, double
                                  void *stream) {
   FSIMG_TRY(check_level(h, level, false));
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
+  if (h->opts.smoother != FSIMG_SMOOTHER_VANKA)
+    return fail(FSIMG_ERR_STATE, "the hierarchy uses the ILU smoother");
   DevLevel &L = h->lev[level];
   if (patch < 0 || patch >= L.npatch || !out) return fail(FSIMG_ERR_ARG, "bad patch index");
   hipStream_t s = static_cast<hipStream_t>(stream);

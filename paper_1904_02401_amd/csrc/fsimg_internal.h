@@ -31,6 +31,7 @@ constexpr int spmv_group_rows(int b, int word) {
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
 constexpr int kCoarseStage = 32;  // panel width of the coarse Gauss-Jordan (staged pivot rows)
+constexpr int kIluMaxRow = 256;   // longest block row the ILU factorisation stages in LDS
 
 // Block patches (2 x 2 (x 2) elements, 5^d nodes) of a level: the second
 // patch group, empty unless requested.  Their corrections follow those of
@@ -86,6 +87,18 @@ struct DevLevel {
   // hierarchy so that refactoring never allocates
   double *gj_a = nullptr, *gj_rowk = nullptr, *gj_colk = nullptr, *gj_part = nullptr;
   int *gj_piv = nullptr, *gj_colmap = nullptr;
+  // block ILU(0) smoother (smoother == ILU): factors in the matrix's layout
+  // (L strictly left of the diagonal block, U from it on), inverses of the
+  // diagonal blocks of U, and the level schedules of the lower and upper
+  // triangles (rows of one level are independent)
+  double *ilu64 = nullptr, *dinv64 = nullptr;
+  float *ilu32 = nullptr, *dinv32 = nullptr;
+  double *iw64 = nullptr;               // triangular-solve work vector (one precision)
+  float *iw32 = nullptr;
+  int32_t *idiag = nullptr;             // [nrows] position of the diagonal block
+  int32_t *lorder = nullptr, *uorder = nullptr;  // [nrows] rows sorted by level
+  std::vector<int64_t> lptr, uptr;      // host: level boundaries in lorder / uorder
+  int ilu_maxrow = 0;                   // longest block row (LDS of the factorisation)
 };
 
 // ------------------------------------------------- batched execution
@@ -214,6 +227,14 @@ void launch_vanka_blocks(const DevLevel &L, const T *inv, int npc, const T *d, T
 template <typename T>
 void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega, bool assign, T *x,
                          hipStream_t s);
+// block ILU(0): factor level L in place (ilu64 = vals64 on entry, then L / U;
+// dinv64 the inverted diagonal blocks of U); status[0] = 1, status[1] = row
+// on a singular diagonal block
+void launch_ilu_factor(const DevLevel &L, int *status, hipStream_t s);
+// x (+)= omega (L U)^{-1} d, identity dofs kept (assign: x = that correction)
+template <typename T>
+void launch_ilu_apply(const DevLevel &L, const T *F, const T *dinv, T *work, const T *d, T omega,
+                      bool assign, T *x, hipStream_t s);
 template <typename T>
 void launch_restrict(const DevLevel &F, const DevLevel &C, const T *rf, T *rc, hipStream_t s);
 template <typename T>

@@ -155,6 +155,8 @@ extern "C" {
 fsimg_status fsimg_server_create(fsimg_ctx *ctx, const fsimg_opts *opts, int max_active,
                                  fsimg_server **out) {
   if (!ctx || !opts || !out || max_active < 0) return set_error(FSIMG_ERR_ARG, "bad server arguments");
+  if (opts->smoother != FSIMG_SMOOTHER_VANKA)
+    return set_error(FSIMG_ERR_ARG, "the server batches Vanka hierarchies only");
   auto *S = new fsimg_server;
   S->ctx = ctx;
   S->opts = *opts;

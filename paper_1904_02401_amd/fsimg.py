@@ -24,6 +24,7 @@ FSIMG_VANKA_GATHER, FSIMG_VANKA_PARITY, FSIMG_VANKA_GREEDY = 0, 1, 2
 FSIMG_WEIGHT_PLAIN, FSIMG_WEIGHT_MULT = 0, 1
 FSIMG_TUNE_SPMV_ROWS, FSIMG_TUNE_VANKA_PPW = 0, 1
 FSIMG_PATCH_ELEMENT, FSIMG_PATCH_BLOCK = 0, 1
+FSIMG_SMOOTHER_VANKA, FSIMG_SMOOTHER_ILU = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_SINGULAR",
                  5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_BUDGET", 8: "ERR_STATE"}
@@ -48,7 +49,8 @@ class fsimg_opts(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("vanka_schedule", ctypes.c_int),
                 ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int),
-                ("graphs", ctypes.c_int), ("vanka_patches", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("vanka_patches", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("omega_ilu", ctypes.c_double)]
 
 
 class fsimg_stats(ctypes.Structure):
@@ -103,6 +105,8 @@ _SIGS = {
     "fsimg_level_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "fsimg_level_residual": (_I, [_P, _I, _I, _P, _P, _P, _P]),
     "fsimg_vanka_step": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_ilu_step": (_I, [_P, _I, _I, _P, _P, _P]),
+    "fsimg_ilu_factors": (_I, [_P, _I, _P]),
     "fsimg_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
     "fsimg_prolong_add": (_I, [_P, _I, _I, _P, _P, _P]),
     "fsimg_coarse_solve": (_I, [_P, _P, _P, _P]),
@@ -304,6 +308,17 @@ def fsimg_level_residual(h, level, precision, b, x, d, stream=None):
 
 def fsimg_vanka_step(h, level, precision, b, x, stream=None):
     _check(load().fsimg_vanka_step(h, level, precision, _dev(b), _dev(x), _stream(stream)))
+
+
+def fsimg_ilu_step(h, level, precision, b, x, stream=None):
+    _check(load().fsimg_ilu_step(h, level, precision, _dev(b), _dev(x), _stream(stream)))
+
+
+def fsimg_ilu_factors(h, level: int, nnzb: int, b: int) -> np.ndarray:
+    """The FP64 ILU factors of a level, [nnzb, b, b] in the matrix's layout."""
+    out = np.empty(nnzb * b * b, dtype=np.float64)
+    _check(load().fsimg_ilu_factors(h, level, out.ctypes.data))
+    return out.reshape(nnzb, b, b)
 
 
 def fsimg_restrict(h, level, precision, rf, rc, stream=None):
