@@ -115,7 +115,7 @@ def calib_copy(nbytes, reps):
     log(f"calib-copy: {reps} copies of {nbytes} bytes")
 
 
-def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0):
+def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0, smoother=0):
     import torch
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import level_dicts
@@ -127,7 +127,7 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     systems = ["mom", "ale"] + (["mass"] if with_mass else [])
     for name in systems:
         o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches,
-                                     vanka_schedule=schedule)
+                                     vanka_schedule=schedule, smoother=smoother)
         hs[name] = fsimg.fsimg_hier_create(ctx, level_dicts(P, name), o)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -491,6 +491,8 @@ def main():
                     help="Vanka schedule: per-dof gather (batched path) or coloured scatter")
     ap.add_argument("--patches", choices=["element", "block"], default="element",
                     help="Vanka patches: one element, or 2x2(x2) element blocks (3D: solid only)")
+    ap.add_argument("--smoother", choices=["vanka", "ilu"], default="vanka",
+                    help="multigrid smoother (ilu: block ILU(0), level-scheduled)")
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
@@ -556,7 +558,8 @@ def main():
         r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass, tune=not args.no_tune,
                     patches=fsimg.FSIMG_PATCH_BLOCK if args.patches == "block" else fsimg.FSIMG_PATCH_ELEMENT,
                     schedule={"gather": fsimg.FSIMG_VANKA_GATHER, "parity": fsimg.FSIMG_VANKA_PARITY,
-                              "greedy": fsimg.FSIMG_VANKA_GREEDY}[args.schedule])
+                              "greedy": fsimg.FSIMG_VANKA_GREEDY}[args.schedule],
+                    smoother=fsimg.FSIMG_SMOOTHER_ILU if args.smoother == "ilu" else fsimg.FSIMG_SMOOTHER_VANKA)
         A = to_csr(lev.systems["mom"])
         mask = lev.systems["mom"].dirichlet.astype(bool)
         rr = P.rhs["mom"] - A @ r["x_mom"]
@@ -602,7 +605,7 @@ def main():
     def factor_rate(R, tag):
         # algorithmic flops of inverting one n_p x n_p matrix: 2 n_p^3
         info = R["info_m"]
-        if args.patches != "element" or not R["factor_ms"]:
+        if args.patches != "element" or args.smoother != "vanka" or not R["factor_ms"]:
             return None
         ms = sum(R["factor_ms"]) / len(R["factor_ms"])
         flops = info["npatch"] * 2.0 * info["np"] ** 3
@@ -644,7 +647,7 @@ def main():
                    "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
                    "precision": main_tag, "vanka_patches": args.patches,
-                   "vanka_schedule": args.schedule},
+                   "vanka_schedule": args.schedule, "smoother": args.smoother},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],

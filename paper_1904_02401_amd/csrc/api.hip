@@ -890,7 +890,9 @@ fsimg_status fsimg_hier_info(const fsimg_hier *h, int level, fsimg_level_info *o
   const void *ptrs[] = {L.rowptr, L.colind, L.vals64, L.vals32, L.mask, L.pnodes, L.inv64, L.inv32,
                         L.gptr, L.gidx, L.scale64, L.scale32, L.r64, L.x64, L.d64, L.Y64,
                         L.r32, L.x32, L.d32, L.Y32, L.cinv, L.ct0, L.ct1, L.cfree, L.cidx,
-                        L.gj_a, L.gj_rowk, L.gj_colk, L.gj_piv, L.gj_colmap, L.gj_part};
+                        L.gj_a, L.gj_rowk, L.gj_colk, L.gj_piv, L.gj_colmap, L.gj_part,
+                        L.ilu64, L.ilu32, L.dinv64, L.dinv32, L.iw64, L.iw32, L.idiag, L.lorder,
+                        L.uorder};
   for (const void *p : ptrs)
     for (const auto &a : h->allocs)
       if (p && a.first == p) bytes += a.second;

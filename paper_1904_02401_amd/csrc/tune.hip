@@ -160,6 +160,7 @@ struct Tuner {
     for (int l = 0; l + 1 < nl; ++l) {  // levels that smooth
       const DevLevel &L = h->lev[l];
       spmv<T>(L, LevelVec<T>::vals(L), LevelVec<T>::x(L), LevelVec<T>::r(L), LevelVec<T>::d(L));
+      if (h->opts.smoother != FSIMG_SMOOTHER_VANKA) continue;  // no patch inverses to time
       vanka<T>(L, 0);
       vanka<T>(L, 1);
     }
