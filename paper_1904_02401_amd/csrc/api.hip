@@ -441,13 +441,47 @@ template <> struct IluSel<float> {
   static float *work(DevLevel &L) { return L.iw32; }
 };
 
+// the ILU level sweeps of level l (reading the level's residual buffer,
+// writing its work vector) as a graph, captured the first time on the
+// hierarchy's own stream
+template <typename T>
+hipError_t ilu_graph(fsimg_hier *h, int l, hipGraphExec_t *out) {
+  DevLevel &L = h->lev[l];
+  const int k = std::is_same<T, double>::value ? 0 : 1;
+  if (!L.ilu_exec[k]) {
+    hipError_t e = hipSuccess;
+    if (!h->ilu_cap) e = hipStreamCreateWithFlags(&h->ilu_cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(h->ilu_cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    launch_ilu_solve<T>(L, IluSel<T>::F(L), IluSel<T>::dinv(L), Sel<T>::d(L), IluSel<T>::work(L),
+                        h->ilu_cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->ilu_cap, &g);
+    if (e == hipSuccess) e = hipGraphInstantiate(&L.ilu_exec[k], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      L.ilu_exec[k] = nullptr;
+      return e;
+    }
+  }
+  *out = L.ilu_exec[k];
+  return hipSuccess;
+}
+
 // one smoothing step with the residual d already computed (Vanka or ILU)
 template <typename T>
 void smooth_apply(fsimg_hier *h, int l, const T *d, T *x, bool assign, hipStream_t s) {
   if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
     DevLevel &L = h->lev[l];
-    launch_ilu_apply<T>(L, IluSel<T>::F(L), IluSel<T>::dinv(L), IluSel<T>::work(L), d,
-                        (T)h->opts.omega_ilu, assign, x, s);
+    T *dl = Sel<T>::d(L);
+    if (d != dl) (void)hipMemcpyAsync(dl, d, L.n * sizeof(T), hipMemcpyDeviceToDevice, s);
+    hipGraphExec_t g = nullptr;
+    if (h->opts.graphs && ilu_graph<T>(h, l, &g) == hipSuccess)
+      (void)hipGraphLaunch(g, s);
+    else
+      launch_ilu_solve<T>(L, IluSel<T>::F(L), IluSel<T>::dinv(L), dl, IluSel<T>::work(L), s);
+    launch_ilu_axpy<T>(L, IluSel<T>::work(L), (T)h->opts.omega_ilu, assign, x, s);
     return;
   }
   vanka_apply<T>(h, l, d, x, assign, s);
@@ -626,6 +660,13 @@ void fsimg_hier_destroy(fsimg_hier *h) {
     h->ctx->in_use -= a.second;
   }
   h->allocs.clear();
+  for (auto &L : h->lev)
+    for (hipGraphExec_t &g : L.ilu_exec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  if (h->ilu_cap) (void)hipStreamDestroy(h->ilu_cap);
   if (h->hpin) (void)hipHostFree(h->hpin);
   if (h->hstatus) (void)hipHostFree(h->hstatus);
   delete h;

@@ -99,6 +99,7 @@ struct DevLevel {
   int32_t *lorder = nullptr, *uorder = nullptr;  // [nrows] rows sorted by level
   std::vector<int64_t> lptr, uptr;      // host: level boundaries in lorder / uorder
   int ilu_maxrow = 0;                   // longest block row (LDS of the factorisation)
+  hipGraphExec_t ilu_exec[2] = {nullptr, nullptr};  // captured sweeps (FP64, FP32)
 };
 
 // ------------------------------------------------- batched execution
@@ -231,10 +232,13 @@ void launch_vanka_gather(const DevLevel &L, const T *Y, const T *scale, T omega,
 // dinv64 the inverted diagonal blocks of U); status[0] = 1, status[1] = row
 // on a singular diagonal block
 void launch_ilu_factor(const DevLevel &L, int *status, hipStream_t s);
-// x (+)= omega (L U)^{-1} d, identity dofs kept (assign: x = that correction)
+// work = (L U)^{-1} d by the level sweeps (fixed buffers: graph-capturable)
 template <typename T>
-void launch_ilu_apply(const DevLevel &L, const T *F, const T *dinv, T *work, const T *d, T omega,
-                      bool assign, T *x, hipStream_t s);
+void launch_ilu_solve(const DevLevel &L, const T *F, const T *dinv, const T *d, T *work,
+                      hipStream_t s);
+// x (+)= omega z, identity dofs kept (assign: x = omega z, 0 at identity dofs)
+template <typename T>
+void launch_ilu_axpy(const DevLevel &L, const T *z, T omega, bool assign, T *x, hipStream_t s);
 template <typename T>
 void launch_restrict(const DevLevel &F, const DevLevel &C, const T *rf, T *rc, hipStream_t s);
 template <typename T>

@@ -72,6 +72,7 @@ struct fsimg_hier {
   int *hstatus = nullptr;
   EventTimer tv, ts;
   bool profiling = false;
+  hipStream_t ilu_cap = nullptr;  // capture stream of the ILU sweep graphs
 };
 
 

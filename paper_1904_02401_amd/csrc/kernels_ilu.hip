@@ -10,8 +10,10 @@
 // a row's blocks are staged in LDS while it is eliminated.
 //
 // Apply: y = L^{-1} d by levels of the lower triangle, z = U^{-1} y by levels
-// of the upper triangle (U_ii^{-1} stored), x += omega z.  One wavefront per
-// block row, lanes over the row's blocks, fixed-order wave reductions.
+// of the upper triangle (U_ii^{-1} stored), then x += omega z.  One wavefront
+// per block row, lanes over the row's blocks, fixed-order wave reductions.
+// The two level sweeps read and write fixed buffers only, so a caller can
+// capture them once as a graph.
 #include <cfloat>
 
 #include "fsimg_internal.h"
@@ -180,8 +182,7 @@ __global__ __launch_bounds__(256) void k_ilu_lower(const int32_t *__restrict__ r
 }
 
 // z_i = U_ii^{-1} (y_i - sum_{j > i} U_ij z_j) in place of y for the rows of
-// one level; x_i (+)= omega z_i at the non-identity dofs (identity dofs: kept,
-// or 0 when assigning)
+// one level
 template <int B, typename T>
 __global__ __launch_bounds__(256) void k_ilu_upper(const int32_t *__restrict__ rows, int nr,
                                                    const int32_t *__restrict__ rowptr,
@@ -189,9 +190,7 @@ __global__ __launch_bounds__(256) void k_ilu_upper(const int32_t *__restrict__ r
                                                    const int32_t *__restrict__ idiag,
                                                    const T *__restrict__ F,
                                                    const T *__restrict__ dinv,
-                                                   const uint8_t *__restrict__ mask, T omega,
-                                                   int assign, T *__restrict__ y,
-                                                   T *__restrict__ x) {
+                                                   T *__restrict__ y) {
   constexpr int BB = B * B;
   const int wv = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (wv >= nr) return;
@@ -223,14 +222,23 @@ __global__ __launch_bounds__(256) void k_ilu_upper(const int32_t *__restrict__ r
       T z = T(0);
 #pragma unroll
       for (int c = 0; c < B; ++c) z += di[r * B + c] * s[c];
-      const int64_t o = (int64_t)i * B + r;
-      y[o] = z;
-      if (mask[o]) {
-        if (assign) x[o] = T(0);
-      } else {
-        x[o] = assign ? omega * z : x[o] + omega * z;
-      }
+      y[(int64_t)i * B + r] = z;
     }
+  }
+}
+
+// x (+)= omega z at the non-identity dofs (identity dofs: kept, or 0 when
+// assigning)
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_axpy(int64_t n, const T *__restrict__ z,
+                                                  const uint8_t *__restrict__ mask, T omega,
+                                                  int assign, T *__restrict__ x) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  if (mask[o]) {
+    if (assign) x[o] = T(0);
+  } else {
+    x[o] = assign ? omega * z[o] : x[o] + omega * z[o];
   }
 }
 
@@ -258,8 +266,8 @@ void launch_ilu_factor(const DevLevel &L, int *status, hipStream_t s) {
 }
 
 template <typename T>
-void launch_ilu_apply(const DevLevel &L, const T *F, const T *dinv, T *work, const T *d, T omega,
-                      bool assign, T *x, hipStream_t s) {
+void launch_ilu_solve(const DevLevel &L, const T *F, const T *dinv, const T *d, T *work,
+                      hipStream_t s) {
   for (size_t lv = 0; lv + 1 < L.lptr.size(); ++lv) {
     const int64_t r0 = L.lptr[lv], cnt = L.lptr[lv + 1] - r0;
     if (cnt == 0) continue;
@@ -280,8 +288,7 @@ void launch_ilu_apply(const DevLevel &L, const T *F, const T *dinv, T *work, con
 #define FSIMG_ILUU(BV)                                                                           \
   case BV:                                                                                       \
     hipLaunchKernelGGL((k_ilu_upper<BV, T>), dim3(blocks_for(cnt, 4)), dim3(256), 0, s,         \
-                       L.uorder + r0, (int)cnt, L.rowptr, L.colind, L.idiag, F, dinv, L.mask,    \
-                       omega, assign ? 1 : 0, work, x);                                          \
+                       L.uorder + r0, (int)cnt, L.rowptr, L.colind, L.idiag, F, dinv, work);     \
     break;
     switch (L.b) {
       FSIMG_ILUU(1) FSIMG_ILUU(2) FSIMG_ILUU(3) FSIMG_ILUU(4)
@@ -290,9 +297,19 @@ void launch_ilu_apply(const DevLevel &L, const T *F, const T *dinv, T *work, con
 #undef FSIMG_ILUU
   }
 }
-template void launch_ilu_apply<double>(const DevLevel &, const double *, const double *, double *,
-                                       const double *, double, bool, double *, hipStream_t);
-template void launch_ilu_apply<float>(const DevLevel &, const float *, const float *, float *,
-                                      const float *, float, bool, float *, hipStream_t);
+
+template <typename T>
+void launch_ilu_axpy(const DevLevel &L, const T *z, T omega, bool assign, T *x, hipStream_t s) {
+  hipLaunchKernelGGL((k_ilu_axpy<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, L.n, z, L.mask,
+                     omega, assign ? 1 : 0, x);
+}
+
+#define FSIMG_ILUI(T)                                                                             \
+  template void launch_ilu_solve<T>(const DevLevel &, const T *, const T *, const T *, T *,       \
+                                    hipStream_t);                                                 \
+  template void launch_ilu_axpy<T>(const DevLevel &, const T *, T, bool, T *, hipStream_t);
+FSIMG_ILUI(double)
+FSIMG_ILUI(float)
+#undef FSIMG_ILUI
 
 }  // namespace fsimg

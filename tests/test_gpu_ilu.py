@@ -178,3 +178,26 @@ def test_calls_that_refuse_ilu_hierarchies(ctx, probs):
     with pytest.raises(fsimg.FsimgError) as ei:
         fsimg.fsimg_server_create(ctx, fsimg.fsimg_default_opts(**ILU))
     assert ei.value.status == fsimg.FSIMG_ERR_ARG
+
+
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_ilu_graph_replays_equal_eager_launches(ctx, probs, precision):
+    """The captured level sweeps, replayed in several solves in a row (eager
+    work and synchronisation between them), give bitwise the eager result."""
+    P = probs["t3"]
+    b = torch.tensor(P.rhs["mom"], device=DEV)
+    out = {}
+    for graphs in (0, 1):
+        with Hier(ctx, P, "mom", precision=precision, graphs=graphs, **ILU) as h:
+            fsimg.fsimg_factor(h)
+            res = []
+            for _ in range(3):
+                x = torch.zeros_like(b)
+                fsimg.fsimg_solve(h, b, x)
+                torch.cuda.synchronize()
+                res.append(x.cpu().numpy())
+            out[graphs] = res
+    for r in out[1]:
+        np.testing.assert_array_equal(r, out[0][0])
+    for r in out[0]:
+        np.testing.assert_array_equal(r, out[0][0])
