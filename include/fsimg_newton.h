@@ -1,0 +1,131 @@
+/*
+ * fsimg_newton.h -- the approximate Newton loop around the linear solves of
+ * fsimg.h: the condensed nonlinear residual of one theta time step of the
+ * monolithic ALE fluid-structure model (Sec. 2, eq. aletime:2, with the solid
+ * deformation condensed into the velocity, Sec. 3.1 eq. defgrad), its
+ * approximate Jacobian (Sec. 4.2: every derivative with respect to the ALE
+ * deformation dropped, the momentum block of eq. REDUCEDMATRIX = eq.
+ * problem:1), assembled on the GPU on every multigrid level, and the Newton
+ * iteration of eq. newton with the Jacobian-reuse rule of Sec. 5.5 and a
+ * line search.
+ *
+ * Discretisation: equal-order Q2 elements on a tensor-product mesh (Sec.
+ * 3.2), 3 Gauss points per axis, nodes numbered lexicographically with x
+ * fastest, 2*cells[a]+1 nodes per axis; the pressure is stabilised by
+ * s_h(p, xi) = sum_K delta_K (grad p, grad xi)_K,
+ * delta_K = alpha0 k^2 h_K^2 / (rho_f (h_K^2 + k theta nu_f)), h_K the
+ * longest cell side.  Inertia and convection carry rho_f; the pressure
+ * enters the momentum rows as -k (J p F^-T, grad phi) and the divergence row
+ * as +k (J tr(grad v F^-1), xi); the mesh-transport term uses
+ * vbar = theta v_n + (1 - theta) v_{n-1}.
+ *
+ * Vectors (all FP64 device pointers, node-major):
+ *   x      [nrows*(d+1)]  (p, v_1..v_d) per node: the momentum unknowns
+ *   u      [nrows*d]      deformation; in fluid cells the ALE deformation,
+ *                         in solid cells the residual uses the condensation
+ *                         u_old + k theta v + k (1 - theta) v_old instead
+ *   x_old, u_old          the same at t_{n-1} (the pressure of x_old is unused)
+ * Errors are reported as in fsimg.h (status code, fsimg_last_error()).
+ */
+#ifndef FSIMG_NEWTON_H
+#define FSIMG_NEWTON_H
+
+#include "fsimg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Material and time-stepping parameters of eq. aletime:2. */
+typedef struct {
+  double rho_f, nu_f;        /* fluid density and kinematic viscosity */
+  double rho_s, mu_s, lambda_s; /* solid density and Lame parameters (St. Venant-Kirchhoff) */
+  double k, theta;           /* time step and theta of the theta scheme */
+  double alpha0;             /* pressure stabilisation scale */
+} fsimg_phys;
+
+/* Geometry of one multigrid level (host arrays, copied). */
+typedef struct {
+  const double *coords[3];   /* per-axis node coordinates, 2*cells[a]+1 each (unused axes:
+                                NULL) */
+  const uint8_t *cell_solid; /* [prod(cells)] 1 = solid cell, 0 = fluid cell */
+} fsimg_fsi_level;
+
+typedef struct fsimg_fsi fsimg_fsi;
+
+/* Bind the Newton loop to a momentum hierarchy `mom` (block d+1, its level
+   matrices carry the identity rows of the momentum system and the full Q2
+   element pattern) and an ALE hierarchy `ale` (block d, the vector Laplacian
+   of eq. problem:3 with identity rows at interface, solid and outer-boundary
+   nodes; NULL: residual and Jacobian only, no Newton loop).  levels[l]
+   describes level l of `mom` (cells taken from it).  Both hierarchies must
+   use FP64 or mixed precision and stay alive while the object exists; the
+   object allocates its work vectors from mom's context (budget-charged).
+   ERR_ARG on inconsistent sizes. */
+fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_level *levels,
+                              const fsimg_phys *phys, fsimg_fsi **out);
+void fsimg_fsi_destroy(fsimg_fsi *f);
+
+/* res = B - A(U) of the momentum and divergence rows on the finest level
+   (B = 0: no volume forces), zero at the identity rows.  ERR_SINGULAR if
+   det F <= 0 at a Gauss point.  Synchronises the stream. */
+fsimg_status fsimg_fsi_residual(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                                const double *u_old, double *res, void *stream);
+
+/* Assemble the approximate Jacobian at U into the momentum hierarchy's FP64
+   values on every level (the state injected to the coarse levels: coarse
+   node g is fine node 2g per axis), with that hierarchy's identity rows
+   (row and column eliminated, diagonal one), and its FP32 copies in mixed
+   mode.  Invalidates the factorisation (call fsimg_factor).  ERR_SINGULAR as
+   above; ERR_ARG if a level's block pattern lacks an element coupling.
+   Synchronises the stream. */
+fsimg_status fsimg_fsi_jacobian(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                                const double *u_old, void *stream);
+
+typedef struct {
+  double rtol;       /* stop when ||B - A(U)||_inf <= rtol * (its initial value) (default 1e-8) */
+  double atol;       /* ... or <= atol (default 0) */
+  int max_steps;     /* Newton steps (default 20) */
+  double gamma;      /* reassemble the Jacobian when the rate rho_l > gamma (default 0.05) */
+  int max_halvings;  /* line search: halve omega while the residual does not decrease, at
+                        most this often (default 4) */
+} fsimg_newton_opts;
+
+typedef struct {
+  int status;           /* fsimg_status of the loop */
+  int steps;            /* Newton steps taken */
+  int jacobians;        /* Jacobians assembled (and factored) in this call */
+  int halvings;         /* line-search halvings in this call */
+  int lin_iters_mom, lin_iters_ale;  /* FGMRES iterations of the momentum / ALE solves */
+  double res0, res;     /* initial and final max-norm of B - A(U) (momentum and ALE rows) */
+  double res_hist[32];  /* the max-norm before step l (l < 32) */
+  double omega_hist[32];/* the accepted line-search parameter of step l */
+  double ms_total, ms_residual, ms_jacobian, ms_factor, ms_solve;  /* host wall times */
+} fsimg_newton_stats;
+
+void fsimg_default_newton_opts(fsimg_newton_opts *o);
+
+/* One time step t_{n-1} -> t_n by the approximate Newton method, in place on
+   (x, u) (the initial guess on entry; identity-row values of x are kept).
+   Each step: the residual R = B - A(U) and the ALE residual b5 = -E u at the
+   fluid rows; the Jacobian is assembled and factored if none is held yet or
+   the last rate ||R_l|| / ||R_{l-1}|| exceeded gamma (a Jacobian is kept
+   across calls, i.e. across time steps); the momentum system J W = R
+   (eq. problem:1) is solved by FGMRES + multigrid; the interface and solid
+   deformation increment is k theta W_v (eq. problem:2, one vector
+   addition); the ALE system E du = b5 with du = k theta W_v at its identity
+   rows (eq. problem:3) is solved likewise; then U += omega (W, du) with
+   omega = 1, halved while the max-norm of the residual does not decrease.
+   Requires an ALE hierarchy.  Returns OK, NOCONV (max_steps reached), a
+   linear-solve failure, or ERR_SINGULAR (det F <= 0). */
+fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *x_old,
+                              const double *u_old, const fsimg_newton_opts *opts,
+                              fsimg_newton_stats *stats, void *stream);
+
+/* Forget the Jacobian held by the object (the next Newton call assembles). */
+fsimg_status fsimg_fsi_drop_jacobian(fsimg_fsi *f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

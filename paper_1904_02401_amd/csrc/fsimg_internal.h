@@ -290,4 +290,36 @@ void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, doubl
                    const double *v_new, int v_stride, int v_offset, const double *u_old,
                    const double *v_old, double *u_new, hipStream_t s);
 
+// ------------------------------------------- element assembly (Newton loop)
+// Device view of one level of the tensor Q2 mesh for the element kernels.
+struct AsmLevel {
+  const double *coord[3];          // per-axis node coordinates (2*cells[a]+1)
+  const uint8_t *solid;            // [prod(cells)] 1 = solid cell
+  const int32_t *rowptr, *colind;  // block pattern of the momentum matrix
+  const uint8_t *mask;             // [nrows*(d+1)] identity rows of the momentum matrix
+  int cells[3], nnode[3];
+};
+// material and time-stepping parameters (eq. aletime:2)
+struct AsmPhys {
+  double rho_f, nu_f, rho_s, mu_s, lambda_s, k, theta, alpha0;
+};
+// a state: x = (p, v) per node [nrows*(d+1)], u [nrows*d]; x_old, u_old at t_{n-1}
+struct AsmState {
+  const double *x, *u, *xo, *uo;
+};
+// the approximate Jacobian into vals [nnzb*(d+1)^2] (zeroed first, identity
+// rows and columns of L.mask applied); flag[0] = 1 if det F <= 0 at a Gauss
+// point, flag[1] = 1 if the pattern lacks an element coupling
+void launch_asm_jacobian(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S,
+                         double *vals, int64_t nrows, int64_t nnzb, int *flag, hipStream_t s);
+// res = -A(U) (zero at identity rows), flags as above
+void launch_asm_residual(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S,
+                         double *res, int64_t nrows, int *flag, hipStream_t s);
+void launch_inject(const double *f, double *c, const int *nnode_f, const int *nnode_c, int comps,
+                   hipStream_t s);
+void launch_axpy_to(const double *x, const double *z, double omega, double *y, int64_t n,
+                    hipStream_t s);
+void launch_neg_free(double *y, const uint8_t *mask, int64_t n, hipStream_t s);
+void launch_absmax_u64(const double *x, int64_t n, unsigned long long *out, hipStream_t s);
+
 }  // namespace fsimg

@@ -1,0 +1,448 @@
+// The approximate Newton loop of one theta time step (eq. newton) around the
+// linear solves of the library: residual and Jacobian assembly on the GPU
+// (kernels_asm.hip) on every level of the momentum hierarchy, Jacobian reuse
+// by the rate rule of Sec. 5.5, the reduced splitting of eq. REDUCEDMATRIX
+// into the momentum solve (eq. problem:1), the deformation update (eq.
+// problem:2) and the ALE solve (eq. problem:3), and a halving line search.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fsimg_newton.h"
+#include "hier.h"
+
+using namespace fsimg;
+
+namespace {
+
+struct FsiLevel {
+  AsmLevel dev{};          // device view (pattern and mask borrowed from the hierarchy)
+  double *coord[3] = {nullptr, nullptr, nullptr};
+  uint8_t *solid = nullptr;
+  // the state injected to this level (coarse levels only)
+  double *x = nullptr, *u = nullptr, *xo = nullptr, *uo = nullptr;
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct fsimg_fsi {
+  fsimg_hier *mom = nullptr, *ale = nullptr;
+  fsimg_phys phys{};
+  int dim = 0;
+  std::vector<FsiLevel> lev;
+  std::vector<std::pair<void *, size_t>> allocs;
+  uint8_t *node_solid = nullptr;     // [nrows] fine nodes of a solid cell
+  // finest-level work vectors
+  double *res = nullptr, *W = nullptr, *xt = nullptr;           // [n_mom]
+  double *du = nullptr, *b5 = nullptr, *ut = nullptr;           // [n_ale]
+  int *dflag = nullptr;                                          // [2] assembly flags
+  unsigned long long *dnorm = nullptr;                           // max-norm slot
+  int *hflag = nullptr;                                          // pinned host mirror
+  unsigned long long *hnorm = nullptr;
+  bool have_jac = false;
+};
+
+namespace {
+
+fsimg_status nfail(fsimg_status s, const std::string &m) { return set_error(s, m); }
+
+#define NW_HIP(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return nfail(FSIMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+#define NW_TRY(expr)                 \
+  do {                               \
+    fsimg_status st_ = (expr);       \
+    if (st_ != FSIMG_OK) return st_; \
+  } while (0)
+
+template <typename T>
+fsimg_status falloc(fsimg_fsi *f, T **p, size_t count) {
+  *p = nullptr;
+  const size_t bytes = count * sizeof(T);
+  if (bytes == 0) return FSIMG_OK;
+  fsimg_ctx *ctx = f->mom->ctx;
+  if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+    return nfail(FSIMG_ERR_BUDGET, "Newton work vectors exceed the context's HBM budget");
+  void *q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nfail(FSIMG_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  ctx->in_use += bytes;
+  f->allocs.push_back({q, bytes});
+  *p = static_cast<T *>(q);
+  return FSIMG_OK;
+}
+
+AsmPhys asm_phys(const fsimg_phys &p) {
+  return AsmPhys{p.rho_f, p.nu_f, p.rho_s, p.mu_s, p.lambda_s, p.k, p.theta, p.alpha0};
+}
+
+// copy the assembly flags and the max-norm slot to the host and wait
+fsimg_status read_flags(fsimg_fsi *f, hipStream_t s, int *flags, double *norm) {
+  NW_HIP(hipMemcpyAsync(f->hflag, f->dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  NW_HIP(hipMemcpyAsync(f->hnorm, f->dnorm, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  NW_HIP(hipStreamSynchronize(s));
+  flags[0] = f->hflag[0];
+  flags[1] = f->hflag[1];
+  if (norm) {
+    double v;
+    std::memcpy(&v, f->hnorm, sizeof v);
+    *norm = v;
+  }
+  return FSIMG_OK;
+}
+
+fsimg_status clear_flags(fsimg_fsi *f, hipStream_t s) {
+  NW_HIP(hipMemsetAsync(f->dflag, 0, 2 * sizeof(int), s));
+  NW_HIP(hipMemsetAsync(f->dnorm, 0, sizeof(unsigned long long), s));
+  return FSIMG_OK;
+}
+
+fsimg_status flags_status(const int *flags) {
+  if (flags[1]) return nfail(FSIMG_ERR_ARG, "the momentum block pattern lacks an element coupling");
+  if (flags[0]) return nfail(FSIMG_ERR_SINGULAR, "det F <= 0 at a Gauss point (inverted element)");
+  return FSIMG_OK;
+}
+
+// residual R = -A(U) on the finest level into f->res, and (with ALE) the ALE
+// residual b5 = -E u at the fluid rows; *norm = max-norm of both
+fsimg_status eval_residual(fsimg_fsi *f, const double *x, const double *u, const double *xo,
+                           const double *uo, hipStream_t s, double *norm, bool with_ale) {
+  const DevLevel &L = f->mom->lev[0];
+  NW_TRY(clear_flags(f, s));
+  launch_asm_residual(f->lev[0].dev, f->dim, asm_phys(f->phys), AsmState{x, u, xo, uo}, f->res,
+                      L.nrows, f->dflag, s);
+  launch_absmax_u64(f->res, L.n, f->dnorm, s);
+  if (with_ale) {
+    DevLevel &A = f->ale->lev[0];
+    NW_TRY(fsimg_level_apply(f->ale, 0, FSIMG_FP64, u, f->b5, s));
+    launch_neg_free(f->b5, A.mask, A.n, s);
+    launch_absmax_u64(f->b5, A.n, f->dnorm, s);
+  }
+  NW_HIP(hipGetLastError());
+  int flags[2];
+  NW_TRY(read_flags(f, s, flags, norm));
+  return flags_status(flags);
+}
+
+fsimg_status assemble_jacobian(fsimg_fsi *f, const double *x, const double *u, const double *xo,
+                               const double *uo, hipStream_t s) {
+  fsimg_hier *h = f->mom;
+  const int nlev = (int)h->lev.size();
+  const AsmPhys P = asm_phys(f->phys);
+  NW_TRY(clear_flags(f, s));
+  for (int l = 0; l < nlev; ++l) {
+    DevLevel &L = h->lev[l];
+    FsiLevel &F = f->lev[l];
+    AsmState S{x, u, xo, uo};
+    if (l > 0) {
+      const DevLevel &Lf = h->lev[l - 1];
+      const FsiLevel &Ff = f->lev[l - 1];
+      const double *src[4] = {l == 1 ? x : Ff.x, l == 1 ? u : Ff.u, l == 1 ? xo : Ff.xo,
+                              l == 1 ? uo : Ff.uo};
+      double *dst[4] = {F.x, F.u, F.xo, F.uo};
+      const int comps[4] = {f->dim + 1, f->dim, f->dim + 1, f->dim};
+      for (int q = 0; q < 4; ++q) launch_inject(src[q], dst[q], Lf.nnode, L.nnode, comps[q], s);
+      S = AsmState{F.x, F.u, F.xo, F.uo};
+    }
+    launch_asm_jacobian(F.dev, f->dim, P, S, L.vals64, L.nrows, L.nnzb, f->dflag, s);
+    if (L.vals32) launch_cast_d2f(L.vals64, L.vals32, L.nnzb * L.b * L.b, s);
+  }
+  NW_HIP(hipGetLastError());
+  h->factored = false;
+  int flags[2];
+  NW_TRY(read_flags(f, s, flags, nullptr));
+  return flags_status(flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+void fsimg_default_newton_opts(fsimg_newton_opts *o) {
+  if (!o) return;
+  o->rtol = 1e-8;
+  o->atol = 0.0;
+  o->max_steps = 20;
+  o->gamma = 0.05;
+  o->max_halvings = 4;
+}
+
+void fsimg_fsi_destroy(fsimg_fsi *f) {
+  if (!f) return;
+  (void)hipSetDevice(f->mom->ctx->device);
+  for (auto &a : f->allocs) {
+    (void)hipFree(a.first);
+    f->mom->ctx->in_use -= a.second;
+  }
+  if (f->hflag) (void)hipHostFree(f->hflag);
+  if (f->hnorm) (void)hipHostFree(f->hnorm);
+  delete f;
+}
+
+fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_level *levels,
+                              const fsimg_phys *phys, fsimg_fsi **out) {
+  if (!out) return nfail(FSIMG_ERR_ARG, "null output");
+  *out = nullptr;
+  if (!mom || !levels || !phys) return nfail(FSIMG_ERR_ARG, "null hierarchy, levels or parameters");
+  const DevLevel &L0 = mom->lev[0];
+  const int d = L0.dim;
+  if (d < 2 || d > 3 || L0.b != d + 1)
+    return nfail(FSIMG_ERR_ARG, "the momentum hierarchy needs dimension 2 or 3 and block d+1");
+  if (!(phys->k > 0.0) || !(phys->theta > 0.0) || phys->theta > 1.0 || !(phys->rho_f > 0.0))
+    return nfail(FSIMG_ERR_ARG, "bad physical parameters");
+  if (ale) {
+    const DevLevel &A0 = ale->lev[0];
+    if (ale->ctx != mom->ctx || A0.dim != d || A0.b != d || A0.nrows != L0.nrows)
+      return nfail(FSIMG_ERR_ARG, "the ALE hierarchy must share context, mesh and dimension (block d)");
+  }
+  for (size_t l = 0; l < mom->lev.size(); ++l) {
+    const DevLevel &L = mom->lev[l];
+    for (int a = 0; a < d; ++a)
+      if (L.cells[a] < 1 || L.nnode[a] != 2 * L.cells[a] + 1 || !levels[l].coords[a])
+        return nfail(FSIMG_ERR_ARG, "level " + std::to_string(l) + ": coordinates / cells missing");
+    if (!levels[l].cell_solid) return nfail(FSIMG_ERR_ARG, "null cell_solid");
+    if (l > 0) {
+      const DevLevel &Lf = mom->lev[l - 1];
+      for (int a = 0; a < d; ++a)
+        if (Lf.cells[a] != 2 * L.cells[a])
+          return nfail(FSIMG_ERR_ARG, "levels must be nested (cells halved per axis)");
+    }
+  }
+  if (hipSetDevice(mom->ctx->device) != hipSuccess) return nfail(FSIMG_ERR_HIP, "hipSetDevice");
+  auto *f = new fsimg_fsi;
+  f->mom = mom;
+  f->ale = ale;
+  f->phys = *phys;
+  f->dim = d;
+  f->lev.resize(mom->lev.size());
+  auto bail = [&](fsimg_status st) {
+    fsimg_fsi_destroy(f);
+    return st;
+  };
+#define NW_CHK(expr)                          \
+  do {                                        \
+    fsimg_status st__ = (expr);               \
+    if (st__ != FSIMG_OK) return bail(st__);  \
+  } while (0)
+  for (size_t l = 0; l < mom->lev.size(); ++l) {
+    const DevLevel &L = mom->lev[l];
+    FsiLevel &F = f->lev[l];
+    int64_t ncell = 1;
+    for (int a = 0; a < d; ++a) ncell *= L.cells[a];
+    for (int a = 0; a < d; ++a) {
+      NW_CHK(falloc(f, &F.coord[a], (size_t)L.nnode[a]));
+      if (hipMemcpy(F.coord[a], levels[l].coords[a], L.nnode[a] * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return bail(nfail(FSIMG_ERR_HIP, "coordinate upload failed"));
+    }
+    NW_CHK(falloc(f, &F.solid, (size_t)ncell));
+    if (hipMemcpy(F.solid, levels[l].cell_solid, ncell, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(nfail(FSIMG_ERR_HIP, "cell flag upload failed"));
+    if (l > 0) {
+      NW_CHK(falloc(f, &F.x, (size_t)(L.nrows * (d + 1))));
+      NW_CHK(falloc(f, &F.xo, (size_t)(L.nrows * (d + 1))));
+      NW_CHK(falloc(f, &F.u, (size_t)(L.nrows * d)));
+      NW_CHK(falloc(f, &F.uo, (size_t)(L.nrows * d)));
+    }
+    AsmLevel &A = F.dev;
+    for (int a = 0; a < 3; ++a) {
+      A.coord[a] = a < d ? F.coord[a] : nullptr;
+      A.cells[a] = L.cells[a];
+      A.nnode[a] = L.nnode[a];
+    }
+    A.solid = F.solid;
+    A.rowptr = L.rowptr;
+    A.colind = L.colind;
+    A.mask = L.mask;
+  }
+  // fine nodes of a solid cell (interface and solid: the support of eq. problem:2)
+  {
+    const DevLevel &L = mom->lev[0];
+    std::vector<uint8_t> ns(L.nrows, 0);
+    int64_t ncell = 1;
+    for (int a = 0; a < d; ++a) ncell *= L.cells[a];
+    for (int64_t e = 0; e < ncell; ++e) {
+      if (!levels[0].cell_solid[e]) continue;
+      int ea[3] = {0, 0, 0};
+      int64_t r = e;
+      for (int a = 0; a < d; ++a) {
+        ea[a] = (int)(r % L.cells[a]);
+        r /= L.cells[a];
+      }
+      for (int i = 0; i < (d == 3 ? 27 : 9); ++i) {
+        int64_t g = 0, st = 1;
+        for (int a = 0; a < d; ++a) {
+          const int la = (i / (a == 0 ? 1 : (a == 1 ? 3 : 9))) % 3;
+          g += st * (2 * ea[a] + la);
+          st *= L.nnode[a];
+        }
+        ns[g] = 1;
+      }
+    }
+    NW_CHK(falloc(f, &f->node_solid, (size_t)L.nrows));
+    if (hipMemcpy(f->node_solid, ns.data(), L.nrows, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(nfail(FSIMG_ERR_HIP, "node flag upload failed"));
+    NW_CHK(falloc(f, &f->res, (size_t)L.n));
+    NW_CHK(falloc(f, &f->W, (size_t)L.n));
+    NW_CHK(falloc(f, &f->xt, (size_t)L.n));
+    if (ale) {
+      const int64_t na = ale->lev[0].n;
+      NW_CHK(falloc(f, &f->du, (size_t)na));
+      NW_CHK(falloc(f, &f->b5, (size_t)na));
+      NW_CHK(falloc(f, &f->ut, (size_t)na));
+    }
+    NW_CHK(falloc(f, &f->dflag, 2));
+    NW_CHK(falloc(f, &f->dnorm, 1));
+  }
+  if (hipHostMalloc((void **)&f->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&f->hnorm, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    return bail(nfail(FSIMG_ERR_OOM, "pinned host memory"));
+#undef NW_CHK
+  *out = f;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_fsi_residual(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                                const double *u_old, double *res, void *stream) {
+  if (!f || !x || !u || !x_old || !u_old || !res) return nfail(FSIMG_ERR_ARG, "null argument");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double nrm;
+  NW_TRY(eval_residual(f, x, u, x_old, u_old, s, &nrm, false));
+  NW_HIP(hipMemcpyAsync(res, f->res, f->mom->lev[0].n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  NW_HIP(hipStreamSynchronize(s));
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_fsi_jacobian(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                                const double *u_old, void *stream) {
+  if (!f || !x || !u || !x_old || !u_old) return nfail(FSIMG_ERR_ARG, "null argument");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  f->have_jac = false;
+  NW_TRY(assemble_jacobian(f, x, u, x_old, u_old, static_cast<hipStream_t>(stream)));
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_fsi_drop_jacobian(fsimg_fsi *f) {
+  if (!f) return nfail(FSIMG_ERR_ARG, "null object");
+  f->have_jac = false;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *x_old,
+                              const double *u_old, const fsimg_newton_opts *opts,
+                              fsimg_newton_stats *stats, void *stream) {
+  if (!f || !x || !u || !x_old || !u_old) return nfail(FSIMG_ERR_ARG, "null argument");
+  if (!f->ale) return nfail(FSIMG_ERR_ARG, "the Newton loop needs an ALE hierarchy");
+  fsimg_newton_opts o;
+  fsimg_default_newton_opts(&o);
+  if (opts) o = *opts;
+  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0))
+    return nfail(FSIMG_ERR_ARG, "bad Newton options");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  fsimg_newton_stats st;
+  std::memset(&st, 0, sizeof st);
+  const auto t_start = std::chrono::steady_clock::now();
+  const DevLevel &Lm = f->mom->lev[0];
+  const DevLevel &La = f->ale->lev[0];
+  const int d = f->dim;
+  auto finish = [&](fsimg_status status) {
+    st.status = status;
+    st.ms_total = ms_since(t_start);
+    if (stats) *stats = st;
+    return status;
+  };
+  // the ALE matrix never changes: factor it once
+  if (!f->ale->factored) {
+    const fsimg_status fs = fsimg_factor(f->ale, s);
+    if (fs != FSIMG_OK) return finish(fs);
+  }
+
+  double nrm = 0.0;
+  auto t0 = std::chrono::steady_clock::now();
+  fsimg_status rs = eval_residual(f, x, u, x_old, u_old, s, &nrm, true);
+  st.ms_residual += ms_since(t0);
+  if (rs != FSIMG_OK) return finish(rs);
+  const double nrm0 = nrm;
+  st.res0 = nrm0;
+  st.res_hist[0] = nrm;
+  double rate = -1.0;  // no rate before the first step
+  fsimg_status status = FSIMG_ERR_NOCONV;
+  for (int l = 0;; ++l) {
+    if (nrm <= std::max(o.rtol * nrm0, o.atol)) {
+      status = FSIMG_OK;
+      break;
+    }
+    if (l >= o.max_steps) break;
+    if (!f->have_jac || rate > o.gamma) {
+      t0 = std::chrono::steady_clock::now();
+      fsimg_status js = assemble_jacobian(f, x, u, x_old, u_old, s);
+      st.ms_jacobian += ms_since(t0);
+      if (js != FSIMG_OK) return finish(js);
+      t0 = std::chrono::steady_clock::now();
+      js = fsimg_factor(f->mom, s);
+      NW_HIP(hipStreamSynchronize(s));
+      st.ms_factor += ms_since(t0);
+      if (js != FSIMG_OK) return finish(js);
+      f->have_jac = true;
+      ++st.jacobians;
+    }
+    // momentum: J W = R (eq. problem:1)
+    t0 = std::chrono::steady_clock::now();
+    launch_fill<double>(f->W, Lm.n, 0.0, s);
+    fsimg_stats ls;
+    fsimg_status ss = fsimg_solve(f->mom, f->res, f->W, &ls, s);
+    st.lin_iters_mom += ls.iters;
+    if (ss != FSIMG_OK) {
+      st.ms_solve += ms_since(t0);
+      return finish(ss);
+    }
+    // interface / solid deformation increment k theta W_v (eq. problem:2), the
+    // initial guess and identity-row data of the ALE solve (eq. problem:3)
+    launch_deform(Lm.nrows, d, f->node_solid, f->phys.k, f->phys.theta, f->W, d + 1, 1, nullptr,
+                  nullptr, f->du, s);
+    NW_HIP(hipGetLastError());
+    ss = fsimg_solve(f->ale, f->b5, f->du, &ls, s);
+    st.lin_iters_ale += ls.iters;
+    st.ms_solve += ms_since(t0);
+    if (ss != FSIMG_OK) return finish(ss);
+    // line search
+    double omega = 1.0, nt = 0.0;
+    for (int hv = 0;; ++hv) {
+      launch_axpy_to(x, f->W, omega, f->xt, Lm.n, s);
+      launch_axpy_to(u, f->du, omega, f->ut, La.n, s);
+      t0 = std::chrono::steady_clock::now();
+      rs = eval_residual(f, f->xt, f->ut, x_old, u_old, s, &nt, true);
+      st.ms_residual += ms_since(t0);
+      if (rs != FSIMG_OK) return finish(rs);
+      if (nt < nrm || hv >= o.max_halvings) break;
+      omega *= 0.5;
+      ++st.halvings;
+    }
+    NW_HIP(hipMemcpyAsync(x, f->xt, Lm.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NW_HIP(hipMemcpyAsync(u, f->ut, La.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (l < 32) st.omega_hist[l] = omega;
+    rate = nt / nrm;
+    nrm = nt;
+    ++st.steps;
+    if (st.steps < 32) st.res_hist[st.steps] = nrm;
+  }
+  NW_HIP(hipStreamSynchronize(s));
+  st.res = nrm;
+  return finish(status);
+}
+
+}  // extern "C"

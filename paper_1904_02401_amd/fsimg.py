@@ -1,4 +1,4 @@
-"""ctypes binding of the fsimg C ABI (include/fsimg.h).
+"""ctypes binding of the fsimg C ABI (include/fsimg.h, include/fsimg_newton.h).
 
 Argument marshalling only: every function forwards to the entry point of the
 same name in libfsimg.so, which runs all numerical work in HIP kernels on the
@@ -82,6 +82,36 @@ class fsimg_level_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fsimg_phys(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("rho_f", "nu_f", "rho_s", "mu_s", "lambda_s", "k",
+                                                "theta", "alpha0")]
+
+
+class fsimg_fsi_level(ctypes.Structure):
+    _fields_ = [("coords", ctypes.c_void_p * 3), ("cell_solid", ctypes.c_void_p)]
+
+
+class fsimg_newton_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("max_halvings", ctypes.c_int)]
+
+
+class fsimg_newton_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_int), ("jacobians", ctypes.c_int),
+                ("halvings", ctypes.c_int), ("lin_iters_mom", ctypes.c_int),
+                ("lin_iters_ale", ctypes.c_int), ("res0", ctypes.c_double), ("res", ctypes.c_double),
+                ("res_hist", ctypes.c_double * 32), ("omega_hist", ctypes.c_double * 32),
+                ("ms_total", ctypes.c_double), ("ms_residual", ctypes.c_double),
+                ("ms_jacobian", ctypes.c_double), ("ms_factor", ctypes.c_double),
+                ("ms_solve", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n not in ("res_hist", "omega_hist")}
+        d["res_hist"] = [self.res_hist[i] for i in range(min(self.steps + 1, 32))]
+        d["omega_hist"] = [self.omega_hist[i] for i in range(min(self.steps, 32))]
+        return d
+
+
 # entry point -> argument types
 _P, _I, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
@@ -127,6 +157,15 @@ _SIGS = {
     "fsimg_tune_save": (_I, [_P, ctypes.c_char_p]),
     "fsimg_tune_load": (_I, [_P, ctypes.c_char_p]),
     "fsimg_last_error": (ctypes.c_char_p, []),
+    "fsimg_fsi_create": (_I, [_P, _P, ctypes.POINTER(fsimg_fsi_level), ctypes.POINTER(fsimg_phys),
+                              ctypes.POINTER(_P)]),
+    "fsimg_fsi_destroy": (None, [_P]),
+    "fsimg_fsi_residual": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "fsimg_fsi_jacobian": (_I, [_P, _P, _P, _P, _P, _P]),
+    "fsimg_default_newton_opts": (None, [ctypes.POINTER(fsimg_newton_opts)]),
+    "fsimg_fsi_newton": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(fsimg_newton_opts),
+                              ctypes.POINTER(fsimg_newton_stats), _P]),
+    "fsimg_fsi_drop_jacobian": (_I, [_P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -456,3 +495,61 @@ def fsimg_tune_save(ctx, path: str):
 
 def fsimg_tune_load(ctx, path: str):
     _check(load().fsimg_tune_load(ctx, os.fsencode(path)))
+
+
+# ------------------------------------------------------------ Newton loop
+def fsimg_phys_of(params: dict) -> fsimg_phys:
+    return fsimg_phys(**{n: float(params[n]) for n, _ in fsimg_phys._fields_})
+
+
+def fsimg_fsi_create(mom, ale, levels, params: dict):
+    """levels: per multigrid level (coords per axis, cell_solid uint8) of the
+    momentum hierarchy; params: the fsimg_phys fields."""
+    keep = []
+    arr = (fsimg_fsi_level * len(levels))()
+    for l, (coords, solid) in enumerate(levels):
+        cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coords]
+        sd = np.ascontiguousarray(solid, dtype=np.uint8)
+        keep += cs + [sd]
+        for a in range(3):
+            arr[l].coords[a] = cs[a].ctypes.data if a < len(cs) else None
+        arr[l].cell_solid = sd.ctypes.data
+    out = ctypes.c_void_p()
+    _check(load().fsimg_fsi_create(mom, ale, arr, ctypes.byref(fsimg_phys_of(params)),
+                                   ctypes.byref(out)))
+    return out.value
+
+
+def fsimg_fsi_destroy(f):
+    load().fsimg_fsi_destroy(f)
+
+
+def fsimg_fsi_residual(f, x, u, x_old, u_old, res, stream=None):
+    _check(load().fsimg_fsi_residual(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _dev(res),
+                                     _stream(stream)))
+
+
+def fsimg_fsi_jacobian(f, x, u, x_old, u_old, stream=None):
+    _check(load().fsimg_fsi_jacobian(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _stream(stream)))
+
+
+def fsimg_default_newton_opts(**overrides) -> fsimg_newton_opts:
+    o = fsimg_newton_opts()
+    load().fsimg_default_newton_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def fsimg_fsi_newton(f, x, u, x_old, u_old, opts=None, stream=None, raise_on_noconv: bool = True) -> dict:
+    st = fsimg_newton_stats()
+    o = opts if opts is not None else fsimg_default_newton_opts()
+    rc = load().fsimg_fsi_newton(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), ctypes.byref(o),
+                                 ctypes.byref(st), _stream(stream))
+    if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
+        _check(rc)
+    return st.as_dict()
+
+
+def fsimg_fsi_drop_jacobian(f):
+    _check(load().fsimg_fsi_drop_jacobian(f))

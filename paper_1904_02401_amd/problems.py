@@ -25,3 +25,22 @@ def request_data(problem, states=(), rhs=()):
     return RequestData(level_dicts(problem, "mom"), level_dicts(problem, "ale"), problem.rhs["mom"],
                        problem.rhs["ale"], fine.node_solid, problem.params["k"],
                        problem.params["theta"], states=vals, rhs=list(rhs))
+
+
+def fsi_levels(problem):
+    """Per-level geometry (coordinates per axis, cell_solid) for
+    fsimg.fsimg_fsi_create."""
+    return [(list(lev.coords), lev.cell_solid) for lev in problem.levels]
+
+
+def fsi_state(problem):
+    """The generator's state as Newton-loop vectors (node-major FP64 numpy):
+    x = (p = 0, v_cur), u_cur, x_old = (0, v_old), u_old."""
+    import numpy as np
+    n, d = problem.levels[0].nnodes, problem.dim
+    x = np.zeros((n, d + 1))
+    x[:, 1:] = problem.v_cur
+    xo = np.zeros((n, d + 1))
+    xo[:, 1:] = problem.v_old
+    return (x.ravel(), np.ascontiguousarray(problem.u_cur).ravel(), xo.ravel(),
+            np.ascontiguousarray(problem.u_old).ravel())

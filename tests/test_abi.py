@@ -10,7 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "fsimg.h")).read()
+    inc = os.path.join(ROOT, "include")
+    txt = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(fsimg_[a-z_0-9]+)\s*\(", txt)))
 
@@ -18,7 +19,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("fsimg_hier_create", "fsimg_factor", "fsimg_solve", "fsimg_deform_update",
-              "fsimg_vcycle", "fsimg_last_error"):
+              "fsimg_vcycle", "fsimg_last_error", "fsimg_fsi_residual", "fsimg_fsi_jacobian",
+              "fsimg_fsi_newton"):
         assert n in names
 
 

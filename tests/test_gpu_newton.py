@@ -1,0 +1,221 @@
+"""The Newton loop on the GPU (include/fsimg_newton.h) against the oracle
+(oracle.fsi): the condensed residual element by element, the assembled
+approximate Jacobian on every multigrid level (its action on random vectors,
+against the oracle's complex-step Jacobian at the injected state), and whole
+Newton time steps (residual histories, Jacobian reuse decisions, the final
+state) against the oracle's Newton loop with direct solves."""
+import numpy as np
+import pytest
+
+from fsigen import config_problem
+from oracle import to_csr
+from oracle.fsi import Mesh, inject, jacobian_bsr, newton, newton_residual
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1904_02401_amd import fsimg  # noqa: E402
+from paper_1904_02401_amd.problems import fsi_levels, fsi_state, level_dicts  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fsimg.fsimg_ctx_create(0)
+    yield c
+    fsimg.fsimg_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def probs():
+    return {name: config_problem(name, seed=0) for name in ("t2", "t3")}
+
+
+class Fsi:
+    """momentum + ALE hierarchies and the Newton object of a problem."""
+
+    def __init__(self, ctx, P, precision=fsimg.FSIMG_FP64, rtol=1e-10, ale=True):
+        o = fsimg.fsimg_default_opts(precision=precision, rtol=rtol)
+        self.mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
+        self.ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), o) if ale else None
+        self.f = fsimg.fsimg_fsi_create(self.mom, self.ale, fsi_levels(P), P.params)
+
+    def close(self):
+        fsimg.fsimg_fsi_destroy(self.f)
+        fsimg.fsimg_hier_destroy(self.mom)
+        if self.ale:
+            fsimg.fsimg_hier_destroy(self.ale)
+
+
+def _perturbed(P, seed):
+    """the generator's state with a pressure field and perturbed velocity and
+    fluid deformation (a state off the generator's own)."""
+    x, u, xo, uo = fsi_state(P)
+    d, n = P.dim, P.levels[0].nnodes
+    rng = np.random.default_rng(seed)
+    X = x.reshape(n, d + 1).copy()
+    X[:, 0] = rng.standard_normal(n)
+    X[:, 1:] += 0.02 * rng.standard_normal((n, d))
+    mask = P.levels[0].systems["mom"].dirichlet.astype(bool)
+    Xf = X.ravel()
+    Xf[mask] = x[mask]
+    u2 = u + 1e-3 * rng.standard_normal(u.size)
+    return Xf, u2, xo, uo
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, dtype=torch.float64)
+
+
+@pytest.mark.parametrize("name", ["t2", "t3"])
+def test_residual_matches_oracle(ctx, probs, name):
+    P = probs[name]
+    lev = P.levels[0]
+    mask = lev.systems["mom"].dirichlet
+    S = Fsi(ctx, P, ale=False)
+    try:
+        for seed in (0, 1):
+            x, u, xo, uo = _perturbed(P, seed) if seed else fsi_state(P)
+            ref = newton_residual(Mesh(lev), P.params, x, u, xo, uo, mask)
+            res = torch.empty(x.size, device=DEV, dtype=torch.float64)
+            fsimg.fsimg_fsi_residual(S.f, _t(x), _t(u), _t(xo), _t(uo), res)
+            got = res.cpu().numpy()
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+            assert np.all(got[mask.astype(bool)] == 0.0)
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("name", ["t2", "t3"])
+def test_jacobian_matches_oracle_on_every_level(ctx, probs, name):
+    """The assembled Jacobian's action y = J_l z on three random vectors per
+    level equals the oracle's complex-step Jacobian at the state injected to
+    that level, with the level's identity rows."""
+    P = probs[name]
+    d = P.dim
+    x, u, xo, uo = _perturbed(P, 2)
+    S = Fsi(ctx, P, ale=False)
+    try:
+        fsimg.fsimg_fsi_jacobian(S.f, _t(x), _t(u), _t(xo), _t(uo))
+        meshes = [Mesh(lv) for lv in P.levels]
+        st = [x, u, xo, uo]
+        rng = np.random.default_rng(3)
+        for l, lv in enumerate(P.levels):
+            if l > 0:
+                st = [inject(meshes[l - 1], meshes[l], a, c)
+                      for a, c in zip(st, (d + 1, d, d + 1, d))]
+            A = lv.systems["mom"]
+            vals = jacobian_bsr(meshes[l], P.params, *st, A.rowptr, A.colind, A.dirichlet)
+            J = to_csr(type("M", (), dict(rowptr=A.rowptr, colind=A.colind, vals=vals, b=d + 1)))
+            for _ in range(3):
+                z = rng.standard_normal(J.shape[0])
+                y = torch.empty(z.size, device=DEV, dtype=torch.float64)
+                fsimg.fsimg_level_apply(S.mom, l, fsimg.FSIMG_FP64, _t(z), y)
+                torch.cuda.synchronize()
+                ref = J @ z
+                assert np.abs(y.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max(), l
+    finally:
+        S.close()
+
+
+def _oracle_newton(P, gamma, state=None, jac=None):
+    lev = P.levels[0]
+    A, E = lev.systems["mom"], lev.systems["ale"]
+    x, u, xo, uo = state if state is not None else fsi_state(P)
+    return newton(Mesh(lev), P.params, (A.rowptr, A.colind), A.dirichlet, to_csr(E), E.dirichlet,
+                  x, u, xo, uo, gamma=gamma, jac=jac)
+
+
+@pytest.mark.parametrize("name,gamma", [("t2", 0.05), ("t2", 0.0), ("t3", 0.05)])
+def test_newton_time_step_matches_oracle(ctx, probs, name, gamma):
+    """One time step: the same number of Newton steps and Jacobian
+    assemblies, residual histories within the linear-solve tolerance, and
+    the same converged state (the oracle solves its linear systems directly,
+    the GPU by FGMRES + multigrid to 1e-10)."""
+    P = probs[name]
+    xr, ur, info, _ = _oracle_newton(P, gamma)
+    x, u, xo, uo = fsi_state(P)
+    S = Fsi(ctx, P)
+    try:
+        X, U = _t(x), _t(u)
+        st = fsimg.fsimg_fsi_newton(S.f, X, U, _t(xo), _t(uo),
+                                    fsimg.fsimg_default_newton_opts(gamma=gamma))
+        torch.cuda.synchronize()
+    finally:
+        S.close()
+    assert st["status"] == fsimg.FSIMG_OK and info["status"] == "ok"
+    assert st["steps"] == info["steps"] and st["jacobians"] == info["jacobians"]
+    h_gpu, h_ref = np.array(st["res_hist"]), np.array(info["res"])
+    big = h_ref > 1e-5 * h_ref[0]
+    np.testing.assert_allclose(h_gpu[big], h_ref[big], rtol=1e-5)
+    assert st["omega_hist"] == info["omegas"]
+    xg, ug = X.cpu().numpy(), U.cpu().numpy()
+    assert np.abs(xg - xr).max() <= 1e-7 * np.abs(xr).max()
+    assert np.abs(ug - ur).max() <= 1e-7 * np.abs(ur).max()
+
+
+def test_newton_reuses_jacobian_across_time_steps(ctx, probs):
+    """A Jacobian carried into the next time step is kept while the rate
+    stays below gamma (here: always), as in the oracle."""
+    P = probs["t2"]
+    x1, u1, _, jac = _oracle_newton(P, 0.05)
+    _, _, info2, _ = _oracle_newton(P, 2.0, state=(x1, u1, x1, u1), jac=jac)
+    x, u, xo, uo = fsi_state(P)
+    S = Fsi(ctx, P)
+    try:
+        X, U = _t(x), _t(u)
+        fsimg.fsimg_fsi_newton(S.f, X, U, _t(xo), _t(uo), fsimg.fsimg_default_newton_opts(gamma=0.05))
+        Xo, Uo = X.clone(), U.clone()
+        st = fsimg.fsimg_fsi_newton(S.f, X, U, Xo, Uo, fsimg.fsimg_default_newton_opts(gamma=2.0))
+        torch.cuda.synchronize()
+    finally:
+        S.close()
+    assert info2["jacobians"] == 0 and st["jacobians"] == 0
+    assert st["steps"] == info2["steps"]
+
+
+def test_newton_mixed_precision_reaches_the_fp64_state(ctx, probs):
+    """FP32 V-cycles inside FP64 FGMRES and FP64 residuals: the same
+    converged time step."""
+    P = probs["t3"]
+    out = {}
+    for prec in (fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED):
+        x, u, xo, uo = fsi_state(P)
+        S = Fsi(ctx, P, precision=prec, rtol=1e-8)
+        try:
+            X, U = _t(x), _t(u)
+            st = fsimg.fsimg_fsi_newton(S.f, X, U, _t(xo), _t(uo))
+            torch.cuda.synchronize()
+            assert st["status"] == fsimg.FSIMG_OK
+            out[prec] = (X.cpu().numpy(), U.cpu().numpy())
+        finally:
+            S.close()
+    for a, b in zip(out[fsimg.FSIMG_FP64], out[fsimg.FSIMG_MIXED]):
+        assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+
+
+def test_newton_refusals(ctx, probs):
+    P = probs["t2"]
+    S = Fsi(ctx, P, ale=False)
+    try:
+        x, u, xo, uo = (_t(a) for a in fsi_state(P))
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_fsi_newton(S.f, x, u, xo, uo)
+        assert ei.value.status == fsimg.FSIMG_ERR_ARG
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_fsi_create(S.mom, None, fsi_levels(P), dict(P.params, k=0.0))
+        assert ei.value.status == fsimg.FSIMG_ERR_ARG
+        # an inverted fluid deformation (u_1 = -2 x_1: det F = -1) is reported
+        X1 = np.stack(np.meshgrid(*P.levels[0].coords[::-1], indexing="ij")[::-1], axis=-1).reshape(-1, 2)
+        ub = np.zeros_like(X1)
+        ub[:, 0] = -2.0 * X1[:, 0]
+        bad = _t(ub.ravel())
+        res = torch.empty_like(x)
+        with pytest.raises(fsimg.FsimgError) as ei:
+            fsimg.fsimg_fsi_residual(S.f, x, bad, xo, uo, res)
+        assert ei.value.status == fsimg.FSIMG_ERR_SINGULAR
+    finally:
+        S.close()
