@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix rate
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector rate
 
 
 def log(msg):
@@ -213,6 +214,129 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
         fsimg.fsimg_hier_destroy(h)
     fsimg.fsimg_ctx_destroy(ctx)
     return res
+
+
+def asm_flops_per_element(dim, solid):
+    """Algorithmic flops of one element Jacobian as the kernel's formula
+    states it: per (row node, column node, Gauss point) the fluid block
+    (inertia, transport, convection, viscous, pressure, divergence and
+    stabilisation entries) costs 100 flops in 3D / 57 in 2D, the solid block
+    (mass and the linearised first Piola stress) 129 / 62; 3^d Gauss points,
+    (3^d)^2 node pairs."""
+    nn = 3 ** dim
+    per = (129 if solid else 100) if dim == 3 else (62 if solid else 57)
+    return nn * nn * nn * per
+
+
+def run_newton(args, P):
+    """Time steps of the approximate Newton loop on the GPU (residual and
+    Jacobian assembly, Jacobian reuse, momentum / deformation / ALE solves,
+    line search), each from the generator's seeded state."""
+    import numpy as np
+    import torch
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import fsi_levels, fsi_state, level_dicts
+
+    prec = fsimg.FSIMG_FP64 if args.only == "fp64" else fsimg.FSIMG_MIXED
+    tag = "fp64" if prec == fsimg.FSIMG_FP64 else "mixed"
+    ctx = fsimg.fsimg_ctx_create(0)
+    o = fsimg.fsimg_default_opts(precision=prec)
+    t0 = time.perf_counter()
+    mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
+    ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), o)
+    f = fsimg.fsimg_fsi_create(mom, ale, fsi_levels(P), P.params)
+    if not args.no_tune:
+        fsimg.fsimg_factor(mom)
+        fsimg.fsimg_factor(ale)
+        fsimg.fsimg_hier_tune(mom)
+        fsimg.fsimg_hier_tune(ale)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    init = [torch.tensor(a, device=dev) for a in fsi_state(P)]
+    x, u, xo, uo = (a.clone() for a in init)
+    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma)
+
+    def time_step():
+        # one time step from the seeded state, Jacobian assembled afresh: every
+        # timed step does the same work
+        for dst, src in zip((x, u, xo, uo), init):
+            dst.copy_(src)
+        fsimg.fsimg_fsi_drop_jacobian(f)
+        st = fsimg.fsimg_fsi_newton(f, x, u, xo, uo, nopts, raise_on_noconv=False)
+        log(f"newton time step: status {st['status']}, {st['steps']} steps, {st['jacobians']} "
+            f"Jacobians, {st['halvings']} halvings, res {st['res0']:.3e} -> {st['res']:.3e}, "
+            f"{st['ms_total']:.0f} ms")
+        return st
+
+    for _ in range(args.warmup):
+        time_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [time_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_ts = (time.perf_counter() - t0) / args.steps
+    for st in stats:
+        if st["status"] != fsimg.FSIMG_OK:
+            log(f"newton: a time step ended with status {st['status']} after {st['steps']} steps")
+    # the finest level's element kernels, event-timed per launch on the launch stream
+    fsimg.fsimg_fsi_set_profile(f, 1)
+    for _ in range(3):
+        fsimg.fsimg_fsi_jacobian(f, x, u, xo, uo)
+        res = torch.empty_like(x)
+        fsimg.fsimg_fsi_residual(f, x, u, xo, uo, res)
+    prof = fsimg.fsimg_fsi_profile(f)
+    fsimg.fsimg_fsi_set_profile(f, 0)
+    lev = P.levels[0]
+    ns = int(lev.cell_solid.sum())
+    nf = lev.ncells - ns
+    flops = nf * asm_flops_per_element(P.dim, False) + ns * asm_flops_per_element(P.dim, True)
+    launches_per_pass = 2 ** P.dim
+    jac_pass_ms = prof["jac_ms"] / max(prof["jac_launches"], 1) * launches_per_pass
+    avg_launch_ms = prof["jac_ms"] / max(prof["jac_launches"], 1)
+    tf = flops / (jac_pass_ms * 1e-3) / 1e12
+    n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
+    n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
+    nb = lev.systems["mom"].nnzb
+    b = P.dim + 1
+    # bytes the colouring moves: every element reads and writes its (3^d)^2 blocks
+    rmw_bytes = lev.ncells * (3 ** P.dim) ** 2 * b * b * 8 * 2
+    tot = lambda k: sum(s[k] for s in stats)
+    out = {
+        "metric": "Newton time steps: (momentum + ALE unknowns) x time steps per second",
+        "value": (n_mom + n_ale) / t_ts,
+        "unit": "DoF/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_ts * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if tag == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: one Newton time step (theta = {P.params['theta']}, "
+                               f"k = {P.params['k']}) from the seeded state, Jacobian assembled afresh, "
+                               f"gamma_nt = {args.gamma}, Newton rtol 1e-8 (max-norm), linear solves to 1e-8",
+                   "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag},
+        "roofline": {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops / launches_per_pass, "avg_launch_ms": avg_launch_ms,
+                     "launches": prof["jac_launches"],
+                     "rmw_GBs": rmw_bytes / (jac_pass_ms * 1e-3) / 1e9,
+                     "matrix_bytes": nb * b * b * 8},
+        "residual_kernel": {"kernel": f"k_asm_res<{P.dim}>",
+                            "avg_launch_ms": prof["res_ms"] / max(prof["res_launches"], 1),
+                            "launches": prof["res_launches"]},
+        "newton": {"time_steps": args.steps, "newton_steps": tot("steps"),
+                   "jacobians": tot("jacobians"), "halvings": tot("halvings"),
+                   "momentum_iters": tot("lin_iters_mom"), "ale_iters": tot("lin_iters_ale"),
+                   "ms_residual": tot("ms_residual") / args.steps,
+                   "ms_jacobian_assembly": tot("ms_jacobian") / args.steps,
+                   "ms_factor": tot("ms_factor") / args.steps, "ms_solve": tot("ms_solve") / args.steps,
+                   "res_hist_last": stats[-1]["res_hist"], "setup_s": t_setup},
+    }
+    fsimg.fsimg_fsi_destroy(f)
+    fsimg.fsimg_hier_destroy(mom)
+    fsimg.fsimg_hier_destroy(ale)
+    fsimg.fsimg_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(P, iters_gpu, budget_s=20.0):
@@ -494,6 +618,10 @@ def main():
     ap.add_argument("--smoother", choices=["vanka", "ilu"], default="vanka",
                     help="multigrid smoother (ilu: block ILU(0), level-scheduled)")
     ap.add_argument("--no-mass", action="store_true")
+    ap.add_argument("--newton", action="store_true",
+                    help="time steps of the GPU Newton loop (residual / Jacobian assembly, reuse, "
+                         "line search) instead of one linear Newton-step solve")
+    ap.add_argument("--gamma", type=float, default=0.05, help="Newton: Jacobian reuse threshold")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
@@ -544,6 +672,9 @@ def main():
     if args.kernels_only:
         kernels_only(P, fsimg.FSIMG_MIXED if args.only == "mixed" else fsimg.FSIMG_FP64,
                      args.kernels_only)
+        return
+    if args.newton:
+        run_newton(args, P)
         return
     lev = P.levels[0]
     n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b

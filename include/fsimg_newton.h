@@ -97,7 +97,8 @@ typedef struct {
   int jacobians;        /* Jacobians assembled (and factored) in this call */
   int halvings;         /* line-search halvings in this call */
   int lin_iters_mom, lin_iters_ale;  /* FGMRES iterations of the momentum / ALE solves */
-  double res0, res;     /* initial and final max-norm of B - A(U) (momentum and ALE rows) */
+  double res0, res;     /* initial and final max-norm of B - A(U) (momentum, ALE and
+                           condensation rows) */
   double res_hist[32];  /* the max-norm before step l (l < 32) */
   double omega_hist[32];/* the accepted line-search parameter of step l */
   double ms_total, ms_residual, ms_jacobian, ms_factor, ms_solve;  /* host wall times */
@@ -112,10 +113,13 @@ void fsimg_default_newton_opts(fsimg_newton_opts *o);
    the last rate ||R_l|| / ||R_{l-1}|| exceeded gamma (a Jacobian is kept
    across calls, i.e. across time steps); the momentum system J W = R
    (eq. problem:1) is solved by FGMRES + multigrid; the interface and solid
-   deformation increment is k theta W_v (eq. problem:2, one vector
-   addition); the ALE system E du = b5 with du = k theta W_v at its identity
-   rows (eq. problem:3) is solved likewise; then U += omega (W, du) with
-   omega = 1, halved while the max-norm of the residual does not decrease.
+   deformation increment is r_u + k theta W_v (eq. problem:2, one vector
+   addition), r_u = u_old + k theta v + k (1 - theta) v_old - u the residual
+   of the condensation relation at the nodes of solid cells (nonzero when a
+   time step starts from u = u_old); the ALE system E du = b5 with that
+   increment at its identity rows (eq. problem:3) is solved likewise; then
+   U += omega (W, du) with omega = 1, halved while the max-norm of the
+   residual (momentum, ALE and condensation rows) does not decrease.
    Requires an ALE hierarchy.  Returns OK, NOCONV (max_steps reached), a
    linear-solve failure, or ERR_SINGULAR (det F <= 0). */
 fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *x_old,
@@ -124,6 +128,15 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
 
 /* Forget the Jacobian held by the object (the next Newton call assembles). */
 fsimg_status fsimg_fsi_drop_jacobian(fsimg_fsi *f);
+
+/* Timing only: on != 0 records HIP events on the launch stream around every
+   launch of the finest level's element kernels (one launch per parity colour)
+   of the following residual and Jacobian assemblies and resets the sums;
+   fsimg_fsi_profile returns the summed milliseconds and launch counts
+   (any output pointer may be NULL). */
+fsimg_status fsimg_fsi_set_profile(fsimg_fsi *f, int on);
+fsimg_status fsimg_fsi_profile(const fsimg_fsi *f, double *jac_ms, int *jac_launches, double *res_ms,
+                               int *res_launches);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,11 @@ eq. aletime:2) with the solid deformation condensed into the velocity
 with respect to the ALE deformation dropped, eq. REDUCEDMATRIX / problem:1),
 and the Newton iteration of eq. newton with the Jacobian reuse rule of
 Sec. 5.5 (reassemble when the rate rho_l exceeds gamma_nt) and a halving line
-search.
+search (a trial state with det F <= 0 at a Gauss point counts as no
+decrease).  The Newton increment of the deformation on interface and solid
+nodes is k theta times the velocity increment plus the residual of the
+condensation relation (eq. problem:2 with its right-hand side b6, b7), so a
+time step may start from u = u_{n-1}.
 
 Readings (the same as the input generator's matrices): inertia and convection
 carry rho_f; the pressure enters the momentum rows as -k (J p F^-T, grad phi)
@@ -311,6 +315,28 @@ def jacobian_bsr(mesh, prm, x, u, x_old, u_old, rowptr, colind, mask):
     return vals
 
 
+def min_jacobian_det(mesh, prm, x, u, x_old, u_old):
+    """The smallest det F over all Gauss points (solid cells: F of the
+    condensed deformation)."""
+    f = _fields(mesh, prm, *_gather(mesh, x, u, x_old, u_old))
+    return float(np.linalg.det(np.eye(mesh.dim) + f["gu"][0]).min())
+
+
+def condensation_residual(mesh, prm, x, u, x_old, u_old):
+    """The residual of the deformation rows (eq. aletime:2, last line; eq.
+    problem:2) with the solid mass matrix cancelled: at the nodes of solid
+    cells u_old + k theta v + k (1 - theta) v_old - u, elsewhere 0.  Its
+    Newton increment is the residual itself plus k theta times the velocity
+    increment."""
+    d = mesh.dim
+    k, th = prm["k"], prm["theta"]
+    _, v = _split(x, d)
+    _, vo = _split(x_old, d)
+    r = np.asarray(u_old).reshape(-1, d) + k * th * v + k * (1 - th) * vo - np.asarray(u).reshape(-1, d)
+    r[~mesh.node_solid] = 0.0
+    return r.ravel()
+
+
 def inject(mesh_f, mesh_c, f, comps):
     """Nodal values of a fine-level field at the coarse nodes (nested Q2
     meshes: coarse node g is fine node 2g per axis)."""
@@ -339,9 +365,10 @@ def newton(mesh, prm, A_pattern, mom_mask, E, ale_mask, x, u, x_old, u_old, rtol
         R = newton_residual(mesh, prm, xs, us, x_old, u_old, mmask)
         b5 = -(E @ us)
         b5[amask] = 0.0
-        return R, b5, max(np.abs(R).max(), np.abs(b5).max())
+        ru = condensation_residual(mesh, prm, xs, us, x_old, u_old)
+        return R, b5, ru, max(np.abs(R).max(), np.abs(b5).max(), np.abs(ru).max())
 
-    R, b5, nrm = residuals(x, u)
+    R, b5, ru, nrm = residuals(x, u)
     info = dict(res=[nrm], jacobians=0, omegas=[], status="noconv")
     nrm0, rate = nrm, None
     for _ in range(max_steps):
@@ -356,19 +383,24 @@ def newton(mesh, prm, A_pattern, mom_mask, E, ale_mask, x, u, x_old, u_old, rtol
         dv = W.reshape(-1, d + 1)[:, 1:]
         lift = np.zeros_like(dv)
         lift[mesh.node_solid] = k * th * dv[mesh.node_solid]
+        lift += ru.reshape(-1, d)
         rhs = b5.copy()
         rhs[amask] = lift.ravel()[amask]
         du = spla.spsolve(E.tocsc(), rhs)
         omega = 1.0
         for h in range(max_halvings + 1):
             xt, ut = x + omega * W, u + omega * du
-            Rt, b5t, nt = residuals(xt, ut)
-            if nt < nrm or h == max_halvings:
+            inverted = min_jacobian_det(mesh, prm, xt, ut, x_old, u_old) <= 0.0
+            Rt, b5t, rut, nt = residuals(xt, ut)
+            if inverted and h == max_halvings:
+                info["status"] = "inverted"
+                return xt, ut, info, jac
+            if not inverted and (nt < nrm or h == max_halvings):
                 break
             omega *= 0.5
         info["omegas"].append(omega)
         rate = nt / nrm
-        x, u, R, b5, nrm = xt, ut, Rt, b5t, nt
+        x, u, R, b5, ru, nrm = xt, ut, Rt, b5t, rut, nt
         info["res"].append(nrm)
     else:
         if nrm <= max(rtol * nrm0, atol):

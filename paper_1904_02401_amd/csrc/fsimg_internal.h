@@ -309,17 +309,24 @@ struct AsmState {
 };
 // the approximate Jacobian into vals [nnzb*(d+1)^2] (zeroed first, identity
 // rows and columns of L.mask applied); flag[0] = 1 if det F <= 0 at a Gauss
-// point, flag[1] = 1 if the pattern lacks an element coupling
+// point, flag[1] = 1 if the pattern lacks an element coupling.  ev (nullable):
+// 2 events per parity colour, recorded around that colour's launch
 void launch_asm_jacobian(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S,
-                         double *vals, int64_t nrows, int64_t nnzb, int *flag, hipStream_t s);
-// res = -A(U) (zero at identity rows), flags as above
+                         double *vals, int64_t nrows, int64_t nnzb, int *flag, hipStream_t s,
+                         hipEvent_t *ev = nullptr);
+// res = -A(U) (zero at identity rows), flags and events as above
 void launch_asm_residual(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S,
-                         double *res, int64_t nrows, int *flag, hipStream_t s);
+                         double *res, int64_t nrows, int *flag, hipStream_t s,
+                         hipEvent_t *ev = nullptr);
 void launch_inject(const double *f, double *c, const int *nnode_f, const int *nnode_c, int comps,
                    hipStream_t s);
 void launch_axpy_to(const double *x, const double *z, double omega, double *y, int64_t n,
                     hipStream_t s);
 void launch_neg_free(double *y, const uint8_t *mask, int64_t n, hipStream_t s);
 void launch_absmax_u64(const double *x, int64_t n, unsigned long long *out, hipStream_t s);
+// r = u_old + k theta v + k (1 - theta) v_old - u at mask nodes, 0 elsewhere
+void launch_cond_residual(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
+                          const double *x, const double *xo, const double *u, const double *uo, double *r,
+                          hipStream_t s);
 
 }  // namespace fsimg

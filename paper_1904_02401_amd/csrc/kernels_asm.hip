@@ -587,6 +587,23 @@ __global__ __launch_bounds__(256) void k_neg_free(double *__restrict__ y, const 
   if (i < n) y[i] = mask[i] ? 0.0 : -y[i];
 }
 
+// residual of the condensation relation (deformation rows, mass matrix
+// cancelled): r = u_old + k theta v + k (1 - theta) v_old - u at the nodes of
+// solid cells, 0 elsewhere; v, v_old from the (p, v) vectors x, x_old
+__global__ __launch_bounds__(256) void k_cond_residual(int64_t nnodes, int dim, const uint8_t *__restrict__ mask,
+                                                       double kt, double k1, const double *__restrict__ x,
+                                                       const double *__restrict__ xo,
+                                                       const double *__restrict__ u,
+                                                       const double *__restrict__ uo, double *__restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  const bool on = mask[i] != 0;
+  for (int c = 0; c < dim; ++c) {
+    const int64_t q = i * dim + c, pv = i * (dim + 1) + 1 + c;
+    r[q] = on ? uo[q] + kt * x[pv] + k1 * xo[pv] - u[q] : 0.0;
+  }
+}
+
 // *out = max(*out, max_i |x_i|); the bit patterns of non-negative doubles
 // order like the values, so an unsigned 64-bit atomic max is exact
 __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ x, int64_t n,
@@ -613,33 +630,39 @@ inline int64_t colour_count(const AsmLevel &L, int dim, int colour) {
 }  // namespace
 
 void launch_asm_jacobian(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S, double *vals,
-                         int64_t nrows, int64_t nnzb, int *flag, hipStream_t s) {
+                         int64_t nrows, int64_t nnzb, int *flag, hipStream_t s, hipEvent_t *ev) {
   const int b = dim + 1;
   const int64_t nv = nnzb * b * b;
   hipLaunchKernelGGL(k_asm_fill, dim3(grid_for(nv, 256)), dim3(256), 0, s, vals, nv, 0.0);
   for (int c = 0; c < (1 << dim); ++c) {
     const int64_t ne = colour_count(L, dim, c);
-    if (ne == 0) continue;
-    if (dim == 3)
-      hipLaunchKernelGGL(k_asm_jac<3>, dim3(ne), dim3(768), 0, s, L, P, S, vals, c, flag);
-    else
-      hipLaunchKernelGGL(k_asm_jac<2>, dim3(ne), dim3(128), 0, s, L, P, S, vals, c, flag);
+    if (ev) (void)hipEventRecord(ev[2 * c], s);
+    if (ne > 0) {
+      if (dim == 3)
+        hipLaunchKernelGGL(k_asm_jac<3>, dim3(ne), dim3(768), 0, s, L, P, S, vals, c, flag);
+      else
+        hipLaunchKernelGGL(k_asm_jac<2>, dim3(ne), dim3(128), 0, s, L, P, S, vals, c, flag);
+    }
+    if (ev) (void)hipEventRecord(ev[2 * c + 1], s);
   }
   hipLaunchKernelGGL(k_asm_identity, dim3(grid_for(nrows, 256)), dim3(256), 0, s, L.rowptr, L.colind,
                      L.mask, nrows, b, vals, flag);
 }
 
 void launch_asm_residual(const AsmLevel &L, int dim, const AsmPhys &P, const AsmState &S, double *res,
-                         int64_t nrows, int *flag, hipStream_t s) {
+                         int64_t nrows, int *flag, hipStream_t s, hipEvent_t *ev) {
   const int64_t n = nrows * (dim + 1);
   hipLaunchKernelGGL(k_asm_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, res, n, 0.0);
   for (int c = 0; c < (1 << dim); ++c) {
     const int64_t ne = colour_count(L, dim, c);
-    if (ne == 0) continue;
-    if (dim == 3)
-      hipLaunchKernelGGL(k_asm_res<3>, dim3(ne), dim3(256), 0, s, L, P, S, res, c, flag);
-    else
-      hipLaunchKernelGGL(k_asm_res<2>, dim3(ne), dim3(128), 0, s, L, P, S, res, c, flag);
+    if (ev) (void)hipEventRecord(ev[2 * c], s);
+    if (ne > 0) {
+      if (dim == 3)
+        hipLaunchKernelGGL(k_asm_res<3>, dim3(ne), dim3(256), 0, s, L, P, S, res, c, flag);
+      else
+        hipLaunchKernelGGL(k_asm_res<2>, dim3(ne), dim3(128), 0, s, L, P, S, res, c, flag);
+    }
+    if (ev) (void)hipEventRecord(ev[2 * c + 1], s);
   }
 }
 
@@ -656,6 +679,14 @@ void launch_axpy_to(const double *x, const double *z, double omega, double *y, i
 
 void launch_neg_free(double *y, const uint8_t *mask, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_neg_free, dim3(grid_for(n, 256)), dim3(256), 0, s, y, mask, n);
+}
+
+void launch_cond_residual(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
+                          const double *x, const double *xo, const double *u, const double *uo, double *r,
+                          hipStream_t s) {
+  if (nnodes > 0)
+    hipLaunchKernelGGL(k_cond_residual, dim3(grid_for(nnodes, 256)), dim3(256), 0, s, nnodes, dim, mask,
+                       k * theta, k * (1.0 - theta), x, xo, u, uo, r);
 }
 
 void launch_absmax_u64(const double *x, int64_t n, unsigned long long *out, hipStream_t s) {

@@ -42,11 +42,18 @@ struct fsimg_fsi {
   // finest-level work vectors
   double *res = nullptr, *W = nullptr, *xt = nullptr;           // [n_mom]
   double *du = nullptr, *b5 = nullptr, *ut = nullptr;           // [n_ale]
+  double *ru = nullptr;  // [nrows*d] residual of the condensation relation (eq. problem:2)
   int *dflag = nullptr;                                          // [2] assembly flags
   unsigned long long *dnorm = nullptr;                           // max-norm slot
   int *hflag = nullptr;                                          // pinned host mirror
   unsigned long long *hnorm = nullptr;
   bool have_jac = false;
+  // profiling: events around the finest level's element launches (one pair
+  // per parity colour) and the accumulated times
+  bool profile = false;
+  hipEvent_t ev_jac[16] = {}, ev_res[16] = {};
+  double jac_ms = 0.0, res_ms = 0.0;
+  int jac_launches = 0, res_launches = 0;
 };
 
 namespace {
@@ -109,30 +116,46 @@ fsimg_status clear_flags(fsimg_fsi *f, hipStream_t s) {
   return FSIMG_OK;
 }
 
+// after a synchronisation: add the colour launches' event times
+void add_event_times(const hipEvent_t *ev, int ncolour, double *ms, int *count) {
+  for (int c = 0; c < ncolour; ++c) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * c], ev[2 * c + 1]) == hipSuccess) {
+      *ms += t;
+      ++*count;
+    }
+  }
+}
+
 fsimg_status flags_status(const int *flags) {
   if (flags[1]) return nfail(FSIMG_ERR_ARG, "the momentum block pattern lacks an element coupling");
   if (flags[0]) return nfail(FSIMG_ERR_SINGULAR, "det F <= 0 at a Gauss point (inverted element)");
   return FSIMG_OK;
 }
 
-// residual R = -A(U) on the finest level into f->res, and (with ALE) the ALE
-// residual b5 = -E u at the fluid rows; *norm = max-norm of both
+// residual R = -A(U) on the finest level into f->res; with the ALE system
+// also its residual b5 = -E u at the fluid rows and the residual of the
+// condensation relation on interface and solid nodes (f->ru); *norm = the
+// max-norm over all of them
 fsimg_status eval_residual(fsimg_fsi *f, const double *x, const double *u, const double *xo,
                            const double *uo, hipStream_t s, double *norm, bool with_ale) {
   const DevLevel &L = f->mom->lev[0];
   NW_TRY(clear_flags(f, s));
   launch_asm_residual(f->lev[0].dev, f->dim, asm_phys(f->phys), AsmState{x, u, xo, uo}, f->res,
-                      L.nrows, f->dflag, s);
+                      L.nrows, f->dflag, s, f->profile ? f->ev_res : nullptr);
   launch_absmax_u64(f->res, L.n, f->dnorm, s);
   if (with_ale) {
     DevLevel &A = f->ale->lev[0];
     NW_TRY(fsimg_level_apply(f->ale, 0, FSIMG_FP64, u, f->b5, s));
     launch_neg_free(f->b5, A.mask, A.n, s);
     launch_absmax_u64(f->b5, A.n, f->dnorm, s);
+    launch_cond_residual(L.nrows, f->dim, f->node_solid, f->phys.k, f->phys.theta, x, xo, u, uo, f->ru, s);
+    launch_absmax_u64(f->ru, A.n, f->dnorm, s);
   }
   NW_HIP(hipGetLastError());
   int flags[2];
   NW_TRY(read_flags(f, s, flags, norm));
+  if (f->profile) add_event_times(f->ev_res, 1 << f->dim, &f->res_ms, &f->res_launches);
   return flags_status(flags);
 }
 
@@ -156,13 +179,15 @@ fsimg_status assemble_jacobian(fsimg_fsi *f, const double *x, const double *u, c
       for (int q = 0; q < 4; ++q) launch_inject(src[q], dst[q], Lf.nnode, L.nnode, comps[q], s);
       S = AsmState{F.x, F.u, F.xo, F.uo};
     }
-    launch_asm_jacobian(F.dev, f->dim, P, S, L.vals64, L.nrows, L.nnzb, f->dflag, s);
+    launch_asm_jacobian(F.dev, f->dim, P, S, L.vals64, L.nrows, L.nnzb, f->dflag, s,
+                        (f->profile && l == 0) ? f->ev_jac : nullptr);
     if (L.vals32) launch_cast_d2f(L.vals64, L.vals32, L.nnzb * L.b * L.b, s);
   }
   NW_HIP(hipGetLastError());
   h->factored = false;
   int flags[2];
   NW_TRY(read_flags(f, s, flags, nullptr));
+  if (f->profile) add_event_times(f->ev_jac, 1 << f->dim, &f->jac_ms, &f->jac_launches);
   return flags_status(flags);
 }
 
@@ -188,7 +213,35 @@ void fsimg_fsi_destroy(fsimg_fsi *f) {
   }
   if (f->hflag) (void)hipHostFree(f->hflag);
   if (f->hnorm) (void)hipHostFree(f->hnorm);
+  for (int i = 0; i < 16; ++i) {
+    if (f->ev_jac[i]) (void)hipEventDestroy(f->ev_jac[i]);
+    if (f->ev_res[i]) (void)hipEventDestroy(f->ev_res[i]);
+  }
   delete f;
+}
+
+fsimg_status fsimg_fsi_set_profile(fsimg_fsi *f, int on) {
+  if (!f) return nfail(FSIMG_ERR_ARG, "null object");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  if (on && !f->ev_jac[0])
+    for (int i = 0; i < 16; ++i) {
+      NW_HIP(hipEventCreate(&f->ev_jac[i]));
+      NW_HIP(hipEventCreate(&f->ev_res[i]));
+    }
+  f->profile = on != 0;
+  f->jac_ms = f->res_ms = 0.0;
+  f->jac_launches = f->res_launches = 0;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_fsi_profile(const fsimg_fsi *f, double *jac_ms, int *jac_launches, double *res_ms,
+                               int *res_launches) {
+  if (!f) return nfail(FSIMG_ERR_ARG, "null object");
+  if (jac_ms) *jac_ms = f->jac_ms;
+  if (jac_launches) *jac_launches = f->jac_launches;
+  if (res_ms) *res_ms = f->res_ms;
+  if (res_launches) *res_launches = f->res_launches;
+  return FSIMG_OK;
 }
 
 fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_level *levels,
@@ -302,6 +355,7 @@ fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_
       NW_CHK(falloc(f, &f->du, (size_t)na));
       NW_CHK(falloc(f, &f->b5, (size_t)na));
       NW_CHK(falloc(f, &f->ut, (size_t)na));
+      NW_CHK(falloc(f, &f->ru, (size_t)na));
     }
     NW_CHK(falloc(f, &f->dflag, 2));
     NW_CHK(falloc(f, &f->dnorm, 1));
@@ -410,16 +464,18 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
       st.ms_solve += ms_since(t0);
       return finish(ss);
     }
-    // interface / solid deformation increment k theta W_v (eq. problem:2), the
-    // initial guess and identity-row data of the ALE solve (eq. problem:3)
-    launch_deform(Lm.nrows, d, f->node_solid, f->phys.k, f->phys.theta, f->W, d + 1, 1, nullptr,
+    // interface / solid deformation increment (eq. problem:2 with its
+    // right-hand side): the condensation residual plus k theta W_v; it is the
+    // initial guess and the identity-row data of the ALE solve (eq. problem:3)
+    launch_deform(Lm.nrows, d, f->node_solid, f->phys.k, f->phys.theta, f->W, d + 1, 1, f->ru,
                   nullptr, f->du, s);
     NW_HIP(hipGetLastError());
     ss = fsimg_solve(f->ale, f->b5, f->du, &ls, s);
     st.lin_iters_ale += ls.iters;
     st.ms_solve += ms_since(t0);
     if (ss != FSIMG_OK) return finish(ss);
-    // line search
+    // line search: a trial state with an inverted element (det F <= 0) counts
+    // as no decrease
     double omega = 1.0, nt = 0.0;
     for (int hv = 0;; ++hv) {
       launch_axpy_to(x, f->W, omega, f->xt, Lm.n, s);
@@ -427,8 +483,10 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
       t0 = std::chrono::steady_clock::now();
       rs = eval_residual(f, f->xt, f->ut, x_old, u_old, s, &nt, true);
       st.ms_residual += ms_since(t0);
-      if (rs != FSIMG_OK) return finish(rs);
-      if (nt < nrm || hv >= o.max_halvings) break;
+      const bool inverted = rs == FSIMG_ERR_SINGULAR;
+      if (rs != FSIMG_OK && !inverted) return finish(rs);
+      if (inverted && hv >= o.max_halvings) return finish(rs);
+      if (!inverted && (nt < nrm || hv >= o.max_halvings)) break;
       omega *= 0.5;
       ++st.halvings;
     }

@@ -166,6 +166,9 @@ _SIGS = {
     "fsimg_fsi_newton": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(fsimg_newton_opts),
                               ctypes.POINTER(fsimg_newton_stats), _P]),
     "fsimg_fsi_drop_jacobian": (_I, [_P]),
+    "fsimg_fsi_set_profile": (_I, [_P, _I]),
+    "fsimg_fsi_profile": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D),
+                               ctypes.POINTER(_I)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -553,3 +556,15 @@ def fsimg_fsi_newton(f, x, u, x_old, u_old, opts=None, stream=None, raise_on_noc
 
 def fsimg_fsi_drop_jacobian(f):
     _check(load().fsimg_fsi_drop_jacobian(f))
+
+
+def fsimg_fsi_set_profile(f, on: int):
+    _check(load().fsimg_fsi_set_profile(f, on))
+
+
+def fsimg_fsi_profile(f) -> dict:
+    jm, rm = ctypes.c_double(), ctypes.c_double()
+    jn, rn = ctypes.c_int(), ctypes.c_int()
+    _check(load().fsimg_fsi_profile(f, ctypes.byref(jm), ctypes.byref(jn), ctypes.byref(rm),
+                                    ctypes.byref(rn)))
+    return dict(jac_ms=jm.value, jac_launches=jn.value, res_ms=rm.value, res_launches=rn.value)

@@ -219,3 +219,30 @@ def test_newton_refusals(ctx, probs):
         assert ei.value.status == fsimg.FSIMG_ERR_SINGULAR
     finally:
         S.close()
+
+
+def test_successive_time_steps_match_oracle(ctx, probs):
+    """Three time steps, each from the last converged state (u = u_old at
+    the start: the deformation increment carries the condensation residual),
+    with the Jacobian carried across steps: per step the same Newton and
+    Jacobian counts as the oracle and the same state."""
+    P = probs["t2"]
+    xr, ur, xor, uor = fsi_state(P)
+    jac = None
+    x, u, xo, uo = (_t(a) for a in fsi_state(P))
+    S = Fsi(ctx, P)
+    try:
+        for step in range(3):
+            if step:
+                xor, uor = xr.copy(), ur.copy()
+                xo.copy_(x)
+                uo.copy_(u)
+            xr, ur, info, jac = _oracle_newton(P, 0.05, state=(xr, ur, xor, uor), jac=jac)
+            st = fsimg.fsimg_fsi_newton(S.f, x, u, xo, uo, fsimg.fsimg_default_newton_opts(gamma=0.05))
+            torch.cuda.synchronize()
+            assert st["status"] == fsimg.FSIMG_OK and info["status"] == "ok"
+            assert (st["steps"], st["jacobians"]) == (info["steps"], info["jacobians"]), step
+            assert np.abs(x.cpu().numpy() - xr).max() <= 1e-7 * np.abs(xr).max()
+            assert np.abs(u.cpu().numpy() - ur).max() <= 1e-7 * np.abs(ur).max()
+    finally:
+        S.close()

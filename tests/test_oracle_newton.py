@@ -190,3 +190,29 @@ def test_newton_jacobian_reuse_rule(prob_t2):
     (x, u, i2, jac), _ = _newton(P, 0.05)
     (_, _, i3, _), _ = _newton(P, 2.0, jac=jac, state=(x, u, x, u))
     assert i3["jacobians"] == 0 and i3["status"] == "ok"
+
+
+def test_time_steps_from_the_previous_state_stay_bounded(prob_t2):
+    """Successive time steps, each started from the last converged state
+    (u = u_old, which violates the condensation relation by k v_old): the
+    deformation increment carries that residual (eq. problem:2 with its
+    right-hand side), every step converges, the condensation holds at the
+    end of each step, and the Crank-Nicolson solution stays bounded.  (With
+    the increment k theta dv alone, u loses k v_old per step and the same
+    run grows by a factor ~2.7 per step.)"""
+    P = prob_t2
+    lev = P.levels[0]
+    m = Mesh(lev)
+    d, n = P.dim, lev.nnodes
+    k, th = P.params["k"], P.params["theta"]
+    (x, u, info, jac), (xo, uo) = _newton(P, 0.05)
+    vmax = [np.abs(x.reshape(n, d + 1)[:, 1:]).max()]
+    for _ in range(4):
+        xo, uo = x.copy(), u.copy()
+        (x, u, info, jac), _ = _newton(P, 0.05, jac=jac, state=(x, u, xo, uo))
+        assert info["status"] == "ok"
+        v = x.reshape(n, d + 1)[:, 1:]
+        cond = uo.reshape(n, d) + k * th * v + k * (1 - th) * xo.reshape(n, d + 1)[:, 1:]
+        np.testing.assert_allclose(u.reshape(n, d)[m.node_solid], cond[m.node_solid], atol=1e-12)
+        vmax.append(np.abs(v).max())
+    assert max(vmax) < 2.0 * vmax[0]
