@@ -10,8 +10,9 @@
 // order is fixed (colours in order, Gauss points in order).  The element's
 // nodal fields, the basis values at the 3^d Gauss points, the fields at the
 // Gauss points and the per-point material data are staged in LDS; for the
-// Jacobian each thread owns one (row node, column node) pair and keeps its
-// (d+1) x (d+1) block in registers while it sums over the Gauss points.
+// Jacobian each thread owns one row node and (in 3D) two column nodes and
+// keeps their (d+1) x (d+1) blocks in registers while it sums over the Gauss
+// points (the row node's basis data are loaded once for both).
 #include "fsimg_internal.h"
 
 namespace fsimg {
@@ -162,10 +163,15 @@ __device__ __forceinline__ double qweight(int q) {
 //   solid (deformation condensed, dF = k theta grad dv):
 //     rho_s (dv, phi) + k theta (dF Sigma + F dSigma, grad phi).
 template <int D>
-__global__ __launch_bounds__(D == 3 ? 768 : 128) void k_asm_jac(AsmLevel L, AsmPhys P, AsmState S,
-                                                              double *__restrict__ vals, int colour,
-                                                              int *__restrict__ flag) {
+constexpr int jac_threads() { return D == 3 ? 384 : 128; }
+
+template <int D>
+__global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhys P, AsmState S,
+                                                            double *__restrict__ vals, int colour,
+                                                            int *__restrict__ flag) {
   constexpr int NN = D == 3 ? 27 : 9, B = D + 1, NF = 3 * D * (D + 1), NQS = 32;
+  constexpr int JT = D == 3 ? 2 : 1, NJ = (NN + JT - 1) / JT;  // column nodes per thread
+  static_assert(NN * NJ <= jac_threads<D>(), "one thread per (row node, column group)");
   __shared__ double s_nod[4][NN][D];  // v, v_old, u (condensed in solid cells), u_old
   __shared__ double s_N[NN][NN];      // [q][i]
   __shared__ double s_dN[D][NN][NN];  // [m][q][i], physical
@@ -189,8 +195,8 @@ __global__ __launch_bounds__(D == 3 ? 768 : 128) void k_asm_jac(AsmLevel L, AsmP
       s_nod[3][t][c] = uo;
     }
   }
-  if (t < NN * NN) {
-    const int q = t / NN, i = t % NN;
+  for (int it = t; it < NN * NN; it += blockDim.x) {
+    const int q = it / NN, i = it % NN;
     double N, dN[D];
     basis_at<D, NN>(q, i, G.h, N, dN);
     s_N[q][i] = N;
@@ -270,8 +276,8 @@ __global__ __launch_bounds__(D == 3 ? 768 : 128) void k_asm_jac(AsmLevel L, AsmP
     }
   }
   __syncthreads();
-  if (t < NN * NN) {
-    const int q = t / NN, i = t % NN;
+  for (int it = t; it < NN * NN; it += blockDim.x) {
+    const int q = it / NN, i = it % NN;
     const double *qs = s_qs[q];
     double dN[D];
     for (int m = 0; m < D; ++m) dN[m] = s_dN[m][q][i];
@@ -293,69 +299,95 @@ __global__ __launch_bounds__(D == 3 ? 768 : 128) void k_asm_jac(AsmLevel L, AsmP
     }
   }
   __syncthreads();
-  if (t >= NN * NN) return;
-  const int i = t / NN, j = t % NN;
-  double K[B][B];
-  for (int a = 0; a < B; ++a)
-    for (int c = 0; c < B; ++c) K[a][c] = 0.0;
+  // each thread: row node i and JT column nodes j = jb + jj * NJ (the i-side
+  // loads are shared by the JT blocks)
+  if (t >= NN * NJ) return;
+  const int i = t / NJ, jb = t % NJ;
+  int js[JT];
+  bool jok[JT];
+  for (int jj = 0; jj < JT; ++jj) {
+    const int j = jb + jj * NJ;
+    jok[jj] = j < NN;
+    js[jj] = jok[jj] ? j : NN - 1;
+  }
+  double K[JT][B][B];
+  for (int jj = 0; jj < JT; ++jj)
+    for (int a = 0; a < B; ++a)
+      for (int c = 0; c < B; ++c) K[jj][a][c] = 0.0;
   const double dK = P.alpha0 * k * k * G.hK * G.hK / (P.rho_f * (G.hK * G.hK + kt * P.nu_f));
   const double kt2 = kt * kt;
   for (int q = 0; q < NN; ++q) {
     const double *qs = s_qs[q];
     const double wq = qs[0];
-    const double Ni = s_N[q][i], Nj = s_N[q][j], NNij = Ni * Nj;
-    double dNi[D], dNj[D], dd = 0.0;
-    for (int m = 0; m < D; ++m) {
-      dNi[m] = s_dN[m][q][i];
-      dNj[m] = s_dN[m][q][j];
-      dd += dNi[m] * dNj[m];
-    }
+    const double Ni = s_N[q][i];
+    double dNi[D];
+    for (int m = 0; m < D; ++m) dNi[m] = s_dN[m][q][i];
     if (!G.solid) {
-      double gi[D], gj[D], gg = 0.0;
-      for (int c = 0; c < D; ++c) {
-        gi[c] = s_tf[c][q][i];
-        gj[c] = s_tf[c][q][j];
-        gg += gi[c] * gj[c];
-      }
-      const double visc = qs[2], kJ = qs[3];
-      const double diag = qs[1] * NNij + Ni * s_tf[D][q][j] + visc * gg;
-      K[0][0] += wq * dK * dd;
-      for (int b = 0; b < D; ++b) K[0][1 + b] += wq * kJ * Ni * gj[b];
-      for (int a = 0; a < D; ++a) {
-        K[1 + a][0] -= wq * kJ * Nj * gi[a];
-        for (int b = 0; b < D; ++b)
-          K[1 + a][1 + b] += wq * (NNij * qs[4 + D + a * D + b] + visc * gj[a] * gi[b] +
-                                   (a == b ? diag : 0.0));
+      double gi[D];
+      for (int c = 0; c < D; ++c) gi[c] = s_tf[c][q][i];
+      const double visc = qs[2], kJ = qs[3], cm = qs[1];
+      double R[D][D];
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) R[a][b] = qs[4 + D + a * D + b];
+      for (int jj = 0; jj < JT; ++jj) {
+        const int j = js[jj];
+        const double Nj = s_N[q][j], NNij = Ni * Nj;
+        double dd = 0.0, gg = 0.0, gj[D];
+        for (int m = 0; m < D; ++m) dd += dNi[m] * s_dN[m][q][j];
+        for (int c = 0; c < D; ++c) {
+          gj[c] = s_tf[c][q][j];
+          gg += gi[c] * gj[c];
+        }
+        const double diag = cm * NNij + Ni * s_tf[D][q][j] + visc * gg;
+        K[jj][0][0] += wq * dK * dd;
+        for (int b = 0; b < D; ++b) K[jj][0][1 + b] += wq * kJ * Ni * gj[b];
+        for (int a = 0; a < D; ++a) {
+          K[jj][1 + a][0] -= wq * kJ * Nj * gi[a];
+          for (int b = 0; b < D; ++b)
+            K[jj][1 + a][1 + b] += wq * (NNij * R[a][b] + visc * gj[a] * gi[b] + (a == b ? diag : 0.0));
+        }
       }
     } else {
-      double fi[D], fj[D], cS = 0.0;
-      for (int a = 0; a < D; ++a) {
-        fi[a] = s_tf[a][q][i];
-        fj[a] = s_tf[a][q][j];
-      }
+      double fi[D], Sd[D];
+      for (int a = 0; a < D; ++a) fi[a] = s_tf[a][q][i];
       for (int m = 0; m < D; ++m) {
         double s = 0.0;
         for (int n2 = 0; n2 < D; ++n2) s += qs[1 + m * D + n2] * dNi[n2];
-        cS += dNj[m] * s;
+        Sd[m] = s;  // (Sigma grad N_i)_m
       }
-      for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b)
-          K[1 + a][1 + b] += wq * (kt2 * (P.mu_s * (fj[a] * fi[b] + qs[1 + D * D + a * D + b] * dd) +
-                                          P.lambda_s * fj[b] * fi[a]) +
-                                   (a == b ? P.rho_s * NNij + kt2 * cS : 0.0));
+      for (int jj = 0; jj < JT; ++jj) {
+        const int j = js[jj];
+        const double NNij = Ni * s_N[q][j];
+        double fj[D], dd = 0.0, cS = 0.0;
+        for (int m = 0; m < D; ++m) {
+          const double dnj = s_dN[m][q][j];
+          dd += dNi[m] * dnj;
+          cS += dnj * Sd[m];
+          fj[m] = s_tf[m][q][j];
+        }
+        for (int a = 0; a < D; ++a)
+          for (int b = 0; b < D; ++b)
+            K[jj][1 + a][1 + b] += wq * (kt2 * (P.mu_s * (fj[a] * fi[b] + qs[1 + D * D + a * D + b] * dd) +
+                                                P.lambda_s * fj[b] * fi[a]) +
+                                         (a == b ? P.rho_s * NNij + kt2 * cS : 0.0));
+      }
     }
   }
-  const int64_t gr = local_node<D>(L, e, i), gc = local_node<D>(L, e, j);
-  const int64_t pos = find_block(L.rowptr, L.colind, gr, gc);
-  if (pos < 0) {
-    flag[1] = 1;
-    return;
-  }
-  double *blk = vals + pos * (B * B);
-  for (int a = 0; a < B; ++a) {
-    if (L.mask[gr * B + a]) continue;
-    for (int c = 0; c < B; ++c)
-      if (!L.mask[gc * B + c]) blk[a * B + c] += K[a][c];
+  const int64_t gr = local_node<D>(L, e, i);
+  for (int jj = 0; jj < JT; ++jj) {
+    if (!jok[jj]) continue;
+    const int64_t gc = local_node<D>(L, e, js[jj]);
+    const int64_t pos = find_block(L.rowptr, L.colind, gr, gc);
+    if (pos < 0) {
+      flag[1] = 1;
+      continue;
+    }
+    double *blk = vals + pos * (B * B);
+    for (int a = 0; a < B; ++a) {
+      if (L.mask[gr * B + a]) continue;
+      for (int c = 0; c < B; ++c)
+        if (!L.mask[gc * B + c]) blk[a * B + c] += K[jj][a][c];
+    }
   }
 }
 
@@ -639,9 +671,9 @@ void launch_asm_jacobian(const AsmLevel &L, int dim, const AsmPhys &P, const Asm
     if (ev) (void)hipEventRecord(ev[2 * c], s);
     if (ne > 0) {
       if (dim == 3)
-        hipLaunchKernelGGL(k_asm_jac<3>, dim3(ne), dim3(768), 0, s, L, P, S, vals, c, flag);
+        hipLaunchKernelGGL(k_asm_jac<3>, dim3(ne), dim3(jac_threads<3>()), 0, s, L, P, S, vals, c, flag);
       else
-        hipLaunchKernelGGL(k_asm_jac<2>, dim3(ne), dim3(128), 0, s, L, P, S, vals, c, flag);
+        hipLaunchKernelGGL(k_asm_jac<2>, dim3(ne), dim3(jac_threads<2>()), 0, s, L, P, S, vals, c, flag);
     }
     if (ev) (void)hipEventRecord(ev[2 * c + 1], s);
   }
