@@ -99,6 +99,25 @@ def _mv(A, x):
     return (A @ x[..., None])[..., 0]
 
 
+def element_subset(mesh, elems):
+    """A view of the mesh restricted to the cells `elems` (node numbering and
+    node count unchanged): residuals and Jacobians assembled over it are
+    complete in the rows of every node whose cells are all in `elems`."""
+    import copy
+    sub = copy.copy(mesh)
+    elems = np.asarray(elems)
+    sub.solid = mesh.solid[elems]
+    sub.nodes = mesh.nodes[elems]
+    sub.h = mesh.h[elems]
+    return sub
+
+
+def cells_of_nodes(mesh, nodes):
+    """The cells that contain any of the given nodes."""
+    hit = np.isin(mesh.nodes, np.asarray(nodes)).any(axis=1)
+    return np.nonzero(hit)[0]
+
+
 def _split(x, d):
     """momentum vector [n*(d+1)] (p, v per node) -> p [n], v [n, d]."""
     X = np.asarray(x).reshape(-1, d + 1)

@@ -246,3 +246,64 @@ def test_successive_time_steps_match_oracle(ctx, probs):
             assert np.abs(u.cpu().numpy() - ur).max() <= 1e-7 * np.abs(ur).max()
     finally:
         S.close()
+
+
+def test_c2_full_size_sampled_rows_match_oracle(ctx):
+    """3D 32^3 (the size and launch configuration `bench.py --newton` times,
+    mixed precision): residual rows and Jacobian rows (finest and first
+    coarse level) at sampled fluid, solid and interface nodes against the
+    oracle assembled over the cells around them; then one GPU Newton time
+    step, whose final state the oracle's own residual confirms at those rows."""
+    from oracle.fsi import cells_of_nodes, element_subset
+    P = config_problem("c2", seed=0)
+    d = P.dim
+    lev0 = P.levels[0]
+    rng = np.random.default_rng(12)
+    ns, nf = lev0.node_solid.astype(bool), lev0.node_fluid.astype(bool)
+    nodes = np.concatenate([rng.choice(np.nonzero(ns & ~nf)[0], 6, replace=False),
+                            rng.choice(np.nonzero(ns & nf)[0], 6, replace=False),
+                            rng.choice(np.nonzero(nf & ~ns)[0], 12, replace=False)])
+    S = Fsi(ctx, P, precision=fsimg.FSIMG_MIXED, rtol=1e-8)
+    try:
+        x, u, xo, uo = _perturbed(P, 4)
+        m0 = Mesh(lev0)
+        sub = element_subset(m0, cells_of_nodes(m0, nodes))
+        ref = newton_residual(sub, P.params, x, u, xo, uo, lev0.systems["mom"].dirichlet)
+        res = torch.empty(x.size, device=DEV, dtype=torch.float64)
+        fsimg.fsimg_fsi_residual(S.f, _t(x), _t(u), _t(xo), _t(uo), res)
+        rows = (nodes[:, None] * (d + 1) + np.arange(d + 1)).ravel()
+        got = res.cpu().numpy()[rows]
+        assert np.abs(got - ref[rows]).max() <= 1e-12 * np.abs(ref[rows]).max()
+        # Jacobian rows on levels 0 and 1
+        fsimg.fsimg_fsi_jacobian(S.f, _t(x), _t(u), _t(xo), _t(uo))
+        st = [x, u, xo, uo]
+        meshes = [m0, Mesh(P.levels[1])]
+        for l in (0, 1):
+            lv = P.levels[l]
+            if l == 1:
+                st = [inject(meshes[0], meshes[1], a, c) for a, c in zip(st, (d + 1, d, d + 1, d))]
+                nl = np.unique(rng.choice(lv.nnodes, 24, replace=False))
+            else:
+                nl = nodes
+            subl = element_subset(meshes[l], cells_of_nodes(meshes[l], nl))
+            A = lv.systems["mom"]
+            vals = jacobian_bsr(subl, P.params, *st, A.rowptr, A.colind, A.dirichlet)
+            J = to_csr(type("M", (), dict(rowptr=A.rowptr, colind=A.colind, vals=vals, b=d + 1)))
+            z = rng.standard_normal(J.shape[0])
+            y = torch.empty(z.size, device=DEV, dtype=torch.float64)
+            fsimg.fsimg_level_apply(S.mom, l, fsimg.FSIMG_FP64, _t(z), y)
+            torch.cuda.synchronize()
+            rl = (nl[:, None] * (d + 1) + np.arange(d + 1)).ravel()
+            yr = (J @ z)[rl]
+            assert np.abs(y.cpu().numpy()[rl] - yr).max() <= 1e-12 * np.abs(yr).max(), l
+        # one Newton time step from the seeded state
+        x0, u0, xo0, uo0 = fsi_state(P)
+        X, U = _t(x0), _t(u0)
+        stn = fsimg.fsimg_fsi_newton(S.f, X, U, _t(xo0), _t(uo0))
+        torch.cuda.synchronize()
+        assert stn["status"] == fsimg.FSIMG_OK
+        xf, uf = X.cpu().numpy(), U.cpu().numpy()
+        rf = newton_residual(sub, P.params, xf, uf, xo0, uo0, lev0.systems["mom"].dirichlet)
+        assert np.abs(rf[rows]).max() <= 1e-7 * stn["res0"]
+    finally:
+        S.close()

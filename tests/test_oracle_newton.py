@@ -216,3 +216,28 @@ def test_time_steps_from_the_previous_state_stay_bounded(prob_t2):
         np.testing.assert_allclose(u.reshape(n, d)[m.node_solid], cond[m.node_solid], atol=1e-12)
         vmax.append(np.abs(v).max())
     assert max(vmax) < 2.0 * vmax[0]
+
+
+def test_element_subset_rows_are_complete(prob_t2):
+    """Rows of sampled nodes assembled over only the cells that contain them
+    equal the full assembly's rows (the full-size GPU checks rely on it)."""
+    from oracle.fsi import cells_of_nodes, element_subset
+    P = prob_t2
+    m = Mesh(P.levels[0])
+    x, u, xo, uo = _state(P)
+    rng = np.random.default_rng(11)
+    nodes = rng.choice(m.nnodes, 12, replace=False)
+    sub = element_subset(m, cells_of_nodes(m, nodes))
+    d = m.dim
+    full = operator_value(m, P.params, x, u, xo, uo).reshape(-1, d + 1)
+    part = operator_value(sub, P.params, x, u, xo, uo).reshape(-1, d + 1)
+    np.testing.assert_array_equal(part[nodes], full[nodes])
+    A = P.levels[0].systems["mom"]
+    Jf = to_csr(type("M", (), dict(rowptr=A.rowptr, colind=A.colind, b=d + 1,
+                                   vals=jacobian_bsr(m, P.params, x, u, xo, uo, A.rowptr, A.colind,
+                                                     A.dirichlet))))
+    Js = to_csr(type("M", (), dict(rowptr=A.rowptr, colind=A.colind, b=d + 1,
+                                   vals=jacobian_bsr(sub, P.params, x, u, xo, uo, A.rowptr, A.colind,
+                                                     A.dirichlet))))
+    rows = (nodes[:, None] * (d + 1) + np.arange(d + 1)).ravel()
+    assert abs(Jf[rows] - Js[rows]).max() == 0.0
