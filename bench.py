@@ -257,12 +257,21 @@ def run_newton(args, P):
     x, u, xo, uo = (a.clone() for a in init)
     nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma)
 
+    count = [0]
+
     def time_step():
-        # one time step from the seeded state, Jacobian assembled afresh: every
-        # timed step does the same work
-        for dst, src in zip((x, u, xo, uo), init):
-            dst.copy_(src)
-        fsimg.fsimg_fsi_drop_jacobian(f)
+        if args.chain and count[0] > 0:
+            # t_{n-1} <- the last converged state, which is also the initial guess;
+            # the Jacobian is carried over
+            xo.copy_(x)
+            uo.copy_(u)
+        else:
+            # one time step from the seeded state, Jacobian assembled afresh: every
+            # timed step does the same work
+            for dst, src in zip((x, u, xo, uo), init):
+                dst.copy_(src)
+            fsimg.fsimg_fsi_drop_jacobian(f)
+        count[0] += 1
         st = fsimg.fsimg_fsi_newton(f, x, u, xo, uo, nopts, raise_on_noconv=False)
         log(f"newton time step: status {st['status']}, {st['steps']} steps, {st['jacobians']} "
             f"Jacobians, {st['halvings']} halvings, res {st['res0']:.3e} -> {st['res']:.3e}, "
@@ -310,9 +319,12 @@ def run_newton(args, P):
         "ms_per_step": t_ts * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if tag == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: one Newton time step (theta = {P.params['theta']}, "
-                               f"k = {P.params['k']}) from the seeded state, Jacobian assembled afresh, "
-                               f"gamma_nt = {args.gamma}, Newton rtol 1e-8 (max-norm), linear solves to 1e-8",
+        "config": {"workload": (f"{args.config}: " + (
+                       f"{args.warmup + args.steps} successive Newton time steps from the seeded state "
+                       f"(the last {args.steps} timed), Jacobian carried over" if args.chain else
+                       "one Newton time step from the seeded state, Jacobian assembled afresh") +
+                       f" (theta = {P.params['theta']}, k = {P.params['k']}), gamma_nt = {args.gamma}, "
+                       f"Newton rtol 1e-8 (max-norm), linear solves to 1e-8"),
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag},
         "roofline": {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -324,7 +336,10 @@ def run_newton(args, P):
         "residual_kernel": {"kernel": f"k_asm_res<{P.dim}>",
                             "avg_launch_ms": prof["res_ms"] / max(prof["res_launches"], 1),
                             "launches": prof["res_launches"]},
-        "newton": {"time_steps": args.steps, "newton_steps": tot("steps"),
+        "newton": {"per_step": [{k: st[k] for k in ("status", "steps", "jacobians", "halvings",
+                                                    "lin_iters_mom", "lin_iters_ale", "ms_total")}
+                                for st in stats],
+                   "time_steps": args.steps, "newton_steps": tot("steps"),
                    "jacobians": tot("jacobians"), "halvings": tot("halvings"),
                    "momentum_iters": tot("lin_iters_mom"), "ale_iters": tot("lin_iters_ale"),
                    "ms_residual": tot("ms_residual") / args.steps,
@@ -622,6 +637,9 @@ def main():
                     help="time steps of the GPU Newton loop (residual / Jacobian assembly, reuse, "
                          "line search) instead of one linear Newton-step solve")
     ap.add_argument("--gamma", type=float, default=0.05, help="Newton: Jacobian reuse threshold")
+    ap.add_argument("--chain", action="store_true",
+                    help="Newton: successive time steps (warm-up ones included), each from the last "
+                         "converged state with the Jacobian carried over")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="run one precision only (profiling runs)")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
