@@ -298,6 +298,9 @@ struct AsmLevel {
   const int32_t *rowptr, *colind;  // block pattern of the momentum matrix
   const uint8_t *mask;             // [nrows*(d+1)] identity rows of the momentum matrix
   int cells[3], nnode[3];
+  int structured;                  // 1: the pattern is exactly the full Q2 stencil (every node
+                                   // coupled with the nodes of its cells, lexicographic), so
+                                   // block positions follow from the node coordinates
 };
 // material and time-stepping parameters (eq. aletime:2)
 struct AsmPhys {
@@ -324,6 +327,8 @@ void launch_axpy_to(const double *x, const double *z, double omega, double *y, i
                     hipStream_t s);
 void launch_neg_free(double *y, const uint8_t *mask, int64_t n, hipStream_t s);
 void launch_absmax_u64(const double *x, int64_t n, unsigned long long *out, hipStream_t s);
+// *bad = 1 unless L's block pattern is exactly the full Q2 stencil of its mesh
+void launch_check_structured(const AsmLevel &L, int dim, int64_t nrows, int *bad, hipStream_t s);
 // r = u_old + k theta v + k (1 - theta) v_old - u at mask nodes, 0 elsewhere
 void launch_cond_residual(int64_t nnodes, int dim, const uint8_t *mask, double k, double theta,
                           const double *x, const double *xo, const double *u, const double *uo, double *r,

@@ -98,6 +98,39 @@ __device__ __forceinline__ int64_t find_block(const int32_t *rowptr, const int32
   return -1;
 }
 
+// the node range of row node g's stencil along one axis (n nodes): a
+// mid-cell node couples with its own cell only, a vertex with both neighbours
+__device__ __forceinline__ void stencil_range(int g, int n, int &lo, int &hi) {
+  if (g & 1) {
+    lo = g - 1;
+    hi = g + 1;
+  } else {
+    lo = g - 2 < 0 ? 0 : g - 2;
+    hi = g + 2 > n - 1 ? n - 1 : g + 2;
+  }
+}
+
+// position of block (row, col) in a full Q2 stencil pattern: the row's columns
+// are its stencil box, lexicographic with x fastest
+__device__ __forceinline__ int64_t stencil_block(const AsmLevel &L, int64_t row, int64_t col) {
+  int64_t off = 0, span = 1, r = row, c = col;
+  for (int a = 0; a < 3; ++a) {
+    const int n = L.nnode[a];
+    const int gr = (int)(r % n), gc = (int)(c % n);
+    r /= n;
+    c /= n;
+    int lo, hi;
+    stencil_range(gr, n, lo, hi);
+    off += span * (gc - lo);
+    span *= hi - lo + 1;
+  }
+  return L.rowptr[row] + off;
+}
+
+__device__ __forceinline__ int64_t block_position(const AsmLevel &L, int64_t row, int64_t col) {
+  return L.structured ? stencil_block(L, row, col) : find_block(L.rowptr, L.colind, row, col);
+}
+
 template <int D>
 struct ElemGeom {
   double h[D];
@@ -377,7 +410,7 @@ __global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhy
   for (int jj = 0; jj < JT; ++jj) {
     if (!jok[jj]) continue;
     const int64_t gc = local_node<D>(L, e, js[jj]);
-    const int64_t pos = find_block(L.rowptr, L.colind, gr, gc);
+    const int64_t pos = block_position(L, gr, gc);
     if (pos < 0) {
       flag[1] = 1;
       continue;
@@ -619,6 +652,35 @@ __global__ __launch_bounds__(256) void k_neg_free(double *__restrict__ y, const 
   if (i < n) y[i] = mask[i] ? 0.0 : -y[i];
 }
 
+// *bad = 1 unless every row's columns are exactly its Q2 stencil box
+__global__ __launch_bounds__(256) void k_check_structured(AsmLevel L, int64_t nrows, int *__restrict__ bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int lo[3], hi[3], g[3];
+  int64_t q = r;
+  for (int a = 0; a < 3; ++a) {
+    g[a] = (int)(q % L.nnode[a]);
+    q /= L.nnode[a];
+    stencil_range(g[a], L.nnode[a], lo[a], hi[a]);
+  }
+  const int64_t cnt = (int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+  const int64_t p0 = L.rowptr[r];
+  if (L.rowptr[r + 1] - p0 != cnt) {
+    bad[0] = 1;
+    return;
+  }
+  int64_t p = p0;
+  for (int z = lo[2]; z <= hi[2]; ++z)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int x = lo[0]; x <= hi[0]; ++x, ++p) {
+        const int64_t col = x + (int64_t)L.nnode[0] * (y + (int64_t)L.nnode[1] * z);
+        if (L.colind[p] != col) {
+          bad[0] = 1;
+          return;
+        }
+      }
+}
+
 // residual of the condensation relation (deformation rows, mass matrix
 // cancelled): r = u_old + k theta v + k (1 - theta) v_old - u at the nodes of
 // solid cells, 0 elsewhere; v, v_old from the (p, v) vectors x, x_old
@@ -719,6 +781,12 @@ void launch_cond_residual(int64_t nnodes, int dim, const uint8_t *mask, double k
   if (nnodes > 0)
     hipLaunchKernelGGL(k_cond_residual, dim3(grid_for(nnodes, 256)), dim3(256), 0, s, nnodes, dim, mask,
                        k * theta, k * (1.0 - theta), x, xo, u, uo, r);
+}
+
+void launch_check_structured(const AsmLevel &L, int dim, int64_t nrows, int *bad, hipStream_t s) {
+  (void)dim;
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_check_structured, dim3(grid_for(nrows, 256)), dim3(256), 0, s, L, nrows, bad);
 }
 
 void launch_absmax_u64(const double *x, int64_t n, unsigned long long *out, hipStream_t s) {

@@ -363,6 +363,17 @@ fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_
   if (hipHostMalloc((void **)&f->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&f->hnorm, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
     return bail(nfail(FSIMG_ERR_OOM, "pinned host memory"));
+  // levels whose pattern is exactly the Q2 stencil find block positions by
+  // arithmetic instead of a search in the row
+  for (size_t l = 0; l < mom->lev.size(); ++l) {
+    FsiLevel &F = f->lev[l];
+    if (hipMemsetAsync(f->dflag, 0, sizeof(int), nullptr) != hipSuccess)
+      return bail(nfail(FSIMG_ERR_HIP, "hipMemsetAsync failed"));
+    launch_check_structured(F.dev, d, mom->lev[l].nrows, f->dflag, nullptr);
+    if (hipMemcpy(f->hflag, f->dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(nfail(FSIMG_ERR_HIP, "pattern check failed"));
+    F.dev.structured = f->hflag[0] == 0 ? 1 : 0;
+  }
 #undef NW_CHK
   *out = f;
   return FSIMG_OK;

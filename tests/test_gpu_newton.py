@@ -307,3 +307,46 @@ def test_c2_full_size_sampled_rows_match_oracle(ctx):
         assert np.abs(rf[rows]).max() <= 1e-7 * stn["res0"]
     finally:
         S.close()
+
+
+def test_jacobian_on_a_general_block_pattern(ctx, probs):
+    """A finest-level pattern that is not exactly the Q2 stencil (one extra
+    block outside it) takes the search path for block positions: the result
+    still equals the oracle's, and the extra block stays zero."""
+    P = probs["t2"]
+    d, b = P.dim, P.dim + 1
+    levels = level_dicts(P, "mom")
+    L0 = dict(levels[0])
+    rp, ci, vals = L0["rowptr"], L0["colind"], L0["vals"]
+    far = P.levels[0].nnodes - 1
+    assert far not in ci[rp[0]:rp[1]]
+    L0["colind"] = np.insert(ci, rp[1], far).astype(np.int32)
+    L0["vals"] = np.insert(vals, rp[1], 0.0, axis=0)
+    L0["rowptr"] = np.concatenate([rp[:1], rp[1:] + 1]).astype(np.int32)
+    levels[0] = L0
+    o = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_FP64)
+    mom = fsimg.fsimg_hier_create(ctx, levels, o)
+    f = fsimg.fsimg_fsi_create(mom, None, fsi_levels(P), P.params)
+    try:
+        x, u, xo, uo = _perturbed(P, 5)
+        fsimg.fsimg_fsi_jacobian(f, _t(x), _t(u), _t(xo), _t(uo))
+        A = P.levels[0].systems["mom"]
+        ref_vals = jacobian_bsr(Mesh(P.levels[0]), P.params, x, u, xo, uo, L0["rowptr"], L0["colind"],
+                                A.dirichlet)
+        J = to_csr(type("M", (), dict(rowptr=L0["rowptr"], colind=L0["colind"], vals=ref_vals, b=b)))
+        rng = np.random.default_rng(6)
+        z = rng.standard_normal(J.shape[0])
+        y = torch.empty(z.size, device=DEV, dtype=torch.float64)
+        fsimg.fsimg_level_apply(mom, 0, fsimg.FSIMG_FP64, _t(z), y)
+        torch.cuda.synchronize()
+        ref = J @ z
+        assert np.abs(y.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+        # the extra block contributes nothing: a vector supported on the far node
+        z2 = np.zeros(J.shape[0])
+        z2[far * b:(far + 1) * b] = 1.0
+        fsimg.fsimg_level_apply(mom, 0, fsimg.FSIMG_FP64, _t(z2), y)
+        torch.cuda.synchronize()
+        assert np.all(y.cpu().numpy()[:b] == 0.0)
+    finally:
+        fsimg.fsimg_fsi_destroy(f)
+        fsimg.fsimg_hier_destroy(mom)
