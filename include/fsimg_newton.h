@@ -138,6 +138,38 @@ fsimg_status fsimg_fsi_set_profile(fsimg_fsi *f, int on);
 fsimg_status fsimg_fsi_profile(const fsimg_fsi *f, double *jac_ms, int *jac_launches, double *res_ms,
                                int *res_launches);
 
+/* A serving request that runs real Newton time steps (instead of the
+   synthetic states and right-hand sides of fsimg_request): the server creates
+   its momentum and ALE hierarchies and its Newton object at admission, and
+   every server step advances each running Newton request by one Newton step
+   of fsimg_fsi_newton, with the momentum and ALE solves of all of them
+   batched (fsimg_solve_batch).  A time step ends when its residual meets the
+   tolerance; the next starts from the converged state with the Jacobian
+   carried over.  Each request's result is bitwise the one fsimg_fsi_newton
+   gives it alone, time step after time step.  Host arrays are read at
+   admission; the caller keeps them valid until the request completes. */
+typedef struct {
+  int nlev;                         /* levels of both systems */
+  const fsimg_level_desc *mom;      /* momentum levels, finest first */
+  const fsimg_level_desc *ale;      /* ALE levels, finest first */
+  const fsimg_fsi_level *geom;      /* [nlev] geometry of the momentum levels */
+  fsimg_phys phys;
+  const double *x, *u;              /* initial state (host, finest level) */
+  const double *x_old, *u_old;      /* the state at t_{n-1} of the first time step */
+  int time_steps;
+  fsimg_newton_opts newton;
+  double arrival;                   /* arrival time on the server clock (s) */
+} fsimg_newton_request;
+
+fsimg_status fsimg_server_submit_newton(fsimg_server *srv, const fsimg_newton_request *req,
+                                        int64_t *id);
+/* Newton statistics of a Newton request summed over its finished time steps
+   (steps, Jacobians, halvings, linear iterations, times; res0 / res /
+   res_hist of the last one).  fsimg_server_result returns its state: x as the
+   momentum vector, u as the ALE vector.  ERR_ARG for an unknown id or a
+   request of the other kind. */
+fsimg_status fsimg_server_newton_stats(fsimg_server *srv, int64_t id, fsimg_newton_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,52 +11,15 @@
 #include <string>
 #include <vector>
 
-#include "fsimg_newton.h"
-#include "hier.h"
+#include "fsi.h"
 
 using namespace fsimg;
 
 namespace {
 
-struct FsiLevel {
-  AsmLevel dev{};          // device view (pattern and mask borrowed from the hierarchy)
-  double *coord[3] = {nullptr, nullptr, nullptr};
-  uint8_t *solid = nullptr;
-  // the state injected to this level (coarse levels only)
-  double *x = nullptr, *u = nullptr, *xo = nullptr, *uo = nullptr;
-};
-
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
-
-}  // namespace
-
-struct fsimg_fsi {
-  fsimg_hier *mom = nullptr, *ale = nullptr;
-  fsimg_phys phys{};
-  int dim = 0;
-  std::vector<FsiLevel> lev;
-  std::vector<std::pair<void *, size_t>> allocs;
-  uint8_t *node_solid = nullptr;     // [nrows] fine nodes of a solid cell
-  // finest-level work vectors
-  double *res = nullptr, *W = nullptr, *xt = nullptr;           // [n_mom]
-  double *du = nullptr, *b5 = nullptr, *ut = nullptr;           // [n_ale]
-  double *ru = nullptr;  // [nrows*d] residual of the condensation relation (eq. problem:2)
-  int *dflag = nullptr;                                          // [2] assembly flags
-  unsigned long long *dnorm = nullptr;                           // max-norm slot
-  int *hflag = nullptr;                                          // pinned host mirror
-  unsigned long long *hnorm = nullptr;
-  bool have_jac = false;
-  // profiling: events around the finest level's element launches (one pair
-  // per parity colour) and the accumulated times
-  bool profile = false;
-  hipEvent_t ev_jac[16] = {}, ev_res[16] = {};
-  double jac_ms = 0.0, res_ms = 0.0;
-  int jac_launches = 0, res_launches = 0;
-};
-
-namespace {
 
 fsimg_status nfail(fsimg_status s, const std::string &m) { return set_error(s, m); }
 
@@ -418,100 +381,166 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
     return nfail(FSIMG_ERR_ARG, "bad Newton options");
   NW_HIP(hipSetDevice(f->mom->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  fsimg_newton_stats st;
-  std::memset(&st, 0, sizeof st);
-  const auto t_start = std::chrono::steady_clock::now();
-  const DevLevel &Lm = f->mom->lev[0];
-  const DevLevel &La = f->ale->lev[0];
-  const int d = f->dim;
-  auto finish = [&](fsimg_status status) {
-    st.status = status;
-    st.ms_total = ms_since(t_start);
-    if (stats) *stats = st;
-    return status;
-  };
-  // the ALE matrix never changes: factor it once
-  if (!f->ale->factored) {
-    const fsimg_status fs = fsimg_factor(f->ale, s);
-    if (fs != FSIMG_OK) return finish(fs);
-  }
-
-  double nrm = 0.0;
-  auto t0 = std::chrono::steady_clock::now();
-  fsimg_status rs = eval_residual(f, x, u, x_old, u_old, s, &nrm, true);
-  st.ms_residual += ms_since(t0);
-  if (rs != FSIMG_OK) return finish(rs);
-  const double nrm0 = nrm;
-  st.res0 = nrm0;
-  st.res_hist[0] = nrm;
-  double rate = -1.0;  // no rate before the first step
-  fsimg_status status = FSIMG_ERR_NOCONV;
-  for (int l = 0;; ++l) {
-    if (nrm <= std::max(o.rtol * nrm0, o.atol)) {
-      status = FSIMG_OK;
-      break;
-    }
-    if (l >= o.max_steps) break;
-    if (!f->have_jac || rate > o.gamma) {
-      t0 = std::chrono::steady_clock::now();
-      fsimg_status js = assemble_jacobian(f, x, u, x_old, u_old, s);
-      st.ms_jacobian += ms_since(t0);
-      if (js != FSIMG_OK) return finish(js);
-      t0 = std::chrono::steady_clock::now();
-      js = fsimg_factor(f->mom, s);
-      NW_HIP(hipStreamSynchronize(s));
-      st.ms_factor += ms_since(t0);
-      if (js != FSIMG_OK) return finish(js);
-      f->have_jac = true;
-      ++st.jacobians;
-    }
+  NewtonRun &R = f->run;
+  newton_begin(f, x, u, x_old, u_old, o, s);
+  while (!R.done) {
+    newton_prepare(f, s);
+    if (R.done) break;
     // momentum: J W = R (eq. problem:1)
-    t0 = std::chrono::steady_clock::now();
-    launch_fill<double>(f->W, Lm.n, 0.0, s);
+    auto t0 = std::chrono::steady_clock::now();
     fsimg_stats ls;
     fsimg_status ss = fsimg_solve(f->mom, f->res, f->W, &ls, s);
-    st.lin_iters_mom += ls.iters;
+    R.st.lin_iters_mom += ls.iters;
     if (ss != FSIMG_OK) {
-      st.ms_solve += ms_since(t0);
-      return finish(ss);
+      R.st.ms_solve += ms_since(t0);
+      newton_fail(f, ss);
+      break;
     }
-    // interface / solid deformation increment (eq. problem:2 with its
-    // right-hand side): the condensation residual plus k theta W_v; it is the
-    // initial guess and the identity-row data of the ALE solve (eq. problem:3)
-    launch_deform(Lm.nrows, d, f->node_solid, f->phys.k, f->phys.theta, f->W, d + 1, 1, f->ru,
-                  nullptr, f->du, s);
-    NW_HIP(hipGetLastError());
+    newton_lift(f, s);
+    // ALE extension (eq. problem:3)
     ss = fsimg_solve(f->ale, f->b5, f->du, &ls, s);
-    st.lin_iters_ale += ls.iters;
-    st.ms_solve += ms_since(t0);
-    if (ss != FSIMG_OK) return finish(ss);
-    // line search: a trial state with an inverted element (det F <= 0) counts
-    // as no decrease
-    double omega = 1.0, nt = 0.0;
-    for (int hv = 0;; ++hv) {
-      launch_axpy_to(x, f->W, omega, f->xt, Lm.n, s);
-      launch_axpy_to(u, f->du, omega, f->ut, La.n, s);
-      t0 = std::chrono::steady_clock::now();
-      rs = eval_residual(f, f->xt, f->ut, x_old, u_old, s, &nt, true);
-      st.ms_residual += ms_since(t0);
-      const bool inverted = rs == FSIMG_ERR_SINGULAR;
-      if (rs != FSIMG_OK && !inverted) return finish(rs);
-      if (inverted && hv >= o.max_halvings) return finish(rs);
-      if (!inverted && (nt < nrm || hv >= o.max_halvings)) break;
-      omega *= 0.5;
-      ++st.halvings;
+    R.st.lin_iters_ale += ls.iters;
+    R.st.ms_solve += ms_since(t0);
+    if (ss != FSIMG_OK) {
+      newton_fail(f, ss);
+      break;
     }
-    NW_HIP(hipMemcpyAsync(x, f->xt, Lm.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    NW_HIP(hipMemcpyAsync(u, f->ut, La.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (l < 32) st.omega_hist[l] = omega;
-    rate = nt / nrm;
-    nrm = nt;
-    ++st.steps;
-    if (st.steps < 32) st.res_hist[st.steps] = nrm;
+    newton_finish_step(f, s);
   }
-  NW_HIP(hipStreamSynchronize(s));
-  st.res = nrm;
-  return finish(status);
+  const fsimg_newton_stats st = newton_end(f, s);
+  if (stats) *stats = st;
+  return static_cast<fsimg_status>(st.status);
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ Newton stages
+namespace fsimg {
+
+void newton_fail(fsimg_fsi *f, fsimg_status status) {
+  f->run.done = true;
+  f->run.status = status;
+}
+
+void newton_begin(fsimg_fsi *f, double *x, double *u, const double *xo, const double *uo,
+                  const fsimg_newton_opts &o, hipStream_t s) {
+  NewtonRun &R = f->run;
+  R = NewtonRun{};
+  R.o = o;
+  R.x = x;
+  R.u = u;
+  R.xo = xo;
+  R.uo = uo;
+  R.done = false;
+  R.status = FSIMG_OK;
+  std::memset(&R.st, 0, sizeof R.st);
+  R.t_start = std::chrono::steady_clock::now();
+  // the ALE matrix never changes: factor it once
+  if (!f->ale->factored) {
+    const fsimg_status fs = fsimg_factor(f->ale, s);
+    if (fs != FSIMG_OK) return newton_fail(f, fs);
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const fsimg_status rs = eval_residual(f, x, u, xo, uo, s, &R.nrm, true);
+  R.st.ms_residual += ms_since(t0);
+  if (rs != FSIMG_OK) return newton_fail(f, rs);
+  R.nrm0 = R.nrm;
+  R.st.res0 = R.nrm;
+  R.st.res_hist[0] = R.nrm;
+  R.rate = -1.0;
+  if (R.nrm <= std::max(o.rtol * R.nrm0, o.atol)) R.done = true;
+}
+
+void newton_prepare(fsimg_fsi *f, hipStream_t s) {
+  NewtonRun &R = f->run;
+  if (R.done) return;
+  if (R.st.steps >= R.o.max_steps)
+    return newton_fail(f, nfail(FSIMG_ERR_NOCONV, "the Newton loop reached max_steps"));
+  if (!f->have_jac || R.rate > R.o.gamma) {
+    auto t0 = std::chrono::steady_clock::now();
+    fsimg_status js = assemble_jacobian(f, R.x, R.u, R.xo, R.uo, s);
+    R.st.ms_jacobian += ms_since(t0);
+    if (js != FSIMG_OK) return newton_fail(f, js);
+    t0 = std::chrono::steady_clock::now();
+    f->have_jac = false;
+    js = fsimg_factor(f->mom, s);
+    if (js == FSIMG_OK && hipStreamSynchronize(s) != hipSuccess)
+      js = nfail(FSIMG_ERR_HIP, "synchronisation after the factorisation failed");
+    R.st.ms_factor += ms_since(t0);
+    if (js != FSIMG_OK) return newton_fail(f, js);
+    f->have_jac = true;
+    ++R.st.jacobians;
+  }
+  launch_fill<double>(f->W, f->mom->lev[0].n, 0.0, s);
+}
+
+void newton_lift(fsimg_fsi *f, hipStream_t s) {
+  // interface / solid deformation increment (eq. problem:2 with its
+  // right-hand side): the condensation residual plus k theta W_v
+  const DevLevel &Lm = f->mom->lev[0];
+  launch_deform(Lm.nrows, f->dim, f->node_solid, f->phys.k, f->phys.theta, f->W, f->dim + 1, 1, f->ru,
+                nullptr, f->du, s);
+}
+
+void newton_finish_step(fsimg_fsi *f, hipStream_t s) {
+  NewtonRun &R = f->run;
+  if (R.done) return;
+  const DevLevel &Lm = f->mom->lev[0];
+  const DevLevel &La = f->ale->lev[0];
+  // line search: a trial state with an inverted element (det F <= 0) counts
+  // as no decrease
+  double omega = 1.0, nt = 0.0;
+  for (int hv = 0;; ++hv) {
+    launch_axpy_to(R.x, f->W, omega, f->xt, Lm.n, s);
+    launch_axpy_to(R.u, f->du, omega, f->ut, La.n, s);
+    const auto t0 = std::chrono::steady_clock::now();
+    const fsimg_status rs = eval_residual(f, f->xt, f->ut, R.xo, R.uo, s, &nt, true);
+    R.st.ms_residual += ms_since(t0);
+    const bool inverted = rs == FSIMG_ERR_SINGULAR;
+    if (rs != FSIMG_OK && !inverted) return newton_fail(f, rs);
+    if (inverted && hv >= R.o.max_halvings) return newton_fail(f, rs);
+    if (!inverted && (nt < R.nrm || hv >= R.o.max_halvings)) break;
+    omega *= 0.5;
+    ++R.st.halvings;
+  }
+  if (hipMemcpyAsync(R.x, f->xt, Lm.n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(R.u, f->ut, La.n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return newton_fail(f, nfail(FSIMG_ERR_HIP, "state update failed"));
+  if (R.st.steps < 32) R.st.omega_hist[R.st.steps] = omega;
+  R.rate = nt / R.nrm;
+  R.nrm = nt;
+  ++R.st.steps;
+  if (R.st.steps < 32) R.st.res_hist[R.st.steps] = R.nrm;
+  if (R.nrm <= std::max(R.o.rtol * R.nrm0, R.o.atol)) R.done = true;
+}
+
+fsimg_newton_stats newton_end(fsimg_fsi *f, hipStream_t s) {
+  NewtonRun &R = f->run;
+  if (hipStreamSynchronize(s) != hipSuccess && R.status == FSIMG_OK)
+    R.status = nfail(FSIMG_ERR_HIP, "synchronisation at the end of the time step failed");
+  R.st.res = R.nrm;
+  R.st.status = R.status;
+  R.st.ms_total = ms_since(R.t_start);
+  R.done = true;
+  return R.st;
+}
+
+size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale) {
+  size_t b = 0;
+  const int d = mom[0].dim;
+  for (int l = 0; l < nlev; ++l) {
+    int64_t ncell = 1;
+    for (int a = 0; a < d; ++a) {
+      b += (size_t)(2 * mom[l].cells[a] + 1) * sizeof(double);
+      ncell *= mom[l].cells[a];
+    }
+    b += (size_t)ncell;
+    if (l > 0) b += (size_t)mom[l].nrows * (2 * (d + 1) + 2 * d) * sizeof(double);
+  }
+  const int64_t n = mom[0].nrows;
+  b += (size_t)n + 3 * (size_t)n * (d + 1) * sizeof(double);
+  if (with_ale) b += 4 * (size_t)n * d * sizeof(double);
+  return b + 2 * sizeof(int) + sizeof(unsigned long long);
+}
+
+}  // namespace fsimg

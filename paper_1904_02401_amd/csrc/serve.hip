@@ -6,11 +6,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <vector>
 
-#include "hier.h"
+#include "fsi.h"
 
 using namespace fsimg;
 
@@ -35,6 +36,12 @@ struct Req {
   int64_t nnodes = 0, nm = 0, na = 0;
   double admitted = -1.0, finished = -1.0;
   std::vector<double> xm_host, xa_host;
+  // Newton requests: x_mom holds the state x, x_ale the state u
+  bool nt = false;
+  fsimg_newton_request nreq{};
+  fsimg_fsi *fsi = nullptr;
+  double *xo = nullptr, *uo = nullptr;
+  fsimg_newton_stats acc{};
 };
 
 }  // namespace
@@ -59,6 +66,11 @@ double now_s(const fsimg_server *s) {
 }
 
 void release_device(fsimg_server *S, Req *q) {
+  if (q->fsi) fsimg_fsi_destroy(q->fsi);
+  q->fsi = nullptr;
+  for (void *p : {(void *)q->xo, (void *)q->uo})
+    if (p) (void)hipFree(p);
+  q->xo = q->uo = nullptr;
   if (q->hm) fsimg_hier_destroy(q->hm);
   if (q->ha) fsimg_hier_destroy(q->ha);
   q->hm = q->ha = nullptr;
@@ -86,12 +98,58 @@ size_t request_bytes(const fsimg_server *S, const Req *q, fsimg_status *st) {
   size_t fm = 0, fa = 0;
   *st = fsimg_hier_footprint(q->r.mom, q->r.nlev, &S->opts, &fm);
   if (*st == FSIMG_OK) *st = fsimg_hier_footprint(q->r.ale, q->r.nlev, &S->opts, &fa);
+  if (q->nt)
+    return fm + fa + fsi_bytes(q->r.mom, q->r.nlev, true) + (size_t)(2 * q->nm + 2 * q->na) * 8 +
+           plan_reserve();
   return fm + fa + (size_t)((q->rhs.size() + 1) * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes +
          plan_reserve();
 }
 
+// a Newton request: hierarchies, Newton object, state vectors, first residual
+fsimg_status admit_newton(fsimg_server *S, Req *q, hipStream_t s) {
+  const fsimg_newton_request &N = q->nreq;
+  fsimg_status st = fsimg_hier_create(S->ctx, N.mom, N.nlev, &S->opts, s, &q->hm);
+  if (st == FSIMG_OK) st = fsimg_hier_create(S->ctx, N.ale, N.nlev, &S->opts, s, &q->ha);
+  if (st == FSIMG_OK) st = fsimg_fsi_create(q->hm, q->ha, N.geom, &N.phys, &q->fsi);
+  if (st != FSIMG_OK) {
+    release_device(S, q);
+    return st;
+  }
+  const size_t bytes = (size_t)(2 * q->nm + 2 * q->na) * 8;
+  if (S->ctx->budget && S->ctx->in_use + bytes > S->ctx->budget) {
+    release_device(S, q);
+    return set_error(FSIMG_ERR_BUDGET, "request vectors exceed the budget");
+  }
+  bool ok = hipMalloc(&q->x_mom, q->nm * 8) == hipSuccess && hipMalloc(&q->xo, q->nm * 8) == hipSuccess &&
+            hipMalloc(&q->x_ale, q->na * 8) == hipSuccess && hipMalloc(&q->uo, q->na * 8) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    release_device(S, q);
+    return set_error(FSIMG_ERR_OOM, "request vector allocation failed");
+  }
+  q->vec_bytes = bytes;
+  S->ctx->in_use += bytes;
+  q->reserve = plan_reserve();
+  S->reserved += q->reserve;
+  ok = hipMemcpyAsync(q->x_mom, N.x, q->nm * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipMemcpyAsync(q->xo, N.x_old, q->nm * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipMemcpyAsync(q->x_ale, N.u, q->na * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipMemcpyAsync(q->uo, N.u_old, q->na * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+       hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    release_device(S, q);
+    return set_error(FSIMG_ERR_HIP, "request upload failed");
+  }
+  std::memset(&q->acc, 0, sizeof q->acc);
+  newton_begin(q->fsi, q->x_mom, q->x_ale, q->xo, q->uo, N.newton, s);
+  q->state = 1;
+  q->admitted = now_s(S);
+  return FSIMG_OK;
+}
+
 // create hierarchies, factor, upload vectors; false if it does not fit now
 fsimg_status admit(fsimg_server *S, Req *q, hipStream_t s) {
+  if (q->nt) return admit_newton(S, q, s);
   fsimg_status st = fsimg_hier_create(S->ctx, q->r.mom, q->r.nlev, &S->opts, s, &q->hm);
   if (st == FSIMG_OK) st = fsimg_hier_create(S->ctx, q->r.ale, q->r.nlev, &S->opts, s, &q->ha);
   if (st == FSIMG_OK) st = fsimg_factor(q->hm, s);
@@ -146,6 +204,114 @@ void finish(fsimg_server *S, Req *q, hipStream_t s) {
   q->state = 2;
   release_device(S, q);
   S->finished_unpolled.push_back(q);
+}
+
+// a Newton request whose time step has ended: add its statistics, then
+// finish it (error or last time step) or start the next time step from the
+// converged state; repeated while a new time step meets the tolerance at once
+void advance_newton(fsimg_server *S, Req *q, hipStream_t s) {
+  while (q->state == 1 && q->fsi->run.done) {
+    const fsimg_newton_stats st = newton_end(q->fsi, s);
+    fsimg_newton_stats &a = q->acc;
+    a.steps += st.steps;
+    a.jacobians += st.jacobians;
+    a.halvings += st.halvings;
+    a.lin_iters_mom += st.lin_iters_mom;
+    a.lin_iters_ale += st.lin_iters_ale;
+    a.ms_total += st.ms_total;
+    a.ms_residual += st.ms_residual;
+    a.ms_jacobian += st.ms_jacobian;
+    a.ms_factor += st.ms_factor;
+    a.ms_solve += st.ms_solve;
+    a.res0 = st.res0;
+    a.res = st.res;
+    std::memcpy(a.res_hist, st.res_hist, sizeof a.res_hist);
+    std::memcpy(a.omega_hist, st.omega_hist, sizeof a.omega_hist);
+    a.status = st.status;
+    if (st.status != FSIMG_OK) {
+      q->status = st.status;
+      finish(S, q, s);
+      return;
+    }
+    if (++q->t == q->nreq.time_steps) {
+      finish(S, q, s);
+      return;
+    }
+    // t_{n-1} <- the converged state, which is also the next initial guess
+    if (hipMemcpyAsync(q->xo, q->x_mom, q->nm * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(q->uo, q->x_ale, q->na * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      q->status = set_error(FSIMG_ERR_HIP, "state copy failed");
+      finish(S, q, s);
+      return;
+    }
+    newton_begin(q->fsi, q->x_mom, q->x_ale, q->xo, q->uo, q->nreq.newton, s);
+  }
+}
+
+// one Newton step of every running Newton request of one dimension, the
+// linear solves batched
+fsimg_status newton_group_step(fsimg_server *S, int dim, hipStream_t s) {
+  std::vector<Req *> group;
+  for (Req *q : S->running)
+    if (q->nt && q->dim == dim && q->state == 1) {
+      advance_newton(S, q, s);
+      if (q->state != 1) continue;
+      newton_prepare(q->fsi, s);
+      if (q->fsi->run.done) {
+        advance_newton(S, q, s);
+        continue;
+      }
+      group.push_back(q);
+    }
+  if (group.empty()) return FSIMG_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<fsimg_hier *> hs;
+  std::vector<const double *> bs;
+  std::vector<double *> xs;
+  for (Req *q : group) {
+    hs.push_back(q->hm);
+    bs.push_back(q->fsi->res);
+    xs.push_back(q->fsi->W);
+  }
+  std::vector<fsimg_stats> st(group.size());
+  fsimg_status r1 = solve_batch(S->ctx, (int)group.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
+  if (r1 != FSIMG_OK && r1 != FSIMG_ERR_NOCONV && r1 != FSIMG_ERR_NONFINITE) return r1;
+  std::vector<Req *> alive;
+  for (size_t g = 0; g < group.size(); ++g) {
+    Req *q = group[g];
+    q->fsi->run.st.lin_iters_mom += st[g].iters;
+    if (st[g].status != FSIMG_OK) {
+      newton_fail(q->fsi, (fsimg_status)st[g].status);
+      continue;
+    }
+    newton_lift(q->fsi, s);
+    alive.push_back(q);
+  }
+  hs.clear();
+  bs.clear();
+  xs.clear();
+  for (Req *q : alive) {
+    hs.push_back(q->ha);
+    bs.push_back(q->fsi->b5);
+    xs.push_back(q->fsi->du);
+  }
+  if (!alive.empty()) {
+    st.assign(alive.size(), fsimg_stats{});
+    fsimg_status r2 = solve_batch(S->ctx, (int)alive.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
+    if (r2 != FSIMG_OK && r2 != FSIMG_ERR_NOCONV && r2 != FSIMG_ERR_NONFINITE) return r2;
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (size_t g = 0; g < alive.size(); ++g) {
+    Req *q = alive[g];
+    q->fsi->run.st.lin_iters_ale += st[g].iters;
+    if (st[g].status != FSIMG_OK) newton_fail(q->fsi, (fsimg_status)st[g].status);
+  }
+  for (Req *q : group) {
+    q->fsi->run.st.ms_solve += ms;
+    newton_finish_step(q->fsi, s);
+    advance_newton(S, q, s);
+  }
+  return FSIMG_OK;
 }
 
 }  // namespace
@@ -226,6 +392,47 @@ fsimg_status fsimg_server_submit(fsimg_server *S, const fsimg_request *r, int64_
   return FSIMG_OK;
 }
 
+fsimg_status fsimg_server_submit_newton(fsimg_server *S, const fsimg_newton_request *r, int64_t *id) {
+  if (!S || !r || !r->mom || !r->ale || !r->geom || !r->x || !r->u || !r->x_old || !r->u_old ||
+      r->time_steps < 1 || r->nlev < 1)
+    return set_error(FSIMG_ERR_ARG, "incomplete Newton request");
+  const fsimg_level_desc &m0 = r->mom[0], &a0 = r->ale[0];
+  if (m0.dim < 2 || m0.dim != a0.dim || m0.block != m0.dim + 1 || a0.block != a0.dim ||
+      m0.nrows != a0.nrows)
+    return set_error(FSIMG_ERR_ARG, "request systems must be momentum (b = d+1) and ALE (b = d) "
+                                    "on the same mesh");
+  const fsimg_newton_opts &o = r->newton;
+  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0))
+    return set_error(FSIMG_ERR_ARG, "bad Newton options");
+  auto *q = new Req;
+  q->id = S->next_id++;
+  q->nt = true;
+  q->nreq = *r;
+  q->r.nlev = r->nlev;
+  q->r.mom = r->mom;
+  q->r.ale = r->ale;
+  q->r.arrival = r->arrival;
+  q->r.time_steps = r->time_steps;
+  q->dim = m0.dim;
+  q->bm = m0.block;
+  q->ba = a0.block;
+  q->nnodes = m0.nrows;
+  q->nm = m0.nrows * m0.block;
+  q->na = a0.nrows * a0.block;
+  S->queue.push_back(q);
+  S->all[q->id] = q;
+  if (id) *id = q->id;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_server_newton_stats(fsimg_server *S, int64_t id, fsimg_newton_stats *out) {
+  if (!S || !out) return set_error(FSIMG_ERR_ARG, "null argument");
+  auto it = S->all.find(id);
+  if (it == S->all.end() || !it->second->nt) return set_error(FSIMG_ERR_ARG, "no Newton request with this id");
+  *out = it->second->acc;
+  return FSIMG_OK;
+}
+
 fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, void *stream) {
   if (!S) return set_error(FSIMG_ERR_ARG, "null server");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -269,14 +476,26 @@ fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, vo
     }
   }
   if (!S->running.empty()) {
-    // one Newton step of every running request: batched per system and dimension
+    // Newton requests: one Newton step each, linear solves batched per dimension
+    for (int dim = 2; dim <= 3; ++dim) {
+      const fsimg_status r = newton_group_step(S, dim, s);
+      if (r != FSIMG_OK) return r;
+    }
+    {  // those that finished leave the running list
+      std::vector<Req *> still;
+      for (Req *q : S->running)
+        if (q->state == 1) still.push_back(q);
+      S->running.swap(still);
+    }
+    // one Newton step of every running synthetic request: batched per system
+    // and dimension
     for (int dim = 2; dim <= 3; ++dim) {
       std::vector<fsimg_hier *> hs;
       std::vector<const double *> bs;
       std::vector<double *> xs;
       std::vector<Req *> group;
       for (Req *q : S->running)
-        if (q->dim == dim) group.push_back(q);
+        if (q->dim == dim && !q->nt) group.push_back(q);
       if (group.empty()) continue;
       for (Req *q : group) {
         launch_fill<double>(q->x_mom, q->nm, 0.0, s);
@@ -306,6 +525,10 @@ fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, vo
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(FSIMG_ERR_HIP, "server step sync failed");
     std::vector<Req *> still;
     for (Req *q : S->running) {
+      if (q->nt) {
+        still.push_back(q);
+        continue;
+      }
       ++q->newton_done;
       if (++q->nstep == q->newton[q->t]) {
         q->nstep = 0;

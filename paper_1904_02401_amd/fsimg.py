@@ -112,6 +112,13 @@ class fsimg_newton_stats(ctypes.Structure):
         return d
 
 
+class fsimg_newton_request(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int), ("mom", ctypes.c_void_p), ("ale", ctypes.c_void_p),
+                ("geom", ctypes.c_void_p), ("phys", fsimg_phys), ("x", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("x_old", ctypes.c_void_p), ("u_old", ctypes.c_void_p),
+                ("time_steps", ctypes.c_int), ("newton", fsimg_newton_opts), ("arrival", ctypes.c_double)]
+
+
 # entry point -> argument types
 _P, _I, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
@@ -166,6 +173,8 @@ _SIGS = {
     "fsimg_fsi_newton": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(fsimg_newton_opts),
                               ctypes.POINTER(fsimg_newton_stats), _P]),
     "fsimg_fsi_drop_jacobian": (_I, [_P]),
+    "fsimg_server_submit_newton": (_I, [_P, ctypes.POINTER(fsimg_newton_request), ctypes.POINTER(_I64)]),
+    "fsimg_server_newton_stats": (_I, [_P, _I64, ctypes.POINTER(fsimg_newton_stats)]),
     "fsimg_fsi_set_profile": (_I, [_P, _I]),
     "fsimg_fsi_profile": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_D),
                                ctypes.POINTER(_I)]),
@@ -568,3 +577,48 @@ def fsimg_fsi_profile(f) -> dict:
     _check(load().fsimg_fsi_profile(f, ctypes.byref(jm), ctypes.byref(jn), ctypes.byref(rm),
                                     ctypes.byref(rn)))
     return dict(jac_ms=jm.value, jac_launches=jn.value, res_ms=rm.value, res_launches=rn.value)
+
+
+class NewtonRequestData:
+    """Host data of one Newton serving request: momentum / ALE level
+    descriptors, the momentum levels' geometry (coordinates per axis,
+    cell_solid), material parameters and the initial state (x, u) with its
+    t_{n-1} state.  The arrays must stay alive until the request completes."""
+
+    def __init__(self, mom_levels, ale_levels, geometry, params, x, u, x_old, u_old):
+        self.mom = LevelDescs(mom_levels)
+        self.ale = LevelDescs(ale_levels)
+        self.nlev = self.mom.n
+        self._keep = []
+        self.geom = (fsimg_fsi_level * self.nlev)()
+        for l, (coords, solid) in enumerate(geometry):
+            cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coords]
+            sd = np.ascontiguousarray(solid, dtype=np.uint8)
+            self._keep += cs + [sd]
+            for a in range(3):
+                self.geom[l].coords[a] = cs[a].ctypes.data if a < len(cs) else None
+            self.geom[l].cell_solid = sd.ctypes.data
+        self.phys = fsimg_phys_of(params)
+        self.vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, u, x_old, u_old)]
+
+
+def fsimg_server_submit_newton(srv, data: NewtonRequestData, time_steps: int, opts=None,
+                               arrival: float = 0.0) -> int:
+    o = opts if opts is not None else fsimg_default_newton_opts()
+    x, u, xo, uo = data.vecs
+    req = fsimg_newton_request(nlev=data.nlev, mom=ctypes.cast(data.mom.arr, ctypes.c_void_p),
+                               ale=ctypes.cast(data.ale.arr, ctypes.c_void_p),
+                               geom=ctypes.cast(data.geom, ctypes.c_void_p), phys=data.phys,
+                               x=x.ctypes.data, u=u.ctypes.data, x_old=xo.ctypes.data,
+                               u_old=uo.ctypes.data, time_steps=int(time_steps), newton=o,
+                               arrival=float(arrival))
+    rid = ctypes.c_int64()
+    _check(load().fsimg_server_submit_newton(srv, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def fsimg_server_newton_stats(srv, rid: int) -> dict:
+    st = fsimg_newton_stats()
+    _check(load().fsimg_server_newton_stats(srv, rid, ctypes.byref(st)))
+    d = {n: getattr(st, n) for n, _ in st._fields_ if n not in ("res_hist", "omega_hist")}
+    return d

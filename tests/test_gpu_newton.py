@@ -350,3 +350,54 @@ def test_jacobian_on_a_general_block_pattern(ctx, probs):
     finally:
         fsimg.fsimg_fsi_destroy(f)
         fsimg.fsimg_hier_destroy(mom)
+
+
+def test_served_newton_requests_equal_solo_runs(ctx, probs):
+    """Three Newton requests (2D and 3D, different seeds) served together for
+    two time steps each, their momentum and ALE solves batched: every final
+    state is bitwise the one fsimg_fsi_newton gives the request alone over
+    the same two time steps, with the same Newton and Jacobian counts."""
+    Ps = [probs["t2"], config_problem("t2", seed=1), probs["t3"]]
+    opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
+    nopts = fsimg.fsimg_default_newton_opts()
+    solo = []
+    for P in Ps:
+        mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), opts)
+        ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), opts)
+        f = fsimg.fsimg_fsi_create(mom, ale, fsi_levels(P), P.params)
+        try:
+            x, u, xo, uo = (_t(a) for a in fsi_state(P))
+            sts = []
+            for t in range(2):
+                if t:
+                    xo.copy_(x)
+                    uo.copy_(u)
+                sts.append(fsimg.fsimg_fsi_newton(f, x, u, xo, uo, nopts))
+            torch.cuda.synchronize()
+            solo.append((x.cpu().numpy(), u.cpu().numpy(), sts))
+        finally:
+            fsimg.fsimg_fsi_destroy(f)
+            fsimg.fsimg_hier_destroy(mom)
+            fsimg.fsimg_hier_destroy(ale)
+    srv = fsimg.fsimg_server_create(ctx, opts)
+    try:
+        datas = [fsimg.NewtonRequestData(level_dicts(P, "mom"), level_dicts(P, "ale"), fsi_levels(P),
+                                         P.params, *fsi_state(P)) for P in Ps]
+        ids = [fsimg.fsimg_server_submit_newton(srv, dd, 2, nopts) for dd in datas]
+        for _ in range(200):
+            active, queued = fsimg.fsimg_server_step(srv)
+            if active == 0 and queued == 0:
+                break
+        assert active == 0 and queued == 0
+        for P, rid, (xs, us, sts) in zip(Ps, ids, solo):
+            assert fsimg.fsimg_server_request_status(srv, rid) == fsimg.FSIMG_OK
+            n = P.levels[0].nnodes
+            xm, xa = fsimg.fsimg_server_result(srv, rid, n * (P.dim + 1), n * P.dim)
+            np.testing.assert_array_equal(xm, xs)
+            np.testing.assert_array_equal(xa, us)
+            acc = fsimg.fsimg_server_newton_stats(srv, rid)
+            assert acc["steps"] == sum(s["steps"] for s in sts)
+            assert acc["jacobians"] == sum(s["jacobians"] for s in sts)
+            assert acc["lin_iters_mom"] == sum(s["lin_iters_mom"] for s in sts)
+    finally:
+        fsimg.fsimg_server_destroy(srv)
