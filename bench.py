@@ -481,9 +481,15 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
         arrivals.append((t, d, sz, ns))
     ctx = fsimg.fsimg_ctx_create(0, int(args.budget_gb * (1 << 30)))
     opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
+    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma, max_steps=args.max_newton)
     srv = fsimg.fsimg_server_create(ctx, opts, args.max_active)
+
+    def submit(server, key, ns, arrival):
+        if args.newton:
+            return fsimg.fsimg_server_submit_newton(server, pool[key][0], args.time_steps, nopts, arrival)
+        return fsimg.fsimg_server_submit(server, pool[key][0], ns, arrival)
     stream = torch.cuda.current_stream()
-    meta, lat, qdelay, done_ids, work, failed = {}, [], [], [], 0.0, []
+    meta, lat, qdelay, done_ids, work, failed, newton_steps = {}, [], [], [], 0.0, [], []
     nxt, steps, max_active_seen = 0, 0, 0
     start = fsimg.fsimg_server_clock(srv)
     last_log = 0.0
@@ -492,7 +498,7 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
         while nxt < len(arrivals) and arrivals[nxt][0] <= now:
             ta, d, sz, ns = arrivals[nxt]
             data, nm, na = pool[(d, sz)]
-            rid = fsimg.fsimg_server_submit(srv, data, ns, start + ta)
+            rid = submit(srv, (d, sz), ns, start + ta)
             meta[rid] = (start + ta, d, sz, nm, na, int(ns.sum()), ns)
             nxt += 1
         active, queued = fsimg.fsimg_server_step(srv, stream)
@@ -504,6 +510,9 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
                 lat.append(f - arr)
                 qdelay.append(a - arr)
                 done_ids.append(int(rid))
+                if args.newton:  # Newton steps actually taken over the request's time steps
+                    nsteps = fsimg.fsimg_server_newton_stats(srv, int(rid))["steps"]
+                    newton_steps.append(nsteps)
                 work += nsteps * (nm + na)
             else:
                 st = fsimg.fsimg_server_request_status(srv, abs(int(rid)))
@@ -529,7 +538,7 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
         arr, d, sz, nm, na, nsteps, ns = meta[rid]
         xm_mix, xa_mix = fsimg.fsimg_server_result(srv, rid, nm, na)
         srv2 = fsimg.fsimg_server_create(ctx, opts)
-        rid2 = fsimg.fsimg_server_submit(srv2, pool[(d, sz)][0], ns, fsimg.fsimg_server_clock(srv2))
+        rid2 = submit(srv2, (d, sz), ns, fsimg.fsimg_server_clock(srv2))
         while True:
             act, q = fsimg.fsimg_server_step(srv2, stream)
             if act == 0 and q == 0:
@@ -550,12 +559,14 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
             "latency_p99_s": float(np.percentile(lat_a, 99)),
             "queue_delay_p50_s": float(np.percentile(q_a, 50)),
             "queue_delay_p99_s": float(np.percentile(q_a, 99)),
-            "alone_equals_mix": same, "failed": failed}
+            "alone_equals_mix": same, "failed": failed,
+            "newton_steps_per_request": (float(np.mean(newton_steps)) if newton_steps else None)}
 
 
 def run_serving(args):
     """Serving workload: Poisson arrivals of FSI simulations (10 time steps of
-    3..5 Newton steps; 70 % 2D 64^2..256^2, 30 % 3D 16^3..48^3), hierarchies
+    3..5 Newton steps, or with --newton --time-steps real Newton time steps
+    on the GPU; 70 % 2D 64^2..256^2, 30 % 3D 16^3..48^3), hierarchies
     resident in HBM, first-fit admission by footprint, continuous batching,
     mixed precision.  Latency = arrival -> last solve of the simulation.
     --rates runs a sweep of arrival rates on the same request pool."""
@@ -578,6 +589,17 @@ def run_serving(args):
 
     pool = {}
     for d, sz in [(2, n) for n in sizes2] + [(3, n) for n in sizes3]:
+        if args.newton:
+            from fsigen import serve_instance
+            from paper_1904_02401_amd import fsimg
+            from paper_1904_02401_amd.problems import fsi_levels, fsi_state, level_dicts
+            P = serve_instance(d, sz, seed=sz)
+            pool[(d, sz)] = (fsimg.NewtonRequestData(level_dicts(P, "mom"), level_dicts(P, "ale"),
+                                                     fsi_levels(P), P.params, *fsi_state(P)),
+                             P.levels[0].systems["mom"].nrows * (d + 1),
+                             P.levels[0].systems["ale"].nrows * d)
+            log(f"  pool: {d}D {sz}^{d}, {len(P.levels)} levels, Newton request")
+            continue
         P, states, rhs = serve_request(d, sz, seed=sz, n_states=args.n_states, n_rhs=args.n_rhs)
         if args.n_states > 1:
             for prob in [P] + states:
@@ -600,12 +622,18 @@ def run_serving(args):
         "warmup": 0, "ms_per_step": main["wall_s"] / max(main["server_steps"], 1) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": ("serving: Poisson arrivals of FSI simulations, 10 time steps x 3..5 "
-                                "Newton steps (momentum + deformation + ALE solves to 1e-8; a new "
-                                "Jacobian state uploaded and refactored every time step, a new "
-                                "right-hand side every Newton step), 70% 2D "
-                                f"64^2..256^2, 30% 3D 16^3..{max(sizes3)}^3, mixed precision, resident "
-                                "hierarchies, first-fit admission by HBM footprint, continuous batching"),
+        "config": {"workload": (
+            ("serving: Poisson arrivals of FSI simulations, " + (
+                f"{args.time_steps} Newton time steps each on the GPU (residual and Jacobian "
+                f"assembly, reuse with gamma_nt = {args.gamma}, line search; Newton tolerance 1e-8, "
+                f"at most {args.max_newton} Newton steps per time step, "
+                "momentum + deformation + ALE solves to 1e-8, batched across requests), "
+                if args.newton else
+                "10 time steps x 3..5 Newton steps (momentum + deformation + ALE solves to 1e-8; a new "
+                "Jacobian state uploaded and refactored every time step, a new right-hand side every "
+                "Newton step), ") +
+            f"70% 2D 64^2..256^2, 30% 3D 16^3..{max(sizes3)}^3, mixed precision, resident "
+            "hierarchies, first-fit admission by HBM footprint, continuous batching")),
                    "window_s": args.window, "budget_GiB": args.budget_gb,
                    "max_active": args.max_active, "states_cycled": args.n_states,
                    "rhs_cycled": args.n_rhs, **main},
@@ -637,6 +665,10 @@ def main():
                     help="time steps of the GPU Newton loop (residual / Jacobian assembly, reuse, "
                          "line search) instead of one linear Newton-step solve")
     ap.add_argument("--gamma", type=float, default=0.05, help="Newton: Jacobian reuse threshold")
+    ap.add_argument("--time-steps", type=int, default=1,
+                    help="serving with --newton: Newton time steps per request")
+    ap.add_argument("--max-newton", type=int, default=50,
+                    help="serving with --newton: Newton steps per time step at most")
     ap.add_argument("--chain", action="store_true",
                     help="Newton: successive time steps (warm-up ones included), each from the last "
                          "converged state with the Jacobian carried over")
