@@ -351,7 +351,35 @@ def run_newton(args, P):
     fsimg.fsimg_hier_destroy(mom)
     fsimg.fsimg_hier_destroy(ale)
     fsimg.fsimg_ctx_destroy(ctx)
+    # GPU assembly rate of the finest level (elements / s), the oracle's beside it
+    out["assembly_elements_per_s"] = lev.ncells / (jac_pass_ms * 1e-3)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_assembly_baseline(P)
     print(json.dumps(out), flush=True)
+
+
+def cpu_assembly_baseline(P, n_elems=1024):
+    """The oracle's element assembly on the host: residual and complex-step
+    Jacobian over a seeded sample of the finest level's cells, in elements
+    per second (the oracle cannot run the whole time step at this size: its
+    linear solves are direct)."""
+    import numpy as np
+    from oracle.fsi import Mesh, element_jacobians, element_subset, operator_value
+    from paper_1904_02401_amd.problems import fsi_state
+    lev = P.levels[0]
+    m = Mesh(lev)
+    rng = np.random.default_rng(0)
+    sub = element_subset(m, np.sort(rng.choice(lev.ncells, n_elems, replace=False)))
+    x, u, xo, uo = fsi_state(P)
+    t0, c0 = time.perf_counter(), time.process_time()
+    operator_value(sub, P.params, x, u, xo, uo)
+    element_jacobians(sub, P.params, x, u, xo, uo)
+    dt = time.perf_counter() - t0
+    cores = round((time.process_time() - c0) / dt, 1)
+    return {"value": n_elems / dt, "unit": "elements/s (residual + Jacobian)", "cores": cores,
+            "kind": "oracle",
+            "sample": f"residual and complex-step Jacobian of {n_elems} seeded cells of the finest "
+                      f"level ({dt:.1f} s); GPU: the same per cell in assembly_elements_per_s"}
 
 
 def cpu_baseline(P, iters_gpu, budget_s=20.0):
