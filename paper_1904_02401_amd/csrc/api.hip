@@ -655,6 +655,7 @@ void fsimg_hier_destroy(fsimg_hier *h) {
       }
     }
   }
+  if (h->side) (void)hipStreamSynchronize(h->side);
   for (auto &a : h->allocs) {
     (void)hipFree(a.first);
     h->ctx->in_use -= a.second;
@@ -667,6 +668,9 @@ void fsimg_hier_destroy(fsimg_hier *h) {
         g = nullptr;
       }
   if (h->ilu_cap) (void)hipStreamDestroy(h->ilu_cap);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->hpin) (void)hipHostFree(h->hpin);
   if (h->hstatus) (void)hipHostFree(h->hstatus);
   delete h;
@@ -982,109 +986,138 @@ fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } ev_guard{ev};
-  for (int l = 0; l + 1 < nlev; ++l) {
-    DevLevel &L = h->lev[l];
-    L.factor_ms = 0.0;
-    if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
-      const int64_t nv = L.nnzb * L.b * L.b;
-      const int init[2] = {0, INT_MAX};
-      FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
-      FSIMG_HIP(hipMemcpyAsync(L.ilu64, L.vals64, nv * 8, hipMemcpyDeviceToDevice, s));
-      if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
-      launch_ilu_factor(L, h->dstatus, s);
-      FSIMG_HIP(hipGetLastError());
-      if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
-      if (mixed) {
-        launch_cast_d2f(L.ilu64, L.ilu32, nv, s);
-        launch_cast_d2f(L.dinv64, L.dinv32, L.nrows * L.b * L.b, s);
-      }
-      FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-      FSIMG_HIP(hipStreamSynchronize(s));
-      if (prof) {
-        float ms = 0.0f;
-        FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        L.factor_ms = ms;
-      }
-      if (h->hstatus[0])
-        return fail(FSIMG_ERR_SINGULAR, "singular diagonal block in the ILU factors of level " +
-                                            std::to_string(l) + ": block row " +
-                                            std::to_string(h->hstatus[1]));
-      continue;
-    }
-    for (int g = 0; g < 2; ++g) {  // element patches, then block patches
-      const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
-      if (np_ == 0) continue;
-      const int init[2] = {0, INT_MAX};
-      FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
-      if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
-      if (g == 0) {
-        if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
-        else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
-      } else {
-        if (mixed) launch_patch_factor_blocks<float>(L, L.blk.inv32, L.blk.npc32, h->dstatus, s);
-        else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, s);
-      }
-      FSIMG_HIP(hipGetLastError());
-      if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
-      FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-      FSIMG_HIP(hipStreamSynchronize(s));
-      if (prof) {
-        float ms = 0.0f;
-        FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        L.factor_ms += ms;
-      }
-      if (h->hstatus[0]) {
-        const int64_t p = h->hstatus[1];
-        return fail(FSIMG_ERR_SINGULAR,
-                    std::string("singular ") + (g == 0 ? "patch" : "block patch") +
-                        " matrix on level " + std::to_string(l) + ": patch " + std::to_string(p) +
-                        (g == 0 ? " (cell " + std::to_string(p >= 0 && p < L.npatch ? L.pelem[p] : -1) +
-                                      ")"
-                                : std::string()));
-      }
-    }
-  }
-  // coarsest level: dense Gauss-Jordan inverse in FP64
+  // coarsest level: dense Gauss-Jordan inverse in FP64 on the side stream,
+  // concurrently with the patch factorisations of the finer levels (it needs
+  // only the coarsest matrix and its own workspace and status slots 8, 9).
+  // The dense matrix and its largest entry (the pivot threshold) are taken
+  // first on the caller's stream; the chain of Gauss-Jordan launches is
+  // enqueued on the side stream right after the first patch kernel has been
+  // launched, so that the host enqueues it while that kernel runs.
   DevLevel &C = h->lev.back();
   const int64_t n = C.nfree;
-  if (n == 0) {
-    h->factored = true;
-    return FSIMG_OK;
-  }
-  double *a = C.gj_a, *rowk = C.gj_rowk, *colk = C.gj_colk, *part = C.gj_part;
-  int *piv = C.gj_piv, *colmap = C.gj_colmap;
-  fsimg_status st = FSIMG_OK;
-  do {
-    launch_fill<double>(a, n * n, 0.0, s);
-    launch_densify(C, a, s);
-    launch_absmax(a, n * n, part, s);
+  bool coarse = false;
+  double amax = 0.0;
+  if (n > 0) {
+    if (!h->side) FSIMG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    if (!h->ev_fork) FSIMG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    if (!h->ev_join) FSIMG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    launch_fill<double>(C.gj_a, n * n, 0.0, s);
+    launch_densify(C, C.gj_a, s);
+    launch_absmax(C.gj_a, n * n, C.gj_part, s);
     std::vector<double> hp(kRedBlocks);
-    if (hipMemcpyAsync(hp.data(), part, kRedBlocks * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) { st = fail(FSIMG_ERR_HIP, "coarse absmax copy"); break; }
-    double amax = 0.0;
+    if (hipMemcpyAsync(hp.data(), C.gj_part, kRedBlocks * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(FSIMG_ERR_HIP, "coarse absmax copy");
     for (double v : hp) amax = std::max(amax, v);
-    const int init[2] = {0, INT_MAX};
-    if (hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) {
-      st = fail(FSIMG_ERR_HIP, "status init");
-      break;
-    }
-    if (!launch_coarse_gj_blocked(n, a, piv, colmap, colk, rowk, 1e-15 * amax, h->dstatus, C.cinv,
-                                  s)) {
+    FSIMG_HIP(hipEventRecord(h->ev_fork, s));
+  }
+  auto start_coarse = [&]() -> fsimg_status {
+    if (n == 0 || coarse) return FSIMG_OK;
+    hipStream_t c = h->side;
+    double *a = C.gj_a, *rowk = C.gj_rowk, *colk = C.gj_colk;
+    int *piv = C.gj_piv, *colmap = C.gj_colmap;
+    FSIMG_HIP(hipStreamWaitEvent(c, h->ev_fork, 0));
+    h->hstatus[10] = 0;
+    h->hstatus[11] = INT_MAX;
+    FSIMG_HIP(hipMemcpyAsync(h->dstatus + 8, h->hstatus + 10, 2 * sizeof(int), hipMemcpyHostToDevice, c));
+    coarse = true;  // from here on the side stream has work to join
+    if (!launch_coarse_gj_blocked(n, a, piv, colmap, colk, rowk, 1e-15 * amax, h->dstatus + 8, C.cinv,
+                                  c)) {
       // beyond the blocked kernel's size: one pivot and one update launch per column
       for (int64_t k = 0; k < n; ++k) {
-        launch_gj_pivot(n, k, a, piv, rowk, colk, 1e-15 * amax, h->dstatus, s);
-        launch_gj_update(n, k, a, rowk, colk, s);
+        launch_gj_pivot(n, k, a, piv, rowk, colk, 1e-15 * amax, h->dstatus + 8, c);
+        launch_gj_update(n, k, a, rowk, colk, c);
       }
-      launch_gj_finish(n, a, piv, colmap, C.cinv, s);
+      launch_gj_finish(n, a, piv, colmap, C.cinv, c);
     }
-    if (hipGetLastError() != hipSuccess) { st = fail(FSIMG_ERR_HIP, "coarse factor launch"); break; }
-    if (hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) { st = fail(FSIMG_ERR_HIP, "coarse status copy"); break; }
-    if (h->hstatus[0])
-      st = fail(FSIMG_ERR_SINGULAR, "singular coarse matrix (level " + std::to_string(nlev - 1) +
-                                        ", pivot column " + std::to_string(h->hstatus[1]) + ")");
-  } while (0);
-  if (st != FSIMG_OK) return st;
+    FSIMG_HIP(hipGetLastError());
+    FSIMG_HIP(hipMemcpyAsync(h->hstatus + 8, h->dstatus + 8, 2 * sizeof(int), hipMemcpyDeviceToHost, c));
+    FSIMG_HIP(hipEventRecord(h->ev_join, c));
+    return FSIMG_OK;
+  };
+  auto patches = [&]() -> fsimg_status {
+    for (int l = 0; l + 1 < nlev; ++l) {
+      DevLevel &L = h->lev[l];
+      L.factor_ms = 0.0;
+      if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
+        const int64_t nv = L.nnzb * L.b * L.b;
+        const int init[2] = {0, INT_MAX};
+        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
+        FSIMG_HIP(hipMemcpyAsync(L.ilu64, L.vals64, nv * 8, hipMemcpyDeviceToDevice, s));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
+        launch_ilu_factor(L, h->dstatus, s);
+        FSIMG_HIP(hipGetLastError());
+        FSIMG_TRY(start_coarse());
+        if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
+        if (mixed) {
+          launch_cast_d2f(L.ilu64, L.ilu32, nv, s);
+          launch_cast_d2f(L.dinv64, L.dinv32, L.nrows * L.b * L.b, s);
+        }
+        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        FSIMG_HIP(hipStreamSynchronize(s));
+        if (prof) {
+          float ms = 0.0f;
+          FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          L.factor_ms = ms;
+        }
+        if (h->hstatus[0])
+          return fail(FSIMG_ERR_SINGULAR, "singular diagonal block in the ILU factors of level " +
+                                              std::to_string(l) + ": block row " +
+                                              std::to_string(h->hstatus[1]));
+        continue;
+      }
+      for (int g = 0; g < 2; ++g) {  // element patches, then block patches
+        const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
+        if (np_ == 0) continue;
+        const int init[2] = {0, INT_MAX};
+        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
+        if (g == 0) {
+          if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
+          else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
+        } else {
+          if (mixed) launch_patch_factor_blocks<float>(L, L.blk.inv32, L.blk.npc32, h->dstatus, s);
+          else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, s);
+        }
+        FSIMG_HIP(hipGetLastError());
+        FSIMG_TRY(start_coarse());
+        if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
+        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        FSIMG_HIP(hipStreamSynchronize(s));
+        if (prof) {
+          float ms = 0.0f;
+          FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          L.factor_ms += ms;
+        }
+        if (h->hstatus[0]) {
+          const int64_t p = h->hstatus[1];
+          return fail(FSIMG_ERR_SINGULAR,
+                      std::string("singular ") + (g == 0 ? "patch" : "block patch") +
+                          " matrix on level " + std::to_string(l) + ": patch " + std::to_string(p) +
+                          (g == 0 ? " (cell " + std::to_string(p >= 0 && p < L.npatch ? L.pelem[p] : -1) +
+                                        ")"
+                                  : std::string()));
+        }
+      }
+    }
+    return FSIMG_OK;
+  };
+  fsimg_status pst = patches();
+  if (pst == FSIMG_OK) pst = start_coarse();  // no patch kernel ran
+  if (coarse) {  // join: the caller's stream waits for the coarse inverse
+    if (pst != FSIMG_OK) {  // nothing of the side stream may outlive a failed call
+      (void)hipStreamSynchronize(h->side);
+      return pst;
+    }
+    if (hipEventSynchronize(h->ev_join) != hipSuccess || hipStreamWaitEvent(s, h->ev_join, 0) != hipSuccess) {
+      (void)hipStreamSynchronize(h->side);
+      return fail(FSIMG_ERR_HIP, "coarse factor join");
+    }
+  }
+  if (pst != FSIMG_OK) return pst;
+  if (coarse && h->hstatus[8])
+    return fail(FSIMG_ERR_SINGULAR, "singular coarse matrix (level " + std::to_string(nlev - 1) +
+                                        ", pivot column " + std::to_string(h->hstatus[9]) + ")");
   h->factored = true;
   return FSIMG_OK;
 }

@@ -73,6 +73,10 @@ struct fsimg_hier {
   EventTimer tv, ts;
   bool profiling = false;
   hipStream_t ilu_cap = nullptr;  // capture stream of the ILU sweep graphs
+  // the coarse inverse runs on this stream while the patch factorisations of
+  // the finer levels run on the caller's (fork / join events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 
