@@ -44,22 +44,29 @@ def build(verbose: bool = False) -> str:
 
 
 CABI_DRIVER = os.path.join(ROOT, "tests", "_cabi_driver")
+CABI_NEWTON = os.path.join(ROOT, "tests", "_cabi_newton")
 
 
 def build_cabi_driver() -> str:
-    """The plain-C test client of the ABI (tests/cabi_driver.c), linked
-    against libfsimg.so and the HIP runtime with gcc."""
+    """The plain-C test clients of the ABI (tests/cabi_driver.c: a solve;
+    tests/cabi_newton.c: a Newton time step), linked against libfsimg.so and
+    the HIP runtime with gcc.  Returns the solve client's path."""
+    _build_client("cabi_newton.c", CABI_NEWTON)
+    return _build_client("cabi_driver.c", CABI_DRIVER)
+
+
+def _build_client(src: str, out: str) -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__",
            "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
-           os.path.join(ROOT, "tests", "cabi_driver.c"), "-o", CABI_DRIVER,
+           os.path.join(ROOT, "tests", src), "-o", out,
            "-L", HERE, "-lfsimg", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
            "-Wl,-rpath," + HERE, "-Wl,-rpath,$ORIGIN/../paper_1904_02401_amd",
            "-Wl,-rpath," + os.path.join(rocm, "lib")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"gcc failed for the C client:\n{r.stdout}\n{r.stderr}")
-    return CABI_DRIVER
+        raise RuntimeError(f"gcc failed for the C client {src}:\n{r.stdout}\n{r.stderr}")
+    return out
 
 
 if __name__ == "__main__":
