@@ -255,7 +255,7 @@ def run_newton(args, P):
     dev = torch.device("cuda:0")
     init = [torch.tensor(a, device=dev) for a in fsi_state(P)]
     x, u, xo, uo = (a.clone() for a in init)
-    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma)
+    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma, lin_rtol=args.lin_rtol, atol=args.newton_atol)
 
     count = [0]
 
@@ -324,7 +324,8 @@ def run_newton(args, P):
                        f"(the last {args.steps} timed), Jacobian carried over" if args.chain else
                        "one Newton time step from the seeded state, Jacobian assembled afresh") +
                        f" (theta = {P.params['theta']}, k = {P.params['k']}), gamma_nt = {args.gamma}, "
-                       f"Newton rtol 1e-8 (max-norm), linear solves to 1e-8"),
+                       f"Newton stop at 1e-8 relative or {args.newton_atol:g} absolute (max-norm), "
+                       f"momentum solves to {args.lin_rtol:g} relative, ALE solves to 1e-8"),
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag},
         "roofline": {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -509,7 +510,8 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
         arrivals.append((t, d, sz, ns))
     ctx = fsimg.fsimg_ctx_create(0, int(args.budget_gb * (1 << 30)))
     opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
-    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma, max_steps=args.max_newton)
+    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma, max_steps=args.max_newton,
+                                            lin_rtol=args.lin_rtol, atol=args.newton_atol)
     srv = fsimg.fsimg_server_create(ctx, opts, args.max_active)
 
     def submit(server, key, ns, arrival):
@@ -653,9 +655,10 @@ def run_serving(args):
         "config": {"workload": (
             ("serving: Poisson arrivals of FSI simulations, " + (
                 f"{args.time_steps} Newton time steps each on the GPU (residual and Jacobian "
-                f"assembly, reuse with gamma_nt = {args.gamma}, line search; Newton tolerance 1e-8, "
-                f"at most {args.max_newton} Newton steps per time step, "
-                "momentum + deformation + ALE solves to 1e-8, batched across requests), "
+                f"assembly, reuse with gamma_nt = {args.gamma}, line search; Newton stop at 1e-8 "
+                f"relative or {args.newton_atol:g} absolute, at most {args.max_newton} Newton steps per "
+                f"time step, momentum solves to {args.lin_rtol:g}, ALE solves to 1e-8, batched across "
+                "requests), "
                 if args.newton else
                 "10 time steps x 3..5 Newton steps (momentum + deformation + ALE solves to 1e-8; a new "
                 "Jacobian state uploaded and refactored every time step, a new right-hand side every "
@@ -693,6 +696,10 @@ def main():
                     help="time steps of the GPU Newton loop (residual / Jacobian assembly, reuse, "
                          "line search) instead of one linear Newton-step solve")
     ap.add_argument("--gamma", type=float, default=0.05, help="Newton: Jacobian reuse threshold")
+    ap.add_argument("--lin-rtol", type=float, default=1e-4,
+                    help="Newton: relative tolerance of each momentum solve (the paper: 1e-4)")
+    ap.add_argument("--newton-atol", type=float, default=1e-8,
+                    help="Newton: absolute max-norm stop (the paper: 1e-8, besides the relative 1e-8)")
     ap.add_argument("--time-steps", type=int, default=1,
                     help="serving with --newton: Newton time steps per request")
     ap.add_argument("--max-newton", type=int, default=50,

@@ -89,6 +89,9 @@ typedef struct {
   double gamma;      /* reassemble the Jacobian when the rate rho_l > gamma (default 0.05) */
   int max_halvings;  /* line search: halve omega while the residual does not decrease, at
                         most this often (default 4) */
+  double lin_rtol;   /* relative tolerance of each momentum solve inside the loop (Sec. 5.5
+                        reduces the error by 1e-4 per Newton step); 0 (default): the momentum
+                        hierarchy's own rtol.  The ALE solves keep the ALE hierarchy's rtol. */
 } fsimg_newton_opts;
 
 typedef struct {

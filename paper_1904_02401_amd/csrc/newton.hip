@@ -165,6 +165,7 @@ void fsimg_default_newton_opts(fsimg_newton_opts *o) {
   o->max_steps = 20;
   o->gamma = 0.05;
   o->max_halvings = 4;
+  o->lin_rtol = 0.0;
 }
 
 void fsimg_fsi_destroy(fsimg_fsi *f) {
@@ -377,7 +378,8 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
   fsimg_newton_opts o;
   fsimg_default_newton_opts(&o);
   if (opts) o = *opts;
-  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0))
+  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
+      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0))
     return nfail(FSIMG_ERR_ARG, "bad Newton options");
   NW_HIP(hipSetDevice(f->mom->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -389,7 +391,10 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
     // momentum: J W = R (eq. problem:1)
     auto t0 = std::chrono::steady_clock::now();
     fsimg_stats ls;
+    const double keep = f->mom->opts.rtol;
+    if (o.lin_rtol > 0.0) f->mom->opts.rtol = o.lin_rtol;
     fsimg_status ss = fsimg_solve(f->mom, f->res, f->W, &ls, s);
+    f->mom->opts.rtol = keep;
     R.st.lin_iters_mom += ls.iters;
     if (ss != FSIMG_OK) {
       R.st.ms_solve += ms_since(t0);

@@ -268,24 +268,45 @@ fsimg_status newton_group_step(fsimg_server *S, int dim, hipStream_t s) {
   std::vector<fsimg_hier *> hs;
   std::vector<const double *> bs;
   std::vector<double *> xs;
-  for (Req *q : group) {
-    hs.push_back(q->hm);
-    bs.push_back(q->fsi->res);
-    xs.push_back(q->fsi->W);
-  }
-  std::vector<fsimg_stats> st(group.size());
-  fsimg_status r1 = solve_batch(S->ctx, (int)group.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
-  if (r1 != FSIMG_OK && r1 != FSIMG_ERR_NOCONV && r1 != FSIMG_ERR_NONFINITE) return r1;
+  std::vector<fsimg_stats> st;
   std::vector<Req *> alive;
-  for (size_t g = 0; g < group.size(); ++g) {
-    Req *q = group[g];
-    q->fsi->run.st.lin_iters_mom += st[g].iters;
-    if (st[g].status != FSIMG_OK) {
-      newton_fail(q->fsi, (fsimg_status)st[g].status);
-      continue;
+  // momentum solves, batched per tolerance (the Newton option lin_rtol, else the
+  // hierarchy's own rtol)
+  std::vector<Req *> pending = group;
+  while (!pending.empty()) {
+    const double tol = pending[0]->nreq.newton.lin_rtol > 0.0 ? pending[0]->nreq.newton.lin_rtol
+                                                             : pending[0]->hm->opts.rtol;
+    std::vector<Req *> part, rest;
+    for (Req *q : pending) {
+      const double t = q->nreq.newton.lin_rtol > 0.0 ? q->nreq.newton.lin_rtol : q->hm->opts.rtol;
+      (t == tol ? part : rest).push_back(q);
     }
-    newton_lift(q->fsi, s);
-    alive.push_back(q);
+    hs.clear();
+    bs.clear();
+    xs.clear();
+    std::vector<double> keep;
+    for (Req *q : part) {
+      keep.push_back(q->hm->opts.rtol);
+      q->hm->opts.rtol = tol;
+      hs.push_back(q->hm);
+      bs.push_back(q->fsi->res);
+      xs.push_back(q->fsi->W);
+    }
+    st.assign(part.size(), fsimg_stats{});
+    fsimg_status r1 = solve_batch(S->ctx, (int)part.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
+    for (size_t g = 0; g < part.size(); ++g) part[g]->hm->opts.rtol = keep[g];
+    if (r1 != FSIMG_OK && r1 != FSIMG_ERR_NOCONV && r1 != FSIMG_ERR_NONFINITE) return r1;
+    for (size_t g = 0; g < part.size(); ++g) {
+      Req *q = part[g];
+      q->fsi->run.st.lin_iters_mom += st[g].iters;
+      if (st[g].status != FSIMG_OK) {
+        newton_fail(q->fsi, (fsimg_status)st[g].status);
+        continue;
+      }
+      newton_lift(q->fsi, s);
+      alive.push_back(q);
+    }
+    pending.swap(rest);
   }
   hs.clear();
   bs.clear();
@@ -402,7 +423,8 @@ fsimg_status fsimg_server_submit_newton(fsimg_server *S, const fsimg_newton_requ
     return set_error(FSIMG_ERR_ARG, "request systems must be momentum (b = d+1) and ALE (b = d) "
                                     "on the same mesh");
   const fsimg_newton_opts &o = r->newton;
-  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0))
+  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
+      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0))
     return set_error(FSIMG_ERR_ARG, "bad Newton options");
   auto *q = new Req;
   q->id = S->next_id++;

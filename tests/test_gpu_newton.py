@@ -401,3 +401,26 @@ def test_served_newton_requests_equal_solo_runs(ctx, probs):
             assert acc["lin_iters_mom"] == sum(s["lin_iters_mom"] for s in sts)
     finally:
         fsimg.fsimg_server_destroy(srv)
+
+
+@pytest.mark.parametrize("name", ["t2", "t3"])
+def test_inexact_momentum_solves_reach_the_same_time_step(ctx, probs, name):
+    """With the paper's setting (each momentum solve reduces the error by
+    1e-4, Newton stops at a relative or absolute 1e-8, Sec. 5.5) the loop
+    converges to the oracle's time step (solved with exact linear solves) to
+    within the Newton tolerance."""
+    P = probs[name]
+    xr, ur, info, _ = _oracle_newton(P, 0.05)
+    x, u, xo, uo = fsi_state(P)
+    S = Fsi(ctx, P, rtol=1e-8)
+    try:
+        X, U = _t(x), _t(u)
+        st = fsimg.fsimg_fsi_newton(S.f, X, U, _t(xo), _t(uo),
+                                    fsimg.fsimg_default_newton_opts(lin_rtol=1e-4, atol=1e-8, max_steps=40))
+        torch.cuda.synchronize()
+    finally:
+        S.close()
+    assert st["status"] == fsimg.FSIMG_OK
+    assert st["res"] <= max(1e-8 * st["res0"], 1e-8)
+    assert np.abs(X.cpu().numpy() - xr).max() <= 1e-6 * np.abs(xr).max()
+    assert np.abs(U.cpu().numpy() - ur).max() <= 1e-6 * np.abs(ur).max()
