@@ -424,3 +424,31 @@ def test_inexact_momentum_solves_reach_the_same_time_step(ctx, probs, name):
     assert st["res"] <= max(1e-8 * st["res0"], 1e-8)
     assert np.abs(X.cpu().numpy() - xr).max() <= 1e-6 * np.abs(xr).max()
     assert np.abs(U.cpu().numpy() - ur).max() <= 1e-6 * np.abs(ur).max()
+
+
+@pytest.mark.parametrize("variant", ["block_patches", "ilu"])
+def test_newton_with_other_momentum_smoothers(ctx, probs, variant):
+    """The Newton loop does not depend on the smoother of the momentum
+    hierarchy: with 2 x 2 block Vanka patches or the block ILU(0) smoother it
+    reaches the oracle's time step (exact linear solves) to within the Newton
+    tolerance."""
+    P = probs["t2"]
+    xr, ur, info, _ = _oracle_newton(P, 0.05)
+    over = (dict(vanka_patches=fsimg.FSIMG_PATCH_BLOCK) if variant == "block_patches"
+            else dict(smoother=fsimg.FSIMG_SMOOTHER_ILU))
+    o = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_FP64, rtol=1e-10, **over)
+    mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
+    ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), fsimg.fsimg_default_opts(rtol=1e-10))
+    f = fsimg.fsimg_fsi_create(mom, ale, fsi_levels(P), P.params)
+    try:
+        X, U, Xo, Uo = (_t(a) for a in fsi_state(P))
+        st = fsimg.fsimg_fsi_newton(f, X, U, Xo, Uo)
+        torch.cuda.synchronize()
+    finally:
+        fsimg.fsimg_fsi_destroy(f)
+        fsimg.fsimg_hier_destroy(mom)
+        fsimg.fsimg_hier_destroy(ale)
+    assert st["status"] == fsimg.FSIMG_OK
+    assert (st["steps"], st["jacobians"]) == (info["steps"], info["jacobians"])
+    assert np.abs(X.cpu().numpy() - xr).max() <= 1e-7 * np.abs(xr).max()
+    assert np.abs(U.cpu().numpy() - ur).max() <= 1e-7 * np.abs(ur).max()
