@@ -46,24 +46,25 @@ def spmv_bytes(nnzb, nrows, b, s):
 
 
 KERNEL_SOURCES = ("batch_kernels.hip", "device_ops.h")
+ASM_SOURCES = ("kernels_asm.hip",)
 
 
-def kernel_source_hash():
-    """sha256[:16] over the sources that define the batched solve kernels."""
+def kernel_source_hash(sources=KERNEL_SOURCES):
+    """sha256[:16] over the sources that define the kernels measured."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_1904_02401_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(role, workload, prec):
+def measured_traffic(role, workload, prec, sources=KERNEL_SOURCES):
     """HBM bytes per launch recorded from rocprofv3 counters, or None when the
     kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    cur = kernel_source_hash()
+    cur = kernel_source_hash(sources)
     for line in open(path):
         f = line.split()
         if len(f) == 5 and not line.startswith("#") and f[:3] == [role, workload, prec]:
@@ -329,7 +330,10 @@ def run_newton(args, P):
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag},
         "roofline": {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic("asm_jac", f"{args.config}-momentum-level0", "fp64",
+                                                 ASM_SOURCES),
+                     "rmw_bytes_per_launch": rmw_bytes / launches_per_pass,
                      "flops_per_launch": flops / launches_per_pass, "avg_launch_ms": avg_launch_ms,
                      "launches": prof["jac_launches"],
                      "rmw_GBs": rmw_bytes / (jac_pass_ms * 1e-3) / 1e9,
