@@ -7,8 +7,10 @@ transfer, Krylov or coarse-solve code).
 """
 from .problem import (BSR, Level, Problem, PARAMS_DEFAULT, build_native, graded_axis,
                       make_problem, make_level, config_problem, batch_instance, serve_instance,
-                      serve_request)
+                      serve_request, Channel, make_channel, inflow_profile, inflow_ramp,
+                      graded_breaks, CHANNEL_PARAMS)
 
 __all__ = ["BSR", "Level", "Problem", "PARAMS_DEFAULT", "build_native", "graded_axis",
            "make_problem", "make_level", "config_problem", "batch_instance", "serve_instance",
-           "serve_request"]
+           "serve_request", "Channel", "make_channel", "inflow_profile", "inflow_ramp",
+           "graded_breaks", "CHANNEL_PARAMS"]

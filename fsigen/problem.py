@@ -107,6 +107,7 @@ class Level:
     node_fluid: np.ndarray  # uint8 [nnodes]: touches a fluid cell
     node_bdry: np.ndarray   # uint8 [nnodes]: bit a = on face x_a=0, bit a+3 = on x_a=1
     systems: dict = field(default_factory=dict)  # "mom", "ale", "mass" -> BSR
+    node_rigid: np.ndarray = None  # bool [nnodes]: touches a rigid obstacle cell
 
     @property
     def nnodes(self) -> int:
@@ -138,17 +139,26 @@ class Problem:
 def graded_axis(n_coarse: int, lo: float, hi: float, nlev: int) -> list:
     """Vertex coordinates per level (finest first) of a graded axis on [0,1]
     whose coarsest level has n_coarse cells with vertices at lo and hi."""
-    lens = np.array([lo, hi - lo, 1.0 - hi])
-    share = n_coarse * lens
+    return graded_breaks(n_coarse, [0.0, lo, hi, 1.0], nlev)
+
+
+def graded_breaks(n_coarse: int, ends, nlev: int) -> list:
+    """Vertex coordinates per level (finest first) of an axis from ends[0] to
+    ends[-1] whose coarsest level has n_coarse cells and a vertex at every
+    break in `ends`: each segment gets its share of the cells by length
+    (floor, at least one, remainder by largest fraction, ties to the lower
+    segment); finer levels bisect every cell."""
+    ends = [float(e) for e in ends]
+    lens = np.diff(np.array(ends))
+    share = n_coarse * lens / (ends[-1] - ends[0])
     cnt = np.maximum(np.floor(share).astype(int), 1)
     if cnt.sum() > n_coarse:
-        raise ValueError(f"{n_coarse} coarse cells cannot resolve interval {lo}..{hi}")
+        raise ValueError(f"{n_coarse} coarse cells cannot resolve the breaks {ends}")
     while cnt.sum() < n_coarse:
         frac = np.round(share - cnt, 9)  # exact ties must not depend on rounding
         cnt[int(np.argmax(frac))] += 1  # argmax takes the lowest index on ties
-    ends = [0.0, lo, hi, 1.0]
-    verts = [0.0]
-    for s in range(3):
+    verts = [ends[0]]
+    for s in range(len(lens)):
         verts.extend(np.linspace(ends[s], ends[s + 1], cnt[s] + 1)[1:].tolist())
     v = np.array(verts)
     out = [v]
@@ -256,10 +266,13 @@ def _compress(rowptr, colind, vals):
 
 
 def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom", "ale", "mass"),
-               need_smass=False):
+               need_smass=False, rigid_box=None):
     """Assemble the requested systems on one level.
 
     state_nodal: dict of nodal [nnodes, dim] arrays v_old, u_old, v_cur, u_cur.
+    rigid_box: cells whose centroid lies inside it form a rigid obstacle: they
+    are flagged solid and every node touching them has the velocity held
+    (no-slip), so with zero velocity there they contribute nothing.
     """
     lib = _native()
     cells = tuple(int(c) for c in cells)
@@ -274,6 +287,13 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
     lo, hi = solid_box
     inside = [((cen[a] > lo[a]) & (cen[a] < hi[a])).astype(np.uint8) for a in range(dim)]
     cell_solid = _tensor(inside, dim).astype(np.uint8)
+    if rigid_box is not None:
+        rin = [((cen[a] > rigid_box[0][a]) & (cen[a] < rigid_box[1][a])).astype(np.uint8)
+               for a in range(dim)]
+        cell_rigid = _tensor(rin, dim).astype(bool)
+        cell_solid[cell_rigid] = 1
+    else:
+        cell_rigid = np.zeros(cell_solid.shape, dtype=bool)
     # node flags: a node touches the cells e with 2e <= g <= 2e+2 per axis
     cs = cell_solid.reshape([cells[a] for a in range(dim)][::-1])
     touch_s = np.zeros([nnode_axis[a] for a in range(dim)][::-1], dtype=bool)
@@ -283,6 +303,12 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
         touch_s[sl] |= cs.astype(bool)
         touch_f[sl] |= ~cs.astype(bool)
     node_solid = touch_s.ravel().astype(np.uint8)
+    touch_r = np.zeros_like(touch_s)
+    cr = cell_rigid.reshape(cs.shape)
+    for off in np.ndindex(*([3] * dim)):
+        sl = tuple(slice(off[a], off[a] + 2 * cells[::-1][a], 2) for a in range(dim))
+        touch_r[sl] |= cr
+    node_rigid = touch_r.ravel()
     node_fluid = touch_f.ravel().astype(np.uint8)
     node_bdry = np.zeros(nnodes, dtype=np.uint8)
     for a in range(dim):
@@ -293,7 +319,8 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
         per_axis[a] = e
         node_bdry |= _tensor(per_axis, dim).astype(np.uint8)
     lev = Level(dim=dim, cells=cells, coords=[np.asarray(c) for c in coords], cell_solid=cell_solid,
-                node_solid=node_solid, node_fluid=node_fluid, node_bdry=node_bdry)
+                node_solid=node_solid, node_fluid=node_fluid, node_bdry=node_bdry,
+                node_rigid=node_rigid)
 
     rowptr, colind = _pattern(dim, cells)
     nnzb = colind.shape[0]
@@ -319,6 +346,7 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
     walls |= (node_bdry & 1).astype(bool)
     for a in range(1, dim):
         walls |= (node_bdry & ((1 << a) | (1 << (a + 3)))).astype(bool)
+    walls |= node_rigid
     if vm is not None:
         mask = np.zeros((nnodes, bm), dtype=np.uint8)
         mask[walls, 1:] = 1
@@ -491,6 +519,95 @@ def serve_request(dim: int, n: int, seed: int = 0, n_states: int = 2, n_rhs: int
     states = [make_problem(dim, n, nlev, box, seed=seed + 7919 * s, systems=("mom",))
               for s in range(1, n_states)]
     return P, states, list(P.rhs.get("mom_more", []))
+
+
+# ------------------------------------------------- the benchmark channel
+# The 3D benchmark of Sec. 5 (Fig. config3d): channel (0, 2.8) x (0, 0.41)^2,
+# an obstacle around the axis x = 0.5, y = 0.2 spanning the channel in z,
+# an elastic beam 0.5 < x < 0.9, 0.19 < y < 0.21, 0.1 < z < 0.3 behind it.
+# On the rectilinear Q2 mesh the cylinder of radius 0.05 is read as the square
+# prism 0.45 < x < 0.55, 0.15 < y < 0.25 (so the beam starts at x = 0.55 and is
+# 0.35 long); the 2D channel is the cut z = const of the same geometry.
+CHANNEL_ENDS = ([0.0, 0.45, 0.55, 0.9, 2.8], [0.0, 0.15, 0.19, 0.21, 0.25, 0.41],
+                [0.0, 0.1, 0.3, 0.41])
+CHANNEL_COARSE = (7, 5, 3)
+CHANNEL_OBSTACLE = ((0.45, 0.15, -1.0), (0.55, 0.25, 1.0))
+CHANNEL_BEAM = ((0.55, 0.19, 0.1), (0.9, 0.21, 0.3))
+CHANNEL_HEIGHT = 0.41
+# material and inflow of the benchmark table (Sec. 5): mean inflow 2 (2D) and
+# 1.75 (3D) m/s; time step k = 0.002 s with theta = 0.5 + 2k
+CHANNEL_PARAMS = dict(rho_f=1.0e3, nu_f=1.0e-3, rho_s=1.0e3, mu_s=2.0e6, lambda_s=8.0e6,
+                      k=0.002, theta=0.504, alpha0=1.0)
+CHANNEL_VBAR = {2: 2.0, 3: 1.75}
+
+
+@dataclass
+class Channel:
+    """The benchmark channel: the problem (levels with momentum and ALE
+    systems, rest state), the inflow rows of the Newton vector x with the
+    unscaled inflow profile there, the nodes of the obstacle (the drag / lift
+    test function is one on them) and the beam's cross-section where it meets
+    the obstacle (area in 3D, length in 2D)."""
+    problem: Problem
+    inflow_rows: np.ndarray   # int64 indices into x (node * (d + 1) + 1)
+    inflow_vals: np.ndarray   # float64 profile at those rows (ramp factor 1)
+    force_nodes: np.ndarray   # int64 nodes touching obstacle cells
+    root_area: float
+    vbar: float
+
+
+def inflow_profile(dim, y, z=None, vbar=1.0):
+    """Inflow x-velocity of the benchmark (Sec. 5): bi-parabolic
+    36 vbar y (H - y) z (H - z) / H^4 in 3D, and its 2D analog
+    6 vbar y (H - y) / H^2; both have the mean vbar over the inflow face."""
+    H = CHANNEL_HEIGHT
+    if dim == 2:
+        return 6.0 * vbar * y * (H - y) / H ** 2
+    return 36.0 * vbar * y * (H - y) * z * (H - z) / H ** 4
+
+
+def inflow_ramp(t):
+    """Start-up factor of the inflow (Sec. 5): (1 - cos(pi t)) / 2 on [0, 1),
+    then 1."""
+    return 0.5 - 0.5 * np.cos(np.pi * t) if t < 1.0 else 1.0
+
+
+def make_channel(dim: int, nlev: int, params=None, coarse=None) -> Channel:
+    """The benchmark channel with nlev levels (coarsest: CHANNEL_COARSE cells
+    per axis, graded so that every level resolves the obstacle and beam
+    faces), at rest (v = u = 0): momentum and ALE systems assembled at that
+    state, no right-hand sides."""
+    p = dict(CHANNEL_PARAMS)
+    if params:
+        p.update(params)
+    coarse = coarse or CHANNEL_COARSE[:dim]
+    verts = [graded_breaks(coarse[a], CHANNEL_ENDS[a], nlev) for a in range(dim)]
+    beam = (CHANNEL_BEAM[0][:dim], CHANNEL_BEAM[1][:dim])
+    obst = (CHANNEL_OBSTACLE[0][:dim], CHANNEL_OBSTACLE[1][:dim])
+    levels = []
+    for l in range(nlev):
+        coords = [_nodes_from_verts(verts[a][l]) for a in range(dim)]
+        n = int(np.prod([c.shape[0] for c in coords]))
+        zero = np.zeros((n, dim))
+        st = dict(v_old=zero, u_old=zero, v_cur=zero, u_cur=zero)
+        cells = tuple(len(verts[a][l]) - 1 for a in range(dim))
+        levels.append(make_level(dim, cells, coords, beam, st, p, systems=("mom", "ale"),
+                                 rigid_box=obst))
+    fine = levels[0]
+    nn = fine.nnodes
+    zero = np.zeros((nn, dim))
+    P = Problem(dim=dim, params=p, seed=0, levels=levels, v_old=zero, u_old=zero.copy(),
+                v_cur=zero.copy(), u_cur=zero.copy(), rhs={}, solid_box=beam)
+    X = _grid_coords(fine.coords, dim)
+    node = np.nonzero(fine.node_bdry & 1)[0]           # the face x = 0
+    vbar = CHANNEL_VBAR[dim]
+    vals = inflow_profile(dim, X[node, 1], X[node, 2] if dim == 3 else None, vbar)
+    rows = node.astype(np.int64) * (dim + 1) + 1
+    force = np.nonzero(fine.node_rigid)[0].astype(np.int64)
+    b = CHANNEL_BEAM
+    area = (b[1][1] - b[0][1]) * ((b[1][2] - b[0][2]) if dim == 3 else 1.0)
+    return Channel(problem=P, inflow_rows=rows, inflow_vals=vals, force_nodes=force,
+                   root_area=area, vbar=vbar)
 
 
 def config_problem(name: str, seed: int = 0, **kw) -> Problem:

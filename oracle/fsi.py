@@ -426,3 +426,31 @@ def newton(mesh, prm, A_pattern, mom_mask, E, ale_mask, x, u, x_old, u_old, rtol
             info["status"] = "ok"
     info["steps"] = len(info["res"]) - 1
     return x, u, info, jac
+
+
+def force(mesh, prm, x, u, x_old, u_old, nodes):
+    """Mean force of the fluid (and of anything attached) on a rigid obstacle
+    over the time step, in the residual form of the benchmark's quantities of
+    interest (Sec. 5): the step's operator tested with psi e_j, psi the nodal
+    function that is one at the obstacle's nodes and zero at all others,
+    divided by k.  The operator tested with that function equals the boundary
+    integral of the traction with the fluid's outward normal; the sign is
+    flipped so that the result is the force *on* the obstacle (a flow past it
+    has positive drag).  Returns [d]: drag (x), lift (y) and, in 3D, z."""
+    d = mesh.dim
+    A = operator_value(mesh, prm, x, u, x_old, u_old).reshape(-1, d + 1)
+    return -A[np.asarray(nodes), 1:].sum(axis=0) / prm["k"]
+
+
+def time_step(mesh, prm, A_pattern, mom_mask, E, ale_mask, x, u, rows, vals, scale, jac=None,
+              **newton_kw):
+    """One time step of the benchmark: the previous state becomes the old
+    level, the held velocity rows take scale * vals (inflow profile times
+    the start-up factor), the Newton loop starts from the previous state.
+    Returns (x, u, x_old, u_old, info, jac)."""
+    x_old, u_old = np.array(x, dtype=np.float64), np.array(u, dtype=np.float64)
+    x = x_old.copy()
+    x[np.asarray(rows)] = scale * np.asarray(vals)
+    x, u, info, jac = newton(mesh, prm, A_pattern, mom_mask, E, ale_mask, x, u_old.copy(), x_old,
+                             u_old, jac=jac, **newton_kw)
+    return x, u, x_old, u_old, info, jac
