@@ -229,6 +229,160 @@ def asm_flops_per_element(dim, solid):
     return nn * nn * nn * per
 
 
+def asm_roofline(f, P, x, u, xo, uo, workload):
+    """The finest level's element kernels, event-timed per launch on the
+    launch stream (three Jacobian and residual assemblies at the given
+    state): the Jacobian kernel's roofline entry, the residual kernel's
+    launch time and the finest level's assembly rate (elements / s)."""
+    import torch
+    from paper_1904_02401_amd import fsimg
+    fsimg.fsimg_fsi_set_profile(f, 1)
+    for _ in range(3):
+        fsimg.fsimg_fsi_jacobian(f, x, u, xo, uo)
+        res = torch.empty_like(x)
+        fsimg.fsimg_fsi_residual(f, x, u, xo, uo, res)
+    prof = fsimg.fsimg_fsi_profile(f)
+    fsimg.fsimg_fsi_set_profile(f, 0)
+    lev = P.levels[0]
+    ns = int(lev.cell_solid.sum())
+    nf = lev.ncells - ns
+    flops = nf * asm_flops_per_element(P.dim, False) + ns * asm_flops_per_element(P.dim, True)
+    launches_per_pass = 2 ** P.dim
+    jac_pass_ms = prof["jac_ms"] / max(prof["jac_launches"], 1) * launches_per_pass
+    avg_launch_ms = prof["jac_ms"] / max(prof["jac_launches"], 1)
+    tf = flops / (jac_pass_ms * 1e-3) / 1e12
+    nb = lev.systems["mom"].nnzb
+    b = P.dim + 1
+    # bytes the colouring moves: every element reads and writes its (3^d)^2 blocks
+    rmw_bytes = lev.ncells * (3 ** P.dim) ** 2 * b * b * 8 * 2
+    roof = {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": measured_traffic("asm_jac", workload, "fp64", ASM_SOURCES),
+            "rmw_bytes_per_launch": rmw_bytes / launches_per_pass,
+            "flops_per_launch": flops / launches_per_pass, "avg_launch_ms": avg_launch_ms,
+            "launches": prof["jac_launches"],
+            "rmw_GBs": rmw_bytes / (jac_pass_ms * 1e-3) / 1e9,
+            "matrix_bytes": nb * b * b * 8}
+    res_kernel = {"kernel": f"k_asm_res<{P.dim}>",
+                  "avg_launch_ms": prof["res_ms"] / max(prof["res_launches"], 1),
+                  "launches": prof["res_launches"]}
+    return roof, res_kernel, lev.ncells / (jac_pass_ms * 1e-3)
+
+
+CHANNEL_CONFIGS = {"channel3": (3, 4), "channel2": (2, 5)}
+
+
+def run_channel(args):
+    """The benchmark channel of Sec. 5 from rest: time steps of the start-up
+    (inflow ramped by (1 - cos(pi t)) / 2), each one fsimg_fsi_time_step
+    (old level <- state, inflow rows, Newton loop with Jacobian reuse) and
+    one fsimg_fsi_force (drag and lift in residual form)."""
+    import numpy as np
+    import torch
+    from fsigen import inflow_ramp, make_channel
+    from paper_1904_02401_amd import fsimg
+    from paper_1904_02401_amd.problems import fsi_levels, level_dicts
+
+    dim, nlev = CHANNEL_CONFIGS[args.config]
+    t0 = time.perf_counter()
+    C = make_channel(dim, nlev)
+    P = C.problem
+    lev = P.levels[0]
+    log(f"{args.config}: {lev.cells} cells on the finest of {nlev} levels, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    prec = fsimg.FSIMG_FP64 if args.only == "fp64" else fsimg.FSIMG_MIXED
+    tag = "fp64" if prec == fsimg.FSIMG_FP64 else "mixed"
+    ctx = fsimg.fsimg_ctx_create(0)
+    # the channel's cells reach aspect ratio 24 (the beam's rows run the whole
+    # length): element patches stall there, block patches (2^d elements) do not
+    patches = args.patches or "block"
+    o = fsimg.fsimg_default_opts(precision=prec, max_iter=1000, vanka_patches=(
+        fsimg.FSIMG_PATCH_BLOCK if patches == "block" else fsimg.FSIMG_PATCH_ELEMENT))
+    t0 = time.perf_counter()
+    mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
+    ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), o)
+    f = fsimg.fsimg_fsi_create(mom, ale, fsi_levels(P), P.params)
+    if not args.no_tune:
+        fsimg.fsimg_factor(mom)
+        fsimg.fsimg_factor(ale)
+        fsimg.fsimg_hier_tune(mom)
+        fsimg.fsimg_hier_tune(ale)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    n, d = lev.nnodes, dim
+    x = torch.zeros(n * (d + 1), device=dev, dtype=torch.float64)
+    u = torch.zeros(n * d, device=dev, dtype=torch.float64)
+    xo, uo = x.clone(), u.clone()
+    rows = torch.tensor(C.inflow_rows, device=dev)
+    vals = torch.tensor(C.inflow_vals, device=dev)
+    nodes = torch.tensor(C.force_nodes, device=dev)
+    nopts = fsimg.fsimg_default_newton_opts(gamma=args.gamma, lin_rtol=args.lin_rtol, atol=args.newton_atol,
+                                            max_steps=args.max_newton)
+    k = P.params["k"]
+    hist = []
+
+    def step(i):
+        t = i * k
+        st = fsimg.fsimg_fsi_time_step(f, x, u, xo, uo, rows, vals, inflow_ramp(t), nopts,
+                                       raise_on_noconv=False)
+        F = fsimg.fsimg_fsi_force(f, x, u, xo, uo, nodes, d)
+        log(f"t = {t:.4f}: status {st['status']}, {st['steps']} Newton steps, {st['jacobians']} Jacobians, "
+            f"res {st['res0']:.3e} -> {st['res']:.3e}, {st['ms_total']:.0f} ms, drag {F[0]:.6e}, "
+            f"lift {F[1]:.6e}")
+        hist.append(dict(t=t, drag=F[0], lift=F[1], **{q: st[q] for q in (
+            "status", "steps", "jacobians", "halvings", "lin_iters_mom", "lin_iters_ale", "ms_total")}))
+        return st
+
+    for i in range(1, args.warmup + 1):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step(i) for i in range(args.warmup + 1, args.warmup + args.steps + 1)]
+    torch.cuda.synchronize()
+    t_ts = (time.perf_counter() - t0) / args.steps
+    bad = [h for h in hist if h["status"] != fsimg.FSIMG_OK]
+    roof, res_kernel, elems_per_s = asm_roofline(f, P, x, u, xo, uo, f"{args.config}-momentum-level0")
+    n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
+    n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
+    tot = lambda q: sum(s[q] for s in stats)
+    out = {
+        "metric": "benchmark channel time steps: (momentum + ALE unknowns) x time steps per second",
+        "value": (n_mom + n_ale) / t_ts,
+        "unit": "DoF/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_ts * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if tag == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"{args.config}: the {dim}D benchmark channel of Sec. 5 (cylinder read as a "
+                                f"square prism), {'x'.join(map(str, lev.cells))} Q2 cells, {nlev} levels, "
+                                f"start-up from rest, time steps {args.warmup + 1}..{args.warmup + args.steps} "
+                                f"timed (k = {k}, theta = {P.params['theta']}), each with drag / lift; "
+                                f"gamma_nt = {args.gamma}, Newton stop at 1e-8 relative or "
+                                f"{args.newton_atol:g} absolute, momentum solves to {args.lin_rtol:g}, "
+                                f"{patches} Vanka patches"),
+                   "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag,
+                   "vanka_patches": patches},
+        "roofline": roof,
+        "residual_kernel": res_kernel,
+        "newton": {"time_steps": args.steps, "newton_steps": tot("steps"), "jacobians": tot("jacobians"),
+                   "halvings": tot("halvings"), "momentum_iters": tot("lin_iters_mom"),
+                   "ale_iters": tot("lin_iters_ale"), "ms_jacobian_assembly": tot("ms_jacobian") / args.steps,
+                   "ms_factor": tot("ms_factor") / args.steps, "ms_solve": tot("ms_solve") / args.steps,
+                   "not_converged": len(bad), "setup_s": t_setup},
+        "functionals": hist,
+        "assembly_elements_per_s": elems_per_s,
+    }
+    fsimg.fsimg_fsi_destroy(f)
+    fsimg.fsimg_hier_destroy(mom)
+    fsimg.fsimg_hier_destroy(ale)
+    fsimg.fsimg_ctx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_assembly_baseline(P)
+    print(json.dumps(out), flush=True)
+
+
 def run_newton(args, P):
     """Time steps of the approximate Newton loop on the GPU (residual and
     Jacobian assembly, Jacobian reuse, momentum / deformation / ALE solves,
@@ -289,28 +443,10 @@ def run_newton(args, P):
     for st in stats:
         if st["status"] != fsimg.FSIMG_OK:
             log(f"newton: a time step ended with status {st['status']} after {st['steps']} steps")
-    # the finest level's element kernels, event-timed per launch on the launch stream
-    fsimg.fsimg_fsi_set_profile(f, 1)
-    for _ in range(3):
-        fsimg.fsimg_fsi_jacobian(f, x, u, xo, uo)
-        res = torch.empty_like(x)
-        fsimg.fsimg_fsi_residual(f, x, u, xo, uo, res)
-    prof = fsimg.fsimg_fsi_profile(f)
-    fsimg.fsimg_fsi_set_profile(f, 0)
+    roof, res_kernel, elems_per_s = asm_roofline(f, P, x, u, xo, uo, f"{args.config}-momentum-level0")
     lev = P.levels[0]
-    ns = int(lev.cell_solid.sum())
-    nf = lev.ncells - ns
-    flops = nf * asm_flops_per_element(P.dim, False) + ns * asm_flops_per_element(P.dim, True)
-    launches_per_pass = 2 ** P.dim
-    jac_pass_ms = prof["jac_ms"] / max(prof["jac_launches"], 1) * launches_per_pass
-    avg_launch_ms = prof["jac_ms"] / max(prof["jac_launches"], 1)
-    tf = flops / (jac_pass_ms * 1e-3) / 1e12
     n_mom = lev.systems["mom"].nrows * lev.systems["mom"].b
     n_ale = lev.systems["ale"].nrows * lev.systems["ale"].b
-    nb = lev.systems["mom"].nnzb
-    b = P.dim + 1
-    # bytes the colouring moves: every element reads and writes its (3^d)^2 blocks
-    rmw_bytes = lev.ncells * (3 ** P.dim) ** 2 * b * b * 8 * 2
     tot = lambda k: sum(s[k] for s in stats)
     out = {
         "metric": "Newton time steps: (momentum + ALE unknowns) x time steps per second",
@@ -328,19 +464,8 @@ def run_newton(args, P):
                        f"Newton stop at 1e-8 relative or {args.newton_atol:g} absolute (max-norm), "
                        f"momentum solves to {args.lin_rtol:g} relative, ALE solves to 1e-8"),
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale, "precision": tag},
-        "roofline": {"bound": "alu", "kernel": f"k_asm_jac<{P.dim}>", "achieved": tf,
-                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic("asm_jac", f"{args.config}-momentum-level0", "fp64",
-                                                 ASM_SOURCES),
-                     "rmw_bytes_per_launch": rmw_bytes / launches_per_pass,
-                     "flops_per_launch": flops / launches_per_pass, "avg_launch_ms": avg_launch_ms,
-                     "launches": prof["jac_launches"],
-                     "rmw_GBs": rmw_bytes / (jac_pass_ms * 1e-3) / 1e9,
-                     "matrix_bytes": nb * b * b * 8},
-        "residual_kernel": {"kernel": f"k_asm_res<{P.dim}>",
-                            "avg_launch_ms": prof["res_ms"] / max(prof["res_launches"], 1),
-                            "launches": prof["res_launches"]},
+        "roofline": roof,
+        "residual_kernel": res_kernel,
         "newton": {"per_step": [{k: st[k] for k in ("status", "steps", "jacobians", "halvings",
                                                     "lin_iters_mom", "lin_iters_ale", "ms_total")}
                                 for st in stats],
@@ -357,7 +482,7 @@ def run_newton(args, P):
     fsimg.fsimg_hier_destroy(ale)
     fsimg.fsimg_ctx_destroy(ctx)
     # GPU assembly rate of the finest level (elements / s), the oracle's beside it
-    out["assembly_elements_per_s"] = lev.ncells / (jac_pass_ms * 1e-3)
+    out["assembly_elements_per_s"] = elems_per_s
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_assembly_baseline(P)
     print(json.dumps(out), flush=True)
@@ -691,8 +816,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes, no tuning")
     ap.add_argument("--schedule", choices=["gather", "parity", "greedy"], default="gather",
                     help="Vanka schedule: per-dof gather (batched path) or coloured scatter")
-    ap.add_argument("--patches", choices=["element", "block"], default="element",
-                    help="Vanka patches: one element, or 2x2(x2) element blocks (3D: solid only)")
+    ap.add_argument("--patches", choices=["element", "block"], default=None,
+                    help="Vanka patches: one element, or 2x2(x2) element blocks (3D: solid only); "
+                         "default element, block on the benchmark channel")
     ap.add_argument("--smoother", choices=["vanka", "ilu"], default="vanka",
                     help="multigrid smoother (ilu: block ILU(0), level-scheduled)")
     ap.add_argument("--no-mass", action="store_true")
@@ -745,6 +871,10 @@ def main():
     if args.calib_copy:
         calib_copy(args.calib_copy << 20, 5)
         return
+    if args.config in CHANNEL_CONFIGS:
+        run_channel(args)
+        return
+    args.patches = args.patches or "element"
     import numpy as np
     from fsigen import config_problem
     from oracle import to_csr

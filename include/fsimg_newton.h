@@ -132,6 +132,34 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
 /* Forget the Jacobian held by the object (the next Newton call assembles). */
 fsimg_status fsimg_fsi_drop_jacobian(fsimg_fsi *f);
 
+/* One step of a time-stepping run (Sec. 5: the benchmark's start-up from
+   rest, with time-dependent inflow): copies the current state (x, u) into the
+   old level (x_old, u_old: buffers of their own, sizes as for x and u), sets
+   the held rows rows[i] of x to scale * vals[i] (the Dirichlet data of t_n,
+   e.g. the inflow profile times the start-up factor), then runs
+   fsimg_fsi_newton from the previous state.  rows and vals are device arrays
+   of n_rows entries (n_rows may be 0); every row must be a held (identity)
+   row of the momentum system, else ERR_ARG (x may then be partly written).
+   The Jacobian held by the object carries over from the previous step. */
+fsimg_status fsimg_fsi_time_step(fsimg_fsi *f, double *x, double *u, double *x_old, double *u_old,
+                                 const int64_t *rows, const double *vals, int64_t n_rows, double scale,
+                                 const fsimg_newton_opts *opts, fsimg_newton_stats *stats, void *stream);
+
+/* Drag and lift in the residual form of Sec. 5 (quantities of interest): the
+   step operator A(U) of the momentum rows (eq. aletime:2, no identity rows)
+   tested with psi e_j, psi the nodal function equal to one at the listed
+   nodes (device int64 array of n_nodes node numbers of the finest level,
+   e.g. every node of a rigid obstacle) and zero elsewhere, divided by k and
+   negated: the mean force on the obstacle over the step (positive drag for a
+   flow past it).  force: host array of d doubles (x, y[, z]).  The sum runs
+   in a fixed order (same result on every call).  Uses the object's residual
+   work vector (not during a Newton call on the same object); synchronises
+   the stream.  ERR_ARG for a node out of range, ERR_SINGULAR for an
+   inverted element. */
+fsimg_status fsimg_fsi_force(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                             const double *u_old, const int64_t *nodes, int64_t n_nodes, double *force,
+                             void *stream);
+
 /* Timing only: on != 0 records HIP events on the launch stream around every
    launch of the finest level's element kernels (one launch per parity colour)
    of the following residual and Jacobian assemblies and resets the sums;

@@ -49,6 +49,10 @@ struct fsimg_fsi {
   int *hflag = nullptr;                                          // pinned host mirror
   unsigned long long *hnorm = nullptr;
   bool have_jac = false;
+  // the force evaluation (allocated on its first call): an all-zero row mask
+  // (the residual without identity rows) and the summed force components
+  uint8_t *zero_mask = nullptr;
+  double *dforce = nullptr;
   fsimg::NewtonRun run;
   // profiling: events around the finest level's element launches (one pair
   // per parity colour) and the accumulated times

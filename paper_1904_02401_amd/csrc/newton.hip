@@ -154,6 +154,51 @@ fsimg_status assemble_jacobian(fsimg_fsi *f, const double *x, const double *u, c
   return flags_status(flags);
 }
 
+// held rows of x take scale * vals (a time step's Dirichlet data); a row out
+// of range or not held in the momentum system sets bad[0] and is skipped
+__global__ __launch_bounds__(256) void k_set_held_rows(double *__restrict__ x, const int64_t *__restrict__ rows,
+                                                       const double *__restrict__ vals, int64_t n, int64_t nx,
+                                                       const uint8_t *__restrict__ mask, double scale,
+                                                       int *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = rows[i];
+  if (r < 0 || r >= nx || !mask[r]) {
+    bad[0] = 1;
+    return;
+  }
+  x[r] = scale * vals[i];
+}
+
+// out[j] = sum over the listed nodes of res[node * B + 1 + j] / k, j < D: one
+// workgroup, each thread a strided partial sum, then a fixed-order tree in
+// LDS (the same order on every call); a node out of range sets bad[0]
+constexpr int kForceThreads = 256;
+__global__ __launch_bounds__(kForceThreads) void k_force_sum(const double *__restrict__ res,
+                                                             const int64_t *__restrict__ nodes, int64_t n,
+                                                             int64_t nrows, int D, double inv_k,
+                                                             double *__restrict__ out, int *__restrict__ bad) {
+  __shared__ double part[3][kForceThreads];
+  const int t = threadIdx.x, B = D + 1;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = t; i < n; i += kForceThreads) {
+    const int64_t g = nodes[i];
+    if (g < 0 || g >= nrows) {
+      bad[0] = 1;
+      continue;
+    }
+    for (int j = 0; j < D; ++j) acc[j] += res[g * B + 1 + j];
+  }
+  for (int j = 0; j < 3; ++j) part[j][t] = acc[j];
+  __syncthreads();
+  for (int w = kForceThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int j = 0; j < 3; ++j) part[j][t] += part[j][t + w];
+    __syncthreads();
+  }
+  if (t < D) out[t] = part[t][0] * inv_k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,6 +460,62 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
   const fsimg_newton_stats st = newton_end(f, s);
   if (stats) *stats = st;
   return static_cast<fsimg_status>(st.status);
+}
+
+fsimg_status fsimg_fsi_time_step(fsimg_fsi *f, double *x, double *u, double *x_old, double *u_old,
+                                 const int64_t *rows, const double *vals, int64_t n_rows, double scale,
+                                 const fsimg_newton_opts *opts, fsimg_newton_stats *stats, void *stream) {
+  if (!f || !x || !u || !x_old || !u_old) return nfail(FSIMG_ERR_ARG, "null argument");
+  if (n_rows < 0 || (n_rows > 0 && (!rows || !vals))) return nfail(FSIMG_ERR_ARG, "bad held-row list");
+  if (!f->ale) return nfail(FSIMG_ERR_ARG, "the Newton loop needs an ALE hierarchy");
+  if (x == x_old || u == u_old) return nfail(FSIMG_ERR_ARG, "the old level needs buffers of its own");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLevel &L = f->mom->lev[0];
+  const int64_t na = L.nrows * f->dim;
+  NW_HIP(hipMemcpyAsync(x_old, x, L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  NW_HIP(hipMemcpyAsync(u_old, u, na * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (n_rows > 0) {
+    NW_TRY(clear_flags(f, s));
+    hipLaunchKernelGGL(k_set_held_rows, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s, x, rows, vals,
+                       n_rows, L.n, L.mask, scale, f->dflag);
+    NW_HIP(hipGetLastError());
+    int flags[2];
+    NW_TRY(read_flags(f, s, flags, nullptr));
+    if (flags[0]) return nfail(FSIMG_ERR_ARG, "a held-row index is out of range or not a held row");
+  }
+  return fsimg_fsi_newton(f, x, u, x_old, u_old, opts, stats, stream);
+}
+
+fsimg_status fsimg_fsi_force(fsimg_fsi *f, const double *x, const double *u, const double *x_old,
+                             const double *u_old, const int64_t *nodes, int64_t n_nodes, double *force,
+                             void *stream) {
+  if (!f || !x || !u || !x_old || !u_old || !force) return nfail(FSIMG_ERR_ARG, "null argument");
+  if (n_nodes < 0 || (n_nodes > 0 && !nodes)) return nfail(FSIMG_ERR_ARG, "bad node list");
+  NW_HIP(hipSetDevice(f->mom->ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLevel &L = f->mom->lev[0];
+  if (!f->zero_mask) {
+    NW_TRY(falloc(f, &f->zero_mask, (size_t)L.n));
+    NW_TRY(falloc(f, &f->dforce, 3));
+    NW_HIP(hipMemset(f->zero_mask, 0, (size_t)L.n));
+  }
+  AsmLevel all = f->lev[0].dev;
+  all.mask = f->zero_mask;
+  NW_TRY(clear_flags(f, s));
+  launch_asm_residual(all, f->dim, asm_phys(f->phys), AsmState{x, u, x_old, u_old}, f->res, L.nrows,
+                      f->dflag, s, nullptr);
+  hipLaunchKernelGGL(k_force_sum, dim3(1), dim3(kForceThreads), 0, s, f->res, nodes, n_nodes, L.nrows, f->dim,
+                     1.0 / f->phys.k, f->dforce, f->dflag + 1);
+  NW_HIP(hipGetLastError());
+  double h[3];
+  NW_HIP(hipMemcpyAsync(h, f->dforce, f->dim * sizeof(double), hipMemcpyDeviceToHost, s));
+  int flags[2];
+  NW_TRY(read_flags(f, s, flags, nullptr));
+  if (flags[1]) return nfail(FSIMG_ERR_ARG, "a force node index is out of range");
+  if (flags[0]) return nfail(FSIMG_ERR_SINGULAR, "det F <= 0 at a Gauss point (inverted element)");
+  for (int j = 0; j < f->dim; ++j) force[j] = h[j];
+  return FSIMG_OK;
 }
 
 }  // extern "C"

@@ -173,6 +173,9 @@ _SIGS = {
     "fsimg_fsi_newton": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(fsimg_newton_opts),
                               ctypes.POINTER(fsimg_newton_stats), _P]),
     "fsimg_fsi_drop_jacobian": (_I, [_P]),
+    "fsimg_fsi_time_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _I64, _D, ctypes.POINTER(fsimg_newton_opts),
+                                 ctypes.POINTER(fsimg_newton_stats), _P]),
+    "fsimg_fsi_force": (_I, [_P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(_D), _P]),
     "fsimg_server_submit_newton": (_I, [_P, ctypes.POINTER(fsimg_newton_request), ctypes.POINTER(_I64)]),
     "fsimg_server_newton_stats": (_I, [_P, _I64, ctypes.POINTER(fsimg_newton_stats)]),
     "fsimg_fsi_set_profile": (_I, [_P, _I]),
@@ -565,6 +568,29 @@ def fsimg_fsi_newton(f, x, u, x_old, u_old, opts=None, stream=None, raise_on_noc
 
 def fsimg_fsi_drop_jacobian(f):
     _check(load().fsimg_fsi_drop_jacobian(f))
+
+
+def fsimg_fsi_time_step(f, x, u, x_old, u_old, rows=None, vals=None, scale: float = 1.0, opts=None,
+                        stream=None, raise_on_noconv: bool = True) -> dict:
+    """rows (int64) and vals (float64): device tensors of the held rows of x
+    and their unscaled values, or None."""
+    st = fsimg_newton_stats()
+    o = opts if opts is not None else fsimg_default_newton_opts()
+    n = 0 if rows is None else int(rows.numel())
+    rc = load().fsimg_fsi_time_step(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old),
+                                    _dev(rows) if n else None, _dev(vals) if n else None, n,
+                                    float(scale), ctypes.byref(o), ctypes.byref(st), _stream(stream))
+    if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
+        _check(rc)
+    return st.as_dict()
+
+
+def fsimg_fsi_force(f, x, u, x_old, u_old, nodes, dim: int, stream=None):
+    """nodes: int64 device tensor; returns [dim] floats (drag, lift[, z])."""
+    out = (_D * 3)()
+    _check(load().fsimg_fsi_force(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _dev(nodes),
+                                  int(nodes.numel()), out, _stream(stream)))
+    return [out[j] for j in range(dim)]
 
 
 def fsimg_fsi_set_profile(f, on: int):
