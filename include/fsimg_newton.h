@@ -91,7 +91,9 @@ typedef struct {
                         most this often (default 4) */
   double lin_rtol;   /* relative tolerance of each momentum solve inside the loop (Sec. 5.5
                         reduces the error by 1e-4 per Newton step); 0 (default): the momentum
-                        hierarchy's own rtol.  The ALE solves keep the ALE hierarchy's rtol. */
+                        hierarchy's own rtol. */
+  double ale_rtol;   /* relative tolerance of each ALE solve inside the loop; 0 (default):
+                        the ALE hierarchy's own rtol */
 } fsimg_newton_opts;
 
 typedef struct {

@@ -211,6 +211,7 @@ void fsimg_default_newton_opts(fsimg_newton_opts *o) {
   o->gamma = 0.05;
   o->max_halvings = 4;
   o->lin_rtol = 0.0;
+  o->ale_rtol = 0.0;
 }
 
 void fsimg_fsi_destroy(fsimg_fsi *f) {
@@ -424,7 +425,7 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
   fsimg_default_newton_opts(&o);
   if (opts) o = *opts;
   if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
-      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0))
+      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0) || !(o.ale_rtol >= 0.0 && o.ale_rtol < 1.0))
     return nfail(FSIMG_ERR_ARG, "bad Newton options");
   NW_HIP(hipSetDevice(f->mom->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -448,7 +449,10 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
     }
     newton_lift(f, s);
     // ALE extension (eq. problem:3)
+    const double keep_ale = f->ale->opts.rtol;
+    if (o.ale_rtol > 0.0) f->ale->opts.rtol = o.ale_rtol;
     ss = fsimg_solve(f->ale, f->b5, f->du, &ls, s);
+    f->ale->opts.rtol = keep_ale;
     R.st.lin_iters_ale += ls.iters;
     R.st.ms_solve += ms_since(t0);
     if (ss != FSIMG_OK) {

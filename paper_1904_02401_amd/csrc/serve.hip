@@ -265,68 +265,57 @@ fsimg_status newton_group_step(fsimg_server *S, int dim, hipStream_t s) {
     }
   if (group.empty()) return FSIMG_OK;
   const auto t0 = std::chrono::steady_clock::now();
-  std::vector<fsimg_hier *> hs;
-  std::vector<const double *> bs;
-  std::vector<double *> xs;
-  std::vector<fsimg_stats> st;
-  std::vector<Req *> alive;
-  // momentum solves, batched per tolerance (the Newton option lin_rtol, else the
-  // hierarchy's own rtol)
-  std::vector<Req *> pending = group;
-  while (!pending.empty()) {
-    const double tol = pending[0]->nreq.newton.lin_rtol > 0.0 ? pending[0]->nreq.newton.lin_rtol
-                                                             : pending[0]->hm->opts.rtol;
-    std::vector<Req *> part, rest;
-    for (Req *q : pending) {
-      const double t = q->nreq.newton.lin_rtol > 0.0 ? q->nreq.newton.lin_rtol : q->hm->opts.rtol;
-      (t == tol ? part : rest).push_back(q);
-    }
-    hs.clear();
-    bs.clear();
-    xs.clear();
-    std::vector<double> keep;
-    for (Req *q : part) {
-      keep.push_back(q->hm->opts.rtol);
-      q->hm->opts.rtol = tol;
-      hs.push_back(q->hm);
-      bs.push_back(q->fsi->res);
-      xs.push_back(q->fsi->W);
-    }
-    st.assign(part.size(), fsimg_stats{});
-    fsimg_status r1 = solve_batch(S->ctx, (int)part.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
-    for (size_t g = 0; g < part.size(); ++g) part[g]->hm->opts.rtol = keep[g];
-    if (r1 != FSIMG_OK && r1 != FSIMG_ERR_NOCONV && r1 != FSIMG_ERR_NONFINITE) return r1;
-    for (size_t g = 0; g < part.size(); ++g) {
-      Req *q = part[g];
-      q->fsi->run.st.lin_iters_mom += st[g].iters;
-      if (st[g].status != FSIMG_OK) {
-        newton_fail(q->fsi, (fsimg_status)st[g].status);
-        continue;
+  // one batched solve per distinct tolerance (a batch shares its solver options):
+  // the request's Newton option when set, else the hierarchy's own rtol; done(q, st)
+  // takes each request's result
+  auto solve_grouped = [&](const std::vector<Req *> &reqs, bool ale, auto &&done) -> fsimg_status {
+    auto hier = [ale](Req *q) { return ale ? q->ha : q->hm; };
+    auto tol_of = [&](Req *q) {
+      const double t = ale ? q->nreq.newton.ale_rtol : q->nreq.newton.lin_rtol;
+      return t > 0.0 ? t : hier(q)->opts.rtol;
+    };
+    std::vector<Req *> pending = reqs;
+    while (!pending.empty()) {
+      const double tol = tol_of(pending[0]);
+      std::vector<Req *> part, rest;
+      for (Req *q : pending) (tol_of(q) == tol ? part : rest).push_back(q);
+      std::vector<fsimg_hier *> hs;
+      std::vector<const double *> bs;
+      std::vector<double *> xs;
+      std::vector<double> keep;
+      for (Req *q : part) {
+        keep.push_back(hier(q)->opts.rtol);
+        hier(q)->opts.rtol = tol;
+        hs.push_back(hier(q));
+        bs.push_back(ale ? q->fsi->b5 : q->fsi->res);
+        xs.push_back(ale ? q->fsi->du : q->fsi->W);
       }
-      newton_lift(q->fsi, s);
-      alive.push_back(q);
+      std::vector<fsimg_stats> st(part.size(), fsimg_stats{});
+      const fsimg_status r = solve_batch(S->ctx, (int)part.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
+      for (size_t g = 0; g < part.size(); ++g) hier(part[g])->opts.rtol = keep[g];
+      if (r != FSIMG_OK && r != FSIMG_ERR_NOCONV && r != FSIMG_ERR_NONFINITE) return r;
+      for (size_t g = 0; g < part.size(); ++g) done(part[g], st[g]);
+      pending.swap(rest);
     }
-    pending.swap(rest);
-  }
-  hs.clear();
-  bs.clear();
-  xs.clear();
-  for (Req *q : alive) {
-    hs.push_back(q->ha);
-    bs.push_back(q->fsi->b5);
-    xs.push_back(q->fsi->du);
-  }
-  if (!alive.empty()) {
-    st.assign(alive.size(), fsimg_stats{});
-    fsimg_status r2 = solve_batch(S->ctx, (int)alive.size(), hs.data(), bs.data(), xs.data(), st.data(), s);
-    if (r2 != FSIMG_OK && r2 != FSIMG_ERR_NOCONV && r2 != FSIMG_ERR_NONFINITE) return r2;
-  }
+    return FSIMG_OK;
+  };
+  std::vector<Req *> alive;
+  fsimg_status r1 = solve_grouped(group, false, [&](Req *q, const fsimg_stats &st) {
+    q->fsi->run.st.lin_iters_mom += st.iters;
+    if (st.status != FSIMG_OK) {
+      newton_fail(q->fsi, (fsimg_status)st.status);
+      return;
+    }
+    newton_lift(q->fsi, s);
+    alive.push_back(q);
+  });
+  if (r1 != FSIMG_OK) return r1;
+  fsimg_status r2 = solve_grouped(alive, true, [&](Req *q, const fsimg_stats &st) {
+    q->fsi->run.st.lin_iters_ale += st.iters;
+    if (st.status != FSIMG_OK) newton_fail(q->fsi, (fsimg_status)st.status);
+  });
+  if (r2 != FSIMG_OK) return r2;
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  for (size_t g = 0; g < alive.size(); ++g) {
-    Req *q = alive[g];
-    q->fsi->run.st.lin_iters_ale += st[g].iters;
-    if (st[g].status != FSIMG_OK) newton_fail(q->fsi, (fsimg_status)st[g].status);
-  }
   for (Req *q : group) {
     q->fsi->run.st.ms_solve += ms;
     newton_finish_step(q->fsi, s);
@@ -424,7 +413,7 @@ fsimg_status fsimg_server_submit_newton(fsimg_server *S, const fsimg_newton_requ
                                     "on the same mesh");
   const fsimg_newton_opts &o = r->newton;
   if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
-      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0))
+      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0) || !(o.ale_rtol >= 0.0 && o.ale_rtol < 1.0))
     return set_error(FSIMG_ERR_ARG, "bad Newton options");
   auto *q = new Req;
   q->id = S->next_id++;

@@ -93,7 +93,8 @@ class fsimg_fsi_level(ctypes.Structure):
 
 class fsimg_newton_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_steps", ctypes.c_int),
-                ("gamma", ctypes.c_double), ("max_halvings", ctypes.c_int), ("lin_rtol", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("max_halvings", ctypes.c_int), ("lin_rtol", ctypes.c_double),
+                ("ale_rtol", ctypes.c_double)]
 
 
 class fsimg_newton_stats(ctypes.Structure):

@@ -171,6 +171,43 @@ def test_time_steps_match_oracle_2d(ctx):
         S.close()
 
 
+def test_inexact_solves_reach_the_oracles_time_steps_2d(ctx):
+    """Momentum and ALE solves to 1e-4 inside the Newton loop (the paper's
+    error reduction per Newton step applied to both solves of the splitting):
+    three start-up steps of the 2D channel end, within the Newton tolerance,
+    at the oracle's states (exact linear solves)."""
+    k = 0.05
+    C = make_channel(2, 3, params=dict(k=k, theta=0.5 + 2 * k))
+    P = C.problem
+    lev = P.levels[0]
+    A, E = lev.systems["mom"], lev.systems["ale"]
+    M = Mesh(lev)
+    d, n = 2, lev.nnodes
+    xr, ur = np.zeros(n * (d + 1)), np.zeros(n * d)
+    X = torch.zeros(n * (d + 1), device=DEV, dtype=torch.float64)
+    U = torch.zeros(n * d, device=DEV, dtype=torch.float64)
+    Xo, Uo = X.clone(), U.clone()
+    rows, vals = _ti(C.inflow_rows), _t(C.inflow_vals)
+    opts = fsimg.fsimg_default_newton_opts(rtol=1e-10, atol=1e-10, max_steps=60, lin_rtol=1e-4, ale_rtol=1e-4)
+    S = Fsi(ctx, P)
+    jac = None
+    try:
+        with pytest.raises(fsimg.FsimgError, match="bad Newton options"):
+            fsimg.fsimg_fsi_newton(S.f, X, U, Xo, Uo, fsimg.fsimg_default_newton_opts(ale_rtol=1.0))
+        for s in range(1, 4):
+            scale = inflow_ramp(s * k)
+            xr, ur, _, _, info, jac = time_step(M, P.params, (A.rowptr, A.colind), A.dirichlet, to_csr(E),
+                                                E.dirichlet, xr, ur, C.inflow_rows, C.inflow_vals, scale,
+                                                jac=jac, rtol=1e-10, atol=1e-10, max_steps=30)
+            st = fsimg.fsimg_fsi_time_step(S.f, X, U, Xo, Uo, rows, vals, scale, opts)
+            assert st["status"] == fsimg.FSIMG_OK
+            x, u = X.cpu().numpy(), U.cpu().numpy()
+            assert np.abs(x - xr).max() <= 1e-6 * np.abs(xr).max(), s
+            assert np.abs(u - ur).max() <= 1e-6 * np.abs(ur).max(), s
+    finally:
+        S.close()
+
+
 def test_time_steps_3d_converge_to_the_oracles_residual(ctx):
     """Two start-up steps of the 3D channel (two levels, k = 0.05; block
     patches, momentum solves to 1e-4 inside the Newton loop): the oracle's

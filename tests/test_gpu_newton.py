@@ -352,16 +352,24 @@ def test_jacobian_on_a_general_block_pattern(ctx, probs):
         fsimg.fsimg_hier_destroy(mom)
 
 
-def test_served_newton_requests_equal_solo_runs(ctx, probs):
+@pytest.mark.parametrize("tolerances", ["same", "mixed"])
+def test_served_newton_requests_equal_solo_runs(ctx, probs, tolerances):
     """Three Newton requests (2D and 3D, different seeds) served together for
-    two time steps each, their momentum and ALE solves batched: every final
-    state is bitwise the one fsimg_fsi_newton gives the request alone over
-    the same two time steps, with the same Newton and Jacobian counts."""
+    two time steps each, their momentum and ALE solves batched (per distinct
+    tolerance when the requests ask for different momentum / ALE
+    tolerances): every final state is bitwise the one fsimg_fsi_newton gives
+    the request alone over the same two time steps, with the same Newton and
+    Jacobian counts."""
     Ps = [probs["t2"], config_problem("t2", seed=1), probs["t3"]]
     opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
-    nopts = fsimg.fsimg_default_newton_opts()
+    if tolerances == "same":
+        nall = [fsimg.fsimg_default_newton_opts()] * 3
+    else:
+        nall = [fsimg.fsimg_default_newton_opts(),
+                fsimg.fsimg_default_newton_opts(lin_rtol=1e-4, ale_rtol=1e-4, atol=1e-8, max_steps=40),
+                fsimg.fsimg_default_newton_opts(ale_rtol=1e-6, max_steps=40)]
     solo = []
-    for P in Ps:
+    for P, nopts in zip(Ps, nall):
         mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), opts)
         ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), opts)
         f = fsimg.fsimg_fsi_create(mom, ale, fsi_levels(P), P.params)
@@ -383,7 +391,7 @@ def test_served_newton_requests_equal_solo_runs(ctx, probs):
     try:
         datas = [fsimg.NewtonRequestData(level_dicts(P, "mom"), level_dicts(P, "ale"), fsi_levels(P),
                                          P.params, *fsi_state(P)) for P in Ps]
-        ids = [fsimg.fsimg_server_submit_newton(srv, dd, 2, nopts) for dd in datas]
+        ids = [fsimg.fsimg_server_submit_newton(srv, dd, 2, no) for dd, no in zip(datas, nall)]
         for _ in range(200):
             active, queued = fsimg.fsimg_server_step(srv)
             if active == 0 and queued == 0:
@@ -399,6 +407,7 @@ def test_served_newton_requests_equal_solo_runs(ctx, probs):
             assert acc["steps"] == sum(s["steps"] for s in sts)
             assert acc["jacobians"] == sum(s["jacobians"] for s in sts)
             assert acc["lin_iters_mom"] == sum(s["lin_iters_mom"] for s in sts)
+            assert acc["lin_iters_ale"] == sum(s["lin_iters_ale"] for s in sts)
     finally:
         fsimg.fsimg_server_destroy(srv)
 
