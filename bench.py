@@ -328,10 +328,11 @@ def run_channel(args):
         st = fsimg.fsimg_fsi_time_step(f, x, u, xo, uo, rows, vals, inflow_ramp(t), nopts,
                                        raise_on_noconv=False)
         F = fsimg.fsimg_fsi_force(f, x, u, xo, uo, nodes, d)
+        uB = u[C.probe_node * d:(C.probe_node + 1) * d].tolist()   # the beam's probe point
         log(f"t = {t:.4f}: status {st['status']}, {st['steps']} Newton steps, {st['jacobians']} Jacobians, "
             f"res {st['res0']:.3e} -> {st['res']:.3e}, {st['ms_total']:.0f} ms, drag {F[0]:.6e}, "
-            f"lift {F[1]:.6e}")
-        hist.append(dict(t=t, drag=F[0], lift=F[1], **{q: st[q] for q in (
+            f"lift {F[1]:.6e}, u_B {uB[0]:.3e} {uB[1]:.3e}")
+        hist.append(dict(t=t, drag=F[0], lift=F[1], u_B=uB, **{q: st[q] for q in (
             "status", "steps", "jacobians", "halvings", "lin_iters_mom", "lin_iters_ale", "ms_total")}))
         return st
 

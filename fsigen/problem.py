@@ -546,14 +546,17 @@ class Channel:
     """The benchmark channel: the problem (levels with momentum and ALE
     systems, rest state), the inflow rows of the Newton vector x with the
     unscaled inflow profile there, the nodes of the obstacle (the drag / lift
-    test function is one on them) and the beam's cross-section where it meets
-    the obstacle (area in 3D, length in 2D)."""
+    test function is one on them), the beam's cross-section where it meets
+    the obstacle (area in 3D, length in 2D) and the node at the point where
+    the paper reads the beam's displacement (Sec. 5: B = (0.9, 0.2, 0.3) on
+    the beam's back face; (0.9, 0.2) in 2D)."""
     problem: Problem
     inflow_rows: np.ndarray   # int64 indices into x (node * (d + 1) + 1)
     inflow_vals: np.ndarray   # float64 profile at those rows (ramp factor 1)
     force_nodes: np.ndarray   # int64 nodes touching obstacle cells
     root_area: float
     vbar: float
+    probe_node: int           # the node at the beam's probe point (0.9, 0.2[, 0.3])
 
 
 def inflow_profile(dim, y, z=None, vbar=1.0):
@@ -606,8 +609,13 @@ def make_channel(dim: int, nlev: int, params=None, coarse=None) -> Channel:
     force = np.nonzero(fine.node_rigid)[0].astype(np.int64)
     b = CHANNEL_BEAM
     area = (b[1][1] - b[0][1]) * ((b[1][2] - b[0][2]) if dim == 3 else 1.0)
+    probe = np.array([0.9, 0.2, 0.3][:dim])
+    dist = np.abs(X - probe).max(axis=1)
+    pn = int(np.argmin(dist))
+    if dist[pn] > 1e-12:
+        raise ValueError("the probe point is not a mesh node")
     return Channel(problem=P, inflow_rows=rows, inflow_vals=vals, force_nodes=force,
-                   root_area=area, vbar=vbar)
+                   root_area=area, vbar=vbar, probe_node=pn)
 
 
 def config_problem(name: str, seed: int = 0, **kw) -> Problem:

@@ -35,8 +35,8 @@ class Fsi:
     the element-patch multigrid needs a few hundred FGMRES iterations to
     1e-10, hence the larger iteration limit."""
 
-    def __init__(self, ctx, P, rtol=1e-10, max_iter=2000, **kw):
-        o = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_FP64, rtol=rtol, max_iter=max_iter, **kw)
+    def __init__(self, ctx, P, rtol=1e-10, max_iter=2000, precision=fsimg.FSIMG_FP64, **kw):
+        o = fsimg.fsimg_default_opts(precision=precision, rtol=rtol, max_iter=max_iter, **kw)
         self.mom = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
         self.ale = fsimg.fsimg_hier_create(ctx, level_dicts(P, "ale"), o)
         self.f = fsimg.fsimg_fsi_create(self.mom, self.ale, fsi_levels(P), P.params)
@@ -245,3 +245,50 @@ def test_time_steps_3d_converge_to_the_oracles_residual(ctx):
     finally:
         S.close()
     assert 0 < drags[0] < drags[1]
+
+
+def test_channel3_full_size_time_steps_match_oracle(ctx):
+    """The 3D channel at the size and in the configuration `bench.py --config
+    channel3` times (4 levels, 56 x 40 x 24 cells, mixed precision, block
+    patches, momentum and ALE solves to 1e-4, Newton stop at 1e-8 relative or
+    absolute): three start-up time steps; then the oracle, assembled over the
+    cells around sampled beam, interface and fluid nodes, finds its residual
+    within the Newton tolerance at those rows, and the oracle's force over
+    the cells around the obstacle equals the GPU's."""
+    from oracle.fsi import cells_of_nodes, element_subset
+    C = make_channel(3, 4)
+    P = C.problem
+    lev = P.levels[0]
+    d, n = 3, lev.nnodes
+    assert lev.cells == (56, 40, 24)
+    rng = np.random.default_rng(5)
+    ns, nf = lev.node_solid.astype(bool), lev.node_fluid.astype(bool)
+    nr = lev.node_rigid
+    nodes = np.concatenate([rng.choice(np.nonzero(ns & ~nf & ~nr)[0], 6, replace=False),
+                            rng.choice(np.nonzero(ns & nf & ~nr)[0], 6, replace=False),
+                            rng.choice(np.nonzero(nf & ~ns)[0], 12, replace=False)])
+    S = Fsi(ctx, P, rtol=1e-8, max_iter=1000, precision=fsimg.FSIMG_MIXED,
+            vanka_patches=fsimg.FSIMG_PATCH_BLOCK)
+    try:
+        X = torch.zeros(n * (d + 1), device=DEV, dtype=torch.float64)
+        U = torch.zeros(n * d, device=DEV, dtype=torch.float64)
+        Xo, Uo = X.clone(), U.clone()
+        rows, vals, fnodes = _ti(C.inflow_rows), _t(C.inflow_vals), _ti(C.force_nodes)
+        opts = fsimg.fsimg_default_newton_opts(lin_rtol=1e-4, ale_rtol=1e-4, atol=1e-8, max_steps=50)
+        k = P.params["k"]
+        for s in range(1, 4):
+            st = fsimg.fsimg_fsi_time_step(S.f, X, U, Xo, Uo, rows, vals, inflow_ramp(s * k), opts)
+            assert st["status"] == fsimg.FSIMG_OK
+        x, u, xo, uo = (t.cpu().numpy() for t in (X, U, Xo, Uo))
+        m0 = Mesh(lev)
+        sub = element_subset(m0, cells_of_nodes(m0, nodes))
+        R = newton_residual(sub, P.params, x, u, xo, uo, lev.systems["mom"].dirichlet)
+        rr = (nodes[:, None] * (d + 1) + np.arange(d + 1)).ravel()
+        assert np.abs(R[rr]).max() <= 2e-8, np.abs(R[rr]).max()
+        F = np.array(fsimg.fsimg_fsi_force(S.f, X, U, Xo, Uo, fnodes, d))
+        fsub = element_subset(m0, cells_of_nodes(m0, C.force_nodes))
+        Fr = force(fsub, P.params, x, u, xo, uo, C.force_nodes)
+        assert np.abs(F - Fr).max() <= 1e-10 * np.abs(Fr).max(), (F, Fr)
+        assert F[0] > 0
+    finally:
+        S.close()

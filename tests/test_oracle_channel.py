@@ -75,6 +75,18 @@ def test_inflow_profile_has_mean_vbar_and_vanishes_on_the_walls(dim):
     assert np.all(lev.systems["mom"].dirichlet[C.inflow_rows] == 1)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_probe_node_is_on_the_beams_back_face(dim):
+    C = make_channel(dim, 2)
+    lev = C.problem.levels[0]
+    X = _grid_coords(lev.coords, dim)
+    assert np.abs(X[C.probe_node] - np.array([0.9, 0.2, 0.3][:dim])).max() <= 1e-12
+    # on the interface: touches the beam and the fluid, its velocity is free
+    assert lev.node_solid[C.probe_node] and lev.node_fluid[C.probe_node]
+    assert not lev.node_rigid[C.probe_node]
+    assert np.all(lev.systems["mom"].dirichlet.reshape(-1, dim + 1)[C.probe_node, 1:] == 0)
+
+
 def test_ramp_definition():
     assert inflow_ramp(0.0) == 0.0
     assert abs(inflow_ramp(0.5) - 0.5) < 1e-15
