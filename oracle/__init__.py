@@ -6,7 +6,8 @@ Sec. 4.3), the block ILU(0) smoother (Sec. 5.5's comparison smoother), Q2 grid t
 flexible GMRES (Sec. 4.3 (I)), the condensed deformation update (Sec. 3.1,
 eq. problem:2), the ALE extension solve (eq. problem:3), and the approximate
 Newton loop around them (eq. newton: the condensed residual of eq. aletime:2,
-its Jacobian by the complex step, Jacobian reuse and line search).
+its Jacobian by the complex step, Jacobian reuse and line search), and the
+benchmark's time step and its drag / lift in residual form (Sec. 5).
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library; both receive
@@ -14,7 +15,8 @@ their inputs from the separate input generator ``fsigen``.
 
 Every function here is pinned by a ``-m "not gpu"`` test against something
 other than itself (closed forms, library routines, invariants); see
-``tests/test_oracle_pins.py``.
+``tests/test_oracle_pins.py``, ``tests/test_oracle_newton.py`` and
+``tests/test_oracle_channel.py``.
 """
 from .linalg import to_csr, matvec, masked_residual
 from .patches import element_patches, patch_dofs
