@@ -349,7 +349,8 @@ size_t level_bytes(const fsimg_level_desc &L, int64_t npatch, int64_t ngidx, boo
       s += (size_t)nblk * nlb * 4 + (size_t)nblk * npb * npc_for(npb, (int)ts) * ts +
            (size_t)nblk * npb * ts;
       if (npb > 128 || nlb > 27)
-        s += (size_t)nblk * npb * npb * 8 + (size_t)nblk * npb * (8 + 8 + 4) + (size_t)nblk * 8;
+        s += (size_t)nblk * npb * npb * 8 + (size_t)nblk * npb * (2 * kCoarseStage * 8 + 4 + 4) +
+             (size_t)nblk * 8;
     }
   } else {
     const int64_t nf = count_free(L);
@@ -820,9 +821,10 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
                                   hipMemcpyHostToDevice, s));
         if (B.np > 128 || B.nl > 27) {
           FSIMG_CHK(dalloc(h, &B.work, B.npatch * B.np * B.np));
-          FSIMG_CHK(dalloc(h, &B.rowk, B.npatch * B.np));
-          FSIMG_CHK(dalloc(h, &B.colk, B.npatch * B.np));
+          FSIMG_CHK(dalloc(h, &B.ub, B.npatch * kCoarseStage * B.np));
+          FSIMG_CHK(dalloc(h, &B.rb, B.npatch * kCoarseStage * B.np));
           FSIMG_CHK(dalloc(h, &B.piv, B.npatch * B.np));
+          FSIMG_CHK(dalloc(h, &B.iwork, B.npatch * B.np));
           FSIMG_CHK(dalloc(h, &B.amax, B.npatch));
         }
       }

@@ -43,10 +43,11 @@ struct PatchBlocks {
   double *inv64 = nullptr;              // [npatch*np*npc64]
   float *inv32 = nullptr;               // [npatch*np*npc32]
   int64_t yofs = 0;                     // offset in Y (entries): npatch * np of the element group
-  // batched Gauss-Jordan scratch of the factorisation when np > 128
+  // batched blocked Gauss-Jordan scratch of the factorisation when np > 128
   double *work = nullptr;               // [npatch*np*np]
-  double *rowk = nullptr, *colk = nullptr, *amax = nullptr;  // [npatch*np], [npatch*np], [npatch]
-  int *piv = nullptr;                   // [npatch*np]
+  double *ub = nullptr, *rb = nullptr;  // [npatch*kCoarseStage*np] panel updates, staged pivot rows
+  double *amax = nullptr;               // [npatch]
+  int *piv = nullptr, *iwork = nullptr; // [npatch*np]: pivot rows; used flags, then the inverse order
 };
 
 // One multigrid level on the device.  Vectors of the V-cycle exist in the

@@ -608,11 +608,11 @@ k_patch_factor_mfma(
 
 // -------------------------------------------------- large patches
 // Patches with more than 128 dofs (the 500-dof solid blocks of 3D) are
-// inverted by batched Gauss-Jordan with partial pivoting in FP64: A_i is
-// assembled into a per-patch n_p x n_p work matrix, then one pivot launch
-// and one update launch per column eliminate that column in every patch at
-// once, and the row interchanges are undone as column interchanges when
-// the inverse is written in the apply kernel's column-group-major layout.
+// inverted by Gauss-Jordan with partial pivoting in FP64: A_i is assembled
+// into a per-patch n_p x n_p work matrix, which the coarse level's blocked
+// exchange-form kernels (panels of 32 columns, below) factor for every patch
+// of a launch at once (batch index blockIdx.z); the inverse is then written
+// in the apply kernel's column-group-major layout.
 __global__ __launch_bounds__(256) void k_big_load(int64_t npatch, int b, int nl, int np,
                                                   const int32_t *__restrict__ pnodes,
                                                   const int32_t *__restrict__ rowptr,
@@ -643,96 +643,22 @@ __global__ __launch_bounds__(256) void k_big_load(int64_t npatch, int b, int nl,
   if (threadIdx.x == 0) amax[p] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-__global__ __launch_bounds__(256) void k_big_pivot(int64_t npatch, int np, int k,
-                                                   double *__restrict__ work, int *__restrict__ piv,
-                                                   double *__restrict__ rowk,
-                                                   double *__restrict__ colk,
-                                                   const double *__restrict__ amax,
-                                                   int *__restrict__ status) {
-  __shared__ double sb[4];
-  __shared__ int si[4];
-  __shared__ int s_p;
-  const int64_t p = blockIdx.x;
-  if (p >= npatch) return;
-  double *a = work + p * (int64_t)np * np;
-  double best = -1.0;
-  int bi = k;
-  for (int i = k + threadIdx.x; i < np; i += blockDim.x) {
-    const double v = fabs(a[(int64_t)i * np + k]);
-    if (v > best) { best = v; bi = i; }
-  }
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const double ob = __shfl_xor(best, o);
-    const int oi = __shfl_xor(bi, o);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) { sb[w] = best; si[w] = bi; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double bv = sb[0];
-    int bix = si[0];
-    for (int i = 1; i < (int)(blockDim.x / kWave); ++i)
-      if (sb[i] > bv || (sb[i] == bv && si[i] < bix)) { bv = sb[i]; bix = si[i]; }
-    s_p = bix;
-    piv[p * np + k] = bix;
-  }
-  __syncthreads();
-  const int pr = s_p;
-  if (pr != k)
-    for (int j = threadIdx.x; j < np; j += blockDim.x) {
-      const double t = a[(int64_t)k * np + j];
-      a[(int64_t)k * np + j] = a[(int64_t)pr * np + j];
-      a[(int64_t)pr * np + j] = t;
-    }
-  __syncthreads();
-  const double pv = a[(int64_t)k * np + k];
-  if (threadIdx.x == 0 && !(fabs(pv) > 1e-15 * amax[p])) {
-    atomicOr(&status[0], 1);
-    atomicMin(&status[1], (int)p);
-  }
-  for (int j = threadIdx.x; j < np; j += blockDim.x)
-    rowk[p * np + j] = (j == k ? 1.0 : a[(int64_t)k * np + j]) / pv;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) colk[p * np + i] = a[(int64_t)i * np + k];
-}
-
-__global__ __launch_bounds__(256) void k_big_update(int64_t npatch, int np, int k,
-                                                    double *__restrict__ work,
-                                                    const double *__restrict__ rowk,
-                                                    const double *__restrict__ colk) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= np) return;
-  for (int64_t p = blockIdx.z; p < npatch; p += gridDim.z) {
-    double *a = work + p * (int64_t)np * np;
-    const double *rk = rowk + p * np;
-    const int64_t o = (int64_t)i * np + j;
-    if (i == k) a[o] = rk[j];
-    else a[o] = (j == k ? 0.0 : a[o]) - colk[p * np + i] * rk[j];
-  }
-}
-
+// the inverse of patch blockIdx.x from its blocked Gauss-Jordan result
+// (coarse convention: A^{-1}[r][c] = a[rinv[r] np + piv[c]]), written in the
+// apply kernel's column-group-major layout with zero columns up to npc
 template <typename Tout>
-__global__ __launch_bounds__(256) void k_big_out(int np, int npc, const double *__restrict__ work,
+__global__ __launch_bounds__(256) void k_bgj_out(int np, int npc, const double *__restrict__ work,
                                                  const int *__restrict__ piv,
+                                                 const int *__restrict__ rinv,
                                                  Tout *__restrict__ inv) {
-  __shared__ int colmap[1024];
   const int64_t p = blockIdx.x;
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < npc; ++j) colmap[j] = j;
-    for (int k = np - 1; k >= 0; --k) {
-      const int t = colmap[k], q = piv[p * np + k];
-      colmap[k] = colmap[q];
-      colmap[q] = t;
-    }
-  }
-  __syncthreads();
   constexpr int G = 16 / sizeof(Tout);
   const double *a = work + p * (int64_t)np * np;
+  const int *pv = piv + p * np, *ri = rinv + p * np;
   Tout *out = inv + p * (int64_t)np * npc;
   for (int e = threadIdx.x; e < np * npc; e += blockDim.x) {
     const int r = e / npc, c = e - r * npc;
-    const double v = c < np ? a[(int64_t)r * np + colmap[c]] : 0.0;
+    const double v = c < np ? a[(int64_t)ri[r] * np + pv[c]] : 0.0;
     out[((int64_t)(c / G) * np + r) * G + (c % G)] = (Tout)v;
   }
 }
@@ -887,17 +813,30 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return mx(mx(readlane_u64(x, 0), readlane_u64(x, 16)), mx(readlane_u64(x, 32), readlane_u64(x, 48)));
 }
 
+// Batched use (many matrices of one size n, e.g. the large Vanka patches):
+// matrix z = blockIdx.z of a launch owns a[z n^2 ..], piv / used_g[z n ..],
+// ub / rb[z PB n ..]; with amax != nullptr its pivot threshold is
+// thr * amax[z] and a singular matrix reports its index zbase + z in
+// status[1] (else the first singular column).  A launch of depth 1 is the
+// single coarse matrix.
 template <int RPT, int PW>
 __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, double *__restrict__ a,
                                                     int *__restrict__ piv, int *__restrict__ used_g,
                                                     double *__restrict__ ub, double thr,
-                                                    int *__restrict__ status) {
+                                                    int *__restrict__ status,
+                                                    const double *__restrict__ amax, int zbase) {
   constexpr int PB = kCoarsePB, NSUB = PB / PW;
   __shared__ unsigned long long skey[2][16];
   __shared__ double srow[2][16][PW];
   __shared__ double rbs[PW][PW];
   __shared__ int ptv[PB];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int64_t z = blockIdx.z;
+  a += z * n * n;
+  piv += z * n;
+  used_g += z * n;
+  ub += z * (int64_t)PB * n;
+  if (amax) thr *= amax[z];
   const int64_t kend = min(k0 + (int64_t)PB, n);
   const int npb = (int)(kend - k0);
   int row[RPT];
@@ -1024,7 +963,7 @@ __global__ __launch_bounds__(1024) void k_cgj_panel(int64_t n, int64_t k0, doubl
     if (ok[s]) used_g[row[s]] = used[s] ? 1 : 0;
   if (t == 0 && singular) {
     atomicOr(&status[0], 1);
-    atomicMin(&status[1], sing_k);
+    atomicMin(&status[1], amax ? zbase + (int)z : sing_k);
   }
 }
 
@@ -1042,6 +981,11 @@ __global__ __launch_bounds__(256) void k_cgj_stage(int64_t n, int64_t k0, int np
   constexpr int PB = kCoarsePB, JW = 256 / PB, NSUB = PB / PW;
   __shared__ double ured[PB][PB + 1];
   __shared__ double rbl[PB][JW];
+  const int64_t z = blockIdx.z;
+  a += z * n * n;
+  piv += z * n;
+  ub += z * (int64_t)PB * n;
+  rb += z * (int64_t)PB * n;
   for (int idx = threadIdx.x; idx < PB * PB; idx += 256) {
     const int p = idx / PB, q = idx - p * PB;
     ured[p][q] = (p < npb && q < npb) ? ub[(int64_t)q * n + piv[k0 + p]] : 0.0;
@@ -1073,6 +1017,10 @@ __global__ __launch_bounds__(256) void k_cgj_update(int64_t n, int npb, double *
                                                     const double *__restrict__ rb) {
   constexpr int PB = kCoarsePB, TC = kCgjCols;
   __shared__ double rbs[TC][PB];
+  const int64_t z = blockIdx.z;
+  a += z * n * n;
+  ub += z * (int64_t)PB * n;
+  rb += z * (int64_t)PB * n;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.y * TC;
   for (int idx = threadIdx.x; idx < TC * PB; idx += 256) {
@@ -1107,12 +1055,13 @@ __global__ __launch_bounds__(256) void k_cgj_update(int64_t n, int npb, double *
 
 __global__ void k_cgj_zero(int64_t n, int *__restrict__ v) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) v[k] = 0;
+  if (k < n) v[(int64_t)blockIdx.z * n + k] = 0;
 }
 
 __global__ void k_cgj_rinv(int64_t n, const int *__restrict__ piv, int *__restrict__ rinv) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) rinv[piv[k]] = (int)k;
+  const int64_t z = (int64_t)blockIdx.z * n;
+  if (k < n) rinv[z + piv[z + k]] = (int)k;
 }
 
 // out[x][y] = A^{-1}[x][y] = M(r_y, rinv(x)) = a[rinv(x) n + r_y]
@@ -1258,15 +1207,28 @@ void factor_group(const DevLevel &L, int64_t npatch, int nl, int np, const int32
   if (big && big->work && np <= 1024) {
     hipLaunchKernelGGL(k_big_load, dim3((unsigned)npatch), dim3(256), 0, s, npatch, L.b, nl, np,
                        pnodes, L.rowptr, L.colind, L.vals64, big->work, big->amax);
-    for (int k = 0; k < np; ++k) {
-      hipLaunchKernelGGL(k_big_pivot, dim3((unsigned)npatch), dim3(256), 0, s, npatch, np, k,
-                         big->work, big->piv, big->rowk, big->colk, big->amax, status);
-      hipLaunchKernelGGL(k_big_update, dim3((unsigned)((np + 255) / 256), (unsigned)np,
-                                            (unsigned)std::min<int64_t>(npatch, 65535)),
-                         dim3(256), 0, s, npatch, np, k, big->work, big->rowk, big->colk);
+    constexpr int64_t kMaxZ = 65535;  // grid depth limit: patches per launch
+    const int64_t n = np;
+    for (int64_t c0 = 0; c0 < npatch; c0 += kMaxZ) {
+      const unsigned nz = (unsigned)std::min<int64_t>(kMaxZ, npatch - c0);
+      double *a = big->work + c0 * n * n;
+      int *pv = big->piv + c0 * n, *iw = big->iwork + c0 * n;
+      double *ub = big->ub + c0 * kCoarsePB * n, *rb = big->rb + c0 * kCoarsePB * n;
+      hipLaunchKernelGGL(k_cgj_zero, dim3((unsigned)grid_for(n, 256), 1, nz), dim3(256), 0, s, n, iw);
+      for (int64_t k0 = 0; k0 < n; k0 += kCoarsePB) {
+        const int npb = (int)std::min<int64_t>(kCoarsePB, n - k0);
+        hipLaunchKernelGGL((k_cgj_panel<1, 8>), dim3(1, 1, nz), dim3(1024), 0, s, n, k0, a, pv, iw, ub,
+                           1e-15, status, big->amax + c0, (int)c0);
+        hipLaunchKernelGGL((k_cgj_stage<8>), dim3((unsigned)grid_for(n, 8), 1, nz), dim3(256), 0, s, n, k0,
+                           npb, a, pv, ub, rb);
+        hipLaunchKernelGGL(k_cgj_update,
+                           dim3((unsigned)grid_for(n, 256), (unsigned)grid_for(n, kCgjCols), nz), dim3(256),
+                           0, s, n, npb, a, ub, rb);
+      }
+      hipLaunchKernelGGL(k_cgj_rinv, dim3((unsigned)grid_for(n, 256), 1, nz), dim3(256), 0, s, n, pv, iw);
+      hipLaunchKernelGGL((k_bgj_out<Tout>), dim3(nz), dim3(256), 0, s, np, npc, a, pv, iw,
+                         inv + c0 * n * npc);
     }
-    hipLaunchKernelGGL((k_big_out<Tout>), dim3((unsigned)npatch), dim3(256), 0, s, np, npc,
-                       big->work, big->piv, inv);
     return;
   }
   const size_t lds = patch_factor_lds_bytes(np);
@@ -1322,14 +1284,14 @@ bool launch_coarse_gj_blocked(int64_t n, double *a, int *piv, int *iwork, double
     // rows per thread 1 to 3: sub-panels of 8 columns; 4: of 4 (registers)
     if (rpt <= 3) {
       if (rpt == 1)
-        hipLaunchKernelGGL((k_cgj_panel<1, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+        hipLaunchKernelGGL((k_cgj_panel<1, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status, nullptr, 0);
       else if (rpt == 2)
-        hipLaunchKernelGGL((k_cgj_panel<2, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+        hipLaunchKernelGGL((k_cgj_panel<2, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status, nullptr, 0);
       else
-        hipLaunchKernelGGL((k_cgj_panel<3, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+        hipLaunchKernelGGL((k_cgj_panel<3, 8>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status, nullptr, 0);
       hipLaunchKernelGGL((k_cgj_stage<8>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
     } else {
-      hipLaunchKernelGGL((k_cgj_panel<4, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status);
+      hipLaunchKernelGGL((k_cgj_panel<4, 4>), dim3(1), dim3(1024), 0, s, n, k0, a, piv, iwork, ub, thr, status, nullptr, 0);
       hipLaunchKernelGGL((k_cgj_stage<4>), dim3(grid_for(n, 8)), dim3(256), 0, s, n, k0, npb, a, piv, ub, rb);
     }
     hipLaunchKernelGGL(k_cgj_update, dim3(grid_for(n, 256), (unsigned)grid_for(n, kCgjCols)),

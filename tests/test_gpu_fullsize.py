@@ -142,8 +142,11 @@ def test_c2_sampled_vanka_update(ctx, c2):
 
 def test_c2_sampled_block_vanka_update(ctx, c2):
     """Block patches at full size (128 solid blocks of 500 dofs, batched
-    Gauss-Jordan): at a node strictly inside a solid block the only patch is
-    the block, so the update is omega times the block's local solve."""
+    blocked Gauss-Jordan): at a node strictly inside a solid block the only
+    patch is the block, so the update is omega times the block's local solve.
+    These blocks have condition numbers near 6e9, so an inverse exact up to
+    rounding (any pivot order) is only determined to eps * kappa ~ 1e-6
+    relative; the bound asks for 1/100 of that."""
     from oracle.patches import block_patch_groups
     from oracle.vanka import local_matrices_nodes
     P = c2
@@ -180,7 +183,7 @@ def test_c2_sampled_block_vanka_update(ctx, c2):
                 if m.dirichlet[dof]:
                     continue
                 ref = x0[dof] + 0.8 * y[ln * b + c]
-                assert abs(xg[dof] - ref) <= 1e-10 * max(abs(ref - x0[dof]), 1e-30) + 1e-15
+                assert abs(xg[dof] - ref) <= 1e-8 * max(abs(ref - x0[dof]), 1e-30) + 1e-15
 
 
 def test_c3_mixed_solve(ctx):
