@@ -502,7 +502,7 @@ fsimg_status fsimg_fsi_force(fsimg_fsi *f, const double *x, const double *u, con
   if (!f->zero_mask) {
     NW_TRY(falloc(f, &f->zero_mask, (size_t)L.n));
     NW_TRY(falloc(f, &f->dforce, 3));
-    NW_HIP(hipMemset(f->zero_mask, 0, (size_t)L.n));
+    NW_HIP(hipMemsetAsync(f->zero_mask, 0, (size_t)L.n, s));
   }
   AsmLevel all = f->lev[0].dev;
   all.mask = f->zero_mask;
