@@ -90,6 +90,17 @@ void add_event_times(const hipEvent_t *ev, int ncolour, double *ms, int *count) 
   }
 }
 
+// the options in effect (defaults when opts is null), refused if out of range
+fsimg_status newton_options(const fsimg_newton_opts *opts, fsimg_newton_opts *o) {
+  fsimg_default_newton_opts(o);
+  if (opts) *o = *opts;
+  if (o->max_steps < 0 || o->max_halvings < 0 || !(o->rtol >= 0.0) || !(o->atol >= 0.0) ||
+      !(o->gamma >= 0.0) || !(o->lin_rtol >= 0.0 && o->lin_rtol < 1.0) ||
+      !(o->ale_rtol >= 0.0 && o->ale_rtol < 1.0))
+    return nfail(FSIMG_ERR_ARG, "bad Newton options");
+  return FSIMG_OK;
+}
+
 fsimg_status flags_status(const int *flags) {
   if (flags[1]) return nfail(FSIMG_ERR_ARG, "the momentum block pattern lacks an element coupling");
   if (flags[0]) return nfail(FSIMG_ERR_SINGULAR, "det F <= 0 at a Gauss point (inverted element)");
@@ -422,11 +433,7 @@ fsimg_status fsimg_fsi_newton(fsimg_fsi *f, double *x, double *u, const double *
   if (!f || !x || !u || !x_old || !u_old) return nfail(FSIMG_ERR_ARG, "null argument");
   if (!f->ale) return nfail(FSIMG_ERR_ARG, "the Newton loop needs an ALE hierarchy");
   fsimg_newton_opts o;
-  fsimg_default_newton_opts(&o);
-  if (opts) o = *opts;
-  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
-      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0) || !(o.ale_rtol >= 0.0 && o.ale_rtol < 1.0))
-    return nfail(FSIMG_ERR_ARG, "bad Newton options");
+  NW_TRY(newton_options(opts, &o));
   NW_HIP(hipSetDevice(f->mom->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   NewtonRun &R = f->run;
@@ -473,6 +480,8 @@ fsimg_status fsimg_fsi_time_step(fsimg_fsi *f, double *x, double *u, double *x_o
   if (n_rows < 0 || (n_rows > 0 && (!rows || !vals))) return nfail(FSIMG_ERR_ARG, "bad held-row list");
   if (!f->ale) return nfail(FSIMG_ERR_ARG, "the Newton loop needs an ALE hierarchy");
   if (x == x_old || u == u_old) return nfail(FSIMG_ERR_ARG, "the old level needs buffers of its own");
+  fsimg_newton_opts o;
+  NW_TRY(newton_options(opts, &o));  // before anything is written
   NW_HIP(hipSetDevice(f->mom->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevLevel &L = f->mom->lev[0];
