@@ -192,7 +192,11 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [step() for _ in range(steps)]
+    stats, lat = [], []
+    for _ in range(steps):
+        ts = time.perf_counter()
+        stats.append(step())  # every solve returns to the host when it has converged
+        lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
     # per-kernel timing with HIP events on the launch stream, over one more
@@ -209,7 +213,9 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     opts_prof(hs["mom"], 0)
     info_m = fsimg.fsimg_hier_info(hs["mom"], 0)
     res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, t_tune=t_tune, shapes=shapes,
-               stats=stats[-1], prof=prof, factor_ms=factor_ms,
+               stats=stats[-1], prof=prof, factor_ms=factor_ms, lat=lat,
+               solve_ms={k: [st[j]["solve_ms"] for st in stats if st[j] is not None]
+                         for j, k in enumerate(("mom", "mass", "ale"))},
                info_m=info_m, x_mom=x_mom.cpu().numpy(), x_ale=x_ale.cpu().numpy())
     for h in hs.values():
         fsimg.fsimg_hier_destroy(h)
@@ -514,40 +520,189 @@ def cpu_assembly_baseline(P, n_elems=1024):
                       f"level ({dt:.1f} s); GPU: the same per cell in assembly_elements_per_s"}
 
 
-def cpu_baseline(P, iters_gpu, budget_s=20.0):
-    """The FP64 oracle on the host: FGMRES iterations on the momentum system of
-    the same workload for about budget_s seconds (setup untimed); the
-    per-iteration time scaled by the GPU's iteration count gives the oracle's
-    momentum DoF/s."""
-    import numpy as np
-    from oracle.fgmres import fgmres
-    from oracle.mg import Hierarchy, vcycle
+def _median_time(fn, reps=3):
+    """median wall time of fn() over reps calls"""
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
 
-    t0 = time.perf_counter()
+
+def _oracle_setup(P, name, chunk=(2048, 4096), slab_rows=65536):
+    """The untimed inputs of the oracle's sampled operations on system `name`
+    (see _oracle_costs): per smoothing level a slab of block rows as scipy
+    CSR, the oracle's VankaData of the first chunk[-1] patches (LAPACK
+    inverses) with the level's averaging weights, the prolongation; the
+    coarsest level's LU factors; a diagonal operator of the finest size."""
+    import numpy as np
+    import scipy.linalg as sla
+    import scipy.sparse as sp
+    from oracle import prolongation, to_csr
+    from oracle.patches import patch_dofs
+    from oracle.vanka import VankaData, local_matrices
+
+    mats = P.system(name)
     cells = [lv.cells for lv in P.levels]
-    H = Hierarchy(P.system("mom"), cells, omega=0.8, weighting="mult")
+    rng = np.random.default_rng(0)
+    levels = []
+    for l in range(len(mats) - 1):
+        m = mats[l]
+        n = m.nrows * m.b
+        r1 = min(m.nrows, slab_rows)
+        rp = m.rowptr[:r1 + 1].astype(np.int64)
+        slab = sp.bsr_matrix((np.asarray(m.vals[:rp[-1]], dtype=np.float64).reshape(-1, m.b, m.b),
+                              m.colind[:rp[-1]], rp), shape=(r1 * m.b, n)).tocsr()
+        npatch = int(np.prod(cells[l]))
+        dofs_all = patch_dofs(cells[l], m.b)
+        scale = 1.0 / np.maximum(np.bincount(dofs_all.ravel(), minlength=n), 1.0)
+        c = min(chunk[-1], npatch)
+        idx = np.arange(c)
+        V = VankaData(dofs=dofs_all[idx], inv=np.linalg.inv(local_matrices(m, cells[l], idx)),
+                      scale=scale, omega=0.8)
+        levels.append(dict(slab=slab, slab_frac=m.nnzb / max(int(rp[-1]), 1), V=V, npatch=npatch,
+                           mask=m.dirichlet.astype(bool), x=rng.standard_normal(n),
+                           Pm=prolongation(tuple(cells[l + 1]), m.b)))
+    mc = mats[-1]
+    m0 = mats[0]
+    n0 = m0.nrows * m0.b
+    return dict(levels=levels, chunk=chunk, lu=sla.lu_factor(to_csr(mc).toarray()),
+                rc=rng.standard_normal(mc.nrows * mc.b), D=sp.diags(1.0 + rng.random(n0)).tocsr(),
+                b=rng.standard_normal(n0), mask0=m0.dirichlet.astype(bool), n0=n0)
+
+
+def _oracle_costs(S):
+    """Wall time of the FP64 oracle's operations on one system of the
+    workload, each timed on the bounded sample of _oracle_setup and scaled to
+    the whole level:
+      spmv[l]   the oracle's residual product A_l @ x (scipy CSR) on the slab
+                of block rows, scaled by nonzero blocks;
+      vanka[l]  oracle.vanka_sweep with the residual given (local solves with
+                the stored inverses, scatter, update) on two patch counts: the
+                slope per patch times the level's patches plus the per-call part;
+      R[l], Pr[l]  the oracle's restriction P^T d and prolongation P x (full);
+      vec[l]    one whole-vector NumPy pass (x - x) of the level's length;
+      coarse    scipy lu_solve of the coarsest level;
+      krylov(k) the oracle's FGMRES(20) itself for k iterations on vectors of
+                the finest size with a diagonal operator and the identity
+                preconditioner (its Gram-Schmidt, rotations, update and true
+                residuals), minus those diagonal products."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle.fgmres import fgmres
+    from oracle.vanka import VankaData, vanka_sweep
+
+    out = {"spmv": [], "vanka": [], "R": [], "Pr": [], "vec": []}
+    for lv in S["levels"]:
+        x = lv["x"]
+        out["spmv"].append(_median_time(lambda: lv["slab"] @ x) * lv["slab_frac"])
+        out["vec"].append(_median_time(lambda: x - x))
+        V = lv["V"]
+        n = x.shape[0]
+        z = np.zeros(n)
+        ts, cs = [], []
+        for c in S["chunk"]:
+            c = min(c, V.dofs.shape[0])
+            Vc = VankaData(dofs=V.dofs[:c], inv=V.inv[:c], scale=V.scale, omega=V.omega)
+            ts.append(_median_time(lambda: vanka_sweep(None, x, z, Vc, lv["mask"], d=x)))
+            cs.append(c)
+        if cs[-1] > cs[0]:
+            slope = max((ts[-1] - ts[0]) / (cs[-1] - cs[0]), 0.0)
+            out["vanka"].append(max(ts[0] - slope * cs[0], 0.0) + slope * lv["npatch"])
+        else:
+            out["vanka"].append(ts[-1] * lv["npatch"] / cs[-1])
+        Pm = lv["Pm"]
+        xc = x[:Pm.shape[1]]
+        out["R"].append(_median_time(lambda: Pm.T @ x))
+        out["Pr"].append(_median_time(lambda: Pm @ xc))
+    out["coarse"] = _median_time(lambda: sla.lu_solve(S["lu"], S["rc"]))
+    out["spmv0"] = out["spmv"][0]
+    D, b, n0 = S["D"], S["b"], S["n0"]
+    t_diag = _median_time(lambda: D @ b)
+
+    def krylov(k):
+        t0 = time.perf_counter()
+        fgmres(D, b, np.zeros(n0), lambda v: v.copy(), S["mask0"], rtol=1e-300, maxiter=k, restart=20)
+        return max(time.perf_counter() - t0 - (k + 2) * t_diag, 0.0)
+    out["krylov"] = krylov
+    return out
+
+
+def _oracle_solve_time(c, iters, nu=(2, 2)):
+    """Oracle time of one FGMRES(20) + V-cycle solve with `iters` iterations
+    from the per-operation costs c: every iteration runs the V-cycle (per
+    smoothing level nu_pre + nu_post Vanka steps, the first with the residual
+    given, one residual product per later step and one before the
+    restriction, restriction, prolongation, and the cycle's whole-vector
+    passes: copy and mask of r, x = 0, the residual subtractions and masks,
+    x + P x_c and its mask; the coarse LU solve) and one finest-level product
+    A z; the Krylov part is timed as a whole."""
+    nu1, nu2 = nu
+    vc = c["coarse"]
+    for l in range(len(c["spmv"])):
+        nres = nu1 - 1 + 1 + nu2
+        vc += ((nu1 + nu2) * c["vanka"][l] + nres * c["spmv"][l] + c["R"][l] + c["Pr"][l]
+               + (5 + 2 * nres) * c["vec"][l])
+    return iters * (vc + c["spmv0"]) + c["krylov"](iters) + 2 * c["spmv0"]
+
+
+def cpu_baseline(P, iters, n_value):
+    """The FP64 oracle timed on the host on a bounded sample of the same
+    Newton-step workload (momentum, deformation mass and ALE solves with the
+    GPU's iteration counts), once with every host core available to its
+    BLAS / LAPACK and once limited to one thread; value = the unknowns of the
+    GPU figure / the oracle's step time."""
+    import platform
+    import threadpoolctl
+
+    systems = [(name, key) for name, key in (("mom", "momentum_iters"), ("mass", "mass_iters"),
+                                             ("ale", "ale_iters")) if iters.get(key) is not None]
+    t0 = time.perf_counter()
+    setup = {name: _oracle_setup(P, name) for name, _ in systems}
     t_setup = time.perf_counter() - t0
-    log(f"oracle hierarchy built in {t_setup:.0f} s")
-    lev = H.levels[0]
-    b = P.rhs["mom"]
-    # one iteration first to size the sample
-    w0, c0 = time.perf_counter(), time.process_time()
-    fgmres(lev.A, b, np.zeros_like(b), lambda v: vcycle(H, v), lev.mask, rtol=1e-30, maxiter=1)
-    t1 = time.perf_counter() - w0
-    n_it = max(1, min(20, int(budget_s / max(t1, 1e-3))))
-    w0, c0 = time.perf_counter(), time.process_time()
-    fgmres(lev.A, b, np.zeros_like(b), lambda v: vcycle(H, v), lev.mask, rtol=1e-30, maxiter=n_it,
-           restart=20)
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
-    t_it = wall / n_it
-    n = b.shape[0]
-    return dict(value=n / (t_it * iters_gpu), unit="DoF/s", cores=round(cpu / wall, 1),
-                kind="oracle",
-                sample=(f"{n_it} FGMRES(20)+V-cycle iterations of the momentum system ({n} unknowns), "
-                        f"{wall:.1f} s wall; DoF/s = unknowns / (s per iteration x {iters_gpu} "
-                        f"iterations the GPU solve took); host {os.cpu_count()} cpus; oracle setup "
-                        f"{t_setup:.0f} s untimed"))
+
+    def model():
+        t_w, t_c = time.perf_counter(), time.process_time()
+        total = 0.0
+        parts = {}
+        for name, key in systems:
+            t = _oracle_solve_time(_oracle_costs(setup[name]), iters[key])
+            parts[name] = t
+            total += t
+        wall = time.perf_counter() - t_w
+        cpu = time.process_time() - t_c
+        return total, parts, wall, cpu
+
+    model_name = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model_name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    res = {}
+    total, parts, wall, cpu = model()
+    res["all"] = (total, parts, wall, cpu)
+    with threadpoolctl.threadpool_limits(1):
+        res["one"] = model()
+    t_all, parts_all, wall_all, cpu_all = res["all"]
+    t_one, parts_one, wall_one, _ = res["one"]
+    return dict(
+        value=n_value / t_all, unit="DoF/s", cores=round(cpu_all / wall_all, 1), kind="oracle",
+        value_1thread=n_value / t_one,
+        step_s=t_all, step_s_1thread=t_one,
+        solve_s={k: round(v, 3) for k, v in parts_all.items()},
+        host={"cpus": os.cpu_count(), "model": model_name or platform.processor()},
+        sample=(f"the oracle's operations on the same workload, each timed on a bounded sample "
+                f"and scaled to its level: residual products on slabs of <= 65536 block rows, "
+                f"Vanka steps on 2048 and 4096 patches (per-patch slope), full restriction / "
+                f"prolongation, the coarse LU solve, and the oracle's FGMRES(20) on finest-size "
+                f"vectors; composed with the GPU step's iteration counts "
+                f"{ {k: iters.get(k) for k in ('momentum_iters', 'mass_iters', 'ale_iters')} } "
+                f"(V-cycle 2/2); {wall_all:.0f} s wall (all cores), {wall_one:.0f} s (1 thread), "
+                f"sample set-up {t_setup:.0f} s untimed"))
 
 
 def run_batched(args):
@@ -809,9 +964,9 @@ def run_serving(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c3")
     ap.add_argument("--mu", type=float, default=None, help="solid shear modulus override")
     ap.add_argument("--lam", type=float, default=None, help="solid Lame lambda override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -974,6 +1129,18 @@ def main():
                 "frac": tf / FP64_MFMA_PEAK_TFLOPS, "flops_per_launch": flops, "avg_launch_ms": ms,
                 "launches": len(R["factor_ms"]), "patches": info["npatch"], "n_p": info["np"]}
 
+    def latency(R):
+        """p50 / p99 over the timed steps: the whole Newton-step solve
+        (momentum, deformation update, mass and ALE solves) and each solve"""
+        def pct(v):
+            v = np.asarray(v, dtype=np.float64)
+            return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)),
+                    "max": float(v.max()), "n": int(v.size)} if v.size else None
+        out = {"step": pct([t * 1e3 for t in R["lat"]])}
+        for k, v in R["solve_ms"].items():
+            out[f"{k}_solve"] = pct(v)
+        return out
+
     main_tag = precs[0][0]
     R = runs[main_tag]
     kr = kernel_rates(R, main_tag)
@@ -1012,6 +1179,7 @@ def main():
                      "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"]},
         "kernels": kr,
         "patch_factor": factor_rate(R, main_tag),
+        "latency_ms": latency(R),
         "solve": {"momentum_converged": R["stats"][0]["status"] == fsimg.FSIMG_OK,
                   "momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
@@ -1022,6 +1190,7 @@ def main():
     if "fp64" in runs and main_tag != "fp64":
         F = runs["fp64"]
         out["fp64"] = {"value": (n_mom + n_ale) / F["t_step"], "ms_per_step": F["t_step"] * 1e3,
+                       "latency_ms": latency(F),
                        "momentum_iters": F["stats"][0]["iters"], "ale_iters": F["stats"][2]["iters"],
                        "rel_res_momentum_fp64_host": F["rel_res_host"],
                        "kernels": kernel_rates(F, "fp64")}
@@ -1029,7 +1198,7 @@ def main():
         out["mixed_rel_err_vs_fp64"] = _split_err(R["x_mom"], F["x_mom"], P.dim + 1)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(P, R["stats"][0]["iters"])
+        out["cpu_baseline"] = cpu_baseline(P, out["solve"], n_mom + n_ale)
     log(f"peak host RSS {resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6:.1f} GB")
     print(json.dumps(out), flush=True)
 

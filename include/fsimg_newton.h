@@ -141,8 +141,9 @@ fsimg_status fsimg_fsi_drop_jacobian(fsimg_fsi *f);
    e.g. the inflow profile times the start-up factor), then runs
    fsimg_fsi_newton from the previous state.  rows and vals are device arrays
    of n_rows entries (n_rows may be 0); every row must be a held (identity)
-   row of the momentum system, else ERR_ARG (x_old and u_old then hold the
-   state, and x may be partly written).
+   row of the momentum system, else ERR_ARG; the list is checked before
+   anything is written, so a refused call leaves x, u, x_old and u_old as
+   they were.
    The Jacobian held by the object carries over from the previous step. */
 fsimg_status fsimg_fsi_time_step(fsimg_fsi *f, double *x, double *u, double *x_old, double *u_old,
                                  const int64_t *rows, const double *vals, int64_t n_rows, double scale,

@@ -1270,6 +1270,8 @@ fsimg_status fsimg_deform_update(int64_t nnodes, int dim, const uint8_t *mask, d
 }
 
 // ------------------------------------------------------- single steps
+static bool batched_steps(const fsimg_hier *h, int precision);
+
 fsimg_status fsimg_level_apply(fsimg_hier *h, int level, int precision, const void *x, void *y,
                                void *stream) {
   FSIMG_TRY(check_level(h, level, true));
@@ -1291,6 +1293,8 @@ fsimg_status fsimg_level_residual(fsimg_hier *h, int level, int precision, const
   FSIMG_TRY(check_level(h, level, true));
   if (!x || !b || !d) return fail(FSIMG_ERR_ARG, "null vector");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (level + 1 < (int)h->lev.size() && batched_steps(h, precision))
+    return single_step(h, ONE_RESIDUAL, level, b, x, d, s);
   DevLevel &L = h->lev[level];
   if (precision == FSIMG_FP64) {
     launch_bsr_spmv<double>(L, L.vals64, (const double *)x, (const double *)b, (double *)d, true, s);
@@ -1300,6 +1304,13 @@ fsimg_status fsimg_level_residual(fsimg_hier *h, int level, int precision, const
   }
   FSIMG_HIP(hipGetLastError());
   return FSIMG_OK;
+}
+
+// hierarchies whose solve runs the batched kernels (GATHER schedule, Vanka
+// smoother): their single steps run the same kernels, with one instance
+static bool batched_steps(const fsimg_hier *h, int precision) {
+  return h->opts.vanka_schedule == FSIMG_VANKA_GATHER && h->opts.smoother == FSIMG_SMOOTHER_VANKA &&
+         (precision == FSIMG_MIXED) == hier_mixed(h);
 }
 
 static fsimg_status check_prec(const fsimg_hier *h, int precision) {
@@ -1317,6 +1328,7 @@ fsimg_status fsimg_vanka_step(fsimg_hier *h, int level, int precision, const voi
     return fail(FSIMG_ERR_STATE, "the hierarchy uses the ILU smoother");
   if (!b || !x) return fail(FSIMG_ERR_ARG, "null vector");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batched_steps(h, precision)) return single_step(h, ONE_VANKA, level, b, nullptr, x, s);
   if (precision == FSIMG_FP64) {
     residual<double>(h, level, (const double *)b, (const double *)x, h->lev[level].d64, s);
     vanka_apply<double>(h, level, h->lev[level].d64, (double *)x, false, s);
@@ -1365,6 +1377,7 @@ fsimg_status fsimg_restrict(fsimg_hier *h, int level, int precision, const void 
   FSIMG_TRY(check_level(h, level, false));
   if (!rf || !rc) return fail(FSIMG_ERR_ARG, "null vector");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batched_steps(h, precision)) return single_step(h, ONE_RESTRICT, level, rf, nullptr, rc, s);
   if (precision == FSIMG_FP64)
     launch_restrict<double>(h->lev[level], h->lev[level + 1], (const double *)rf, (double *)rc, s);
   else
@@ -1378,6 +1391,7 @@ fsimg_status fsimg_prolong_add(fsimg_hier *h, int level, int precision, const vo
   FSIMG_TRY(check_level(h, level, false));
   if (!xc || !xf) return fail(FSIMG_ERR_ARG, "null vector");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batched_steps(h, precision)) return single_step(h, ONE_PROLONG, level, xc, nullptr, xf, s);
   if (precision == FSIMG_FP64)
     launch_prolong_add<double>(h->lev[level], h->lev[level + 1], (const double *)xc, (double *)xf, s);
   else
@@ -1389,6 +1403,9 @@ fsimg_status fsimg_prolong_add(fsimg_hier *h, int level, int precision, const vo
 fsimg_status fsimg_coarse_solve(fsimg_hier *h, const double *r, double *x, void *stream) {
   if (!h || !r || !x) return fail(FSIMG_ERR_ARG, "null argument");
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
+  if (batched_steps(h, FSIMG_FP64))
+    return single_step(h, ONE_COARSE, (int)h->lev.size() - 1, r, nullptr, x,
+                       static_cast<hipStream_t>(stream));
   coarse_solve64(h, r, x, static_cast<hipStream_t>(stream));
   FSIMG_HIP(hipGetLastError());
   return FSIMG_OK;
@@ -1399,6 +1416,7 @@ fsimg_status fsimg_vcycle(fsimg_hier *h, int precision, const void *r, void *z, 
   FSIMG_TRY(check_prec(h, precision));
   if (!h->factored) return fail(FSIMG_ERR_STATE, "fsimg_factor must run first");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batched_steps(h, precision)) return single_step(h, ONE_VCYCLE, 0, r, nullptr, z, s);
   if (precision == FSIMG_FP64) vcycle<double>(h, 0, (const double *)r, (double *)z, s);
   else vcycle<float>(h, 0, (const float *)r, (float *)z, s);
   FSIMG_HIP(hipGetLastError());

@@ -420,6 +420,32 @@ struct InstState {
   std::vector<double> H, cs, sn, g, y;
 };
 
+// the cached descriptor tables of this batch composition (built on first
+// use), moved to the front of the context's LRU list
+fsimg_status acquire_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan **out) {
+  BatchPlan *P = nullptr;
+  for (size_t c = 0; c < ctx->plans.size() && !P; ++c) {
+    BatchPlan *q = ctx->plans[c];
+    bool same = (int)q->key.size() == n;
+    for (int i = 0; same && i < n; ++i) same = q->key[i] == hs[i]->uid;
+    if (same) {
+      P = q;
+      ctx->plans.erase(ctx->plans.begin() + (long)c);
+    }
+  }
+  if (!P) {
+    while (ctx->plans.size() >= kPlanCache) {  // least recently used first
+      destroy_plan(ctx->plans.back());
+      ctx->plans.pop_back();
+    }
+    fsimg_status st = build_plan(ctx, n, hs, &P);
+    if (st != FSIMG_OK) return st;
+  }
+  ctx->plans.insert(ctx->plans.begin(), P);  // most recent first
+  *out = P;
+  return FSIMG_OK;
+}
+
 }  // namespace
 
 fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
@@ -442,24 +468,10 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
   }
   const auto t0 = std::chrono::steady_clock::now();
   BatchPlan *P = nullptr;
-  for (size_t c = 0; c < ctx->plans.size() && !P; ++c) {
-    BatchPlan *q = ctx->plans[c];
-    bool same = (int)q->key.size() == n;
-    for (int i = 0; same && i < n; ++i) same = q->key[i] == hs[i]->uid;
-    if (same) {
-      P = q;
-      ctx->plans.erase(ctx->plans.begin() + (long)c);
-    }
-  }
-  if (!P) {
-    while (ctx->plans.size() >= kPlanCache) {  // least recently used first
-      destroy_plan(ctx->plans.back());
-      ctx->plans.pop_back();
-    }
-    fsimg_status st = build_plan(ctx, n, hs, &P);
+  {
+    fsimg_status st = acquire_plan(ctx, n, hs, &P);
     if (st != FSIMG_OK) return st;
   }
-  ctx->plans.insert(ctx->plans.begin(), P);  // most recent first
   const bool prof = o.profile != 0;
   const bool use_graph = o.graphs != 0 && !prof;
   P->tv.begin_solve();
@@ -639,6 +651,88 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
   if (ret == FSIMG_ERR_NOCONV) return set_error(ret, "an instance reached max_iter without converging");
   if (ret == FSIMG_ERR_NONFINITE) return set_error(ret, "non-finite residual in an instance");
   return ret;
+}
+
+
+// ------------------------------------------------- one hierarchy, one step
+namespace {
+template <typename T> struct HV;
+template <> struct HV<double> {
+  static double *r(DevLevel &L) { return L.r64; }
+  static double *x(DevLevel &L) { return L.x64; }
+  static double *d(DevLevel &L) { return L.d64; }
+};
+template <> struct HV<float> {
+  static float *r(DevLevel &L) { return L.r32; }
+  static float *x(DevLevel &L) { return L.x32; }
+  static float *d(DevLevel &L) { return L.d32; }
+};
+
+template <typename T>
+fsimg_status single_step_t(fsimg_hier *h, int op, int l, const void *a, const void *b, void *out,
+                           hipStream_t s) {
+  BatchPlan *P = nullptr;
+  fsimg_status st = acquire_plan(h->ctx, 1, &h, &P);
+  if (st != FSIMG_OK) return st;
+  launch_b_activate(P->active, 1, s);
+  const fsimg_opts &o = h->opts;
+  const DLev *dl = P->dlev + l;  // one instance: one descriptor per level
+  DevLevel &F = h->lev[l];
+  hipError_t e = hipSuccess;
+  auto cp = [&](void *dst, const void *src, int64_t n) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, s);
+  };
+  switch (op) {
+    case ONE_RESIDUAL:  // out = a - A_l b
+      cp(HV<T>::r(F), a, F.n);
+      cp(HV<T>::x(F), b, F.n);
+      launch_b_spmv<T>(P->b, BS_VCYCLE, P->rpw[l], dl, P->dkry, P->active, P->ws_spmv[l], 0, s);
+      cp(out, HV<T>::d(F), F.n);
+      break;
+    case ONE_VANKA:  // out += Vanka correction of the residual a - A_l out
+      cp(HV<T>::r(F), a, F.n);
+      cp(HV<T>::x(F), out, F.n);
+      launch_b_spmv<T>(P->b, BS_VCYCLE, P->rpw[l], dl, P->dkry, P->active, P->ws_spmv[l], 0, s);
+      launch_b_vanka_blocks<T>(P->np2, P->b, P->nl2, P->npc2, P->ppw2[l], false, dl, P->active,
+                               P->ws_patch2[l], s);
+      launch_b_vanka<T>(P->np, P->b, P->nl, P->npc, P->ppw[l], (T)o.omega, false, false, dl, P->active,
+                        P->ws_patch[l], P->ws_gather[l], s, nullptr, nullptr);
+      cp(out, HV<T>::x(F), F.n);
+      break;
+    case ONE_RESTRICT:  // out = R a (level l -> l + 1)
+      cp(HV<T>::d(F), a, F.n);
+      launch_b_restrict<T>(P->b, P->dim, dl, dl + 1, P->active, P->ws_restrict[l], s);
+      cp(out, HV<T>::r(h->lev[l + 1]), h->lev[l + 1].n);
+      break;
+    case ONE_PROLONG:  // out += P a (level l + 1 -> l)
+      cp(HV<T>::x(h->lev[l + 1]), a, h->lev[l + 1].n);
+      cp(HV<T>::x(F), out, F.n);
+      launch_b_prolong<T>(P->b, P->dim, dl, dl + 1, P->active, P->ws_prolong[l], s);
+      cp(out, HV<T>::x(F), F.n);
+      break;
+    case ONE_COARSE:  // out = A_{L-1}^{-1} a (FP64 hierarchies)
+      cp(HV<T>::r(F), a, F.n);
+      launch_b_coarse<T>(dl, P->active, P->ws_cn[l], P->ws_cf[l], s);
+      cp(out, HV<T>::x(F), F.n);
+      break;
+    case ONE_VCYCLE:  // out = V-cycle(a) on level 0
+      cp(HV<T>::r(F), a, F.n);
+      vcycle_batch<T>(*P, o, s, false);
+      cp(out, HV<T>::x(F), F.n);
+      break;
+    default:
+      return set_error(FSIMG_ERR_ARG, "unknown single-step operation");
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return set_error(FSIMG_ERR_HIP, std::string("single step: ") + hipGetErrorString(e));
+  return FSIMG_OK;
+}
+}  // namespace
+
+fsimg_status single_step(fsimg_hier *h, int op, int level, const void *a, const void *b, void *out,
+                         hipStream_t s) {
+  if (h->opts.precision == FSIMG_MIXED) return single_step_t<float>(h, op, level, a, b, out, s);
+  return single_step_t<double>(h, op, level, a, b, out, s);
 }
 
 }  // namespace fsimg

@@ -373,6 +373,11 @@ __global__ __launch_bounds__(256) void kb_nonfinite(const DKry *__restrict__ kry
   if (k < K.n && !isfinite(K.w[k])) atomicOr(&flags[i], 1);
 }
 
+__global__ __launch_bounds__(256) void kb_activate(int *__restrict__ active, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) active[i] = 1;
+}
+
 inline dim3 grid_of(const WorkSet &ws) { return dim3((unsigned)ws.nblocks); }
 
 }  // namespace
@@ -551,6 +556,10 @@ void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, i
                         hipStream_t s) {
   if (wv.nblocks > 0)
     hipLaunchKernelGGL(kb_nonfinite, grid_of(wv), dim3(256), 0, s, kry, active, wv, flags);
+}
+
+void launch_b_activate(int *active, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_activate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, active, n);
 }
 
 #define FSIMG_BINST(T)                                                                           \

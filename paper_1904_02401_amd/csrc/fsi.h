@@ -82,6 +82,9 @@ void newton_finish_step(fsimg_fsi *f, hipStream_t s);
 void newton_fail(fsimg_fsi *f, fsimg_status status);
 // The time step's statistics (final norm, wall time) once run.done.
 fsimg_newton_stats newton_end(fsimg_fsi *f, hipStream_t s);
+// the Newton options in effect (defaults when opts is null); ERR_ARG if one
+// is out of range (the one check of the solo and the served Newton loops)
+fsimg_status check_newton_options(const fsimg_newton_opts *opts, fsimg_newton_opts *o);
 // device bytes fsimg_fsi_create allocates for these momentum levels
 size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale);
 

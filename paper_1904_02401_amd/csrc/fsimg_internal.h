@@ -202,6 +202,7 @@ void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, con
                       const int *kcnt, int kmax, hipStream_t s);
 void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, int *flags,
                         hipStream_t s);
+void launch_b_activate(int *active, int n, hipStream_t s);  // active[0..n) = 1
 
 // ---------------------------------------------------------------- kernels
 template <typename T>

@@ -92,4 +92,19 @@ void drop_plans(fsimg_ctx *ctx);  // destroy every cached batch plan (e.g. after
 // batched FGMRES over n hierarchies (shared options / precision / block size)
 fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
                          double *const *x, fsimg_stats *stats, hipStream_t s);
+// One step of the multigrid path of one hierarchy through the batched kernels
+// (the launches its solve makes, with one instance), on the caller's vectors
+// of the hierarchy's V-cycle precision: the inputs are copied into the
+// level's work vectors and the result is copied out.  GATHER / Vanka
+// hierarchies only; `level` < the coarsest except for ONE_COARSE (the
+// coarsest, FP64 hierarchies) and ONE_VCYCLE (0).
+//   ONE_RESIDUAL  out = a - A_l b, 0 at identity rows
+//   ONE_VANKA     out += Vanka correction of a - A_l out (one smoothing step)
+//   ONE_RESTRICT  out = R a (level l -> l + 1), 0 at coarse identity rows
+//   ONE_PROLONG   out += P a (level l + 1 -> l), then 0 at fine identity rows
+//   ONE_COARSE    out = A_{L-1}^{-1} a on the free dofs, 0 at identity rows
+//   ONE_VCYCLE    out = V-cycle(a)
+enum SingleOp { ONE_RESIDUAL = 0, ONE_VANKA, ONE_RESTRICT, ONE_PROLONG, ONE_COARSE, ONE_VCYCLE };
+fsimg_status single_step(fsimg_hier *h, int op, int level, const void *a, const void *b, void *out,
+                         hipStream_t s);
 }  // namespace fsimg

@@ -166,11 +166,12 @@ fsimg_status assemble_jacobian(fsimg_fsi *f, const double *x, const double *u, c
 }
 
 // held rows of x take scale * vals (a time step's Dirichlet data); a row out
-// of range or not held in the momentum system sets bad[0] and is skipped
+// of range or not held in the momentum system sets bad[0] and is skipped.
+// write = 0 only checks the list (nothing of x is written)
 __global__ __launch_bounds__(256) void k_set_held_rows(double *__restrict__ x, const int64_t *__restrict__ rows,
                                                        const double *__restrict__ vals, int64_t n, int64_t nx,
                                                        const uint8_t *__restrict__ mask, double scale,
-                                                       int *__restrict__ bad) {
+                                                       int write, int *__restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t r = rows[i];
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_set_held_rows(double *__restrict__ x, c
     bad[0] = 1;
     return;
   }
-  x[r] = scale * vals[i];
+  if (write) x[r] = scale * vals[i];
 }
 
 // out[j] = sum over the listed nodes of res[node * B + 1 + j] / k, j < D: one
@@ -486,16 +487,22 @@ fsimg_status fsimg_fsi_time_step(fsimg_fsi *f, double *x, double *u, double *x_o
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevLevel &L = f->mom->lev[0];
   const int64_t na = L.nrows * f->dim;
-  NW_HIP(hipMemcpyAsync(x_old, x, L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  NW_HIP(hipMemcpyAsync(u_old, u, na * sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (n_rows > 0) {
+  const dim3 grid((unsigned)((n_rows + 255) / 256));
+  if (n_rows > 0) {  // check the list first: a refused call writes none of x, u, x_old, u_old
     NW_TRY(clear_flags(f, s));
-    hipLaunchKernelGGL(k_set_held_rows, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s, x, rows, vals,
-                       n_rows, L.n, L.mask, scale, f->dflag);
+    hipLaunchKernelGGL(k_set_held_rows, grid, dim3(256), 0, s, x, rows, vals, n_rows, L.n, L.mask, scale, 0,
+                       f->dflag);
     NW_HIP(hipGetLastError());
     int flags[2];
     NW_TRY(read_flags(f, s, flags, nullptr));
     if (flags[0]) return nfail(FSIMG_ERR_ARG, "a held-row index is out of range or not a held row");
+  }
+  NW_HIP(hipMemcpyAsync(x_old, x, L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  NW_HIP(hipMemcpyAsync(u_old, u, na * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (n_rows > 0) {
+    hipLaunchKernelGGL(k_set_held_rows, grid, dim3(256), 0, s, x, rows, vals, n_rows, L.n, L.mask, scale, 1,
+                       f->dflag);
+    NW_HIP(hipGetLastError());
   }
   return fsimg_fsi_newton(f, x, u, x_old, u_old, opts, stats, stream);
 }
@@ -535,6 +542,10 @@ fsimg_status fsimg_fsi_force(fsimg_fsi *f, const double *x, const double *u, con
 
 // ------------------------------------------------------------ Newton stages
 namespace fsimg {
+
+fsimg_status check_newton_options(const fsimg_newton_opts *opts, fsimg_newton_opts *o) {
+  return newton_options(opts, o);
+}
 
 void newton_fail(fsimg_fsi *f, fsimg_status status) {
   f->run.done = true;

@@ -411,14 +411,16 @@ fsimg_status fsimg_server_submit_newton(fsimg_server *S, const fsimg_newton_requ
       m0.nrows != a0.nrows)
     return set_error(FSIMG_ERR_ARG, "request systems must be momentum (b = d+1) and ALE (b = d) "
                                     "on the same mesh");
-  const fsimg_newton_opts &o = r->newton;
-  if (o.max_steps < 0 || o.max_halvings < 0 || !(o.rtol >= 0.0) || !(o.atol >= 0.0) || !(o.gamma >= 0.0) ||
-      !(o.lin_rtol >= 0.0 && o.lin_rtol < 1.0) || !(o.ale_rtol >= 0.0 && o.ale_rtol < 1.0))
-    return set_error(FSIMG_ERR_ARG, "bad Newton options");
+  fsimg_newton_opts o;
+  {
+    const fsimg_status st = check_newton_options(&r->newton, &o);
+    if (st != FSIMG_OK) return st;
+  }
   auto *q = new Req;
   q->id = S->next_id++;
   q->nt = true;
   q->nreq = *r;
+  q->nreq.newton = o;
   q->r.nlev = r->nlev;
   q->r.mom = r->mom;
   q->r.ale = r->ale;

@@ -208,15 +208,31 @@ def _check(status: int):
         raise FsimgError(status, load().fsimg_last_error().decode())
 
 
-def _dev(t):
-    """device address of a tensor (or an int address / None)."""
+def _dev(t, dtype=None, numel=None):
+    """device address of a tensor (or an int address / None).  dtype: the
+    torch dtype the kernels read (checked when given); numel: the number of
+    elements they read (the tensor must hold at least that many)."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected a {dtype} tensor, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"expected at least {numel} elements, got {t.numel()}")
     return t.data_ptr()
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
+def _i64():
+    import torch
+    return torch.int64
 
 
 def _stream(s):
@@ -533,20 +549,34 @@ def fsimg_fsi_create(mom, ale, levels, params: dict):
     out = ctypes.c_void_p()
     _check(load().fsimg_fsi_create(mom, ale, arr, ctypes.byref(fsimg_phys_of(params)),
                                    ctypes.byref(out)))
+    info = fsimg_hier_info(mom, 0)
+    _FSI_SIZES[out.value] = (info["n"], info["nrows"] * len(levels[0][0]))
     return out.value
 
 
+# finest-level lengths of x = (p, v) and u per Newton object (the kernels read
+# that many FP64 entries of every state vector)
+_FSI_SIZES = {}
+
+
+def _state(f, x, u, x_old, u_old):
+    nx, nu = _FSI_SIZES.get(f, (None, None))
+    f64 = _f64()
+    return (_dev(x, f64, nx), _dev(u, f64, nu), _dev(x_old, f64, nx), _dev(u_old, f64, nu))
+
+
 def fsimg_fsi_destroy(f):
+    _FSI_SIZES.pop(f, None)
     load().fsimg_fsi_destroy(f)
 
 
 def fsimg_fsi_residual(f, x, u, x_old, u_old, res, stream=None):
-    _check(load().fsimg_fsi_residual(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _dev(res),
-                                     _stream(stream)))
+    _check(load().fsimg_fsi_residual(f, *_state(f, x, u, x_old, u_old),
+                                     _dev(res, _f64(), _FSI_SIZES.get(f, (None,))[0]), _stream(stream)))
 
 
 def fsimg_fsi_jacobian(f, x, u, x_old, u_old, stream=None):
-    _check(load().fsimg_fsi_jacobian(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _stream(stream)))
+    _check(load().fsimg_fsi_jacobian(f, *_state(f, x, u, x_old, u_old), _stream(stream)))
 
 
 def fsimg_default_newton_opts(**overrides) -> fsimg_newton_opts:
@@ -560,7 +590,7 @@ def fsimg_default_newton_opts(**overrides) -> fsimg_newton_opts:
 def fsimg_fsi_newton(f, x, u, x_old, u_old, opts=None, stream=None, raise_on_noconv: bool = True) -> dict:
     st = fsimg_newton_stats()
     o = opts if opts is not None else fsimg_default_newton_opts()
-    rc = load().fsimg_fsi_newton(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), ctypes.byref(o),
+    rc = load().fsimg_fsi_newton(f, *_state(f, x, u, x_old, u_old), ctypes.byref(o),
                                  ctypes.byref(st), _stream(stream))
     if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
         _check(rc)
@@ -578,8 +608,9 @@ def fsimg_fsi_time_step(f, x, u, x_old, u_old, rows=None, vals=None, scale: floa
     st = fsimg_newton_stats()
     o = opts if opts is not None else fsimg_default_newton_opts()
     n = 0 if rows is None else int(rows.numel())
-    rc = load().fsimg_fsi_time_step(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old),
-                                    _dev(rows) if n else None, _dev(vals) if n else None, n,
+    rc = load().fsimg_fsi_time_step(f, *_state(f, x, u, x_old, u_old),
+                                    _dev(rows, _i64()) if n else None,
+                                    _dev(vals, _f64(), n) if n else None, n,
                                     float(scale), ctypes.byref(o), ctypes.byref(st), _stream(stream))
     if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
         _check(rc)
@@ -589,7 +620,7 @@ def fsimg_fsi_time_step(f, x, u, x_old, u_old, rows=None, vals=None, scale: floa
 def fsimg_fsi_force(f, x, u, x_old, u_old, nodes, dim: int, stream=None):
     """nodes: int64 device tensor; returns [dim] floats (drag, lift[, z])."""
     out = (_D * 3)()
-    _check(load().fsimg_fsi_force(f, _dev(x), _dev(u), _dev(x_old), _dev(u_old), _dev(nodes),
+    _check(load().fsimg_fsi_force(f, *_state(f, x, u, x_old, u_old), _dev(nodes, _i64()),
                                   int(nodes.numel()), out, _stream(stream)))
     return [out[j] for j in range(dim)]
 

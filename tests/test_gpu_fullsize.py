@@ -186,9 +186,22 @@ def test_c2_sampled_block_vanka_update(ctx, c2):
                 assert abs(xg[dof] - ref) <= 1e-8 * max(abs(ref - x0[dof]), 1e-30) + 1e-15
 
 
-def test_c3_mixed_solve(ctx):
+@pytest.fixture(scope="module")
+def c3():
+    return config_problem("c3", seed=0, systems=("mom",))
+
+
+def test_c3_sampled_vanka_step_fp32(ctx, c3):
+    """3D 64^3 (the bench's headline workload): one FP32 smoothing step of the
+    batched kernels (kb_spmv<4, float>, kb_vanka_patch<float>,
+    kb_vanka_gather<float>) at sampled dofs within the per-dof FP32 bound."""
+    from test_gpu_kernel_bounds import sampled_vanka_check
+    sampled_vanka_check(ctx, c3, fsimg.FSIMG_MIXED, 30, 41)
+
+
+def test_c3_mixed_solve(ctx, c3):
     """64^3 mixed precision (FP32 V-cycle, FP64 outer): FP64 residual <= 1e-8."""
-    P = config_problem("c3", seed=0, systems=("mom",))
+    P = c3
     m = P.levels[0].systems["mom"]
     h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"),
                                 fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED))

@@ -1,0 +1,415 @@
+"""Per-dof parity of the kernels the solve runs (the batched kb_* kernels, one
+instance) against the FP64 oracle, in FP64 and in FP32.
+
+fsimg_level_residual, fsimg_vanka_step, fsimg_restrict, fsimg_prolong_add,
+fsimg_coarse_solve and fsimg_vcycle of a GATHER / Vanka hierarchy launch the
+batched kernels of the solve (kb_spmv<b, T, 0, R>, kb_vanka_patch<T> +
+kb_vanka_gather<T>, kb_restrict<b, d, T>, kb_prolong<b, d, T>,
+kb_coarse_*) with one instance.  Each result is compared per dof with the
+oracle's definition of the step evaluated in FP64 on the data the kernel
+reads: for FP32 the matrix rounded to FP32, the oracle's LAPACK inverses
+rounded to FP32, omega rounded to FP32.  The bound is the forward error bound
+of the kernel's arithmetic (Higham, Accuracy and Stability of Numerical
+Algorithms, 2nd ed., Sec. 3.1: gamma_n = n u / (1 - n u) for a sum of n
+products in any order), plus, for the Vanka step, the difference between the
+GPU's and LAPACK's inverses (both exact up to rounding: the componentwise
+rounding bound of each FP64 inverse with LAPACK's pivoted factors, then two
+FP32 roundings in mixed mode).
+A wrong index, a dropped term or a transposed block exceeds these bounds by
+orders of magnitude: every test also checks that the step moves the dofs by
+far more than the bound.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from fsigen import config_problem
+from oracle import VankaData, local_matrices, prolongation, to_csr
+from oracle.patches import element_patches
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1904_02401_amd import fsimg  # noqa: E402
+from paper_1904_02401_amd.problems import level_dicts  # noqa: E402
+
+DEV = "cuda:0"
+U = {fsimg.FSIMG_FP64: 2.0 ** -53, fsimg.FSIMG_MIXED: 2.0 ** -24}
+DT = {fsimg.FSIMG_FP64: (np.float64, torch.float64), fsimg.FSIMG_MIXED: (np.float32, torch.float32)}
+
+
+def gamma(n, u):
+    n = np.asarray(n, dtype=np.float64)
+    return n * u / (1.0 - n * u)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = fsimg.fsimg_ctx_create(0)
+    yield c
+    fsimg.fsimg_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def probs():
+    return {name: config_problem(name, seed=0) for name in ("t2", "t3", "c1")}
+
+
+def _t(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _rounded(A, prec):
+    """the matrix as the kernel reads it (FP32 copies in mixed mode)"""
+    if prec == fsimg.FSIMG_MIXED:
+        A = A.copy()
+        A.data = A.data.astype(np.float32).astype(np.float64)
+    return A
+
+
+def _row_terms(m):
+    """products per scalar row of the BSR matrix, plus one for b"""
+    nb = np.diff(m.rowptr).astype(np.int64)
+    return np.repeat(nb * m.b + 1, m.b)
+
+
+def _check(got, ref, bound, what):
+    err = np.abs(got - ref)
+    bad = err > bound
+    ratio = float(np.max(err / np.maximum(bound, 1e-300)))
+    assert not bad.any(), (f"{what}: {int(bad.sum())} of {got.size} dofs outside the bound, "
+                           f"worst err/bound {ratio:.3g} at {int(np.argmax(err - bound))}")
+    return ratio
+
+
+# ------------------------------------------------------------------ residual
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("t3", "ale"), ("c1", "mom")])
+def test_residual_per_dof(ctx, probs, name, system, prec):
+    """kb_spmv<b, T, 0, R>: d = b - A x, zero at identity rows, on every
+    smoothing level."""
+    P = probs[name]
+    npt, tt = DT[prec]
+    u = U[prec]
+    rng = np.random.default_rng(21)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, system), fsimg.fsimg_default_opts(precision=prec))
+    try:
+        for l in range(len(P.levels) - 1):
+            m = P.levels[l].systems[system]
+            A = _rounded(to_csr(m), prec)
+            n = A.shape[0]
+            x = rng.standard_normal(n).astype(npt).astype(np.float64)
+            b = rng.standard_normal(n).astype(npt).astype(np.float64)
+            d = torch.empty(n, device=DEV, dtype=tt)
+            fsimg.fsimg_level_residual(h, l, prec, _t(b, tt), _t(x, tt), d)
+            mask = m.dirichlet.astype(bool)
+            ref = b - A @ x
+            ref[mask] = 0.0
+            bound = gamma(_row_terms(m), u) * (np.abs(b) + abs(A) @ np.abs(x))
+            _check(_np(d), ref, bound, f"{name}/{system} L{l} residual")
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+
+
+# ---------------------------------------------------------------- transfers
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("c1", "ale")])
+def test_transfers_per_dof(ctx, probs, name, system, prec):
+    """kb_restrict / kb_prolong: r_c = P^T r_f and x_f += P x_c with the
+    canonical Q2 interpolation, identity rows zeroed.  The weights 1, 3/4,
+    3/8, -1/8 and their products are exact in FP32."""
+    P = probs[name]
+    npt, tt = DT[prec]
+    u = U[prec]
+    rng = np.random.default_rng(22)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, system), fsimg.fsimg_default_opts(precision=prec))
+    try:
+        for l in range(len(P.levels) - 1):
+            mf = P.levels[l].systems[system]
+            mc = P.levels[l + 1].systems[system]
+            Pm = prolongation(P.levels[l + 1].cells, mf.b)
+            Pa = abs(Pm)
+            rf = rng.standard_normal(Pm.shape[0]).astype(npt).astype(np.float64)
+            rc = torch.empty(Pm.shape[1], device=DEV, dtype=tt)
+            fsimg.fsimg_restrict(h, l, prec, _t(rf, tt), rc)
+            ref = Pm.T @ rf
+            cmask = mc.dirichlet.astype(bool)
+            ref[cmask] = 0.0
+            nterm = np.diff(Pm.T.tocsr().indptr)
+            _check(_np(rc), ref, gamma(nterm, u) * (Pa.T @ np.abs(rf)), f"{name} L{l} restrict")
+            xc = rng.standard_normal(Pm.shape[1]).astype(npt).astype(np.float64)
+            xf0 = rng.standard_normal(Pm.shape[0]).astype(npt).astype(np.float64)
+            xf = _t(xf0, tt)
+            fsimg.fsimg_prolong_add(h, l, prec, _t(xc, tt), xf)
+            ref = xf0 + Pm @ xc
+            fmask = mf.dirichlet.astype(bool)
+            ref[fmask] = 0.0
+            nterm = np.diff(Pm.tocsr().indptr) + 1
+            _check(_np(xf), ref, gamma(nterm, u) * (np.abs(xf0) + Pa @ np.abs(xc)),
+                   f"{name} L{l} prolong")
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+
+
+# --------------------------------------------------------------- Vanka step
+def lu_abs(A):
+    """P |L| |U| of LAPACK's LU with partial pivoting of each matrix in the
+    batch A [k, n, n]: the growth that enters the inverses' error bound (the
+    saddle-point patches of the momentum system grow by 1e2-1e4 over |A|)."""
+    out = np.empty_like(A)
+    for i in range(A.shape[0]):
+        p, l, u = sla.lu(A[i])
+        out[i] = p @ (np.abs(l) @ np.abs(u))
+    return out
+
+
+def inverse_mismatch(ai, aa, ad, prec):
+    """|X_gpu - X_oracle| |d| for two inverses of the same patch matrix A,
+    each exact up to rounding: Gauss-Jordan or LU with partial pivoting gives
+    |X^ - X| <= gamma_3n |X| P|L||U| |X| (Higham, Ch. 14, the componentwise
+    bounds of the inversion methods with the computed factors), so the two
+    FP64 inverses differ by at most twice that; in mixed mode each is then
+    rounded to FP32 (u |X| each).  ai = |X|, aa = P|L||U|, ad = |d| as
+    [..., n, 1] columns (batched)."""
+    n = ai.shape[-1]
+    x = np.matmul(ai, np.matmul(aa, np.matmul(ai, ad)))
+    e = 2 * gamma(3 * n, U[fsimg.FSIMG_FP64]) * x
+    if prec == fsimg.FSIMG_MIXED:
+        e = e + 2 * U[prec] * np.matmul(ai, ad)
+    return e
+
+
+def vanka_reference(A, m, cells, b, x, prec, omega=0.8):
+    """One additive Vanka step (eq. vanka, averaged over the element patches
+    containing a dof) in FP64 on the data the kernel reads, and its per-dof
+    forward error bound."""
+    u = U[prec]
+    npt = DT[prec][0]
+    V = VankaData.build(m, cells, omega=omega, weighting="mult")
+    inv = V.inv
+    Aloc = lu_abs(local_matrices(m, cells))
+    mask = m.dirichlet.astype(bool)
+    d = b - A @ x
+    d[mask] = 0.0
+    D = np.abs(b) + abs(A) @ np.abs(x)
+    eD = gamma(_row_terms(m), u) * D  # residual rounding per dof
+    eD[mask] = 0.0
+    inv_k = inv.astype(npt).astype(np.float64)
+    npp = inv.shape[1]
+    dl = d[V.dofs]
+    loc = np.matmul(inv_k, dl[:, :, None])[:, :, 0]
+    ai = np.abs(inv)
+    ad = np.abs(dl)[:, :, None]
+    t = (np.matmul(np.abs(inv_k), (eD[V.dofs] + gamma(npp, u) * np.abs(dl))[:, :, None])[:, :, 0]
+         + inverse_mismatch(ai, Aloc, ad, prec)[:, :, 0])
+    n = x.shape[0]
+    corr = np.bincount(V.dofs.ravel(), weights=loc.ravel(), minlength=n)
+    tsum = np.bincount(V.dofs.ravel(), weights=t.ravel(), minlength=n)
+    asum = np.bincount(V.dofs.ravel(), weights=np.abs(loc).ravel(), minlength=n)
+    mult = np.bincount(V.dofs.ravel(), minlength=n)
+    w = float(npt(omega))
+    ref = x + w * V.scale * corr
+    ref[mask] = x[mask]
+    bound = gamma(2, u) * np.abs(x) + w * V.scale * (tsum + gamma(mult + 3, u) * asum)
+    bound[mask] = 0.0
+    return ref, bound
+
+
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+@pytest.mark.parametrize("name,system", [("t2", "mom"), ("t3", "mom"), ("t3", "ale"), ("c1", "mom")])
+def test_vanka_step_per_dof(ctx, probs, name, system, prec):
+    """kb_vanka_patch<T> + kb_vanka_gather<T> (after kb_spmv): one smoothing
+    step on the finest level, per dof within the forward error bound."""
+    P = probs[name]
+    lev = P.levels[0]
+    m = lev.systems[system]
+    npt, tt = DT[prec]
+    A = _rounded(to_csr(m), prec)
+    mask = m.dirichlet.astype(bool)
+    rng = np.random.default_rng(23)
+    b = rng.standard_normal(A.shape[0]).astype(npt).astype(np.float64)
+    b[mask] = 0.0
+    x0 = (rng.standard_normal(A.shape[0]) * 0.1).astype(npt).astype(np.float64)
+    ref, bound = vanka_reference(A, m, lev.cells, b, x0, prec)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, system), fsimg.fsimg_default_opts(precision=prec))
+    try:
+        fsimg.fsimg_factor(h)
+        x = _t(x0, tt)
+        fsimg.fsimg_vanka_step(h, 0, prec, _t(b, tt), x)
+        got = _np(x)
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+    np.testing.assert_array_equal(got[mask], x0[mask])
+    r = _check(got, ref, bound, f"{name}/{system} Vanka step")
+    # the step moved every free dof that a patch touches by far more than the bound
+    moved = np.abs(ref - x0)[~mask]
+    assert np.median(moved / np.maximum(bound[~mask], 1e-300)) > 100, r
+
+
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_coarse_and_vcycle_match_single_kernels(ctx, probs, prec):
+    """The one-instance batched V-cycle and coarse solve against the oracle:
+    the FP64 coarse solve per dof within the inverse's rounding, the V-cycle
+    normwise (FP32: within the FP32 rounding of the cycle, 1e-5 relative)."""
+    from oracle import Hierarchy, vcycle
+    P = probs["t3"]
+    mats = P.system("mom")
+    cells = [lv.cells for lv in P.levels]
+    Ho = Hierarchy(mats, cells, omega=0.8, weighting="mult")
+    npt, tt = DT[prec]
+    rng = np.random.default_rng(24)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), fsimg.fsimg_default_opts(precision=prec))
+    try:
+        fsimg.fsimg_factor(h)
+        if prec == fsimg.FSIMG_FP64:
+            mc = mats[-1]
+            rc = rng.standard_normal(mc.nrows * mc.b)
+            rc[mc.dirichlet.astype(bool)] = 0.0
+            xc = torch.empty(rc.shape[0], device=DEV, dtype=torch.float64)
+            fsimg.fsimg_coarse_solve(h, _t(rc, torch.float64), xc)
+            ref = Ho.coarse_solve(rc)
+            Ad = to_csr(mc).toarray()
+            free = ~mc.dirichlet.astype(bool)
+            Af = Ad[np.ix_(free, free)]
+            cinv = np.linalg.inv(Af)
+            ac = np.abs(cinv)
+            arc = np.abs(rc[free])[:, None]
+            bound = inverse_mismatch(ac, lu_abs(Af[None])[0], arc, prec)[:, 0] + \
+                gamma(free.sum(), U[prec]) * (ac @ arc)[:, 0]
+            got = _np(xc)
+            _check(got[free], ref[free], bound, "coarse solve")
+            assert not got[~free].any()
+        r = rng.standard_normal(mats[0].nrows * mats[0].b).astype(npt).astype(np.float64)
+        r[mats[0].dirichlet.astype(bool)] = 0.0
+        z = torch.empty(r.shape[0], device=DEV, dtype=tt)
+        fsimg.fsimg_vcycle(h, prec, _t(r, tt), z)
+        zr = vcycle(Ho, r)
+        rel = np.linalg.norm(_np(z) - zr) / np.linalg.norm(zr)
+        assert rel < (1e-10 if prec == fsimg.FSIMG_FP64 else 1e-3), rel
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+
+
+# ------------------------------------------------------- full size, sampled
+def _patch_cells(cells, node):
+    """elements whose 3^d node box contains the node (lexicographic)"""
+    nn = [2 * c + 1 for c in cells]
+    g = []
+    t = node
+    for a in range(len(cells)):
+        g.append(t % nn[a])
+        t //= nn[a]
+    ranges = []
+    for a in range(len(cells)):
+        e = g[a] // 2
+        cand = {e - 1, e} if g[a] % 2 == 0 else {e}
+        ranges.append(sorted(c for c in cand if 0 <= c < cells[a]))
+    out = []
+    if len(cells) == 3:
+        for ez in ranges[2]:
+            for ey in ranges[1]:
+                for ex in ranges[0]:
+                    out.append(ex + cells[0] * (ey + cells[1] * ez))
+    else:
+        for ey in ranges[1]:
+            for ex in ranges[0]:
+                out.append(ex + cells[0] * ey)
+    return out
+
+
+def sampled_vanka_check(ctx, P, prec, nsample, seed):
+    """One FP32 / FP64 Vanka step at full size: sampled dofs against the
+    definition with the per-dof bound of vanka_reference, from the rows of the
+    matrix the sampled patches touch."""
+    lev = P.levels[0]
+    m = lev.systems["mom"]
+    b_ = m.b
+    npt, tt = DT[prec]
+    u = U[prec]
+    rng = np.random.default_rng(seed)
+    n = m.nrows * b_
+    mask = m.dirichlet.astype(bool)
+    x0 = (rng.standard_normal(n) * 1e-3).astype(npt).astype(np.float64)
+    x0[mask] = 0.0
+    rhs = P.rhs["mom"].astype(npt).astype(np.float64)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), fsimg.fsimg_default_opts(precision=prec))
+    try:
+        fsimg.fsimg_factor(h)
+        xt = _t(x0, tt)
+        fsimg.fsimg_vanka_step(h, 0, prec, _t(rhs, tt), xt)
+        xg = _np(xt)
+    finally:
+        fsimg.fsimg_hier_destroy(h)
+    vals = m.vals.astype(npt).astype(np.float64) if prec == fsimg.FSIMG_MIXED else m.vals
+    xb = x0.reshape(-1, b_)
+
+    def rows(nodes):
+        """d, D = |b| + |A||x| and the residual's terms at the dofs of nodes"""
+        d = np.zeros((len(nodes), b_))
+        D = np.zeros((len(nodes), b_))
+        nt = np.zeros(len(nodes))
+        for t, r in enumerate(nodes):
+            js = slice(m.rowptr[r], m.rowptr[r + 1])
+            blk = vals[js]
+            xc = xb[m.colind[js]]
+            d[t] = rhs[r * b_:(r + 1) * b_] - np.einsum("kij,kj->i", blk, xc)
+            D[t] = np.abs(rhs[r * b_:(r + 1) * b_]) + np.einsum("kij,kj->i", np.abs(blk), np.abs(xc))
+            nt[t] = (m.rowptr[r + 1] - m.rowptr[r]) * b_ + 1
+        d, D = d.ravel(), D.ravel()
+        dm = mask[(np.asarray(nodes)[:, None] * b_ + np.arange(b_)).ravel()]
+        d[dm] = 0.0
+        eD = gamma(np.repeat(nt, b_), u) * D
+        eD[dm] = 0.0
+        return d, eD
+
+    enodes = element_patches(lev.cells)
+    free = np.nonzero(~mask)[0]
+    w = float(npt(0.8))
+    worst = 0.0
+    moved = []
+    sample = rng.choice(free, nsample, replace=False)
+    cells_of = {int(dof): _patch_cells(lev.cells, int(dof) // b_) for dof in sample}
+    union = sorted({e for es in cells_of.values() for e in es})
+    mats_u = local_matrices(m, lev.cells, np.array(union))  # one pass over the matrix
+    mat_of = {e: mats_u[i] for i, e in enumerate(union)}
+    for dof in sample:
+        node, comp = divmod(int(dof), b_)
+        elems = cells_of[int(dof)]
+        loc_mats = [mat_of[e] for e in elems]
+        corr = tsum = asum = 0.0
+        for t, e in enumerate(elems):
+            nodes = enodes[e]
+            d, eD = rows(nodes)
+            inv = np.linalg.inv(loc_mats[t])
+            q = list(nodes).index(node) * b_ + comp
+            invk = inv.astype(npt).astype(np.float64)
+            loc = invk[q] @ d
+            e_inv = inverse_mismatch(np.abs(inv), lu_abs(loc_mats[t][None])[0], np.abs(d)[:, None],
+                                     prec)[q, 0]
+            corr += loc
+            asum += abs(loc)
+            tsum += np.abs(invk[q]) @ (eD + gamma(inv.shape[0], u) * np.abs(d)) + e_inv
+        k = len(elems)
+        ref = x0[dof] + w * corr / k
+        bound = gamma(2, u) * abs(x0[dof]) + w / k * (tsum + gamma(k + 3, u) * asum)
+        err = abs(xg[dof] - ref)
+        assert err <= bound, (int(dof), err, bound, ref)
+        worst = max(worst, err / bound)
+        moved.append(abs(ref - x0[dof]) / bound)
+    # the step moved the sampled dofs by far more than the bound
+    assert np.median(moved) > 100, np.median(moved)
+    return worst
+
+
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_c2_sampled_vanka_step_per_dof(ctx, prec):
+    """3D 32^3 (the bench's C2 workload): kb_vanka_patch<T> at sampled dofs."""
+    P = config_problem("c2", seed=0, systems=("mom",))
+    sampled_vanka_check(ctx, P, prec, 40, 31)
