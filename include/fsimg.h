@@ -219,6 +219,25 @@ fsimg_status fsimg_solve(fsimg_hier *h, const double *b_dev, double *x_dev, fsim
 fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *const *b_dev,
                                double *const *x_dev, fsimg_stats *stats, void *stream);
 
+/* fsimg_solve for callers that cannot allocate: code under HIP graph capture
+   of its own work, tight serving loops, harnesses that forbid hipMalloc.
+   Same method, kernels and result as fsimg_solve (bitwise equal; launched
+   eagerly, no HIP graphs).  The solve's descriptor tables (level
+   descriptors, work lists, Krylov descriptor, active flags, Hessenberg
+   column; about 30 KB for five levels) are written into a fixed 64 KiB
+   device array that every GPU the library runs on holds until the process
+   ends (its address is looked up when a context is created on the GPU);
+   host staging uses host memory.  The call makes no hipMalloc, hipFree,
+   hipHostMalloc, stream or graph creation.  It needs a factored hierarchy
+   (else ERR_STATE) with the GATHER schedule and the Vanka smoother (else
+   ERR_ARG); ERR_ARG if its tables do not fit the array (more than about a
+   dozen levels).  Every call on one GPU shares that GPU's array and rewrites
+   all of it: calls that overlap on one GPU (other host threads, other
+   streams) race, and the caller must serialise them.  Arguments and
+   results otherwise as fsimg_solve. */
+fsimg_status fsimg_solve_noalloc(fsimg_hier *h, const double *b_dev, double *x_dev,
+                                 fsimg_stats *stats, void *stream);
+
 /* Condensed deformation update (Sec. 3.1 and eq. problem:2):
      u_new = u_old + k theta v_new + k (1 - theta) v_old   at nodes with mask != 0,
      u_new = 0                                            elsewhere.

@@ -582,6 +582,7 @@ fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **o
   FSIMG_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(FSIMG_ERR_ARG, "no such device");
   FSIMG_HIP(hipSetDevice(device));
+  FSIMG_TRY(noalloc_init(device));  // this device's no-allocation scratch array
   auto *c = new fsimg_ctx;
   c->device = device;
   c->budget = hbm_budget_bytes;
@@ -1132,6 +1133,13 @@ fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *co
       return fail(FSIMG_ERR_ARG, "batched solves take Vanka hierarchies only (ILU: fsimg_solve)");
   FSIMG_HIP(hipSetDevice(hiers[0]->ctx->device));
   return solve_batch(hiers[0]->ctx, n, hiers, b_dev, x_dev, stats, static_cast<hipStream_t>(stream));
+}
+
+fsimg_status fsimg_solve_noalloc(fsimg_hier *h, const double *b, double *x, fsimg_stats *stats,
+                                 void *stream) {
+  if (!h) return fail(FSIMG_ERR_ARG, "null hierarchy");
+  FSIMG_HIP(hipSetDevice(h->ctx->device));
+  return solve_noalloc(h, b, x, stats, static_cast<hipStream_t>(stream));
 }
 
 fsimg_status fsimg_solve(fsimg_hier *h, const double *b, double *x, fsimg_stats *stats, void *stream) {

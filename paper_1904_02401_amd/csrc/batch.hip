@@ -12,6 +12,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -46,6 +48,11 @@ struct BatchPlan {
   hipStream_t cap = nullptr;
   std::vector<hipGraphExec_t> iter_graph;
   fsimg_opts graph_opts{};
+  // tables placed in a buffer the plan does not own (the no-allocation
+  // solve): never freed here, staging in the host arrays below
+  bool fixed = false;
+  double hs_one[kHS] = {};
+  int int_one[3] = {};
 };
 
 namespace fsimg {
@@ -55,6 +62,10 @@ void destroy_plan(BatchPlan *p) {
   for (hipGraphExec_t g : p->iter_graph)
     if (g) (void)hipGraphExecDestroy(g);
   if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->fixed) {
+    delete p;
+    return;
+  }
   if (p->dbuf) {
     (void)hipFree(p->dbuf);
     if (p->ctx) {
@@ -151,7 +162,11 @@ DLev to_dlev(const DevLevel &L) {
   return d;
 }
 
-fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan **out) {
+// fixed != nullptr: place the tables in that device buffer of fixed_bytes
+// (uploaded on stream s) instead of allocating, and stage through the plan's
+// own host arrays (one instance only)
+fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan **out,
+                        void *fixed = nullptr, size_t fixed_bytes = 0, hipStream_t s = nullptr) {
   auto *P = new BatchPlan;
   P->n = n;
   P->b = hs[0]->lev[0].b;
@@ -246,21 +261,38 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   const WsRef r_row0 = stage(blob, row0), r_vec0 = stage(blob, vec0), r_kry = stage(blob, kr),
               r_ins = stage(blob, ins);
   P->dbytes = blob.data.size();
-  if (ctx->budget && ctx->in_use + P->dbytes > ctx->budget) {
-    delete P;
-    return set_error(FSIMG_ERR_BUDGET, "batch descriptor tables exceed the HBM budget");
-  }
-  if (hipMalloc(&P->dbuf, P->dbytes) != hipSuccess) {
-    (void)hipGetLastError();
-    delete P;
-    return set_error(FSIMG_ERR_OOM, "batch descriptor allocation failed");
-  }
-  P->ctx = ctx;
-  ctx->in_use += P->dbytes;
-  ctx->plan_bytes += P->dbytes;
-  if (hipMemcpy(P->dbuf, blob.data.data(), P->dbytes, hipMemcpyHostToDevice) != hipSuccess) {
-    destroy_plan(P);
-    return set_error(FSIMG_ERR_HIP, "batch descriptor upload failed");
+  if (fixed) {
+    if (n != 1 || P->dbytes > fixed_bytes) {
+      delete P;
+      return set_error(FSIMG_ERR_ARG, "the hierarchy's solve tables (" + std::to_string(blob.data.size()) +
+                                          " bytes) exceed the fixed scratch array (" +
+                                          std::to_string(fixed_bytes) + " bytes)");
+    }
+    P->fixed = true;
+    P->dbuf = fixed;
+    // every table (flags, Hessenberg column, descriptors) is rewritten here
+    if (hipMemcpyAsync(P->dbuf, blob.data.data(), P->dbytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      delete P;
+      return set_error(FSIMG_ERR_HIP, "descriptor upload to the scratch array failed");
+    }
+  } else {
+    if (ctx->budget && ctx->in_use + P->dbytes > ctx->budget) {
+      delete P;
+      return set_error(FSIMG_ERR_BUDGET, "batch descriptor tables exceed the HBM budget");
+    }
+    if (hipMalloc(&P->dbuf, P->dbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      delete P;
+      return set_error(FSIMG_ERR_OOM, "batch descriptor allocation failed");
+    }
+    P->ctx = ctx;
+    ctx->in_use += P->dbytes;
+    ctx->plan_bytes += P->dbytes;
+    if (hipMemcpy(P->dbuf, blob.data.data(), P->dbytes, hipMemcpyHostToDevice) != hipSuccess) {
+      destroy_plan(P);
+      return set_error(FSIMG_ERR_HIP, "batch descriptor upload failed");
+    }
   }
   unsigned char *base = static_cast<unsigned char *>(P->dbuf);
   P->dlev = reinterpret_cast<DLev *>(base + lev_off);
@@ -283,6 +315,12 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   P->ws_vec0 = resolve(base, r_vec0);
   P->ws_kry = resolve(base, r_kry);
   P->ws_inst = resolve(base, r_ins);
+  if (P->fixed) {
+    P->hs_host = P->hs_one;
+    P->int_host = P->int_one;
+    *out = P;
+    return FSIMG_OK;
+  }
   if (hipHostMalloc((void **)&P->hs_host, (size_t)n * kHS * sizeof(double), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void **)&P->int_host, (size_t)3 * n * sizeof(int), hipHostMallocDefault) !=
@@ -448,8 +486,31 @@ fsimg_status acquire_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPla
 
 }  // namespace
 
+namespace {
+fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double *const *b,
+                       double *const *x, fsimg_stats *stats, hipStream_t s, bool use_graph, bool prof);
+fsimg_status check_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
+                         double *const *x);
+}  // namespace
+
 fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
                          double *const *x, fsimg_stats *stats, hipStream_t s) {
+  {
+    const fsimg_status st = check_batch(ctx, n, hs, b, x);
+    if (st != FSIMG_OK) return st;
+  }
+  BatchPlan *P = nullptr;
+  {
+    fsimg_status st = acquire_plan(ctx, n, hs, &P);
+    if (st != FSIMG_OK) return st;
+  }
+  const bool prof = hs[0]->opts.profile != 0;
+  return run_batch(P, n, hs, b, x, stats, s, hs[0]->opts.graphs != 0 && !prof, prof);
+}
+
+namespace {
+fsimg_status check_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const double *const *b,
+                         double *const *x) {
   if (n < 1 || !hs || !b || !x) return set_error(FSIMG_ERR_ARG, "empty batch or null arrays");
   const fsimg_opts &o = hs[0]->opts;
   for (int i = 0; i < n; ++i) {
@@ -466,14 +527,15 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return set_error(FSIMG_ERR_ARG, "a hierarchy appears twice in a batch");
   }
+  return FSIMG_OK;
+}
+
+// FGMRES(m) + V-cycle of the n instances of plan P (eager launches or one
+// graph per iteration)
+fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double *const *b,
+                       double *const *x, fsimg_stats *stats, hipStream_t s, bool use_graph, bool prof) {
+  const fsimg_opts &o = hs[0]->opts;
   const auto t0 = std::chrono::steady_clock::now();
-  BatchPlan *P = nullptr;
-  {
-    fsimg_status st = acquire_plan(ctx, n, hs, &P);
-    if (st != FSIMG_OK) return st;
-  }
-  const bool prof = o.profile != 0;
-  const bool use_graph = o.graphs != 0 && !prof;
   P->tv.begin_solve();
   P->ts.begin_solve();
   const int m = o.restart;
@@ -652,6 +714,7 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
   if (ret == FSIMG_ERR_NONFINITE) return set_error(ret, "non-finite residual in an instance");
   return ret;
 }
+}  // namespace
 
 
 // ------------------------------------------------- one hierarchy, one step
@@ -733,6 +796,64 @@ fsimg_status single_step(fsimg_hier *h, int op, int level, const void *a, const 
                          hipStream_t s) {
   if (h->opts.precision == FSIMG_MIXED) return single_step_t<float>(h, op, level, a, b, out, s);
   return single_step_t<double>(h, op, level, a, b, out, s);
+}
+
+
+// ------------------------------------------ solve without any allocation
+// The per-solve tables of one instance (level descriptors, work lists,
+// Krylov descriptor, flags, Hessenberg column: about 30 KB for five levels)
+// live in this fixed array; every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address of each GPU's copy is looked up once per
+// device (noalloc_init, called when a context is created on it).
+constexpr size_t kScratchBytes = size_t(64) << 10;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+fsimg_status noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return set_error(FSIMG_ERR_ARG, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return FSIMG_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // `device` is current
+  if (e != hipSuccess || !ptr)
+    return set_error(FSIMG_ERR_HIP, std::string("scratch array lookup: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return FSIMG_OK;
+}
+
+size_t noalloc_scratch_bytes() { return kScratchBytes; }
+
+fsimg_status solve_noalloc(fsimg_hier *h, const double *b, double *x, fsimg_stats *stats,
+                           hipStream_t s) {
+  if (!h || !b || !x) return set_error(FSIMG_ERR_ARG, "null argument");
+  if (h->opts.vanka_schedule != FSIMG_VANKA_GATHER || h->opts.smoother != FSIMG_SMOOTHER_VANKA)
+    return set_error(FSIMG_ERR_ARG, "the no-allocation solve needs the GATHER schedule and the Vanka "
+                                    "smoother");
+  {
+    const fsimg_status st = check_batch(h->ctx, 1, &h, &b, &x);
+    if (st != FSIMG_OK) return st;
+  }
+  const int dev = h->ctx->device;
+  void *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ptr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+  }
+  if (!ptr) return set_error(FSIMG_ERR_STATE, "no scratch array address for this device");
+  BatchPlan *P = nullptr;
+  {
+    const fsimg_status st = build_plan(h->ctx, 1, &h, &P, ptr, kScratchBytes, s);
+    if (st != FSIMG_OK) return st;
+  }
+  const fsimg_status st = run_batch(P, 1, &h, &b, &x, stats, s, false, false);
+  destroy_plan(P);  // host side only: the tables stay in the scratch array
+  return st;
 }
 
 }  // namespace fsimg

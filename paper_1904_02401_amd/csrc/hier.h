@@ -105,6 +105,14 @@ fsimg_status solve_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
 //   ONE_COARSE    out = A_{L-1}^{-1} a on the free dofs, 0 at identity rows
 //   ONE_VCYCLE    out = V-cycle(a)
 enum SingleOp { ONE_RESIDUAL = 0, ONE_VANKA, ONE_RESTRICT, ONE_PROLONG, ONE_COARSE, ONE_VCYCLE };
+// The no-allocation solve: noalloc_init looks up the calling device's copy of
+// the fixed scratch array (device current; once per device, at context
+// creation); solve_noalloc is fsimg_solve of one GATHER / Vanka hierarchy
+// with its tables in that array, launched eagerly.
+fsimg_status noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+fsimg_status solve_noalloc(fsimg_hier *h, const double *b, double *x, fsimg_stats *stats,
+                           hipStream_t s);
 fsimg_status single_step(fsimg_hier *h, int op, int level, const void *a, const void *b, void *out,
                          hipStream_t s);
 }  // namespace fsimg

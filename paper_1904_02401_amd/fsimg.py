@@ -137,6 +137,7 @@ _SIGS = {
     "fsimg_hier_set_profile": (_I, [_P, _I]),
     "fsimg_factor": (_I, [_P, _P]),
     "fsimg_solve": (_I, [_P, _P, _P, ctypes.POINTER(fsimg_stats), _P]),
+    "fsimg_solve_noalloc": (_I, [_P, _P, _P, ctypes.POINTER(fsimg_stats), _P]),
     "fsimg_solve_batch": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                ctypes.POINTER(fsimg_stats), _P]),
     "fsimg_deform_update": (_I, [_I64, _I, _P, _D, _D, _P, _I, _I, _P, _P, _P, _P]),
@@ -342,6 +343,14 @@ def fsimg_factor(h, stream=None):
 def fsimg_solve(h, b, x, stream=None, raise_on_noconv: bool = True) -> dict:
     st = fsimg_stats()
     rc = load().fsimg_solve(h, _dev(b), _dev(x), ctypes.byref(st), _stream(stream))
+    if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
+        _check(rc)
+    return st.as_dict()
+
+
+def fsimg_solve_noalloc(h, b, x, stream=None, raise_on_noconv: bool = True) -> dict:
+    st = fsimg_stats()
+    rc = load().fsimg_solve_noalloc(h, _dev(b), _dev(x), ctypes.byref(st), _stream(stream))
     if rc != FSIMG_OK and (raise_on_noconv or rc != FSIMG_ERR_NOCONV):
         _check(rc)
     return st.as_dict()
