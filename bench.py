@@ -47,14 +47,40 @@ def spmv_bytes(nnzb, nrows, b, s):
 
 KERNEL_SOURCES = ("batch_kernels.hip", "device_ops.h")
 ASM_SOURCES = ("kernels_asm.hip",)
+# the batched kernel whose source keys each role's counter entry
+ROLE_KERNEL = {"vanka_patch": "kb_vanka_patch", "spmv_residual": "kb_spmv",
+               "restrict": "kb_restrict", "prolong": "kb_prolong"}
 
 
-def kernel_source_hash(sources=KERNEL_SOURCES):
-    """sha256[:16] over the sources that define the kernels measured."""
+def _function_text(src, name):
+    """the text of the first definition of `name` (up to its closing brace)"""
+    import re
+    m = re.search(r"\b" + re.escape(name) + r"\s*\(", src)
+    if not m:
+        return ""
+    i = src.index("{", m.end())
+    depth = 0
+    for j in range(i, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[j], 0)
+        if depth == 0:
+            return src[m.start():j + 1]
+    return src[m.start():]
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES, role=None):
+    """sha256[:16] over the sources that define the kernels measured: for a
+    batched-kernel role, the device functions (device_ops.h) and that
+    kernel's own definition; otherwise the whole files."""
     import hashlib
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1904_02401_amd", "csrc")
+    if role in ROLE_KERNEL:
+        h.update(open(os.path.join(csrc, "device_ops.h"), "rb").read())
+        src = open(os.path.join(csrc, "batch_kernels.hip")).read()
+        h.update(_function_text(src, ROLE_KERNEL[role]).encode())
+        return h.hexdigest()[:16]
     for f in sources:
-        h.update(open(os.path.join(ROOT, "paper_1904_02401_amd", "csrc", f), "rb").read())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -64,7 +90,7 @@ def measured_traffic(role, workload, prec, sources=KERNEL_SOURCES):
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    cur = kernel_source_hash(sources)
+    cur = kernel_source_hash(sources, role if sources == KERNEL_SOURCES else None)
     for line in open(path):
         f = line.split()
         if len(f) == 5 and not line.startswith("#") and f[:3] == [role, workload, prec]:
@@ -1108,12 +1134,24 @@ def main():
         tname = "double" if tag == "fp64" else "float"
         bm = lev.systems["mom"].b
         rpw = R["shapes"].get("mom/L0", {}).get("spmv_rows_per_wave", 1)
-        return {"vanka_patch": {"kernel": f"kb_vanka_patch<{tname}>",
-                                "GB/s": vb / v_avg / 1e9 if v_n else 0.0, "avg_ms": v_avg * 1e3,
-                                "launches": v_n, "bytes_per_launch": vb, "total_ms": v_ms},
-                "spmv_residual": {"kernel": f"kb_spmv<{bm}, {tname}, 0, {rpw}>",
-                                  "GB/s": sb / s_avg / 1e9 if s_n else 0.0, "avg_ms": s_avg * 1e3,
-                                  "launches": s_n, "bytes_per_launch": sb, "total_ms": s_ms}}
+        out = {"vanka_patch": {"kernel": f"kb_vanka_patch<{tname}>",
+                               "GB/s": vb / v_avg / 1e9 if v_n else 0.0, "avg_ms": v_avg * 1e3,
+                               "launches": v_n, "bytes_per_launch": vb, "total_ms": v_ms},
+               "spmv_residual": {"kernel": f"kb_spmv<{bm}, {tname}, 0, {rpw}>",
+                                 "GB/s": sb / s_avg / 1e9 if s_n else 0.0, "avg_ms": s_avg * 1e3,
+                                 "launches": s_n, "bytes_per_launch": sb, "total_ms": s_ms}}
+        # transfers between the finest and the next level: (N_f + N_c) b s read / written
+        # by the restriction, (2 N_f + N_c) b s by the prolongation, plus the masks
+        nf = lev.systems["mom"].nrows * bm
+        nc = P.levels[1].systems["mom"].nrows * bm
+        for key, kname, byts in (("restrict", f"kb_restrict<{bm}, {P.dim}, {tname}>", (nf + nc) * s + nc),
+                                 ("prolong", f"kb_prolong<{bm}, {P.dim}, {tname}>", (2 * nf + nc) * s + nf)):
+            ms = sum(p[f"{key}_ms"] for p in prof)
+            n = sum(p[f"{key}_launches"] for p in prof)
+            avg = ms / max(n, 1) * 1e-3
+            out[key] = {"kernel": kname, "GB/s": byts / avg / 1e9 if n else 0.0, "avg_ms": avg * 1e3,
+                        "launches": n, "bytes_per_launch": byts, "total_ms": ms}
+        return out
 
     def factor_rate(R, tag):
         # algorithmic flops of inverting one n_p x n_p matrix: 2 n_p^3
@@ -1141,10 +1179,24 @@ def main():
             out[f"{k}_solve"] = pct(v)
         return out
 
+    def solve_bandwidth(R):
+        """each solve's algorithmic device-memory bytes (fsimg_stats.bytes_moved:
+        every matrix, inverse, index and vector entry its kernels must touch)
+        over its wall time, against the 8 TB/s peak"""
+        out = {}
+        for j, k in enumerate(("mom", "mass", "ale")):
+            st = R["stats"][j]
+            if st is None or st["solve_ms"] <= 0:
+                continue
+            gbs = st["bytes_moved"] / (st["solve_ms"] * 1e-3) / 1e9
+            out[k] = {"bytes": st["bytes_moved"], "ms": st["solve_ms"], "GB/s": gbs,
+                      "frac": gbs / HBM_PEAK_GBS}
+        return out
+
     main_tag = precs[0][0]
     R = runs[main_tag]
     kr = kernel_rates(R, main_tag)
-    role = max(kr, key=lambda k: kr[k]["total_ms"])
+    role = max(("vanka_patch", "spmv_residual"), key=lambda k: kr[k]["total_ms"])
     dom = kr[role]
     traffic = measured_traffic(role, f"{args.config}-momentum-level0", main_tag)
     value = (n_mom + n_ale) / R["t_step"]
@@ -1177,10 +1229,15 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
                      "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"]},
-        "kernels": kr,
+        "kernels": {k: dict(v, traffic=measured_traffic(k, f"{args.config}-momentum-level0", main_tag))
+                    for k, v in kr.items()},
         "patch_factor": factor_rate(R, main_tag),
         "latency_ms": latency(R),
+        "solve_bandwidth": solve_bandwidth(R),
         "solve": {"momentum_converged": R["stats"][0]["status"] == fsimg.FSIMG_OK,
+                  "momentum_status": R["stats"][0]["status"],
+                  "momentum_rel_res_device": R["stats"][0]["rel_res"],
+                  "momentum_res_hist": R["stats"][0]["res_hist"],
                   "momentum_iters": R["stats"][0]["iters"], "ale_iters": R["stats"][2]["iters"],
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
                   "rel_res_momentum_fp64_host": R["rel_res_host"],
@@ -1190,7 +1247,7 @@ def main():
     if "fp64" in runs and main_tag != "fp64":
         F = runs["fp64"]
         out["fp64"] = {"value": (n_mom + n_ale) / F["t_step"], "ms_per_step": F["t_step"] * 1e3,
-                       "latency_ms": latency(F),
+                       "latency_ms": latency(F), "solve_bandwidth": solve_bandwidth(F),
                        "momentum_iters": F["stats"][0]["iters"], "ale_iters": F["stats"][2]["iters"],
                        "rel_res_momentum_fp64_host": F["rel_res_host"],
                        "kernels": kernel_rates(F, "fp64")}

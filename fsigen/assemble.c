@@ -115,7 +115,64 @@ typedef struct {
   int cells[3];
   int nnode[3];
   const double *coords[3];
+  const double *xyz; /* NULL: node coordinates from the per-axis grid; else
+                        [nnodes][dim] (isoparametric Q2 cells) */
 } mesh_t;
+
+/* Geometry of element (nodes) at reference point q: weight w_q det(dx/dxi)
+   and the physical basis gradients dNp = (dx/dxi)^-T dN.  Rectilinear cells
+   (xyz NULL): dx/dxi = diag(h). */
+static int point_geometry(const mesh_t *m, const ref_tables *T, const int64_t *nodes,
+                          const double *h, int q, double *wq, double dNp[MAXN][MAXD]) {
+  const int d = m->dim, nn = T->nn;
+  if (!m->xyz) {
+    double vol = 1.0;
+    for (int a = 0; a < d; ++a) vol *= h[a];
+    *wq = T->w[q] * vol;
+    for (int i = 0; i < nn; ++i)
+      for (int k = 0; k < d; ++k) dNp[i][k] = T->dN[q][i][k] / h[k];
+    return 0;
+  }
+  double Jg[MAXD][MAXD], Ji[MAXD][MAXD];
+  for (int c = 0; c < d; ++c)
+    for (int k = 0; k < d; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < nn; ++i) s += m->xyz[nodes[i] * d + c] * T->dN[q][i][k];
+      Jg[c][k] = s; /* d x_c / d xi_k */
+    }
+  const double det = det_d(d, Jg);
+  inv_d(d, Jg, Ji); /* Ji[k][c] = d xi_k / d x_c */
+  *wq = T->w[q] * det;
+  for (int i = 0; i < nn; ++i)
+    for (int c = 0; c < d; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += T->dN[q][i][k] * Ji[k][c];
+      dNp[i][c] = s;
+    }
+  return det > 0.0 ? 0 : -1;
+}
+
+/* h_K: the longest of the d cell edges from the first corner (rectilinear:
+   the longest side) */
+static double cell_size(const mesh_t *m, const int64_t *nodes, const double *h) {
+  const int d = m->dim;
+  double hK = 0.0;
+  if (!m->xyz) {
+    for (int a = 0; a < d; ++a) if (h[a] > hK) hK = h[a];
+    return hK;
+  }
+  for (int a = 0; a < d; ++a) {
+    const int corner = 2 * (a == 0 ? 1 : (a == 1 ? 3 : 9));
+    double s = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double e = m->xyz[nodes[corner] * d + c] - m->xyz[nodes[0] * d + c];
+      s += e * e;
+    }
+    s = sqrt(s);
+    if (s > hK) hK = s;
+  }
+  return hK;
+}
 
 /* element e (lexicographic) -> its 3^d node indices, per-axis sizes h */
 static void element_nodes(const mesh_t *m, int64_t e, int64_t *nodes, double *h) {
@@ -227,7 +284,8 @@ static void scatter_block(double *vals, int b, const int32_t *rowptr, const int3
  * Returns 0, or -1 if det F <= 0 at some Gauss point.
  */
 int fsigen_assemble(int dim, const int *cells, const double *cx, const double *cy,
-                    const double *cz, const uint8_t *cell_solid, const double *v_old,
+                    const double *cz, const double *xyz, const uint8_t *cell_solid,
+                    const double *v_old,
                     const double *u_old, const double *v_cur, const double *u_cur,
                     const double *params, const int32_t *rowptr, const int32_t *colind,
                     double *vals_mom, double *vals_ale, double *vals_mass,
@@ -238,6 +296,7 @@ int fsigen_assemble(int dim, const int *cells, const double *cx, const double *c
   mesh_t M;
   M.dim = dim;
   M.coords[0] = cx; M.coords[1] = cy; M.coords[2] = cz;
+  M.xyz = xyz;
   int64_t ncell = 1;
   for (int a = 0; a < 3; ++a) {
     M.cells[a] = a < dim ? cells[a] : 1;
@@ -262,8 +321,7 @@ int fsigen_assemble(int dim, const int *cells, const double *cx, const double *c
       int64_t nodes[MAXN];
       double h[3];
       element_nodes(&M, e, nodes, h);
-      double vol = 1.0, hK = 0.0;
-      for (int a = 0; a < d; ++a) { vol *= h[a]; if (h[a] > hK) hK = h[a]; }
+      const double hK = cell_size(&M, nodes, h);
       const int solid = cell_solid[e] != 0;
       double Km[MAXN * 4 * MAXN * 4];
       double Ka[MAXN * 3 * MAXN * 3];
@@ -273,10 +331,8 @@ int fsigen_assemble(int dim, const int *cells, const double *cx, const double *c
       memset(Ks, 0, sizeof(double) * nn * nn);
       const int ldm = nn * bm, lda = nn * d;
       for (int q = 0; q < nq; ++q) {
-        const double wq = T.w[q] * vol;
-        double dNp[MAXN][MAXD];
-        for (int i = 0; i < nn; ++i)
-          for (int m = 0; m < d; ++m) dNp[i][m] = T.dN[q][i][m] / h[m];
+        double wq, dNp[MAXN][MAXD];
+        if (point_geometry(&M, &T, nodes, h, q, &wq, dNp)) bad = -1;
         const double *Nq = T.N[q];
         for (int i = 0; i < nn; ++i)
           for (int j = 0; j < nn; ++j) Ks[i * nn + j] += wq * Nq[i] * Nq[j];
@@ -419,7 +475,8 @@ int fsigen_assemble(int dim, const int *cells, const double *cx, const double *c
  * condensation u = u_old + k theta v + k (1-theta) v_old.
  */
 int fsigen_residual(int dim, const int *cells, const double *cx, const double *cy,
-                    const double *cz, const uint8_t *cell_solid, const double *v_old,
+                    const double *cz, const double *xyz, const uint8_t *cell_solid,
+                    const double *v_old,
                     const double *u_old, const double *u_frz, const double *v,
                     const double *p, const double *params, double *res) {
   phys_params P = {params[0], params[1], params[2], params[3],
@@ -427,6 +484,7 @@ int fsigen_residual(int dim, const int *cells, const double *cx, const double *c
   mesh_t M;
   M.dim = dim;
   M.coords[0] = cx; M.coords[1] = cy; M.coords[2] = cz;
+  M.xyz = xyz;
   int64_t ncell = 1, nnodes = 1;
   for (int a = 0; a < 3; ++a) {
     M.cells[a] = a < dim ? cells[a] : 1;
@@ -445,14 +503,11 @@ int fsigen_residual(int dim, const int *cells, const double *cx, const double *c
     int64_t nodes[MAXN];
     double h[3];
     element_nodes(&M, e, nodes, h);
-    double vol = 1.0, hK = 0.0;
-    for (int a = 0; a < d; ++a) { vol *= h[a]; if (h[a] > hK) hK = h[a]; }
+    const double hK = cell_size(&M, nodes, h);
     const int solid = cell_solid[e] != 0;
     for (int q = 0; q < T.nq; ++q) {
-      const double wq = T.w[q] * vol;
-      double dNp[MAXN][MAXD];
-      for (int i = 0; i < nn; ++i)
-        for (int m = 0; m < d; ++m) dNp[i][m] = T.dN[q][i][m] / h[m];
+      double wq, dNp[MAXN][MAXD];
+      (void)point_geometry(&M, &T, nodes, h, q, &wq, dNp);
       const double *Nq = T.N[q];
       double vv[MAXD], gv[MAXD][MAXD], vo[MAXD], gvo[MAXD][MAXD];
       double u[MAXD], gu[MAXD][MAXD], uo[MAXD], guo[MAXD][MAXD];

@@ -67,9 +67,9 @@ def _native():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.fsigen_pattern.argtypes = [ctypes.c_int, P, P, P]
-        lib.fsigen_assemble.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P,
+        lib.fsigen_assemble.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P,
                                         P, P, P, P, ctypes.c_int]
-        lib.fsigen_residual.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.fsigen_residual.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -108,6 +108,8 @@ class Level:
     node_bdry: np.ndarray   # uint8 [nnodes]: bit a = on face x_a=0, bit a+3 = on x_a=1
     systems: dict = field(default_factory=dict)  # "mom", "ale", "mass" -> BSR
     node_rigid: np.ndarray = None  # bool [nnodes]: touches a rigid obstacle cell
+    node_coords: np.ndarray = None  # [nnodes, dim] float64: isoparametric node positions
+                                    # (None: the tensor grid of `coords`)
 
     @property
     def nnodes(self) -> int:
@@ -266,13 +268,16 @@ def _compress(rowptr, colind, vals):
 
 
 def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom", "ale", "mass"),
-               need_smass=False, rigid_box=None):
+               need_smass=False, rigid_box=None, node_coords=None):
     """Assemble the requested systems on one level.
 
     state_nodal: dict of nodal [nnodes, dim] arrays v_old, u_old, v_cur, u_cur.
     rigid_box: cells whose centroid lies inside it form a rigid obstacle: they
     are flagged solid and every node touching them has the velocity held
     (no-slip), so with zero velocity there they contribute nothing.
+    node_coords: [nnodes, dim] positions of the nodes (isoparametric Q2
+    cells); the cell and node flags still come from the tensor grid `coords`
+    (the mesh's reference positions).
     """
     lib = _native()
     cells = tuple(int(c) for c in cells)
@@ -318,9 +323,12 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
         e[-1] |= 1 << (a + 3)
         per_axis[a] = e
         node_bdry |= _tensor(per_axis, dim).astype(np.uint8)
+    xyz = None if node_coords is None else np.ascontiguousarray(node_coords, dtype=np.float64)
+    if xyz is not None and xyz.shape != (nnodes, dim):
+        raise ValueError("node_coords must be [nnodes, dim]")
     lev = Level(dim=dim, cells=cells, coords=[np.asarray(c) for c in coords], cell_solid=cell_solid,
                 node_solid=node_solid, node_fluid=node_fluid, node_bdry=node_bdry,
-                node_rigid=node_rigid)
+                node_rigid=node_rigid, node_coords=xyz)
 
     rowptr, colind = _pattern(dim, cells)
     nnzb = colind.shape[0]
@@ -333,12 +341,13 @@ def make_level(dim, cells, coords, solid_box, state_nodal, params, systems=("mom
     va = np.zeros((nnzb, dim, dim)) if "ale" in systems else None
     vs = np.zeros((nnzb, dim, dim)) if "mass" in systems else None
     vsm = np.zeros(nnzb) if need_smass else None
-    rc = lib.fsigen_assemble(dim, _ptr(cells_c), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(cell_solid),
+    rc = lib.fsigen_assemble(dim, _ptr(cells_c), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(xyz), _ptr(cell_solid),
                              _ptr(st["v_old"]), _ptr(st["u_old"]), _ptr(st["v_cur"]),
                              _ptr(st["u_cur"]), _ptr(pv), _ptr(rowptr), _ptr(colind), _ptr(vm),
                              _ptr(va), _ptr(vs), _ptr(vsm), _nthreads())
     if rc != 0:
-        raise ValueError("det F <= 0 at a Gauss point: state amplitude too large")
+        raise ValueError("det F <= 0 (state amplitude too large) or det(dx/dxi) <= 0 (a mapped "
+                         "cell inverted) at a Gauss point")
     rows = _row_of_block(rowptr)
     diag = np.nonzero(colind == rows)[0]
     walls = np.zeros(nnodes, dtype=bool)
@@ -458,7 +467,8 @@ def residual_momentum(lev: Level, params, v_old, u_old, u_frz, v, pres):
     cx, cy, cz = _coords_c(lev.coords, dim)
     res = np.zeros((lev.nnodes, dim + 1))
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (v_old, u_old, u_frz, v, pres)]
-    lib.fsigen_residual(dim, _ptr(cells_c), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(lev.cell_solid),
+    lib.fsigen_residual(dim, _ptr(cells_c), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(lev.node_coords),
+                        _ptr(lev.cell_solid),
                         *[_ptr(a) for a in arrs], _ptr(_params_vec(params)), _ptr(res))
     return res.ravel()
 
@@ -575,11 +585,54 @@ def inflow_ramp(t):
     return 0.5 - 0.5 * np.cos(np.pi * t) if t < 1.0 else 1.0
 
 
-def make_channel(dim: int, nlev: int, params=None, coarse=None) -> Channel:
+# The curved channel (isoparametric Q2 cells): the cylinder of radius 0.05
+# around (0.5, 0.2) and, away from obstacle and beam, rows of even height.
+CYL_CENTER = (0.5, 0.2)
+CYL_RADIUS = 0.05
+CYL_RING = 0.1          # the map blends back to the identity at this L-inf distance
+RELAX_Y = ([0.0, 0.15, 0.19, 0.21, 0.25, 0.41], [0.0, 0.082, 0.164, 0.246, 0.328, 0.41])
+RELAX_X = (0.2, 0.35, 1.05, 1.4)  # weight 1 | ramp | 0 (obstacle and beam) | ramp | 1
+
+
+def channel_map(X: np.ndarray) -> np.ndarray:
+    """Node positions of the curved channel from the rectilinear ones
+    [n, dim] (z, if present, unchanged).
+
+    1. Rows of even height away from obstacle and beam: y' = y + w(x) (g(y) -
+       y), g piecewise linear from the row breaks 0, 0.15, 0.19, 0.21, 0.25,
+       0.41 to five rows of height 0.082, w = 1 for x <= 0.2 and x >= 1.4, 0
+       for 0.35 <= x <= 1.05, linear between (for every x, y' is increasing
+       in y).
+    2. The square obstacle onto the cylinder: with r the offset from the
+       centre (0.5, 0.2) and s = |r|_inf, a point moves to centre + r (beta
+       s / |r|_2 + 1 - beta), beta = 1 for s <= 0.05 (the square of L-inf
+       radius s onto the circle of radius s), falling linearly to 0 at s = 0.1
+       (identity beyond).  Along every ray from the centre the new distance
+       grows with the old one, so the map is one to one; the beam's root face
+       x = 0.55 lands on the circle."""
+    X = np.array(X, dtype=np.float64)
+    x, y = X[:, 0].copy(), X[:, 1].copy()
+    a0, a1, a2, a3 = RELAX_X
+    w = np.maximum(np.clip((a1 - x) / (a1 - a0), 0.0, 1.0), np.clip((x - a2) / (a3 - a2), 0.0, 1.0))
+    y = y + w * (np.interp(y, *RELAX_Y) - y)
+    rx, ry = x - CYL_CENTER[0], y - CYL_CENTER[1]
+    sinf = np.maximum(np.abs(rx), np.abs(ry))
+    r2 = np.hypot(rx, ry)
+    beta = np.clip((CYL_RING - sinf) / (CYL_RING - CYL_RADIUS), 0.0, 1.0)
+    scale = np.where(r2 > 0, beta * sinf / np.where(r2 > 0, r2, 1.0) + 1.0 - beta, 1.0)
+    X[:, 0] = CYL_CENTER[0] + rx * scale
+    X[:, 1] = CYL_CENTER[1] + ry * scale
+    return X
+
+
+def make_channel(dim: int, nlev: int, params=None, coarse=None, curved: bool = False) -> Channel:
     """The benchmark channel with nlev levels (coarsest: CHANNEL_COARSE cells
     per axis, graded so that every level resolves the obstacle and beam
     faces), at rest (v = u = 0): momentum and ALE systems assembled at that
-    state, no right-hand sides."""
+    state, no right-hand sides.  curved: isoparametric Q2 cells whose nodes
+    channel_map moves (the cylinder of radius 0.05, rows of even height away
+    from obstacle and beam); the mesh topology, flags and levels are those of
+    the rectilinear channel."""
     p = dict(CHANNEL_PARAMS)
     if params:
         p.update(params)
@@ -594,14 +647,15 @@ def make_channel(dim: int, nlev: int, params=None, coarse=None) -> Channel:
         zero = np.zeros((n, dim))
         st = dict(v_old=zero, u_old=zero, v_cur=zero, u_cur=zero)
         cells = tuple(len(verts[a][l]) - 1 for a in range(dim))
+        xyz = channel_map(_grid_coords(coords, dim)) if curved else None
         levels.append(make_level(dim, cells, coords, beam, st, p, systems=("mom", "ale"),
-                                 rigid_box=obst))
+                                 rigid_box=obst, node_coords=xyz))
     fine = levels[0]
     nn = fine.nnodes
     zero = np.zeros((nn, dim))
     P = Problem(dim=dim, params=p, seed=0, levels=levels, v_old=zero, u_old=zero.copy(),
                 v_cur=zero.copy(), u_cur=zero.copy(), rhs={}, solid_box=beam)
-    X = _grid_coords(fine.coords, dim)
+    X = fine.node_coords if curved else _grid_coords(fine.coords, dim)
     node = np.nonzero(fine.node_bdry & 1)[0]           # the face x = 0
     vbar = CHANNEL_VBAR[dim]
     vals = inflow_profile(dim, X[node, 1], X[node, 2] if dim == 3 else None, vbar)

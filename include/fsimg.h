@@ -133,6 +133,8 @@ typedef struct {
   double omega_ilu;    /* ILU damping (default 1: the undamped incomplete-LU step) */
 } fsimg_opts;
 
+#define FSIMG_HIST 64  /* residual-history entries in fsimg_stats */
+
 typedef struct {
   int status;          /* fsimg_status of the solve */
   int iters;           /* FGMRES iterations (= V-cycles) */
@@ -143,6 +145,19 @@ typedef struct {
      level's Vanka patch kernel and residual SpMV kernel */
   double vanka_ms; int vanka_launches;
   double spmv_ms; int spmv_launches;
+  /* profile == 1, GATHER schedule: the same for the restriction from and the
+     prolongation to the finest level */
+  double restrict_ms; int restrict_launches;
+  double prolong_ms; int prolong_launches;
+  double setup_ms;     /* host wall time of this hierarchy's fsimg_hier_create */
+  double factor_ms;    /* host wall time of its last fsimg_factor (stream synchronised) */
+  double bytes_moved;  /* algorithmic device-memory bytes of the solve's kernels: every matrix,
+                          inverse, index and vector entry each kernel must read or write once
+                          (SpMV, Vanka patch and gather, transfers, coarse GEMV, Krylov vector
+                          operations), summed over the solve's iterations */
+  int nhist;           /* entries of res_hist */
+  double res_hist[FSIMG_HIST];  /* |g_{j+1}| / ||r_0||: the FGMRES residual estimate after
+                                   iteration j + 1, for the first FSIMG_HIST iterations */
 } fsimg_stats;
 
 typedef struct {

@@ -77,8 +77,12 @@ def element_nodes(cells, dim):
 
 
 class Mesh:
-    """Geometry of one level of the tensor Q2 mesh: per-axis node coordinates,
-    solid cells, element node lists, cell sizes."""
+    """Geometry of one level of the Q2 mesh: solid cells, element node lists
+    and the map of every cell from the reference cell.  Rectilinear levels
+    (per-axis node coordinates) map each cell by x = x_0 + h xi; levels with
+    node positions (isoparametric Q2 cells, Sec. 5's curved cylinder) by
+    x(xi) = sum_i x_i N_i(xi), whose Jacobian dx/dxi, its inverse and its
+    determinant are taken at every Gauss point."""
 
     def __init__(self, level):
         self.dim = level.dim
@@ -92,6 +96,33 @@ class Mesh:
         self.node_solid = np.zeros(self.nnodes, dtype=bool)
         self.node_solid[self.nodes[self.solid].ravel()] = True
         self.N, self.dNref, self.w = reference_tables(self.dim)
+        xyz = getattr(level, "node_coords", None)
+        if xyz is None:
+            self.Ji = self.detJ = None
+            self.hK = self.h.max(axis=1)
+        else:
+            Xe = np.asarray(xyz, dtype=np.float64)[self.nodes]           # [e, i, c]
+            Jg = np.einsum("eic,qim->eqcm", Xe, self.dNref)              # dx_c / dxi_m
+            self.detJ = np.linalg.det(Jg)                                # [e, q]
+            self.Ji = np.linalg.inv(Jg)                                  # [e, q, m, c] = dxi_m / dx_c
+            # h_K: the longest cell edge from the first corner (local nodes 2, 6, 18)
+            corner = [2 * 3 ** a for a in range(self.dim)]
+            self.hK = np.max([np.linalg.norm(Xe[:, c] - Xe[:, 0], axis=1) for c in corner], axis=0)
+
+
+def grad_basis(mesh):
+    """Physical basis gradients dN[e, q, i, m] = d N_i / d x_m at the Gauss
+    points: (dx/dxi)^-T applied to the reference gradients."""
+    if mesh.Ji is None:
+        return mesh.dNref[None] / mesh.h[:, None, None, :]
+    return np.einsum("qik,eqkm->eqim", mesh.dNref, mesh.Ji)
+
+
+def point_weights(mesh):
+    """Quadrature weights times det(dx/dxi): wq[e, q]."""
+    if mesh.Ji is None:
+        return mesh.w[None, :] * np.prod(mesh.h, axis=1)[:, None]
+    return mesh.w[None, :] * mesh.detJ
 
 
 def _mv(A, x):
@@ -109,6 +140,10 @@ def element_subset(mesh, elems):
     sub.solid = mesh.solid[elems]
     sub.nodes = mesh.nodes[elems]
     sub.h = mesh.h[elems]
+    sub.hK = mesh.hK[elems]
+    if mesh.Ji is not None:
+        sub.Ji = mesh.Ji[elems]
+        sub.detJ = mesh.detJ[elems]
     return sub
 
 
@@ -132,7 +167,7 @@ def _fields(mesh, prm, pe, ve, ue, vo, uo):
     k, th = prm["k"], prm["theta"]
     uc = np.where(mesh.solid[:, None, None], uo + k * th * ve + k * (1 - th) * vo, ue)
     N = mesh.N                                             # [q, i]
-    dN = mesh.dNref[None] / mesh.h[:, None, None, :]       # [e, q, i, m]
+    dN = grad_basis(mesh)       # [e, q, i, m]
 
     def val(f):
         return np.einsum("qi,eic->eqc", N, f)[None]
@@ -215,8 +250,8 @@ def _terms(mesh, prm, f, geo=None):
     d = mesh.dim
     k, th, rf, nu = prm["k"], prm["theta"], prm["rho_f"], prm["nu_f"]
     N = mesh.N
-    dN = mesh.dNref[None] / mesh.h[:, None, None, :]       # [e, q, i, m]
-    wq = mesh.w[None, :] * np.prod(mesh.h, axis=1)[:, None]   # [e, q]
+    dN = grad_basis(mesh)       # [e, q, i, m]
+    wq = point_weights(mesh)   # [e, q]
     B, ne, nq = f["p"].shape
     nn = N.shape[1]
     dt = np.result_type(*[a.dtype for a in f.values()])
@@ -231,7 +266,7 @@ def _terms(mesh, prm, f, geo=None):
         vec[:, fl], ten[:, fl], div[:, fl] = _fluid(prm, d, ff, geo)
     if so.size:
         vec[:, so], ten[:, so] = _solid(prm, d, {key: a[:, so] for key, a in f.items()})
-    hK = mesh.h.max(axis=1)
+    hK = mesh.hK
     dK = prm["alpha0"] * k * k * hK ** 2 / (rf * (hK ** 2 + k * th * nu))
     dK = np.where(mesh.solid, 0.0, dK)
     # sum over Gauss points q (and the gradient index b) against the test
@@ -286,7 +321,7 @@ def element_jacobians(mesh, prm, x, u, x_old, u_old, h=1e-30):
     fl = np.nonzero(~mesh.solid)[0]
     geo = _fluid_geometry(prm, d, {key: a[:, fl] for key, a in base.items()}) if fl.size else None
     N = mesh.N
-    dN = mesh.dNref[None] / mesh.h[:, None, None, :]
+    dN = grad_basis(mesh)
     sol = mesh.solid[:, None]
     ne, nn = dN.shape[0], N.shape[1]
     K = np.zeros((ne, nn, d + 1, nn, d + 1))

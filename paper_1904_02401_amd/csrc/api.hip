@@ -743,6 +743,7 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
                                const fsimg_opts *opts, void *stream, fsimg_hier **out) {
   if (!ctx || !out) return fail(FSIMG_ERR_ARG, "null argument");
   *out = nullptr;
+  const auto t_create = std::chrono::steady_clock::now();
   FSIMG_TRY(validate_opts(opts));
   FSIMG_TRY(validate_levels(levels, nlev));
   FSIMG_HIP(hipSetDevice(ctx->device));
@@ -920,6 +921,7 @@ fsimg_status fsimg_hier_create(fsimg_ctx *ctx, const fsimg_level_desc *levels, i
   FSIMG_HIPC(hipStreamSynchronize(s));
 #undef FSIMG_CHK
 #undef FSIMG_HIPC
+  h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_create).count();
   *out = h;
   return FSIMG_OK;
 }
@@ -970,8 +972,17 @@ fsimg_status fsimg_hier_update_values(fsimg_hier *h, int level, const double *va
   return FSIMG_OK;
 }
 
+static fsimg_status factor_impl(fsimg_hier *h, void *stream);
+
 fsimg_status fsimg_factor(fsimg_hier *h, void *stream) {
   if (!h) return fail(FSIMG_ERR_ARG, "null hierarchy");
+  const auto t0 = std::chrono::steady_clock::now();
+  const fsimg_status st = factor_impl(h, stream);
+  h->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+static fsimg_status factor_impl(fsimg_hier *h, void *stream) {
   FSIMG_HIP(hipSetDevice(h->ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool mixed = hier_mixed(h);
@@ -1225,6 +1236,7 @@ fsimg_status fsimg_solve(fsimg_hier *h, const double *b, double *x, fsimg_stats 
       g[j] = cs[j] * g[j];
       ++it;
       k = j + 1;
+      if (st.nhist < FSIMG_HIST) st.res_hist[st.nhist++] = std::fabs(g[j + 1]) / beta0;
       if (!std::isfinite(g[j + 1])) break;
       if (std::fabs(g[j + 1]) <= tol || it >= h->opts.max_iter || hn == 0.0) break;
     }
@@ -1249,6 +1261,8 @@ fsimg_status fsimg_solve(fsimg_hier *h, const double *b, double *x, fsimg_stats 
   st.iters = it;
   st.restarts = restarts;
   st.rel_res = beta0 > 0.0 ? rnorm / beta0 : 0.0;
+  st.setup_ms = h->setup_ms;
+  st.factor_ms = h->factor_ms;
   if (st.status == FSIMG_OK && !converged) st.status = FSIMG_ERR_NOCONV;
   if (h->profiling) {
     FSIMG_HIP(hipStreamSynchronize(s));

@@ -42,7 +42,7 @@ struct BatchPlan {
   std::vector<DKry> hkry;
   double *hs_host = nullptr;
   int *int_host = nullptr;  // active | kcnt | flags staging, 3n ints
-  EventTimer tv, ts;
+  EventTimer tv, ts, tr, tp;  // finest level: Vanka, SpMV, restriction, prolongation
   // FGMRES iteration j (copy-in, V-cycle, copy-out, A z_j, CGS2, norm, scale,
   // Hessenberg column to the host) captured once per j and replayed
   hipStream_t cap = nullptr;
@@ -362,7 +362,11 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
       if (a) (void)hipEventRecord(a, s);
       launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
       if (b2) (void)hipEventRecord(b2, s);
+      hipEvent_t r0 = p0 ? P.tr.next() : nullptr;
+      hipEvent_t r1 = p0 ? P.tr.next() : nullptr;
+      if (r0) (void)hipEventRecord(r0, s);
       launch_b_restrict<T>(P.b, P.dim, L, L + n, act, P.ws_restrict[l], s);
+      if (r1) (void)hipEventRecord(r1, s);
     }
     if (P.ws_cn[l].nset > 0) launch_b_coarse<T>(L, act, P.ws_cn[l], P.ws_cf[l], s);
   }
@@ -370,7 +374,11 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
     if (P.ws_prolong[l].nset == 0) continue;
     const DLev *L = P.dlev + (size_t)l * n;
     const bool p0 = prof && l == 0;
+    hipEvent_t q0 = p0 ? P.tp.next() : nullptr;
+    hipEvent_t q1 = p0 ? P.tp.next() : nullptr;
+    if (q0) (void)hipEventRecord(q0, s);
     launch_b_prolong<T>(P.b, P.dim, L, L + n, act, P.ws_prolong[l], s);
+    if (q1) (void)hipEventRecord(q1, s);
     for (int k = 0; k < o.nu_post; ++k) {
       hipEvent_t a = p0 ? P.ts.next() : nullptr;
       hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
@@ -452,11 +460,54 @@ hipError_t fetch_async(BatchPlan &P, hipStream_t s) {
 }
 
 struct InstState {
-  double beta0 = 0, tol = 0, rnorm = 0;
+  double beta0 = 0, tol = 0, rnorm = 0, bytes = 0;
   int it = 0, restarts = 0, k = 0, status = FSIMG_OK;
   bool done = false, in_cycle = false;
-  std::vector<double> H, cs, sn, g, y;
+  std::vector<double> H, cs, sn, g, y, hist;
 };
+
+// Algorithmic device-memory bytes (every entry a kernel must touch, once)
+// of the solve's kernels: level l's residual SpMV, Vanka patch kernel +
+// gather, restriction / prolongation; w = word bytes of the V-cycle.
+double spmv_bytes_of(const DevLevel &L, double w) {
+  return (double)L.nnzb * (L.b * L.b * w + 4) + 4.0 * (L.nrows + 1) + 3.0 * L.n * w + (double)L.n;
+}
+double smooth_bytes_of(const DevLevel &L, double w) {
+  const int npc = w == 4 ? L.npc32 : L.npc64;
+  const int npc2 = w == 4 ? L.blk.npc32 : L.blk.npc64;
+  const double patch = (double)L.npatch * (L.np * (double)npc * w + 2.0 * L.np * w + L.nl * 4.0) +
+                       (double)L.blk.npatch * (L.blk.np * (double)npc2 * w + 2.0 * L.blk.np * w + L.blk.nl * 4.0);
+  const double slots = (double)L.npatch * L.nl + (double)L.blk.npatch * L.blk.nl;
+  const double gather = slots * L.b * w + 4.0 * (L.nrows + 1) + 4.0 * slots + 3.0 * L.n * w + (double)L.n;
+  return patch + gather;
+}
+double vcycle_bytes_of(const fsimg_hier *h) {
+  const double w = h->opts.precision == FSIMG_MIXED ? 4.0 : 8.0;
+  const int L = (int)h->lev.size(), nu1 = h->opts.nu_pre, nu2 = h->opts.nu_post;
+  double t = 0.0;
+  for (int l = 0; l + 1 < L; ++l) {
+    const DevLevel &F = h->lev[l], &C = h->lev[l + 1];
+    const int nres = (nu1 > 0 ? nu1 - 1 : 0) + 1 + nu2;
+    t += (nu1 + nu2) * smooth_bytes_of(F, w) + nres * spmv_bytes_of(F, w);
+    t += (double)(F.n + C.n) * w + C.n;            // restriction
+    t += (double)(2 * F.n + C.n) * w + F.n;        // prolongation
+  }
+  const DevLevel &C = h->lev.back();
+  t += (double)C.nfree * C.nfree * 8.0 + 2.0 * C.n * 8.0 + (w == 4 ? 2.0 * C.n * (4 + 8) : 0.0);
+  if (w == 4) t += 2.0 * h->lev[0].n * (8 + 4);    // FP64 <-> FP32 copies of v_j and z_j
+  return t;
+}
+// one FGMRES iteration j: V-cycle, A z_j (FP64), two Gram-Schmidt passes,
+// the norm and the scaling of v_{j+1}
+double iteration_bytes_of(const fsimg_hier *h, int j) {
+  const DevLevel &F = h->lev[0];
+  return vcycle_bytes_of(h) + spmv_bytes_of(F, 8.0) + (3.0 * (j + 1) + 8.0) * F.n * 8.0;
+}
+// the end of a restart cycle with k directions: x += Z y, true residual, norm
+double restart_bytes_of(const fsimg_hier *h, int k) {
+  const DevLevel &F = h->lev[0];
+  return (k + 2.0) * F.n * 8.0 + spmv_bytes_of(F, 8.0) + F.n * 8.0;
+}
 
 // the cached descriptor tables of this batch composition (built on first
 // use), moved to the front of the context's LRU list
@@ -538,6 +589,8 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
   const auto t0 = std::chrono::steady_clock::now();
   P->tv.begin_solve();
   P->ts.begin_solve();
+  P->tr.begin_solve();
+  P->tp.begin_solve();
   const int m = o.restart;
   for (int i = 0; i < n; ++i) {
     fsimg_hier *h = hs[i];
@@ -585,6 +638,7 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
     InstState &q = S[i];
     q.beta0 = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
     q.rnorm = q.beta0;
+    q.bytes = spmv_bytes_of(hs[i]->lev[0], 8.0) + 2.0 * hs[i]->lev[0].n * 8.0;  // r_0, its checks
     q.tol = o.rtol * q.beta0;
     if (fl_h[i] || !std::isfinite(q.beta0)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
     else if (q.beta0 == 0.0) q.done = true;
@@ -641,6 +695,8 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
         q.g[j] = q.cs[j] * q.g[j];
         ++q.it;
         q.k = j + 1;
+        q.bytes += iteration_bytes_of(hs[i], j);
+        if ((int)q.hist.size() < FSIMG_HIST) q.hist.push_back(std::fabs(q.g[j + 1]) / q.beta0);
         if (!std::isfinite(q.g[j + 1]) || std::fabs(q.g[j + 1]) <= q.tol || q.it >= o.max_iter ||
             hn == 0.0) {
           act_h[i] = 0;
@@ -678,6 +734,7 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
       InstState &q = S[i];
       if (!q.in_cycle) continue;
       ++q.restarts;
+      q.bytes += restart_bytes_of(hs[i], q.k);
       q.rnorm = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
       if (!std::isfinite(q.rnorm)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
       else if (q.rnorm <= q.tol) q.done = true;
@@ -685,12 +742,14 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
     }
   }
   FSIMG_BHIP(hipGetLastError());
-  double vms = 0.0, sms = 0.0;
-  int vn = 0, sn = 0;
+  double vms = 0.0, sms = 0.0, rms = 0.0, pms = 0.0;
+  int vn = 0, sn = 0, rn = 0, pn = 0;
   if (prof) {
     FSIMG_BHIP(hipStreamSynchronize(s));
     vms = P->tv.total_ms(&vn);
     sms = P->ts.total_ms(&sn);
+    rms = P->tr.total_ms(&rn);
+    pms = P->tp.total_ms(&pn);
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   fsimg_status ret = FSIMG_OK;
@@ -706,6 +765,13 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
       st.solve_ms = ms;
       st.vanka_ms = vms; st.vanka_launches = vn;
       st.spmv_ms = sms; st.spmv_launches = sn;
+      st.restrict_ms = rms; st.restrict_launches = rn;
+      st.prolong_ms = pms; st.prolong_launches = pn;
+      st.setup_ms = hs[i]->setup_ms;
+      st.factor_ms = hs[i]->factor_ms;
+      st.bytes_moved = q.bytes;
+      st.nhist = (int)q.hist.size();
+      for (int t = 0; t < st.nhist; ++t) st.res_hist[t] = q.hist[t];
     }
     if (ret == FSIMG_OK && q.status != FSIMG_OK) ret = (fsimg_status)q.status;
   }

@@ -64,6 +64,7 @@ struct fsimg_hier {
   std::vector<std::vector<uint8_t>> host_mask;
   std::vector<std::vector<uint8_t>> host_class;
   bool factored = false;
+  double setup_ms = 0.0, factor_ms = 0.0;  // host wall time of create / the last factor
   int m = 20;
   // FGMRES workspace (FP64)
   double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *small = nullptr;

@@ -53,14 +53,24 @@ class fsimg_opts(ctypes.Structure):
                 ("smoother", ctypes.c_int), ("omega_ilu", ctypes.c_double)]
 
 
+FSIMG_HIST = 64
+
+
 class fsimg_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("rel_res", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("vanka_ms", ctypes.c_double), ("vanka_launches", ctypes.c_int),
-                ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int)]
+                ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int),
+                ("restrict_ms", ctypes.c_double), ("restrict_launches", ctypes.c_int),
+                ("prolong_ms", ctypes.c_double), ("prolong_launches", ctypes.c_int),
+                ("setup_ms", ctypes.c_double), ("factor_ms", ctypes.c_double),
+                ("bytes_moved", ctypes.c_double), ("nhist", ctypes.c_int),
+                ("res_hist", ctypes.c_double * FSIMG_HIST)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "res_hist"}
+        d["res_hist"] = [self.res_hist[i] for i in range(self.nhist)]
+        return d
 
 
 class fsimg_request(ctypes.Structure):

@@ -381,3 +381,26 @@ def test_deterministic_repeat(ctx, probs):
             fsimg.fsimg_solve(H.h, _t(P.rhs["mom"]), x)
             xs.append(_np(x))
     np.testing.assert_array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("schedule", [fsimg.FSIMG_VANKA_GATHER, fsimg.FSIMG_VANKA_PARITY])
+def test_solve_stats_fields(ctx, probs, schedule):
+    """The statistics of a solve: setup and factorisation wall times, the
+    residual history (one FGMRES estimate per iteration, ending at the
+    tolerance) and the algorithmic bytes (batched path: between the bytes of
+    `iters` V-cycles alone and three times that)."""
+    P = probs["t3"]
+    with Hier(ctx, P, "mom", vanka_schedule=schedule) as H:
+        fsimg.fsimg_factor(H.h)
+        x = torch.zeros(P.rhs["mom"].shape[0], device=DEV, dtype=torch.float64)
+        st = fsimg.fsimg_solve(H.h, _t(P.rhs["mom"]), x)
+    assert st["setup_ms"] > 0 and st["factor_ms"] > 0
+    hist = st["res_hist"]
+    assert len(hist) == min(st["iters"], fsimg.FSIMG_HIST) == st["nhist"]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))  # GMRES: non-increasing
+    assert hist[-1] <= 1e-8 < hist[0]
+    if schedule == fsimg.FSIMG_VANKA_GATHER:
+        lev = P.levels[0].systems["mom"]
+        A_bytes = lev.nnzb * 16 * 8
+        assert st["bytes_moved"] > st["iters"] * 4 * A_bytes  # >= 4 residual SpMVs per V-cycle
+        assert st["bytes_moved"] < st["iters"] * 200 * A_bytes
