@@ -302,7 +302,11 @@ def asm_roofline(f, P, x, u, xo, uo, workload):
     return roof, res_kernel, lev.ncells / (jac_pass_ms * 1e-3)
 
 
-CHANNEL_CONFIGS = {"channel3": (3, 4), "channel2": (2, 5)}
+# (dimension, levels, curved): the rectilinear channel (square prism) and the
+# curved one (isoparametric Q2 cells: the cylinder, rows of even height away
+# from obstacle and beam)
+CHANNEL_CONFIGS = {"channel3": (3, 4, False), "channel2": (2, 5, False),
+                   "channel3c": (3, 4, True), "channel2c": (2, 5, True)}
 
 
 def run_channel(args):
@@ -316,9 +320,9 @@ def run_channel(args):
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import fsi_levels, level_dicts
 
-    dim, nlev = CHANNEL_CONFIGS[args.config]
+    dim, nlev, curved = CHANNEL_CONFIGS[args.config]
     t0 = time.perf_counter()
-    C = make_channel(dim, nlev)
+    C = make_channel(dim, nlev, curved=curved)
     P = C.problem
     lev = P.levels[0]
     log(f"{args.config}: {lev.cells} cells on the finest of {nlev} levels, generated in "
@@ -388,8 +392,11 @@ def run_channel(args):
         "ms_per_step": t_ts * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if tag == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": (f"{args.config}: the {dim}D benchmark channel of Sec. 5 (cylinder read as a "
-                                f"square prism), {'x'.join(map(str, lev.cells))} Q2 cells, {nlev} levels, "
+        "config": {"workload": (f"{args.config}: the {dim}D benchmark channel of Sec. 5 ("
+                                + ("the cylinder of radius 0.05 on isoparametric Q2 cells, rows of even "
+                                   "height away from obstacle and beam" if curved else
+                                   "cylinder read as a square prism")
+                                + f"), {'x'.join(map(str, lev.cells))} Q2 cells, {nlev} levels, "
                                 f"start-up from rest, time steps {args.warmup + 1}..{args.warmup + args.steps} "
                                 f"timed (k = {k}, theta = {P.params['theta']}), each with drag / lift; "
                                 f"gamma_nt = {args.gamma}, Newton stop at 1e-8 relative or "

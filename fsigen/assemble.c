@@ -7,7 +7,11 @@
  * (Sec. 3.1, eq. aletime:2 with the condensation eq. defgrad; Sec. 4.2,
  * eq. problem:1 with the ALE derivatives dropped; eq. problem:3 for the
  * harmonic mesh extension) with equal-order Q2 elements (Sec. 3.2) on a
- * graded tensor-product mesh of [0,1]^d.
+ * graded tensor-product mesh of [0,1]^d, or on isoparametric Q2 cells when
+ * node positions are given (the curved cylinder of Sec. 5: per Gauss point
+ * the Jacobian dx/dxi of x(xi) = sum_i x_i N_i(xi), physical gradients by its
+ * inverse transpose, weights by its determinant; h_K = the longest cell edge
+ * from the first corner).
  *
  * Per element and Gauss point (3 points per axis):
  *   fluid cells  (u frozen: no derivatives w.r.t. the ALE deformation)

@@ -44,11 +44,17 @@ typedef struct {
   double alpha0;             /* pressure stabilisation scale */
 } fsimg_phys;
 
-/* Geometry of one multigrid level (host arrays, copied). */
+/* Geometry of one multigrid level (host arrays, copied).  A cell is the
+   image of the reference cell under x(xi) = sum_i x_i N_i(xi) over its 3^d
+   nodes (isoparametric Q2, Sec. 3.2 with the curved cylinder of Sec. 5);
+   node positions come from node_coords, or, when it is NULL, from the
+   tensor grid of coords (rectilinear cells).  The pressure stabilisation's
+   h_K is the longest cell edge from the cell's first corner. */
 typedef struct {
   const double *coords[3];   /* per-axis node coordinates, 2*cells[a]+1 each (unused axes:
                                 NULL) */
   const uint8_t *cell_solid; /* [prod(cells)] 1 = solid cell, 0 = fluid cell */
+  const double *node_coords; /* [nnodes * dim] node positions, node-major, or NULL */
 } fsimg_fsi_level;
 
 typedef struct fsimg_fsi fsimg_fsi;

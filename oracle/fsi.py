@@ -20,6 +20,12 @@ s_h(p, xi) = sum_K delta_K (grad p, grad xi)_K with
 delta_K = alpha0 k^2 h_K^2 / (rho_f (h_K^2 + k theta nu_f)); the line search
 halves omega until the max-norm of the residual decreases.
 
+Cells are rectilinear (per-axis node coordinates) or isoparametric Q2 (node
+positions: the cell is the image of the reference cell under
+x(xi) = sum_i x_i N_i(xi), gradients by (dx/dxi)^-T, weights by det(dx/dxi) at
+each Gauss point; h_K of the stabilisation is then the longest cell edge from
+the first corner), which carries the curved cylinder of Sec. 5.
+
 The residual is written out per element and Gauss point in plain NumPy.  The
 Jacobian is *defined* as the derivative of that residual: it is taken by the
 complex step (Im R(x + i h e_j) / h, exact to rounding for this analytic

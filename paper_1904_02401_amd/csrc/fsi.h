@@ -14,6 +14,7 @@ namespace fsimg {
 struct FsiLevel {
   AsmLevel dev{};          // device view (pattern and mask borrowed from the hierarchy)
   double *coord[3] = {nullptr, nullptr, nullptr};
+  double *xyz = nullptr;   // node positions [nrows * d] (isoparametric cells) or null
   uint8_t *solid = nullptr;
   // the state injected to this level (coarse levels only)
   double *x = nullptr, *u = nullptr, *xo = nullptr, *uo = nullptr;
@@ -85,7 +86,8 @@ fsimg_newton_stats newton_end(fsimg_fsi *f, hipStream_t s);
 // the Newton options in effect (defaults when opts is null); ERR_ARG if one
 // is out of range (the one check of the solo and the served Newton loops)
 fsimg_status check_newton_options(const fsimg_newton_opts *opts, fsimg_newton_opts *o);
-// device bytes fsimg_fsi_create allocates for these momentum levels
-size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale);
+// device bytes fsimg_fsi_create allocates for these momentum levels (geom:
+// their geometry, for the node positions it uploads; may be null)
+size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale, const fsimg_fsi_level *geom);
 
 }  // namespace fsimg

@@ -296,6 +296,7 @@ void launch_deform(int64_t nnodes, int dim, const uint8_t *mask, double k, doubl
 // Device view of one level of the tensor Q2 mesh for the element kernels.
 struct AsmLevel {
   const double *coord[3];          // per-axis node coordinates (2*cells[a]+1)
+  const double *xyz;               // [nrows][D] node positions (isoparametric cells) or null
   const uint8_t *solid;            // [prod(cells)] 1 = solid cell
   const int32_t *rowptr, *colind;  // block pattern of the momentum matrix
   const uint8_t *mask;             // [nrows*(d+1)] identity rows of the momentum matrix

@@ -136,17 +136,39 @@ struct ElemGeom {
   double h[D];
   double vol, hK;
   bool solid;
+  bool iso;  // isoparametric cell (node positions): dx/dxi per Gauss point
 };
 
+template <int D>
+__device__ __forceinline__ int64_t local_node(const AsmLevel &L, const int (&e)[3], int i);
+
+// the cell's sizes: rectilinear h per axis (volume, h_K = the longest side);
+// isoparametric cells: h_K = the longest edge from the first corner (local
+// nodes 2, 6, 18), the volume per Gauss point from det(dx/dxi)
 template <int D>
 __device__ __forceinline__ ElemGeom<D> elem_geom(const AsmLevel &L, const int (&e)[3]) {
   ElemGeom<D> g;
   g.vol = 1.0;
   g.hK = 0.0;
-  for (int a = 0; a < D; ++a) {
-    g.h[a] = L.coord[a][2 * e[a] + 2] - L.coord[a][2 * e[a]];
-    g.vol *= g.h[a];
-    g.hK = fmax(g.hK, g.h[a]);
+  g.iso = L.xyz != nullptr;
+  if (g.iso) {
+    const int64_t g0 = local_node<D>(L, e, 0);
+    for (int a = 0; a < D; ++a) {
+      g.h[a] = 1.0;  // reference cell: the basis is staged in reference coordinates
+      const int64_t gc = local_node<D>(L, e, 2 * (a == 0 ? 1 : (a == 1 ? 3 : 9)));
+      double s = 0.0;
+      for (int c = 0; c < D; ++c) {
+        const double dx = L.xyz[gc * D + c] - L.xyz[g0 * D + c];
+        s += dx * dx;
+      }
+      g.hK = fmax(g.hK, sqrt(s));
+    }
+  } else {
+    for (int a = 0; a < D; ++a) {
+      g.h[a] = L.coord[a][2 * e[a] + 2] - L.coord[a][2 * e[a]];
+      g.vol *= g.h[a];
+      g.hK = fmax(g.hK, g.h[a]);
+    }
   }
   int64_t cell = 0, stride = 1;
   for (int a = 0; a < D; ++a) {
@@ -175,6 +197,50 @@ __device__ __forceinline__ void basis_at(int q, int i, const double (&h)[D], dou
     for (int a = 0; a < D; ++a) v *= (a == m) ? dL[a] : L[a];
     dN[m] = v / h[m];
   }
+}
+
+// Isoparametric cells: with the reference gradients s_dN[m][q][i] (h = 1)
+// and the node positions s_x staged, compute per Gauss point q the Jacobian
+// dx/dxi = sum_i x_i grad_xi N_i, its determinant (into s_det[q]) and its
+// inverse, then turn s_dN into physical gradients in place:
+// dN/dx_c = sum_k dN/dxi_k dxi_k/dx_c.  Called by the whole workgroup
+// between barriers; flag[0] = 1 if det(dx/dxi) <= 0 (an inverted cell).
+template <int D, int NN>
+__device__ __forceinline__ void map_gradients(const double (&s_x)[NN][D], double (&s_dN)[D][NN][NN],
+                                              double (&s_ji)[NN][D * D], double (&s_det)[NN],
+                                              int *flag) {
+  const int t = threadIdx.x;
+  if (t < NN) {
+    const int q = t;
+    double Jg[D][D], Ji[D][D];
+    for (int c = 0; c < D; ++c)
+      for (int m = 0; m < D; ++m) Jg[c][m] = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < NN; ++i)
+      for (int c = 0; c < D; ++c) {
+        const double xc = s_x[i][c];
+        for (int m = 0; m < D; ++m) Jg[c][m] += xc * s_dN[m][q][i];
+      }
+    const double det = det_d<D>(Jg);
+    if (!(det > 0.0)) flag[0] = 1;
+    inv_d<D>(Jg, det, Ji);  // Ji[k][c] = dxi_k / dx_c
+    for (int k = 0; k < D; ++k)
+      for (int c = 0; c < D; ++c) s_ji[q][k * D + c] = Ji[k][c];
+    s_det[q] = det;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int it = t; it < NN * NN; it += blockDim.x) {
+    const int q = it / NN, i = it % NN;
+    double r[D];
+    for (int k = 0; k < D; ++k) r[k] = s_dN[k][q][i];
+    for (int c = 0; c < D; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < D; ++k) s += r[k] * s_ji[q][k * D + c];
+      s_dN[c][q][i] = s;
+    }
+  }
+  __syncthreads();
 }
 
 template <int D>
@@ -212,6 +278,9 @@ __global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhy
   __shared__ double s_qs[NN][NQS];    // per point material data
   __shared__ double s_tf[D + 1][NN][NN];  // [c][q][i]: F^-T grad N_i (fluid) or F grad N_i
                                           // (solid); [D]: transport a.grad N_i (fluid)
+  __shared__ double s_x[NN][D];           // node positions (isoparametric cells)
+  __shared__ double s_ji[NN][D * D];      // per point: (dx/dxi)^-1
+  __shared__ double s_det[NN];            // per point: det(dx/dxi)
   const int t = threadIdx.x;
   int e[3];
   colour_cell<D>(L, colour, blockIdx.x, e);
@@ -226,6 +295,7 @@ __global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhy
       s_nod[1][t][c] = vo;
       s_nod[2][t][c] = G.solid ? uo + kt * v + k * (1.0 - th) * vo : S.u[g * D + c];
       s_nod[3][t][c] = uo;
+      if (G.iso) s_x[t][c] = L.xyz[g * D + c];
     }
   }
   for (int it = t; it < NN * NN; it += blockDim.x) {
@@ -236,6 +306,7 @@ __global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhy
     for (int m = 0; m < D; ++m) s_dN[m][q][i] = dN[m];
   }
   __syncthreads();
+  if (G.iso) map_gradients<D, NN>(s_x, s_dN, s_ji, s_det, flag);
   // fields at the Gauss points: item (q, f), f = field * D(D+1) + c (D+1) + w
   for (int it = t; it < NN * NF; it += blockDim.x) {
     const int q = it / NF, f = it % NF;
@@ -260,7 +331,7 @@ __global__ __launch_bounds__(jac_threads<D>()) void k_asm_jac(AsmLevel L, AsmPhy
     if (!(J > 0.0)) flag[0] = 1;
     inv_d<D>(F, J, Fi);
     double *qs = s_qs[q];
-    qs[0] = qweight<D>(q) * G.vol;
+    qs[0] = qweight<D>(q) * (G.iso ? s_det[q] : G.vol);
     if (!G.solid) {
       double Fo[D][D], Fb[D][D], Fbi[D][D];
       for (int a = 0; a < D; ++a)
@@ -460,6 +531,9 @@ __global__ __launch_bounds__(D == 3 ? 256 : 128) void k_asm_res(AsmLevel L, AsmP
   __shared__ double s_dN[D][NN][NN];
   __shared__ double s_qf[NN][NF];        // (v, v_old, u, u_old) x comp x (value, grad); p, grad p
   __shared__ double s_qo[NN][NO];
+  __shared__ double s_x[NN][D];          // node positions (isoparametric cells)
+  __shared__ double s_ji[NN][D * D];     // per point: (dx/dxi)^-1
+  __shared__ double s_det[NN];           // per point: det(dx/dxi)
   const int t = threadIdx.x;
   int e[3];
   colour_cell<D>(L, colour, blockIdx.x, e);
@@ -473,6 +547,7 @@ __global__ __launch_bounds__(D == 3 ? 256 : 128) void k_asm_res(AsmLevel L, AsmP
       s_nod[1][t][c] = vo;
       s_nod[2][t][c] = G.solid ? uo + kt * v + k * (1.0 - th) * vo : S.u[g * D + c];
       s_nod[3][t][c] = uo;
+      if (G.iso) s_x[t][c] = L.xyz[g * D + c];
     }
     s_p[t] = S.x[g * B];
   }
@@ -484,6 +559,7 @@ __global__ __launch_bounds__(D == 3 ? 256 : 128) void k_asm_res(AsmLevel L, AsmP
     for (int m = 0; m < D; ++m) s_dN[m][q][i] = dN[m];
   }
   __syncthreads();
+  if (G.iso) map_gradients<D, NN>(s_x, s_dN, s_ji, s_det, flag);
   for (int it = t; it < NN * NF; it += blockDim.x) {
     const int q = it / NF, f = it % NF;
     double s = 0.0;
@@ -593,7 +669,7 @@ __global__ __launch_bounds__(D == 3 ? 256 : 128) void k_asm_res(AsmLevel L, AsmP
           }
       }
     }
-    const double wq = qweight<D>(q) * G.vol;
+    const double wq = qweight<D>(q) * (G.iso ? s_det[q] : G.vol);
     double *qo = s_qo[q];
     for (int a = 0; a < D; ++a) qo[a] = wq * vec[a];
     for (int a = 0; a < D; ++a)

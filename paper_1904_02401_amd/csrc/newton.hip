@@ -322,6 +322,12 @@ fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_
           hipSuccess)
         return bail(nfail(FSIMG_ERR_HIP, "coordinate upload failed"));
     }
+    if (levels[l].node_coords) {
+      NW_CHK(falloc(f, &F.xyz, (size_t)(L.nrows * d)));
+      if (hipMemcpy(F.xyz, levels[l].node_coords, L.nrows * d * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return bail(nfail(FSIMG_ERR_HIP, "node position upload failed"));
+    }
     NW_CHK(falloc(f, &F.solid, (size_t)ncell));
     if (hipMemcpy(F.solid, levels[l].cell_solid, ncell, hipMemcpyHostToDevice) != hipSuccess)
       return bail(nfail(FSIMG_ERR_HIP, "cell flag upload failed"));
@@ -337,6 +343,7 @@ fsimg_status fsimg_fsi_create(fsimg_hier *mom, fsimg_hier *ale, const fsimg_fsi_
       A.cells[a] = L.cells[a];
       A.nnode[a] = L.nnode[a];
     }
+    A.xyz = F.xyz;
     A.solid = F.solid;
     A.rowptr = L.rowptr;
     A.colind = L.colind;
@@ -655,10 +662,11 @@ fsimg_newton_stats newton_end(fsimg_fsi *f, hipStream_t s) {
   return R.st;
 }
 
-size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale) {
+size_t fsi_bytes(const fsimg_level_desc *mom, int nlev, bool with_ale, const fsimg_fsi_level *geom) {
   size_t b = 0;
   const int d = mom[0].dim;
   for (int l = 0; l < nlev; ++l) {
+    if (geom && geom[l].node_coords) b += (size_t)mom[l].nrows * d * sizeof(double);
     int64_t ncell = 1;
     for (int a = 0; a < d; ++a) {
       b += (size_t)(2 * mom[l].cells[a] + 1) * sizeof(double);

@@ -99,7 +99,7 @@ size_t request_bytes(const fsimg_server *S, const Req *q, fsimg_status *st) {
   *st = fsimg_hier_footprint(q->r.mom, q->r.nlev, &S->opts, &fm);
   if (*st == FSIMG_OK) *st = fsimg_hier_footprint(q->r.ale, q->r.nlev, &S->opts, &fa);
   if (q->nt)
-    return fm + fa + fsi_bytes(q->r.mom, q->r.nlev, true) + (size_t)(2 * q->nm + 2 * q->na) * 8 +
+    return fm + fa + fsi_bytes(q->r.mom, q->r.nlev, true, q->nreq.geom) + (size_t)(2 * q->nm + 2 * q->na) * 8 +
            plan_reserve();
   return fm + fa + (size_t)((q->rhs.size() + 1) * q->nm + 2 * q->na) * 8 + (size_t)q->nnodes +
          plan_reserve();

@@ -98,7 +98,27 @@ class fsimg_phys(ctypes.Structure):
 
 
 class fsimg_fsi_level(ctypes.Structure):
-    _fields_ = [("coords", ctypes.c_void_p * 3), ("cell_solid", ctypes.c_void_p)]
+    _fields_ = [("coords", ctypes.c_void_p * 3), ("cell_solid", ctypes.c_void_p),
+                ("node_coords", ctypes.c_void_p)]
+
+
+def _fill_geometry(arr, levels, keep):
+    """levels: per level (coords per axis, cell_solid[, node_coords or None])"""
+    for l, lv in enumerate(levels):
+        coords, solid = lv[0], lv[1]
+        xyz = lv[2] if len(lv) > 2 else None
+        cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coords]
+        sd = np.ascontiguousarray(solid, dtype=np.uint8)
+        keep += cs + [sd]
+        for a in range(3):
+            arr[l].coords[a] = cs[a].ctypes.data if a < len(cs) else None
+        arr[l].cell_solid = sd.ctypes.data
+        if xyz is not None:
+            xa = np.ascontiguousarray(xyz, dtype=np.float64)
+            keep.append(xa)
+            arr[l].node_coords = xa.ctypes.data
+        else:
+            arr[l].node_coords = None
 
 
 class fsimg_newton_opts(ctypes.Structure):
@@ -554,17 +574,12 @@ def fsimg_phys_of(params: dict) -> fsimg_phys:
 
 
 def fsimg_fsi_create(mom, ale, levels, params: dict):
-    """levels: per multigrid level (coords per axis, cell_solid uint8) of the
-    momentum hierarchy; params: the fsimg_phys fields."""
+    """levels: per multigrid level (coords per axis, cell_solid uint8[, node
+    positions [nnodes, dim] or None]) of the momentum hierarchy; params: the
+    fsimg_phys fields."""
     keep = []
     arr = (fsimg_fsi_level * len(levels))()
-    for l, (coords, solid) in enumerate(levels):
-        cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coords]
-        sd = np.ascontiguousarray(solid, dtype=np.uint8)
-        keep += cs + [sd]
-        for a in range(3):
-            arr[l].coords[a] = cs[a].ctypes.data if a < len(cs) else None
-        arr[l].cell_solid = sd.ctypes.data
+    _fill_geometry(arr, levels, keep)
     out = ctypes.c_void_p()
     _check(load().fsimg_fsi_create(mom, ale, arr, ctypes.byref(fsimg_phys_of(params)),
                                    ctypes.byref(out)))
@@ -668,13 +683,7 @@ class NewtonRequestData:
         self.nlev = self.mom.n
         self._keep = []
         self.geom = (fsimg_fsi_level * self.nlev)()
-        for l, (coords, solid) in enumerate(geometry):
-            cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coords]
-            sd = np.ascontiguousarray(solid, dtype=np.uint8)
-            self._keep += cs + [sd]
-            for a in range(3):
-                self.geom[l].coords[a] = cs[a].ctypes.data if a < len(cs) else None
-            self.geom[l].cell_solid = sd.ctypes.data
+        _fill_geometry(self.geom, geometry, self._keep)
         self.phys = fsimg_phys_of(params)
         self.vecs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, u, x_old, u_old)]
 

@@ -28,9 +28,9 @@ def request_data(problem, states=(), rhs=()):
 
 
 def fsi_levels(problem):
-    """Per-level geometry (coordinates per axis, cell_solid) for
-    fsimg.fsimg_fsi_create."""
-    return [(list(lev.coords), lev.cell_solid) for lev in problem.levels]
+    """Per-level geometry (coordinates per axis, cell_solid, node positions
+    or None) for fsimg.fsimg_fsi_create."""
+    return [(list(lev.coords), lev.cell_solid, lev.node_coords) for lev in problem.levels]
 
 
 def fsi_state(problem):

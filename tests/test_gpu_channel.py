@@ -122,11 +122,19 @@ def test_force_and_time_step_refuse_bad_indices(ctx):
         with pytest.raises(fsimg.FsimgError, match="out of range"):
             fsimg.fsimg_fsi_force(S.f, z, zu, z, zu, _ti([0, n]), d)
         free = np.nonzero(lev.systems["mom"].dirichlet == 0)[0][:1]
-        xo, uo = z.clone(), zu.clone()
+        held = np.nonzero(lev.systems["mom"].dirichlet == 1)[0][:1]
+        x = torch.arange(n * (d + 1), device=DEV, dtype=torch.float64)
+        u = torch.arange(n * d, device=DEV, dtype=torch.float64)
+        xo, uo = -x, -u
+        before = [t.clone() for t in (x, u, xo, uo)]
         with pytest.raises(fsimg.FsimgError, match="held row"):
-            fsimg.fsimg_fsi_time_step(S.f, z, zu, xo, uo, _ti(free), _t([1.0]), 1.0)
+            fsimg.fsimg_fsi_time_step(S.f, x, u, xo, uo, _ti(np.concatenate([held, free])),
+                                      _t([1.0, 1.0]), 1.0)
         with pytest.raises(fsimg.FsimgError, match="held row"):
-            fsimg.fsimg_fsi_time_step(S.f, z, zu, xo, uo, _ti([n * (d + 1)]), _t([1.0]), 1.0)
+            fsimg.fsimg_fsi_time_step(S.f, x, u, xo, uo, _ti([n * (d + 1)]), _t([1.0]), 1.0)
+        # a refused call writes none of the four vectors
+        for t, t0 in zip((x, u, xo, uo), before):
+            assert torch.equal(t, t0)
     finally:
         S.close()
 
