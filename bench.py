@@ -47,9 +47,9 @@ def spmv_bytes(nnzb, nrows, b, s):
 
 KERNEL_SOURCES = ("batch_kernels.hip", "device_ops.h")
 ASM_SOURCES = ("kernels_asm.hip",)
-# the batched kernel whose source keys each role's counter entry
-ROLE_KERNEL = {"vanka_patch": "kb_vanka_patch", "spmv_residual": "kb_spmv",
-               "restrict": "kb_restrict", "prolong": "kb_prolong"}
+# the batched kernels (and their helpers) whose source keys each role's counter entry
+ROLE_KERNEL = {"vanka_patch": ("kb_vanka_patch",), "spmv_residual": ("kb_spmv",),
+               "restrict": ("kb_restrict", "taps_1d", "kb_restrict3"), "prolong": ("kb_prolong",)}
 
 
 def _function_text(src, name):
@@ -77,7 +77,8 @@ def kernel_source_hash(sources=KERNEL_SOURCES, role=None):
     if role in ROLE_KERNEL:
         h.update(open(os.path.join(csrc, "device_ops.h"), "rb").read())
         src = open(os.path.join(csrc, "batch_kernels.hip")).read()
-        h.update(_function_text(src, ROLE_KERNEL[role]).encode())
+        for name in ROLE_KERNEL[role]:
+            h.update(_function_text(src, name).encode())
         return h.hexdigest()[:16]
     for f in sources:
         h.update(open(os.path.join(csrc, f), "rb").read())
@@ -1151,7 +1152,8 @@ def main():
         # by the restriction, (2 N_f + N_c) b s by the prolongation, plus the masks
         nf = lev.systems["mom"].nrows * bm
         nc = P.levels[1].systems["mom"].nrows * bm
-        for key, kname, byts in (("restrict", f"kb_restrict<{bm}, {P.dim}, {tname}>", (nf + nc) * s + nc),
+        rname = f"kb_restrict3<{bm}, {tname}>" if P.dim == 3 else f"kb_restrict<{bm}, 2, {tname}>"
+        for key, kname, byts in (("restrict", rname, (nf + nc) * s + nc),
                                  ("prolong", f"kb_prolong<{bm}, {P.dim}, {tname}>", (2 * nf + nc) * s + nf)):
             ms = sum(p[f"{key}_ms"] for p in prof)
             n = sum(p[f"{key}_launches"] for p in prof)

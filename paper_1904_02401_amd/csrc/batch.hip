@@ -233,7 +233,9 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
         pa.push(i, cdiv(L.npatch, P->ppw[l]));
         pa2.push(i, cdiv(L.blk.npatch, P->ppw2[l]));
         ga.push(i, cdiv(L.n, 256));
-        re.push(i, cdiv(hs[i]->lev[l + 1].nrows, 256));
+        const DevLevel &Cl = hs[i]->lev[l + 1];
+        re.push(i, P->dim == 3 ? restrict3_blocks(Cl.cells[0], Cl.cells[1], Cl.cells[2])
+                               : cdiv(Cl.nrows, 256));
         pr.push(i, cdiv(L.nrows, 256));
       } else if (l == Li - 1) {
         const DevLevel &L = hs[i]->lev[l];

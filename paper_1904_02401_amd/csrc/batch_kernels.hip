@@ -138,6 +138,126 @@ __global__ __launch_bounds__(256) void kb_restrict(const DLev *__restrict__ levF
                                 LV<T>::r(C), C.mask);
 }
 
+// 3D restriction by slabs: a workgroup owns one coarse plane Z and a slab of
+// at most kRTY coarse rows by at most kRTXM coarse columns (the columns of a
+// row split evenly over the fewest slabs).  Each thread first restricts
+// along z for the fine (x, y) positions of the slab and its 3-node halo (the
+// <= 5 fine planes coarse plane Z reaches, loads independent of one another)
+// into LDS; after one barrier each coarse node of the slab sums the <= 5 x 5
+// x-y taps from LDS.  No sequential walk over planes: every load of a
+// workgroup is in flight at once, and the grid has NZ * slabs workgroups.
+constexpr int kRTXM = 64, kRTY = 4;
+
+__host__ __device__ inline void restrict3_slabs(int NX, int NY, int &ntx, int &wx, int &nty) {
+  ntx = (NX + kRTXM - 1) / kRTXM;
+  wx = (NX + ntx - 1) / ntx;
+  nty = (NY + kRTY - 1) / kRTY;
+}
+
+// the fine taps of coarse node I along one axis (fine nodes 0 .. nf-1) in
+// five fixed slots: a vertex reaches 2I, 2I +- 1, 2I +- 3, a mid node 2I,
+// 2I +- 1; a slot outside the mesh or unused points at 2I with weight 0, so
+// every index stays in range and the slots live in registers
+template <typename T>
+__device__ __forceinline__ void taps_1d(int I, int nf, int *f, T *w) {
+  const bool vtx = (I & 1) == 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int d = q == 0 ? 0 : (q == 1 ? -1 : (q == 2 ? 1 : (q == 3 ? -3 : 3)));
+    const T wv = q == 0 ? T(1) : (q < 3 ? T(0.375) : T(-0.125));
+    const T wm = q == 0 ? T(1) : (q < 3 ? T(0.75) : T(0));
+    const int g = 2 * I + d;
+    const bool ok = g >= 0 && g < nf;
+    f[q] = ok ? g : 2 * I;
+    w[q] = ok ? (vtx ? wv : wm) : T(0);
+  }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(256) void kb_restrict3(const DLev *__restrict__ levF,
+                                                    const DLev *__restrict__ levC,
+                                                    const int *__restrict__ active, WorkSet ws) {
+  constexpr int FYW = 2 * kRTY + 5, FXWM = 2 * kRTXM + 5;
+  __shared__ T s_f[FYW * FXWM * B];  // z-restricted fine rows of the slab and halo
+  const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
+  const int sg = seg_of(ws, lb);
+  const int inst = ws.inst[sg];
+  if (!active[inst]) return;  // uniform per workgroup
+  const DLev &C = levC[inst];
+  const DLev &F = levF[inst];
+  const int NX = 2 * C.cells[0] + 1, NY = 2 * C.cells[1] + 1;
+  const int FX = 4 * C.cells[0] + 1, FY = 4 * C.cells[1] + 1, FZ = 4 * C.cells[2] + 1;
+  int ntx, wx, nty;
+  restrict3_slabs(NX, NY, ntx, wx, nty);
+  int64_t blk = lb - ws.pre[sg];
+  const int ty = (int)(blk % nty);
+  blk /= nty;
+  const int tx = (int)(blk % ntx), Z = (int)(blk / ntx);
+  const int X0 = tx * wx, Y0 = ty * kRTY;
+  const int X1 = X0 + wx < NX ? X0 + wx : NX, Y1 = Y0 + kRTY < NY ? Y0 + kRTY : NY;
+  const int fx0 = 2 * X0 - 3, fy0 = 2 * Y0 - 3, fxw = 2 * (X1 - X0) + 5;
+  const int t = threadIdx.x;
+  const T *rf = LV<T>::d(F);
+  T *rc = LV<T>::r(C);
+  int fzt[5];
+  T wzt[5];
+  taps_1d<T>(Z, FZ, fzt, wzt);
+#pragma unroll 2
+  for (int it = t; it < FYW * fxw; it += 256) {
+    const int yy = it / fxw, xx = it - yy * fxw;
+    const int gx = fx0 + xx, gy = fy0 + yy;
+    T a[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) a[c] = T(0);
+    if (gx >= 0 && gx < FX && gy >= 0 && gy < FY) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        if (wzt[q] != T(0)) {  // uniform: the slab's plane Z decides
+          const T *src = rf + (((int64_t)fzt[q] * FY + gy) * FX + gx) * B;
+#pragma unroll
+          for (int c = 0; c < B; ++c) a[c] += wzt[q] * src[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) s_f[it * B + c] = a[c];
+  }
+  __syncthreads();
+  const int nxs = X1 - X0;
+  for (int p = t; p < (Y1 - Y0) * nxs; p += 256) {
+    const int ly = p / nxs, lx = p - ly * nxs;
+    const int X = X0 + lx, Y = Y0 + ly;
+    int fxt[5], fyt[5];
+    T wxt[5], wyt[5];
+    taps_1d<T>(X, FX, fxt, wxt);
+    taps_1d<T>(Y, FY, fyt, wyt);
+    T v[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] = T(0);
+#pragma unroll
+    for (int qy = 0; qy < 5; ++qy) {
+      const T *row = s_f + (fyt[qy] - fy0) * fxw * B;
+      T h[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) h[c] = T(0);
+#pragma unroll
+      for (int qx = 0; qx < 5; ++qx) {
+        const T *e = row + (fxt[qx] - fx0) * B;
+#pragma unroll
+        for (int c = 0; c < B; ++c) h[c] += wxt[qx] * e[c];
+      }
+#pragma unroll
+      for (int c = 0; c < B; ++c) v[c] += wyt[qy] * h[c];
+    }
+    const int64_t node = ((int64_t)Z * NY + Y) * NX + X;
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      const int64_t dof = node * B + c;
+      rc[dof] = C.mask[dof] ? T(0) : v[c];
+    }
+  }
+}
+
 template <int B, int DIM, typename T>
 __global__ __launch_bounds__(256) void kb_prolong(const DLev *__restrict__ levF,
                                                   const DLev *__restrict__ levC,
@@ -382,6 +502,12 @@ inline dim3 grid_of(const WorkSet &ws) { return dim3((unsigned)ws.nblocks); }
 
 }  // namespace
 
+int64_t restrict3_blocks(int cx, int cy, int cz) {
+  int ntx, wx, nty;
+  restrict3_slabs(2 * cx + 1, 2 * cy + 1, ntx, wx, nty);
+  return (int64_t)(2 * cz + 1) * ntx * nty;
+}
+
 int krylov_blocks(int64_t n) {
   const int64_t nb = (n + 1023) / 1024;
   return (int)(nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb));
@@ -450,8 +576,15 @@ void launch_b_restrict(int b, int dim, const DLev *levF, const DLev *levC, const
                        ws);                                                                      \
     return;                                                                                      \
   }
+#define FSIMG_BR3(BV)                                                                            \
+  if (b == BV && dim == 3) {                                                                     \
+    hipLaunchKernelGGL((kb_restrict3<BV, T>), grid_of(ws), dim3(256), 0, s, levF, levC, active,  \
+                       ws);                                                                      \
+    return;                                                                                      \
+  }
   FSIMG_BR(1, 2) FSIMG_BR(2, 2) FSIMG_BR(3, 2) FSIMG_BR(4, 2)
-  FSIMG_BR(1, 3) FSIMG_BR(2, 3) FSIMG_BR(3, 3) FSIMG_BR(4, 3)
+  FSIMG_BR3(1) FSIMG_BR3(2) FSIMG_BR3(3) FSIMG_BR3(4)
+#undef FSIMG_BR3
 #undef FSIMG_BR
 }
 

@@ -174,9 +174,12 @@ void launch_b_vanka_blocks(int np, int b, int nl, int npc, int ppw, bool first, 
                            const int *active, const WorkSet &wp, hipStream_t s);
 template <typename T>
 void launch_b_fill_x(const DLev *lev, const int *active, const WorkSet &ws, hipStream_t s);
+// 3D: the work set counts tiles (restrict3_blocks of the coarse level), 2D
+// workgroups of 256 coarse nodes
 template <typename T>
 void launch_b_restrict(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
                        const WorkSet &ws, hipStream_t s);
+int64_t restrict3_blocks(int cx, int cy, int cz);
 template <typename T>
 void launch_b_prolong(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
                       const WorkSet &ws, hipStream_t s);
