@@ -144,7 +144,8 @@ def calib_copy(nbytes, reps):
     log(f"calib-copy: {reps} copies of {nbytes} bytes")
 
 
-def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0, smoother=0):
+def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0, smoother=0,
+            lookahead=2, small_kib=0):
     import torch
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import level_dicts
@@ -156,7 +157,8 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     systems = ["mom", "ale"] + (["mass"] if with_mass else [])
     for name in systems:
         o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches,
-                                     vanka_schedule=schedule, smoother=smoother)
+                                     vanka_schedule=schedule, smoother=smoother,
+                                     krylov_lookahead=lookahead, small_level_kib=small_kib)
         hs[name] = fsimg.fsimg_hier_create(ctx, level_dicts(P, name), o)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -752,7 +754,8 @@ def run_batched(args):
     prec = fsimg.FSIMG_FP64 if args.only == "fp64" else fsimg.FSIMG_MIXED
     budget = int(args.budget_gb * (1 << 30))
     ctx = fsimg.fsimg_ctx_create(0, budget)
-    opts = fsimg.fsimg_default_opts(precision=prec)
+    opts = fsimg.fsimg_default_opts(precision=prec, krylov_lookahead=args.lookahead,
+                                    small_level_kib=args.small_level_kib)
     dev = torch.device("cuda:0")
     waves, unknowns, solve_s, sizes, iters = [], 0, 0.0, [], []
     pending = list(range(args.instances))
@@ -806,7 +809,8 @@ def run_batched(args):
                                "FGMRES + V-cycle to 1e-8, admission waves under an HBM budget",
                    "budget_GiB": args.budget_gb, "waves": waves,
                    "iters_min_mean_max": [min(iters), float(np.mean(iters)), max(iters)],
-                   "cells_per_axis": sizes, "alone_equals_batched": check},
+                   "cells_per_axis": sizes, "alone_equals_batched": check,
+                   "krylov_lookahead": args.lookahead, "small_level_kib": args.small_level_kib},
     }
     print(json.dumps(out), flush=True)
 
@@ -1014,6 +1018,11 @@ def main():
     ap.add_argument("--smoother", choices=["vanka", "ilu"], default="vanka",
                     help="multigrid smoother (ilu: block ILU(0), level-scheduled)")
     ap.add_argument("--no-mass", action="store_true")
+    ap.add_argument("--lookahead", type=int, choices=[1, 2], default=2,
+                    help="FGMRES iterations the host keeps in flight (1: wait for each)")
+    ap.add_argument("--small-level-kib", type=int, default=0,
+                    help="levels up to this many KiB of smoother + matrix data run in one "
+                         "workgroup per instance (0: a launch per step and level)")
     ap.add_argument("--newton", action="store_true",
                     help="time steps of the GPU Newton loop (residual / Jacobian assembly, reuse, "
                          "line search) instead of one linear Newton-step solve")
@@ -1106,7 +1115,8 @@ def main():
                     patches=fsimg.FSIMG_PATCH_BLOCK if args.patches == "block" else fsimg.FSIMG_PATCH_ELEMENT,
                     schedule={"gather": fsimg.FSIMG_VANKA_GATHER, "parity": fsimg.FSIMG_VANKA_PARITY,
                               "greedy": fsimg.FSIMG_VANKA_GREEDY}[args.schedule],
-                    smoother=fsimg.FSIMG_SMOOTHER_ILU if args.smoother == "ilu" else fsimg.FSIMG_SMOOTHER_VANKA)
+                    smoother=fsimg.FSIMG_SMOOTHER_ILU if args.smoother == "ilu" else fsimg.FSIMG_SMOOTHER_VANKA,
+                    lookahead=args.lookahead, small_kib=args.small_level_kib)
         A = to_csr(lev.systems["mom"])
         mask = lev.systems["mom"].dirichlet.astype(bool)
         rr = P.rhs["mom"] - A @ r["x_mom"]
@@ -1233,7 +1243,8 @@ def main():
                    "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
                    "precision": main_tag, "vanka_patches": args.patches,
-                   "vanka_schedule": args.schedule, "smoother": args.smoother},
+                   "vanka_schedule": args.schedule, "smoother": args.smoother,
+                   "krylov_lookahead": args.lookahead, "small_level_kib": args.small_level_kib},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],

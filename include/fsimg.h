@@ -131,6 +131,24 @@ typedef struct {
   int vanka_patches;   /* fsimg_patches */
   int smoother;        /* fsimg_smoother */
   double omega_ilu;    /* ILU damping (default 1: the undamped incomplete-LU step) */
+  int krylov_lookahead; /* FGMRES iterations the host keeps in flight (1 or 2, default 2).
+                           The Givens update and the stop test run on the device; the host
+                           reads each iteration's stop flags only to stop launching.  With 2
+                           it reads iteration j's flags while iteration j + 1 runs (no idle
+                           GPU between iterations; after the last instance stops at most one
+                           iteration runs with nothing to do); with 1 it waits for every
+                           iteration before launching the next.  Results are identical */
+  int small_level_kib;  /* GATHER / Vanka hierarchies: the levels below the finest whose patch
+                           inverses and matrix values (in the V-cycle's precision) each take at
+                           most this many KiB, down to the coarsest-but-one, run in one
+                           workgroup per instance (one launch for their pre-smoothing,
+                           residuals and restrictions, one for prolongations and
+                           post-smoothing) instead of a launch per step and level; the same
+                           per-row, per-patch and per-dof arithmetic, so results are
+                           identical.  0 (default): never.  One workgroup walks a level's
+                           rows and patches in rounds whose dependent loads it cannot hide,
+                           so on this hardware it pays only for levels of a few hundred
+                           unknowns (2D 32^2 with level 1 in it: 1.8x slower per step) */
 } fsimg_opts;
 
 #define FSIMG_HIST 64  /* residual-history entries in fsimg_stats */
@@ -237,9 +255,10 @@ fsimg_status fsimg_solve_batch(int n, fsimg_hier *const *hiers, const double *co
 /* fsimg_solve for callers that cannot allocate: code under HIP graph capture
    of its own work, tight serving loops, harnesses that forbid hipMalloc.
    Same method, kernels and result as fsimg_solve (bitwise equal; launched
-   eagerly, no HIP graphs).  The solve's descriptor tables (level
-   descriptors, work lists, Krylov descriptor, active flags, Hessenberg
-   column; about 30 KB for five levels) are written into a fixed 64 KiB
+   eagerly, no HIP graphs, one FGMRES iteration in flight).  The solve's
+   descriptor tables (level descriptors, work lists, Krylov descriptor,
+   active flags, Hessenberg column, FGMRES control state; about 25 KB for
+   five levels) are written into a fixed 64 KiB
    device array that every GPU the library runs on holds until the process
    ends (its address is looked up when a context is created on the GPU);
    host staging uses host memory.  The call makes no hipMalloc, hipFree,

@@ -573,6 +573,8 @@ void fsimg_default_opts(fsimg_opts *o) {
   o->vanka_patches = FSIMG_PATCH_ELEMENT;
   o->smoother = FSIMG_SMOOTHER_VANKA;
   o->omega_ilu = 1.0;
+  o->krylov_lookahead = 2;
+  o->small_level_kib = 0;
 }
 
 fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **out) {
@@ -609,6 +611,9 @@ static fsimg_status validate_opts(const fsimg_opts *o) {
   if (o->vanka_schedule < 0 || o->vanka_schedule > 2) return fail(FSIMG_ERR_ARG, "bad schedule");
   if (o->vanka_weighting < 0 || o->vanka_weighting > 1) return fail(FSIMG_ERR_ARG, "bad weighting");
   if (o->graphs < 0 || o->graphs > 1) return fail(FSIMG_ERR_ARG, "graphs must be 0 or 1");
+  if (o->krylov_lookahead < 1 || o->krylov_lookahead > 2)
+    return fail(FSIMG_ERR_ARG, "krylov_lookahead must be 1 or 2");
+  if (o->small_level_kib < 0) return fail(FSIMG_ERR_ARG, "small_level_kib must be >= 0");
   if (o->vanka_patches < 0 || o->vanka_patches > 1) return fail(FSIMG_ERR_ARG, "bad patch shape");
   if (o->vanka_patches == FSIMG_PATCH_BLOCK && o->vanka_schedule != FSIMG_VANKA_GATHER)
     return fail(FSIMG_ERR_ARG, "block patches need the GATHER schedule");

@@ -35,24 +35,39 @@ struct BatchPlan {
   size_t kry_off = 0;
   DLev *dlev = nullptr;  // [Lmax][n]
   DKry *dkry = nullptr;  // [n]
-  int *active = nullptr, *kcnt = nullptr, *flags = nullptr;
+  int *active = nullptr, *kcnt = nullptr, *flags = nullptr, *cyc = nullptr;
   double *hs = nullptr;  // [n * kHS]
+  DGiv *gv = nullptr;    // [n] FGMRES control state
   std::vector<WorkSet> ws_spmv, ws_patch, ws_patch2, ws_gather, ws_restrict, ws_prolong, ws_cn, ws_cf;
+  // the V-cycle's work sets without the levels an instance runs in its
+  // small-level kernel (the same as ws_* where no instance has such levels)
+  std::vector<WorkSet> vs_spmv, vs_patch, vs_patch2, vs_gather, vs_restrict, vs_prolong;
+  // per level c: the instances whose coarsest level is c and that run the
+  // levels tfrom[i] .. c - 1 in kb_vcycle_tail
+  std::vector<const int32_t *> tail_inst;
+  std::vector<int> tail_n;
+  const int32_t *tfrom = nullptr;
+  bool tails = false;
   WorkSet ws_row0{}, ws_vec0{}, ws_kry{}, ws_inst{};
   std::vector<DKry> hkry;
-  double *hs_host = nullptr;
-  int *int_host = nullptr;  // active | kcnt | flags staging, 3n ints
+  // pinned host staging: the active flags after each iteration j of a cycle
+  // (ring[j * n + i]), cyc | kcnt after a cycle, the control states at the end
+  int *ring_host = nullptr;
+  int *int_host = nullptr;
+  DGiv *gv_host = nullptr;
+  hipEvent_t ev[kMaxVec] = {};  // recorded after iteration j's flags are copied
   EventTimer tv, ts, tr, tp;  // finest level: Vanka, SpMV, restriction, prolongation
   // FGMRES iteration j (copy-in, V-cycle, copy-out, A z_j, CGS2, norm, scale,
-  // Hessenberg column to the host) captured once per j and replayed
+  // Givens update and stop test, active flags to the host) captured once per j
   hipStream_t cap = nullptr;
   std::vector<hipGraphExec_t> iter_graph;
   fsimg_opts graph_opts{};
   // tables placed in a buffer the plan does not own (the no-allocation
   // solve): never freed here, staging in the host arrays below
   bool fixed = false;
-  double hs_one[kHS] = {};
-  int int_one[3] = {};
+  int ring_one[kMaxVec] = {};
+  int int_one[2] = {};
+  DGiv gv_one{};
 };
 
 namespace fsimg {
@@ -73,18 +88,23 @@ void destroy_plan(BatchPlan *p) {
       p->ctx->plan_bytes -= p->dbytes;
     }
   }
-  if (p->hs_host) (void)hipHostFree(p->hs_host);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (p->ring_host) (void)hipHostFree(p->ring_host);
   if (p->int_host) (void)hipHostFree(p->int_host);
+  if (p->gv_host) (void)hipHostFree(p->gv_host);
   delete p;
 }
 
 size_t plan_bytes_bound(int nlev) {
-  // per instance: level descriptors, Krylov descriptor, three flags, the
-  // Hessenberg slot and one (instance, prefix) entry in each work set; per
-  // plan: one prefix entry and 256-byte alignment of every table
-  const size_t nset = 8 * (size_t)nlev + 4, ntab = 6 + 2 * nset;
-  return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 3 * sizeof(int) + kHS * sizeof(double) +
-         nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 256;
+  // per instance: level descriptors, Krylov descriptor, four flags, its
+  // first small level and tail-list entry, the Hessenberg slot, the FGMRES
+  // control state and one (instance, prefix) entry in each work set (level
+  // sets twice: all levels, and the V-cycle's without the small levels); per
+  // plan: one prefix entry and 64-byte alignment of every table
+  const size_t nset = 14 * (size_t)nlev + 4, ntab = 9 + 2 * nset + nlev;
+  return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 6 * sizeof(int) + kHS * sizeof(double) +
+         sizeof(DGiv) + nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 64;
 }
 
 void drop_plans(fsimg_ctx *ctx) {
@@ -104,7 +124,7 @@ namespace {
 struct Blob {
   std::vector<unsigned char> data;
   size_t add(const void *src, size_t bytes) {
-    const size_t off = (data.size() + 255) & ~size_t(255);
+    const size_t off = (data.size() + 63) & ~size_t(63);
     data.resize(off + bytes);
     if (src && bytes) std::memcpy(data.data() + off, src, bytes);
     return off;
@@ -160,6 +180,30 @@ DLev to_dlev(const DevLevel &L) {
   d.r32 = L.r32; d.x32 = L.x32; d.d32 = L.d32; d.Y32 = L.Y32;
   d.nfree = L.nfree; d.cfree = L.cfree; d.cinv = L.cinv; d.ct0 = L.ct0; d.ct1 = L.ct1;
   return d;
+}
+
+// the first level of hierarchy h that the small-level kernel runs: the
+// levels from there to the coarsest-but-one each hold at most
+// opts.small_level_kib KiB of patch inverses and matrix values in the
+// V-cycle's precision (L - 1: none)
+int tail_from(const fsimg_hier *h) {
+  const int L = (int)h->lev.size();
+  const double limit = 1024.0 * h->opts.small_level_kib;
+  if (limit <= 0.0 || h->opts.smoother != FSIMG_SMOOTHER_VANKA ||
+      h->opts.vanka_schedule != FSIMG_VANKA_GATHER)
+    return L - 1;
+  const bool f32 = h->opts.precision == FSIMG_MIXED;
+  const double w = f32 ? 4.0 : 8.0;
+  int from = L - 1;
+  for (int l = L - 2; l >= 0; --l) {
+    const DevLevel &D = h->lev[l];
+    const double bytes = (double)D.npatch * D.np * (f32 ? D.npc32 : D.npc64) * w +
+                         (double)D.blk.npatch * D.blk.np * (f32 ? D.blk.npc32 : D.blk.npc64) * w +
+                         (double)D.nnzb * D.b * D.b * w;
+    if (bytes > limit) break;
+    from = l;
+  }
+  return from;
 }
 
 // fixed != nullptr: place the tables in that device buffer of fixed_bytes
@@ -221,12 +265,42 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   const size_t act_off = blob.add(nullptr, n * sizeof(int));
   const size_t k_off = blob.add(nullptr, n * sizeof(int));
   const size_t fl_off = blob.add(nullptr, n * sizeof(int));
+  const size_t cyc_off = blob.add(nullptr, n * sizeof(int));
   const size_t hs_off = blob.add(nullptr, (size_t)n * kHS * sizeof(double));
+  const size_t gv_off = blob.add(nullptr, (size_t)n * sizeof(DGiv));
   std::vector<WsRef> r_spmv, r_patch, r_patch2, r_gather, r_restrict, r_prolong, r_cn, r_cf;
+  std::vector<WsRef> v_spmv, v_patch, v_patch2, v_gather, v_restrict, v_prolong;
+  std::vector<int> from(n);
+  for (int i = 0; i < n; ++i) {
+    from[i] = tail_from(hs[i]);
+    P->tails = P->tails || from[i] < (int)hs[i]->lev.size() - 1;
+  }
+  const size_t tfrom_off = blob.add(from.data(), n * sizeof(int32_t));
+  std::vector<size_t> tail_off(Lmax, 0);
+  P->tail_n.assign(Lmax, 0);
+  for (int l = 0; l < Lmax; ++l) {
+    std::vector<int32_t> tl;
+    for (int i = 0; i < n; ++i)
+      if ((int)hs[i]->lev.size() - 1 == l && from[i] < l) tl.push_back(i);
+    P->tail_n[l] = (int)tl.size();
+    if (!tl.empty()) tail_off[l] = blob.add(tl.data(), tl.size() * sizeof(int32_t));
+  }
   for (int l = 0; l < Lmax; ++l) {
     WsHost sp, pa, pa2, ga, re, pr, cn, cf;
+    WsHost vsp, vpa, vpa2, vga, vre, vpr;
     for (int i = 0; i < n; ++i) {
       const int Li = (int)hs[i]->lev.size();
+      if (l < from[i]) {
+        const DevLevel &L = hs[i]->lev[l];
+        vsp.push(i, cdiv(L.nrows, 4 * P->rpw[l] * spmv_group_rows(P->b, word)));
+        vpa.push(i, cdiv(L.npatch, P->ppw[l]));
+        vpa2.push(i, cdiv(L.blk.npatch, P->ppw2[l]));
+        vga.push(i, cdiv(L.n, 256));
+        const DevLevel &Cl = hs[i]->lev[l + 1];
+        vre.push(i, P->dim == 3 ? restrict3_blocks(Cl.cells[0], Cl.cells[1], Cl.cells[2])
+                                : cdiv(Cl.nrows, 256));
+        vpr.push(i, cdiv(L.nrows, 256));
+      }
       if (l < Li - 1) {
         const DevLevel &L = hs[i]->lev[l];
         sp.push(i, cdiv(L.nrows, 4 * P->rpw[l] * spmv_group_rows(P->b, word)));
@@ -251,6 +325,14 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
     r_prolong.push_back(stage(blob, pr));
     r_cn.push_back(stage(blob, cn));
     r_cf.push_back(stage(blob, cf));
+    if (P->tails) {
+      v_spmv.push_back(stage(blob, vsp));
+      v_patch.push_back(stage(blob, vpa));
+      v_patch2.push_back(stage(blob, vpa2));
+      v_gather.push_back(stage(blob, vga));
+      v_restrict.push_back(stage(blob, vre));
+      v_prolong.push_back(stage(blob, vpr));
+    }
   }
   WsHost row0, vec0, kr, ins;
   for (int i = 0; i < n; ++i) {
@@ -302,7 +384,9 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   P->active = reinterpret_cast<int *>(base + act_off);
   P->kcnt = reinterpret_cast<int *>(base + k_off);
   P->flags = reinterpret_cast<int *>(base + fl_off);
+  P->cyc = reinterpret_cast<int *>(base + cyc_off);
   P->hs = reinterpret_cast<double *>(base + hs_off);
+  P->gv = reinterpret_cast<DGiv *>(base + gv_off);
   for (int l = 0; l < Lmax; ++l) {
     P->ws_spmv.push_back(resolve(base, r_spmv[l]));
     P->ws_patch.push_back(resolve(base, r_patch[l]));
@@ -313,22 +397,48 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
     P->ws_cn.push_back(resolve(base, r_cn[l]));
     P->ws_cf.push_back(resolve(base, r_cf[l]));
   }
+  if (P->tails) {
+    for (int l = 0; l < Lmax; ++l) {
+      P->vs_spmv.push_back(resolve(base, v_spmv[l]));
+      P->vs_patch.push_back(resolve(base, v_patch[l]));
+      P->vs_patch2.push_back(resolve(base, v_patch2[l]));
+      P->vs_gather.push_back(resolve(base, v_gather[l]));
+      P->vs_restrict.push_back(resolve(base, v_restrict[l]));
+      P->vs_prolong.push_back(resolve(base, v_prolong[l]));
+    }
+  } else {
+    P->vs_spmv = P->ws_spmv;
+    P->vs_patch = P->ws_patch;
+    P->vs_patch2 = P->ws_patch2;
+    P->vs_gather = P->ws_gather;
+    P->vs_restrict = P->ws_restrict;
+    P->vs_prolong = P->ws_prolong;
+  }
+  P->tfrom = reinterpret_cast<const int32_t *>(base + tfrom_off);
+  P->tail_inst.assign(Lmax, nullptr);
+  for (int l = 0; l < Lmax; ++l)
+    if (P->tail_n[l] > 0) P->tail_inst[l] = reinterpret_cast<const int32_t *>(base + tail_off[l]);
   P->ws_row0 = resolve(base, r_row0);
   P->ws_vec0 = resolve(base, r_vec0);
   P->ws_kry = resolve(base, r_kry);
   P->ws_inst = resolve(base, r_ins);
   if (P->fixed) {
-    P->hs_host = P->hs_one;
+    P->ring_host = P->ring_one;
     P->int_host = P->int_one;
+    P->gv_host = &P->gv_one;
     *out = P;
     return FSIMG_OK;
   }
-  if (hipHostMalloc((void **)&P->hs_host, (size_t)n * kHS * sizeof(double), hipHostMallocDefault) !=
+  bool ev_ok = true;
+  for (hipEvent_t &e : P->ev) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ev_ok ||
+      hipHostMalloc((void **)&P->ring_host, (size_t)kMaxVec * n * sizeof(int), hipHostMallocDefault) !=
           hipSuccess ||
-      hipHostMalloc((void **)&P->int_host, (size_t)3 * n * sizeof(int), hipHostMallocDefault) !=
-          hipSuccess) {
+      hipHostMalloc((void **)&P->int_host, (size_t)2 * n * sizeof(int), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&P->gv_host, (size_t)n * sizeof(DGiv), hipHostMallocDefault) != hipSuccess) {
     destroy_plan(P);
-    return set_error(FSIMG_ERR_HIP, "pinned host staging allocation failed");
+    return set_error(FSIMG_ERR_HIP, "event or pinned host staging creation failed");
   }
   *out = P;
   return FSIMG_OK;
@@ -339,67 +449,81 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
   const int n = P.n;
   const T omega = (T)o.omega;
   const int *act = P.active;
+  // profiling times the finest level's level-wide kernels: no small-level kernel then
+  const bool tail = P.tails && !prof;
+  const std::vector<WorkSet> &Wsp = tail ? P.vs_spmv : P.ws_spmv, &Wpa = tail ? P.vs_patch : P.ws_patch,
+                             &Wpa2 = tail ? P.vs_patch2 : P.ws_patch2,
+                             &Wga = tail ? P.vs_gather : P.ws_gather,
+                             &Wre = tail ? P.vs_restrict : P.ws_restrict,
+                             &Wpr = tail ? P.vs_prolong : P.ws_prolong;
   for (int l = 0; l < P.Lmax; ++l) {
     const DLev *L = P.dlev + (size_t)l * n;
-    if (P.ws_patch[l].nset > 0 || P.ws_patch2[l].nset > 0 || P.ws_spmv[l].nset > 0) {
+    if (Wpa[l].nset > 0 || Wpa2[l].nset > 0 || Wsp[l].nset > 0) {
       const bool p0 = prof && l == 0;
-      if (o.nu_pre == 0) launch_b_fill_x<T>(L, act, P.ws_gather[l], s);
+      if (o.nu_pre == 0) launch_b_fill_x<T>(L, act, Wga[l], s);
       for (int k = 0; k < o.nu_pre; ++k) {
         if (k > 0) {
           hipEvent_t a = p0 ? P.ts.next() : nullptr;
           hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
           if (a) (void)hipEventRecord(a, s);
-          launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
+          launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, Wsp[l], 0, s);
           if (b2) (void)hipEventRecord(b2, s);
         }
         hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
         hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
-        launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], k == 0, L, act,
-                                 P.ws_patch2[l], s);
-        launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, k == 0, k == 0, L, act, P.ws_patch[l],
-                          P.ws_gather[l], s, v0, v1);
+        launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], k == 0, L, act, Wpa2[l], s);
+        launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, k == 0, k == 0, L, act, Wpa[l],
+                          Wga[l], s, v0, v1);
       }
       hipEvent_t a = p0 ? P.ts.next() : nullptr;
       hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
       if (a) (void)hipEventRecord(a, s);
-      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, Wsp[l], 0, s);
       if (b2) (void)hipEventRecord(b2, s);
       hipEvent_t r0 = p0 ? P.tr.next() : nullptr;
       hipEvent_t r1 = p0 ? P.tr.next() : nullptr;
       if (r0) (void)hipEventRecord(r0, s);
-      launch_b_restrict<T>(P.b, P.dim, L, L + n, act, P.ws_restrict[l], s);
+      launch_b_restrict<T>(P.b, P.dim, L, L + n, act, Wre[l], s);
       if (r1) (void)hipEventRecord(r1, s);
     }
+    const bool tl = tail && P.tail_n[l] > 0;
+    if (tl)
+      launch_b_tail<T>(P.b, P.dim, P.dlev, n, act, P.tail_inst[l], P.tail_n[l], P.tfrom, l, false, P.np,
+                       P.npc, P.nl, P.np2, P.npc2, P.nl2, omega, o.nu_pre, o.nu_post, s);
     if (P.ws_cn[l].nset > 0) launch_b_coarse<T>(L, act, P.ws_cn[l], P.ws_cf[l], s);
+    if (tl)
+      launch_b_tail<T>(P.b, P.dim, P.dlev, n, act, P.tail_inst[l], P.tail_n[l], P.tfrom, l, true, P.np,
+                       P.npc, P.nl, P.np2, P.npc2, P.nl2, omega, o.nu_pre, o.nu_post, s);
   }
   for (int l = P.Lmax - 2; l >= 0; --l) {
-    if (P.ws_prolong[l].nset == 0) continue;
+    if (Wpr[l].nset == 0) continue;
     const DLev *L = P.dlev + (size_t)l * n;
     const bool p0 = prof && l == 0;
     hipEvent_t q0 = p0 ? P.tp.next() : nullptr;
     hipEvent_t q1 = p0 ? P.tp.next() : nullptr;
     if (q0) (void)hipEventRecord(q0, s);
-    launch_b_prolong<T>(P.b, P.dim, L, L + n, act, P.ws_prolong[l], s);
+    launch_b_prolong<T>(P.b, P.dim, L, L + n, act, Wpr[l], s);
     if (q1) (void)hipEventRecord(q1, s);
     for (int k = 0; k < o.nu_post; ++k) {
       hipEvent_t a = p0 ? P.ts.next() : nullptr;
       hipEvent_t b2 = p0 ? P.ts.next() : nullptr;
       if (a) (void)hipEventRecord(a, s);
-      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, P.ws_spmv[l], 0, s);
+      launch_b_spmv<T>(P.b, BS_VCYCLE, P.rpw[l], L, P.dkry, act, Wsp[l], 0, s);
       if (b2) (void)hipEventRecord(b2, s);
       hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
       hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
-      launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], false, L, act,
-                               P.ws_patch2[l], s);
-      launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, false, false, L, act, P.ws_patch[l],
-                        P.ws_gather[l], s, v0, v1);
+      launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], false, L, act, Wpa2[l], s);
+      launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, false, false, L, act, Wpa[l], Wga[l],
+                        s, v0, v1);
     }
   }
 }
 
 // the launches of FGMRES iteration j for every active instance: z_j = M^-1 v_j
 // (V-cycle in the plan's precision), w = A z_j, two Gram-Schmidt passes, the
-// norm of w and v_{j+1} = w / ||w|| (Hessenberg column left in P.hs)
+// norm of w and v_{j+1} = w / ||w|| (Hessenberg column left in P.hs), then
+// the device-side Givens update and stop test, and the copy of the active
+// flags to the host ring (slot j)
 void issue_iteration(BatchPlan &P, const fsimg_opts &o, int j, hipStream_t s, bool prof) {
   if (P.mixed) {
     launch_b_copy_in<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
@@ -420,6 +544,9 @@ void issue_iteration(BatchPlan &P, const fsimg_opts &o, int j, hipStream_t s, bo
   launch_b_reduce(P.dkry, P.active, P.ws_inst, 1, P.hs, kOffSS, s);
   launch_b_add_h(P.active, P.ws_inst, j + 1, P.hs, s);
   launch_b_scale(P.dkry, P.active, P.ws_vec0, P.hs, j + 1, s);
+  launch_kry_givens(P.gv, P.hs, P.active, P.n, j, s);
+  (void)hipMemcpyAsync(P.ring_host + (size_t)j * P.n, P.active, P.n * sizeof(int), hipMemcpyDeviceToHost,
+                       s);
 }
 
 bool same_solver_opts(const fsimg_opts &a, const fsimg_opts &b) {
@@ -429,10 +556,9 @@ bool same_solver_opts(const fsimg_opts &a, const fsimg_opts &b) {
 
 // the executable graph of iteration j, captured on the plan's own stream the
 // first time it is needed (kernel and copy nodes only; the instances' active
-// flags are read from device memory, so one graph serves every iteration j of
-// every later solve of this batch composition)
-hipError_t iteration_graph(BatchPlan &P, const fsimg_opts &o, int j,
-                           hipError_t (*fetch_async)(BatchPlan &, hipStream_t)) {
+// flags and control states are read from device memory, so one graph serves
+// every iteration j of every later solve of this batch composition)
+hipError_t iteration_graph(BatchPlan &P, const fsimg_opts &o, int j) {
   if (!P.iter_graph.empty() && !same_solver_opts(P.graph_opts, o)) {
     for (hipGraphExec_t g : P.iter_graph)
       if (g) (void)hipGraphExecDestroy(g);
@@ -447,7 +573,7 @@ hipError_t iteration_graph(BatchPlan &P, const fsimg_opts &o, int j,
   e = hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   issue_iteration(P, o, j, P.cap, false);
-  hipError_t e2 = fetch_async(P, P.cap);
+  hipError_t e2 = hipGetLastError();
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(P.cap, &g);
   if (e == hipSuccess) e = e2;
@@ -456,17 +582,7 @@ hipError_t iteration_graph(BatchPlan &P, const fsimg_opts &o, int j,
   return e;
 }
 
-hipError_t fetch_async(BatchPlan &P, hipStream_t s) {
-  return hipMemcpyAsync(P.hs_host, P.hs, (size_t)P.n * kHS * sizeof(double), hipMemcpyDeviceToHost,
-                        s);
-}
 
-struct InstState {
-  double beta0 = 0, tol = 0, rnorm = 0, bytes = 0;
-  int it = 0, restarts = 0, k = 0, status = FSIMG_OK;
-  bool done = false, in_cycle = false;
-  std::vector<double> H, cs, sn, g, y, hist;
-};
 
 // Algorithmic device-memory bytes (every entry a kernel must touch, once)
 // of the solve's kernels: level l's residual SpMV, Vanka patch kernel +
@@ -584,7 +700,17 @@ fsimg_status check_batch(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, const dou
 }
 
 // FGMRES(m) + V-cycle of the n instances of plan P (eager launches or one
-// graph per iteration)
+// graph per iteration).  The Givens update, the stop test and the
+// least-squares solve run on the device (kb_kry_*), so the host never waits
+// inside a restart cycle for the GPU: it keeps up to `lookahead` iterations
+// in flight and reads each iteration's active flags (copied into a pinned
+// ring) only to stop launching once every instance has stopped; with
+// lookahead 2 the GPU runs iteration j + 1 while the host reads j's flags.
+// The host does not speculate past an iteration that every active instance
+// expects to finish on (the device's flag 2), so an iteration with no active
+// instance (its kernels return at once) runs only after a wrong guess.  The host reads the
+// control state once per restart cycle (continue flags and directions) and
+// the counters once at the end.
 fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double *const *b,
                        double *const *x, fsimg_stats *stats, hipStream_t s, bool use_graph, bool prof) {
   const fsimg_opts &o = hs[0]->opts;
@@ -594,155 +720,89 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
   P->tr.begin_solve();
   P->tp.begin_solve();
   const int m = o.restart;
+  // the no-allocation plan stages through pageable host arrays and has no
+  // events: one iteration at a time, waits on the stream
+  const int depth = P->fixed ? 1 : std::max(1, std::min(o.krylov_lookahead, 2));
   for (int i = 0; i < n; ++i) {
     fsimg_hier *h = hs[i];
     DKry &K = P->hkry[i];
     K.V = h->V; K.Z = h->Z; K.w = h->w; K.partial = h->partial;
     K.b = b[i]; K.x = x[i]; K.n = h->lev[0].n; K.nblk = krylov_blocks(K.n); K.pad = 0;
   }
-  int *act_h = P->int_host, *k_h = P->int_host + n, *fl_h = P->int_host + 2 * n;
-  double *hh = P->hs_host;
-  auto upload_act = [&]() {
-    return hipMemcpyAsync(P->active, act_h, n * sizeof(int), hipMemcpyHostToDevice, s);
-  };
-  auto fetch = [&](bool flags) {
-    hipError_t e = hipMemcpyAsync(hh, P->hs, (size_t)n * kHS * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && flags)
-      e = hipMemcpyAsync(fl_h, P->flags, n * sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e;
-  };
+  int *cyc_h = P->int_host, *k_h = P->int_host + n;
 #define FSIMG_BHIP(expr)                                                                        \
   do {                                                                                          \
     hipError_t e_ = (expr);                                                                     \
     if (e_ != hipSuccess)                                                                       \
       return set_error(FSIMG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
   } while (0)
+  // the continue flags and direction counts of a finished cycle
+  auto read_cycle = [&]() {
+    hipError_t e = hipMemcpyAsync(cyc_h, P->cyc, n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(k_h, P->kcnt, n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
   FSIMG_BHIP(hipMemcpyAsync(P->dkry, P->hkry.data(), n * sizeof(DKry), hipMemcpyHostToDevice, s));
-  std::vector<InstState> S(n);
-  for (int i = 0; i < n; ++i) {
-    act_h[i] = 1;
-    fl_h[i] = 0;
-    S[i].H.assign((size_t)(m + 1) * m, 0.0);
-    S[i].cs.assign(m, 0.0);
-    S[i].sn.assign(m, 0.0);
-    S[i].g.assign(m + 1, 0.0);
-    S[i].y.assign(m, 0.0);
-  }
-  FSIMG_BHIP(upload_act());
-  FSIMG_BHIP(hipMemcpyAsync(P->flags, fl_h, n * sizeof(int), hipMemcpyHostToDevice, s));
+  std::vector<double> bytes(n, 0.0);
+  launch_kry_reset(P->active, P->flags, n, s);
   launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
   launch_b_nonfinite(P->dkry, P->active, P->ws_vec0, P->flags, s);
   launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
   launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
-  FSIMG_BHIP(fetch(true));
-  for (int i = 0; i < n; ++i) {
-    InstState &q = S[i];
-    q.beta0 = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
-    q.rnorm = q.beta0;
-    q.bytes = spmv_bytes_of(hs[i]->lev[0], 8.0) + 2.0 * hs[i]->lev[0].n * 8.0;  // r_0, its checks
-    q.tol = o.rtol * q.beta0;
-    if (fl_h[i] || !std::isfinite(q.beta0)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
-    else if (q.beta0 == 0.0) q.done = true;
-    act_h[i] = q.done ? 0 : 1;
-  }
+  launch_kry_start(P->gv, P->hs, P->flags, P->active, P->cyc, n, o.rtol, o.max_iter, s);
+  for (int i = 0; i < n; ++i) k_h[i] = 0;
+  FSIMG_BHIP(hipMemcpyAsync(cyc_h, P->cyc, n * sizeof(int), hipMemcpyDeviceToHost, s));
+  FSIMG_BHIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i)
+    bytes[i] = spmv_bytes_of(hs[i]->lev[0], 8.0) + 2.0 * hs[i]->lev[0].n * 8.0;  // r_0, its checks
   while (true) {
     bool any = false;
-    for (int i = 0; i < n; ++i) {
-      S[i].in_cycle = !S[i].done;
-      act_h[i] = S[i].in_cycle ? 1 : 0;
-      any |= S[i].in_cycle;
-      if (S[i].in_cycle) {
-        std::fill(S[i].H.begin(), S[i].H.end(), 0.0);
-        std::fill(S[i].g.begin(), S[i].g.end(), 0.0);
-        S[i].g[0] = S[i].rnorm;
-        S[i].k = 0;
-      }
-    }
+    for (int i = 0; i < n; ++i) any |= cyc_h[i] != 0;
     if (!any) break;
-    FSIMG_BHIP(upload_act());
     launch_b_scale(P->dkry, P->active, P->ws_vec0, P->hs, 0, s);  // v_0 = r / ||r||
-    for (int j = 0; j < m; ++j) {
-      bool live = false;
-      for (int i = 0; i < n; ++i) live |= act_h[i] != 0;
-      if (!live) break;
-      if (use_graph) {
-        FSIMG_BHIP(iteration_graph(*P, o, j, &fetch_async));
-        FSIMG_BHIP(hipGraphLaunch(P->iter_graph[j], s));
-        FSIMG_BHIP(hipStreamSynchronize(s));
-      } else {
-        issue_iteration(*P, o, j, s, prof);
-        FSIMG_BHIP(fetch(false));
+    // speculate: launch the next iteration before the previous one's flags
+    // are read, unless every active instance expects to stop (active = 2)
+    // at the iteration in flight, which would leave the speculative one empty
+    int launched = 0, checked = 0;
+    bool live = true, speculate = true;
+    while (live && (launched < m || checked < launched)) {
+      if (launched < m && launched - checked < depth && (launched == checked || speculate)) {
+        const int j = launched++;
+        if (use_graph) {
+          FSIMG_BHIP(iteration_graph(*P, o, j));
+          FSIMG_BHIP(hipGraphLaunch(P->iter_graph[j], s));
+        } else {
+          issue_iteration(*P, o, j, s, prof);
+        }
+        if (!P->fixed) FSIMG_BHIP(hipEventRecord(P->ev[j], s));
+        continue;
       }
-      bool changed = false;
+      FSIMG_BHIP(P->fixed ? hipStreamSynchronize(s) : hipEventSynchronize(P->ev[checked]));
+      const int *fl = P->ring_host + (size_t)checked * n;
+      live = false;
+      speculate = false;
       for (int i = 0; i < n; ++i) {
-        if (!act_h[i]) continue;
-        InstState &q = S[i];
-        const double *hc = hh + (size_t)i * kHS;
-        for (int r = 0; r <= j; ++r) q.H[(size_t)r * m + j] = hc[kOffH + r];
-        const double hn = std::sqrt(hc[kOffSS]);
-        q.H[(size_t)(j + 1) * m + j] = hn;
-        for (int r = 0; r < j; ++r) {
-          const double a0 = q.H[(size_t)r * m + j], a1 = q.H[(size_t)(r + 1) * m + j];
-          q.H[(size_t)r * m + j] = q.cs[r] * a0 + q.sn[r] * a1;
-          q.H[(size_t)(r + 1) * m + j] = -q.sn[r] * a0 + q.cs[r] * a1;
-        }
-        const double hjj = q.H[(size_t)j * m + j];
-        const double den = std::hypot(hjj, hn);
-        q.cs[j] = hjj / den;
-        q.sn[j] = hn / den;
-        q.H[(size_t)j * m + j] = den;
-        q.H[(size_t)(j + 1) * m + j] = 0.0;
-        q.g[j + 1] = -q.sn[j] * q.g[j];
-        q.g[j] = q.cs[j] * q.g[j];
-        ++q.it;
-        q.k = j + 1;
-        q.bytes += iteration_bytes_of(hs[i], j);
-        if ((int)q.hist.size() < FSIMG_HIST) q.hist.push_back(std::fabs(q.g[j + 1]) / q.beta0);
-        if (!std::isfinite(q.g[j + 1]) || std::fabs(q.g[j + 1]) <= q.tol || q.it >= o.max_iter ||
-            hn == 0.0) {
-          act_h[i] = 0;
-          changed = true;
-        }
+        live |= fl[i] != 0;
+        speculate |= fl[i] == 1;
       }
-      if (changed) FSIMG_BHIP(upload_act());
+      ++checked;
     }
     // x += Z y for every instance of this cycle, then the true residual
-    int kmax = 1;
-    for (int i = 0; i < n; ++i) {
-      InstState &q = S[i];
-      k_h[i] = 0;
-      act_h[i] = q.in_cycle ? 1 : 0;
-      if (!q.in_cycle) continue;
-      const int k = q.k;
-      for (int r = k - 1; r >= 0; --r) {
-        double t = q.g[r];
-        for (int c = r + 1; c < k; ++c) t -= q.H[(size_t)r * m + c] * q.y[c];
-        q.y[r] = t / q.H[(size_t)r * m + r];
-      }
-      for (int r = 0; r < k; ++r) hh[(size_t)i * kHS + kOffY + r] = q.y[r];
-      k_h[i] = k;
-      kmax = std::max(kmax, k);
-    }
-    FSIMG_BHIP(hipMemcpyAsync(P->hs, hh, (size_t)n * kHS * sizeof(double), hipMemcpyHostToDevice, s));
-    FSIMG_BHIP(hipMemcpyAsync(P->kcnt, k_h, n * sizeof(int), hipMemcpyHostToDevice, s));
-    FSIMG_BHIP(upload_act());
-    launch_b_combine(P->dkry, P->active, P->ws_vec0, P->hs, P->kcnt, kmax, s);
+    launch_kry_ysolve(P->gv, P->hs, P->active, P->kcnt, n, s);
+    launch_b_combine(P->dkry, P->active, P->ws_vec0, P->hs, P->kcnt, launched, s);
     launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
     launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
     launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
-    FSIMG_BHIP(fetch(false));
+    launch_kry_restart(P->gv, P->hs, P->active, P->cyc, n, s);
+    FSIMG_BHIP(read_cycle());
     for (int i = 0; i < n; ++i) {
-      InstState &q = S[i];
-      if (!q.in_cycle) continue;
-      ++q.restarts;
-      q.bytes += restart_bytes_of(hs[i], q.k);
-      q.rnorm = std::sqrt(hh[(size_t)i * kHS + kOffSS]);
-      if (!std::isfinite(q.rnorm)) { q.status = FSIMG_ERR_NONFINITE; q.done = true; }
-      else if (q.rnorm <= q.tol) q.done = true;
-      else if (q.it >= o.max_iter) { q.status = FSIMG_ERR_NOCONV; q.done = true; }
+      for (int j = 0; j < k_h[i]; ++j) bytes[i] += iteration_bytes_of(hs[i], j);
+      if (k_h[i] > 0) bytes[i] += restart_bytes_of(hs[i], k_h[i]);
     }
   }
+  FSIMG_BHIP(hipMemcpyAsync(P->gv_host, P->gv, n * sizeof(DGiv), hipMemcpyDeviceToHost, s));
+  FSIMG_BHIP(hipStreamSynchronize(s));
   FSIMG_BHIP(hipGetLastError());
   double vms = 0.0, sms = 0.0, rms = 0.0, pms = 0.0;
   int vn = 0, sn = 0, rn = 0, pn = 0;
@@ -756,7 +816,7 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   fsimg_status ret = FSIMG_OK;
   for (int i = 0; i < n; ++i) {
-    const InstState &q = S[i];
+    const DGiv &q = P->gv_host[i];
     if (stats) {
       fsimg_stats &st = stats[i];
       st = fsimg_stats{};
@@ -771,8 +831,8 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
       st.prolong_ms = pms; st.prolong_launches = pn;
       st.setup_ms = hs[i]->setup_ms;
       st.factor_ms = hs[i]->factor_ms;
-      st.bytes_moved = q.bytes;
-      st.nhist = (int)q.hist.size();
+      st.bytes_moved = bytes[i];
+      st.nhist = std::min(q.nhist, FSIMG_HIST);
       for (int t = 0; t < st.nhist; ++t) st.res_hist[t] = q.hist[t];
     }
     if (ret == FSIMG_OK && q.status != FSIMG_OK) ret = (fsimg_status)q.status;

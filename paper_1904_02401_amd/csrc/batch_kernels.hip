@@ -4,6 +4,7 @@
 // per-instance computation (rows, patches, nodes, reduction blocking) depends
 // on that instance alone, so an instance's result does not depend on which
 // other instances share the launch.
+#include <algorithm>
 #include <type_traits>
 
 #include "device_ops.h"
@@ -258,6 +259,155 @@ __global__ __launch_bounds__(256) void kb_restrict3(const DLev *__restrict__ lev
   }
 }
 
+// one coarse node of the 3D restriction with the slab kernel's summation
+// order (z taps, then x, then y), so both give the same bits
+template <int B, typename T>
+__device__ __forceinline__ void restrict3_node(int64_t node, const DLev &C, const T *rf_, T *rc_) {
+  const dev::gptr<const T> rf = dev::glb(rf_);
+  const dev::gptr<T> rc = dev::glb(rc_);
+  const dev::gptr<const uint8_t> mask = dev::glb(C.mask);
+  const int NX = 2 * C.cells[0] + 1, NY = 2 * C.cells[1] + 1;
+  const int FX = 4 * C.cells[0] + 1, FY = 4 * C.cells[1] + 1, FZ = 4 * C.cells[2] + 1;
+  const int X = (int)(node % NX), Y = (int)((node / NX) % NY), Z = (int)(node / ((int64_t)NX * NY));
+  int fxt[5], fyt[5], fzt[5];
+  T wxt[5], wyt[5], wzt[5];
+  taps_1d<T>(X, FX, fxt, wxt);
+  taps_1d<T>(Y, FY, fyt, wyt);
+  taps_1d<T>(Z, FZ, fzt, wzt);
+  T v[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) v[c] = T(0);
+#pragma unroll 1
+  for (int qy = 0; qy < 5; ++qy) {
+    T h[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) h[c] = T(0);
+#pragma unroll 1
+    for (int qx = 0; qx < 5; ++qx) {
+      T a[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) a[c] = T(0);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        if (wzt[q] != T(0)) {
+          const dev::gptr<const T> src = rf + (((int64_t)fzt[q] * FY + fyt[qy]) * FX + fxt[qx]) * B;
+#pragma unroll
+          for (int c = 0; c < B; ++c) a[c] += wzt[q] * src[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < B; ++c) h[c] += wxt[qx] * a[c];
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[c] += wyt[qy] * h[c];
+  }
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const int64_t dof = node * B + c;
+    rc[dof] = mask[dof] ? T(0) : v[c];
+  }
+}
+
+// ------------------------------------------------------------ small levels
+// The levels of an instance from tfrom[i] down to (excluding) its coarsest
+// level `coarse`, in one workgroup per instance (1024 threads in FP32, 512 in
+// FP64, where the register budget of 1024 threads would spill): every step
+// of the V-cycle there (Vanka sweeps, residuals, transfers) as a loop of the
+// same per-row / per-patch / per-dof device bodies the level-wide kernels
+// run, with workgroup barriers between the steps instead of kernel
+// boundaries.  A row, patch or dof is computed by the same lanes in the same
+// order as in the level-wide kernels, so the results are the same bits.
+// up = 0: pre-smoothing, residual and restriction of each level, top down;
+// up = 1: prolongation and post-smoothing of each level, bottom up.  The
+// coarse solve runs between the two launches.
+template <int B, int DIM, typename T>
+__device__ __forceinline__ void tail_residual(const DLev &F) {
+  constexpr int GR = spmv_group_rows(B, (int)sizeof(T));
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = blockDim.x / kWave;
+  for (int64_t row0 = (int64_t)(threadIdx.x / kWave) * GR; row0 < F.nrows; row0 += nw * GR)
+    dev::spmv_rows<B, T, 1, 1>(row0, F.nrows, lane, F.rowptr, F.colind, LV<T>::vals(F), LV<T>::x(F),
+                               LV<T>::r(F), F.mask, LV<T>::d(F));
+  __syncthreads();
+}
+
+template <int B, typename T>
+__device__ __forceinline__ void tail_smooth(const DLev &F, int np, int npc, int nl, int np2, int npc2,
+                                            int nl2, T omega, bool first, T *dl) {
+  const T *dsrc = first ? LV<T>::r(F) : LV<T>::d(F);
+  if (F.npatch2 > 0) {  // block patches first, as the level-wide launches
+    const int ppw = (int)blockDim.x / np2;
+    for (int64_t pf = 0; pf < F.npatch2; pf += ppw) {
+      dev::vanka_patch_wg<T>(pf, F.npatch2, np2, npc2, B, nl2, ppw, F.pnodes2, LV<T>::inv2(F), dsrc,
+                             LV<T>::Y(F) + F.yofs2, 0, nullptr, nullptr, F.mask, T(0), dl);
+      __syncthreads();
+    }
+  }
+  if (F.npatch > 0) {
+    const int ppw = (int)blockDim.x / np;
+    for (int64_t pf = 0; pf < F.npatch; pf += ppw) {
+      dev::vanka_patch_wg<T>(pf, F.npatch, np, npc, B, nl, ppw, F.pnodes, LV<T>::inv(F), dsrc,
+                             LV<T>::Y(F), 0, nullptr, nullptr, F.mask, T(0), dl);
+      __syncthreads();
+    }
+  }
+  for (int64_t dof = threadIdx.x; dof < F.n; dof += blockDim.x)
+    dev::vanka_gather_dof<T>(dof, B, F.gptr, F.gidx, LV<T>::Y(F), LV<T>::sc(F), F.mask, omega,
+                             first ? 1 : 0, LV<T>::x(F));
+  __syncthreads();
+}
+
+template <int B, int DIM, typename T>
+__global__ __launch_bounds__(tail_threads<T>()) void kb_vcycle_tail(const DLev *__restrict__ lev, int n,
+                                                       const int *__restrict__ active,
+                                                       const int32_t *__restrict__ tinst,
+                                                       const int32_t *__restrict__ tfrom, int coarse,
+                                                       int up, int np, int npc, int nl, int np2,
+                                                       int npc2, int nl2, T omega, int nu_pre,
+                                                       int nu_post) {
+  extern __shared__ unsigned char smem_raw[];
+  T *dl = reinterpret_cast<T *>(smem_raw);
+  const int i = tinst[blockIdx.x];
+  if (!active[i]) return;  // uniform per workgroup
+  const int l0 = tfrom[i];
+  if (!up) {
+    for (int l = l0; l < coarse; ++l) {
+      const DLev &F = lev[(size_t)l * n + i];
+      if (nu_pre == 0) {
+        for (int64_t k = threadIdx.x; k < F.n; k += blockDim.x) LV<T>::x(F)[k] = T(0);
+        __syncthreads();
+      }
+      for (int k = 0; k < nu_pre; ++k) {
+        if (k > 0) tail_residual<B, DIM, T>(F);
+        tail_smooth<B, T>(F, np, npc, nl, np2, npc2, nl2, omega, k == 0, dl);
+      }
+      tail_residual<B, DIM, T>(F);
+      const DLev &C = lev[(size_t)(l + 1) * n + i];
+      for (int64_t node = threadIdx.x; node < C.nrows; node += blockDim.x) {
+        if constexpr (DIM == 3)
+          restrict3_node<B, T>(node, C, LV<T>::d(F), LV<T>::r(C));
+        else
+          dev::restrict_node<B, DIM, T>(node, C.cells[0], C.cells[1], C.cells[2], LV<T>::d(F),
+                                        LV<T>::r(C), C.mask);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int l = coarse - 1; l >= l0; --l) {
+      const DLev &F = lev[(size_t)l * n + i];
+      const DLev &C = lev[(size_t)(l + 1) * n + i];
+      for (int64_t node = threadIdx.x; node < F.nrows; node += blockDim.x)
+        dev::prolong_node<B, DIM, T>(node, C.cells[0], C.cells[1], C.cells[2], LV<T>::x(C), LV<T>::x(F),
+                                     F.mask);
+      __syncthreads();
+      for (int k = 0; k < nu_post; ++k) {
+        tail_residual<B, DIM, T>(F);
+        tail_smooth<B, T>(F, np, npc, nl, np2, npc2, nl2, omega, false, dl);
+      }
+    }
+  }
+}
+
 template <int B, int DIM, typename T>
 __global__ __launch_bounds__(256) void kb_prolong(const DLev *__restrict__ levF,
                                                   const DLev *__restrict__ levC,
@@ -498,6 +648,143 @@ __global__ __launch_bounds__(256) void kb_activate(int *__restrict__ active, int
   if (i < n) active[i] = 1;
 }
 
+// ------------------------------------------------ FGMRES control (device)
+// One thread per instance.  The arithmetic is that of FGMRES with Givens
+// rotations (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.6):
+// each new Hessenberg column is rotated by the previous rotations, a new
+// rotation zeroes its subdiagonal, and |g_{j+1}| is the residual norm of the
+// least-squares solution.
+__global__ __launch_bounds__(64) void kb_kry_reset(int *__restrict__ active, int *__restrict__ flags,
+                                                   int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  active[i] = 1;
+  flags[i] = 0;
+}
+
+__device__ __forceinline__ void kry_open_cycle(DGiv &G, double rn) {
+  G.g[0] = rn;
+  for (int r = 1; r <= kMaxVec; ++r) G.g[r] = 0.0;
+  G.k = 0;
+}
+
+__global__ __launch_bounds__(64) void kb_kry_start(DGiv *__restrict__ gv, const double *__restrict__ hs,
+                                                   const int *__restrict__ flags,
+                                                   int *__restrict__ active, int *__restrict__ cyc,
+                                                   int n, double rtol, int max_iter) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  DGiv &G = gv[i];
+  const double beta0 = sqrt(hs[(int64_t)i * kHS + kOffSS]);
+  G.beta0 = beta0;
+  G.rnorm = beta0;
+  G.rprev = 0.0;
+  G.tol = rtol * beta0;
+  G.it = 0;
+  G.restarts = 0;
+  G.nhist = 0;
+  G.maxit = max_iter;
+  G.status = FSIMG_OK;
+  int go = 1;
+  if (flags[i] || !isfinite(beta0)) {
+    G.status = FSIMG_ERR_NONFINITE;
+    go = 0;
+  } else if (beta0 == 0.0) {
+    go = 0;
+  }
+  kry_open_cycle(G, beta0);
+  G.incyc = go;
+  active[i] = go;
+  cyc[i] = go;
+}
+
+__global__ __launch_bounds__(64) void kb_kry_givens(DGiv *__restrict__ gv, const double *__restrict__ hs,
+                                                    int *__restrict__ active, int n, int j) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n || !active[i]) return;
+  DGiv &G = gv[i];
+  const double *hc = hs + (int64_t)i * kHS;
+  double *col = G.R + j * kMaxVec;
+  for (int r = 0; r <= j; ++r) col[r] = hc[kOffH + r];
+  const double hn = sqrt(hc[kOffSS]);
+  for (int r = 0; r < j; ++r) {
+    const double a0 = col[r], a1 = col[r + 1];
+    col[r] = G.cs[r] * a0 + G.sn[r] * a1;
+    col[r + 1] = -G.sn[r] * a0 + G.cs[r] * a1;
+  }
+  const double hjj = col[j];
+  const double den = hypot(hjj, hn);
+  G.cs[j] = hjj / den;
+  G.sn[j] = hn / den;
+  col[j] = den;
+  const double gj = G.g[j];
+  G.g[j + 1] = -G.sn[j] * gj;
+  G.g[j] = G.cs[j] * gj;
+  ++G.it;
+  G.k = j + 1;
+  const double res = fabs(G.g[j + 1]);
+  if (G.nhist < FSIMG_HIST) G.hist[G.nhist++] = res / G.beta0;
+  if (!isfinite(G.g[j + 1]) || res <= G.tol || G.it >= G.maxit || hn == 0.0) {
+    active[i] = 0;
+  } else {
+    const double rho = G.rprev > 0.0 ? res / G.rprev : 1.0;
+    active[i] = (res * rho <= G.tol || G.it + 1 >= G.maxit) ? 2 : 1;
+  }
+  G.rprev = res;
+}
+
+__global__ __launch_bounds__(64) void kb_kry_ysolve(DGiv *__restrict__ gv, double *__restrict__ hs,
+                                                    int *__restrict__ active, int *__restrict__ kcnt,
+                                                    int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  DGiv &G = gv[i];
+  if (!G.incyc) {
+    active[i] = 0;
+    kcnt[i] = 0;
+    return;
+  }
+  const int k = G.k;
+  double *y = hs + (int64_t)i * kHS + kOffY;
+  for (int r = k - 1; r >= 0; --r) {
+    double t = G.g[r];
+    for (int c = r + 1; c < k; ++c) t -= G.R[c * kMaxVec + r] * y[c];
+    y[r] = t / G.R[r * kMaxVec + r];
+  }
+  kcnt[i] = k;
+  active[i] = 1;
+}
+
+__global__ __launch_bounds__(64) void kb_kry_restart(DGiv *__restrict__ gv, const double *__restrict__ hs,
+                                                     int *__restrict__ active, int *__restrict__ cyc,
+                                                     int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  DGiv &G = gv[i];
+  if (!G.incyc) {
+    active[i] = 0;
+    cyc[i] = 0;
+    return;
+  }
+  ++G.restarts;
+  const double rn = sqrt(hs[(int64_t)i * kHS + kOffSS]);
+  G.rnorm = rn;
+  int go = 1;
+  if (!isfinite(rn)) {
+    G.status = FSIMG_ERR_NONFINITE;
+    go = 0;
+  } else if (rn <= G.tol) {
+    go = 0;
+  } else if (G.it >= G.maxit) {
+    G.status = FSIMG_ERR_NOCONV;
+    go = 0;
+  }
+  if (go) kry_open_cycle(G, rn);
+  G.incyc = go;
+  active[i] = go;
+  cyc[i] = go;
+}
+
 inline dim3 grid_of(const WorkSet &ws) { return dim3((unsigned)ws.nblocks); }
 
 }  // namespace
@@ -604,6 +891,27 @@ void launch_b_prolong(int b, int dim, const DLev *levF, const DLev *levC, const 
 }
 
 template <typename T>
+void launch_b_tail(int b, int dim, const DLev *lev, int n, const int *active, const int32_t *tinst,
+                   int ninst, const int32_t *tfrom, int coarse, bool up, int np, int npc, int nl,
+                   int np2, int npc2, int nl2, T omega, int nu_pre, int nu_post, hipStream_t s) {
+  if (ninst == 0) return;
+  constexpr int nt = tail_threads<T>();
+  size_t lds = (size_t)(nt / np) * npc;
+  if (np2 > 0) lds = std::max(lds, (size_t)(nt / np2) * npc2);
+  lds *= sizeof(T);
+#define FSIMG_BT(BV, DV)                                                                          \
+  if (b == BV && dim == DV) {                                                                     \
+    hipLaunchKernelGGL((kb_vcycle_tail<BV, DV, T>), dim3((unsigned)ninst), dim3(nt), lds,          \
+                       s, lev, n, active, tinst, tfrom, coarse, up ? 1 : 0, np, npc, nl, np2, npc2, \
+                       nl2, omega, nu_pre, nu_post);                                              \
+    return;                                                                                       \
+  }
+  FSIMG_BT(1, 2) FSIMG_BT(2, 2) FSIMG_BT(3, 2) FSIMG_BT(4, 2)
+  FSIMG_BT(1, 3) FSIMG_BT(2, 3) FSIMG_BT(3, 3) FSIMG_BT(4, 3)
+#undef FSIMG_BT
+}
+
+template <typename T>
 void launch_b_coarse(const DLev *lev, const int *active, const WorkSet &wn, const WorkSet &wf,
                      hipStream_t s) {
   if (wn.nblocks > 0) hipLaunchKernelGGL((kb_coarse_pre<T>), grid_of(wn), dim3(256), 0, s, lev, active, wn);
@@ -695,6 +1003,29 @@ void launch_b_activate(int *active, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(kb_activate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, active, n);
 }
 
+namespace {
+dim3 kry_grid(int n) { return dim3((unsigned)((n + 63) / 64)); }
+}  // namespace
+
+void launch_kry_reset(int *active, int *flags, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_kry_reset, kry_grid(n), dim3(64), 0, s, active, flags, n);
+}
+void launch_kry_start(DGiv *gv, const double *hs, const int *flags, int *active, int *cyc, int n,
+                      double rtol, int max_iter, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(kb_kry_start, kry_grid(n), dim3(64), 0, s, gv, hs, flags, active, cyc, n, rtol,
+                       max_iter);
+}
+void launch_kry_givens(DGiv *gv, const double *hs, int *active, int n, int j, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_kry_givens, kry_grid(n), dim3(64), 0, s, gv, hs, active, n, j);
+}
+void launch_kry_ysolve(DGiv *gv, double *hs, int *active, int *kcnt, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_kry_ysolve, kry_grid(n), dim3(64), 0, s, gv, hs, active, kcnt, n);
+}
+void launch_kry_restart(DGiv *gv, const double *hs, int *active, int *cyc, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_kry_restart, kry_grid(n), dim3(64), 0, s, gv, hs, active, cyc, n);
+}
+
 #define FSIMG_BINST(T)                                                                           \
   template void launch_b_spmv<T>(int, int, int, const DLev *, const DKry *, const int *,         \
                                  const WorkSet &, int, hipStream_t);                             \
@@ -705,6 +1036,9 @@ void launch_b_activate(int *active, int n, hipStream_t s) {
   template void launch_b_vanka_blocks<T>(int, int, int, int, int, bool, const DLev *, const int *, \
                                          const WorkSet &, hipStream_t);                          \
   template void launch_b_fill_x<T>(const DLev *, const int *, const WorkSet &, hipStream_t);     \
+  template void launch_b_tail<T>(int, int, const DLev *, int, const int *, const int32_t *, int,  \
+                                 const int32_t *, int, bool, int, int, int, int, int, int, T, int,  \
+                                 int, hipStream_t);                                               \
   template void launch_b_restrict<T>(int, int, const DLev *, const DLev *, const int *,          \
                                      const WorkSet &, hipStream_t);                              \
   template void launch_b_prolong<T>(int, int, const DLev *, const DLev *, const int *,           \

@@ -157,6 +157,21 @@ constexpr int kOffH1 = 0, kOffH2 = 32, kOffH = 64, kOffSS = 96, kOffY = 128;
 
 int krylov_blocks(int64_t n);  // reduction blocks of a vector of length n
 
+// FGMRES control state of one instance, kept on the device and written only by
+// the kb_kry_* kernels: the counters and outcome the host reads after the
+// solve, then the least-squares data of the current restart cycle (rotated
+// Hessenberg columns R, column j at R[j * kMaxVec + r] for r <= j, the Givens
+// rotations and the rotated right-hand side g).
+struct DGiv {
+  double beta0, tol, rnorm;   // ||r_0||, stop threshold rtol ||r_0||, last true residual
+  double rprev;               // the previous iteration's residual estimate
+  int it, k, restarts, status;
+  int nhist, incyc, maxit, pad;
+  double hist[FSIMG_HIST];    // |g_{j+1}| / ||r_0|| after each of the first iterations
+  double cs[kMaxVec], sn[kMaxVec], g[kMaxVec + 1];
+  double R[kMaxVec * kMaxVec];
+};
+
 enum BatchSpmvSrc { BS_VCYCLE = 0, BS_AZ = 1, BS_RESID = 2 };
 
 // rpw: block rows per wavefront (the work set counts workgroups of 4 * rpw rows)
@@ -180,6 +195,16 @@ template <typename T>
 void launch_b_restrict(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
                        const WorkSet &ws, hipStream_t s);
 int64_t restrict3_blocks(int cx, int cy, int cz);
+// the levels of each listed instance below tfrom[i] in one workgroup of
+// tail_threads<T>() threads (kb_vcycle_tail): up = false pre-smooths, forms
+// the residual and restricts on levels tfrom[i] .. coarse - 1; up = true
+// prolongs and post-smooths them bottom up
+template <typename T>
+constexpr int tail_threads() { return sizeof(T) == 8 ? 512 : 1024; }
+template <typename T>
+void launch_b_tail(int b, int dim, const DLev *lev, int n, const int *active, const int32_t *tinst,
+                   int ninst, const int32_t *tfrom, int coarse, bool up, int np, int npc, int nl,
+                   int np2, int npc2, int nl2, T omega, int nu_pre, int nu_post, hipStream_t s);
 template <typename T>
 void launch_b_prolong(int b, int dim, const DLev *levF, const DLev *levC, const int *active,
                       const WorkSet &ws, hipStream_t s);
@@ -206,6 +231,24 @@ void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, con
 void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, int *flags,
                         hipStream_t s);
 void launch_b_activate(int *active, int n, hipStream_t s);  // active[0..n) = 1
+// device-side FGMRES control, one thread per instance (see DGiv):
+// reset: active = 1, flags = 0 before the first residual
+void launch_kry_reset(int *active, int *flags, int n, hipStream_t s);
+// start: beta0 = ||r_0|| from hs[kOffSS]; an instance with a non-finite or
+// zero residual is done; the others open their first cycle (active = cyc = 1)
+void launch_kry_start(DGiv *gv, const double *hs, const int *flags, int *active, int *cyc, int n,
+                      double rtol, int max_iter, hipStream_t s);
+// after iteration j: rotate the Hessenberg column hs[kOffH..], new rotation,
+// g update, residual history; active = 0 once |g_{j+1}| <= tol, max_iter is
+// reached, the column breaks down (h_{j+1,j} = 0) or g is not finite; else
+// active = 2 when the next iteration is expected to stop it (the last
+// residual reduction factor repeated reaches tol, or max_iter is next),
+// 1 otherwise (kernels treat any non-zero value as active)
+void launch_kry_givens(DGiv *gv, const double *hs, int *active, int n, int j, hipStream_t s);
+// end of a cycle: y = R^-1 g into hs[kOffY..], kcnt = k; active = in cycle
+void launch_kry_ysolve(DGiv *gv, double *hs, int *active, int *kcnt, int n, hipStream_t s);
+// after the true residual: stop test, next cycle's g; active = cyc = continues
+void launch_kry_restart(DGiv *gv, const double *hs, int *active, int *cyc, int n, hipStream_t s);
 
 // ---------------------------------------------------------------- kernels
 template <typename T>

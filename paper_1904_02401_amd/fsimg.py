@@ -50,7 +50,8 @@ class fsimg_opts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("vanka_schedule", ctypes.c_int),
                 ("vanka_weighting", ctypes.c_int), ("profile", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("vanka_patches", ctypes.c_int),
-                ("smoother", ctypes.c_int), ("omega_ilu", ctypes.c_double)]
+                ("smoother", ctypes.c_int), ("omega_ilu", ctypes.c_double),
+                ("krylov_lookahead", ctypes.c_int), ("small_level_kib", ctypes.c_int)]
 
 
 FSIMG_HIST = 64

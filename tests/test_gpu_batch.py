@@ -142,3 +142,66 @@ def test_graph_replays_equal_eager(ctx, instances, precision):
     finally:
         for h in hg + he:
             fsimg.fsimg_hier_destroy(h)
+
+
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_device_krylov_control(ctx, instances, precision):
+    """The Givens update, the stop test and the least-squares solve run on the
+    device.  Whether the host keeps one or two FGMRES iterations in flight
+    (krylov_lookahead) and whether iterations are launched eagerly or from
+    graphs, the solutions, iteration and restart counts and residual
+    histories are identical.  Short restart cycles (m = 3) reach the
+    tolerance with ceil(iters / 3) cycles, within one iteration of the
+    oracle's FGMRES(3) with its own V-cycle (FP64), and max_iter stops a
+    cycle midway."""
+    from oracle.step import solve_system
+
+    sub = instances[:4]
+
+    def run(**kw):
+        o = fsimg.fsimg_default_opts(precision=precision, restart=3, **kw)
+        hs = [fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o) for P in sub]
+        try:
+            for h in hs:
+                fsimg.fsimg_factor(h)
+            bs = [torch.tensor(P.rhs["mom"], device=DEV) for P in sub]
+            xs = [torch.zeros_like(b) for b in bs]
+            sts = fsimg.fsimg_solve_batch(hs, bs, xs)
+            torch.cuda.synchronize()
+            return [x.cpu().numpy() for x in xs], sts
+        finally:
+            for h in hs:
+                fsimg.fsimg_hier_destroy(h)
+
+    ref_x, ref_st = run(krylov_lookahead=1, graphs=0)
+    for kw in (dict(krylov_lookahead=2, graphs=0), dict(krylov_lookahead=2, graphs=1),
+               dict(krylov_lookahead=1, graphs=1)):
+        xs, sts = run(**kw)
+        for k in range(len(sub)):
+            np.testing.assert_array_equal(xs[k], ref_x[k])
+            for key in ("iters", "restarts", "nhist", "status"):
+                assert sts[k][key] == ref_st[k][key], (kw, k, key)
+            assert list(sts[k]["res_hist"]) == list(ref_st[k]["res_hist"]), (kw, k)
+    for k, P in enumerate(sub):
+        st = ref_st[k]
+        assert st["restarts"] == -(-st["iters"] // 3), st
+        assert _res(P, ref_x[k]) <= 1e-8 * 1.01
+        if precision == fsimg.FSIMG_FP64:
+            cells = [lv.cells for lv in P.levels]
+            _, info, _ = solve_system(P.system("mom"), cells, P.rhs["mom"], rtol=1e-8, restart=3,
+                                      weighting="mult")
+            assert abs(st["iters"] - info["iters"]) <= 1, (st["iters"], info["iters"])
+    # max_iter = 5 with m = 3: one full cycle, then two iterations of the second
+    P = sub[0]
+    o = fsimg.fsimg_default_opts(precision=precision, restart=3, max_iter=5, rtol=1e-14)
+    h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), o)
+    try:
+        fsimg.fsimg_factor(h)
+        b = torch.tensor(P.rhs["mom"], device=DEV)
+        x = torch.zeros_like(b)
+        st = fsimg.fsimg_solve(h, b, x, raise_on_noconv=False)
+        assert st["status"] == fsimg.FSIMG_ERR_NOCONV
+        assert st["iters"] == 5 and st["restarts"] == 2 and st["nhist"] == 5
+        assert 0.0 < st["rel_res"] < 1.0
+    finally:
+        fsimg.fsimg_hier_destroy(h)

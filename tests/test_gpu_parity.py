@@ -404,3 +404,43 @@ def test_solve_stats_fields(ctx, probs, schedule):
         A_bytes = lev.nnzb * 16 * 8
         assert st["bytes_moved"] > st["iters"] * 4 * A_bytes  # >= 4 residual SpMVs per V-cycle
         assert st["bytes_moved"] < st["iters"] * 200 * A_bytes
+
+
+@pytest.mark.parametrize("name,system,patches", [("t2", "mom", fsimg.FSIMG_PATCH_ELEMENT),
+                                                 ("c1", "mom", fsimg.FSIMG_PATCH_ELEMENT),
+                                                 ("c1", "ale", fsimg.FSIMG_PATCH_ELEMENT),
+                                                 ("t3", "mom", fsimg.FSIMG_PATCH_ELEMENT),
+                                                 ("t3", "mom", fsimg.FSIMG_PATCH_BLOCK),
+                                                 ("t3", "ale", fsimg.FSIMG_PATCH_ELEMENT)])
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_small_level_kernel_same_bits(ctx, probs, name, system, patches, precision):
+    """The levels run in one workgroup per instance (kb_vcycle_tail) give the
+    level-wide kernels' bits: a V-cycle and a whole solve with no small
+    levels, the default threshold and every level in the small-level kernel
+    (finest included) agree exactly, and the solve meets the FP64-checked
+    tolerance."""
+    P = probs[name]
+    m = P.levels[0].systems[system]
+    b = P.rhs[system] if system in P.rhs else np.random.default_rng(5).standard_normal(m.nrows * m.b)
+    b = b.copy()
+    b[m.dirichlet.astype(bool)] = 0.0
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(m.nrows * m.b)
+    outs = []
+    for kib in (0, 2048, 1 << 20):
+        with Hier(ctx, P, system, precision=precision, vanka_patches=patches, small_level_kib=kib) as H:
+            fsimg.fsimg_factor(H.h)
+            T = torch.float32 if precision == fsimg.FSIMG_MIXED else torch.float64
+            z = torch.empty(v.size, device=DEV, dtype=T)
+            fsimg.fsimg_vcycle(H.h, precision, _t(v, T), z)
+            x = torch.zeros(b.size, device=DEV, dtype=torch.float64)
+            st = fsimg.fsimg_solve(H.h, _t(b), x)
+            outs.append((_np(z), _np(x), st["iters"]))
+    for z, x, it in outs[1:]:
+        np.testing.assert_array_equal(z, outs[0][0])
+        np.testing.assert_array_equal(x, outs[0][1])
+        assert it == outs[0][2]
+    A = to_csr(m)
+    r = b - A @ outs[0][1]
+    r[m.dirichlet.astype(bool)] = 0.0
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * 1.01
