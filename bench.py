@@ -155,10 +155,15 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     hs = {}
     t0 = time.perf_counter()
     systems = ["mom", "ale"] + (["mass"] if with_mass else [])
+    sched_ms = {}
     for name in systems:
         o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches,
-                                     vanka_schedule=schedule, smoother=smoother,
+                                     vanka_schedule=max(schedule, 0), smoother=smoother,
                                      krylov_lookahead=lookahead, small_level_kib=small_kib)
+        if schedule < 0:  # auto: the fastest schedule, measured on this system's hierarchy
+            ms, best = fsimg.fsimg_tune_schedule(ctx, level_dicts(P, name), o, reps=3)
+            sched_ms[name] = {"gather": ms[0], "parity": ms[1], "greedy": ms[2], "chosen": best}
+            o.vanka_schedule = best
         hs[name] = fsimg.fsimg_hier_create(ctx, level_dicts(P, name), o)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -242,6 +247,7 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     opts_prof(hs["mom"], 0)
     info_m = fsimg.fsimg_hier_info(hs["mom"], 0)
     res = dict(t_step=t_step, t_setup=t_setup, t_factor=t_factor, t_tune=t_tune, shapes=shapes,
+               schedule_ms=sched_ms,
                stats=stats[-1], prof=prof, factor_ms=factor_ms, lat=lat,
                solve_ms={k: [st[j]["solve_ms"] for st in stats if st[j] is not None]
                          for j, k in enumerate(("mom", "mass", "ale"))},
@@ -1010,8 +1016,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes, no tuning")
-    ap.add_argument("--schedule", choices=["gather", "parity", "greedy"], default="gather",
-                    help="Vanka schedule: per-dof gather (batched path) or coloured scatter")
+    ap.add_argument("--schedule", choices=["gather", "parity", "greedy", "auto"], default="gather",
+                    help="Vanka schedule: per-dof gather (batched path), coloured scatter, or "
+                         "auto (time all three per system at setup, use the fastest)")
     ap.add_argument("--patches", choices=["element", "block"], default=None,
                     help="Vanka patches: one element, or 2x2(x2) element blocks (3D: solid only); "
                          "default element, block on the benchmark channel")
@@ -1114,7 +1121,7 @@ def main():
         r = run_gpu(P, prec, args.steps, args.warmup, with_mass=not args.no_mass, tune=not args.no_tune,
                     patches=fsimg.FSIMG_PATCH_BLOCK if args.patches == "block" else fsimg.FSIMG_PATCH_ELEMENT,
                     schedule={"gather": fsimg.FSIMG_VANKA_GATHER, "parity": fsimg.FSIMG_VANKA_PARITY,
-                              "greedy": fsimg.FSIMG_VANKA_GREEDY}[args.schedule],
+                              "greedy": fsimg.FSIMG_VANKA_GREEDY, "auto": -1}[args.schedule],
                     smoother=fsimg.FSIMG_SMOOTHER_ILU if args.smoother == "ilu" else fsimg.FSIMG_SMOOTHER_VANKA,
                     lookahead=args.lookahead, small_kib=args.small_level_kib)
         A = to_csr(lev.systems["mom"])
@@ -1262,7 +1269,8 @@ def main():
                   "mass_iters": R["stats"][1]["iters"] if R["stats"][1] else None,
                   "rel_res_momentum_fp64_host": R["rel_res_host"],
                   "setup_s": R["t_setup"], "factor_s": R["t_factor"], "tune_s": R["t_tune"],
-                  "launch_shapes": R["shapes"]},
+                  "launch_shapes": R["shapes"],
+                  "schedule_ms_per_vcycle": R["schedule_ms"] or None},
     }
     if "fp64" in runs and main_tag != "fp64":
         F = runs["fp64"]

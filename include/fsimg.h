@@ -349,6 +349,22 @@ fsimg_status fsimg_tune_get(const fsimg_ctx *ctx, int kind, int key, int word, i
 fsimg_status fsimg_tune_save(const fsimg_ctx *ctx, const char *path);
 fsimg_status fsimg_tune_load(fsimg_ctx *ctx, const char *path);
 
+/* The Vanka schedule (fsimg_vanka_schedule: the patch-correction gather or
+   one of the two colourings of the paper's coloured scatter) changes the
+   summation order, so it is not a launch shape: it is fixed when a
+   hierarchy is created.  This call measures it for the caller: for each of
+   GATHER, PARITY and GREEDY it creates the hierarchy of `levels` with
+   `opts` and that schedule, factors it, and times `reps` V-cycles (after one
+   warm-up) with HIP events on `stream`; ms_out[0..2] receive the mean
+   milliseconds per V-cycle in that order (-1 where the schedule does not
+   apply, e.g. block patches, which need GATHER), *best the fastest
+   schedule.  One hierarchy exists at a time (the context's budget
+   applies); the call allocates two vectors of the finest level and frees
+   everything before it returns.  Synchronises the stream. */
+fsimg_status fsimg_tune_schedule(fsimg_ctx *ctx, const fsimg_level_desc *levels, int nlev,
+                                 const fsimg_opts *opts, int reps, double *ms_out, int *best,
+                                 void *stream);
+
 /* ---- serving: many simulations sharing one GPU ----
    A request is one FSI simulation: time_steps time steps, newton_steps[t]
    Newton steps in step t; every Newton step is the linear solve of the

@@ -36,6 +36,7 @@ struct BatchPlan {
   DLev *dlev = nullptr;  // [Lmax][n]
   DKry *dkry = nullptr;  // [n]
   int *active = nullptr, *kcnt = nullptr, *flags = nullptr, *cyc = nullptr;
+  int *cnt = nullptr;  // per instance: workgroups done in the current reduction pass
   double *hs = nullptr;  // [n * kHS]
   DGiv *gv = nullptr;    // [n] FGMRES control state
   std::vector<WorkSet> ws_spmv, ws_patch, ws_patch2, ws_gather, ws_restrict, ws_prolong, ws_cn, ws_cf;
@@ -48,6 +49,7 @@ struct BatchPlan {
   std::vector<int> tail_n;
   const int32_t *tfrom = nullptr;
   bool tails = false;
+  bool zfuse = false;  // every instance has >= 2 levels: z_j can come from the last gather
   WorkSet ws_row0{}, ws_vec0{}, ws_kry{}, ws_inst{};
   std::vector<DKry> hkry;
   // pinned host staging: the active flags after each iteration j of a cycle
@@ -97,13 +99,13 @@ void destroy_plan(BatchPlan *p) {
 }
 
 size_t plan_bytes_bound(int nlev) {
-  // per instance: level descriptors, Krylov descriptor, four flags, its
+  // per instance: level descriptors, Krylov descriptor, five flags, its
   // first small level and tail-list entry, the Hessenberg slot, the FGMRES
   // control state and one (instance, prefix) entry in each work set (level
   // sets twice: all levels, and the V-cycle's without the small levels); per
   // plan: one prefix entry and 64-byte alignment of every table
-  const size_t nset = 14 * (size_t)nlev + 4, ntab = 9 + 2 * nset + nlev;
-  return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 6 * sizeof(int) + kHS * sizeof(double) +
+  const size_t nset = 14 * (size_t)nlev + 4, ntab = 10 + 2 * nset + nlev;
+  return (size_t)nlev * sizeof(DLev) + sizeof(DKry) + 7 * sizeof(int) + kHS * sizeof(double) +
          sizeof(DGiv) + nset * (sizeof(int32_t) + 2 * sizeof(int64_t)) + ntab * 64;
 }
 
@@ -266,14 +268,17 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   const size_t k_off = blob.add(nullptr, n * sizeof(int));
   const size_t fl_off = blob.add(nullptr, n * sizeof(int));
   const size_t cyc_off = blob.add(nullptr, n * sizeof(int));
+  const size_t cnt_off = blob.add(nullptr, n * sizeof(int));
   const size_t hs_off = blob.add(nullptr, (size_t)n * kHS * sizeof(double));
   const size_t gv_off = blob.add(nullptr, (size_t)n * sizeof(DGiv));
   std::vector<WsRef> r_spmv, r_patch, r_patch2, r_gather, r_restrict, r_prolong, r_cn, r_cf;
   std::vector<WsRef> v_spmv, v_patch, v_patch2, v_gather, v_restrict, v_prolong;
   std::vector<int> from(n);
+  P->zfuse = true;
   for (int i = 0; i < n; ++i) {
     from[i] = tail_from(hs[i]);
     P->tails = P->tails || from[i] < (int)hs[i]->lev.size() - 1;
+    P->zfuse = P->zfuse && hs[i]->lev.size() >= 2;
   }
   const size_t tfrom_off = blob.add(from.data(), n * sizeof(int32_t));
   std::vector<size_t> tail_off(Lmax, 0);
@@ -385,6 +390,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   P->kcnt = reinterpret_cast<int *>(base + k_off);
   P->flags = reinterpret_cast<int *>(base + fl_off);
   P->cyc = reinterpret_cast<int *>(base + cyc_off);
+  P->cnt = reinterpret_cast<int *>(base + cnt_off);
   P->hs = reinterpret_cast<double *>(base + hs_off);
   P->gv = reinterpret_cast<DGiv *>(base + gv_off);
   for (int l = 0; l < Lmax; ++l) {
@@ -444,8 +450,11 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
   return FSIMG_OK;
 }
 
+// zj >= 0: an FGMRES iteration's V-cycle; when every instance smooths the
+// finest level, its last gather also writes z_zj (returns true; else the
+// caller copies x to z_zj)
 template <typename T>
-void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
+bool vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof, int zj = -1) {
   const int n = P.n;
   const T omega = (T)o.omega;
   const int *act = P.active;
@@ -456,6 +465,7 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
                              &Wga = tail ? P.vs_gather : P.ws_gather,
                              &Wre = tail ? P.vs_restrict : P.ws_restrict,
                              &Wpr = tail ? P.vs_prolong : P.ws_prolong;
+  const bool zf = zj >= 0 && !tail && P.zfuse && o.nu_post > 0;
   for (int l = 0; l < P.Lmax; ++l) {
     const DLev *L = P.dlev + (size_t)l * n;
     if (Wpa[l].nset > 0 || Wpa2[l].nset > 0 || Wsp[l].nset > 0) {
@@ -513,10 +523,12 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
       hipEvent_t v0 = p0 ? P.tv.next() : nullptr;
       hipEvent_t v1 = p0 ? P.tv.next() : nullptr;
       launch_b_vanka_blocks<T>(P.np2, P.b, P.nl2, P.npc2, P.ppw2[l], false, L, act, Wpa2[l], s);
+      const bool zl = zf && l == 0 && k == o.nu_post - 1;
       launch_b_vanka<T>(P.np, P.b, P.nl, P.npc, P.ppw[l], omega, false, false, L, act, Wpa[l], Wga[l],
-                        s, v0, v1);
+                        s, v0, v1, zl ? P.dkry : nullptr, zl ? zj : -1);
     }
   }
+  return zf;
 }
 
 // the launches of FGMRES iteration j for every active instance: z_j = M^-1 v_j
@@ -525,26 +537,23 @@ void vcycle_batch(BatchPlan &P, const fsimg_opts &o, hipStream_t s, bool prof) {
 // the device-side Givens update and stop test, and the copy of the active
 // flags to the host ring (slot j)
 void issue_iteration(BatchPlan &P, const fsimg_opts &o, int j, hipStream_t s, bool prof) {
+  // v_j is already in the finest level's r (written with v_j itself)
   if (P.mixed) {
-    launch_b_copy_in<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
-    vcycle_batch<float>(P, o, s, prof);
-    launch_b_copy_out<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+    if (!vcycle_batch<float>(P, o, s, prof, j))
+      launch_b_copy_out<float>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
   } else {
-    launch_b_copy_in<double>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
-    vcycle_batch<double>(P, o, s, prof);
-    launch_b_copy_out<double>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
+    if (!vcycle_batch<double>(P, o, s, prof, j))
+      launch_b_copy_out<double>(P.dlev, P.dkry, P.active, P.ws_vec0, j, s);
   }
   launch_b_spmv<double>(P.b, BS_AZ, P.rpw0, P.dlev, P.dkry, P.active, P.ws_row0, j, s);
-  // classical Gram-Schmidt, two passes
-  launch_b_multidot(P.dkry, P.active, P.ws_kry, j + 1, false, s);
-  launch_b_reduce(P.dkry, P.active, P.ws_inst, j + 1, P.hs, kOffH1, s);
-  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, false, P.hs, kOffH1, s);
-  launch_b_reduce(P.dkry, P.active, P.ws_inst, j + 1, P.hs, kOffH2, s);
-  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, true, P.hs, kOffH2, s);
-  launch_b_reduce(P.dkry, P.active, P.ws_inst, 1, P.hs, kOffSS, s);
-  launch_b_add_h(P.active, P.ws_inst, j + 1, P.hs, s);
-  launch_b_scale(P.dkry, P.active, P.ws_vec0, P.hs, j + 1, s);
-  launch_kry_givens(P.gv, P.hs, P.active, P.n, j, s);
+  // classical Gram-Schmidt, two passes; the w.w pass ends with the Givens step
+  launch_b_multidot(P.dkry, P.active, P.ws_kry, j + 1, false, P.hs, kOffH1, P.cnt, s);
+  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, false, P.hs, kOffH1, kOffH2, P.cnt, nullptr, j, s);
+  launch_b_axpy_red(P.dkry, P.active, P.ws_kry, j + 1, true, P.hs, kOffH2, kOffSS, P.cnt, P.gv, j, s);
+  if (P.mixed)
+    launch_b_scale<float>(P.dkry, P.active, P.ws_vec0, P.hs, j + 1, P.dlev, s);
+  else
+    launch_b_scale<double>(P.dkry, P.active, P.ws_vec0, P.hs, j + 1, P.dlev, s);
   (void)hipMemcpyAsync(P.ring_host + (size_t)j * P.n, P.active, P.n * sizeof(int), hipMemcpyDeviceToHost,
                        s);
 }
@@ -745,11 +754,10 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
   };
   FSIMG_BHIP(hipMemcpyAsync(P->dkry, P->hkry.data(), n * sizeof(DKry), hipMemcpyHostToDevice, s));
   std::vector<double> bytes(n, 0.0);
-  launch_kry_reset(P->active, P->flags, n, s);
+  launch_kry_reset(P->active, P->flags, P->cnt, n, s);
   launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
   launch_b_nonfinite(P->dkry, P->active, P->ws_vec0, P->flags, s);
-  launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
-  launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
+  launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, P->hs, kOffSS, P->cnt, s);
   launch_kry_start(P->gv, P->hs, P->flags, P->active, P->cyc, n, o.rtol, o.max_iter, s);
   for (int i = 0; i < n; ++i) k_h[i] = 0;
   FSIMG_BHIP(hipMemcpyAsync(cyc_h, P->cyc, n * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -760,7 +768,10 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
     bool any = false;
     for (int i = 0; i < n; ++i) any |= cyc_h[i] != 0;
     if (!any) break;
-    launch_b_scale(P->dkry, P->active, P->ws_vec0, P->hs, 0, s);  // v_0 = r / ||r||
+    if (P->mixed)  // v_0 = r / ||r||
+      launch_b_scale<float>(P->dkry, P->active, P->ws_vec0, P->hs, 0, P->dlev, s);
+    else
+      launch_b_scale<double>(P->dkry, P->active, P->ws_vec0, P->hs, 0, P->dlev, s);
     // speculate: launch the next iteration before the previous one's flags
     // are read, unless every active instance expects to stop (active = 2)
     // at the iteration in flight, which would leave the speculative one empty
@@ -792,8 +803,7 @@ fsimg_status run_batch(BatchPlan *P, int n, fsimg_hier *const *hs, const double 
     launch_kry_ysolve(P->gv, P->hs, P->active, P->kcnt, n, s);
     launch_b_combine(P->dkry, P->active, P->ws_vec0, P->hs, P->kcnt, launched, s);
     launch_b_spmv<double>(P->b, BS_RESID, P->rpw0, P->dlev, P->dkry, P->active, P->ws_row0, 0, s);
-    launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, s);
-    launch_b_reduce(P->dkry, P->active, P->ws_inst, 1, P->hs, kOffSS, s);
+    launch_b_multidot(P->dkry, P->active, P->ws_kry, 1, true, P->hs, kOffSS, P->cnt, s);
     launch_kry_restart(P->gv, P->hs, P->active, P->cyc, n, s);
     FSIMG_BHIP(read_cycle());
     for (int i = 0; i < n; ++i) {
@@ -908,7 +918,7 @@ fsimg_status single_step_t(fsimg_hier *h, int op, int l, const void *a, const vo
       break;
     case ONE_VCYCLE:  // out = V-cycle(a) on level 0
       cp(HV<T>::r(F), a, F.n);
-      vcycle_batch<T>(*P, o, s, false);
+      (void)vcycle_batch<T>(*P, o, s, false);
       cp(out, HV<T>::x(F), F.n);
       break;
     default:

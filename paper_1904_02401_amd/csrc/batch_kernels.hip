@@ -98,10 +98,13 @@ __global__ __launch_bounds__(1024) void kb_vanka_patch(const DLev *__restrict__ 
                          nullptr, nullptr, L.mask, T(0), reinterpret_cast<T *>(smem_raw));
 }
 
+// zj >= 0 (the last post-smoothing step on the finest level): also z_j =
+// the updated x in FP64, the FGMRES direction of iteration zj
 template <typename T>
 __global__ __launch_bounds__(256) void kb_vanka_gather(const DLev *__restrict__ lev,
                                                        const int *__restrict__ active, WorkSet ws,
-                                                       int b, T omega, int assign) {
+                                                       int b, T omega, int assign,
+                                                       const DKry *__restrict__ kry, int zj) {
   const int64_t lb = dev::xcd_block(blockIdx.x, gridDim.x);
   const int s = seg_of(ws, lb);
   const int i = ws.inst[s];
@@ -111,6 +114,10 @@ __global__ __launch_bounds__(256) void kb_vanka_gather(const DLev *__restrict__ 
   if (dof >= L.n) return;
   dev::vanka_gather_dof<T>(dof, b, L.gptr, L.gidx, LV<T>::Y(L), LV<T>::sc(L), L.mask, omega, assign,
                            LV<T>::x(L));
+  if (zj >= 0) {
+    const DKry &K = kry[i];
+    K.Z[(int64_t)zj * K.n + dof] = (double)LV<T>::x(L)[dof];
+  }
 }
 
 template <typename T>
@@ -494,13 +501,79 @@ __global__ __launch_bounds__(256) void kb_copy_out(const DLev *__restrict__ lev0
   if (k < K.n) K.Z[(int64_t)j * K.n + k] = (double)LV<T>::x(lev0[i])[k];
 }
 
-// per-block partials of V[0..nvec)^T w (or of w.w): each instance owns nblk
-// blocks and strides over its own vector only
+// The last of an instance's nblk workgroups to finish a reduction pass:
+// each workgroup's thread 0 publishes its partials with a device-scope
+// release fence before counting itself in cnt; the workgroup that counts
+// last (and resets cnt for the next pass) takes an acquire fence and sums
+// every partial.  No workgroup waits for another.
+__device__ __forceinline__ bool last_of(int *cnt, int nblk, int *flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(cnt, 1);
+    *flag = prev == nblk - 1;
+    if (*flag) atomicExch(cnt, 0);
+  }
+  __syncthreads();
+  const bool last = *flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// hsi[k] = sum over the instance's workgroups b of partial[b nvec + k], in
+// workgroup order with the block-sum tree (run by the last workgroup)
+__device__ __forceinline__ void sum_partials(const DKry &K, int nvec, double *hsi, double *red) {
+  for (int k = 0; k < nvec; ++k) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < K.nblk; b += blockDim.x) t += K.partial[(int64_t)b * nvec + k];
+    t = dev::block_sum(t, red);
+    if (threadIdx.x == 0) hsi[k] = t;
+  }
+}
+
+// FGMRES column j after both Gram-Schmidt passes: h = h1 + h2 and
+// h_{j+1,j} = sqrt(ss), rotated by the previous rotations; a new rotation,
+// g, the residual history and the stop test (see DGiv)
+__device__ __forceinline__ void kry_givens_step(DGiv &G, const double *hc, int j, int *act) {
+  double *col = G.R + j * kMaxVec;
+  for (int r = 0; r <= j; ++r) col[r] = hc[kOffH1 + r] + hc[kOffH2 + r];
+  const double hn = sqrt(hc[kOffSS]);
+  for (int r = 0; r < j; ++r) {
+    const double a0 = col[r], a1 = col[r + 1];
+    col[r] = G.cs[r] * a0 + G.sn[r] * a1;
+    col[r + 1] = -G.sn[r] * a0 + G.cs[r] * a1;
+  }
+  const double hjj = col[j];
+  const double den = hypot(hjj, hn);
+  G.cs[j] = hjj / den;
+  G.sn[j] = hn / den;
+  col[j] = den;
+  const double gj = G.g[j];
+  G.g[j + 1] = -G.sn[j] * gj;
+  G.g[j] = G.cs[j] * gj;
+  ++G.it;
+  G.k = j + 1;
+  const double res = fabs(G.g[j + 1]);
+  if (G.nhist < FSIMG_HIST) G.hist[G.nhist++] = res / G.beta0;
+  if (!isfinite(G.g[j + 1]) || res <= G.tol || G.it >= G.maxit || hn == 0.0) {
+    *act = 0;
+  } else {
+    const double rho = G.rprev > 0.0 ? res / G.rprev : 1.0;
+    *act = (res * rho <= G.tol || G.it + 1 >= G.maxit) ? 2 : 1;
+  }
+  G.rprev = res;
+}
+
+// V[0..nvec)^T w (or w.w) into hs[off ..]: per-workgroup partials, summed by
+// the instance's last workgroup; each instance owns nblk workgroups and
+// strides over its own vector only
 template <int NV, int NORM>
 __global__ __launch_bounds__(256) void kb_multidot(const DKry *__restrict__ kry,
                                                    const int *__restrict__ active, WorkSet ws,
-                                                   int nvec) {
+                                                   int nvec, double *__restrict__ hs, int off,
+                                                   int *__restrict__ cnt) {
   __shared__ double red[4];
+  __shared__ int flag;
   const int s = seg_of(ws, blockIdx.x);
   const int i = ws.inst[s];
   if (!active[i]) return;
@@ -523,15 +596,22 @@ __global__ __launch_bounds__(256) void kb_multidot(const DKry *__restrict__ kry,
       const double tt = dev::block_sum(acc[k], red);
       if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
     }
+  if (last_of(cnt + i, K.nblk, &flag)) sum_partials(K, nvec, hs + (int64_t)i * kHS + off, red);
 }
 
-// w -= V h, then partials of V^T w (NORM 0) or of w.w (NORM 1)
+// w -= V h (h = hs[hoff ..]), then V^T w (NORM 0) or w.w (NORM 1) into
+// hs[off ..] as kb_multidot; with NORM 1 and gv != nullptr the last
+// workgroup also takes the Givens step of column j, which may clear the
+// instance's active flag
 template <int NV, int NORM>
 __global__ __launch_bounds__(256) void kb_axpy_red(const DKry *__restrict__ kry,
-                                                   const int *__restrict__ active, WorkSet ws,
-                                                   int nvec, const double *__restrict__ hs, int hoff) {
+                                                   int *__restrict__ active, WorkSet ws, int nvec,
+                                                   double *__restrict__ hs, int hoff, int off,
+                                                   int *__restrict__ cnt, DGiv *__restrict__ gv,
+                                                   int j) {
   __shared__ double red[4];
   __shared__ double hv[NV];
+  __shared__ int flag;
   const int s = seg_of(ws, blockIdx.x);
   const int i = ws.inst[s];
   if (!active[i]) return;
@@ -572,41 +652,30 @@ __global__ __launch_bounds__(256) void kb_axpy_red(const DKry *__restrict__ kry,
         if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
       }
   }
+  if (last_of(cnt + i, K.nblk, &flag)) {
+    double *hsi = hs + (int64_t)i * kHS;
+    sum_partials(K, NORM ? 1 : nvec, hsi + off, red);
+    if (NORM && gv && threadIdx.x == 0) kry_givens_step(gv[i], hsi, j, active + i);
+  }
 }
 
-// one workgroup per (instance, component): fixed-order sum of the partials
-__global__ __launch_bounds__(256) void kb_reduce(const DKry *__restrict__ kry,
-                                                 const int *__restrict__ active, WorkSet ws,
-                                                 int nvec, double *__restrict__ hs, int off) {
-  __shared__ double red[4];
-  const int s = blockIdx.x / nvec, k = blockIdx.x - s * nvec;
-  const int i = ws.inst[s];
-  if (!active[i]) return;
-  const DKry &K = kry[i];
-  double t = 0.0;
-  for (int b = threadIdx.x; b < K.nblk; b += blockDim.x) t += K.partial[(int64_t)b * nvec + k];
-  t = dev::block_sum(t, red);
-  if (threadIdx.x == 0) hs[(int64_t)i * kHS + off + k] = t;
-}
-
-__global__ void kb_add_h(const int *__restrict__ active, WorkSet ws, int nvec,
-                         double *__restrict__ hs) {
-  const int i = ws.inst[blockIdx.x];
-  if (!active[i] || threadIdx.x >= nvec) return;
-  double *h = hs + (int64_t)i * kHS;
-  h[kOffH + threadIdx.x] = h[kOffH1 + threadIdx.x] + h[kOffH2 + threadIdx.x];
-}
-
-// V[target] = w / sqrt(ss)
+// V[target] = w / sqrt(ss), and the same vector in the V-cycle's precision
+// as the finest level's right-hand side (the next iteration's input)
+template <typename T>
 __global__ __launch_bounds__(256) void kb_scale(const DKry *__restrict__ kry,
                                                 const int *__restrict__ active, WorkSet ws,
-                                                const double *__restrict__ hs, int target) {
+                                                const double *__restrict__ hs, int target,
+                                                const DLev *__restrict__ lev0) {
   const int s = seg_of(ws, blockIdx.x);
   const int i = ws.inst[s];
   if (!active[i]) return;
   const DKry &K = kry[i];
   const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
-  if (k < K.n) K.V[(int64_t)target * K.n + k] = K.w[k] / sqrt(hs[(int64_t)i * kHS + kOffSS]);
+  if (k < K.n) {
+    const double v = K.w[k] / sqrt(hs[(int64_t)i * kHS + kOffSS]);
+    K.V[(int64_t)target * K.n + k] = v;
+    LV<T>::r(lev0[i])[k] = (T)v;
+  }
 }
 
 // x += Z y with this instance's k directions
@@ -655,11 +724,12 @@ __global__ __launch_bounds__(256) void kb_activate(int *__restrict__ active, int
 // rotation zeroes its subdiagonal, and |g_{j+1}| is the residual norm of the
 // least-squares solution.
 __global__ __launch_bounds__(64) void kb_kry_reset(int *__restrict__ active, int *__restrict__ flags,
-                                                   int n) {
+                                                   int *__restrict__ cnt, int n) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
   active[i] = 1;
   flags[i] = 0;
+  cnt[i] = 0;
 }
 
 __device__ __forceinline__ void kry_open_cycle(DGiv &G, double rn) {
@@ -696,41 +766,6 @@ __global__ __launch_bounds__(64) void kb_kry_start(DGiv *__restrict__ gv, const 
   G.incyc = go;
   active[i] = go;
   cyc[i] = go;
-}
-
-__global__ __launch_bounds__(64) void kb_kry_givens(DGiv *__restrict__ gv, const double *__restrict__ hs,
-                                                    int *__restrict__ active, int n, int j) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= n || !active[i]) return;
-  DGiv &G = gv[i];
-  const double *hc = hs + (int64_t)i * kHS;
-  double *col = G.R + j * kMaxVec;
-  for (int r = 0; r <= j; ++r) col[r] = hc[kOffH + r];
-  const double hn = sqrt(hc[kOffSS]);
-  for (int r = 0; r < j; ++r) {
-    const double a0 = col[r], a1 = col[r + 1];
-    col[r] = G.cs[r] * a0 + G.sn[r] * a1;
-    col[r + 1] = -G.sn[r] * a0 + G.cs[r] * a1;
-  }
-  const double hjj = col[j];
-  const double den = hypot(hjj, hn);
-  G.cs[j] = hjj / den;
-  G.sn[j] = hn / den;
-  col[j] = den;
-  const double gj = G.g[j];
-  G.g[j + 1] = -G.sn[j] * gj;
-  G.g[j] = G.cs[j] * gj;
-  ++G.it;
-  G.k = j + 1;
-  const double res = fabs(G.g[j + 1]);
-  if (G.nhist < FSIMG_HIST) G.hist[G.nhist++] = res / G.beta0;
-  if (!isfinite(G.g[j + 1]) || res <= G.tol || G.it >= G.maxit || hn == 0.0) {
-    active[i] = 0;
-  } else {
-    const double rho = G.rprev > 0.0 ? res / G.rprev : 1.0;
-    active[i] = (res * rho <= G.tol || G.it + 1 >= G.maxit) ? 2 : 1;
-  }
-  G.rprev = res;
 }
 
 __global__ __launch_bounds__(64) void kb_kry_ysolve(DGiv *__restrict__ gv, double *__restrict__ hs,
@@ -826,7 +861,7 @@ void launch_b_spmv(int b, int src, int rpw, const DLev *lev, const DKry *kry, co
 template <typename T>
 void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first, bool assign,
                     const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
-                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1, const DKry *kry, int zj) {
   if (e0) (void)hipEventRecord(e0, s);
   if (wp.nblocks > 0)
     hipLaunchKernelGGL((kb_vanka_patch<T>), grid_of(wp), dim3(vanka_threads(np, ppw)),
@@ -835,7 +870,7 @@ void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first
   if (e1) (void)hipEventRecord(e1, s);
   if (wg.nblocks > 0)
     hipLaunchKernelGGL((kb_vanka_gather<T>), grid_of(wg), dim3(256), 0, s, lev, active, wg, b, omega,
-                       assign ? 1 : 0);
+                       assign ? 1 : 0, kry, zj);
 }
 
 template <typename T>
@@ -942,47 +977,36 @@ void launch_b_copy_out(const DLev *lev0, const DKry *kry, const int *active, con
   } while (0)
 
 void launch_b_multidot(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm_w,
-                       hipStream_t s) {
+                       double *hs, int off, int *cnt, hipStream_t s) {
   if (wk.nblocks == 0) return;
   if (norm_w) {
-    hipLaunchKernelGGL((kb_multidot<8, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, 1);
+    hipLaunchKernelGGL((kb_multidot<8, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, 1, hs, off, cnt);
     return;
   }
-#define K(NV) hipLaunchKernelGGL((kb_multidot<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec)
+#define K(NV) hipLaunchKernelGGL((kb_multidot<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, off, cnt)
   FSIMG_NVB(nvec, K);
 #undef K
 }
 
-void launch_b_axpy_red(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm,
-                       const double *hs, int hoff, hipStream_t s) {
+void launch_b_axpy_red(const DKry *kry, int *active, const WorkSet &wk, int nvec, bool norm, double *hs,
+                       int hoff, int off, int *cnt, DGiv *gv, int j, hipStream_t s) {
   if (wk.nblocks == 0) return;
   if (norm) {
-#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff)
+#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 1>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff, off, cnt, gv, j)
     FSIMG_NVB(nvec, K);
 #undef K
   } else {
-#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff)
+#define K(NV) hipLaunchKernelGGL((kb_axpy_red<NV, 0>), grid_of(wk), dim3(256), 0, s, kry, active, wk, nvec, hs, hoff, off, cnt, gv, j)
     FSIMG_NVB(nvec, K);
 #undef K
   }
 }
 
-void launch_b_reduce(const DKry *kry, const int *active, const WorkSet &wk, int nvec, double *hs,
-                     int off, hipStream_t s) {
-  if (wk.nset == 0) return;
-  hipLaunchKernelGGL(kb_reduce, dim3((unsigned)(wk.nset * nvec)), dim3(256), 0, s, kry, active, wk,
-                     nvec, hs, off);
-}
-
-void launch_b_add_h(const int *active, const WorkSet &wk, int nvec, double *hs, hipStream_t s) {
-  if (wk.nset == 0) return;
-  hipLaunchKernelGGL(kb_add_h, dim3((unsigned)wk.nset), dim3(64), 0, s, active, wk, nvec, hs);
-}
-
+template <typename T>
 void launch_b_scale(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
-                    int target, hipStream_t s) {
+                    int target, const DLev *lev0, hipStream_t s) {
   if (wv.nblocks > 0)
-    hipLaunchKernelGGL(kb_scale, grid_of(wv), dim3(256), 0, s, kry, active, wv, hs, target);
+    hipLaunchKernelGGL((kb_scale<T>), grid_of(wv), dim3(256), 0, s, kry, active, wv, hs, target, lev0);
 }
 
 void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
@@ -1007,17 +1031,14 @@ namespace {
 dim3 kry_grid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 }  // namespace
 
-void launch_kry_reset(int *active, int *flags, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(kb_kry_reset, kry_grid(n), dim3(64), 0, s, active, flags, n);
+void launch_kry_reset(int *active, int *flags, int *cnt, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(kb_kry_reset, kry_grid(n), dim3(64), 0, s, active, flags, cnt, n);
 }
 void launch_kry_start(DGiv *gv, const double *hs, const int *flags, int *active, int *cyc, int n,
                       double rtol, int max_iter, hipStream_t s) {
   if (n > 0)
     hipLaunchKernelGGL(kb_kry_start, kry_grid(n), dim3(64), 0, s, gv, hs, flags, active, cyc, n, rtol,
                        max_iter);
-}
-void launch_kry_givens(DGiv *gv, const double *hs, int *active, int n, int j, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(kb_kry_givens, kry_grid(n), dim3(64), 0, s, gv, hs, active, n, j);
 }
 void launch_kry_ysolve(DGiv *gv, double *hs, int *active, int *kcnt, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(kb_kry_ysolve, kry_grid(n), dim3(64), 0, s, gv, hs, active, kcnt, n);
@@ -1032,7 +1053,7 @@ void launch_kry_restart(DGiv *gv, const double *hs, int *active, int *cyc, int n
   template void launch_b_vanka<T>(int, int, int, int, int, T, bool, bool, const DLev *,          \
                                   const int *,                                                   \
                                   const WorkSet &, const WorkSet &, hipStream_t, hipEvent_t,     \
-                                  hipEvent_t);                                                   \
+                                  hipEvent_t, const DKry *, int);                                \
   template void launch_b_vanka_blocks<T>(int, int, int, int, int, bool, const DLev *, const int *, \
                                          const WorkSet &, hipStream_t);                          \
   template void launch_b_fill_x<T>(const DLev *, const int *, const WorkSet &, hipStream_t);     \
@@ -1045,6 +1066,8 @@ void launch_kry_restart(DGiv *gv, const double *hs, int *active, int *cyc, int n
                                     const WorkSet &, hipStream_t);                               \
   template void launch_b_coarse<T>(const DLev *, const int *, const WorkSet &, const WorkSet &,  \
                                    hipStream_t);                                                 \
+  template void launch_b_scale<T>(const DKry *, const int *, const WorkSet &, const double *, int,   \
+                                  const DLev *, hipStream_t);                                      \
   template void launch_b_copy_in<T>(const DLev *, const DKry *, const int *, const WorkSet &, int, \
                                     hipStream_t);                                                \
   template void launch_b_copy_out<T>(const DLev *, const DKry *, const int *, const WorkSet &,   \

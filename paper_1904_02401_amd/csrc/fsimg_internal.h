@@ -178,11 +178,13 @@ enum BatchSpmvSrc { BS_VCYCLE = 0, BS_AZ = 1, BS_RESID = 2 };
 template <typename T>
 void launch_b_spmv(int b, int src, int rpw, const DLev *lev, const DKry *kry, const int *active,
                    const WorkSet &ws, int j, hipStream_t s);
-// ppw: patches per workgroup (the work set counts workgroups of ppw patches)
+// ppw: patches per workgroup (the work set counts workgroups of ppw patches);
+// zj >= 0: the gather also writes z_zj = x in FP64 (kry[i].Z, finest level)
 template <typename T>
 void launch_b_vanka(int np, int b, int nl, int npc, int ppw, T omega, bool first, bool assign,
                     const DLev *lev, const int *active, const WorkSet &wp, const WorkSet &wg,
-                    hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1, const DKry *kry = nullptr,
+                    int zj = -1);
 // the block-patch group's local corrections (before launch_b_vanka's gather)
 template <typename T>
 void launch_b_vanka_blocks(int np, int b, int nl, int npc, int ppw, bool first, const DLev *lev,
@@ -217,34 +219,38 @@ void launch_b_copy_in(const DLev *lev0, const DKry *kry, const int *active, cons
 template <typename T>
 void launch_b_copy_out(const DLev *lev0, const DKry *kry, const int *active, const WorkSet &ws,
                        int j, hipStream_t s);
+// Krylov reductions: each instance's nblk workgroups write partials and the
+// last one to finish (counted in cnt[i], zero between passes) sums them in
+// a fixed order into hs[i kHS + off ..]
+// V[0..nvec)^T w, or w.w (norm_w)
 void launch_b_multidot(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm_w,
-                       hipStream_t s);
-void launch_b_axpy_red(const DKry *kry, const int *active, const WorkSet &wk, int nvec, bool norm,
-                       const double *hs, int hoff, hipStream_t s);
-void launch_b_reduce(const DKry *kry, const int *active, const WorkSet &wk, int nvec, double *hs,
-                     int off, hipStream_t s);
-void launch_b_add_h(const int *active, const WorkSet &wk, int nvec, double *hs, hipStream_t s);
+                       double *hs, int off, int *cnt, hipStream_t s);
+// w -= V h with h = hs[hoff ..], then V^T w or w.w (norm); with norm and
+// gv != nullptr the Givens step of FGMRES column j (h = h1 + h2, stop test)
+void launch_b_axpy_red(const DKry *kry, int *active, const WorkSet &wk, int nvec, bool norm, double *hs,
+                       int hoff, int off, int *cnt, DGiv *gv, int j, hipStream_t s);
+// V[target] = w / sqrt(hs[kOffSS]), also into the finest level's r in T
+template <typename T>
 void launch_b_scale(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
-                    int target, hipStream_t s);
+                    int target, const DLev *lev0, hipStream_t s);
 void launch_b_combine(const DKry *kry, const int *active, const WorkSet &wv, const double *hs,
                       const int *kcnt, int kmax, hipStream_t s);
 void launch_b_nonfinite(const DKry *kry, const int *active, const WorkSet &wv, int *flags,
                         hipStream_t s);
 void launch_b_activate(int *active, int n, hipStream_t s);  // active[0..n) = 1
 // device-side FGMRES control, one thread per instance (see DGiv):
-// reset: active = 1, flags = 0 before the first residual
-void launch_kry_reset(int *active, int *flags, int n, hipStream_t s);
+// reset: active = 1, flags = 0 and the reduction counters 0 before the first residual
+void launch_kry_reset(int *active, int *flags, int *cnt, int n, hipStream_t s);
 // start: beta0 = ||r_0|| from hs[kOffSS]; an instance with a non-finite or
 // zero residual is done; the others open their first cycle (active = cyc = 1)
 void launch_kry_start(DGiv *gv, const double *hs, const int *flags, int *active, int *cyc, int n,
                       double rtol, int max_iter, hipStream_t s);
-// after iteration j: rotate the Hessenberg column hs[kOffH..], new rotation,
-// g update, residual history; active = 0 once |g_{j+1}| <= tol, max_iter is
+// (the Givens step of iteration j runs in the last workgroup of its w.w
+// pass, launch_b_axpy_red: active = 0 once |g_{j+1}| <= tol, max_iter is
 // reached, the column breaks down (h_{j+1,j} = 0) or g is not finite; else
 // active = 2 when the next iteration is expected to stop it (the last
 // residual reduction factor repeated reaches tol, or max_iter is next),
-// 1 otherwise (kernels treat any non-zero value as active)
-void launch_kry_givens(DGiv *gv, const double *hs, int *active, int n, int j, hipStream_t s);
+// 1 otherwise; kernels treat any non-zero value as active)
 // end of a cycle: y = R^-1 g into hs[kOffY..], kcnt = k; active = in cycle
 void launch_kry_ysolve(DGiv *gv, double *hs, int *active, int *kcnt, int n, hipStream_t s);
 // after the true residual: stop test, next cycle's g; active = cyc = continues

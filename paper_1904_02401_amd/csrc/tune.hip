@@ -290,3 +290,77 @@ fsimg_status fsimg_tune_load(fsimg_ctx *ctx, const char *path) {
 }
 
 }  // extern "C"
+
+// ---- Vanka schedule: measured, not result-invariant, so it is reported and
+// left to the caller (the hierarchy's schedule is fixed when it is created)
+extern "C" fsimg_status fsimg_tune_schedule(fsimg_ctx *ctx, const fsimg_level_desc *levels, int nlev,
+                                            const fsimg_opts *opts, int reps, double *ms_out,
+                                            int *best, void *stream) {
+  if (!ctx || !levels || nlev < 1 || !opts || !ms_out || !best || reps < 1)
+    return set_error(FSIMG_ERR_ARG, "bad schedule tuning arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int sched[3] = {FSIMG_VANKA_GATHER, FSIMG_VANKA_PARITY, FSIMG_VANKA_GREEDY};
+  const bool f32 = opts->precision == FSIMG_MIXED;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return set_error(FSIMG_ERR_HIP, "event creation failed");
+  }
+  void *r = nullptr, *z = nullptr;
+  fsimg_status ret = FSIMG_OK;
+  *best = -1;
+  for (int k = 0; k < 3 && ret == FSIMG_OK; ++k) {
+    ms_out[k] = -1.0;
+    fsimg_opts o = *opts;
+    o.vanka_schedule = sched[k];
+    o.profile = 0;
+    fsimg_hier *h = nullptr;
+    const fsimg_status st = fsimg_hier_create(ctx, levels, nlev, &o, stream, &h);
+    if (st == FSIMG_ERR_ARG) continue;  // the schedule does not apply (e.g. block patches)
+    if (st != FSIMG_OK) {
+      ret = st;
+      break;
+    }
+    ret = fsimg_factor(h, stream);
+    const size_t bytes = (size_t)h->lev[0].n * (f32 ? sizeof(float) : sizeof(double));
+    if (ret == FSIMG_OK && !r) {
+      if (hipMalloc(&r, bytes) != hipSuccess || hipMalloc(&z, bytes) != hipSuccess)
+        ret = set_error(FSIMG_ERR_OOM, "schedule tuning vectors");
+    }
+    if (ret == FSIMG_OK) {
+      // a fixed non-zero right-hand side: the constant 1 in every dof
+      if (f32) {
+        std::vector<float> one(h->lev[0].n, 1.0f);
+        if (hipMemcpyAsync(r, one.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          ret = set_error(FSIMG_ERR_HIP, "schedule tuning upload");
+      } else {
+        std::vector<double> one(h->lev[0].n, 1.0);
+        if (hipMemcpyAsync(r, one.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          ret = set_error(FSIMG_ERR_HIP, "schedule tuning upload");
+      }
+    }
+    if (ret == FSIMG_OK) ret = fsimg_vcycle(h, o.precision, r, z, stream);  // warm-up
+    if (ret == FSIMG_OK) {
+      (void)hipEventRecord(e0, s);
+      for (int q = 0; q < reps && ret == FSIMG_OK; ++q) ret = fsimg_vcycle(h, o.precision, r, z, stream);
+      (void)hipEventRecord(e1, s);
+      float t = 0.0f;
+      if (ret == FSIMG_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        ret = set_error(FSIMG_ERR_HIP, "schedule tuning timing");
+      if (ret == FSIMG_OK) {
+        ms_out[k] = (double)t / reps;
+        if (*best < 0 || ms_out[k] < ms_out[*best]) *best = k;
+      }
+    }
+    fsimg_hier_destroy(h);
+  }
+  if (r) (void)hipFree(r);
+  if (z) (void)hipFree(z);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ret == FSIMG_OK && *best >= 0) *best = sched[*best];
+  return ret;
+}

@@ -192,6 +192,8 @@ _SIGS = {
     "fsimg_server_request_status": (_I, [_P, _I64, ctypes.POINTER(_I)]),
     "fsimg_server_release": (_I, [_P, _I64]),
     "fsimg_hier_tune": (_I, [_P, _I, _P]),
+    "fsimg_tune_schedule": (_I, [_P, ctypes.POINTER(fsimg_level_desc), _I, ctypes.POINTER(fsimg_opts), _I,
+                                 ctypes.POINTER(_D), ctypes.POINTER(_I), _P]),
     "fsimg_tune_set": (_I, [_P, _I, _I, _I, _I64, _I]),
     "fsimg_tune_get": (_I, [_P, _I, _I, _I, _I64, ctypes.POINTER(_I)]),
     "fsimg_tune_save": (_I, [_P, ctypes.c_char_p]),
@@ -549,6 +551,17 @@ def fsimg_server_release(srv, rid: int):
 
 def fsimg_hier_tune(h, force: bool = False, stream=None):
     _check(load().fsimg_hier_tune(h, 1 if force else 0, _stream(stream)))
+
+
+def fsimg_tune_schedule(ctx, levels, opts, reps: int = 5, stream=None):
+    """(ms per V-cycle for GATHER, PARITY, GREEDY (-1: not applicable), the
+    fastest schedule)"""
+    d = LevelDescs(levels)
+    ms = (ctypes.c_double * 3)()
+    best = ctypes.c_int()
+    _check(load().fsimg_tune_schedule(ctx, d.arr, d.n, ctypes.byref(opts), reps, ms, ctypes.byref(best),
+                                      _stream(stream)))
+    return list(ms), best.value
 
 
 def fsimg_tune_set(ctx, kind: int, key: int, word: int, size: int, value: int):

@@ -108,3 +108,23 @@ def test_tuner_and_cache(insts, tmp_path):
             fsimg.fsimg_ctx_destroy(ctx2)
     finally:
         fsimg.fsimg_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_schedule_timing(insts, precision):
+    """fsimg_tune_schedule times a V-cycle under each Vanka schedule and names
+    the fastest; block patches admit only the gather; the context holds no
+    memory afterwards."""
+    ctx = fsimg.fsimg_ctx_create(0)
+    try:
+        levels = level_dicts(insts[1], "mom")
+        ms, best = fsimg.fsimg_tune_schedule(ctx, levels, fsimg.fsimg_default_opts(precision=precision), reps=3)
+        assert all(t > 0 for t in ms), ms
+        assert best == int(np.argmin(ms))
+        assert fsimg.fsimg_ctx_bytes_in_use(ctx) == 0
+        ms, best = fsimg.fsimg_tune_schedule(
+            ctx, levels, fsimg.fsimg_default_opts(precision=precision, vanka_patches=fsimg.FSIMG_PATCH_BLOCK),
+            reps=2)
+        assert ms[0] > 0 and ms[1] == -1 and ms[2] == -1 and best == fsimg.FSIMG_VANKA_GATHER, ms
+    finally:
+        fsimg.fsimg_ctx_destroy(ctx)
