@@ -676,6 +676,7 @@ void fsimg_hier_destroy(fsimg_hier *h) {
       }
   if (h->ilu_cap) (void)hipStreamDestroy(h->ilu_cap);
   if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->pstream) (void)hipStreamDestroy(h->pstream);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->hpin) (void)hipHostFree(h->hpin);
@@ -1030,6 +1031,41 @@ static fsimg_status factor_impl(fsimg_hier *h, void *stream) {
     for (double v : hp) amax = std::max(amax, v);
     FSIMG_HIP(hipEventRecord(h->ev_fork, s));
   }
+  // the patch kernels' stream: with a coarse inverse to overlap, a stream
+  // restricted to all CUs but kReservedCus (created once; if the runtime
+  // refuses the CU mask, the caller's stream), ordered after everything the
+  // caller's stream holds (ev_fork)
+  hipStream_t ps = s;
+  // worth it only while the patch work is about as long as the coarse chain:
+  // patch kernels at ~15 TFLOP/s against ~3.4 us of chain per coarse dof
+  // (C2: 5.3 and 6.4 ms); at C3 the patch kernels take 41 ms and hide the
+  // chain on all CUs anyway
+  double pflops = 0.0;
+  for (int l = 0; l + 1 < nlev; ++l) {
+    const DevLevel &L = h->lev[l];
+    pflops += 2.0 * L.npatch * L.np * (double)L.np * L.np +
+              2.0 * L.blk.npatch * L.blk.np * (double)L.blk.np * L.blk.np;
+  }
+  const bool mask_patches = n > 0 && pflops / 15e12 < 1.5 * 3.4e-6 * (double)n;
+  if (mask_patches) {
+    if (!h->pstream_tried) {
+      h->pstream_tried = true;
+      int ncu = 0;
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->ctx->device) == hipSuccess &&
+          ncu > 2 * kReservedCus) {
+        std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+        for (int c = 0; c < ncu - kReservedCus; ++c) mask[c / 32] |= 1u << (c % 32);
+        if (hipExtStreamCreateWithCUMask(&h->pstream, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+          (void)hipGetLastError();
+          h->pstream = nullptr;
+        }
+      }
+    }
+    if (h->pstream) {
+      ps = h->pstream;
+      FSIMG_HIP(hipStreamWaitEvent(ps, h->ev_fork, 0));
+    }
+  }
   auto start_coarse = [&]() -> fsimg_status {
     if (n == 0 || coarse) return FSIMG_OK;
     hipStream_t c = h->side;
@@ -1061,19 +1097,19 @@ static fsimg_status factor_impl(fsimg_hier *h, void *stream) {
       if (h->opts.smoother == FSIMG_SMOOTHER_ILU) {
         const int64_t nv = L.nnzb * L.b * L.b;
         const int init[2] = {0, INT_MAX};
-        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
-        FSIMG_HIP(hipMemcpyAsync(L.ilu64, L.vals64, nv * 8, hipMemcpyDeviceToDevice, s));
-        if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
-        launch_ilu_factor(L, h->dstatus, s);
+        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, ps));
+        FSIMG_HIP(hipMemcpyAsync(L.ilu64, L.vals64, nv * 8, hipMemcpyDeviceToDevice, ps));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[0], ps));
+        launch_ilu_factor(L, h->dstatus, ps);
         FSIMG_HIP(hipGetLastError());
         FSIMG_TRY(start_coarse());
-        if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[1], ps));
         if (mixed) {
-          launch_cast_d2f(L.ilu64, L.ilu32, nv, s);
-          launch_cast_d2f(L.dinv64, L.dinv32, L.nrows * L.b * L.b, s);
+          launch_cast_d2f(L.ilu64, L.ilu32, nv, ps);
+          launch_cast_d2f(L.dinv64, L.dinv32, L.nrows * L.b * L.b, ps);
         }
-        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-        FSIMG_HIP(hipStreamSynchronize(s));
+        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, ps));
+        FSIMG_HIP(hipStreamSynchronize(ps));
         if (prof) {
           float ms = 0.0f;
           FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -1089,20 +1125,20 @@ static fsimg_status factor_impl(fsimg_hier *h, void *stream) {
         const int64_t np_ = g == 0 ? L.npatch : L.blk.npatch;
         if (np_ == 0) continue;
         const int init[2] = {0, INT_MAX};
-        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, s));
-        if (prof) FSIMG_HIP(hipEventRecord(ev[0], s));
+        FSIMG_HIP(hipMemcpyAsync(h->dstatus, init, sizeof(init), hipMemcpyHostToDevice, ps));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[0], ps));
         if (g == 0) {
-          if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, s);
-          else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, s);
+          if (mixed) launch_patch_factor<float>(L, L.inv32, L.npc32, h->dstatus, ps);
+          else launch_patch_factor<double>(L, L.inv64, L.npc64, h->dstatus, ps);
         } else {
-          if (mixed) launch_patch_factor_blocks<float>(L, L.blk.inv32, L.blk.npc32, h->dstatus, s);
-          else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, s);
+          if (mixed) launch_patch_factor_blocks<float>(L, L.blk.inv32, L.blk.npc32, h->dstatus, ps);
+          else launch_patch_factor_blocks<double>(L, L.blk.inv64, L.blk.npc64, h->dstatus, ps);
         }
         FSIMG_HIP(hipGetLastError());
         FSIMG_TRY(start_coarse());
-        if (prof) FSIMG_HIP(hipEventRecord(ev[1], s));
-        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-        FSIMG_HIP(hipStreamSynchronize(s));
+        if (prof) FSIMG_HIP(hipEventRecord(ev[1], ps));
+        FSIMG_HIP(hipMemcpyAsync(h->hstatus, h->dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, ps));
+        FSIMG_HIP(hipStreamSynchronize(ps));
         if (prof) {
           float ms = 0.0f;
           FSIMG_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));

@@ -31,6 +31,7 @@ constexpr int spmv_group_rows(int b, int word) {
 constexpr int kMaxVec = 32;     // FGMRES: restart length + 1 must not exceed this
 constexpr int kRedBlocks = 1024; // blocks of the two-stage reductions
 constexpr int kCoarseStage = 32;  // panel width of the coarse Gauss-Jordan (staged pivot rows)
+constexpr int kReservedCus = 16;  // CUs the patch factorisations leave to the coarse inverse
 constexpr int kIluMaxRow = 256;   // longest block row the ILU factorisation stages in LDS
 
 // Block patches (2 x 2 (x 2) elements, 5^d nodes) of a level: the second

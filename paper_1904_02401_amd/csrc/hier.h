@@ -77,6 +77,11 @@ struct fsimg_hier {
   // the coarse inverse runs on this stream while the patch factorisations of
   // the finer levels run on the caller's (fork / join events)
   hipStream_t side = nullptr;
+  // the patch factorisations' stream while the coarse inverse runs beside
+  // them: all CUs but kReservedCus, so that the coarse chain's one-workgroup
+  // panel launches find a free CU at once (nullptr: the caller's stream)
+  hipStream_t pstream = nullptr;
+  bool pstream_tried = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
