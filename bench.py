@@ -844,6 +844,7 @@ def serve_once(args, pool, rate, sizes2, sizes3, check_alone):
                                             lin_rtol=args.lin_rtol, atol=args.newton_atol,
                                             ale_rtol=args.ale_rtol)
     srv = fsimg.fsimg_server_create(ctx, opts, args.max_active)
+    fsimg.fsimg_server_set_order(srv, 1 if args.order == "work" else 0)
 
     def submit(server, key, ns, arrival):
         if args.newton:
@@ -997,7 +998,8 @@ def run_serving(args):
             f"70% 2D 64^2..256^2, 30% 3D 16^3..{max(sizes3)}^3, mixed precision, resident "
             "hierarchies, first-fit admission by HBM footprint, continuous batching")),
                    "window_s": args.window, "budget_GiB": args.budget_gb,
-                   "max_active": args.max_active, "states_cycled": args.n_states,
+                   "max_active": args.max_active, "admission_order": args.order,
+                   "states_cycled": args.n_states,
                    "rhs_cycled": args.n_rhs, **main},
     }
     if len(runs) > 1:
@@ -1068,6 +1070,8 @@ def main():
     ap.add_argument("--n-rhs", type=int, default=3,
                     help="serving: momentum right-hand sides cycled over a request's Newton steps")
     ap.add_argument("--max3d", type=int, default=48, help="serving: largest 3D mesh (cells per axis)")
+    ap.add_argument("--order", choices=["arrival", "work"], default="arrival",
+                    help="serving: admission in arrival order or least work first")
     args = ap.parse_args()
     if args.ale_rtol is None:
         args.ale_rtol = 1e-4 if args.config in CHANNEL_CONFIGS else 0.0

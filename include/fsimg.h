@@ -412,6 +412,13 @@ fsimg_status fsimg_server_create(fsimg_ctx *ctx, const fsimg_opts *opts, int max
 void fsimg_server_destroy(fsimg_server *srv);
 double fsimg_server_clock(const fsimg_server *srv);  /* seconds since creation */
 fsimg_status fsimg_server_submit(fsimg_server *srv, const fsimg_request *req, int64_t *id);
+/* Admission order of the queue: 0 (default) first fit in arrival order; 1
+   first fit in order of least work (finest-level unknowns of both systems
+   times the Newton steps the request asks for; a Newton request counts one
+   step per time step), ties in arrival order.  Least work first lowers the
+   median latency when requests of very different size compete for the
+   budget; a large request may then wait while smaller ones keep arriving. */
+fsimg_status fsimg_server_set_order(fsimg_server *srv, int order);
 /* Admit what fits, then run one Newton step of every admitted request.
    Reports the number of admitted (running) and queued requests after the
    step.  ERR_BUDGET if the queue head can never fit an empty budget. */

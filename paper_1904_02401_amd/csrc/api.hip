@@ -595,6 +595,7 @@ fsimg_status fsimg_ctx_create(int device, size_t hbm_budget_bytes, fsimg_ctx **o
 void fsimg_ctx_destroy(fsimg_ctx *ctx) {
   if (!ctx) return;
   drop_plans(ctx);
+  if (ctx->pstream) (void)hipStreamDestroy(ctx->pstream);
   delete ctx;
 }
 
@@ -676,7 +677,6 @@ void fsimg_hier_destroy(fsimg_hier *h) {
       }
   if (h->ilu_cap) (void)hipStreamDestroy(h->ilu_cap);
   if (h->side) (void)hipStreamDestroy(h->side);
-  if (h->pstream) (void)hipStreamDestroy(h->pstream);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->hpin) (void)hipHostFree(h->hpin);
@@ -1047,22 +1047,23 @@ static fsimg_status factor_impl(fsimg_hier *h, void *stream) {
               2.0 * L.blk.npatch * L.blk.np * (double)L.blk.np * L.blk.np;
   }
   const bool mask_patches = n > 0 && pflops / 15e12 < 1.5 * 3.4e-6 * (double)n;
+  fsimg_ctx *cx = h->ctx;
   if (mask_patches) {
-    if (!h->pstream_tried) {
-      h->pstream_tried = true;
+    if (!cx->pstream_tried) {
+      cx->pstream_tried = true;
       int ncu = 0;
       if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->ctx->device) == hipSuccess &&
           ncu > 2 * kReservedCus) {
         std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
         for (int c = 0; c < ncu - kReservedCus; ++c) mask[c / 32] |= 1u << (c % 32);
-        if (hipExtStreamCreateWithCUMask(&h->pstream, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        if (hipExtStreamCreateWithCUMask(&cx->pstream, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
           (void)hipGetLastError();
-          h->pstream = nullptr;
+          cx->pstream = nullptr;
         }
       }
     }
-    if (h->pstream) {
-      ps = h->pstream;
+    if (cx->pstream) {
+      ps = cx->pstream;
       FSIMG_HIP(hipStreamWaitEvent(ps, h->ev_fork, 0));
     }
   }

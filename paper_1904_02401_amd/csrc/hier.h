@@ -26,6 +26,14 @@ struct fsimg_ctx {
   size_t plan_bytes = 0;  // part of in_use held by cached batch plans
   std::vector<BatchPlan *> plans;  // descriptor tables of recent batch compositions (LRU)
   fsimg::TuneTable tune;           // launch shapes of this context's kernels
+  // the patch factorisations' stream while a coarse inverse runs beside
+  // them: all CUs but kReservedCus, so that the coarse chain's one-workgroup
+  // panel launches find a free CU at once.  One per context: a CU-masked
+  // stream holds a hardware queue of its own, and one per hierarchy
+  // oversubscribes the queues (every kernel of the process slows down).
+  // nullptr: not created yet, or the runtime refused the mask
+  hipStream_t pstream = nullptr;
+  bool pstream_tried = false;
 };
 
 struct EventTimer {
@@ -77,11 +85,6 @@ struct fsimg_hier {
   // the coarse inverse runs on this stream while the patch factorisations of
   // the finer levels run on the caller's (fork / join events)
   hipStream_t side = nullptr;
-  // the patch factorisations' stream while the coarse inverse runs beside
-  // them: all CUs but kReservedCus, so that the coarse chain's one-workgroup
-  // panel launches find a free CU at once (nullptr: the caller's stream)
-  hipStream_t pstream = nullptr;
-  bool pstream_tried = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 

@@ -35,6 +35,7 @@ struct Req {
   int t = 0, nstep = 0, dim = 0, bm = 0, ba = 0;
   int64_t nnodes = 0, nm = 0, na = 0;
   double admitted = -1.0, finished = -1.0;
+  double work = 0.0;  // unknowns x Newton steps asked for (the least-work-first key)
   std::vector<double> xm_host, xa_host;
   // Newton requests: x_mom holds the state x, x_ale the state u
   bool nt = false;
@@ -54,6 +55,7 @@ struct fsimg_server {
   int64_t next_id = 1;
   size_t reserved = 0;  // plan allowance of the running requests
   std::deque<Req *> queue;
+  int order = 0;  // fsimg_server_set_order
   std::vector<Req *> running;
   std::vector<Req *> finished_unpolled;
   std::map<int64_t, Req *> all;
@@ -396,6 +398,9 @@ fsimg_status fsimg_server_submit(fsimg_server *S, const fsimg_request *r, int64_
   q->nnodes = m0.nrows;
   q->nm = m0.nrows * m0.block;
   q->na = a0.nrows * a0.block;
+  int64_t nsteps = 0;
+  for (int t = 0; t < r->time_steps; ++t) nsteps += r->newton_steps[t];
+  q->work = (double)(q->nm + q->na) * (double)std::max<int64_t>(nsteps, 1);
   S->queue.push_back(q);
   S->all[q->id] = q;
   if (id) *id = q->id;
@@ -432,9 +437,16 @@ fsimg_status fsimg_server_submit_newton(fsimg_server *S, const fsimg_newton_requ
   q->nnodes = m0.nrows;
   q->nm = m0.nrows * m0.block;
   q->na = a0.nrows * a0.block;
+  q->work = (double)(q->nm + q->na) * r->time_steps;  // Newton steps not known in advance
   S->queue.push_back(q);
   S->all[q->id] = q;
   if (id) *id = q->id;
+  return FSIMG_OK;
+}
+
+fsimg_status fsimg_server_set_order(fsimg_server *S, int order) {
+  if (!S || order < 0 || order > 1) return set_error(FSIMG_ERR_ARG, "order must be 0 or 1");
+  S->order = order;
   return FSIMG_OK;
 }
 
@@ -450,7 +462,10 @@ fsimg_status fsimg_server_step(fsimg_server *S, int *n_active, int *n_queued, vo
   if (!S) return set_error(FSIMG_ERR_ARG, "null server");
   hipStream_t s = static_cast<hipStream_t>(stream);
   fsimg_status ret = FSIMG_OK;
-  // admission: first fit in arrival order
+  // admission: first fit in arrival order, or in order of least work (ties
+  // in arrival order)
+  if (S->order == 1)
+    std::stable_sort(S->queue.begin(), S->queue.end(), [](const Req *a, const Req *b) { return a->work < b->work; });
   for (auto it = S->queue.begin(); it != S->queue.end();) {
     Req *q = *it;
     if (S->max_active && (int)S->running.size() >= S->max_active) break;

@@ -192,6 +192,7 @@ _SIGS = {
     "fsimg_server_request_status": (_I, [_P, _I64, ctypes.POINTER(_I)]),
     "fsimg_server_release": (_I, [_P, _I64]),
     "fsimg_hier_tune": (_I, [_P, _I, _P]),
+    "fsimg_server_set_order": (_I, [_P, _I]),
     "fsimg_tune_schedule": (_I, [_P, ctypes.POINTER(fsimg_level_desc), _I, ctypes.POINTER(fsimg_opts), _I,
                                  ctypes.POINTER(_D), ctypes.POINTER(_I), _P]),
     "fsimg_tune_set": (_I, [_P, _I, _I, _I, _I64, _I]),
@@ -551,6 +552,11 @@ def fsimg_server_release(srv, rid: int):
 
 def fsimg_hier_tune(h, force: bool = False, stream=None):
     _check(load().fsimg_hier_tune(h, 1 if force else 0, _stream(stream)))
+
+
+def fsimg_server_set_order(srv, order: int):
+    """0: first fit in arrival order; 1: least work first"""
+    _check(load().fsimg_server_set_order(srv, order))
 
 
 def fsimg_tune_schedule(ctx, levels, opts, reps: int = 5, stream=None):

@@ -160,3 +160,47 @@ def test_footprint_bounds_hierarchy_and_refactor_allocates_nothing(probs, precis
                 assert fsimg.fsimg_ctx_bytes_in_use(ctx) == 0
     finally:
         fsimg.fsimg_ctx_destroy(ctx)
+
+
+def test_least_work_first_admission(probs):
+    """With order 1 a small request queued behind a large one is admitted
+    first when the budget holds one at a time; results are unchanged."""
+    opts = fsimg.fsimg_default_opts(precision=fsimg.FSIMG_MIXED)
+    big = probs[(2, 16)][1]
+    need = (fsimg.fsimg_hier_footprint(big.mom.levels, opts) +
+            fsimg.fsimg_hier_footprint(big.ale.levels, opts))
+    stream = torch.cuda.current_stream()
+    ctx = fsimg.fsimg_ctx_create(0, int(need * 1.5))
+    try:
+        finish = {}
+        for order in (0, 1):
+            srv = fsimg.fsimg_server_create(ctx, opts)
+            fsimg.fsimg_server_set_order(srv, order)
+            try:
+                # the running one, then a long and a short request queued behind it
+                first = fsimg.fsimg_server_submit(srv, big, [1], 0.0)
+                long_ = fsimg.fsimg_server_submit(srv, big, [3, 3], 0.0)
+                short = fsimg.fsimg_server_submit(srv, big, [1], 0.0)
+                step, done = 0, {}
+                while len(done) < 3 and step < 100:
+                    fsimg.fsimg_server_step(srv, stream)
+                    step += 1
+                    for rid, a, f in zip(*fsimg.fsimg_server_poll(srv)):
+                        done[int(rid)] = step
+                assert sorted(done) == sorted([first, long_, short])
+                finish[order] = (done[long_], done[short])
+                nm, na = _sizes(probs[(2, 16)][0])
+                for rid in (first, long_, short):
+                    fsimg.fsimg_server_release(srv, rid)
+            finally:
+                fsimg.fsimg_server_destroy(srv)
+        assert finish[0][0] < finish[0][1], "arrival order: the long request finishes first"
+        assert finish[1][1] < finish[1][0], "least work first: the short request finishes first"
+        with pytest.raises(fsimg.FsimgError):
+            srv = fsimg.fsimg_server_create(ctx, opts)
+            try:
+                fsimg.fsimg_server_set_order(srv, 2)
+            finally:
+                fsimg.fsimg_server_destroy(srv)
+    finally:
+        fsimg.fsimg_ctx_destroy(ctx)
