@@ -319,7 +319,7 @@ fsimg_status build_plan(fsimg_ctx *ctx, int n, fsimg_hier *const *hs, BatchPlan 
       } else if (l == Li - 1) {
         const DevLevel &L = hs[i]->lev[l];
         cn.push(i, cdiv(L.n, 256));
-        cf.push(i, cdiv(L.nfree, 4));
+        cf.push(i, cdiv(L.nfree, 4) + cdiv(L.n, 256));
       }
     }
     r_spmv.push_back(stage(blob, sp));

@@ -431,22 +431,11 @@ __global__ __launch_bounds__(256) void kb_prolong(const DLev *__restrict__ levF,
 }
 
 // ------------------------------------------------------------ coarse solve
-// FP64 dense inverse on the free dofs: x = C^-1 r.  Mixed precision casts the
-// FP32 residual into ct0 first and the FP64 result ct1 back afterwards.
-template <typename T>
-__global__ __launch_bounds__(256) void kb_coarse_pre(const DLev *__restrict__ lev,
-                                                     const int *__restrict__ active, WorkSet ws) {
-  const int s = seg_of(ws, blockIdx.x);
-  const int i = ws.inst[s];
-  if (!active[i]) return;
-  const DLev &L = lev[i];
-  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
-  if (k >= L.n) return;
-  double *out = std::is_same<T, double>::value ? L.x64 : L.ct1;
-  if (L.mask[k]) out[k] = 0.0;
-  if (!std::is_same<T, double>::value) L.ct0[k] = (double)L.r32[k];
-}
-
+// x = A_{L-1}^{-1} r in one launch: the first ceil(nfree/4) workgroups of an
+// instance take a wave per row of the free-dof inverse (FP64 arithmetic; in
+// mixed precision the FP32 residual is widened as it is read and the result
+// rounded as it is written), the remaining ceil(n/256) zero the identity-row
+// entries of x.
 template <typename T>
 __global__ __launch_bounds__(256) void kb_coarse_gemv(const DLev *__restrict__ lev,
                                                       const int *__restrict__ active, WorkSet ws) {
@@ -454,26 +443,21 @@ __global__ __launch_bounds__(256) void kb_coarse_gemv(const DLev *__restrict__ l
   const int i = ws.inst[s];
   if (!active[i]) return;
   const DLev &L = lev[i];
-  const int64_t row = (blockIdx.x - ws.pre[s]) * 4 + threadIdx.x / kWave;
+  const int64_t b = blockIdx.x - ws.pre[s], nrb = (L.nfree + 3) / 4;
+  if (b >= nrb) {
+    const int64_t k = (b - nrb) * 256 + threadIdx.x;
+    if (k < L.n && L.mask[k]) LV<T>::x(L)[k] = T(0);
+    return;
+  }
+  const int64_t row = b * 4 + threadIdx.x / kWave;
   if (row >= L.nfree) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const double *in = std::is_same<T, double>::value ? L.r64 : L.ct0;
-  double *out = std::is_same<T, double>::value ? L.x64 : L.ct1;
+  const T *in = LV<T>::r(L);
   const double *ar = L.cinv + row * L.nfree;
   double acc = 0.0;
-  for (int64_t c = lane; c < L.nfree; c += kWave) acc += ar[c] * in[L.cfree[c]];
+  for (int64_t c = lane; c < L.nfree; c += kWave) acc += ar[c] * (double)in[L.cfree[c]];
   acc = dev::wave_sum(acc);
-  if (lane == 0) out[L.cfree[row]] = acc;
-}
-
-__global__ __launch_bounds__(256) void kb_coarse_post(const DLev *__restrict__ lev,
-                                                      const int *__restrict__ active, WorkSet ws) {
-  const int s = seg_of(ws, blockIdx.x);
-  const int i = ws.inst[s];
-  if (!active[i]) return;
-  const DLev &L = lev[i];
-  const int64_t k = (blockIdx.x - ws.pre[s]) * 256 + threadIdx.x;
-  if (k < L.n) L.x32[k] = (float)L.ct1[k];
+  if (lane == 0) LV<T>::x(L)[L.cfree[row]] = (T)acc;
 }
 
 // ------------------------------------------------------------ Krylov
@@ -949,10 +933,8 @@ void launch_b_tail(int b, int dim, const DLev *lev, int n, const int *active, co
 template <typename T>
 void launch_b_coarse(const DLev *lev, const int *active, const WorkSet &wn, const WorkSet &wf,
                      hipStream_t s) {
-  if (wn.nblocks > 0) hipLaunchKernelGGL((kb_coarse_pre<T>), grid_of(wn), dim3(256), 0, s, lev, active, wn);
+  (void)wn;  // wf covers the identity rows as well
   if (wf.nblocks > 0) hipLaunchKernelGGL((kb_coarse_gemv<T>), grid_of(wf), dim3(256), 0, s, lev, active, wf);
-  if (!std::is_same<T, double>::value && wn.nblocks > 0)
-    hipLaunchKernelGGL(kb_coarse_post, grid_of(wn), dim3(256), 0, s, lev, active, wn);
 }
 
 template <typename T>
