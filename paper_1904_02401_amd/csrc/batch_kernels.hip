@@ -485,23 +485,32 @@ __global__ __launch_bounds__(256) void kb_copy_out(const DLev *__restrict__ lev0
   if (k < K.n) K.Z[(int64_t)j * K.n + k] = (double)LV<T>::x(lev0[i])[k];
 }
 
-// The last of an instance's nblk workgroups to finish a reduction pass:
-// each workgroup's thread 0 publishes its partials with a device-scope
-// release fence before counting itself in cnt; the workgroup that counts
-// last (and resets cnt for the next pass) takes an acquire fence and sums
-// every partial.  No workgroup waits for another.
+// The last of an instance's nblk workgroups to finish a reduction pass.
+// Partials are written and read with device-scope relaxed atomics, which this
+// chip keeps coherent across its per-XCD L2 caches (write-through stores,
+// loads that do not hit a stale line); each workgroup's thread 0 waits until
+// its partial stores have completed before it counts itself in cnt, so the
+// workgroup that counts last (and resets cnt for the next pass) reads every
+// partial.  No workgroup waits for another, and no workgroup writes back or
+// invalidates its L2, which a device-scope fence would do.
+__device__ __forceinline__ void put_partial(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get_partial(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ bool last_of(int *cnt, int nblk, int *flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(cnt, 1);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores are complete
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *flag = prev == nblk - 1;
-    if (*flag) atomicExch(cnt, 0);
+    if (*flag) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  const bool last = *flag != 0;
-  if (last) __threadfence();
-  return last;
+  return *flag != 0;
 }
 
 // hsi[k] = sum over the instance's workgroups b of partial[b nvec + k], in
@@ -509,7 +518,7 @@ __device__ __forceinline__ bool last_of(int *cnt, int nblk, int *flag) {
 __device__ __forceinline__ void sum_partials(const DKry &K, int nvec, double *hsi, double *red) {
   for (int k = 0; k < nvec; ++k) {
     double t = 0.0;
-    for (int b = threadIdx.x; b < K.nblk; b += blockDim.x) t += K.partial[(int64_t)b * nvec + k];
+    for (int b = threadIdx.x; b < K.nblk; b += blockDim.x) t += get_partial(K.partial + (int64_t)b * nvec + k);
     t = dev::block_sum(t, red);
     if (threadIdx.x == 0) hsi[k] = t;
   }
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(256) void kb_multidot(const DKry *__restrict__ kry,
   for (int k = 0; k < NV; ++k)
     if (k < nvec) {
       const double tt = dev::block_sum(acc[k], red);
-      if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
+      if (threadIdx.x == 0) put_partial(K.partial + lb * nvec + k, tt);
     }
   if (last_of(cnt + i, K.nblk, &flag)) sum_partials(K, nvec, hs + (int64_t)i * kHS + off, red);
 }
@@ -627,13 +636,13 @@ __global__ __launch_bounds__(256) void kb_axpy_red(const DKry *__restrict__ kry,
   }
   if (NORM) {
     const double tt = dev::block_sum(acc[0], red);
-    if (threadIdx.x == 0) K.partial[lb] = tt;
+    if (threadIdx.x == 0) put_partial(K.partial + lb, tt);
   } else {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
       if (k < nvec) {
         const double tt = dev::block_sum(acc[k], red);
-        if (threadIdx.x == 0) K.partial[lb * nvec + k] = tt;
+        if (threadIdx.x == 0) put_partial(K.partial + lb * nvec + k, tt);
       }
   }
   if (last_of(cnt + i, K.nblk, &flag)) {
