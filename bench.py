@@ -49,7 +49,7 @@ KERNEL_SOURCES = ("batch_kernels.hip", "device_ops.h")
 ASM_SOURCES = ("kernels_asm.hip",)
 # the batched kernels (and their helpers) whose source keys each role's counter entry
 ROLE_KERNEL = {"vanka_patch": ("kb_vanka_patch",), "spmv_residual": ("kb_spmv",),
-               "restrict": ("kb_restrict", "taps_1d", "kb_restrict3"), "prolong": ("kb_prolong",)}
+               "restrict": ("kb_restrict", "taps_1d", "kb_restrict3"), "prolong": ("kb_prolong", "prolong_node4")}
 
 
 def _function_text(src, name):
