@@ -98,6 +98,36 @@ __global__ __launch_bounds__(1024) void kb_vanka_patch(const DLev *__restrict__ 
                          nullptr, nullptr, L.mask, T(0), reinterpret_cast<T *>(smem_raw));
 }
 
+// One dof of the additive Vanka update, the sum of dev::vanka_gather_dof
+// (same order, same bits) with the node's first 8 slot indices, and then
+// their values, requested before any is summed: two round trips per wave
+// instead of two per slot (a Q2 vertex node lies in 8 element patches);
+// slots past the 8th, where block patches add some, follow in a loop.
+template <typename T>
+__device__ __forceinline__ void gather_dof(int64_t dof, int b, const int32_t *gptr_, const int32_t *gidx_,
+                                           const T *Y_, const T *scale_, const uint8_t *mask_, T omega,
+                                           int assign, T *x_) {
+  const dev::gptr<const int32_t> gp = dev::glb(gptr_), gidx = dev::glb(gidx_);
+  const dev::gptr<const T> Y = dev::glb(Y_), scale = dev::glb(scale_);
+  const dev::gptr<T> x = dev::glb(x_);
+  const int64_t node = dof / b;
+  const int c = (int)(dof - node * b);
+  const int e0 = gp[node], e1 = gp[node + 1], ne = e1 - e0;
+  int32_t g[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) g[q] = q < ne ? gidx[e0 + q] : 0;
+  T y[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) y[q] = q < ne ? Y[(int64_t)g[q] * b + c] : T(0);
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (q < ne) s += y[q];
+  for (int e = e0 + 8; e < e1; ++e) s += Y[(int64_t)gidx[e] * b + c];
+  const T xv = assign ? T(0) : x[dof];
+  x[dof] = dev::glb(mask_)[dof] ? xv : xv + omega * scale[node] * s;
+}
+
 // zj >= 0 (the last post-smoothing step on the finest level): also z_j =
 // the updated x in FP64, the FGMRES direction of iteration zj
 template <typename T>
@@ -112,8 +142,7 @@ __global__ __launch_bounds__(256) void kb_vanka_gather(const DLev *__restrict__ 
   const DLev &L = lev[i];
   const int64_t dof = (lb - ws.pre[s]) * 256 + threadIdx.x;
   if (dof >= L.n) return;
-  dev::vanka_gather_dof<T>(dof, b, L.gptr, L.gidx, LV<T>::Y(L), LV<T>::sc(L), L.mask, omega, assign,
-                           LV<T>::x(L));
+  gather_dof<T>(dof, b, L.gptr, L.gidx, LV<T>::Y(L), LV<T>::sc(L), L.mask, omega, assign, LV<T>::x(L));
   if (zj >= 0) {
     const DKry &K = kry[i];
     K.Z[(int64_t)zj * K.n + dof] = (double)LV<T>::x(L)[dof];
