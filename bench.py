@@ -145,7 +145,7 @@ def calib_copy(nbytes, reps):
 
 
 def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, schedule=0, smoother=0,
-            lookahead=2, small_kib=0):
+            lookahead=2, small_kib=0, omega=0.8):
     import torch
     from paper_1904_02401_amd import fsimg
     from paper_1904_02401_amd.problems import level_dicts
@@ -159,7 +159,7 @@ def run_gpu(P, precision, steps, warmup, with_mass=True, tune=True, patches=0, s
     for name in systems:
         o = fsimg.fsimg_default_opts(precision=precision, profile=0, vanka_patches=patches,
                                      vanka_schedule=max(schedule, 0), smoother=smoother,
-                                     krylov_lookahead=lookahead, small_level_kib=small_kib)
+                                     krylov_lookahead=lookahead, small_level_kib=small_kib, omega=omega)
         if schedule < 0:  # auto: the fastest schedule, measured on this system's hierarchy
             ms, best = fsimg.fsimg_tune_schedule(ctx, level_dicts(P, name), o, reps=3)
             sched_ms[name] = {"gather": ms[0], "parity": ms[1], "greedy": ms[2], "chosen": best}
@@ -1015,6 +1015,8 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--mu", type=float, default=None, help="solid shear modulus override")
     ap.add_argument("--lam", type=float, default=None, help="solid Lame lambda override")
+    ap.add_argument("--omega", type=float, default=0.8,
+                    help="Vanka damping omega_V (the paper's 0.8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes, no tuning")
@@ -1127,7 +1129,7 @@ def main():
                     schedule={"gather": fsimg.FSIMG_VANKA_GATHER, "parity": fsimg.FSIMG_VANKA_PARITY,
                               "greedy": fsimg.FSIMG_VANKA_GREEDY, "auto": -1}[args.schedule],
                     smoother=fsimg.FSIMG_SMOOTHER_ILU if args.smoother == "ilu" else fsimg.FSIMG_SMOOTHER_VANKA,
-                    lookahead=args.lookahead, small_kib=args.small_level_kib)
+                    lookahead=args.lookahead, small_kib=args.small_level_kib, omega=args.omega)
         A = to_csr(lev.systems["mom"])
         mask = lev.systems["mom"].dirichlet.astype(bool)
         rr = P.rhs["mom"] - A @ r["x_mom"]
@@ -1254,7 +1256,7 @@ def main():
                    "mu_s": P.params["mu_s"], "lambda_s": P.params["lambda_s"],
                    "unknowns_momentum": n_mom, "unknowns_ale": n_ale,
                    "precision": main_tag, "vanka_patches": args.patches,
-                   "vanka_schedule": args.schedule, "smoother": args.smoother,
+                   "vanka_schedule": args.schedule, "smoother": args.smoother, "omega_vanka": args.omega,
                    "krylov_lookahead": args.lookahead, "small_level_kib": args.small_level_kib},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GB/s"] / HBM_PEAK_GBS,
