@@ -297,6 +297,47 @@ def test_coarse_and_vcycle_match_single_kernels(ctx, probs, prec):
         fsimg.fsimg_hier_destroy(h)
 
 
+@pytest.mark.parametrize("prec", [fsimg.FSIMG_FP64, fsimg.FSIMG_MIXED])
+def test_coarse_identity_rows_zero_after_foreign_values(ctx, probs, prec):
+    """The coarse solve writes x = 0 at the coarsest level's identity rows on
+    every call, whatever that level's x held before: a single-step
+    prolongation leaves arbitrary values there (it stages its coarse input in
+    the level's x), and the V-cycle and coarse solve that follow must give the
+    same bits as on a fresh hierarchy."""
+    P = probs["t3"]
+    mats = P.system("mom")
+    npt, tt = DT[prec]
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(mats[0].nrows * mats[0].b).astype(npt).astype(np.float64)
+    r[mats[0].dirichlet.astype(bool)] = 0.0
+    mc = mats[-1]
+    rc = rng.standard_normal(mc.nrows * mc.b)
+    rc[mc.dirichlet.astype(bool)] = 0.0
+    out = []
+    for foreign in (False, True):
+        h = fsimg.fsimg_hier_create(ctx, level_dicts(P, "mom"), fsimg.fsimg_default_opts(precision=prec))
+        try:
+            fsimg.fsimg_factor(h)
+            if foreign:  # every coarse entry, identity rows included, set to 1e3 + noise
+                L = len(mats)
+                xc = _t(1e3 + rng.standard_normal(mc.nrows * mc.b), tt)
+                xf = torch.zeros(mats[L - 2].nrows * mats[L - 2].b, device=DEV, dtype=tt)
+                fsimg.fsimg_prolong_add(h, L - 2, prec, xc, xf)
+            z = torch.empty(r.shape[0], device=DEV, dtype=tt)
+            fsimg.fsimg_vcycle(h, prec, _t(r, tt), z)
+            got = [_np(z)]
+            if prec == fsimg.FSIMG_FP64:
+                x = torch.empty(rc.shape[0], device=DEV, dtype=torch.float64)
+                fsimg.fsimg_coarse_solve(h, _t(rc, torch.float64), x)
+                got.append(_np(x))
+                assert not got[-1][mc.dirichlet.astype(bool)].any()
+            out.append(got)
+        finally:
+            fsimg.fsimg_hier_destroy(h)
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
 # ------------------------------------------------------- full size, sampled
 def _patch_cells(cells, node):
     """elements whose 3^d node box contains the node (lexicographic)"""
