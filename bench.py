@@ -1063,7 +1063,8 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--rates", default="", help="serving: comma-separated arrival-rate sweep")
     ap.add_argument("--window", type=float, default=3.0, help="serving: arrival window (s)")
-    ap.add_argument("--max-wall", type=float, default=90.0, help="serving: stop after this many s")
+    ap.add_argument("--max-wall", type=float, default=200.0,
+                    help="serving: stop after this many s (long enough for rate 20 to complete every request)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-active", type=int, default=0,
                     help="serving: admitted requests at most (0 = as many as fit)")
